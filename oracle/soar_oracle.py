@@ -1,0 +1,405 @@
+"""CPU FP64 oracle for SOAR spilled assignment and the Lloyd k-means that trains its codebook.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the GPU library imports, links or runs this file; only the
+tests, the smoke check and the benchmark's CPU-baseline leg may use it.  It shares no code with
+the HIP path.
+
+Everything is computed in float64 from float32 inputs (promotion is exact), by direct
+differences, in the order the paper states the method:
+
+* primary assignment, Section 2.2: pi(x) = argmin_i ||x - C_i||^2;
+* partitioning residual, Section 3.1: r = x - C_pi(x);
+* SOAR spill, Section 3.4 (Eq. 2 evaluated by Theorem 3.1):
+  pi'(x) = argmin_{j != pi(x)} ||x - C_j||^2 + lambda * ||proj_r (x - C_j)||^2, and
+  ||proj_r r'||^2 = <r, r'>^2 / ||r||^2;
+* indexing pipeline, Section 3.5: train VQ, primary, residual, spill;
+* KMR curve, Eq. 1 (Section 2.2.1), with Rank as in Section 2.1.
+
+Readings where the paper is silent (each is listed with its reason in the design notes):
+
+* arg-min ties go to the lowest index (paper silent);
+* the primary is excluded *by index* (a duplicate centroid at another index stays eligible);
+* ||r|| = 0 makes the projection term 0 (the formula is 0/0 there);
+* Lloyd: an empty cluster keeps its previous centroid; the iteration count is exact;
+* k-means++: first centre uniform over rows, then one row per round drawn with probability
+  proportional to D^2; if sum D^2 = 0 the lowest-index row not yet chosen is taken.  Its random
+  draws come from Philox4x32-10 (``oracle/philox.py``), the same published generator the GPU
+  library implements on its own.
+
+Two modes:
+* ``*_plain``: the definition, all K distances/losses by direct differences (chunked);
+* ``*_fast``: an FP64 GEMM expansion screens candidates with a rigorous rounding margin, and every
+  surviving candidate is recomputed by the very same direct-difference routine, so the result is
+  bit-identical to plain mode (checked in the tests).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .philox import philox_uniform24, philox_index
+
+_U64 = 2.0 ** -53
+_CHUNK_BYTES = 128 << 20
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _chunk_rows(K: int, d: int, planes: int = 2) -> int:
+    return max(1, int(_CHUNK_BYTES // max(1, planes * K * d * 8)))
+
+
+# ----------------------------------------------------------------------------------------------
+# Direct-difference kernels (the definition).  Every loss the oracle reports comes from these two
+# functions, in both modes, so the two modes agree to the last bit.
+# ----------------------------------------------------------------------------------------------
+
+def _sqdist(diff: np.ndarray) -> np.ndarray:
+    """||x - c||^2 from diff = x - c over the last axis (Section 2.2)."""
+    return (diff * diff).sum(axis=-1)
+
+
+def _soar_loss(diff: np.ndarray, r: np.ndarray, rr: np.ndarray, lam: float) -> np.ndarray:
+    """||r'||^2 + lam * <r, r'>^2 / ||r||^2 with r' = diff (Theorem 3.1; zero penalty if r = 0)."""
+    sq = _sqdist(diff)
+    proj = (diff * r).sum(axis=-1)
+    safe = np.where(rr > 0.0, rr, 1.0)
+    pen = np.where(rr > 0.0, lam * (proj * proj) / safe, 0.0)
+    return sq + pen
+
+
+# ----------------------------------------------------------------------------------------------
+# Primary assignment (Section 2.2)
+# ----------------------------------------------------------------------------------------------
+
+def primary_plain(X, C):
+    """pi_i = argmin_j ||x_i - c_j||^2 (lowest index on ties) and that distance, float64."""
+    X, C = _f64(X), _f64(C)
+    n, d = X.shape
+    K = C.shape[0]
+    pi = np.empty(n, dtype=np.int64)
+    dist = np.empty(n, dtype=np.float64)
+    step = _chunk_rows(K, d)
+    for lo in range(0, n, step):
+        hi = min(n, lo + step)
+        D = _sqdist(X[lo:hi, None, :] - C[None, :, :])
+        pi[lo:hi] = np.argmin(D, axis=1)
+        dist[lo:hi] = D[np.arange(hi - lo), pi[lo:hi]]
+    return pi, dist
+
+
+def _pick_min(rows, cols, vals, n):
+    """Per row, the smallest value, ties to the lowest column."""
+    order = np.lexsort((cols, vals, rows))
+    r_sorted = rows[order]
+    first = np.ones(len(order), dtype=bool)
+    first[1:] = r_sorted[1:] != r_sorted[:-1]
+    sel = order[first]
+    out_c = np.full(n, -1, dtype=np.int64)
+    out_v = np.full(n, np.inf)
+    out_c[rows[sel]] = cols[sel]
+    out_v[rows[sel]] = vals[sel]
+    return out_c, out_v
+
+
+def _screen_bound(X, C, scale):
+    """Rigorous bound on |expansion - exact| and |direct - exact| per row: scale*(d+8)*u*(|x|+cmax)^2."""
+    d = X.shape[1]
+    cmax = np.sqrt((C * C).sum(axis=1).max())
+    xn = np.sqrt((X * X).sum(axis=1))
+    return 4.0 * scale * (d + 8) * _U64 * (xn + cmax) ** 2
+
+
+def primary_fast(X, C):
+    """Same result as ``primary_plain``; an FP64 GEMM screens, direct differences decide."""
+    X, C = _f64(X), _f64(C)
+    n, d = X.shape
+    K = C.shape[0]
+    cc = (C * C).sum(axis=1)
+    xx = (X * X).sum(axis=1)
+    bound = _screen_bound(X, C, 1.0)
+    pi = np.empty(n, dtype=np.int64)
+    dist = np.empty(n, dtype=np.float64)
+    step = _chunk_rows(K, 1, planes=2)
+    for lo in range(0, n, step):
+        hi = min(n, lo + step)
+        Dh = xx[lo:hi, None] - 2.0 * (X[lo:hi] @ C.T) + cc[None, :]
+        thr = Dh.min(axis=1) + 2.0 * bound[lo:hi]
+        rows, cols = np.nonzero(Dh <= thr[:, None])
+        vals = _sqdist(X[lo + rows] - C[cols])
+        c, v = _pick_min(rows, cols, vals, hi - lo)
+        pi[lo:hi], dist[lo:hi] = c, v
+    return pi, dist
+
+
+# ----------------------------------------------------------------------------------------------
+# SOAR spilled assignment (Section 3.4, Eq. 2, Theorem 3.1)
+# ----------------------------------------------------------------------------------------------
+
+def _check_lambda(lam):
+    lam = float(lam)
+    if not np.isfinite(lam) or lam < 0.0:
+        raise ValueError("lambda must be finite and >= 0")
+    return lam
+
+
+def soar_losses(x, C, lam, p):
+    """All K losses of one row given its primary index p (the primary itself included)."""
+    x, C = _f64(x), _f64(C)
+    r = x - C[p]
+    rr = _sqdist(r)
+    return _soar_loss(x[None, :] - C, r[None, :], np.full(C.shape[0], rr), float(lam))
+
+
+def spill_plain(X, C, lam, primary=None):
+    """pi'_i = argmin_{j != pi_i} L_ij (lowest index on ties) and L at that index, float64.
+
+    ``primary`` may be given (for example a GPU primary that was a legitimate near-tie); otherwise
+    it is recomputed by ``primary_plain``."""
+    lam = _check_lambda(lam)
+    X, C = _f64(X), _f64(C)
+    n, d = X.shape
+    K = C.shape[0]
+    if K < 2:
+        raise ValueError("a spill needs at least two centroids")
+    p = primary_plain(X, C)[0] if primary is None else np.asarray(primary, dtype=np.int64)
+    sp = np.empty(n, dtype=np.int64)
+    loss = np.empty(n, dtype=np.float64)
+    step = _chunk_rows(K, d, planes=3)
+    for lo in range(0, n, step):
+        hi = min(n, lo + step)
+        m = hi - lo
+        R = X[lo:hi] - C[p[lo:hi]]
+        rr = _sqdist(R)
+        L = _soar_loss(X[lo:hi, None, :] - C[None, :, :], R[:, None, :], rr[:, None], lam)
+        L[np.arange(m), p[lo:hi]] = np.inf
+        sp[lo:hi] = np.argmin(L, axis=1)
+        loss[lo:hi] = L[np.arange(m), sp[lo:hi]]
+    return sp, loss
+
+
+def spill_fast(X, C, lam, primary=None):
+    """Same result as ``spill_plain``; FP64 GEMMs screen, the direct-difference loss decides."""
+    lam = _check_lambda(lam)
+    X, C = _f64(X), _f64(C)
+    n, d = X.shape
+    K = C.shape[0]
+    if K < 2:
+        raise ValueError("a spill needs at least two centroids")
+    p = primary_fast(X, C)[0] if primary is None else np.asarray(primary, dtype=np.int64)
+    cc = (C * C).sum(axis=1)
+    xx = (X * X).sum(axis=1)
+    bound = _screen_bound(X, C, 1.0 + 3.0 * lam)
+    sp = np.empty(n, dtype=np.int64)
+    loss = np.empty(n, dtype=np.float64)
+    step = _chunk_rows(K, 1, planes=4)
+    for lo in range(0, n, step):
+        hi = min(n, lo + step)
+        m = hi - lo
+        Xb = X[lo:hi]
+        R = Xb - C[p[lo:hi]]
+        rr = _sqdist(R)
+        a = (R * Xb).sum(axis=1)
+        S = Xb @ C.T
+        T = R @ C.T
+        E = a[:, None] - T
+        pen = np.where(rr[:, None] > 0, lam * E * E / np.where(rr > 0, rr, 1.0)[:, None], 0.0)
+        Lh = xx[lo:hi, None] - 2.0 * S + cc[None, :] + pen
+        Lh[np.arange(m), p[lo:hi]] = np.inf
+        thr = Lh.min(axis=1) + 2.0 * bound[lo:hi]
+        rows, cols = np.nonzero(Lh <= thr[:, None])
+        vals = _soar_loss(Xb[rows] - C[cols], R[rows], rr[rows], lam)
+        c, v = _pick_min(rows, cols, vals, m)
+        sp[lo:hi], loss[lo:hi] = c, v
+    return sp, loss
+
+
+def assign(X, C, lam, fast=True):
+    """The indexing pipeline's assignment step (Section 3.5): primary, residual, spill."""
+    prim = primary_fast if fast else primary_plain
+    spl = spill_fast if fast else spill_plain
+    p, dp = prim(X, C)
+    s, ls = spl(X, C, lam, primary=p)
+    return p, dp, s, ls
+
+
+# ----------------------------------------------------------------------------------------------
+# Codebook training: k-means++ seeding and Lloyd iterations
+# ----------------------------------------------------------------------------------------------
+
+def dsq_sample(D2, u):
+    """Inverse-CDF draw proportional to D^2: row i owns [prefix_{i-1}, prefix_i) of [0, sum D^2),
+    so the pick is the smallest i with prefix_i > u * sum(D^2).  Returns -1 if sum(D^2) = 0."""
+    pref = np.cumsum(np.asarray(D2, dtype=np.float64))
+    S = pref[-1]
+    if not S > 0.0:
+        return -1
+    return int(np.searchsorted(pref, u * S, side="right"))
+
+
+def kmeanspp(X, K, seed):
+    """k-means++ seeding.  Round 0 takes row philox_index(seed, 0, n); round m >= 1 draws
+    u = philox_uniform24(seed, m) and takes the smallest row i with prefix_i(D^2) > u * sum(D^2),
+    where D is the distance to the nearest centre chosen so far.  Returns (C float64 K x d, rows)."""
+    X = _f64(X)
+    n, d = X.shape
+    if K < 1 or K > n:
+        raise ValueError("need 1 <= K <= n")
+    rows = np.empty(K, dtype=np.int64)
+    chosen = np.zeros(n, dtype=bool)
+    rows[0] = philox_index(seed, 0, n)
+    chosen[rows[0]] = True
+    D2 = _sqdist(X - X[rows[0]])
+    for m in range(1, K):
+        i = dsq_sample(D2, philox_uniform24(seed, m))
+        if i < 0:
+            i = int(np.flatnonzero(~chosen)[0])
+        rows[m] = i
+        chosen[i] = True
+        D2 = np.minimum(D2, _sqdist(X - X[i]))
+    return X[rows].copy(), rows
+
+
+def lloyd_update(X, labels, C_prev):
+    """c_j <- mean of the rows labelled j; an empty cluster keeps c_j from ``C_prev``."""
+    X, C_prev = _f64(X), _f64(C_prev)
+    K, d = C_prev.shape
+    labels = np.asarray(labels, dtype=np.int64)
+    counts = np.bincount(labels, minlength=K)
+    sums = np.zeros((K, d))
+    np.add.at(sums, labels, X)
+    C = C_prev.copy()
+    nz = counts > 0
+    C[nz] = sums[nz] / counts[nz, None]
+    return C, counts
+
+
+def lloyd_step(X, C, fast=True):
+    """One Lloyd iteration: assign against C (Section 2.2), then recentre."""
+    prim = primary_fast if fast else primary_plain
+    labels, dist = prim(X, C)
+    C_next, counts = lloyd_update(X, labels, C)
+    return labels, dist, C_next, counts, float(dist.sum())
+
+
+def train_codebook(X, K, iters, seed, C_init=None, fast=True):
+    """k-means++ (unless ``C_init``), then exactly ``iters`` Lloyd iterations.
+
+    Returns (C, labels against the final C, inertia[iters + 1])."""
+    C = kmeanspp(X, K, seed)[0] if C_init is None else _f64(C_init)
+    inertia = []
+    for _ in range(iters):
+        _, _, C, _, e = lloyd_step(X, C, fast)
+        inertia.append(e)
+    prim = primary_fast if fast else primary_plain
+    labels, dist = prim(X, C)
+    inertia.append(float(dist.sum()))
+    return C, labels, inertia
+
+
+# ----------------------------------------------------------------------------------------------
+# MIPS ground truth, Rank, KMR (Section 2.1, Eq. 1)
+# ----------------------------------------------------------------------------------------------
+
+def mips_topk(Q, X, k, chunk=64):
+    """Exact MIPS top-k ids per query (ties to the lowest id), float64."""
+    Q, X = _f64(Q), _f64(X)
+    out = np.empty((Q.shape[0], k), dtype=np.int64)
+    for lo in range(0, Q.shape[0], chunk):
+        S = Q[lo:lo + chunk] @ X.T
+        part = np.argpartition(-S, k, axis=1)[:, :k + 1] if X.shape[0] > k else \
+            np.tile(np.arange(X.shape[0]), (S.shape[0], 1))
+        for i in range(S.shape[0]):
+            # candidates: everything scoring at least the (k)-th best value, ordered by (-s, id)
+            kth = np.sort(S[i, part[i]])[::-1][min(k, part.shape[1]) - 1]
+            cand = np.flatnonzero(S[i] >= kth)
+            order = np.lexsort((cand, -S[i, cand]))
+            out[lo + i] = cand[order[:k]]
+    return out
+
+
+def partition_ranks(Q, C):
+    """Rank(q, C_j, C) = #{j'' : <q, C_j> <= <q, C_j''>} for every query and centroid (ties count
+    against C_j, Section 2.1)."""
+    Q, C = _f64(Q), _f64(C)
+    S = Q @ C.T
+    srt = np.sort(S, axis=1)
+    K = C.shape[0]
+    ranks = np.empty(S.shape, dtype=np.int64)
+    for i in range(S.shape[0]):
+        ranks[i] = K - np.searchsorted(srt[i], S[i], side="left")
+    return ranks
+
+
+def kmr_curve(Q, X, C, assignments, k, ts, gt=None):
+    """Eq. 1 with a datapoint found at depth t if any of its partitions has Rank <= t.
+
+    ``assignments`` is a list of int arrays (one per assignment: [pi] or [pi, pi']).
+    Returns (kmr values at ``ts``, datapoints searched at ``ts``)."""
+    gt = mips_topk(Q, X, k) if gt is None else gt
+    ranks = partition_ranks(Q, C)
+    K = C.shape[0]
+    best = None
+    for a in assignments:
+        rk = np.take_along_axis(ranks, np.asarray(a, dtype=np.int64)[gt], axis=1)
+        best = rk if best is None else np.minimum(best, rk)
+    kmr = np.array([(best <= t).mean() for t in ts])
+    sizes = np.zeros(K, dtype=np.int64)
+    for a in assignments:
+        sizes += np.bincount(np.asarray(a, dtype=np.int64), minlength=K)
+    S = _f64(Q) @ _f64(C).T
+    order = np.argsort(-S, axis=1, kind="stable")
+    csz = np.cumsum(sizes[order], axis=1)
+    searched = np.array([csz[:, min(t, K) - 1].mean() if t > 0 else 0.0 for t in ts])
+    return kmr, searched
+
+
+# ----------------------------------------------------------------------------------------------
+# Acceptance rule for a GPU result
+# ----------------------------------------------------------------------------------------------
+
+def judge(X, C, lam, gpu_primary, gpu_spill, gpu_pdist=None, gpu_sloss=None, fast=True,
+          band=1e-6, loss_tol=1e-5):
+    """Check a GPU assignment against the oracle.
+
+    * primary: accepted if equal to the oracle's, or its exact distance is within ``band``
+      (relative) of the best;
+    * spill: judged with the oracle conditioned on the GPU primary; accepted if equal, or not the
+      primary and its exact loss within ``band`` (relative) of the best;
+    * reported distance / loss: within ``loss_tol`` (relative) of the exact value at the GPU's index.
+    Returns a dict of per-row boolean arrays and regret statistics."""
+    X, C = _f64(X), _f64(C)
+    n = X.shape[0]
+    gp = np.asarray(gpu_primary, dtype=np.int64)
+    gs = np.asarray(gpu_spill, dtype=np.int64)
+    K = C.shape[0]
+    valid = (gp >= 0) & (gp < K) & (gs >= 0) & (gs < K)
+    gp_c = np.clip(gp, 0, K - 1)
+    gs_c = np.clip(gs, 0, K - 1)
+    prim = primary_fast if fast else primary_plain
+    spl = spill_fast if fast else spill_plain
+    p_star, d_star = prim(X, C)
+    d_gpu = _sqdist(X - C[gp_c])
+    dscale = np.maximum(d_star, 1e-12)
+    prim_ok = valid & ((gp == p_star) | (d_gpu - d_star <= band * dscale))
+    s_star, l_star = spl(X, C, lam, primary=gp_c)
+    R = X - C[gp_c]
+    rr = _sqdist(R)
+    l_gpu = _soar_loss(X - C[gs_c], R, rr, float(lam))
+    tau = np.maximum(l_star, 1e-12)
+    spill_ok = valid & ((gs == s_star) | ((gs != gp) & (l_gpu - l_star <= band * tau)))
+    out = dict(primary_ok=prim_ok, spill_ok=spill_ok,
+               primary_regret=(d_gpu - d_star) / dscale,
+               spill_regret=(l_gpu - l_star) / tau,
+               primary_mismatch=int((gp != p_star).sum()),
+               spill_mismatch=int((gs != s_star).sum()),
+               p_star=p_star, s_star=s_star, d_star=d_star, l_star=l_star)
+    if gpu_pdist is not None:
+        out["pdist_ok"] = np.abs(np.asarray(gpu_pdist, np.float64) - d_gpu) <= loss_tol * dscale
+    if gpu_sloss is not None:
+        out["sloss_ok"] = np.abs(np.asarray(gpu_sloss, np.float64) - l_gpu) <= loss_tol * tau
+    out["all_ok"] = bool(prim_ok.all() and spill_ok.all()
+                         and out.get("pdist_ok", np.ones(n, bool)).all()
+                         and out.get("sloss_ok", np.ones(n, bool)).all())
+    return out

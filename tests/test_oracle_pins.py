@@ -1,0 +1,443 @@
+"""Pins of the CPU oracle to what the paper and the mathematics fix (no GPU needed).
+
+Each test checks the oracle against something other than itself: a value or statement the paper
+makes about its worked example, a closed form, exact rational brute force, a library routine, or
+an invariant.  A dropped term, a wrong sign, a wrong index or a transposed operand in the oracle
+fails at least one of them.
+"""
+import itertools
+import math
+import os
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+from scipy import special, stats
+
+import oracle as O
+from oracle.philox import philox4x32_10, philox_index, philox_uniform24
+
+
+# ------------------------------------------------------------------------------------------------
+# Philox4x32-10: known-answer vectors published with the generator (Random123 distribution).
+# ------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("ctr,key,want", [
+    ((0, 0, 0, 0), (0, 0), (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+    ((0xffffffff,) * 4, (0xffffffff,) * 2, (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+    ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+     (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)),
+])
+def test_philox_known_answers(ctr, key, want):
+    assert philox4x32_10(ctr, key) == want
+
+
+def test_philox_draw_ranges():
+    us = [philox_uniform24(7, m) for m in range(2000)]
+    assert all(0.0 <= u < 1.0 for u in us)
+    assert abs(np.mean(us) - 0.5) < 0.03
+    idx = [philox_index(7, m, 13) for m in range(2000)]
+    assert set(idx) == set(range(13))
+
+
+# ------------------------------------------------------------------------------------------------
+# W1: Figure 3 (Section 3.3), coordinates as drawn in the paper.
+# ------------------------------------------------------------------------------------------------
+def _fig3(golden_dir):
+    pts = {}
+    with open(os.path.join(golden_dir, "fig3_coordinates.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                name, a, b = line.split()
+                pts[name] = (float(a), float(b))
+    x = np.array([pts["x"]], dtype=np.float32)
+    C = np.array([pts["C1"], pts["C2"], pts["C3"]], dtype=np.float32)
+    return x, C
+
+
+def test_fig3_primary_and_naive_spill(golden_dir):
+    x, C = _fig3(golden_dir)
+    p, _ = O.primary_plain(x, C)
+    assert p[0] == 0                       # the text: pi(x) = 1
+    s, _ = O.spill_plain(x, C, 0.0, p)     # lambda = 0 is plain second-nearest (Cor. 3.1.1)
+    assert s[0] == 1                       # the text: the naive spill picks C2
+    d = np.sum((x.astype(np.float64) - C) ** 2, axis=1)
+    assert d[2] > d[1]                     # the text: C3 is farther from x than C2
+
+
+def test_fig3_collinear_centroid_is_penalised_fully(golden_dir):
+    """C2 is collinear with C1 and x, so r' = (1 + eps) r and the projection term is all of
+    ||r'||^2: L(C2) = (1 + lambda) ||r'||^2 for every lambda (up to the figure's rounding)."""
+    x, C = _fig3(golden_dir)
+    r = x[0].astype(np.float64) - C[0]
+    rp = x[0].astype(np.float64) - C[1]
+    eps = np.linalg.norm(rp) / np.linalg.norm(r) - 1.0
+    assert 0.3 < eps < 0.5
+    assert np.allclose(rp, (1 + eps) * r, atol=2e-3)
+    for lam in (0.0, 0.5, 1.0, 2.0):
+        L = O.soar_losses(x[0], C, lam, 0)
+        assert L[1] == pytest.approx((1 + lam) * np.dot(rp, rp), rel=1e-5)
+
+
+def test_fig3_soar_moves_spill_to_c3(golden_dir):
+    """The text: pi'(x) = 3 would have been the better spill; SOAR reaches it once lambda is large
+    enough, and keeps the naive choice for small lambda."""
+    x, C = _fig3(golden_dir)
+    picks = {lam: int(O.spill_plain(x, C, lam, np.array([0]))[0][0])
+             for lam in (0.0, 0.5, 1.0, 1.5, 2.0, 4.0)}
+    assert picks[0.0] == 1 and picks[0.5] == 1
+    assert picks[2.0] == 2 and picks[4.0] == 2
+    lams = sorted(picks)
+    switched = [picks[a] != picks[b] for a, b in zip(lams, lams[1:])]
+    assert sum(switched) == 1              # one crossover, never back
+
+
+# ------------------------------------------------------------------------------------------------
+# W2: Corollary 3.1.2 (orthogonal residual unpenalised) and a parallel residual (fully penalised).
+# ------------------------------------------------------------------------------------------------
+def test_orthogonal_and_parallel_residuals():
+    x = np.zeros((1, 2), dtype=np.float32)
+    C = np.array([[1.0, 0.0], [0.0, 1.25], [-1.125, 0.0]], dtype=np.float32)
+    # r = (-1, 0); r'_1 = (0, -1.25) is orthogonal, r'_2 = (1.125, 0) is parallel to r
+    for lam in (0.0, 0.1, 0.5, 1.0, 3.0):
+        L = O.soar_losses(x[0], C, lam, 0)
+        assert L[1] == 1.5625                        # ||r'||^2, no penalty (Cor. 3.1.2)
+        assert L[2] == pytest.approx(1.265625 * (1 + lam), rel=1e-15)   # proj_r r' = r'
+        s = O.spill_plain(x, C, lam, np.array([0]))[0][0]
+        assert s == (2 if 1.265625 * (1 + lam) < 1.5625 else 1)
+
+
+# ------------------------------------------------------------------------------------------------
+# W3: Corollary 3.1.1 -- lambda = 0 is Euclidean assignment: the spill is the second-nearest.
+# ------------------------------------------------------------------------------------------------
+def test_lambda_zero_is_second_nearest():
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((500, 12)).astype(np.float32)
+    C = rng.standard_normal((40, 12)).astype(np.float32)
+    D = ((X[:, None, :].astype(np.float64) - C[None].astype(np.float64)) ** 2).sum(-1)
+    order = np.argsort(D, axis=1, kind="stable")
+    p, dp = O.primary_plain(X, C)
+    s, ls = O.spill_plain(X, C, 0.0)
+    assert np.array_equal(p, order[:, 0])
+    assert np.array_equal(s, order[:, 1])
+    assert np.allclose(ls, np.take_along_axis(D, order[:, 1:2], 1)[:, 0], rtol=1e-13)
+
+
+# ------------------------------------------------------------------------------------------------
+# W4: exact rational brute force on tiny integer inputs (ties, r = 0, duplicate centroids).
+# The projection is formed as a vector, (<r, r'>/<r, r>) r, and then squared -- a different route
+# to ||proj_r r'||^2 than the oracle's closed form.
+# ------------------------------------------------------------------------------------------------
+def _brute(X, C, lam):
+    K = len(C)
+    out = []
+    for x in X:
+        d = [sum((Fr(a) - Fr(b)) ** 2 for a, b in zip(x, c)) for c in C]
+        p = min(range(K), key=lambda j: (d[j], j))
+        r = [Fr(a) - Fr(b) for a, b in zip(x, C[p])]
+        rr = sum(v * v for v in r)
+        losses = []
+        for c in C:
+            rp = [Fr(a) - Fr(b) for a, b in zip(x, c)]
+            if rr == 0:
+                proj_sq = Fr(0)
+            else:
+                coef = sum(u * v for u, v in zip(r, rp)) / rr
+                proj_sq = sum((coef * u) ** 2 for u in r)
+            losses.append(sum(v * v for v in rp) + lam * proj_sq)
+        s = min((j for j in range(K) if j != p), key=lambda j: (losses[j], j))
+        out.append((p, d[p], s, losses))
+    return out
+
+
+@pytest.mark.parametrize("lam", [Fr(0), Fr(1, 2), Fr(1), Fr(3, 2), Fr(3)])
+def test_bruteforce_exact_rationals(lam):
+    rng = np.random.default_rng(11)
+    ties_seen = 0
+    for trial in range(150):
+        n, K, d = rng.integers(1, 7), rng.integers(2, 6), rng.integers(1, 4)
+        X = rng.integers(-2, 3, size=(n, d))
+        C = rng.integers(-2, 3, size=(K, d))
+        if trial % 5 == 0:
+            C[-1] = C[0]                               # duplicate centroid
+        if trial % 7 == 0:
+            X[0] = C[rng.integers(0, K)]               # r = 0
+        ref = _brute(X.tolist(), C.tolist(), lam)
+        p, dp = O.primary_plain(X.astype(np.float32), C.astype(np.float32))
+        s, ls = O.spill_plain(X.astype(np.float32), C.astype(np.float32), float(lam), p)
+        for i, (bp, bd, bs, bl) in enumerate(ref):
+            assert p[i] == bp                          # integer distances: FP64 exact
+            assert dp[i] == float(bd)
+            best = bl[bs]
+            assert bl[int(s[i])] == best and s[i] != p[i]
+            if sorted(bl[j] for j in range(K) if j != bp)[:2].count(best) > 1:
+                ties_seen += 1
+            if lam == 0:
+                assert s[i] == bs                      # exact: lowest index among equals
+            assert ls[i] == pytest.approx(float(best), rel=1e-14, abs=1e-14)
+    assert ties_seen > 0
+
+
+# ------------------------------------------------------------------------------------------------
+# W5: Theorem 3.1 by Monte Carlo of Eq. 2 with w(t) = |t|^lambda and q uniform on the sphere.
+# The constant of proportionality follows from the moments of one coordinate of a uniform
+# point on S^{d-1}: E|t|^a = Gamma(d/2) Gamma((a+1)/2) / (sqrt(pi) Gamma((a+d)/2)).
+# ------------------------------------------------------------------------------------------------
+def _abs_moment(a, d):
+    return math.exp(special.gammaln(d / 2) + special.gammaln((a + 1) / 2)
+                    - 0.5 * math.log(math.pi) - special.gammaln((a + d) / 2))
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.5, 1.0, 1.5])
+def test_theorem_3_1_monte_carlo(lam):
+    d = 8
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(d)
+    rps = [rng.standard_normal(d), 0.3 * r + 0.1 * rng.standard_normal(d),
+           np.cross(np.r_[1.0, 0, 0], np.r_[0, 1.0, 0]).tolist() + [0.0] * (d - 3)]
+    rps = [np.asarray(v, dtype=np.float64) for v in rps]
+    acc = np.zeros(len(rps))
+    total = 0
+    for _ in range(8):
+        q = rng.standard_normal((250_000, d))
+        q /= np.linalg.norm(q, axis=1, keepdims=True)
+        w = np.abs(q @ r / np.linalg.norm(r)) ** lam
+        for k, rp in enumerate(rps):
+            acc[k] += np.sum(w * (q @ rp) ** 2)
+        total += q.shape[0]
+    mc = acc / total
+    kappa = (_abs_moment(lam, d) - _abs_moment(lam + 2, d)) / (d - 1)
+    # the oracle's loss for residual r (centroid -r of x = 0) and candidate residual r'
+    C = np.vstack([-r] + [-rp for rp in rps])
+    L = O.soar_losses(np.zeros(d), C, lam, 0)[1:]
+    assert np.allclose(mc / L, kappa, rtol=0.012)
+    # the parallel moment must equal (1 + lambda) kappa, i.e. lambda enters linearly
+    assert _abs_moment(lam + 2, d) == pytest.approx((1 + lam) * kappa, rel=1e-12)
+
+
+def test_lemma_3_2_correlation():
+    d = 10
+    rng = np.random.default_rng(9)
+    r, rp = rng.standard_normal(d), rng.standard_normal(d)
+    q = rng.standard_normal((400_000, d))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    rho = np.corrcoef(q @ r, q @ rp)[0, 1]
+    C = np.vstack([-r, -rp])
+    pen = O.soar_losses(np.zeros(d), C, 1.0, 0)[1] - O.soar_losses(np.zeros(d), C, 0.0, 0)[1]
+    # ||proj_r r'|| = ||r'|| rho
+    assert math.sqrt(pen) == pytest.approx(np.linalg.norm(rp) * abs(rho), rel=0.01)
+
+
+# ------------------------------------------------------------------------------------------------
+# Invariants V1-V6
+# ------------------------------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def rnd_case():
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((2000, 16)).astype(np.float32)
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    C = (rng.standard_normal((64, 16)) * 0.3).astype(np.float32)
+    return X, C
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.5, 1.0, 1.5])
+def test_v1_v2_v4_bounds(rnd_case, lam):
+    X, C = rnd_case
+    p, dp = O.primary_plain(X, C)
+    s, ls = O.spill_plain(X, C, lam, p)
+    D = ((X[:, None, :].astype(np.float64) - C[None].astype(np.float64)) ** 2).sum(-1)
+    d2 = np.partition(D, 1, axis=1)[:, 1]
+    assert np.all(d2 <= ls * (1 + 1e-12))
+    assert np.all(ls <= (1 + lam) * d2 * (1 + 1e-12))
+    if lam == 0.0:
+        assert np.allclose(ls, d2, rtol=1e-13)
+    for i in range(0, 2000, 97):
+        L = O.soar_losses(X[i], C, lam, p[i])
+        assert L[p[i]] == pytest.approx((1 + lam) * dp[i], rel=1e-12)   # V2
+
+
+def test_v3_invariances(rnd_case):
+    X, C = rnd_case
+    lam = 1.0
+    p, _ = O.primary_plain(X, C)
+    s, ls = O.spill_plain(X, C, lam, p)
+    # scaling by 2 is exact: same indices, losses times 4 exactly
+    p2, _ = O.primary_plain(2 * X, 2 * C)
+    s2, ls2 = O.spill_plain(2 * X, 2 * C, lam, p2)
+    assert np.array_equal(p, p2) and np.array_equal(s, s2) and np.array_equal(4 * ls, ls2)
+    # permuting centroids permutes the answer
+    perm = np.random.default_rng(1).permutation(C.shape[0])
+    inv = np.argsort(perm)
+    pp, _ = O.primary_plain(X, C[perm])
+    sp, lsp = O.spill_plain(X, C[perm], lam, pp)
+    assert np.array_equal(perm[pp], p) and np.array_equal(perm[sp], s)
+    assert np.allclose(lsp, ls, rtol=1e-12)
+    assert np.array_equal(inv[p], pp)
+    # rotation and translation (float64 inputs to keep them exact enough)
+    Q, _ = np.linalg.qr(np.random.default_rng(2).standard_normal((16, 16)))
+    v = np.random.default_rng(4).standard_normal(16)
+    for f in (lambda A: A.astype(np.float64) @ Q, lambda A: A.astype(np.float64) + v):
+        pr, _ = O.primary_plain(f(X), f(C))
+        sr, lsr = O.spill_plain(f(X), f(C), lam, pr)
+        assert np.array_equal(pr, p) and np.array_equal(sr, s)
+        assert np.allclose(lsr, ls, rtol=1e-9)
+
+
+def test_v6_lambda_sweep_monotone(rnd_case):
+    """Raising lambda can only raise ||r'||^2 and lower cos^2(r, r') (Figure 9's trend, exact per
+    point for minimisers of f + lambda g)."""
+    X, C = rnd_case
+    X64, C64 = X.astype(np.float64), C.astype(np.float64)
+    p, _ = O.primary_plain(X, C)
+    R = X64 - C64[p]
+    prev_sq, prev_cos = None, None
+    for lam in (0.0, 0.25, 0.5, 1.0, 1.5, 2.0, 4.0):
+        s, _ = O.spill_plain(X, C, lam, p)
+        Rp = X64 - C64[s]
+        sq = (Rp * Rp).sum(1)
+        cos2 = (R * Rp).sum(1) ** 2 / ((R * R).sum(1) * sq)
+        if prev_sq is not None:
+            assert np.all(sq >= prev_sq - 1e-12)
+            assert np.all(cos2 <= prev_cos + 1e-12)
+        prev_sq, prev_cos = sq, cos2
+
+
+def test_fast_equals_plain_bitwise(rnd_case):
+    X, C = rnd_case
+    for lam in (0.0, 1.0, 1.5):
+        a = O.assign(X, C, lam, fast=False)
+        b = O.assign(X, C, lam, fast=True)
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+
+
+def test_input_validation():
+    X = np.zeros((3, 2), np.float32)
+    with pytest.raises(ValueError):
+        O.spill_plain(X, np.zeros((1, 2), np.float32), 1.0)
+    with pytest.raises(ValueError):
+        O.spill_plain(X, np.zeros((2, 2), np.float32), -0.5)
+    with pytest.raises(ValueError):
+        O.spill_fast(X, np.zeros((2, 2), np.float32), float("nan"))
+
+
+# ------------------------------------------------------------------------------------------------
+# KMR (Eq. 1) and Rank (Section 2.1)
+# ------------------------------------------------------------------------------------------------
+def test_rank_and_kmr_bruteforce():
+    rng = np.random.default_rng(13)
+    Q = rng.integers(-2, 3, size=(6, 3)).astype(np.float64)
+    X = rng.integers(-2, 3, size=(25, 3)).astype(np.float32)
+    C = rng.integers(-2, 3, size=(5, 3)).astype(np.float32)
+    ranks = O.partition_ranks(Q, C)
+    for i, q in enumerate(Q):
+        for j, c in enumerate(C):
+            want = sum(1 for c2 in C if float(np.dot(q, c)) <= float(np.dot(q, c2)))
+            assert ranks[i, j] == want
+    k = 3
+    gt = O.mips_topk(Q, X, k)
+    for i, q in enumerate(Q):
+        want = sorted(range(len(X)), key=lambda v: (-float(np.dot(q, X[v])), v))[:k]
+        assert list(gt[i]) == want
+    p, _ = O.primary_plain(X, C)
+    s, _ = O.spill_plain(X, C, 1.0, p)
+    ts = list(range(0, 6))
+    kmr1, searched1 = O.kmr_curve(Q, X, C, [p], k, ts, gt)
+    kmr2, searched2 = O.kmr_curve(Q, X, C, [p, s], k, ts, gt)
+    for t, v in zip(ts, kmr1):
+        want = np.mean([[ranks[i, p[vv]] <= t for vv in gt[i]] for i in range(len(Q))])
+        assert v == pytest.approx(want)
+    assert kmr1[0] == 0.0 and kmr1[-1] == 1.0 and np.all(np.diff(kmr1) >= 0)
+    assert np.all(kmr2 >= kmr1)                        # V7
+    assert searched2[-1] == 2 * len(X) and searched1[-1] == len(X)
+
+
+# ------------------------------------------------------------------------------------------------
+# Lloyd iterations and k-means++ seeding
+# ------------------------------------------------------------------------------------------------
+def test_lloyd_textbook_1d():
+    X = np.array([[0.0], [1.0], [10.0], [11.0]], dtype=np.float32)
+    C = np.array([[0.0], [1.0]])
+    lab, _, C1, counts, _ = O.lloyd_step(X, C, fast=False)
+    assert list(lab) == [0, 1, 1, 1] and list(counts) == [1, 3]
+    assert C1[0, 0] == 0.0 and C1[1, 0] == pytest.approx(22 / 3, rel=1e-15)
+    _, _, C2, _, _ = O.lloyd_step(X, C1, fast=False)
+    assert list(C2[:, 0]) == [0.5, 10.5]
+
+
+def test_lloyd_update_group_means_and_empty():
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((300, 5)).astype(np.float32)
+    lab = rng.integers(0, 7, size=300)
+    lab[lab == 3] = 4                                   # cluster 3 empty
+    Cp = rng.standard_normal((7, 5))
+    C, counts = O.lloyd_update(X, lab, Cp)
+    for j in range(7):
+        rows = [X[i].astype(np.float64) for i in range(300) if lab[i] == j]
+        if rows:
+            assert np.allclose(C[j], np.mean(rows, axis=0), rtol=1e-14, atol=1e-15)
+        else:
+            assert np.array_equal(C[j], Cp[j])
+    assert counts[3] == 0
+    # K = 1 gives the global mean
+    C1, _ = O.lloyd_update(X, np.zeros(300, int), np.zeros((1, 5)))
+    assert np.allclose(C1[0], X.astype(np.float64).mean(0), rtol=1e-13)
+
+
+def test_lloyd_inertia_non_increasing():
+    from synth import MixtureSpec, gen_mixture
+    X = gen_mixture(MixtureSpec(3000, 8, 10, 0.3, "unit", 4))
+    _, _, inertia = O.train_codebook(X, 16, 8, seed=3)
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(inertia, inertia[1:]))
+
+
+def test_kmeanspp_frequencies_chi2():
+    X = np.array([[0, 0], [1, 0], [0, 2], [3, 0], [0, -1]], dtype=np.float32)
+    X64 = X.astype(np.float64)
+    n, N = len(X), 6000
+    first = np.zeros(n)
+    pair = np.zeros((n, n))
+    for seed in range(N):
+        _, rows = O.kmeanspp(X, 2, seed)
+        first[rows[0]] += 1
+        pair[rows[0], rows[1]] += 1
+    assert stats.chisquare(first).pvalue > 1e-3
+    for f in range(n):
+        D2 = ((X64 - X64[f]) ** 2).sum(1)
+        prob = D2 / D2.sum()
+        obs = pair[f]
+        mask = prob > 0
+        assert obs[~mask].sum() == 0                    # never re-pick a chosen row
+        expct = prob[mask] * obs.sum()
+        assert stats.chisquare(obs[mask], expct).pvalue > 1e-3
+
+
+def test_dsq_sample_half_open_intervals():
+    # rows own [prefix_{i-1}, prefix_i); zero-width rows (already chosen) are never drawn
+    D2 = np.array([0.0, 1.0, 0.0, 1.0])
+    assert O.dsq_sample(D2, 0.0) == 1
+    assert O.dsq_sample(D2, 0.5) == 3          # target 1.0 sits on the boundary after row 1
+    assert O.dsq_sample(D2, 0.5 - 2 ** -24) == 1
+    assert O.dsq_sample(np.zeros(3), 0.3) == -1
+
+
+def test_kmeanspp_distinct_and_degenerate():
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((200, 4)).astype(np.float32)
+    _, rows = O.kmeanspp(X, 50, 123)
+    assert len(set(rows.tolist())) == 50
+    Xd = np.ones((6, 3), np.float32)                   # sum D^2 = 0 after the first pick
+    _, rows = O.kmeanspp(Xd, 4, 5)
+    rest = [i for i in range(6) if i != rows[0]][:3]
+    assert list(rows[1:]) == rest
+
+
+def test_judge_accepts_oracle_and_rejects_wrong(rnd_case):
+    X, C = rnd_case
+    p, dp, s, ls = O.assign(X, C, 1.0)
+    j = O.judge(X, C, 1.0, p, s, dp, ls)
+    assert j["all_ok"]
+    bad = s.copy()
+    bad[5] = p[5]                                      # the primary is never a valid spill
+    bad[6] = (s[6] + 1) % C.shape[0] if (s[6] + 1) % C.shape[0] != p[6] else (s[6] + 2) % C.shape[0]
+    j = O.judge(X, C, 1.0, p, bad, dp, ls)
+    assert not j["spill_ok"][5] and not j["spill_ok"][6] and j["spill_ok"].sum() == len(X) - 2
