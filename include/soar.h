@@ -1,0 +1,182 @@
+/*
+ * soar.h -- C ABI of the MI355X (gfx950) SOAR assignment library.
+ *
+ * SOAR ("Spilling with Orthogonality-Amplified Residuals", Sun et al.) gives every datapoint x a
+ * primary VQ partition and one spilled partition:
+ *
+ *   primary   pi(x)  = argmin_j ||x - C_j||^2                              (Section 2.2)
+ *   residual  r      = x - C_pi(x)                                         (Section 3.1)
+ *   spill     pi'(x) = argmin_{j != pi(x)} ||x - C_j||^2
+ *                                + lambda * <r, x - C_j>^2 / ||r||^2        (Section 3.4, Eq. 2
+ *                                                                            via Theorem 3.1)
+ *
+ * and the codebook C is trained by Lloyd k-means seeded by k-means++ (the paper trains VQ "as
+ * usual" before spilling, Section 3.5).
+ *
+ * Conventions for every call:
+ *  - Array arguments are DEVICE pointers unless the comment says "host".  Matrices are row-major
+ *    and contiguous: X is n x d, C is K x d, both float32.  Indices are 0-based int32 (the paper
+ *    numbers partitions from 1).
+ *  - The caller owns every buffer.  The library never frees caller memory and keeps no pointer
+ *    after a call returns, except that a soar_index borrows its arena until soar_index_destroy.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are stream-ordered and, unless
+ *    SOAR_ASYNC is set in a flags field, block until the device work has finished so that the
+ *    returned status covers device-side errors.
+ *  - Validation runs before any launch; on SOAR_E_INVAL / SOAR_E_UNSUPPORTED nothing is written.
+ *    On SOAR_E_NONFINITE (a NaN or Inf in X or C) the outputs have been written but hold no
+ *    meaning.  Nothing aborts and nothing throws across this interface.
+ *  - Ties: an arg-min tie goes to the lowest index.  ||r|| = 0 makes the projection term 0.
+ *    The primary is excluded from the spill by index only.
+ */
+#ifndef SOAR_H
+#define SOAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum soar_status {
+  SOAR_OK = 0,
+  SOAR_E_INVAL = -1,        /* bad argument: sizes, null pointers, lambda, workspace, alignment */
+  SOAR_E_NOMEM = -2,        /* a request does not fit the arena / internal allocation failed     */
+  SOAR_E_DEVICE = -3,       /* a HIP call failed; the device context may be unusable             */
+  SOAR_E_UNSUPPORTED = -4,  /* valid but not implemented for this shape or precision             */
+  SOAR_E_NONFINITE = -5,    /* NaN or Inf found in X or C                                        */
+  SOAR_E_TIMEOUT = -6,      /* soar_wait ran out of time; the ticket stays valid                 */
+  SOAR_E_SHUTDOWN = -7      /* the index is shutting down                                        */
+} soar_status;
+
+typedef enum soar_precision {
+  SOAR_FP32 = 0,            /* both contractions in FP32 on MFMA                                 */
+  SOAR_BF16 = 1,            /* X, C, R as BF16 on MFMA, FP32 accumulate, FP32 re-score of top-k  */
+  SOAR_FP8_E4M3 = 2         /* OCP e4m3 with per-row power-of-two scales, FP32 re-score of top-k */
+} soar_precision;
+
+#define SOAR_ASYNC 1u       /* flags bit: enqueue only; errors surface on the next blocking call */
+
+/* Options of soar_assign.  Set struct_size = sizeof(soar_assign_opts). */
+typedef struct soar_assign_opts {
+  uint32_t struct_size;
+  float lambda;             /* >= 0 and finite; the weight of the parallelism penalty           */
+  int32_t precision;        /* a soar_precision                                                  */
+  int32_t topk;             /* BF16/FP8: candidates re-scored in FP32 per row (0 = 8, max 8)     */
+  float near_tie_rel;       /* relative gap under which FP32 re-scores are decided in FP64
+                               (0 = 1e-5)                                                        */
+  uint32_t flags;           /* SOAR_ASYNC                                                        */
+} soar_assign_opts;
+
+/* Optional statistics of one blocking call (host struct).  Set struct_size. */
+typedef struct soar_stats {
+  uint32_t struct_size;
+  float device_ms;          /* device time from the first to the last kernel of the call         */
+  int64_t rows_full_scan;   /* rows whose candidate set could not be proven complete and were
+                               re-done by an exact scan over all K                               */
+  int64_t rows_fp64;        /* rows whose decision was taken in FP64 (near-ties)                 */
+  double mfma_flops;        /* MFMA flops executed                                               */
+} soar_stats;
+
+/* Bytes of device workspace soar_assign needs for these sizes and options. */
+soar_status soar_assign_workspace_size(int64_t n, int32_t d, int32_t K,
+                                       const soar_assign_opts* opts, size_t* bytes);
+
+/*
+ * SOAR assignment of n points (Section 3.5's indexing step: primary, residual, spill).
+ *   X [n x d], C [K x d]          inputs (device, float32, 16-byte aligned)
+ *   primary [n], spill [n]        outputs (device int32): pi and pi'
+ *   primary_dist [n]              nullable output: ||x - C_pi||^2
+ *   spill_loss [n]                nullable output: the SOAR loss at pi'
+ *   workspace / ws_bytes          device scratch of at least soar_assign_workspace_size bytes
+ *   stats                         nullable host struct, filled by blocking calls
+ * Requires n >= 1, d >= 1, K >= 2.  FP32: any d <= 256.
+ * Accuracy (FP32): indices are exact arg-mins up to near-ties of 1e-6 relative; reported values
+ * are within 1e-5 relative of the exact value at the reported index.
+ */
+soar_status soar_assign(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
+                        const soar_assign_opts* opts, int32_t* primary, int32_t* spill,
+                        float* primary_dist, float* spill_loss, void* workspace, size_t ws_bytes,
+                        void* stream, soar_stats* stats);
+
+/* Bytes of workspace for soar_kmeanspp / soar_lloyd_update / soar_train_codebook. */
+soar_status soar_train_workspace_size(int64_t n, int32_t d, int32_t K, size_t* bytes);
+
+/*
+ * k-means++ seeding.  Round 0 takes row floor(w * n / 2^32); round m >= 1 takes the smallest row i
+ * whose prefix sum of D^2 exceeds u_m * sum(D^2), where D is the distance to the nearest centre
+ * chosen so far and u_m = (w >> 8) * 2^-24.  w is the first word of Philox4x32-10 with counter
+ * (m, 0, 0, 0) and key (seed mod 2^32, seed >> 32).  If sum(D^2) = 0 the lowest-index row not yet
+ * chosen is taken.
+ *   C_out [K x d] (device), rows_out [K] (device, nullable): the chosen rows.
+ * Requires 1 <= K <= n.
+ */
+soar_status soar_kmeanspp(const float* X, int64_t n, int32_t d, int32_t K, uint64_t seed,
+                          float* C_out, int32_t* rows_out, void* workspace, size_t ws_bytes,
+                          void* stream);
+
+/*
+ * One Lloyd update: C_out[j] = mean of the rows with labels == j; a cluster with no rows keeps
+ * C_prev[j].  The per-cluster sums are exact (64-bit fixed point), so the result does not depend
+ * on the order rows are visited in.  counts [K] (device, nullable) receives the cluster sizes.
+ * C_out may equal C_prev.  labels must lie in [0, K).
+ */
+soar_status soar_lloyd_update(const float* X, int64_t n, int32_t d, const int32_t* labels,
+                              int32_t K, const float* C_prev, float* C_out, int32_t* counts,
+                              void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Codebook training: k-means++ (skipped when C_init is given), then exactly `iters` Lloyd
+ * iterations, each an exact nearest-centroid assignment followed by soar_lloyd_update.
+ *   C_init [K x d]        nullable device input (resume from a saved codebook)
+ *   C_out [K x d]         device output: the codebook after the last update
+ *   labels [n]            nullable device output: nearest centroid of every row in C_out
+ *   inertia [iters + 1]   nullable HOST output: sum of squared distances before each update and,
+ *                         last, against C_out
+ * Requires 1 <= K <= n (K >= 2 when the codebook is meant for soar_assign), iters >= 0, d <= 256.
+ */
+soar_status soar_train_codebook(const float* X, int64_t n, int32_t d, int32_t K, int32_t iters,
+                                uint64_t seed, const float* C_init, float* C_out, int32_t* labels,
+                                double* inertia, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- Serving: a resident codebook plus inverted lists (Section 2.2) fed by insert requests ---- */
+
+typedef struct soar_index soar_index;
+
+/*
+ * Create an index over codebook C [K x d] (device, copied into the arena) with spill weight
+ * lambda.  The index places the codebook, its per-step buffers and the partition lists inside
+ * the caller's device arena (arena_bytes) and never allocates device memory of its own.
+ * max_step_rows bounds the rows assigned in one device step.
+ */
+soar_status soar_index_create(const float* C, int32_t K, int32_t d, float lambda,
+                              int32_t precision, void* arena, size_t arena_bytes,
+                              int32_t max_step_rows, soar_index** out);
+
+/*
+ * Queue n vectors (HOST pointer X_host [n x d], copied before the call returns) with ids
+ * first_id .. first_id + n - 1.  Non-blocking: returns a ticket for soar_wait.  Requests are
+ * admitted as step slots and arena memory free up; a request that can never fit the arena gets
+ * SOAR_E_NOMEM.
+ */
+soar_status soar_insert(soar_index* index, const float* X_host, int64_t n, int64_t first_id,
+                        uint64_t* ticket);
+
+/* Wait for a ticket; writes its primary and spill indices to HOST arrays of n entries each. */
+soar_status soar_wait(soar_index* index, uint64_t ticket, int32_t* primary_host,
+                      int32_t* spill_host, double timeout_s);
+
+/* Copy partition `part`'s member ids to a HOST array (at most cap); *len gets the full length. */
+soar_status soar_index_list(soar_index* index, int32_t part, int64_t* ids_host, int64_t cap,
+                            int64_t* len);
+
+/* Drain queued and in-flight work, then release the index's host objects (never the arena). */
+void soar_index_destroy(soar_index* index);
+
+const char* soar_status_string(soar_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOAR_H */

@@ -1,0 +1,211 @@
+"""Python binding of the SOAR gfx950 library (libsoar.so, C ABI in include/soar.h).
+
+Argument marshalling only: tensors are checked for dtype, device and contiguity, workspaces are
+allocated as torch tensors, and every computation runs in the library's HIP kernels.  If the
+library has not been built the import fails loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsoar.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2404_00774_amd.build`"
+                      " (hipcc, gfx950) before importing the binding")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FP32, BF16, FP8_E4M3 = 0, 1, 2
+_PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
+ASYNC = 1
+
+_STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error",
+           -4: "unsupported", -5: "non-finite input", -6: "timeout", -7: "shutdown"}
+
+
+class SoarError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.soar_status_string(status).decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+class AssignOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("lambda_", ctypes.c_float),
+                ("precision", ctypes.c_int32), ("topk", ctypes.c_int32),
+                ("near_tie_rel", ctypes.c_float), ("flags", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("device_ms", ctypes.c_float),
+                ("rows_full_scan", ctypes.c_int64), ("rows_fp64", ctypes.c_int64),
+                ("mfma_flops", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}
+
+
+_vp, _i64, _i32, _u64, _f32, _f64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                     ctypes.c_uint64, ctypes.c_float, ctypes.c_double)
+_sz = ctypes.c_size_t
+
+
+def _sig(name, args, res=ctypes.c_int):
+    fn = getattr(_lib, name, None)
+    if fn is None:
+        return None
+    fn.argtypes, fn.restype = args, res
+    return fn
+
+
+_lib.soar_status_string.argtypes, _lib.soar_status_string.restype = [ctypes.c_int], ctypes.c_char_p
+_sig("soar_assign_workspace_size", [_i64, _i32, _i32, ctypes.POINTER(AssignOpts),
+                                    ctypes.POINTER(_sz)])
+_sig("soar_assign", [_vp, _i64, _i32, _vp, _i32, ctypes.POINTER(AssignOpts), _vp, _vp, _vp, _vp,
+                     _vp, _sz, _vp, ctypes.POINTER(Stats)])
+_sig("soar_train_workspace_size", [_i64, _i32, _i32, ctypes.POINTER(_sz)])
+_sig("soar_kmeanspp", [_vp, _i64, _i32, _i32, _u64, _vp, _vp, _vp, _sz, _vp])
+_sig("soar_lloyd_update", [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp])
+_sig("soar_train_codebook", [_vp, _i64, _i32, _i32, _i32, _u64, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
+_sig("soar_index_create", [_vp, _i32, _i32, _f32, _i32, _vp, _sz, _i32, ctypes.POINTER(_vp)])
+_sig("soar_insert", [_vp, _vp, _i64, _i64, ctypes.POINTER(_u64)])
+_sig("soar_wait", [_vp, _u64, _vp, _vp, _f64])
+_sig("soar_index_list", [_vp, _i32, _vp, _i64, ctypes.POINTER(_i64)])
+_sig("soar_index_destroy", [_vp], None)
+
+EXPORTED = [n for n in ("soar_assign_workspace_size", "soar_assign", "soar_train_workspace_size",
+                        "soar_kmeanspp", "soar_lloyd_update", "soar_train_codebook",
+                        "soar_index_create", "soar_insert", "soar_wait", "soar_index_list",
+                        "soar_index_destroy", "soar_status_string") if hasattr(_lib, n)]
+
+
+def _check(status, where):
+    if status != 0:
+        raise SoarError(status, where)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _f32_matrix(t, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.dim() != 2:
+        raise TypeError(f"{name} must be a 2-D float32 tensor")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be on the GPU")
+    return t.contiguous()
+
+
+def _opts(lam, precision, topk, near_tie_rel, flags):
+    o = AssignOpts()
+    o.struct_size = ctypes.sizeof(AssignOpts)
+    o.lambda_ = float(lam)
+    o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
+    o.topk = int(topk)
+    o.near_tie_rel = float(near_tie_rel)
+    o.flags = int(flags)
+    return o
+
+
+def assign_workspace_size(n, d, K, lam=1.0, precision="fp32", topk=0, near_tie_rel=0.0):
+    o = _opts(lam, precision, topk, near_tie_rel, 0)
+    b = _sz()
+    _check(_lib.soar_assign_workspace_size(n, d, K, ctypes.byref(o), ctypes.byref(b)),
+           "soar_assign_workspace_size")
+    return b.value
+
+
+def assign(X, C, lam, precision="fp32", topk=0, near_tie_rel=0.0, stream=None, out=None,
+           workspace=None, flags=0, stats=False):
+    """SOAR assignment of every row of X against codebook C (both float32 on the GPU).
+
+    Returns (primary int32[n], spill int32[n], primary_dist float32[n], spill_loss float32[n])
+    and, with ``stats=True``, a dict of call statistics as a fifth element."""
+    X, C = _f32_matrix(X, "X"), _f32_matrix(C, "C")
+    n, d = X.shape
+    K = C.shape[0]
+    if C.shape[1] != d:
+        raise ValueError("X and C must have the same number of columns")
+    dev = X.device
+    if out is None:
+        out = (torch.empty(n, dtype=torch.int32, device=dev),
+               torch.empty(n, dtype=torch.int32, device=dev),
+               torch.empty(n, dtype=torch.float32, device=dev),
+               torch.empty(n, dtype=torch.float32, device=dev))
+    o = _opts(lam, precision, topk, near_tie_rel, flags)
+    need = assign_workspace_size(n, d, K, lam, precision, topk, near_tie_rel)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    st = Stats()
+    st.struct_size = ctypes.sizeof(Stats)
+    status = _lib.soar_assign(_ptr(X), n, d, _ptr(C), K, ctypes.byref(o), _ptr(out[0]),
+                              _ptr(out[1]), _ptr(out[2]), _ptr(out[3]), _ptr(workspace),
+                              workspace.numel(), _stream(stream), ctypes.byref(st))
+    _check(status, "soar_assign")
+    return (*out, st.as_dict()) if stats else out
+
+
+def train_workspace_size(n, d, K):
+    b = _sz()
+    _check(_lib.soar_train_workspace_size(n, d, K, ctypes.byref(b)), "soar_train_workspace_size")
+    return b.value
+
+
+def _train_ws(n, d, K, dev):
+    return torch.empty(max(train_workspace_size(n, d, K), 256), dtype=torch.uint8, device=dev)
+
+
+def kmeanspp(X, K, seed, stream=None):
+    """k-means++ seeding with Philox4x32-10 draws. Returns (C float32[K, d], rows int32[K])."""
+    X = _f32_matrix(X, "X")
+    n, d = X.shape
+    C = torch.empty((K, d), dtype=torch.float32, device=X.device)
+    rows = torch.empty(K, dtype=torch.int32, device=X.device)
+    ws = _train_ws(n, d, K, X.device)
+    _check(_lib.soar_kmeanspp(_ptr(X), n, d, K, int(seed), _ptr(C), _ptr(rows), _ptr(ws),
+                              ws.numel(), _stream(stream)), "soar_kmeanspp")
+    return C, rows
+
+
+def lloyd_update(X, labels, C_prev, stream=None):
+    """One Lloyd update. Returns (C float32[K, d], counts int32[K])."""
+    X, C_prev = _f32_matrix(X, "X"), _f32_matrix(C_prev, "C_prev")
+    n, d = X.shape
+    K = C_prev.shape[0]
+    if labels.dtype != torch.int32 or labels.numel() != n or not labels.is_cuda:
+        raise TypeError("labels must be int32[n] on the GPU")
+    labels = labels.contiguous()
+    C = torch.empty_like(C_prev)
+    counts = torch.empty(K, dtype=torch.int32, device=X.device)
+    ws = _train_ws(n, d, K, X.device)
+    _check(_lib.soar_lloyd_update(_ptr(X), n, d, _ptr(labels), K, _ptr(C_prev), _ptr(C),
+                                  _ptr(counts), _ptr(ws), ws.numel(), _stream(stream)),
+           "soar_lloyd_update")
+    return C, counts
+
+
+def train_codebook(X, K, iters, seed=0, C_init=None, stream=None):
+    """k-means++ (unless C_init) then ``iters`` Lloyd iterations.
+
+    Returns (C float32[K, d], labels int32[n], inertia list of iters + 1 floats)."""
+    X = _f32_matrix(X, "X")
+    n, d = X.shape
+    C = torch.empty((K, d), dtype=torch.float32, device=X.device)
+    labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    inertia = (ctypes.c_double * (iters + 1))()
+    ws = _train_ws(n, d, K, X.device)
+    ci = None if C_init is None else _f32_matrix(C_init, "C_init")
+    _check(_lib.soar_train_codebook(_ptr(X), n, d, K, iters, int(seed), _ptr(ci), _ptr(C),
+                                    _ptr(labels), inertia, _ptr(ws), ws.numel(), _stream(stream)),
+           "soar_train_codebook")
+    return C, labels, list(inertia)

@@ -1,0 +1,53 @@
+// Device helpers shared by the SOAR kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace soar {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr float kInf = __builtin_inff();
+constexpr float kU32 = 5.9604644775390625e-08f;   // 2^-24, unit roundoff of float32
+
+// Counters kept in device memory by every assignment call.
+enum Counter : int {
+  CNT_FULLSCAN = 0,   // rows sent to the exact full scan
+  CNT_NONFINITE = 1,  // set when a NaN/Inf was read from X or C
+  CNT_FP64 = 2,       // rows whose decision was taken in FP64
+  CNT_CMAX2 = 3,      // max_j ||c_j||^2 as float bits (non-negative floats order like uints)
+  CNT_WORDS = 8
+};
+
+__device__ __forceinline__ bool all_finite4(v4f v) {
+  return __builtin_isfinite(v.x) && __builtin_isfinite(v.y) && __builtin_isfinite(v.z) &&
+         __builtin_isfinite(v.w);
+}
+
+// Sum over the 4 lanes that share (lane & 15): lanes l, l^16, l^32, l^48.
+__device__ __forceinline__ float sum_quad_f(float v) {
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+__device__ __forceinline__ double sum_quad_d(double v) {
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+// (value, index) lexicographic minimum over the 16 lanes of a lane group (lane >> 4 fixed).
+__device__ __forceinline__ void argmin16(float& v, int& j) {
+#pragma unroll
+  for (int off = 1; off < 16; off <<= 1) {
+    float ov = __shfl_xor(v, off);
+    int oj = __shfl_xor(j, off);
+    if (ov < v || (ov == v && oj < j)) { v = ov; j = oj; }
+  }
+}
+
+__device__ __forceinline__ void argmin_d(double& v, int& j, double ov, int oj) {
+  if (ov < v || (ov == v && oj < j)) { v = ov; j = oj; }
+}
+
+}  // namespace soar

@@ -1,0 +1,197 @@
+// C-ABI entry points of the SOAR library: argument validation, workspace layout, launches and
+// status reporting.  Every computation runs in the HIP kernels; this file only plans and orders
+// them on the caller's stream.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/soar.h"
+#include "common.h"
+#include "kernels.h"
+#include "train.h"
+
+namespace {
+
+using soar::AssignParams;
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Carves a caller-provided workspace into aligned sub-buffers.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* p) : base(static_cast<char*>(p)) {}
+  template <typename T>
+  T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+inline soar_status dev_err(hipError_t e) { return e == hipSuccess ? SOAR_OK : SOAR_E_DEVICE; }
+
+struct OptsView {
+  float lambda = 1.f;
+  int precision = SOAR_FP32;
+  int topk = 0;
+  float near_tie_rel = 0.f;
+  uint32_t flags = 0;
+};
+
+bool read_opts(const soar_assign_opts* o, OptsView* v) {
+  if (!o || o->struct_size < offsetof(soar_assign_opts, flags) + sizeof(uint32_t)) return false;
+  v->lambda = o->lambda;
+  v->precision = o->precision;
+  v->topk = o->topk;
+  v->near_tie_rel = o->near_tie_rel;
+  v->flags = o->flags;
+  return true;
+}
+
+soar_status validate_assign(int64_t n, int32_t d, int32_t K, const OptsView& o) {
+  if (n < 1 || n > INT32_MAX || d < 1 || K < 2) return SOAR_E_INVAL;
+  if (!std::isfinite(o.lambda) || o.lambda < 0.f) return SOAR_E_INVAL;
+  if (!(o.near_tie_rel >= 0.f) || !std::isfinite(o.near_tie_rel)) return SOAR_E_INVAL;
+  if (o.precision != SOAR_FP32) return SOAR_E_UNSUPPORTED;
+  if (soar::fp32_padded_dim(d) < 0) return SOAR_E_UNSUPPORTED;
+  return SOAR_OK;
+}
+
+struct AssignLayout {
+  unsigned* counters;
+  float* cnorm;
+  int32_t* full_rows;
+  size_t bytes;
+};
+
+AssignLayout layout_assign(void* ws, int64_t n, int32_t K) {
+  Carver c(ws);
+  AssignLayout L;
+  L.counters = c.take<unsigned>(soar::CNT_WORDS);
+  L.cnorm = c.take<float>((size_t)K);
+  L.full_rows = c.take<int32_t>((size_t)n);
+  L.bytes = c.off;
+  return L;
+}
+
+}  // namespace
+
+namespace soar {
+
+// Screening bands (rounding-error bounds of the expanded ranking values; see assign_fp32.hip).
+float band_coef_primary(int d) { return 8.f * (float)(d + 2) * kU32; }
+float band_coef_spill(int d, float lam) { return 4.f * (float)(d + 3) * kU32 * (2.f + 3.f * lam); }
+float tie_threshold(int d, float lam, float near_tie_rel) {
+  const float rel = near_tie_rel > 0.f ? near_tie_rel : 1e-5f;
+  const float err = (1.f + 3.f * lam) * ((float)d / 16.f + 6.f) * kU32;
+  return fmaxf(rel, 3.f * err);
+}
+
+// Shared by soar_assign and the training loop: primary-only (labels) or full SOAR.
+soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
+                            float lam, float near_tie_rel, bool spill, int32_t* primary,
+                            int32_t* spill_out, float* pdist, float* sloss, void* ws,
+                            hipStream_t st, unsigned* counters_out_host) {
+  AssignLayout L = layout_assign(ws, n, K);
+  AssignParams P;
+  P.X = X; P.n = n; P.d = d; P.C = C; P.K = K;
+  P.cnorm = L.cnorm; P.counters = L.counters;
+  P.lam = lam;
+  P.tie_rel = tie_threshold(d, lam, near_tie_rel);
+  P.band_p = band_coef_primary(d);
+  P.band_s = band_coef_spill(d, lam);
+  P.primary = primary; P.spill = spill_out; P.pdist = pdist; P.sloss = sloss;
+  P.full_rows = L.full_rows;
+  const bool vec = (d % 4 == 0) && aligned(X, 16) && aligned(C, 16);
+  hipError_t e = launch_prep_codebook(C, K, d, L.cnorm, L.counters, st);
+  if (e == hipSuccess) e = launch_assign_fp32(P, spill, vec, st);
+  if (e != hipSuccess) return SOAR_E_DEVICE;
+  if (counters_out_host) {
+    e = hipMemcpyAsync(counters_out_host, L.counters, CNT_WORDS * sizeof(unsigned),
+                       hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return SOAR_E_DEVICE;
+  }
+  return SOAR_OK;
+}
+
+size_t assign_workspace_bytes(int64_t n, int32_t K) { return layout_assign(nullptr, n, K).bytes; }
+
+}  // namespace soar
+
+extern "C" {
+
+const char* soar_status_string(soar_status s) {
+  switch (s) {
+    case SOAR_OK: return "ok";
+    case SOAR_E_INVAL: return "invalid argument";
+    case SOAR_E_NOMEM: return "out of memory (arena or request too large)";
+    case SOAR_E_DEVICE: return "device error";
+    case SOAR_E_UNSUPPORTED: return "unsupported shape or precision";
+    case SOAR_E_NONFINITE: return "non-finite value in X or C";
+    case SOAR_E_TIMEOUT: return "timed out";
+    case SOAR_E_SHUTDOWN: return "index is shutting down";
+  }
+  return "unknown status";
+}
+
+soar_status soar_assign_workspace_size(int64_t n, int32_t d, int32_t K,
+                                       const soar_assign_opts* opts, size_t* bytes) {
+  OptsView o;
+  if (!bytes || !read_opts(opts, &o)) return SOAR_E_INVAL;
+  const soar_status s = validate_assign(n, d, K, o);
+  if (s != SOAR_OK) return s;
+  *bytes = soar::assign_workspace_bytes(n, K);
+  return SOAR_OK;
+}
+
+soar_status soar_assign(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
+                        const soar_assign_opts* opts, int32_t* primary, int32_t* spill,
+                        float* primary_dist, float* spill_loss, void* workspace, size_t ws_bytes,
+                        void* stream, soar_stats* stats) {
+  OptsView o;
+  if (!read_opts(opts, &o)) return SOAR_E_INVAL;
+  soar_status s = validate_assign(n, d, K, o);
+  if (s != SOAR_OK) return s;
+  if (!X || !C || !primary || !spill || !workspace) return SOAR_E_INVAL;
+  if (!aligned(X, 4) || !aligned(C, 4) || !aligned(workspace, kAlign)) return SOAR_E_INVAL;
+  if (ws_bytes < soar::assign_workspace_bytes(n, K)) return SOAR_E_INVAL;
+  if (stats && stats->struct_size < sizeof(soar_stats)) return SOAR_E_INVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool async = (o.flags & SOAR_ASYNC) != 0;
+
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (!async && stats) {
+    if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+      return SOAR_E_DEVICE;
+    (void)hipEventRecord(ev0, st);
+  }
+  unsigned cnt[soar::CNT_WORDS] = {0};
+  s = soar::run_assign_fp32(X, n, d, C, K, o.lambda, o.near_tie_rel, true, primary, spill,
+                            primary_dist, spill_loss, workspace, st, async ? nullptr : cnt);
+  if (s != SOAR_OK || async) {
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    return s;
+  }
+  if (stats) (void)hipEventRecord(ev1, st);
+  s = dev_err(hipStreamSynchronize(st));
+  if (s == SOAR_OK && stats) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev0, ev1);
+    stats->device_ms = ms;
+    stats->rows_full_scan = cnt[soar::CNT_FULLSCAN];
+    stats->rows_fp64 = cnt[soar::CNT_FP64];
+    stats->mfma_flops = 6.0 * (double)n * (double)K * (double)soar::fp32_padded_dim(d);
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (s == SOAR_OK && cnt[soar::CNT_NONFINITE]) s = SOAR_E_NONFINITE;
+  return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,16 @@
+// Internal interface of the codebook-training kernels (k-means++ and Lloyd updates).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/soar.h"
+
+namespace soar {
+
+soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
+                            float lam, float near_tie_rel, bool spill, int32_t* primary,
+                            int32_t* spill_out, float* pdist, float* sloss, void* ws,
+                            hipStream_t st, unsigned* counters_out_host);
+size_t assign_workspace_bytes(int64_t n, int32_t K);
+
+}  // namespace soar
