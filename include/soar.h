@@ -72,6 +72,7 @@ typedef struct soar_assign_opts {
 typedef struct soar_stats {
   uint32_t struct_size;
   float device_ms;          /* device time from the first to the last kernel of the call         */
+  float assign_kernel_ms;   /* device time of the main assignment kernel alone (HIP events)      */
   int64_t rows_full_scan;   /* rows whose candidate set could not be proven complete and were
                                re-done by an exact scan over all K                               */
   int64_t rows_fp64;        /* rows whose decision was taken in FP64 (near-ties)                 */

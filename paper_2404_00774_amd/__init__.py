@@ -43,7 +43,7 @@ class AssignOpts(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("device_ms", ctypes.c_float),
-                ("rows_full_scan", ctypes.c_int64), ("rows_fp64", ctypes.c_int64),
+                ("assign_kernel_ms", ctypes.c_float), ("rows_full_scan", ctypes.c_int64), ("rows_fp64", ctypes.c_int64),
                 ("mfma_flops", ctypes.c_double)]
 
     def as_dict(self):

@@ -623,8 +623,10 @@ hipError_t launch_prep_codebook(const float* C, int K, int d, float* cnorm, unsi
   return hipGetLastError();
 }
 
-hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipStream_t st) {
+hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipStream_t st,
+                              hipEvent_t ev_begin, hipEvent_t ev_end) {
   hipError_t e;
+  if (ev_begin) (void)hipEventRecord(ev_begin, st);
   switch (fp32_padded_dim(P.d)) {
     case 16: e = launch_dp<16, 64>(P, spill, vec, st); break;
     case 32: e = launch_dp<32, 64>(P, spill, vec, st); break;
@@ -637,6 +639,7 @@ hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipSt
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
+  if (ev_end) (void)hipEventRecord(ev_end, st);
   const size_t smem = (size_t)3 * P.d * sizeof(float);
   if (spill)
     hipLaunchKernelGGL(full_scan_kernel<true>, dim3(1024), dim3(FS_THREADS), smem, st, P);

@@ -27,6 +27,8 @@ struct AssignParams {
 int fp32_padded_dim(int d);
 hipError_t launch_prep_codebook(const float* C, int K, int d, float* cnorm, unsigned* counters,
                                 hipStream_t st);
-hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipStream_t st);
+// ev_begin / ev_end (nullable) are recorded around the main assignment kernel alone.
+hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipStream_t st,
+                              hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
 
 }  // namespace soar

@@ -96,7 +96,8 @@ float tie_threshold(int d, float lam, float near_tie_rel) {
 soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
                             float lam, float near_tie_rel, bool spill, int32_t* primary,
                             int32_t* spill_out, float* pdist, float* sloss, void* ws,
-                            hipStream_t st, unsigned* counters_out_host) {
+                            hipStream_t st, unsigned* counters_out_host,
+                            hipEvent_t ev_kernel_begin, hipEvent_t ev_kernel_end) {
   AssignLayout L = layout_assign(ws, n, K);
   AssignParams P;
   P.X = X; P.n = n; P.d = d; P.C = C; P.K = K;
@@ -109,7 +110,7 @@ soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C
   P.full_rows = L.full_rows;
   const bool vec = (d % 4 == 0) && aligned(X, 16) && aligned(C, 16);
   hipError_t e = launch_prep_codebook(C, K, d, L.cnorm, L.counters, st);
-  if (e == hipSuccess) e = launch_assign_fp32(P, spill, vec, st);
+  if (e == hipSuccess) e = launch_assign_fp32(P, spill, vec, st, ev_kernel_begin, ev_kernel_end);
   if (e != hipSuccess) return SOAR_E_DEVICE;
   if (counters_out_host) {
     e = hipMemcpyAsync(counters_out_host, L.counters, CNT_WORDS * sizeof(unsigned),
@@ -164,32 +165,37 @@ soar_status soar_assign(const float* X, int64_t n, int32_t d, const float* C, in
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool async = (o.flags & SOAR_ASYNC) != 0;
 
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  auto destroy = [&]() {
+    for (hipEvent_t& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  };
   if (!async && stats) {
-    if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
-      return SOAR_E_DEVICE;
-    (void)hipEventRecord(ev0, st);
+    for (hipEvent_t& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) { destroy(); return SOAR_E_DEVICE; }
+    (void)hipEventRecord(ev[0], st);
   }
   unsigned cnt[soar::CNT_WORDS] = {0};
   s = soar::run_assign_fp32(X, n, d, C, K, o.lambda, o.near_tie_rel, true, primary, spill,
-                            primary_dist, spill_loss, workspace, st, async ? nullptr : cnt);
+                            primary_dist, spill_loss, workspace, st, async ? nullptr : cnt, ev[1],
+                            ev[2]);
   if (s != SOAR_OK || async) {
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
+    destroy();
     return s;
   }
-  if (stats) (void)hipEventRecord(ev1, st);
+  if (stats) (void)hipEventRecord(ev[3], st);
   s = dev_err(hipStreamSynchronize(st));
   if (s == SOAR_OK && stats) {
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, ev0, ev1);
+    float ms = 0.f, kms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[3]);
+    (void)hipEventElapsedTime(&kms, ev[1], ev[2]);
     stats->device_ms = ms;
+    stats->assign_kernel_ms = kms;
     stats->rows_full_scan = cnt[soar::CNT_FULLSCAN];
     stats->rows_fp64 = cnt[soar::CNT_FP64];
     stats->mfma_flops = 6.0 * (double)n * (double)K * (double)soar::fp32_padded_dim(d);
   }
-  if (ev0) (void)hipEventDestroy(ev0);
-  if (ev1) (void)hipEventDestroy(ev1);
+  destroy();
   if (s == SOAR_OK && cnt[soar::CNT_NONFINITE]) s = SOAR_E_NONFINITE;
   return s;
 }

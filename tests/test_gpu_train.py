@@ -1,0 +1,172 @@
+"""GPU parity of codebook training (Lloyd update, Lloyd iterations, k-means++) against the oracle."""
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle as O
+from oracle.philox import philox_index, philox_uniform24
+from synth import MixtureSpec, WORKLOADS, gen_mixture
+
+pytestmark = pytest.mark.gpu
+
+
+def _soar():
+    import paper_2404_00774_amd as soar
+    return soar
+
+
+def _t(a, dtype=np.float32):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def _c_close(Cg, Co):
+    """Per-row tolerance 1e-5 * max(1, ||c||) between a GPU and an oracle codebook."""
+    err = np.abs(Cg.astype(np.float64) - Co).max(axis=1)
+    tol = 1e-5 * np.maximum(1.0, np.linalg.norm(Co, axis=1))
+    return np.all(err <= tol), float((err / tol).max())
+
+
+@pytest.mark.parametrize("n,d,K", [(5000, 64, 37), (3001, 3, 5), (777, 200, 64), (10, 7, 1),
+                                   (300, 130, 400)])
+def test_lloyd_update_parity_and_order_independence(n, d, K):
+    print(f"lloyd_update n={n} d={d} K={K}", flush=True)
+    soar = _soar()
+    rng = np.random.default_rng(n + d + K)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    lab = rng.integers(0, K, n).astype(np.int32)
+    if K > 3:
+        lab[lab == 2] = 1                          # an empty cluster keeps its centroid
+    Cp = rng.standard_normal((K, d)).astype(np.float32)
+    Cg, cnt = soar.lloyd_update(_t(X), _t(lab, np.int32), _t(Cp))
+    Co, co = O.lloyd_update(X, lab, Cp)
+    ok, worst = _c_close(Cg.cpu().numpy(), Co)
+    assert ok, worst
+    assert np.array_equal(cnt.cpu().numpy(), co)
+    if K > 3:
+        assert np.array_equal(Cg.cpu().numpy()[2], Cp[2])
+    # exact fixed-point sums: any row order gives the same bits
+    perm = rng.permutation(n)
+    Cg2, _ = soar.lloyd_update(_t(X[perm]), _t(lab[perm], np.int32), _t(Cp))
+    assert np.array_equal(Cg.cpu().numpy(), Cg2.cpu().numpy())
+
+
+def test_lloyd_update_rejects_bad_labels():
+    soar = _soar()
+    X = np.zeros((10, 4), np.float32)
+    lab = np.zeros(10, np.int32)
+    lab[3] = 5
+    with pytest.raises(soar.SoarError) as e:
+        soar.lloyd_update(_t(X), _t(lab, np.int32), _t(np.zeros((5, 4))))
+    assert e.value.status == -1
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = WORKLOADS["mix64_n20k_d64"]
+    X = gen_mixture(w["spec"])
+    return X, w
+
+
+def test_lloyd_iterations_per_step(small):
+    """Feed the same C_t to both sides: labels by the acceptance rule, C_{t+1} within tolerance."""
+    soar = _soar()
+    X, w = small
+    K = w["K"]
+    Ct, _ = O.kmeanspp(X, K, 0)
+    for it in range(3):
+        print(f"lloyd step {it}", flush=True)
+        Cg0, lab0, in0 = soar.train_codebook(_t(X), K, 0, C_init=_t(Ct))
+        lab0 = lab0.cpu().numpy()
+        j = O.judge(X, Ct.astype(np.float32), 0.0, lab0, (lab0 + 1) % K)
+        assert j["primary_ok"].all()
+        assert in0[0] == pytest.approx(float(j["d_star"].sum()), rel=1e-5)
+        Cg1, _, in1 = soar.train_codebook(_t(X), K, 1, C_init=_t(Ct))
+        Co1, _ = O.lloyd_update(X, lab0, Ct.astype(np.float32))
+        ok, worst = _c_close(Cg1.cpu().numpy(), Co1)
+        assert ok, worst
+        assert in1[0] == pytest.approx(in0[0], rel=0, abs=0)
+        Ct = Co1
+
+
+def test_train_end_to_end_inertia(small):
+    soar = _soar()
+    X, w = small
+    Cg, labg, inertia = soar.train_codebook(_t(X), w["K"], w["iters"], seed=0)
+    Co, labo, inertia_o = O.train_codebook(X, w["K"], w["iters"], seed=0)
+    print("inertia gpu", inertia[-1], "oracle", inertia_o[-1], flush=True)
+    assert all(b <= a * (1 + 1e-6) for a, b in zip(inertia, inertia[1:]))
+    # trajectories may part after a near-tie flip; the end result must be as good
+    assert abs(inertia[-1] - inertia_o[-1]) <= 1e-3 * inertia_o[-1]
+    j = O.judge(X, Cg.cpu().numpy(), 0.0, labg.cpu().numpy(), (labg.cpu().numpy() + 1) % w["K"])
+    assert j["primary_ok"].all()
+
+
+def _replay_kmeanspp(X, rows, seed, tol=1e-5):
+    """Check every GPU pick against the oracle's D^2 draw, given the GPU's earlier picks."""
+    X64 = X.astype(np.float64)
+    n = len(X)
+    assert rows[0] == philox_index(seed, 0, n)
+    D2 = ((X64 - X64[rows[0]]) ** 2).sum(1)
+    for m in range(1, len(rows)):
+        pref = np.cumsum(D2)
+        S = pref[-1]
+        i = int(rows[m])
+        if S > 0:
+            target = philox_uniform24(seed, m) * S
+            lo = pref[i - 1] if i > 0 else 0.0
+            assert D2[i] > 0, (m, i)
+            assert lo - tol * S <= target <= pref[i] + tol * S, (m, i, lo, target, pref[i])
+        D2 = np.minimum(D2, ((X64 - X64[i]) ** 2).sum(1))
+
+
+@pytest.mark.parametrize("n,d,K,seed", [(20_000, 64, 256, 0), (5000, 3, 50, 11),
+                                        (3000, 130, 20, 2)])
+def test_kmeanspp_conditional_parity(n, d, K, seed):
+    soar = _soar()
+    X = gen_mixture(MixtureSpec(n, d, 16, 0.3, "unit", seed))
+    C, rows = soar.kmeanspp(_t(X), K, seed)
+    rows = rows.cpu().numpy()
+    assert len(set(rows.tolist())) == K
+    assert np.array_equal(C.cpu().numpy(), X[rows])
+    _replay_kmeanspp(X, rows, seed)
+
+
+def test_kmeanspp_exact_on_integer_data():
+    soar = _soar()
+    rng = np.random.default_rng(3)
+    X = rng.integers(-3, 4, size=(400, 3)).astype(np.float32)
+    for seed in (1, 2, 3):
+        _, rows = soar.kmeanspp(_t(X), 30, seed)
+        _, orows = O.kmeanspp(X, 30, seed)
+        assert np.array_equal(rows.cpu().numpy(), orows)
+
+
+def test_kmeanspp_frequencies_chi2():
+    soar = _soar()
+    X = np.array([[0, 0], [1, 0], [0, 2], [3, 0], [0, -1]], dtype=np.float32)
+    X64 = X.astype(np.float64)
+    Xt = _t(X)
+    n, N = 5, 3000
+    first = np.zeros(n)
+    pair = np.zeros((n, n))
+    for seed in range(N):
+        _, rows = soar.kmeanspp(Xt, 2, seed)
+        r = rows.cpu().numpy()
+        first[r[0]] += 1
+        pair[r[0], r[1]] += 1
+    assert stats.chisquare(first).pvalue > 1e-3
+    for f in range(n):
+        D2 = ((X64 - X64[f]) ** 2).sum(1)
+        prob = D2 / D2.sum()
+        mask = prob > 0
+        assert pair[f][~mask].sum() == 0
+        assert stats.chisquare(pair[f][mask], prob[mask] * pair[f].sum()).pvalue > 1e-3
+
+
+def test_kmeanspp_degenerate_all_equal():
+    soar = _soar()
+    X = np.ones((6, 3), np.float32)
+    _, rows = soar.kmeanspp(_t(X), 4, 5)
+    _, orows = O.kmeanspp(X, 4, 5)
+    assert np.array_equal(rows.cpu().numpy(), orows)
