@@ -390,111 +390,102 @@ __global__ __launch_bounds__(256) void assign_f32_kernel(AssignParams P) {
 
 // ------------------------------------------------------------------------------------------------
 // Exact full scan over all K for the rows listed by the assignment kernel (one workgroup a row).
+// Each wave takes one centroid at a time with its lanes across the dimensions (coalesced loads),
+// and a 64-lane tree gives the sum (at most 4 sequential terms per lane for d <= 256).
 // ------------------------------------------------------------------------------------------------
 constexpr int FS_THREADS = 256;
+constexpr int FS_WAVES = FS_THREADS / 64;
 
-__device__ __forceinline__ float fs_sq32(const float* __restrict__ x, const float* __restrict__ c,
-                                         int d) {
-  float acc[16];
+__device__ __forceinline__ float wave_sum_f(float v) {
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-  for (int k = 0; k < d; k += 16) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-      if (k + i < d) { const float e = x[k + i] - c[k + i]; acc[i] = fmaf(e, e, acc[i]); }
-  }
-#pragma unroll
-  for (int h = 8; h >= 1; h >>= 1)
-#pragma unroll
-    for (int i = 0; i < h; ++i) acc[i] += acc[i + h];
-  return acc[0];
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
 }
 
-__device__ __forceinline__ float fs_spill32(const float* __restrict__ x, const float* __restrict__ r,
-                                            float rr, float lam, const float* __restrict__ c,
-                                            int d) {
-  float sq[8], pj[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) sq[i] = pj[i] = 0.f;
-  for (int k = 0; k < d; k += 8) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (k + i < d) {
-        const float e = x[k + i] - c[k + i];
-        sq[i] = fmaf(e, e, sq[i]);
-        pj[i] = fmaf(r[k + i], e, pj[i]);
-      }
+// FP32 value of centroid j for this row: ||x - c||^2, or the SOAR loss given r and ||r||^2.
+template <bool SP>
+__device__ __forceinline__ float fs_value32(const float* __restrict__ c, const float* sx,
+                                            const float* sr, float rr, float lam, int d, int lane) {
+  float sq = 0.f, pj = 0.f;
+  for (int k = lane; k < d; k += 64) {
+    const float e = sx[k] - c[k];
+    sq = fmaf(e, e, sq);
+    if (SP) pj = fmaf(sr[k], e, pj);
   }
-#pragma unroll
-  for (int h = 4; h >= 1; h >>= 1)
-#pragma unroll
-    for (int i = 0; i < h; ++i) { sq[i] += sq[i + h]; pj[i] += pj[i + h]; }
-  return rr > 0.f ? sq[0] + lam * (pj[0] * pj[0]) / rr : sq[0];
+  sq = wave_sum_f(sq);
+  if (!SP) return sq;
+  pj = wave_sum_f(pj);
+  return rr > 0.f ? sq + lam * (pj * pj) / rr : sq;
 }
 
-__device__ __forceinline__ double fs_exact64(const float* __restrict__ x,
-                                             const float* __restrict__ cp, bool sp, float lam,
-                                             const float* __restrict__ c, int d) {
+// FP64 value with the residual formed exactly from C[pi] (near-tie decisions).
+template <bool SP>
+__device__ __forceinline__ double fs_value64(const float* __restrict__ c, const float* sx,
+                                             const float* scp, float lam, int d, int lane) {
   double sq = 0.0, pj = 0.0, rr = 0.0;
-  for (int k = 0; k < d; ++k) {
-    const double e = (double)x[k] - (double)c[k];
+  for (int k = lane; k < d; k += 64) {
+    const double e = (double)sx[k] - (double)c[k];
     sq = fma(e, e, sq);
-    if (sp) {
-      const double rk = (double)x[k] - (double)cp[k];
+    if (SP) {
+      const double rk = (double)sx[k] - (double)scp[k];
       pj = fma(rk, e, pj);
       rr = fma(rk, rk, rr);
     }
   }
-  return (sp && rr > 0.0) ? sq + (double)lam * (pj * pj) / rr : sq;
+  sq = wave_sum_d(sq);
+  if (!SP) return sq;
+  pj = wave_sum_d(pj);
+  rr = wave_sum_d(rr);
+  return rr > 0.0 ? sq + (double)lam * (pj * pj) / rr : sq;
 }
 
 template <typename T>
-__device__ __forceinline__ void block_argmin(T& v, int& j, T* sv, int* sj) {
-  const int tid = threadIdx.x;
-  sv[tid] = v;
-  sj[tid] = j;
+__device__ __forceinline__ void wg_argmin(T& v, int& j, T* sv, int* sj) {
+  const int tid = threadIdx.x, w = tid >> 6;
+  if ((tid & 63) == 0) { sv[w] = v; sj[w] = j; }
   __syncthreads();
-  for (int h = FS_THREADS / 2; h >= 1; h >>= 1) {
-    if (tid < h) {
-      const T ov = sv[tid + h];
-      const int oj = sj[tid + h];
-      if (ov < sv[tid] || (ov == sv[tid] && oj < sj[tid])) { sv[tid] = ov; sj[tid] = oj; }
-    }
-    __syncthreads();
+  if (tid == 0) {
+    for (int i = 1; i < FS_WAVES; ++i)
+      if (sv[i] < sv[0] || (sv[i] == sv[0] && sj[i] < sj[0])) { sv[0] = sv[i]; sj[0] = sj[i]; }
   }
+  __syncthreads();
   v = sv[0];
   j = sj[0];
   __syncthreads();
 }
 
-// Exact arg-min over all columns j != skip of f(j) = FP32 direct value; near-ties in FP64.
+// Exact arg-min over all columns j != skip; FP32 direct values, then FP64 among near-ties.
 template <bool SP>
 __device__ void fs_argmin(const AssignParams& P, const float* sx, const float* sr, float rr,
                           const float* scp, int skip, int& out_j, float& out_v) {
-  __shared__ float rv[FS_THREADS];
-  __shared__ int rj[FS_THREADS];
-  __shared__ double rd[FS_THREADS];
-  const int tid = threadIdx.x, K = P.K, d = P.d;
+  __shared__ float rv[FS_WAVES];
+  __shared__ int rj[FS_WAVES];
+  __shared__ double rd[FS_WAVES];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, K = P.K, d = P.d;
   float bv = kInf;
   int bj = 0x7fffffff;
-  for (int j = tid; j < K; j += FS_THREADS) {
+  for (int j = w; j < K; j += FS_WAVES) {
     if (j == skip) continue;
-    const float* c = P.C + (int64_t)j * d;
-    const float v = SP ? fs_spill32(sx, sr, rr, P.lam, c, d) : fs_sq32(sx, c, d);
+    const float v = fs_value32<SP>(P.C + (int64_t)j * d, sx, sr, rr, P.lam, d, lane);
     if (v < bv) { bv = v; bj = j; }
   }
-  block_argmin<float>(bv, bj, rv, rj);
+  wg_argmin<float>(bv, bj, rv, rj);
   if (!(bv < kInf)) { out_j = -1; out_v = kInf; return; }
   const float lim = bv + bv * P.tie_rel;
   double dv = __builtin_inf();
   int dj = 0x7fffffff;
-  for (int j = tid; j < K; j += FS_THREADS) {
+  for (int j = w; j < K; j += FS_WAVES) {
     if (j == skip) continue;
     const float* c = P.C + (int64_t)j * d;
-    const float v = SP ? fs_spill32(sx, sr, rr, P.lam, c, d) : fs_sq32(sx, c, d);
-    if (v <= lim) argmin_d(dv, dj, fs_exact64(sx, scp, SP, P.lam, c, d), j);
+    const float v = fs_value32<SP>(c, sx, sr, rr, P.lam, d, lane);
+    if (v <= lim) argmin_d(dv, dj, fs_value64<SP>(c, sx, scp, P.lam, d, lane), j);
   }
-  block_argmin<double>(dv, dj, rd, rj);
+  wg_argmin<double>(dv, dj, rd, rj);
   out_j = dj;
   out_v = (float)dv;
 }
@@ -505,8 +496,9 @@ __global__ __launch_bounds__(FS_THREADS) void full_scan_kernel(AssignParams P) {
   float* sx = fs_smem;
   float* sr = fs_smem + P.d;
   float* scp = fs_smem + 2 * P.d;
+  __shared__ float s_rr;
   const unsigned count = P.counters[CNT_FULLSCAN];
-  const int d = P.d, tid = threadIdx.x;
+  const int d = P.d, tid = threadIdx.x, lane = tid & 63;
   for (unsigned e = blockIdx.x; e < count; e += gridDim.x) {
     const int64_t row = P.full_rows[e];
     for (int k = tid; k < d; k += FS_THREADS) sx[k] = P.X[row * d + k];
@@ -521,29 +513,24 @@ __global__ __launch_bounds__(FS_THREADS) void full_scan_kernel(AssignParams P) {
       atomicAdd(&P.counters[CNT_FP64], 1u);
     }
     if (SPILL) {
-      if (pi >= 0) {
+      if (pi >= 0)
         for (int k = tid; k < d; k += FS_THREADS) {
           const float c = P.C[(int64_t)pi * d + k];
           scp[k] = c;
           sr[k] = sx[k] - c;
         }
+      __syncthreads();
+      if (tid < 64) {
+        float a = 0.f;
+        for (int k = lane; k < d; k += 64) a = fmaf(sr[k], sr[k], a);
+        a = wave_sum_f(a);
+        if (tid == 0) s_rr = a;
       }
       __syncthreads();
       int sj = -1;
       float sl = kInf;
       if (pi >= 0) {
-        float acc[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] = 0.f;
-        for (int k = 0; k < d; k += 8)
-#pragma unroll
-          for (int i = 0; i < 8; ++i)
-            if (k + i < d) acc[i] = fmaf(sr[k + i], sr[k + i], acc[i]);
-#pragma unroll
-        for (int h = 4; h >= 1; h >>= 1)
-#pragma unroll
-          for (int i = 0; i < h; ++i) acc[i] += acc[i + h];
-        fs_argmin<true>(P, sx, sr, acc[0], scp, pi, sj, sl);
+        fs_argmin<true>(P, sx, sr, s_rr, scp, pi, sj, sl);
         if (sj >= P.K) sj = -1;
       }
       if (tid == 0) {

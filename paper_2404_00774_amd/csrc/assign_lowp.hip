@@ -1,0 +1,593 @@
+// Low-precision SOAR assignment on gfx950: the two contractions X C^T and R C^T in BF16
+// (v_mfma_f32_16x16x32_bf16) or OCP FP8-e4m3 (v_mfma_scale_f32_16x16x128_f8f6f4, unit block
+// scales) with FP32 accumulation, followed by an FP32 re-score of a few candidates per row by
+// direct differences and an FP64 decision among near-ties.  Same loss as the FP32 path:
+//     primary  argmin_j ||x - c_j||^2                               (Section 2.2)
+//     spill    argmin_{j != pi} ||x - c_j||^2 + lambda <r, x - c_j>^2 / ||r||^2
+//                                                                  (Section 3.4, Theorem 3.1)
+//
+// Pipeline (all on the caller's stream):
+//   quantize  X -> Xq, C -> Cq (rows padded to DP elements with zeros; FP8 rows carry a
+//             power-of-two scale so that max|row| * scale lies in [128, 256))
+//   sweep     primary: ranking value ||c||^2 - 2<x,c>; candidates per row -> cand
+//   rescore   exact FP32 over the candidates, FP64 among near-ties -> pi, ||x - c_pi||^2;
+//             residual r = x - c_pi in FP32, quantized -> Rq, and the row constants
+//   sweep     spill: ||c||^2 - 2<x,c> + lambda/||r||^2 (<r,c> - <r,x>)^2, pi masked -> cand
+//   rescore   exact FP32 SOAR loss over the candidates, FP64 among near-ties -> pi', loss
+//
+// Candidates.  In the 16x16 MFMA result a lane sees one column of every 16-column block, so per
+// row the 16 lanes of a lane group see the 16 residue classes of j mod 16.  Each lane keeps the
+// minimum of its class: the block index is packed into the two low mantissa bits of the value
+// (a 2^-21 relative perturbation) and the tile index is recorded when the minimum improves.
+// The topk (<= 8) smallest of the 16 class minima are re-scored.
+#include "common.h"
+#include "kernels.h"
+
+namespace soar {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kBig = 3.0e38f;       // finite sentinel: never a candidate, survives the packing
+
+template <int FMT>
+struct FmtTraits;
+template <>
+struct FmtTraits<LOWP_BF16> {
+  static constexpr int BYTES = 2;    // bytes per element
+  static constexpr int KSTEP = 32;   // contraction length of one MFMA
+  static constexpr int LANE_B = 16;  // bytes one lane supplies per MFMA
+};
+template <>
+struct FmtTraits<LOWP_FP8> {
+  static constexpr int BYTES = 1;
+  static constexpr int KSTEP = 128;
+  static constexpr int LANE_B = 32;
+};
+
+__device__ __forceinline__ float pack_block(float v, unsigned b) {
+  return __builtin_bit_cast(float, (__builtin_bit_cast(unsigned, v) & ~3u) | b);
+}
+__device__ __forceinline__ unsigned packed_block(float v) {
+  return __builtin_bit_cast(unsigned, v) & 3u;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Quantization of rows (X or C): FP32 -> padded BF16 / FP8 rows, plus per-row inverse scales.
+// One 16-lane group per row.
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ unsigned char fp8_of(float v) {
+  v = fminf(fmaxf(v, -448.f), 448.f);
+  return (unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0u, false) & 0xFFu);
+}
+
+template <int FMT>
+__global__ __launch_bounds__(256) void quantize_rows_kernel(const float* __restrict__ A,
+                                                            int64_t rows, int d, int dp,
+                                                            void* __restrict__ out,
+                                                            float* __restrict__ inv_scale,
+                                                            unsigned* counters) {
+  const int l16 = threadIdx.x & 15;
+  const int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  if (row >= rows) return;
+  const float* a = A + row * d;
+  float scale = 1.f;
+  bool fin = true;
+  if constexpr (FMT == LOWP_FP8) {
+    float m = 0.f;
+    for (int k = l16; k < d; k += 16) {
+      const float v = a[k];
+      fin = fin && __builtin_isfinite(v);
+      m = fmaxf(m, fabsf(v));
+    }
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if (m > 0.f && __builtin_isfinite(m)) {
+      int e;
+      (void)frexpf(m, &e);              // m = f * 2^e with f in [0.5, 1)
+      scale = ldexpf(1.f, 8 - e);        // m * scale in [128, 256)
+    }
+    unsigned char* o = static_cast<unsigned char*>(out) + row * dp;
+    for (int k = l16; k < dp; k += 16) o[k] = k < d ? fp8_of(a[k] * scale) : (unsigned char)0;
+    if (l16 == 0) inv_scale[row] = 1.f / scale;
+  } else {
+    __bf16* o = static_cast<__bf16*>(out) + row * dp;
+    for (int k = l16; k < dp; k += 16) {
+      const float v = k < d ? a[k] : 0.f;
+      fin = fin && __builtin_isfinite(v);
+      o[k] = (__bf16)v;
+    }
+    if (inv_scale && l16 == 0) inv_scale[row] = 1.f;
+  }
+  if (!fin) atomicOr(&counters[CNT_NONFINITE], 1u);
+}
+
+// ------------------------------------------------------------------------------------------------
+// The sweep: one workgroup = 4 waves x SPW stripes x 16 rows; C streamed through LDS tiles.
+// ------------------------------------------------------------------------------------------------
+template <int FMT, int DP>
+struct OperandRegs {
+  static constexpr int NSTEP = DP / FmtTraits<FMT>::KSTEP;
+  static constexpr int W4 = FmtTraits<FMT>::LANE_B / 16;   // u32x4 per lane per step
+  u32x4 v[NSTEP][W4];
+};
+
+template <int FMT, int DP>
+__device__ __forceinline__ void load_operand(const void* __restrict__ base, int64_t row,
+                                             bool ok, int q, OperandRegs<FMT, DP>& r) {
+  using T = FmtTraits<FMT>;
+  constexpr int NSTEP = OperandRegs<FMT, DP>::NSTEP, W4 = OperandRegs<FMT, DP>::W4;
+  const char* p = static_cast<const char*>(base) + (row * DP + q * (DP / 4)) * T::BYTES;
+#pragma unroll
+  for (int s = 0; s < NSTEP; ++s)
+#pragma unroll
+    for (int w = 0; w < W4; ++w)
+      r.v[s][w] = ok ? *reinterpret_cast<const u32x4*>(p + s * T::LANE_B + w * 16)
+                     : u32x4{0u, 0u, 0u, 0u};
+}
+
+template <int FMT>
+__device__ __forceinline__ v4f mfma_step(const u32x4* a, const u32x4* b, v4f acc) {
+  if constexpr (FMT == LOWP_BF16) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[0]),
+                                                   __builtin_bit_cast(bf16x8, b[0]), acc, 0, 0, 0);
+  } else {
+    const i32x8 av = {(int)a[0].x, (int)a[0].y, (int)a[0].z, (int)a[0].w,
+                      (int)a[1].x, (int)a[1].y, (int)a[1].z, (int)a[1].w};
+    const i32x8 bv = {(int)b[0].x, (int)b[0].y, (int)b[0].z, (int)b[0].w,
+                      (int)b[1].x, (int)b[1].y, (int)b[1].z, (int)b[1].w};
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc, 0, 0, 0, 127, 0, 127);
+  }
+}
+
+template <int FMT, int DP, int SPW, int BN, bool SP>
+__global__ __launch_bounds__(256) void lowp_sweep_kernel(LowpParams P) {
+  using T = FmtTraits<FMT>;
+  constexpr int NB = BN / 16;
+  constexpr int NSTEP = OperandRegs<FMT, DP>::NSTEP, W4 = OperandRegs<FMT, DP>::W4;
+  constexpr int ROWB = DP * T::BYTES;              // bytes of one quantized row
+  constexpr int LDWB = ROWB + 16;                  // LDS row stride (bytes), padded
+  constexpr int CHUNKS = BN * ROWB / 16;           // 16-byte chunks per tile
+  constexpr int NLD = (CHUNKS + 255) / 256;
+  constexpr int NR = SPW * 4;                      // rows per lane in the output layout
+  __shared__ __attribute__((aligned(16))) char s_c[2][BN * LDWB];
+  __shared__ float s_cn[2][BN];
+  __shared__ float s_cs[2][BN];
+
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, c16 = lane & 15;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * (16 * SPW);
+
+  // A operands (A layout: lane (q, c16) holds row c16 of each stripe, quarter q of the dims)
+  OperandRegs<FMT, DP> xa[SPW];
+  OperandRegs<FMT, DP> ra[SP ? SPW : 1];
+#pragma unroll
+  for (int st = 0; st < SPW; ++st) {
+    const int64_t r = row0 + st * 16 + c16;
+    load_operand<FMT, DP>(P.Xq, r, r < P.n, q, xa[st]);
+    if constexpr (SP) load_operand<FMT, DP>(P.Rq, r, r < P.n, q, ra[st]);
+  }
+  // row constants in the output layout: row (st, 4q + v)
+  float ks[NR], kt[NR], ka[NR], kl[NR];
+  int kp[NR];
+#pragma unroll
+  for (int st = 0; st < SPW; ++st)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = st * 4 + v;
+      const int64_t r = row0 + st * 16 + 4 * q + v;
+      const bool ok = r < P.n;
+      ks[i] = -2.f * ((FMT == LOWP_FP8 && ok) ? P.xs[r] : 1.f);
+      if constexpr (SP) {
+        const float4 rc = ok ? P.rowc[r] : float4{0.f, 0.f, 0.f, 0.f};
+        kt[i] = rc.x;          // inverse scale of the quantized residual row
+        ka[i] = rc.y;          // <r, x>
+        kl[i] = rc.z;          // lambda / ||r||^2
+        kp[i] = ok ? P.primary[r] : -1;
+      } else {
+        kt[i] = ka[i] = kl[i] = 0.f;
+        kp[i] = -1;
+      }
+    }
+  float b1[NR];
+  int bt[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) { b1[i] = kBig; bt[i] = 0; }
+
+  const int ntiles = (P.K + BN - 1) / BN;
+  u32x4 pre[NLD];
+  float pre_cn = 0.f, pre_cs = 1.f;
+  auto gload = [&](int t) {
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      const int f = tid + i * 256;
+      const int rr = f / (ROWB / 16), cb = (f % (ROWB / 16)) * 16;
+      const int j = t * BN + rr;
+      pre[i] = (f < CHUNKS && j < P.K)
+                   ? *reinterpret_cast<const u32x4*>(static_cast<const char*>(P.Cq) +
+                                                     (int64_t)j * ROWB + cb)
+                   : u32x4{0u, 0u, 0u, 0u};
+    }
+    if (tid < BN) {
+      const int j = t * BN + tid;
+      pre_cn = j < P.K ? P.cnorm[j] : kBig;
+      pre_cs = (FMT == LOWP_FP8 && j < P.K) ? P.cs[j] : 1.f;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      const int f = tid + i * 256;
+      if (f < CHUNKS) {
+        const int rr = f / (ROWB / 16), cb = (f % (ROWB / 16)) * 16;
+        *reinterpret_cast<u32x4*>(&s_c[buf][rr * LDWB + cb]) = pre[i];
+      }
+    }
+    if (tid < BN) { s_cn[buf][tid] = pre_cn; s_cs[buf][tid] = pre_cs; }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int t = 0; t < ntiles; ++t) {
+    const int buf = t & 1;
+    if (t + 1 < ntiles) gload(t + 1);
+    v4f accS[SPW][NB], accT[SP ? SPW : 1][NB];
+#pragma unroll
+    for (int st = 0; st < SPW; ++st)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        accS[st][b] = v4f{0.f, 0.f, 0.f, 0.f};
+        if constexpr (SP) accT[st][b] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+    for (int s = 0; s < NSTEP; ++s) {
+      u32x4 bv[NB][W4];
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int ww = 0; ww < W4; ++ww)
+          bv[b][ww] = *reinterpret_cast<const u32x4*>(
+              &s_c[buf][(b * 16 + c16) * LDWB + (q * (DP / 4)) * T::BYTES + s * T::LANE_B +
+                        ww * 16]);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int st = 0; st < SPW; ++st) {
+          accS[st][b] = mfma_step<FMT>(xa[st].v[s], bv[b], accS[st][b]);
+          if constexpr (SP) accT[st][b] = mfma_step<FMT>(ra[st].v[s], bv[b], accT[st][b]);
+        }
+    }
+    // epilogue: ranking values, class minima, tile of the last improvement
+    float old[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) old[i] = b1[i];
+    const bool mask_tile = SP;   // the primary may fall in any tile; masked by index below
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int jl = b * 16 + c16;
+      const int j = t * BN + jl;
+      const float cn = s_cn[buf][jl];
+      const float cs = s_cs[buf][jl];
+#pragma unroll
+      for (int st = 0; st < SPW; ++st)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = st * 4 + v;
+          float val;
+          if constexpr (FMT == LOWP_FP8) {
+            val = fmaf(accS[st][b][v], ks[i] * cs, cn);
+          } else {
+            val = fmaf(accS[st][b][v], -2.f, cn);
+          }
+          if constexpr (SP) {
+            const float tt = (FMT == LOWP_FP8) ? accT[st][b][v] * (kt[i] * cs) : accT[st][b][v];
+            const float e = tt - ka[i];
+            val = fmaf(kl[i] * e, e, val);
+            if (mask_tile && j == kp[i]) val = kBig;
+          }
+          b1[i] = fminf(b1[i], pack_block(val, (unsigned)b));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) bt[i] = b1[i] < old[i] ? t : bt[i];
+    if (t + 1 < ntiles) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // candidates: rank the 16 class minima of every row, keep the topk smallest
+  const int topk = P.topk;
+#pragma unroll
+  for (int st = 0; st < SPW; ++st)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = st * 4 + v;
+      const int64_t r = row0 + st * 16 + 4 * q + v;
+      const float bv = b1[i];
+      const bool valid = bv < 1.0e38f;
+      const int j = valid ? bt[i] * BN + (int)packed_block(bv) * 16 + c16 : 0x7fffffff;
+      int rank = 0;
+#pragma unroll
+      for (int o = 1; o < 16; ++o) {
+        const int src = (q << 4) | ((c16 + o) & 15);
+        const float ov = __shfl(bv, src);
+        const int oj = __shfl(j, src);
+        rank += (ov < bv || (ov == bv && oj < j)) ? 1 : 0;
+      }
+      if (r < P.n && rank < topk) P.cand[r * topk + rank] = (valid && j < P.K) ? j : -1;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Re-score: 16 lanes per row (4 rows per wave), FP32 direct differences, FP64 among near-ties.
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ float sum16(float v) {
+#pragma unroll
+  for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ __forceinline__ double sum16d(double v) {
+#pragma unroll
+  for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ __forceinline__ float max16(float v) {
+#pragma unroll
+  for (int off = 1; off < 16; off <<= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+
+// RS_MAXD: dimensions held per lane (lane l16 holds l16, l16 + 16, ...), d <= 16 * RS_MAXD.
+template <int FMT, bool SP, int RS_MAXD>
+__global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
+  const int l16 = threadIdx.x & 15;
+  const int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  if (row >= P.n) return;
+  const int d = P.d, topk = P.topk;
+  const int nd = (d - l16 + 15) / 16;   // dims this lane holds: l16, l16 + 16, ...
+  float x[RS_MAXD], r[RS_MAXD];
+  const float* xr = P.X + row * d;
+#pragma unroll
+  for (int m = 0; m < RS_MAXD; ++m) x[m] = m < nd ? xr[l16 + 16 * m] : 0.f;
+  int pi = -1;
+  float rr = 0.f;
+  if constexpr (SP) {
+    pi = P.primary[row];
+    if (pi < 0 || pi >= P.K) {   // no primary: nothing to spill
+      if (l16 == 0) { P.spill[row] = -1; if (P.sloss) P.sloss[row] = kInf; }
+      return;
+    }
+    const float* cp = P.C + (int64_t)pi * d;
+    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+    for (int m = 0; m < RS_MAXD; ++m) {
+      r[m] = m < nd ? x[m] - cp[l16 + 16 * m] : 0.f;
+      if (m & 1) a1 = fmaf(r[m], r[m], a1); else a0 = fmaf(r[m], r[m], a0);
+    }
+    rr = sum16(a0 + a1);
+  }
+  // FP32 pass
+  float best = kInf;
+  int bj = 0x7fffffff;
+  float vals[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    vals[c] = kInf;
+    if (c >= topk) continue;
+    const int j = P.cand[row * topk + c];
+    if (j < 0 || j >= P.K || (SP && j == pi)) continue;
+    const float* cj = P.C + (int64_t)j * d;
+    float s0 = 0.f, s1 = 0.f, p0 = 0.f, p1 = 0.f;
+#pragma unroll
+    for (int m = 0; m < RS_MAXD; ++m) {
+      if (m < nd) {
+        const float e = x[m] - cj[l16 + 16 * m];
+        if (m & 1) { s1 = fmaf(e, e, s1); if (SP) p1 = fmaf(r[m], e, p1); }
+        else { s0 = fmaf(e, e, s0); if (SP) p0 = fmaf(r[m], e, p0); }
+      }
+    }
+    const float sq = sum16(s0 + s1);
+    float val = sq;
+    if constexpr (SP) {
+      const float pj = sum16(p0 + p1);
+      if (rr > 0.f) val = sq + P.lam * (pj * pj) / rr;
+    }
+    vals[c] = val;
+    if (val < best || (val == best && j < bj)) { best = val; bj = j; }
+  }
+  if (bj == 0x7fffffff) {
+    if (l16 == 0) {
+      if (SP) { P.spill[row] = -1; if (P.sloss) P.sloss[row] = kInf; }
+      else { P.primary[row] = -1; if (P.pdist) P.pdist[row] = kInf; }
+    }
+    return;
+  }
+  // FP64 among near-ties
+  const float lim = best + best * P.tie_rel;
+  int ntie = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) ntie += vals[c] <= lim;
+  if (ntie >= 2) {
+    double bd = __builtin_inf();
+    int bdj = 0x7fffffff;
+    const float* cp = SP ? P.C + (int64_t)pi * d : nullptr;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (!(vals[c] <= lim)) continue;
+      const int j = P.cand[row * topk + c];
+      const float* cj = P.C + (int64_t)j * d;
+      double sq = 0.0, pj = 0.0, r2 = 0.0;
+#pragma unroll
+      for (int m = 0; m < RS_MAXD; ++m) {
+        if (m < nd) {
+          const int k = l16 + 16 * m;
+          const double e = (double)x[m] - (double)cj[k];
+          sq = fma(e, e, sq);
+          if (SP) {
+            const double rk = (double)x[m] - (double)cp[k];
+            pj = fma(rk, e, pj);
+            r2 = fma(rk, rk, r2);
+          }
+        }
+      }
+      sq = sum16d(sq);
+      double val = sq;
+      if constexpr (SP) {
+        pj = sum16d(pj);
+        r2 = sum16d(r2);
+        if (r2 > 0.0) val = sq + (double)P.lam * (pj * pj) / r2;
+      }
+      argmin_d(bd, bdj, val, j);
+    }
+    best = (float)bd;
+    bj = bdj;
+    if (l16 == 0) atomicAdd(&P.counters[CNT_FP64], 1u);
+  }
+  if constexpr (SP) {
+    if (l16 == 0) { P.spill[row] = bj; if (P.sloss) P.sloss[row] = best; }
+    return;
+  }
+  if (l16 == 0) { P.primary[row] = bj; if (P.pdist) P.pdist[row] = best; }
+  // residual of the chosen primary, quantized for the spill sweep, and its row constants
+  const float* cp = P.C + (int64_t)bj * d;
+  float a0 = 0.f, r0 = 0.f, m0 = 0.f;
+#pragma unroll
+  for (int m = 0; m < RS_MAXD; ++m) {
+    if (m < nd) {
+      r[m] = x[m] - cp[l16 + 16 * m];
+      a0 = fmaf(r[m], x[m], a0);
+      r0 = fmaf(r[m], r[m], r0);
+      m0 = fmaxf(m0, fabsf(r[m]));
+    } else {
+      r[m] = 0.f;
+    }
+  }
+  const float a = sum16(a0), r2 = sum16(r0);
+  float inv = 1.f, scale = 1.f;
+  if constexpr (FMT == LOWP_FP8) {
+    const float mx = max16(m0);
+    if (mx > 0.f) {
+      int e;
+      (void)frexpf(mx, &e);
+      scale = ldexpf(1.f, 8 - e);
+      inv = 1.f / scale;
+    }
+  }
+  if (l16 == 0) P.rowc_out[row] = float4{inv, a, r2 > 0.f ? P.lam / r2 : 0.f, 0.f};
+  // the whole padded row is written: the padding must hold zeros, not old workspace bytes
+  const int dp = P.dp;
+  if constexpr (FMT == LOWP_FP8) {
+    unsigned char* o = static_cast<unsigned char*>(P.Rq_out) + row * dp;
+#pragma unroll
+    for (int m = 0; m < RS_MAXD; ++m)
+      if (m < nd) o[l16 + 16 * m] = fp8_of(r[m] * scale);
+    for (int k = d + l16; k < dp; k += 16) o[k] = (unsigned char)0;
+  } else {
+    __bf16* o = static_cast<__bf16*>(P.Rq_out) + row * dp;
+#pragma unroll
+    for (int m = 0; m < RS_MAXD; ++m)
+      if (m < nd) o[l16 + 16 * m] = (__bf16)r[m];
+    for (int k = d + l16; k < dp; k += 16) o[k] = (__bf16)0.f;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Host-side launchers
+// ------------------------------------------------------------------------------------------------
+int lowp_padded_dim(int fmt, int d) {
+  static const int bf[] = {32, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
+  static const int f8[] = {128, 256, 384, 512, 768, 1024};
+  if (fmt == LOWP_BF16) {
+    for (int v : bf) if (d <= v) return v;
+  } else {
+    for (int v : f8) if (d <= v) return v;
+  }
+  return -1;
+}
+
+hipError_t launch_lowp_quantize(int fmt, const float* A, int64_t rows, int d, int dp, void* out,
+                                float* inv_scale, unsigned* counters, hipStream_t st) {
+  const dim3 grid((unsigned)((rows + 15) / 16)), block(256);
+  if (fmt == LOWP_BF16)
+    hipLaunchKernelGGL(quantize_rows_kernel<LOWP_BF16>, grid, block, 0, st, A, rows, d, dp, out,
+                       inv_scale, counters);
+  else
+    hipLaunchKernelGGL(quantize_rows_kernel<LOWP_FP8>, grid, block, 0, st, A, rows, d, dp, out,
+                       inv_scale, counters);
+  return hipGetLastError();
+}
+
+template <int FMT, int DP, int SPW, int BN>
+static void sweep_dp(const LowpParams& P, bool spill, hipStream_t st) {
+  const dim3 grid((unsigned)((P.n + 64 * SPW - 1) / (64 * SPW))), block(256);
+  if (spill)
+    hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, SPW, BN, true>), grid, block, 0, st, P);
+  else
+    hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, SPW, BN, false>), grid, block, 0, st, P);
+}
+
+static hipError_t sweep_bf16(const LowpParams& P, bool spill, hipStream_t st) {
+  constexpr int F = LOWP_BF16;
+  switch (P.dp) {
+    case 32: sweep_dp<F, 32, 2, 64>(P, spill, st); break;
+    case 64: sweep_dp<F, 64, 2, 64>(P, spill, st); break;
+    case 96: sweep_dp<F, 96, 2, 64>(P, spill, st); break;
+    case 128: sweep_dp<F, 128, 2, 64>(P, spill, st); break;
+    case 192: sweep_dp<F, 192, 2, 64>(P, spill, st); break;
+    case 256: sweep_dp<F, 256, 2, 64>(P, spill, st); break;
+    case 384: sweep_dp<F, 384, 1, 64>(P, spill, st); break;
+    case 512: sweep_dp<F, 512, 1, 64>(P, spill, st); break;
+    case 768: sweep_dp<F, 768, 1, 32>(P, spill, st); break;
+    case 1024: sweep_dp<F, 1024, 1, 32>(P, spill, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+static hipError_t sweep_fp8(const LowpParams& P, bool spill, hipStream_t st) {
+  constexpr int F = LOWP_FP8;
+  switch (P.dp) {
+    case 128: sweep_dp<F, 128, 2, 64>(P, spill, st); break;
+    case 256: sweep_dp<F, 256, 2, 64>(P, spill, st); break;
+    case 384: sweep_dp<F, 384, 2, 64>(P, spill, st); break;
+    case 512: sweep_dp<F, 512, 2, 64>(P, spill, st); break;
+    case 768: sweep_dp<F, 768, 1, 64>(P, spill, st); break;
+    case 1024: sweep_dp<F, 1024, 1, 32>(P, spill, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lowp_sweep(int fmt, const LowpParams& P, bool spill, hipStream_t st) {
+  return fmt == LOWP_BF16 ? sweep_bf16(P, spill, st) : sweep_fp8(P, spill, st);
+}
+
+template <int FMT, int M>
+static void rescore_m(const LowpParams& P, bool spill, hipStream_t st) {
+  const dim3 grid((unsigned)((P.n + 15) / 16)), block(256);
+  if (spill) hipLaunchKernelGGL((lowp_rescore_kernel<FMT, true, M>), grid, block, 0, st, P);
+  else hipLaunchKernelGGL((lowp_rescore_kernel<FMT, false, M>), grid, block, 0, st, P);
+}
+
+template <int FMT>
+static hipError_t rescore_fmt(const LowpParams& P, bool spill, hipStream_t st) {
+  const int m = (P.d + 15) / 16;
+  if (m <= 2) rescore_m<FMT, 2>(P, spill, st);
+  else if (m <= 4) rescore_m<FMT, 4>(P, spill, st);
+  else if (m <= 6) rescore_m<FMT, 6>(P, spill, st);
+  else if (m <= 8) rescore_m<FMT, 8>(P, spill, st);
+  else if (m <= 12) rescore_m<FMT, 12>(P, spill, st);
+  else if (m <= 16) rescore_m<FMT, 16>(P, spill, st);
+  else if (m <= 24) rescore_m<FMT, 24>(P, spill, st);
+  else if (m <= 32) rescore_m<FMT, 32>(P, spill, st);
+  else if (m <= 48) rescore_m<FMT, 48>(P, spill, st);
+  else if (m <= 64) rescore_m<FMT, 64>(P, spill, st);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_lowp_rescore(int fmt, const LowpParams& P, bool spill, hipStream_t st) {
+  return fmt == LOWP_BF16 ? rescore_fmt<LOWP_BF16>(P, spill, st)
+                          : rescore_fmt<LOWP_FP8>(P, spill, st);
+}
+
+}  // namespace soar

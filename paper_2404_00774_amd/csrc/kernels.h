@@ -31,4 +31,40 @@ hipError_t launch_prep_codebook(const float* C, int K, int d, float* cnorm, unsi
 hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipStream_t st,
                               hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
 
+// ---- low-precision (BF16 / FP8-e4m3) path ----
+enum LowpFormat : int { LOWP_BF16 = 0, LOWP_FP8 = 1 };
+
+struct LowpParams {
+  int64_t n;
+  int d;
+  int dp;                 // padded row length of the quantized operands (elements)
+  int K;
+  int topk;               // candidates re-scored per row (<= 8)
+  float lam;
+  float tie_rel;
+  const float* X;         // FP32 originals
+  const float* C;
+  const void* Xq;         // quantized rows, row stride dp elements
+  const void* Cq;
+  const void* Rq;
+  const float* xs;        // FP8: inverse power-of-two row scales of Xq, Cq
+  const float* cs;
+  const float* cnorm;     // [K] ||c_j||^2 (FP32)
+  const float4* rowc;     // [n] residual rows: {inverse scale, <r, x>, lambda / ||r||^2, 0}
+  int32_t* cand;          // [n * topk]
+  int32_t* primary;
+  int32_t* spill;
+  float* pdist;
+  float* sloss;
+  unsigned* counters;
+  float4* rowc_out;       // written by the primary re-score
+  void* Rq_out;
+};
+
+int lowp_padded_dim(int fmt, int d);
+hipError_t launch_lowp_quantize(int fmt, const float* A, int64_t rows, int d, int dp, void* out,
+                                float* inv_scale, unsigned* counters, hipStream_t st);
+hipError_t launch_lowp_sweep(int fmt, const LowpParams& P, bool spill, hipStream_t st);
+hipError_t launch_lowp_rescore(int fmt, const LowpParams& P, bool spill, hipStream_t st);
+
 }  // namespace soar

@@ -57,10 +57,49 @@ soar_status validate_assign(int64_t n, int32_t d, int32_t K, const OptsView& o) 
   if (n < 1 || n > INT32_MAX || d < 1 || K < 2) return SOAR_E_INVAL;
   if (!std::isfinite(o.lambda) || o.lambda < 0.f) return SOAR_E_INVAL;
   if (!(o.near_tie_rel >= 0.f) || !std::isfinite(o.near_tie_rel)) return SOAR_E_INVAL;
-  if (o.precision != SOAR_FP32) return SOAR_E_UNSUPPORTED;
-  if (soar::fp32_padded_dim(d) < 0) return SOAR_E_UNSUPPORTED;
+  if (o.precision == SOAR_FP32) return soar::fp32_padded_dim(d) < 0 ? SOAR_E_UNSUPPORTED : SOAR_OK;
+  if (o.precision != SOAR_BF16 && o.precision != SOAR_FP8_E4M3) return SOAR_E_INVAL;
+  if (o.topk < 0 || o.topk > 8) return SOAR_E_INVAL;
+  const int fmt = o.precision == SOAR_BF16 ? soar::LOWP_BF16 : soar::LOWP_FP8;
+  if (soar::lowp_padded_dim(fmt, d) < 0) return SOAR_E_UNSUPPORTED;
   return SOAR_OK;
 }
+
+struct LowpLayout {
+  unsigned* counters;
+  float* cnorm;
+  void* Xq;
+  void* Cq;
+  void* Rq;
+  float* xs;
+  float* cs;
+  float4* rowc;
+  int32_t* cand;
+  size_t bytes;
+};
+
+LowpLayout layout_lowp(void* ws, int64_t n, int32_t d, int32_t K, int fmt, int topk) {
+  const int dp = soar::lowp_padded_dim(fmt, d);
+  const size_t eb = fmt == soar::LOWP_BF16 ? 2 : 1;
+  Carver c(ws);
+  LowpLayout L;
+  L.counters = c.take<unsigned>(soar::CNT_WORDS);
+  L.cnorm = c.take<float>((size_t)K);
+  L.Xq = c.take<char>((size_t)n * dp * eb);
+  L.Cq = c.take<char>((size_t)K * dp * eb);
+  L.Rq = c.take<char>((size_t)n * dp * eb);
+  L.xs = c.take<float>((size_t)n);
+  L.cs = c.take<float>((size_t)K);
+  L.rowc = c.take<float4>((size_t)n);
+  L.cand = c.take<int32_t>((size_t)n * topk);
+  L.bytes = c.off;
+  return L;
+}
+
+inline int lowp_fmt(const OptsView& o) {
+  return o.precision == SOAR_BF16 ? soar::LOWP_BF16 : soar::LOWP_FP8;
+}
+inline int lowp_topk(const OptsView& o) { return o.topk > 0 ? o.topk : 8; }
 
 struct AssignLayout {
   unsigned* counters;
@@ -122,6 +161,40 @@ soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C
 
 size_t assign_workspace_bytes(int64_t n, int32_t K) { return layout_assign(nullptr, n, K).bytes; }
 
+// BF16 / FP8 pipeline: quantize, primary sweep + re-score, spill sweep + re-score.
+// ev (nullable, 4 events) brackets the primary sweep [0, 1] and the spill sweep [2, 3].
+soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
+                            float lam, float near_tie_rel, int fmt, int topk, int32_t* primary,
+                            int32_t* spill_out, float* pdist, float* sloss, void* ws,
+                            hipStream_t st, unsigned* counters_out_host, hipEvent_t* ev) {
+  LowpLayout L = layout_lowp(ws, n, d, K, fmt, topk);
+  LowpParams P;
+  P.n = n; P.d = d; P.dp = lowp_padded_dim(fmt, d); P.K = K; P.topk = topk;
+  P.lam = lam;
+  P.tie_rel = tie_threshold(d, lam, near_tie_rel);
+  P.X = X; P.C = C; P.Xq = L.Xq; P.Cq = L.Cq; P.Rq = L.Rq;
+  P.xs = L.xs; P.cs = L.cs; P.cnorm = L.cnorm; P.rowc = L.rowc; P.cand = L.cand;
+  P.primary = primary; P.spill = spill_out; P.pdist = pdist; P.sloss = sloss;
+  P.counters = L.counters; P.rowc_out = L.rowc; P.Rq_out = L.Rq;
+  hipError_t e = launch_prep_codebook(C, K, d, L.cnorm, L.counters, st);
+  if (e == hipSuccess) e = launch_lowp_quantize(fmt, C, K, d, P.dp, L.Cq, L.cs, L.counters, st);
+  if (e == hipSuccess) e = launch_lowp_quantize(fmt, X, n, d, P.dp, L.Xq, L.xs, L.counters, st);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[0], st);
+  if (e == hipSuccess) e = launch_lowp_sweep(fmt, P, false, st);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
+  if (e == hipSuccess) e = launch_lowp_rescore(fmt, P, false, st);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
+  if (e == hipSuccess) e = launch_lowp_sweep(fmt, P, true, st);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
+  if (e == hipSuccess) e = launch_lowp_rescore(fmt, P, true, st);
+  if (e != hipSuccess) return SOAR_E_DEVICE;
+  if (counters_out_host &&
+      hipMemcpyAsync(counters_out_host, L.counters, CNT_WORDS * sizeof(unsigned),
+                     hipMemcpyDeviceToHost, st) != hipSuccess)
+    return SOAR_E_DEVICE;
+  return SOAR_OK;
+}
+
 }  // namespace soar
 
 extern "C" {
@@ -146,7 +219,9 @@ soar_status soar_assign_workspace_size(int64_t n, int32_t d, int32_t K,
   if (!bytes || !read_opts(opts, &o)) return SOAR_E_INVAL;
   const soar_status s = validate_assign(n, d, K, o);
   if (s != SOAR_OK) return s;
-  *bytes = soar::assign_workspace_bytes(n, K);
+  *bytes = o.precision == SOAR_FP32
+               ? soar::assign_workspace_bytes(n, K)
+               : layout_lowp(nullptr, n, d, K, lowp_fmt(o), lowp_topk(o)).bytes;
   return SOAR_OK;
 }
 
@@ -160,12 +235,14 @@ soar_status soar_assign(const float* X, int64_t n, int32_t d, const float* C, in
   if (s != SOAR_OK) return s;
   if (!X || !C || !primary || !spill || !workspace) return SOAR_E_INVAL;
   if (!aligned(X, 4) || !aligned(C, 4) || !aligned(workspace, kAlign)) return SOAR_E_INVAL;
-  if (ws_bytes < soar::assign_workspace_bytes(n, K)) return SOAR_E_INVAL;
+  size_t need = 0;
+  if (soar_assign_workspace_size(n, d, K, opts, &need) != SOAR_OK || ws_bytes < need)
+    return SOAR_E_INVAL;
   if (stats && stats->struct_size < sizeof(soar_stats)) return SOAR_E_INVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool async = (o.flags & SOAR_ASYNC) != 0;
 
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   auto destroy = [&]() {
     for (hipEvent_t& e : ev)
       if (e) (void)hipEventDestroy(e);
@@ -176,24 +253,36 @@ soar_status soar_assign(const float* X, int64_t n, int32_t d, const float* C, in
     (void)hipEventRecord(ev[0], st);
   }
   unsigned cnt[soar::CNT_WORDS] = {0};
-  s = soar::run_assign_fp32(X, n, d, C, K, o.lambda, o.near_tie_rel, true, primary, spill,
-                            primary_dist, spill_loss, workspace, st, async ? nullptr : cnt, ev[1],
-                            ev[2]);
+  const bool lowp = o.precision != SOAR_FP32;
+  if (!lowp)
+    s = soar::run_assign_fp32(X, n, d, C, K, o.lambda, o.near_tie_rel, true, primary, spill,
+                              primary_dist, spill_loss, workspace, st, async ? nullptr : cnt,
+                              ev[1], ev[2]);
+  else
+    s = soar::run_assign_lowp(X, n, d, C, K, o.lambda, o.near_tie_rel, lowp_fmt(o), lowp_topk(o),
+                              primary, spill, primary_dist, spill_loss, workspace, st,
+                              async ? nullptr : cnt, ev[0] ? ev + 1 : nullptr);
   if (s != SOAR_OK || async) {
     destroy();
     return s;
   }
-  if (stats) (void)hipEventRecord(ev[3], st);
+  if (stats) (void)hipEventRecord(ev[5], st);
   s = dev_err(hipStreamSynchronize(st));
   if (s == SOAR_OK && stats) {
-    float ms = 0.f, kms = 0.f;
-    (void)hipEventElapsedTime(&ms, ev[0], ev[3]);
+    float ms = 0.f, kms = 0.f, k2 = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[5]);
     (void)hipEventElapsedTime(&kms, ev[1], ev[2]);
+    if (lowp) {   // the two sweeps: [1, 2] primary, [3, 4] spill
+      (void)hipEventElapsedTime(&k2, ev[3], ev[4]);
+      kms += k2;
+    }
     stats->device_ms = ms;
     stats->assign_kernel_ms = kms;
     stats->rows_full_scan = cnt[soar::CNT_FULLSCAN];
     stats->rows_fp64 = cnt[soar::CNT_FP64];
-    stats->mfma_flops = 6.0 * (double)n * (double)K * (double)soar::fp32_padded_dim(d);
+    stats->mfma_flops =
+        6.0 * (double)n * (double)K *
+        (double)(lowp ? soar::lowp_padded_dim(lowp_fmt(o), d) : soar::fp32_padded_dim(d));
   }
   destroy();
   if (s == SOAR_OK && cnt[soar::CNT_NONFINITE]) s = SOAR_E_NONFINITE;

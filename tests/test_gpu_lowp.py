@@ -1,0 +1,122 @@
+"""BF16 / FP8-e4m3 forms of the SOAR assignment against the FP64 oracle.
+
+These forms are approximations, so the parity bar is the one stated for them: the reported value
+at the chosen index is exact (FP32 re-score, 1e-5 relative), and the loss regret against the
+oracle's best has a mean of at most 1e-3 (BF16) on mixture data.  Index disagreement and regret
+are printed for every case.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import MixtureSpec, WORKLOADS, gen_mixture
+
+pytestmark = pytest.mark.gpu
+
+
+def _soar():
+    import paper_2404_00774_amd as soar
+    return soar
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _run(X, C, lam, prec, topk=0):
+    soar = _soar()
+    p, s, dp, ls, st = soar.assign(_t(X), _t(C), lam, precision=prec, topk=topk, stats=True)
+    return p.cpu().numpy(), s.cpu().numpy(), dp.cpu().numpy(), ls.cpu().numpy(), st
+
+
+def _report(X, C, lam, res, tag):
+    p, s, dp, ls, st = res
+    j = O.judge(X, C, lam, p, s, dp, ls)
+    out = dict(primary_disagree=float((p != j["p_star"]).mean()),
+               spill_disagree=float((s != j["s_star"]).mean()),
+               primary_regret_mean=float(j["primary_regret"].mean()),
+               primary_regret_p99=float(np.quantile(j["primary_regret"], 0.99)),
+               spill_regret_mean=float(j["spill_regret"].mean()),
+               spill_regret_p99=float(np.quantile(j["spill_regret"], 0.99)))
+    print(tag, out, flush=True)
+    worst = np.argsort(-j["spill_regret"])[:3]
+    for i in worst:
+        print(f"  row {i}: gpu p={p[i]} s={s[i]} ls={ls[i]:.6g} | oracle p={j['p_star'][i]} "
+              f"s|gpu p={j['s_star'][i]} L*={j['l_star'][i]:.6g} regret={j['spill_regret'][i]:.3g}",
+              flush=True)
+    # exact re-score: the reported values are those of the reported indices
+    assert j["pdist_ok"].all() and j["sloss_ok"].all()
+    assert np.all(s != p) and np.all((p >= 0) & (p < len(C))) and np.all((s >= 0) & (s < len(C)))
+    assert np.all(j["primary_regret"] >= -1e-6) and np.all(j["spill_regret"] >= -1e-6)
+    return out
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = WORKLOADS["mix64_n20k_d64"]
+    X = gen_mixture(w["spec"])
+    C, _, _ = O.train_codebook(X, w["K"], 4, seed=0)
+    return X, C.astype(np.float32)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("lam", [0.0, 1.0, 1.5])
+def test_small_workload(small, prec, lam):
+    X, C = small
+    r = _report(X, C, lam, _run(X, C, lam, prec), f"{prec} lam={lam}")
+    bound = 1e-3 if prec == "bf16" else 1e-2
+    assert r["primary_regret_mean"] <= bound and r["spill_regret_mean"] <= bound
+
+
+def test_bf16_d96_many_centroids():
+    """Config-3 shapes scaled down: d = 96, K = 4000, loguniform mixture."""
+    spec = MixtureSpec(20_000, 96, 2048, ("loguniform", 0.05, 0.5), "unit", 3)
+    X = gen_mixture(spec)
+    C = X[np.random.default_rng(0).choice(len(X), 4000, replace=False)]
+    r = _report(X, C, 1.0, _run(X, C, 1.0, "bf16"), "bf16 d96 K4000")
+    assert r["primary_regret_mean"] <= 1e-3 and r["spill_regret_mean"] <= 1e-3
+
+
+def test_fp8_d768_lognormal():
+    """Config-4 shapes scaled down: d = 768, unnormalised rows with lognormal norms."""
+    spec = MixtureSpec(4000, 768, 512, ("loguniform", 0.05, 0.5), ("lognormal", 0.5), 4)
+    X = gen_mixture(spec)
+    C = X[np.random.default_rng(1).choice(len(X), 500, replace=False)] * 0.97
+    for prec in ("fp8", "bf16"):
+        r = _report(X, C, 1.0, _run(X, C, 1.0, prec), f"{prec} d768")
+        assert r["spill_regret_mean"] <= (1e-2 if prec == "fp8" else 1e-3)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("n,d,K,topk", [(1, 8, 2, 0), (37, 1, 3, 0), (300, 5, 9, 4), (513, 33, 17, 8),
+                                        (200, 100, 70, 2), (129, 300, 40, 0)])
+def test_edge_shapes(prec, n, d, K, topk):
+    print(f"{prec} edge n={n} d={d} K={K} topk={topk}", flush=True)
+    rng = np.random.default_rng(n + d + K)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    C = (rng.standard_normal((K, d)) * 0.8).astype(np.float32)
+    res = _run(X, C, 1.0, prec, topk)
+    _report(X, C, 1.0, res, f"{prec} edge")
+    if K <= 16 and (topk == 0 or topk >= min(K, 8)):
+        # every class minimum is a candidate, so the answers are exact
+        j = O.judge(X, C, 1.0, res[0], res[1])
+        if K <= 8:
+            assert j["primary_ok"].all() and j["spill_ok"].all()
+
+
+def test_deterministic(small):
+    X, C = small
+    for prec in ("bf16", "fp8"):
+        a = _run(X, C, 1.0, prec)
+        b = _run(X, C, 1.0, prec)
+        for u, v in zip(a[:4], b[:4]):
+            assert np.array_equal(u, v)
+
+
+def test_invalid_topk():
+    soar = _soar()
+    X, C = _t(np.zeros((4, 8))), _t(np.eye(8)[:3])
+    with pytest.raises(soar.SoarError) as e:
+        soar.assign(X, C, 1.0, precision="bf16", topk=9)
+    assert e.value.status == -1
