@@ -7,7 +7,11 @@ re-scoring (soar_assign).  The codebook is trained first on the same GPU (k-mean
 iterations; their times are reported under "train").  Inputs are resident in HBM before the timed
 region starts.
 
-Prints one JSON line (see the "metric"/"config"/"roofline"/"cpu_baseline" keys).
+--precision takes a comma list: the first form is the headline ("value"); every form is timed on
+the same inputs and reported under "forms" with its speedup over FP32 and its index disagreement
+and loss regret against the FP64 oracle on a sample of rows.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -23,8 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2516.0, "fp8": 5032.0}   # MI355X dense MFMA peaks
-HBM_PEAK_GBS = 8000.0
 METRIC = "SOAR-assigned points/sec and % MFMA peak, BF16/FP8 vs FP32 at ≤1e-3 regret"
+DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8_e4m3"}
+KERNEL = {"fp32": "assign_f32_kernel (primary + residual + spill, one kernel)",
+          "bf16": "lowp_sweep_kernel x2 (primary sweep + spill sweep)",
+          "fp8": "lowp_sweep_kernel x2 (primary sweep + spill sweep)"}
 
 
 def parse():
@@ -34,10 +41,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mix4096_n1m_d128")
     ap.add_argument("--lam", type=float, default=1.0)
-    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--precision", default="fp32,bf16,fp8")
+    ap.add_argument("--form-steps", type=int, default=5, help="timed steps of the extra forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=500_000)
-    ap.add_argument("--parity-sample", type=int, default=5_000)
+    ap.add_argument("--judge-sample", type=int, default=5_000)
+    ap.add_argument("--codebook", default="train", choices=["train", "sample"],
+                    help="sample: K uniformly sampled rows, no training (for short profiling runs)")
+    ap.add_argument("--rows", type=int, default=0, help="use only the first N rows (profiling)")
     return ap.parse_args()
 
 
@@ -61,6 +72,47 @@ def cpu_baseline(X, C, lam, sample_rows, spec):
                       f"{dt:.2f} s wall"}
 
 
+def time_form(soar, torch, Xg, Cg, lam, prec, steps, warmup, n, d, K):
+    dev = Xg.device
+    out = tuple(torch.empty(n, dtype=t, device=dev)
+                for t in (torch.int32, torch.int32, torch.float32, torch.float32))
+    ws = torch.empty(soar.assign_workspace_size(n, d, K, lam, prec), dtype=torch.uint8, device=dev)
+    for _ in range(warmup):
+        soar.assign(Xg, Cg, lam, prec, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    kernel_ms, device_ms, full_scan, fp64 = [], [], [], []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        *_, st = soar.assign(Xg, Cg, lam, prec, out=out, workspace=ws, stats=True)
+        kernel_ms.append(st["assign_kernel_ms"])
+        device_ms.append(st["device_ms"])
+        full_scan.append(st["rows_full_scan"])
+        fp64.append(st["rows_fp64"])
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    del ws
+    return dict(ms_per_step=wall * 1e3 / steps, event_ms_per_step=ev0.elapsed_time(ev1) / steps,
+                kernel_ms=float(np.mean(kernel_ms)), device_ms=float(np.mean(device_ms)),
+                rows_full_scan=int(np.mean(full_scan)), rows_fp64=int(np.mean(fp64)),
+                out=tuple(t.cpu().numpy() for t in out))
+
+
+def judge_form(O, X, C, lam, idx, outs):
+    p, s, dp, ls = (a[idx] for a in outs)
+    j = O.judge(X[idx], C, lam, p, s, dp, ls)
+    pr, sr = j["primary_regret"], j["spill_regret"]
+    return {"rows": int(len(idx)), "exact_by_rule": bool(j["all_ok"]),
+            "primary_index_disagreement": float((p != j["p_star"]).mean()),
+            "spill_index_disagreement": float((s != j["s_star"]).mean()),
+            "primary_regret_mean": float(pr.mean()), "primary_regret_p99": float(np.quantile(pr, .99)),
+            "spill_regret_mean": float(sr.mean()), "spill_regret_p99": float(np.quantile(sr, .99)),
+            "values_exact_at_index": bool(j["pdist_ok"].all() and j["sloss_ok"].all())}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -75,70 +127,68 @@ def main():
 
     w = WORKLOADS[args.workload]
     spec, K, iters = w["spec"], w["K"], w["iters"]
+    if args.rows:
+        import dataclasses
+        spec = dataclasses.replace(spec, n=min(args.rows, spec.n))
     n, d = spec.n, spec.d
+    precs = [p.strip() for p in args.precision.split(",") if p.strip()]
     print(f"[bench] generating {args.workload}: n={n} d={d} K={K}", file=sys.stderr, flush=True)
     X = gen_mixture(spec)
     dev = torch.device("cuda:0")
     Xg = torch.from_numpy(X).to(dev)
     torch.cuda.synchronize()
 
-    # ---- codebook: k-means++ then Lloyd, on the GPU (timed separately, not part of a step)
-    print("[bench] training codebook", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    C0, _ = soar.kmeanspp(Xg, K, 0)
-    torch.cuda.synchronize()
-    t_kpp = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    Cg, labels, inertia = soar.train_codebook(Xg, K, iters, C_init=C0)
-    torch.cuda.synchronize()
-    t_lloyd = time.perf_counter() - t0
-
-    # ---- timed assignment steps
-    out = (torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
-           torch.empty(n, dtype=torch.float32, device=dev), torch.empty(n, dtype=torch.float32, device=dev))
-    ws = torch.empty(soar.assign_workspace_size(n, d, K, args.lam, args.precision), dtype=torch.uint8,
-                     device=dev)
-    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        soar.assign(Xg, Cg, args.lam, args.precision, out=out, workspace=ws)
-    torch.cuda.synchronize()
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    kernel_ms, full_scan, fp64 = [], [], []
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        *_, st = soar.assign(Xg, Cg, args.lam, args.precision, out=out, workspace=ws, stats=True)
-        kernel_ms.append(st["assign_kernel_ms"])
-        full_scan.append(st["rows_full_scan"])
-        fp64.append(st["rows_fp64"])
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
-    ev_ms = ev0.elapsed_time(ev1) / args.steps
-    value = n / (ms_per_step / 1e3)
-
-    # ---- roofline of the dominant kernel (algorithmic flops: 4*K*d per point)
-    alg_flops = 4.0 * n * K * d
-    kms = float(np.mean(kernel_ms))
-    achieved = alg_flops / (kms / 1e3) / 1e12
-    peak = PEAKS_TFLOPS[args.precision]
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
-                "kernel": "assign_f32_kernel", "kernel_ms": kms,
-                "algorithmic_flops_per_launch": alg_flops}
-
-    # ---- sampled parity of the benchmarked outputs against the oracle
-    idx = sample_rows(spec, args.parity_sample)
-    p, s, dp, ls = (t.cpu().numpy() for t in out)
+    # ---- codebook: k-means++ (on a subsample for the large workloads), then Lloyd on all rows
+    sub = w.get("seed_subsample")
+    t_kpp = t_lloyd = 0.0
+    inertia = [float("nan")]
+    if args.codebook == "sample":
+        Cg = torch.from_numpy(X[sample_rows(spec, K)]).to(dev)
+    else:
+        print("[bench] training codebook", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        if sub and sub < n:
+            Xs = torch.from_numpy(X[sample_rows(spec, sub)]).to(dev)
+            C0, _ = soar.kmeanspp(Xs, K, 0)
+            del Xs
+        else:
+            C0, _ = soar.kmeanspp(Xg, K, 0)
+        torch.cuda.synchronize()
+        t_kpp = time.perf_counter() - t0
+        print(f"[bench] k-means++ {t_kpp:.2f} s; Lloyd x{iters}", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        Cg, labels, inertia = soar.train_codebook(Xg, K, iters, C_init=C0)
+        torch.cuda.synchronize()
+        t_lloyd = time.perf_counter() - t0
+        del labels, C0
     C = Cg.cpu().numpy()
-    j = O.judge(X[idx], C, args.lam, p[idx], s[idx], dp[idx], ls[idx])
-    parity = {"rows_checked": int(len(idx)), "all_ok": bool(j["all_ok"]),
-              "primary_index_mismatch": int(j["primary_mismatch"]),
-              "spill_index_mismatch": int(j["spill_mismatch"]),
-              "max_spill_regret": float(j["spill_regret"].max())}
+    idx = sample_rows(spec, args.judge_sample)
+
+    forms = {}
+    for k, prec in enumerate(precs):
+        steps, warm = (args.steps, args.warmup) if k == 0 else (args.form_steps, 1)
+        print(f"[bench] {prec}: warmup {warm}, timing {steps} steps", file=sys.stderr, flush=True)
+        r = time_form(soar, torch, Xg, Cg, args.lam, prec, steps, warm, n, d, K)
+        outs = r.pop("out")
+        print(f"[bench] {prec}: {r['ms_per_step']:.3f} ms/step; judging {len(idx)} rows",
+              file=sys.stderr, flush=True)
+        r["oracle_check"] = judge_form(O, X, C, args.lam, idx, outs)
+        alg = 4.0 * n * K * d
+        r["value"] = n / (r["ms_per_step"] / 1e3)
+        r["algorithmic_tflops"] = alg / (r["kernel_ms"] / 1e3) / 1e12
+        r["mfma_peak_frac"] = r["algorithmic_tflops"] / PEAKS_TFLOPS[prec]
+        r["steps"] = steps
+        forms[prec] = r
+    if "fp32" in forms:
+        for prec, r in forms.items():
+            r["speedup_vs_fp32"] = forms["fp32"]["ms_per_step"] / r["ms_per_step"]
+
+    head = forms[precs[0]]
+    alg_flops = 4.0 * n * K * d
+    roofline = {"bound": "mfma", "achieved": head["algorithmic_tflops"],
+                "peak": PEAKS_TFLOPS[precs[0]], "unit": "TFLOP/s", "frac": head["mfma_peak_frac"],
+                "traffic": None, "kernel": KERNEL[precs[0]], "kernel_ms": head["kernel_ms"],
+                "algorithmic_flops_per_launch": alg_flops}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -146,23 +196,21 @@ def main():
         cpu = cpu_baseline(X, C, args.lam, args.cpu_sample, spec)
 
     rec = {
-        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "metric": METRIC, "value": head["value"], "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8_e4m3"}[args.precision],
-        "data": "synthetic",
+        "dtype": DTYPE[precs[0]], "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d, "K": K, "lambda": args.lam,
-                   "precision": args.precision, "mixture_components": spec.components,
-                   "lloyd_iters": iters, "codebook": "k-means++ + Lloyd on the same GPU"},
-        "mfma_peak_frac_algorithmic": roofline["frac"],
-        "event_ms_per_step": ev_ms,
+                   "precision": precs[0], "mixture_components": spec.components,
+                   "lloyd_iters": iters,
+                   "codebook": ("k-means++ + Lloyd on the same GPU" if args.codebook == "train"
+                                else "uniformly sampled rows (profiling run)")},
+        "mfma_peak_frac_algorithmic": head["mfma_peak_frac"],
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "train": {"kmeanspp_s": t_kpp, "lloyd_s": t_lloyd, "inertia_first": inertia[0],
-                  "inertia_last": inertia[-1]},
-        "rows_full_scan_per_step": int(np.mean(full_scan)),
-        "rows_fp64_per_step": int(np.mean(fp64)),
-        "parity_sample": parity,
+        "forms": forms,
+        "train": {"kmeanspp_s": t_kpp, "kmeanspp_rows": int(sub if sub and sub < n else n),
+                  "lloyd_s": t_lloyd, "inertia_first": inertia[0], "inertia_last": inertia[-1]},
     }
     print(json.dumps(rec))
 

@@ -12,11 +12,11 @@
 // dropped)
 //     primary: ||c||^2 - 2<x,c>
 //     spill:   ||c||^2 - 2<x,c> + lambda/||r||^2 * (<r,c> - <r,x>)^2,  masked at j = pi
-// and every lane keeps, per row, its best value and index and its second-best value over the
-// columns it sees.  With delta a proven bound on the expansion's rounding error, every centroid
-// whose value lies within 2*delta of the row minimum is a candidate for the exact arg-min; the
-// lane bests cover all of them unless some lane's second best is itself inside that band, in which
-// case the row is handed to the exact full scan.  Candidates are re-scored by direct differences
+// and every lane keeps, per row, its two best values with their indices and its third-best value
+// over the columns it sees.  With delta a proven bound on the expansion's rounding error, every
+// centroid whose value lies within 2*delta of the row minimum is a candidate for the exact
+// arg-min; the lanes' two bests cover all of them unless some lane's third best is itself inside
+// that band, in which case the row is handed to the exact full scan.  Candidates are re-scored by direct differences
 // in FP32 (16 partial sums per row), and candidates within the near-tie gap of the best are
 // re-decided in FP64.  Ties go to the lowest index.
 #include "common.h"
@@ -140,7 +140,7 @@ __device__ __forceinline__ void sweep(const AssignParams& P, float* s_c, float* 
                                       const float (&xa)[DP / 4], const float (&ra)[DP / 4],
                                       const float (&lp)[4], const float (&av)[4],
                                       const int (&pr)[4], float (&b1)[4], int (&i1)[4],
-                                      float (&b2)[4]) {
+                                      float (&b2)[4], int (&i2)[4], float (&b3)[4]) {
   constexpr int KS = DP / 4, LDW = DP + 4, NB = BN / 16;
   const int lane = tid & 63, q = lane >> 4, c16 = lane & 15;
   const int ntiles = (P.K + BN - 1) / BN;
@@ -191,10 +191,13 @@ __device__ __forceinline__ void sweep(const AssignParams& P, float* s_c, float* 
         } else {
           val = fmaf(-2.f, accS[b][v], cn);
         }
+        // keep (b1, i1) <= (b2, i2) <= b3 over the columns seen so far
+        const bool lt1 = val < b1[v], lt2 = val < b2[v];
+        b3[v] = fminf(b3[v], fmaxf(b2[v], val));
+        i2[v] = lt1 ? i1[v] : (lt2 ? j : i2[v]);
         b2[v] = fminf(b2[v], fmaxf(b1[v], val));
-        const bool better = val < b1[v];
-        b1[v] = better ? val : b1[v];
-        i1[v] = better ? j : i1[v];
+        i1[v] = lt1 ? j : i1[v];
+        b1[v] = fminf(b1[v], val);
       }
     }
     if (t + 1 < ntiles) ld.store(s_c + (buf ^ 1) * (BN * LDW), s_cn + (buf ^ 1) * BN, tid);
@@ -209,14 +212,15 @@ struct RowShared {
   int pi[4][16];       // primary (-1: the row went to the full scan)
   int nc[4][16];       // number of candidates
   int sat[4][16];      // candidate set not proven complete
-  int cand[4][16][16];
-  float cv[4][16][16];
+  int cand[4][16][32];
+  float cv[4][16][32];
 };
 
 // Reduce the lane-level state to per-row candidate lists in LDS (output layout -> LDS).
 __device__ __forceinline__ void publish_candidates(RowShared& S, int w, int lane,
                                                    const float (&b1)[4], const int (&i1)[4],
-                                                   const float (&b2)[4]) {
+                                                   const float (&b2)[4], const int (&i2)[4],
+                                                   const float (&b3)[4]) {
   const int q = lane >> 4, c16 = lane & 15;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -226,18 +230,21 @@ __device__ __forceinline__ void publish_candidates(RowShared& S, int w, int lane
     argmin16(m, mj);
     const float thr = m + S.band[w][r];
     const bool finite_min = m < kInf;
-    const bool sat = b2[v] <= thr;
-    const bool isc = finite_min && b1[v] <= thr;
-    const uint64_t sm = __ballot(sat);
-    const uint64_t cm = __ballot(isc);
-    const unsigned sg = (unsigned)(sm >> (16 * q)) & 0xFFFFu;
-    const unsigned cg = (unsigned)(cm >> (16 * q)) & 0xFFFFu;
+    const bool sat = b3[v] <= thr;
+    const bool c1 = finite_min && b1[v] <= thr;
+    const bool c2 = finite_min && b2[v] <= thr;   // implies c1
+    const unsigned sg = (unsigned)(__ballot(sat) >> (16 * q)) & 0xFFFFu;
+    const unsigned g1 = (unsigned)(__ballot(c1) >> (16 * q)) & 0xFFFFu;
+    const unsigned g2 = (unsigned)(__ballot(c2) >> (16 * q)) & 0xFFFFu;
     if (c16 == 0) {
       // no proven-complete, non-empty candidate set (also covers a NaN band): exact full scan
-      S.sat[w][r] = (sg != 0u) || !finite_min || cg == 0u;
-      S.nc[w][r] = __popc(cg);
+      S.sat[w][r] = (sg != 0u) || !finite_min || g1 == 0u;
+      S.nc[w][r] = __popc(g1) + __popc(g2);
     }
-    if (isc) S.cand[w][r][__popc(cg & ((1u << c16) - 1u))] = i1[v];
+    const unsigned below = (1u << c16) - 1u;
+    const int pos = __popc(g1 & below) + __popc(g2 & below);
+    if (c1) S.cand[w][r][pos] = i1[v];
+    if (c2) S.cand[w][r][pos + 1] = i2[v];
   }
 }
 
@@ -307,15 +314,15 @@ __global__ __launch_bounds__(256) void assign_f32_kernel(AssignParams P) {
   __syncthreads();
 
   // ---------------- primary pass ----------------
-  float b1[4], b2[4], lp[4], av[4];
-  int i1[4], pr[4];
+  float b1[4], b2[4], b3[4], lp[4], av[4];
+  int i1[4], i2[4], pr[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    b1[v] = b2[v] = kInf; i1[v] = 0x7fffffff;
+    b1[v] = b2[v] = b3[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
     lp[v] = av[v] = 0.f; pr[v] = -1;
   }
-  sweep<DP, BN, VEC, false>(P, s_c, s_cn, tid, xa, ra, lp, av, pr, b1, i1, b2);
-  publish_candidates(S, w, lane, b1, i1, b2);
+  sweep<DP, BN, VEC, false>(P, s_c, s_cn, tid, xa, ra, lp, av, pr, b1, i1, b2, i2, b3);
+  publish_candidates(S, w, lane, b1, i1, b2, i2, b3);
   __syncthreads();
 
   int pi = -1;
@@ -364,12 +371,12 @@ __global__ __launch_bounds__(256) void assign_f32_kernel(AssignParams P) {
   for (int v = 0; v < 4; ++v) {
     const int r = 4 * q + v;
     lp[v] = S.lp[w][r]; av[v] = S.av[w][r]; pr[v] = S.pi[w][r];
-    b1[v] = b2[v] = kInf; i1[v] = 0x7fffffff;
+    b1[v] = b2[v] = b3[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
   }
 
   // ---------------- spill pass ----------------
-  sweep<DP, BN, VEC, true>(P, s_c, s_cn, tid, xa, ra, lp, av, pr, b1, i1, b2);
-  publish_candidates(S, w, lane, b1, i1, b2);
+  sweep<DP, BN, VEC, true>(P, s_c, s_cn, tid, xa, ra, lp, av, pr, b1, i1, b2, i2, b3);
+  publish_candidates(S, w, lane, b1, i1, b2, i2, b3);
   __syncthreads();
   if (pi < 0) return;  // full-scan rows are finished by the full-scan kernel
   bool ssat = S.sat[w][c16] != 0;

@@ -17,9 +17,12 @@
 //
 // Candidates.  In the 16x16 MFMA result a lane sees one column of every 16-column block, so per
 // row the 16 lanes of a lane group see the 16 residue classes of j mod 16.  Each lane keeps the
-// minimum of its class: the block index is packed into the two low mantissa bits of the value
-// (a 2^-21 relative perturbation) and the tile index is recorded when the minimum improves.
+// minimum of its class: the block index within the tile is packed into the three low mantissa
+// bits of the value (a 2^-20 relative perturbation) and the tile index is recorded when the
+// minimum improves.
 // The topk (<= 8) smallest of the 16 class minima are re-scored.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -47,10 +50,10 @@ struct FmtTraits<LOWP_FP8> {
 };
 
 __device__ __forceinline__ float pack_block(float v, unsigned b) {
-  return __builtin_bit_cast(float, (__builtin_bit_cast(unsigned, v) & ~3u) | b);
+  return __builtin_bit_cast(float, (__builtin_bit_cast(unsigned, v) & ~7u) | b);
 }
 __device__ __forceinline__ unsigned packed_block(float v) {
-  return __builtin_bit_cast(unsigned, v) & 3u;
+  return __builtin_bit_cast(unsigned, v) & 7u;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -65,7 +68,7 @@ __device__ __forceinline__ unsigned char fp8_of(float v) {
 template <int FMT>
 __global__ __launch_bounds__(256) void quantize_rows_kernel(const float* __restrict__ A,
                                                             int64_t rows, int d, int dp,
-                                                            void* __restrict__ out,
+                                                            float mult, void* __restrict__ out,
                                                             float* __restrict__ inv_scale,
                                                             unsigned* counters) {
   const int l16 = threadIdx.x & 15;
@@ -78,12 +81,12 @@ __global__ __launch_bounds__(256) void quantize_rows_kernel(const float* __restr
     float m = 0.f;
     for (int k = l16; k < d; k += 16) {
       const float v = a[k];
-      fin = fin && __builtin_isfinite(v);
+      fin = fin && is_finite_bits(v);
       m = fmaxf(m, fabsf(v));
     }
 #pragma unroll
     for (int off = 1; off < 16; off <<= 1) m = fmaxf(m, __shfl_xor(m, off));
-    if (m > 0.f && __builtin_isfinite(m)) {
+    if (m > 0.f && is_finite_bits(m)) {
       int e;
       (void)frexpf(m, &e);              // m = f * 2^e with f in [0.5, 1)
       scale = ldexpf(1.f, 8 - e);        // m * scale in [128, 256)
@@ -95,8 +98,8 @@ __global__ __launch_bounds__(256) void quantize_rows_kernel(const float* __restr
     __bf16* o = static_cast<__bf16*>(out) + row * dp;
     for (int k = l16; k < dp; k += 16) {
       const float v = k < d ? a[k] : 0.f;
-      fin = fin && __builtin_isfinite(v);
-      o[k] = (__bf16)v;
+      fin = fin && is_finite_bits(v);
+      o[k] = (__bf16)(v * mult);   // mult is a power of two: exact
     }
     if (inv_scale && l16 == 0) inv_scale[row] = 1.f;
   }
@@ -141,22 +144,117 @@ __device__ __forceinline__ v4f mfma_step(const u32x4* a, const u32x4* b, v4f acc
   }
 }
 
-template <int FMT, int DP, int SPW, int BN, bool SP>
-__global__ __launch_bounds__(256) void lowp_sweep_kernel(LowpParams P) {
+// ------------------------------------------------------------------------------------------------
+// Packed codebook: the sweep streams the codebook in tiles of BN centroids, and each tile is one
+// contiguous record in HBM so that the waves can copy it to LDS with direct global->LDS loads:
+//   [BN quantized rows, row stride DP*BYTES + 16 (padding keeps the B reads conflict-free)]
+//   [BN x float4: ||c_j||^2 four times (a finite 3e38 beyond K)]
+//   [BN x float: inverse row scale (FP8) or 1]
+// Rows beyond K are zero.  A record is read with NI whole 4 KiB wave-group copies.
+// ------------------------------------------------------------------------------------------------
+template <int FMT, int DP, int BN>
+struct TileRec {
+  static constexpr int ROWB = DP * FmtTraits<FMT>::BYTES;
+  static constexpr int LDWB = ROWB + 16;
+  static constexpr int CN_OFF = BN * LDWB;
+  static constexpr int CS_OFF = CN_OFF + BN * 16;
+  static constexpr int BYTES = CS_OFF + BN * 4;
+  static constexpr int NI = (BYTES + 4095) / 4096;     // copies per wave (4 waves x 64 lanes x 16 B)
+  static constexpr int STAGE = NI * 4096;              // LDS bytes per ring stage
+};
+
+template <int FMT, int DP, int BN>
+__global__ __launch_bounds__(256) void pack_codebook_kernel(const float* __restrict__ C, int K,
+                                                            int d, const float* __restrict__ cnorm,
+                                                            char* __restrict__ rec,
+                                                            unsigned* counters) {
+  using R = TileRec<FMT, DP, BN>;
+  const int l16 = threadIdx.x & 15;
+  const int j = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int t = j / BN, jl = j % BN;
+  char* base = rec + (int64_t)t * R::BYTES;
+  const bool ok = j < K;
+  const float* c = C + (int64_t)(ok ? j : 0) * d;
+  float scale = 1.f;
+  bool fin = true;
+  if constexpr (FMT == LOWP_FP8) {
+    float m = 0.f;
+    if (ok)
+      for (int k = l16; k < d; k += 16) {
+        fin = fin && is_finite_bits(c[k]);
+        m = fmaxf(m, fabsf(c[k]));
+      }
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if (m > 0.f && is_finite_bits(m)) {
+      int e;
+      (void)frexpf(m, &e);
+      scale = ldexpf(1.f, 8 - e);
+    }
+    unsigned char* o = reinterpret_cast<unsigned char*>(base + jl * R::LDWB);
+    for (int k = l16; k < R::LDWB; k += 16)
+      o[k] = (ok && k < d) ? fp8_of(c[k] * scale) : (unsigned char)0;
+  } else {
+    __bf16* o = reinterpret_cast<__bf16*>(base + jl * R::LDWB);
+    for (int k = l16; k < R::LDWB / 2; k += 16) {
+      const float v = (ok && k < d) ? c[k] : 0.f;
+      fin = fin && is_finite_bits(v);
+      o[k] = (__bf16)(-2.f * v);   // exact: the accumulator then holds ||c||^2 - 2 <x, c>
+    }
+  }
+  if (l16 == 0) {
+    const float cn = ok ? cnorm[j] : kBig;
+    *reinterpret_cast<v4f*>(base + R::CN_OFF + jl * 16) = v4f{cn, cn, cn, cn};
+    *reinterpret_cast<float*>(base + R::CS_OFF + jl * 4) = 1.f / scale;
+  }
+  if (!fin) atomicOr(&counters[CNT_NONFINITE], 1u);
+}
+
+#define LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+
+// Copy record t into ring stage t % STG with direct global->LDS loads: every wave issues exactly
+// NI copies of 64 x 16 bytes (source addresses past the record end are clamped to its last
+// chunk), so the number of outstanding copies is the same in every wave.
+template <int BYTES, int STAGE, int NI, int STG>
+__device__ __forceinline__ void issue_record(const char* recs, char* ring, int t, int w,
+                                             int lane) {
+  const char* src = recs + (int64_t)t * BYTES;
+  char* dst = ring + (t % STG) * STAGE;
+#pragma unroll
+  for (int k = 0; k < NI; ++k) {
+    const int off = (k * 256 + w * 64) * 16;
+    const int c = off + lane * 16;
+    __builtin_amdgcn_global_load_lds(src + (c < BYTES ? c : BYTES - 16), LDS_PTR(dst + off), 16,
+                                     0, 0);
+  }
+}
+
+// Ranking values in the epilogue (row constants of the loss dropped):
+//   BF16: the record holds -2 c (exact), the S accumulator starts at ||c_j||^2 and the T
+//         accumulator at 2 <r_i, x_i>, so S = ||c||^2 - 2<x,c> and T = -2 (<r,c> - <r,x>); the
+//         spill value is S + lambda/(4 ||r||^2) T^2.
+//   FP8:  rows carry scales, so S and T are rescaled per (row, column) in the epilogue.
+// The codebook records flow through an LDS ring of STG stages filled STG-1 tiles ahead.
+template <int FMT, int DP, int SPW, int BN, int STG, int WPE, bool SP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 2)))
+void lowp_sweep_kernel(LowpParams P) {
   using T = FmtTraits<FMT>;
-  constexpr int NB = BN / 16;
+  using R = TileRec<FMT, DP, BN>;
+  constexpr bool BF = FMT == LOWP_BF16;
+  constexpr int NB = BN / 16;                      // 16-column blocks per tile
+  constexpr int GB = NB < 4 ? NB : 4;              // blocks computed together
+  static_assert(NB % GB == 0 && NB <= 8, "tile of at most 8 blocks");
   constexpr int NSTEP = OperandRegs<FMT, DP>::NSTEP, W4 = OperandRegs<FMT, DP>::W4;
-  constexpr int ROWB = DP * T::BYTES;              // bytes of one quantized row
-  constexpr int LDWB = ROWB + 16;                  // LDS row stride (bytes), padded
-  constexpr int CHUNKS = BN * ROWB / 16;           // 16-byte chunks per tile
-  constexpr int NLD = (CHUNKS + 255) / 256;
   constexpr int NR = SPW * 4;                      // rows per lane in the output layout
-  __shared__ __attribute__((aligned(16))) char s_c[2][BN * LDWB];
-  __shared__ float s_cn[2][BN];
-  __shared__ float s_cs[2][BN];
+  __shared__ __attribute__((aligned(16))) char s_ring[STG * R::STAGE];
 
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, c16 = lane & 15;
   const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * (16 * SPW);
+  const int ntiles = (P.K + BN - 1) / BN;
+  const char* recs = static_cast<const char*>(P.Cq);
+
+  issue_record<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, 0, w, lane);
+  if constexpr (STG > 2) { if (ntiles > 1) issue_record<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, 1, w, lane); }
 
   // A operands (A layout: lane (q, c16) holds row c16 of each stripe, quarter q of the dims)
   OperandRegs<FMT, DP> xa[SPW];
@@ -168,8 +266,11 @@ __global__ __launch_bounds__(256) void lowp_sweep_kernel(LowpParams P) {
     if constexpr (SP) load_operand<FMT, DP>(P.Rq, r, r < P.n, q, ra[st]);
   }
   // row constants in the output layout: row (st, 4q + v)
-  float ks[NR], kt[NR], ka[NR], kl[NR];
-  int kp[NR];
+  constexpr int NRF = BF ? 1 : NR;                 // FP8-only row constants
+  constexpr int NRS = SP ? NR : 1;                 // spill-only row constants
+  float ks[NRF], kt[SP ? NRF : 1], ka[SP ? NRF : 1], kl[NRS];
+  int kp[NRS];
+  v4f a2[SP ? SPW : 1];
 #pragma unroll
   for (int st = 0; st < SPW; ++st)
 #pragma unroll
@@ -177,16 +278,16 @@ __global__ __launch_bounds__(256) void lowp_sweep_kernel(LowpParams P) {
       const int i = st * 4 + v;
       const int64_t r = row0 + st * 16 + 4 * q + v;
       const bool ok = r < P.n;
-      ks[i] = -2.f * ((FMT == LOWP_FP8 && ok) ? P.xs[r] : 1.f);
+      if constexpr (!BF) ks[i] = -2.f * (ok ? P.xs[r] : 1.f);
       if constexpr (SP) {
         const float4 rc = ok ? P.rowc[r] : float4{0.f, 0.f, 0.f, 0.f};
-        kt[i] = rc.x;          // inverse scale of the quantized residual row
-        ka[i] = rc.y;          // <r, x>
-        kl[i] = rc.z;          // lambda / ||r||^2
+        if constexpr (!BF) {
+          kt[i] = rc.x;                      // inverse scale of the quantized residual row
+          ka[i] = rc.y;                      // <r, x>
+        }
+        kl[i] = BF ? 0.25f * rc.z : rc.z;    // lambda / ||r||^2 (BF16: / 4 for T = -2e)
         kp[i] = ok ? P.primary[r] : -1;
-      } else {
-        kt[i] = ka[i] = kl[i] = 0.f;
-        kp[i] = -1;
+        a2[st][v] = 2.f * rc.y;
       }
     }
   float b1[NR];
@@ -194,104 +295,102 @@ __global__ __launch_bounds__(256) void lowp_sweep_kernel(LowpParams P) {
 #pragma unroll
   for (int i = 0; i < NR; ++i) { b1[i] = kBig; bt[i] = 0; }
 
-  const int ntiles = (P.K + BN - 1) / BN;
-  u32x4 pre[NLD];
-  float pre_cn = 0.f, pre_cs = 1.f;
-  auto gload = [&](int t) {
-#pragma unroll
-    for (int i = 0; i < NLD; ++i) {
-      const int f = tid + i * 256;
-      const int rr = f / (ROWB / 16), cb = (f % (ROWB / 16)) * 16;
-      const int j = t * BN + rr;
-      pre[i] = (f < CHUNKS && j < P.K)
-                   ? *reinterpret_cast<const u32x4*>(static_cast<const char*>(P.Cq) +
-                                                     (int64_t)j * ROWB + cb)
-                   : u32x4{0u, 0u, 0u, 0u};
-    }
-    if (tid < BN) {
-      const int j = t * BN + tid;
-      pre_cn = j < P.K ? P.cnorm[j] : kBig;
-      pre_cs = (FMT == LOWP_FP8 && j < P.K) ? P.cs[j] : 1.f;
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < NLD; ++i) {
-      const int f = tid + i * 256;
-      if (f < CHUNKS) {
-        const int rr = f / (ROWB / 16), cb = (f % (ROWB / 16)) * 16;
-        *reinterpret_cast<u32x4*>(&s_c[buf][rr * LDWB + cb]) = pre[i];
-      }
-    }
-    if (tid < BN) { s_cn[buf][tid] = pre_cn; s_cs[buf][tid] = pre_cs; }
-  };
-  gload(0);
-  sstore(0);
-  __syncthreads();
   for (int t = 0; t < ntiles; ++t) {
-    const int buf = t & 1;
-    if (t + 1 < ntiles) gload(t + 1);
-    v4f accS[SPW][NB], accT[SP ? SPW : 1][NB];
-#pragma unroll
-    for (int st = 0; st < SPW; ++st)
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        accS[st][b] = v4f{0.f, 0.f, 0.f, 0.f};
-        if constexpr (SP) accT[st][b] = v4f{0.f, 0.f, 0.f, 0.f};
-      }
-#pragma unroll
-    for (int s = 0; s < NSTEP; ++s) {
-      u32x4 bv[NB][W4];
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int ww = 0; ww < W4; ++ww)
-          bv[b][ww] = *reinterpret_cast<const u32x4*>(
-              &s_c[buf][(b * 16 + c16) * LDWB + (q * (DP / 4)) * T::BYTES + s * T::LANE_B +
-                        ww * 16]);
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int st = 0; st < SPW; ++st) {
-          accS[st][b] = mfma_step<FMT>(xa[st].v[s], bv[b], accS[st][b]);
-          if constexpr (SP) accT[st][b] = mfma_step<FMT>(ra[st].v[s], bv[b], accT[st][b]);
-        }
-    }
-    // epilogue: ranking values, class minima, tile of the last improvement
+    // record t has landed in LDS for this wave (later records may still be in flight) ...
+    // (vmcnt counts VMEM operations of this wave in order: with a later record in flight, at most
+    // its NI copies may remain outstanding)
+    if (STG > 2 && t + 1 < ntiles)
+      __builtin_amdgcn_s_waitcnt((R::NI & 15) | (7 << 4) | (15 << 8) | ((R::NI >> 4) << 14));
+    else
+      __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));
+    // ... and for every wave; every wave is also done reading the stage refilled next
+    __builtin_amdgcn_s_barrier();
+    if (t + STG - 1 < ntiles) issue_record<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, t + STG - 1, w, lane);
+    const char* tile = s_ring + (t % STG) * R::STAGE;
+
     float old[NR];
 #pragma unroll
     for (int i = 0; i < NR; ++i) old[i] = b1[i];
-    const bool mask_tile = SP;   // the primary may fall in any tile; masked by index below
+    // does this tile hold the primary of any row of the wave?
+    bool masked = false;
+    if constexpr (SP) {
+      bool hit = false;
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int jl = b * 16 + c16;
-      const int j = t * BN + jl;
-      const float cn = s_cn[buf][jl];
-      const float cs = s_cs[buf][jl];
+      for (int i = 0; i < NRS; ++i) hit |= (unsigned)(kp[i] - t * BN) < (unsigned)BN;
+      masked = __builtin_amdgcn_readfirstlane((int)__any(hit)) != 0;   // wave-uniform
+    }
 #pragma unroll
-      for (int st = 0; st < SPW; ++st)
+    for (int g = 0; g < NB / GB; ++g) {
+      v4f accS[SPW][GB], accT[SP ? SPW : 1][GB];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = st * 4 + v;
-          float val;
-          if constexpr (FMT == LOWP_FP8) {
-            val = fmaf(accS[st][b][v], ks[i] * cs, cn);
-          } else {
-            val = fmaf(accS[st][b][v], -2.f, cn);
-          }
-          if constexpr (SP) {
-            const float tt = (FMT == LOWP_FP8) ? accT[st][b][v] * (kt[i] * cs) : accT[st][b][v];
-            const float e = tt - ka[i];
-            val = fmaf(kl[i] * e, e, val);
-            if (mask_tile && j == kp[i]) val = kBig;
-          }
-          b1[i] = fminf(b1[i], pack_block(val, (unsigned)b));
+      for (int b = 0; b < GB; ++b) {
+        const v4f init = BF ? *reinterpret_cast<const v4f*>(tile + R::CN_OFF +
+                                                             ((g * GB + b) * 16 + c16) * 16)
+                            : v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < SPW; ++st) {
+          accS[st][b] = init;
+          if constexpr (SP) accT[st][b] = BF ? a2[st] : v4f{0.f, 0.f, 0.f, 0.f};
         }
+      }
+#pragma unroll
+      for (int s = 0; s < NSTEP; ++s) {
+        u32x4 bv[GB][W4];
+#pragma unroll
+        for (int b = 0; b < GB; ++b)
+#pragma unroll
+          for (int ww = 0; ww < W4; ++ww)
+            bv[b][ww] = *reinterpret_cast<const u32x4*>(
+                tile + ((g * GB + b) * 16 + c16) * R::LDWB + (q * (DP / 4)) * T::BYTES +
+                s * T::LANE_B + ww * 16);
+#pragma unroll
+        for (int b = 0; b < GB; ++b)
+#pragma unroll
+          for (int st = 0; st < SPW; ++st) {
+            accS[st][b] = mfma_step<FMT>(xa[st].v[s], bv[b], accS[st][b]);
+            if constexpr (SP) accT[st][b] = mfma_step<FMT>(ra[st].v[s], bv[b], accT[st][b]);
+          }
+      }
+      // epilogue: ranking values, class minima (block index packed in the low mantissa bits);
+      // the compare against each row's primary only runs in tiles that hold one
+      auto epilogue = [&](auto with_mask) {
+#pragma unroll
+        for (int st = 0; st < SPW; ++st)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = st * 4 + v;
+            float pv[GB];
+#pragma unroll
+            for (int b = 0; b < GB; ++b) {
+              const int jl = (g * GB + b) * 16 + c16;
+              float val;
+              if constexpr (BF) {
+                val = accS[st][b][v];
+                if constexpr (SP) val = fmaf(kl[i] * accT[st][b][v], accT[st][b][v], val);
+              } else {
+                const float cs = *reinterpret_cast<const float*>(tile + R::CS_OFF + jl * 4);
+                const float cn = *reinterpret_cast<const float*>(tile + R::CN_OFF + jl * 16);
+                val = fmaf(accS[st][b][v], ks[i] * cs, cn);
+                if constexpr (SP) {
+                  const float e = accT[st][b][v] * (kt[i] * cs) - ka[i];
+                  val = fmaf(kl[i] * e, e, val);
+                }
+              }
+              if constexpr (SP && decltype(with_mask)::value)
+                val = (t * BN + jl == kp[i]) ? kBig : val;
+              pv[b] = pack_block(val, (unsigned)(g * GB + b));
+            }
+            float m = pv[0];
+#pragma unroll
+            for (int b = 1; b < GB; ++b) m = fminf(m, pv[b]);
+            b1[i] = fminf(b1[i], m);
+          }
+      };
+      if (__builtin_expect(SP && masked, 0)) epilogue(std::true_type{});
+      else epilogue(std::false_type{});
     }
 #pragma unroll
     for (int i = 0; i < NR; ++i) bt[i] = b1[i] < old[i] ? t : bt[i];
-    if (t + 1 < ntiles) sstore(buf ^ 1);
-    __syncthreads();
   }
 
   // candidates: rank the 16 class minima of every row, keep the topk smallest
@@ -504,62 +603,135 @@ int lowp_padded_dim(int fmt, int d) {
   return -1;
 }
 
-hipError_t launch_lowp_quantize(int fmt, const float* A, int64_t rows, int d, int dp, void* out,
-                                float* inv_scale, unsigned* counters, hipStream_t st) {
+hipError_t launch_lowp_quantize(int fmt, const float* A, int64_t rows, int d, int dp,
+                                bool codebook, void* out, float* inv_scale, unsigned* counters,
+                                hipStream_t st) {
   const dim3 grid((unsigned)((rows + 15) / 16)), block(256);
   if (fmt == LOWP_BF16)
-    hipLaunchKernelGGL(quantize_rows_kernel<LOWP_BF16>, grid, block, 0, st, A, rows, d, dp, out,
-                       inv_scale, counters);
+    hipLaunchKernelGGL(quantize_rows_kernel<LOWP_BF16>, grid, block, 0, st, A, rows, d, dp,
+                       codebook ? -2.f : 1.f, out, inv_scale, counters);
   else
-    hipLaunchKernelGGL(quantize_rows_kernel<LOWP_FP8>, grid, block, 0, st, A, rows, d, dp, out,
-                       inv_scale, counters);
+    hipLaunchKernelGGL(quantize_rows_kernel<LOWP_FP8>, grid, block, 0, st, A, rows, d, dp, 1.f,
+                       out, inv_scale, counters);
   return hipGetLastError();
 }
 
-template <int FMT, int DP, int SPW, int BN>
+// Tile shapes per padded width: SPW stripes of 16 rows per wave in the primary / spill sweep,
+// BN centroids per tile, STG ring stages.
+template <int FMT, int DP>
+struct SweepShape;
+#define SOAR_SHAPE(F, D, SP_P, W_P, SP_S, W_S, B, S)                                \
+  template <>                                                                       \
+  struct SweepShape<F, D> {                                                         \
+    static constexpr int SPW_P = SP_P, WPE_P = W_P, SPW_S = SP_S, WPE_S = W_S;      \
+    static constexpr int BN = B, STG = S;                                           \
+  };
+//         format     DP  primary  spill   BN  stages   (SPW stripes, waves per SIMD)
+SOAR_SHAPE(LOWP_BF16, 32, 4, 2, 2, 2, 64, 3)
+SOAR_SHAPE(LOWP_BF16, 64, 4, 2, 2, 2, 64, 3)
+SOAR_SHAPE(LOWP_BF16, 96, 4, 2, 2, 2, 64, 3)
+SOAR_SHAPE(LOWP_BF16, 128, 4, 2, 2, 1, 64, 3)
+SOAR_SHAPE(LOWP_BF16, 192, 2, 1, 2, 1, 64, 3)
+SOAR_SHAPE(LOWP_BF16, 256, 2, 1, 1, 1, 64, 3)
+SOAR_SHAPE(LOWP_BF16, 384, 1, 1, 1, 1, 64, 2)
+SOAR_SHAPE(LOWP_BF16, 512, 1, 2, 1, 1, 32, 2)
+SOAR_SHAPE(LOWP_BF16, 768, 1, 1, 1, 1, 32, 2)
+SOAR_SHAPE(LOWP_BF16, 1024, 1, 1, 1, 1, 16, 2)
+SOAR_SHAPE(LOWP_FP8, 128, 2, 2, 2, 2, 64, 3)
+SOAR_SHAPE(LOWP_FP8, 256, 2, 2, 2, 1, 64, 3)
+SOAR_SHAPE(LOWP_FP8, 384, 2, 1, 1, 1, 64, 3)
+SOAR_SHAPE(LOWP_FP8, 512, 2, 2, 1, 2, 64, 2)
+SOAR_SHAPE(LOWP_FP8, 768, 1, 1, 1, 1, 64, 2)
+SOAR_SHAPE(LOWP_FP8, 1024, 1, 2, 1, 2, 32, 2)
+#undef SOAR_SHAPE
+
+template <int FMT, int DP>
 static void sweep_dp(const LowpParams& P, bool spill, hipStream_t st) {
-  const dim3 grid((unsigned)((P.n + 64 * SPW - 1) / (64 * SPW))), block(256);
-  if (spill)
-    hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, SPW, BN, true>), grid, block, 0, st, P);
-  else
-    hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, SPW, BN, false>), grid, block, 0, st, P);
+  using S = SweepShape<FMT, DP>;
+  if (spill) {
+    const dim3 grid((unsigned)((P.n + 64 * S::SPW_S - 1) / (64 * S::SPW_S)));
+    hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, S::SPW_S, S::BN, S::STG, S::WPE_S, true>),
+                       grid, dim3(256), 0, st, P);
+  } else {
+    const dim3 grid((unsigned)((P.n + 64 * S::SPW_P - 1) / (64 * S::SPW_P)));
+    hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, S::SPW_P, S::BN, S::STG, S::WPE_P, false>),
+                       grid, dim3(256), 0, st, P);
+  }
 }
 
-static hipError_t sweep_bf16(const LowpParams& P, bool spill, hipStream_t st) {
-  constexpr int F = LOWP_BF16;
-  switch (P.dp) {
-    case 32: sweep_dp<F, 32, 2, 64>(P, spill, st); break;
-    case 64: sweep_dp<F, 64, 2, 64>(P, spill, st); break;
-    case 96: sweep_dp<F, 96, 2, 64>(P, spill, st); break;
-    case 128: sweep_dp<F, 128, 2, 64>(P, spill, st); break;
-    case 192: sweep_dp<F, 192, 2, 64>(P, spill, st); break;
-    case 256: sweep_dp<F, 256, 2, 64>(P, spill, st); break;
-    case 384: sweep_dp<F, 384, 1, 64>(P, spill, st); break;
-    case 512: sweep_dp<F, 512, 1, 64>(P, spill, st); break;
-    case 768: sweep_dp<F, 768, 1, 32>(P, spill, st); break;
-    case 1024: sweep_dp<F, 1024, 1, 32>(P, spill, st); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+template <int FMT, int DP>
+static void pack_dp(const float* C, int K, int d, const float* cnorm, void* rec,
+                    unsigned* counters, hipStream_t st) {
+  constexpr int BN = SweepShape<FMT, DP>::BN;
+  const int kpad = (K + BN - 1) / BN * BN;
+  hipLaunchKernelGGL((pack_codebook_kernel<FMT, DP, BN>), dim3((unsigned)(kpad / 16)), dim3(256),
+                     0, st, C, K, d, cnorm, static_cast<char*>(rec), counters);
 }
 
-static hipError_t sweep_fp8(const LowpParams& P, bool spill, hipStream_t st) {
-  constexpr int F = LOWP_FP8;
-  switch (P.dp) {
-    case 128: sweep_dp<F, 128, 2, 64>(P, spill, st); break;
-    case 256: sweep_dp<F, 256, 2, 64>(P, spill, st); break;
-    case 384: sweep_dp<F, 384, 2, 64>(P, spill, st); break;
-    case 512: sweep_dp<F, 512, 2, 64>(P, spill, st); break;
-    case 768: sweep_dp<F, 768, 1, 64>(P, spill, st); break;
-    case 1024: sweep_dp<F, 1024, 1, 32>(P, spill, st); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+template <int FMT, int DP>
+static size_t rec_bytes_dp(int K) {
+  using S = SweepShape<FMT, DP>;
+  return (size_t)((K + S::BN - 1) / S::BN) * TileRec<FMT, DP, S::BN>::BYTES;
+}
+
+// Dispatch on the padded width with plain switches (kernel templates instantiated from generic
+// lambdas did not get their host launch stubs emitted).
+#define SOAR_DP_CASES(FMT, X)                                        \
+  case 32: if constexpr (FMT == LOWP_BF16) { X(32); } break;         \
+  case 64: if constexpr (FMT == LOWP_BF16) { X(64); } break;         \
+  case 96: if constexpr (FMT == LOWP_BF16) { X(96); } break;         \
+  case 128: X(128); break;                                           \
+  case 192: if constexpr (FMT == LOWP_BF16) { X(192); } break;       \
+  case 256: X(256); break;                                           \
+  case 384: X(384); break;                                           \
+  case 512: X(512); break;                                           \
+  case 768: X(768); break;                                           \
+  case 1024: X(1024); break;                                         \
+  default: break;
+
+template <int FMT>
+static void sweep_fmt(const LowpParams& P, bool spill, hipStream_t st) {
+#define X(D) sweep_dp<FMT, D>(P, spill, st)
+  switch (P.dp) { SOAR_DP_CASES(FMT, X) }
+#undef X
 }
 
 hipError_t launch_lowp_sweep(int fmt, const LowpParams& P, bool spill, hipStream_t st) {
-  return fmt == LOWP_BF16 ? sweep_bf16(P, spill, st) : sweep_fp8(P, spill, st);
+  if (fmt == LOWP_BF16) sweep_fmt<LOWP_BF16>(P, spill, st);
+  else sweep_fmt<LOWP_FP8>(P, spill, st);
+  return hipGetLastError();
 }
+
+template <int FMT>
+static size_t rec_bytes_fmt(int dp, int K) {
+  size_t b = 0;
+#define X(D) b = rec_bytes_dp<FMT, D>(K)
+  switch (dp) { SOAR_DP_CASES(FMT, X) }
+#undef X
+  return b;
+}
+
+size_t lowp_codebook_bytes(int fmt, int d, int K) {
+  const int dp = lowp_padded_dim(fmt, d);
+  return fmt == LOWP_BF16 ? rec_bytes_fmt<LOWP_BF16>(dp, K) : rec_bytes_fmt<LOWP_FP8>(dp, K);
+}
+
+template <int FMT>
+static void pack_fmt(int dp, const float* C, int K, int d, const float* cnorm, void* rec,
+                     unsigned* counters, hipStream_t st) {
+#define X(D) pack_dp<FMT, D>(C, K, d, cnorm, rec, counters, st)
+  switch (dp) { SOAR_DP_CASES(FMT, X) }
+#undef X
+}
+
+hipError_t launch_lowp_pack_codebook(int fmt, const float* C, int K, int d, const float* cnorm,
+                                     void* rec, unsigned* counters, hipStream_t st) {
+  const int dp = lowp_padded_dim(fmt, d);
+  if (fmt == LOWP_BF16) pack_fmt<LOWP_BF16>(dp, C, K, d, cnorm, rec, counters, st);
+  else pack_fmt<LOWP_FP8>(dp, C, K, d, cnorm, rec, counters, st);
+  return hipGetLastError();
+}
+#undef SOAR_DP_CASES
 
 template <int FMT, int M>
 static void rescore_m(const LowpParams& P, bool spill, hipStream_t st) {

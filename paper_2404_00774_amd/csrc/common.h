@@ -19,9 +19,12 @@ enum Counter : int {
   CNT_WORDS = 8
 };
 
+// Finiteness by the exponent bits, so that no floating-point mode or flag can fold it away.
+__device__ __forceinline__ bool is_finite_bits(float v) {
+  return (__builtin_bit_cast(unsigned, v) & 0x7f800000u) != 0x7f800000u;
+}
 __device__ __forceinline__ bool all_finite4(v4f v) {
-  return __builtin_isfinite(v.x) && __builtin_isfinite(v.y) && __builtin_isfinite(v.z) &&
-         __builtin_isfinite(v.w);
+  return is_finite_bits(v.x) && is_finite_bits(v.y) && is_finite_bits(v.z) && is_finite_bits(v.w);
 }
 
 // Sum over the 4 lanes that share (lane & 15): lanes l, l^16, l^32, l^48.

@@ -45,7 +45,7 @@ struct LowpParams {
   const float* X;         // FP32 originals
   const float* C;
   const void* Xq;         // quantized rows, row stride dp elements
-  const void* Cq;
+  const void* Cq;         // packed codebook records (launch_lowp_pack_codebook)
   const void* Rq;
   const float* xs;        // FP8: inverse power-of-two row scales of Xq, Cq
   const float* cs;
@@ -62,9 +62,15 @@ struct LowpParams {
 };
 
 int lowp_padded_dim(int fmt, int d);
-hipError_t launch_lowp_quantize(int fmt, const float* A, int64_t rows, int d, int dp, void* out,
-                                float* inv_scale, unsigned* counters, hipStream_t st);
+// codebook = true stores BF16 rows as -2 c (the sweep's accumulators start at ||c||^2).
+hipError_t launch_lowp_quantize(int fmt, const float* A, int64_t rows, int d, int dp,
+                                bool codebook, void* out, float* inv_scale, unsigned* counters,
+                                hipStream_t st);
 hipError_t launch_lowp_sweep(int fmt, const LowpParams& P, bool spill, hipStream_t st);
+// The sweep reads the codebook from packed per-tile records (see assign_lowp.hip).
+size_t lowp_codebook_bytes(int fmt, int d, int K);
+hipError_t launch_lowp_pack_codebook(int fmt, const float* C, int K, int d, const float* cnorm,
+                                     void* rec, unsigned* counters, hipStream_t st);
 hipError_t launch_lowp_rescore(int fmt, const LowpParams& P, bool spill, hipStream_t st);
 
 }  // namespace soar

@@ -86,7 +86,7 @@ LowpLayout layout_lowp(void* ws, int64_t n, int32_t d, int32_t K, int fmt, int t
   L.counters = c.take<unsigned>(soar::CNT_WORDS);
   L.cnorm = c.take<float>((size_t)K);
   L.Xq = c.take<char>((size_t)n * dp * eb);
-  L.Cq = c.take<char>((size_t)K * dp * eb);
+  L.Cq = c.take<char>(soar::lowp_codebook_bytes(fmt, d, K));
   L.Rq = c.take<char>((size_t)n * dp * eb);
   L.xs = c.take<float>((size_t)n);
   L.cs = c.take<float>((size_t)K);
@@ -122,9 +122,16 @@ AssignLayout layout_assign(void* ws, int64_t n, int32_t K) {
 
 namespace soar {
 
-// Screening bands (rounding-error bounds of the expanded ranking values; see assign_fp32.hip).
-float band_coef_primary(int d) { return 8.f * (float)(d + 2) * kU32; }
-float band_coef_spill(int d, float lam) { return 4.f * (float)(d + 3) * kU32 * (2.f + 3.f * lam); }
+// Screening bands: twice the rounding-error bound of the expanded ranking values, with a 10%
+// margin.  With scale = ||x|| + max||c||:
+//   primary  |(||c||^2 - 2<x,c>)~ - exact| <= gamma_{d+2} scale^2 (norm, dot product, fma);
+//   spill    adds the penalty: lambda/||r||^2 * e^2 with |e| <= ||r|| ||x - c|| and |e~ - e| <=
+//            gamma_{d+2} ||r|| scale, so its error is <= 3 lambda gamma_{d+4} scale^2, plus the
+//            final roundings; in all <= (1 + 3 lambda) gamma_{d+5} scale^2.
+float band_coef_primary(int d) { return 2.2f * (float)(d + 2) * kU32; }
+float band_coef_spill(int d, float lam) {
+  return 2.2f * (1.f + 3.f * lam) * (float)(d + 5) * kU32;
+}
 float tie_threshold(int d, float lam, float near_tie_rel) {
   const float rel = near_tie_rel > 0.f ? near_tie_rel : 1e-5f;
   const float err = (1.f + 3.f * lam) * ((float)d / 16.f + 6.f) * kU32;
@@ -177,8 +184,10 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
   P.primary = primary; P.spill = spill_out; P.pdist = pdist; P.sloss = sloss;
   P.counters = L.counters; P.rowc_out = L.rowc; P.Rq_out = L.Rq;
   hipError_t e = launch_prep_codebook(C, K, d, L.cnorm, L.counters, st);
-  if (e == hipSuccess) e = launch_lowp_quantize(fmt, C, K, d, P.dp, L.Cq, L.cs, L.counters, st);
-  if (e == hipSuccess) e = launch_lowp_quantize(fmt, X, n, d, P.dp, L.Xq, L.xs, L.counters, st);
+  if (e == hipSuccess)
+    e = launch_lowp_pack_codebook(fmt, C, K, d, L.cnorm, L.Cq, L.counters, st);
+  if (e == hipSuccess)
+    e = launch_lowp_quantize(fmt, X, n, d, P.dp, false, L.Xq, L.xs, L.counters, st);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[0], st);
   if (e == hipSuccess) e = launch_lowp_sweep(fmt, P, false, st);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
