@@ -145,6 +145,13 @@ soar_status soar_train_codebook(const float* X, int64_t n, int32_t d, int32_t K,
 typedef struct soar_index soar_index;
 
 /*
+ * Bytes of arena an index needs for these sizes and a list capacity of list_capacity_ids ids in
+ * total (two per inserted point); the rest of a larger arena also holds list chunks.
+ */
+soar_status soar_index_arena_size(int32_t K, int32_t d, int32_t precision, int32_t max_step_rows,
+                                  int64_t list_capacity_ids, size_t* bytes);
+
+/*
  * Create an index over codebook C [K x d] (device, copied into the arena) with spill weight
  * lambda.  The index places the codebook, its per-step buffers and the partition lists inside
  * the caller's device arena (arena_bytes) and never allocates device memory of its own.
@@ -163,11 +170,14 @@ soar_status soar_index_create(const float* C, int32_t K, int32_t d, float lambda
 soar_status soar_insert(soar_index* index, const float* X_host, int64_t n, int64_t first_id,
                         uint64_t* ticket);
 
-/* Wait for a ticket; writes its primary and spill indices to HOST arrays of n entries each. */
+/* Wait for a ticket; writes its primary and spill indices to HOST arrays of n entries each.
+   timeout_s < 0 waits without limit; on SOAR_E_TIMEOUT the ticket stays valid.  A ticket is
+   consumed by the call that returns its result. */
 soar_status soar_wait(soar_index* index, uint64_t ticket, int32_t* primary_host,
                       int32_t* spill_host, double timeout_s);
 
-/* Copy partition `part`'s member ids to a HOST array (at most cap); *len gets the full length. */
+/* Copy partition `part`'s member ids to a HOST array (at most cap); *len gets the full length.
+   The ids of a list are in no particular order.  Steps in flight finish first. */
 soar_status soar_index_list(soar_index* index, int32_t part, int64_t* ids_host, int64_t cap,
                             int64_t* len);
 

@@ -72,6 +72,7 @@ _sig("soar_train_workspace_size", [_i64, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("soar_kmeanspp", [_vp, _i64, _i32, _i32, _u64, _vp, _vp, _vp, _sz, _vp])
 _sig("soar_lloyd_update", [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp])
 _sig("soar_train_codebook", [_vp, _i64, _i32, _i32, _i32, _u64, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
+_sig("soar_index_arena_size", [_i32, _i32, _i32, _i32, _i64, ctypes.POINTER(_sz)])
 _sig("soar_index_create", [_vp, _i32, _i32, _f32, _i32, _vp, _sz, _i32, ctypes.POINTER(_vp)])
 _sig("soar_insert", [_vp, _vp, _i64, _i64, ctypes.POINTER(_u64)])
 _sig("soar_wait", [_vp, _u64, _vp, _vp, _f64])
@@ -80,7 +81,8 @@ _sig("soar_index_destroy", [_vp], None)
 
 EXPORTED = [n for n in ("soar_assign_workspace_size", "soar_assign", "soar_train_workspace_size",
                         "soar_kmeanspp", "soar_lloyd_update", "soar_train_codebook",
-                        "soar_index_create", "soar_insert", "soar_wait", "soar_index_list",
+                        "soar_index_arena_size", "soar_index_create", "soar_insert", "soar_wait",
+                        "soar_index_list",
                         "soar_index_destroy", "soar_status_string") if hasattr(_lib, n)]
 
 
@@ -209,3 +211,75 @@ def train_codebook(X, K, iters, seed=0, C_init=None, stream=None):
                                     _ptr(labels), inertia, _ptr(ws), ws.numel(), _stream(stream)),
            "soar_train_codebook")
     return C, labels, list(inertia)
+
+
+class SoarIndex:
+    """Serving index: resident codebook and inverted lists in a device arena owned by this object.
+
+    insert() queues host rows and returns a ticket at once; wait() returns their (primary, spill)
+    indices; list(p) returns the ids in partition p.  All work runs in the library's scheduler
+    thread and HIP kernels."""
+
+    def __init__(self, C, lam, precision="bf16", max_step_rows=4096, list_capacity=1 << 20,
+                 arena_bytes=None):
+        C = _f32_matrix(C, "C")
+        self.K, self.d = C.shape
+        self.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
+        need = _sz()
+        _check(_lib.soar_index_arena_size(self.K, self.d, self.precision, int(max_step_rows),
+                                          int(list_capacity), ctypes.byref(need)),
+               "soar_index_arena_size")
+        nbytes = need.value if arena_bytes is None else int(arena_bytes)
+        self.arena = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=C.device)
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        _check(_lib.soar_index_create(_ptr(C), self.K, self.d, float(lam), self.precision,
+                                      _ptr(self.arena), self.arena.numel(), int(max_step_rows),
+                                      ctypes.byref(h)), "soar_index_create")
+        self._h = h
+        self._n = {}
+
+    def insert(self, X, first_id):
+        import numpy as np
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        if X.ndim != 2 or X.shape[1] != self.d:
+            raise ValueError("X must be (n, d) float32")
+        t = _u64()
+        _check(_lib.soar_insert(self._h, X.ctypes.data_as(_vp), X.shape[0], int(first_id),
+                                ctypes.byref(t)), "soar_insert")
+        self._n[t.value] = X.shape[0]
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        import numpy as np
+        n = self._n[ticket]
+        p = np.empty(n, dtype=np.int32)
+        s = np.empty(n, dtype=np.int32)
+        st = _lib.soar_wait(self._h, ticket, p.ctypes.data_as(_vp), s.ctypes.data_as(_vp),
+                            float(timeout))
+        if st != -6:
+            self._n.pop(ticket, None)
+        _check(st, "soar_wait")
+        return p, s
+
+    def list(self, part):
+        import numpy as np
+        ln = _i64()
+        _check(_lib.soar_index_list(self._h, int(part), None, 0, ctypes.byref(ln)),
+               "soar_index_list")
+        out = np.empty(ln.value, dtype=np.int64)
+        if ln.value:
+            _check(_lib.soar_index_list(self._h, int(part), out.ctypes.data_as(_vp), ln.value,
+                                        ctypes.byref(ln)), "soar_index_list")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.soar_index_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass

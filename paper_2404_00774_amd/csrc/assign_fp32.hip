@@ -292,8 +292,10 @@ __global__ __launch_bounds__(256) void assign_f32_kernel(AssignParams P) {
   __shared__ RowShared S;
 
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, c16 = lane & 15;
+  const int64_t n = live_rows(P.n, P.live_n);
+  if ((int64_t)blockIdx.x * 64 >= n) return;   // whole block past the live rows
   const int64_t row = (int64_t)blockIdx.x * 64 + w * 16 + c16;  // A-layout row of this lane
-  const bool ok = row < P.n;
+  const bool ok = row < n;
   const float cmax = sqrtf(__uint_as_float(P.counters[CNT_CMAX2]));
 
   float xa[KS], ra[KS];
@@ -552,8 +554,8 @@ __global__ __launch_bounds__(FS_THREADS) void full_scan_kernel(AssignParams P) {
 // ------------------------------------------------------------------------------------------------
 // Codebook preparation: ||c_j||^2, max ||c||^2 and the finiteness flag; counter reset.
 // ------------------------------------------------------------------------------------------------
-__global__ void reset_counters_kernel(unsigned* counters) {
-  if (threadIdx.x < CNT_WORDS) counters[threadIdx.x] = 0u;
+__global__ void reset_counters_kernel(unsigned* counters, int words) {
+  if ((int)threadIdx.x < words) counters[threadIdx.x] = 0u;
 }
 
 __global__ __launch_bounds__(256) void prep_codebook_kernel(const float* __restrict__ C, int K,
@@ -611,9 +613,15 @@ int fp32_padded_dim(int d) {
 
 hipError_t launch_prep_codebook(const float* C, int K, int d, float* cnorm, unsigned* counters,
                                 hipStream_t st) {
-  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, st, counters);
+  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, st, counters, (int)CNT_WORDS);
   hipLaunchKernelGGL(prep_codebook_kernel, dim3((K + 255) / 256), dim3(256), 0, st, C, K, d,
                      cnorm, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_step_counters(unsigned* counters, hipStream_t st) {
+  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, st, counters,
+                     (int)CNT_STEP_WORDS);
   return hipGetLastError();
 }
 

@@ -70,10 +70,11 @@ __global__ __launch_bounds__(256) void quantize_rows_kernel(const float* __restr
                                                             int64_t rows, int d, int dp,
                                                             float mult, void* __restrict__ out,
                                                             float* __restrict__ inv_scale,
-                                                            unsigned* counters) {
+                                                            unsigned* counters,
+                                                            const int64_t* live_n) {
   const int l16 = threadIdx.x & 15;
   const int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
-  if (row >= rows) return;
+  if (row >= live_rows(rows, live_n)) return;
   const float* a = A + row * d;
   float scale = 1.f;
   bool fin = true;
@@ -249,6 +250,8 @@ void lowp_sweep_kernel(LowpParams P) {
   __shared__ __attribute__((aligned(16))) char s_ring[STG * R::STAGE];
 
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, c16 = lane & 15;
+  const int64_t n = live_rows(P.n, P.live_n);
+  if ((int64_t)blockIdx.x * 64 * SPW >= n) return;   // whole block past the live rows
   const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * (16 * SPW);
   const int ntiles = (P.K + BN - 1) / BN;
   const char* recs = static_cast<const char*>(P.Cq);
@@ -262,8 +265,8 @@ void lowp_sweep_kernel(LowpParams P) {
 #pragma unroll
   for (int st = 0; st < SPW; ++st) {
     const int64_t r = row0 + st * 16 + c16;
-    load_operand<FMT, DP>(P.Xq, r, r < P.n, q, xa[st]);
-    if constexpr (SP) load_operand<FMT, DP>(P.Rq, r, r < P.n, q, ra[st]);
+    load_operand<FMT, DP>(P.Xq, r, r < n, q, xa[st]);
+    if constexpr (SP) load_operand<FMT, DP>(P.Rq, r, r < n, q, ra[st]);
   }
   // row constants in the output layout: row (st, 4q + v)
   constexpr int NRF = BF ? 1 : NR;                 // FP8-only row constants
@@ -277,7 +280,7 @@ void lowp_sweep_kernel(LowpParams P) {
     for (int v = 0; v < 4; ++v) {
       const int i = st * 4 + v;
       const int64_t r = row0 + st * 16 + 4 * q + v;
-      const bool ok = r < P.n;
+      const bool ok = r < n;
       if constexpr (!BF) ks[i] = -2.f * (ok ? P.xs[r] : 1.f);
       if constexpr (SP) {
         const float4 rc = ok ? P.rowc[r] : float4{0.f, 0.f, 0.f, 0.f};
@@ -412,7 +415,7 @@ void lowp_sweep_kernel(LowpParams P) {
         const int oj = __shfl(j, src);
         rank += (ov < bv || (ov == bv && oj < j)) ? 1 : 0;
       }
-      if (r < P.n && rank < topk) P.cand[r * topk + rank] = (valid && j < P.K) ? j : -1;
+      if (r < n && rank < topk) P.cand[r * topk + rank] = (valid && j < P.K) ? j : -1;
     }
 }
 
@@ -440,7 +443,7 @@ template <int FMT, bool SP, int RS_MAXD>
 __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
   const int l16 = threadIdx.x & 15;
   const int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
-  if (row >= P.n) return;
+  if (row >= live_rows(P.n, P.live_n)) return;
   const int d = P.d, topk = P.topk;
   const int nd = (d - l16 + 15) / 16;   // dims this lane holds: l16, l16 + 16, ...
   float x[RS_MAXD], r[RS_MAXD];
@@ -605,14 +608,14 @@ int lowp_padded_dim(int fmt, int d) {
 
 hipError_t launch_lowp_quantize(int fmt, const float* A, int64_t rows, int d, int dp,
                                 bool codebook, void* out, float* inv_scale, unsigned* counters,
-                                hipStream_t st) {
+                                hipStream_t st, const int64_t* live_n) {
   const dim3 grid((unsigned)((rows + 15) / 16)), block(256);
   if (fmt == LOWP_BF16)
     hipLaunchKernelGGL(quantize_rows_kernel<LOWP_BF16>, grid, block, 0, st, A, rows, d, dp,
-                       codebook ? -2.f : 1.f, out, inv_scale, counters);
+                       codebook ? -2.f : 1.f, out, inv_scale, counters, live_n);
   else
     hipLaunchKernelGGL(quantize_rows_kernel<LOWP_FP8>, grid, block, 0, st, A, rows, d, dp, 1.f,
-                       out, inv_scale, counters);
+                       out, inv_scale, counters, live_n);
   return hipGetLastError();
 }
 

@@ -18,6 +18,8 @@ enum Counter : int {
   CNT_CMAX2 = 3,      // max_j ||c_j||^2 as float bits (non-negative floats order like uints)
   CNT_WORDS = 8
 };
+// Counters cleared at the start of every assignment (the codebook's CNT_CMAX2 is kept).
+constexpr int CNT_STEP_WORDS = 3;
 
 // Finiteness by the exponent bits, so that no floating-point mode or flag can fold it away.
 __device__ __forceinline__ bool is_finite_bits(float v) {
@@ -25,6 +27,14 @@ __device__ __forceinline__ bool is_finite_bits(float v) {
 }
 __device__ __forceinline__ bool all_finite4(v4f v) {
   return is_finite_bits(v.x) && is_finite_bits(v.y) && is_finite_bits(v.z) && is_finite_bits(v.w);
+}
+
+// Rows to process: the launch capacity, or fewer when a device-side live count is given (graph
+// replays of serving steps read the batch size from device memory).
+__device__ __forceinline__ int64_t live_rows(int64_t cap, const int64_t* live) {
+  if (!live) return cap;
+  const int64_t l = *live;
+  return l < cap ? (l < 0 ? 0 : l) : cap;
 }
 
 // Sum over the 4 lanes that share (lane & 15): lanes l, l^16, l^32, l^48.

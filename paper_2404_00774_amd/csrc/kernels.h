@@ -22,11 +22,19 @@ struct AssignParams {
   float* pdist;
   float* sloss;
   int32_t* full_rows;   // [n] rows handed to the exact full scan
+  const int64_t* live_n = nullptr;   // device row count <= n (serving steps), or null
 };
 
 int fp32_padded_dim(int d);
+// Screening bands and near-tie threshold of the FP32 path (defined with the C ABI).
+float band_coef_primary(int d);
+float band_coef_spill(int d, float lam);
+float tie_threshold(int d, float lam, float near_tie_rel);
+// Clears all counters, then ||c_j||^2, max ||c||^2 and the finiteness flag of the codebook.
 hipError_t launch_prep_codebook(const float* C, int K, int d, float* cnorm, unsigned* counters,
                                 hipStream_t st);
+// Clears the per-assignment counters only (the codebook's maximum norm is kept).
+hipError_t launch_reset_step_counters(unsigned* counters, hipStream_t st);
 // ev_begin / ev_end (nullable) are recorded around the main assignment kernel alone.
 hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipStream_t st,
                               hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
@@ -59,13 +67,14 @@ struct LowpParams {
   unsigned* counters;
   float4* rowc_out;       // written by the primary re-score
   void* Rq_out;
+  const int64_t* live_n = nullptr;   // device row count <= n (serving steps), or null
 };
 
 int lowp_padded_dim(int fmt, int d);
 // codebook = true stores BF16 rows as -2 c (the sweep's accumulators start at ||c||^2).
 hipError_t launch_lowp_quantize(int fmt, const float* A, int64_t rows, int d, int dp,
                                 bool codebook, void* out, float* inv_scale, unsigned* counters,
-                                hipStream_t st);
+                                hipStream_t st, const int64_t* live_n = nullptr);
 hipError_t launch_lowp_sweep(int fmt, const LowpParams& P, bool spill, hipStream_t st);
 // The sweep reads the codebook from packed per-tile records (see assign_lowp.hip).
 size_t lowp_codebook_bytes(int fmt, int d, int K);

@@ -1,0 +1,644 @@
+// Serving: a resident codebook plus inverted lists (Section 2.2: for each partition the ids of
+// the points assigned to it; with SOAR a point sits in the lists of pi(x) and pi'(x)), fed by
+// streaming insert requests.
+//
+// A scheduler thread batches queued rows FIFO into device steps of at most max_step_rows rows
+// (a request may span steps, a step may hold many requests).  Two step slots, each with its own
+// stream, buffers and pre-captured HIP graphs, let consecutive steps overlap on the GPU; a
+// request is admitted to a step when a slot is free and the list arena can take the step's
+// worst-case growth.  A step is
+//   H2D (live row count, rows, ids) -> compute graph (the SOAR assignment kernels, which read the
+//   live row count from device memory) -> [waits for the previous step's list append] -> append
+//   graph (count, reserve chunks, scatter ids) -> D2H (indices, arena usage).
+//
+// Lists live in the caller's arena as chunks of CH ids; partition p owns up to MAXC chunks listed
+// in dir[p].  Appends of one step: count per partition, one thread per touched partition reserves
+// the chunks it needs (an atomic bump of the chunk pool), then every assignment takes a slot by an
+// atomic cursor.  The order of ids inside a list is therefore not fixed; its content is.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/soar.h"
+#include "common.h"
+#include "kernels.h"
+#include "train.h"
+
+namespace soar {
+
+constexpr int LIST_CH = 64;        // ids per chunk
+constexpr int LIST_MAXC = 1024;    // chunks per partition (65536 ids)
+
+struct ListDev {
+  int32_t* len;      // [K] ids in the list
+  int32_t* cursor;   // [K] append cursor of the current step
+  int32_t* cnt;      // [K] appends of the current step (-1: could not reserve)
+  int32_t* dir;      // [K * LIST_MAXC] chunk numbers
+  int64_t* pool;     // [chunks * LIST_CH] ids
+  int32_t* meta;     // [0] chunks in use, [1] overflow flag
+  int32_t chunks;    // pool capacity in chunks
+  int32_t K;
+};
+
+__global__ void fill_i32(int32_t* p, int64_t count, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void list_count_kernel(const int32_t* __restrict__ prim, const int32_t* __restrict__ spl,
+                                  const int64_t* live, int64_t cap, ListDev L) {
+  const int64_t n = live_rows(cap, live);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int a = prim[i], b = spl[i];
+    if (a >= 0 && a < L.K) atomicAdd(&L.cnt[a], 1);
+    if (b >= 0 && b < L.K) atomicAdd(&L.cnt[b], 1);
+  }
+}
+
+__global__ void list_reserve_kernel(ListDev L) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= L.K) return;
+  const int c = L.cnt[p];
+  if (c <= 0) return;
+  const int old = L.len[p], nw = old + c;
+  const int have = (old + LIST_CH - 1) / LIST_CH, need = (nw + LIST_CH - 1) / LIST_CH;
+  const int k = need - have;
+  if (need > LIST_MAXC) { L.cnt[p] = -1; atomicOr(reinterpret_cast<unsigned*>(&L.meta[1]), 1u); return; }
+  if (k > 0) {
+    const int base = atomicAdd(&L.meta[0], k);
+    if (base + k > L.chunks) {
+      L.cnt[p] = -1;
+      atomicOr(reinterpret_cast<unsigned*>(&L.meta[1]), 2u);
+      return;
+    }
+    for (int i = 0; i < k; ++i) L.dir[(int64_t)p * LIST_MAXC + have + i] = base + i;
+  }
+  L.cursor[p] = old;
+  L.len[p] = nw;
+}
+
+__global__ void list_scatter_kernel(const int32_t* __restrict__ prim,
+                                    const int32_t* __restrict__ spl,
+                                    const int64_t* __restrict__ ids, const int64_t* live,
+                                    int64_t cap, ListDev L) {
+  const int64_t n = live_rows(cap, live);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int ab[2] = {prim[i], spl[i]};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int p = ab[k];
+      if (p < 0 || p >= L.K || L.cnt[p] < 0) continue;
+      const int pos = atomicAdd(&L.cursor[p], 1);
+      const int chunk = L.dir[(int64_t)p * LIST_MAXC + pos / LIST_CH];
+      L.pool[(int64_t)chunk * LIST_CH + pos % LIST_CH] = ids[i];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------------------------
+// Host side
+// --------------------------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kAl = 256;
+inline size_t al(size_t x) { return (x + kAl - 1) / kAl * kAl; }
+
+struct Request {
+  uint64_t ticket = 0;
+  int64_t n = 0, first_id = 0;
+  std::vector<float> X;
+  std::vector<int32_t> prim, spill;
+  int64_t next_row = 0;    // rows handed to steps
+  int64_t done_rows = 0;   // rows whose step completed
+  soar_status status = SOAR_OK;
+  bool complete = false;
+};
+
+struct Part {
+  std::shared_ptr<Request> req;
+  int64_t row0, rows, slot_off;
+};
+
+struct Slot {
+  hipStream_t st = nullptr;
+  hipGraphExec_t g_compute = nullptr, g_append = nullptr;
+  hipEvent_t ev_done = nullptr, ev_append = nullptr;
+  // device
+  float* X = nullptr;
+  int64_t* ids = nullptr;
+  int64_t* live = nullptr;
+  int32_t* prim = nullptr;
+  int32_t* spill = nullptr;
+  void* ws = nullptr;            // assignment workspace of this slot
+  unsigned* counters = nullptr;
+  // pinned host staging
+  char* h_in = nullptr;          // [live int64][ids cap int64][X cap*d float]
+  char* h_out = nullptr;         // [prim cap][spill cap][meta 4][counters 8]
+  bool busy = false;
+  int64_t rows = 0, worst_chunks = 0;
+  uint64_t seq = 0;
+  std::vector<Part> parts;
+};
+
+}  // namespace
+
+}  // namespace soar
+
+using namespace soar;
+
+struct soar_index {
+  int32_t K = 0, d = 0, precision = 0, cap = 0, fmt = 0;
+  float lambda = 0.f;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  // codebook (device, inside the arena)
+  float* C = nullptr;
+  float* cnorm = nullptr;
+  void* crec = nullptr;          // packed codebook records (BF16 / FP8)
+  ListDev L{};
+  Slot slots[2];
+  hipEvent_t last_append = nullptr;   // append event of the latest launched step
+  uint64_t seq = 0;
+  // scheduling state (guarded by mu)
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
+  uint64_t next_ticket = 1;
+  int64_t chunks_used = 0;       // known from the last completed step
+  int64_t chunks_reserved = 0;   // worst case of the steps in flight
+  bool shutdown = false;
+  bool device_error = false;
+  bool paused = false;
+  int in_flight = 0;
+  std::thread worker;
+};
+
+namespace {
+
+size_t step_ws_bytes(int fmt_or_fp32, int64_t cap, int d, int K, bool lowp, int fmt) {
+  if (!lowp) return al(CNT_WORDS * 4) + al((size_t)cap * 4);   // counters + full-scan rows
+  const int dp = lowp_padded_dim(fmt, d);
+  const size_t eb = fmt == LOWP_BF16 ? 2 : 1;
+  (void)fmt_or_fp32;
+  (void)K;
+  return al(CNT_WORDS * 4) + 2 * al((size_t)cap * dp * eb) + al((size_t)cap * 4) +
+         al((size_t)cap * 16) + al((size_t)cap * 8 * 4);
+}
+
+struct ArenaPlan {
+  size_t C, cnorm, crec, L_len, L_cursor, L_cnt, L_dir, L_meta, slot[2], pool;
+  size_t slot_bytes, fixed, total;
+  int64_t chunks;
+};
+
+ArenaPlan plan_arena(int K, int d, int precision, int cap, size_t arena_bytes) {
+  ArenaPlan P{};
+  const bool lowp = precision != SOAR_FP32;
+  const int fmt = precision == SOAR_BF16 ? LOWP_BF16 : LOWP_FP8;
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t o = off; off = al(off + b); return o; };
+  P.C = take((size_t)K * d * 4);
+  P.cnorm = take((size_t)K * 4);
+  P.crec = take(lowp ? lowp_codebook_bytes(fmt, d, K) : 0);
+  P.L_len = take((size_t)K * 4);
+  P.L_cursor = take((size_t)K * 4);
+  P.L_cnt = take((size_t)K * 4);
+  P.L_dir = take((size_t)K * LIST_MAXC * 4);
+  P.L_meta = take(64);
+  P.slot_bytes = al((size_t)cap * d * 4) + al((size_t)cap * 8) + al(8) + 2 * al((size_t)cap * 4) +
+                 step_ws_bytes(0, cap, d, K, lowp, fmt);
+  P.slot[0] = take(P.slot_bytes);
+  P.slot[1] = take(P.slot_bytes);
+  P.fixed = off;
+  P.pool = off;
+  P.chunks = arena_bytes > off ? (int64_t)((arena_bytes - off) / (LIST_CH * 8)) : 0;
+  if (P.chunks > INT32_MAX) P.chunks = INT32_MAX;
+  P.total = off + (size_t)P.chunks * LIST_CH * 8;
+  return P;
+}
+
+int64_t worst_chunks(int64_t rows, int K) {
+  const int64_t a = 2 * rows;
+  return (a + LIST_CH - 1) / LIST_CH + std::min<int64_t>(a, K);
+}
+
+// Launch the assignment kernels of one step on st (captured into the slot's compute graph).
+hipError_t enqueue_compute(soar_index* ix, Slot& s) {
+  const bool lowp = ix->precision != SOAR_FP32;
+  hipError_t e = launch_reset_step_counters(s.counters, s.st);
+  if (e != hipSuccess) return e;
+  if (!lowp) {
+    AssignParams P;
+    P.X = s.X; P.n = ix->cap; P.d = ix->d; P.C = ix->C; P.K = ix->K;
+    P.cnorm = ix->cnorm; P.counters = s.counters;
+    P.lam = ix->lambda;
+    P.tie_rel = tie_threshold(ix->d, ix->lambda, 0.f);
+    P.band_p = band_coef_primary(ix->d);
+    P.band_s = band_coef_spill(ix->d, ix->lambda);
+    P.primary = s.prim; P.spill = s.spill; P.pdist = nullptr; P.sloss = nullptr;
+    char* w = static_cast<char*>(s.ws) + al(CNT_WORDS * 4);
+    P.full_rows = reinterpret_cast<int32_t*>(w);
+    P.live_n = s.live;
+    return launch_assign_fp32(P, true, ix->d % 4 == 0, s.st);
+  }
+  const int fmt = ix->fmt, dp = lowp_padded_dim(fmt, ix->d);
+  const size_t eb = fmt == LOWP_BF16 ? 2 : 1;
+  char* w = static_cast<char*>(s.ws) + al(CNT_WORDS * 4);
+  LowpParams P;
+  P.n = ix->cap; P.d = ix->d; P.dp = dp; P.K = ix->K; P.topk = 8;
+  P.lam = ix->lambda;
+  P.tie_rel = tie_threshold(ix->d, ix->lambda, 0.f);
+  P.X = s.X; P.C = ix->C;
+  P.Xq = w; w += al((size_t)ix->cap * dp * eb);
+  P.Rq = w; P.Rq_out = w; w += al((size_t)ix->cap * dp * eb);
+  P.xs = reinterpret_cast<float*>(w); w += al((size_t)ix->cap * 4);
+  P.rowc = reinterpret_cast<float4*>(w); P.rowc_out = reinterpret_cast<float4*>(w);
+  w += al((size_t)ix->cap * 16);
+  P.cand = reinterpret_cast<int32_t*>(w);
+  P.Cq = ix->crec; P.cs = nullptr; P.cnorm = ix->cnorm;
+  P.primary = s.prim; P.spill = s.spill; P.pdist = nullptr; P.sloss = nullptr;
+  P.counters = s.counters;
+  P.live_n = s.live;
+  e = launch_lowp_quantize(fmt, s.X, ix->cap, ix->d, dp, false, const_cast<void*>(P.Xq),
+                           const_cast<float*>(P.xs), s.counters, s.st, s.live);
+  if (e == hipSuccess) e = launch_lowp_sweep(fmt, P, false, s.st);
+  if (e == hipSuccess) e = launch_lowp_rescore(fmt, P, false, s.st);
+  if (e == hipSuccess) e = launch_lowp_sweep(fmt, P, true, s.st);
+  if (e == hipSuccess) e = launch_lowp_rescore(fmt, P, true, s.st);
+  return e;
+}
+
+hipError_t enqueue_append(soar_index* ix, Slot& s) {
+  const ListDev& L = ix->L;
+  hipLaunchKernelGGL(fill_i32, dim3((L.K + 255) / 256), dim3(256), 0, s.st, L.cnt, (int64_t)L.K, 0);
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((ix->cap + 255) / 256, 1024));
+  hipLaunchKernelGGL(list_count_kernel, dim3(g), dim3(256), 0, s.st, s.prim, s.spill, s.live,
+                     (int64_t)ix->cap, L);
+  hipLaunchKernelGGL(list_reserve_kernel, dim3((L.K + 255) / 256), dim3(256), 0, s.st, L);
+  hipLaunchKernelGGL(list_scatter_kernel, dim3(g), dim3(256), 0, s.st, s.prim, s.spill, s.ids,
+                     s.live, (int64_t)ix->cap, L);
+  return hipGetLastError();
+}
+
+template <typename F>
+hipError_t capture(hipStream_t st, hipGraphExec_t* out, F&& body) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t eb = body();
+  e = hipStreamEndCapture(st, &g);
+  if (eb != hipSuccess) { if (g) (void)hipGraphDestroy(g); return eb; }
+  if (e != hipSuccess) return e;
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
+}
+
+// Completion of the oldest busy slot (called without the lock held while waiting).
+void complete_slot(soar_index* ix, Slot& s, std::unique_lock<std::mutex>& lk) {
+  lk.unlock();
+  const hipError_t e = hipEventSynchronize(s.ev_done);
+  lk.lock();
+  const int32_t* hp = reinterpret_cast<const int32_t*>(s.h_out);
+  const int32_t* hs = hp + ix->cap;
+  const int32_t* meta = hs + ix->cap;
+  const unsigned* cnt = reinterpret_cast<const unsigned*>(meta + 4);
+  soar_status st = SOAR_OK;
+  if (e != hipSuccess) { st = SOAR_E_DEVICE; ix->device_error = true; }
+  else if (meta[1] != 0) st = SOAR_E_NOMEM;
+  else if (cnt[CNT_NONFINITE]) st = SOAR_E_NONFINITE;
+  if (e == hipSuccess) ix->chunks_used = meta[0];
+  ix->chunks_reserved -= s.worst_chunks;
+  for (Part& p : s.parts) {
+    Request& r = *p.req;
+    std::memcpy(r.prim.data() + p.row0, hp + p.slot_off, p.rows * 4);
+    std::memcpy(r.spill.data() + p.row0, hs + p.slot_off, p.rows * 4);
+    if (st != SOAR_OK && r.status == SOAR_OK) r.status = st;
+    r.done_rows += p.rows;
+    if (r.done_rows == r.n) {
+      r.complete = true;
+      r.X.clear();
+      r.X.shrink_to_fit();
+    }
+  }
+  s.parts.clear();
+  s.busy = false;
+  --ix->in_flight;
+  ix->cv_done.notify_all();
+}
+
+// Fill slot s from the queue and launch it (lock held; released around the copies).
+bool try_launch(soar_index* ix, Slot& s, std::unique_lock<std::mutex>& lk) {
+  if (ix->queue.empty() || ix->device_error || ix->paused) return false;
+  // admission by memory: the most rows whose worst-case list growth fits the free chunks
+  const int64_t free_chunks = ix->L.chunks - ix->chunks_used - ix->chunks_reserved;
+  int64_t limit = ix->cap;
+  while (limit > 0 && worst_chunks(limit, ix->K) > free_chunks) limit /= 2;
+  if (limit == 0) {
+    if (ix->in_flight == 0) {
+      // nothing in flight will release memory: the request at the head can never be placed
+      Request& r = *ix->queue.front();
+      r.status = SOAR_E_NOMEM;
+      r.complete = true;
+      ix->queue.pop_front();
+      ix->cv_done.notify_all();
+    }
+    return false;
+  }
+  // rows for this step, FIFO, splitting the last request if needed
+  int64_t rows = 0;
+  std::vector<Part> parts;
+  for (auto it = ix->queue.begin(); it != ix->queue.end() && rows < limit; ++it) {
+    Request& r = **it;
+    const int64_t take = std::min<int64_t>(r.n - r.next_row, limit - rows);
+    if (take <= 0) continue;
+    parts.push_back(Part{*it, r.next_row, take, rows});
+    rows += take;
+  }
+  if (rows == 0) return false;
+  const int64_t worst = worst_chunks(rows, ix->K);
+  // commit the rows to this step
+  for (Part& p : parts) {
+    p.req->next_row += p.rows;
+  }
+  while (!ix->queue.empty() && ix->queue.front()->next_row == ix->queue.front()->n)
+    ix->queue.pop_front();
+  s.parts = parts;
+  s.rows = rows;
+  s.worst_chunks = worst;
+  s.busy = true;
+  s.seq = ++ix->seq;
+  ix->chunks_reserved += worst;
+  ++ix->in_flight;
+  hipEvent_t prev_append = ix->last_append;
+  ix->last_append = s.ev_append;
+  lk.unlock();
+  // stage the rows (pinned), then the step
+  int64_t* hlive = reinterpret_cast<int64_t*>(s.h_in);
+  int64_t* hids = hlive + 1;
+  float* hX = reinterpret_cast<float*>(hids + ix->cap);
+  hlive[0] = rows;
+  for (Part& p : s.parts) {
+    const Request& r = *p.req;
+    std::memcpy(hX + p.slot_off * ix->d, r.X.data() + p.row0 * ix->d, p.rows * ix->d * 4);
+    for (int64_t i = 0; i < p.rows; ++i) hids[p.slot_off + i] = r.first_id + p.row0 + i;
+  }
+  hipError_t e = hipMemcpyAsync(s.live, hlive, 8, hipMemcpyHostToDevice, s.st);
+  if (e == hipSuccess) e = hipMemcpyAsync(s.ids, hids, rows * 8, hipMemcpyHostToDevice, s.st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s.X, hX, rows * ix->d * 4, hipMemcpyHostToDevice, s.st);
+  if (e == hipSuccess) e = hipGraphLaunch(s.g_compute, s.st);
+  if (e == hipSuccess && prev_append) e = hipStreamWaitEvent(s.st, prev_append, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(s.g_append, s.st);
+  if (e == hipSuccess) e = hipEventRecord(s.ev_append, s.st);
+  int32_t* hp = reinterpret_cast<int32_t*>(s.h_out);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hp, s.prim, rows * 4, hipMemcpyDeviceToHost, s.st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hp + ix->cap, s.spill, rows * 4, hipMemcpyDeviceToHost, s.st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hp + 2 * ix->cap, ix->L.meta, 16, hipMemcpyDeviceToHost, s.st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hp + 2 * ix->cap + 4, s.counters, CNT_WORDS * 4, hipMemcpyDeviceToHost,
+                       s.st);
+  if (e == hipSuccess) e = hipEventRecord(s.ev_done, s.st);
+  lk.lock();
+  if (e != hipSuccess) ix->device_error = true;
+  return true;
+}
+
+void worker_loop(soar_index* ix) {
+  std::unique_lock<std::mutex> lk(ix->mu);
+  for (;;) {
+    bool progressed = false;
+    for (Slot& s : ix->slots)
+      if (!s.busy && try_launch(ix, s, lk)) progressed = true;
+    if (progressed) continue;
+    // wait for the oldest step in flight
+    Slot* oldest = nullptr;
+    for (Slot& s : ix->slots)
+      if (s.busy && (!oldest || s.seq < oldest->seq)) oldest = &s;
+    if (oldest) {
+      complete_slot(ix, *oldest, lk);
+      continue;
+    }
+    if (ix->shutdown && ix->queue.empty()) break;
+    if (ix->device_error && !ix->queue.empty()) {
+      for (auto& r : ix->queue) { r->status = SOAR_E_DEVICE; r->complete = true; }
+      ix->queue.clear();
+      ix->cv_done.notify_all();
+      continue;
+    }
+    ix->cv_work.wait(lk);
+  }
+}
+
+void free_index(soar_index* ix) {
+  for (Slot& s : ix->slots) {
+    if (s.g_compute) (void)hipGraphExecDestroy(s.g_compute);
+    if (s.g_append) (void)hipGraphExecDestroy(s.g_append);
+    if (s.ev_done) (void)hipEventDestroy(s.ev_done);
+    if (s.ev_append) (void)hipEventDestroy(s.ev_append);
+    if (s.st) (void)hipStreamDestroy(s.st);
+    if (s.h_in) (void)hipHostFree(s.h_in);
+    if (s.h_out) (void)hipHostFree(s.h_out);
+  }
+  delete ix;
+}
+
+}  // namespace
+
+extern "C" {
+
+soar_status soar_index_arena_size(int32_t K, int32_t d, int32_t precision, int32_t max_step_rows,
+                                  int64_t list_capacity_ids, size_t* bytes) {
+  if (!bytes || K < 2 || d < 1 || max_step_rows < 1 || list_capacity_ids < 0) return SOAR_E_INVAL;
+  if (precision == SOAR_FP32 ? fp32_padded_dim(d) < 0
+                             : lowp_padded_dim(precision == SOAR_BF16 ? LOWP_BF16 : LOWP_FP8, d) < 0)
+    return SOAR_E_UNSUPPORTED;
+  const ArenaPlan P = plan_arena(K, d, precision, max_step_rows, 0);
+  const int64_t chunks = (list_capacity_ids + LIST_CH - 1) / LIST_CH + 2 * (int64_t)K;
+  *bytes = P.fixed + (size_t)chunks * LIST_CH * 8;
+  return SOAR_OK;
+}
+
+soar_status soar_index_create(const float* C, int32_t K, int32_t d, float lambda,
+                              int32_t precision, void* arena, size_t arena_bytes,
+                              int32_t max_step_rows, soar_index** out) {
+  if (!C || !arena || !out || K < 2 || d < 1 || max_step_rows < 1 || !std::isfinite(lambda) ||
+      lambda < 0.f || (reinterpret_cast<uintptr_t>(arena) % 256) != 0)
+    return SOAR_E_INVAL;
+  if (precision != SOAR_FP32 && precision != SOAR_BF16 && precision != SOAR_FP8_E4M3)
+    return SOAR_E_INVAL;
+  const int fmt = precision == SOAR_BF16 ? LOWP_BF16 : LOWP_FP8;
+  if (precision == SOAR_FP32 ? fp32_padded_dim(d) < 0 : lowp_padded_dim(fmt, d) < 0)
+    return SOAR_E_UNSUPPORTED;
+  const ArenaPlan plan = plan_arena(K, d, precision, max_step_rows, arena_bytes);
+  if (plan.chunks < 1) return SOAR_E_NOMEM;
+  soar_index* ix = new soar_index();
+  ix->K = K; ix->d = d; ix->precision = precision; ix->cap = max_step_rows; ix->fmt = fmt;
+  ix->lambda = lambda;
+  ix->arena = static_cast<char*>(arena);
+  ix->arena_bytes = arena_bytes;
+  char* A = ix->arena;
+  ix->C = reinterpret_cast<float*>(A + plan.C);
+  ix->cnorm = reinterpret_cast<float*>(A + plan.cnorm);
+  ix->crec = A + plan.crec;
+  ListDev& L = ix->L;
+  L.len = reinterpret_cast<int32_t*>(A + plan.L_len);
+  L.cursor = reinterpret_cast<int32_t*>(A + plan.L_cursor);
+  L.cnt = reinterpret_cast<int32_t*>(A + plan.L_cnt);
+  L.dir = reinterpret_cast<int32_t*>(A + plan.L_dir);
+  L.meta = reinterpret_cast<int32_t*>(A + plan.L_meta);
+  L.pool = reinterpret_cast<int64_t*>(A + plan.pool);
+  L.chunks = (int32_t)plan.chunks;
+  L.K = K;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    Slot& s = ix->slots[k];
+    char* b = A + plan.slot[k];
+    s.X = reinterpret_cast<float*>(b); b += al((size_t)max_step_rows * d * 4);
+    s.ids = reinterpret_cast<int64_t*>(b); b += al((size_t)max_step_rows * 8);
+    s.live = reinterpret_cast<int64_t*>(b); b += al(8);
+    s.prim = reinterpret_cast<int32_t*>(b); b += al((size_t)max_step_rows * 4);
+    s.spill = reinterpret_cast<int32_t*>(b); b += al((size_t)max_step_rows * 4);
+    s.ws = b;
+    s.counters = reinterpret_cast<unsigned*>(b);
+    e = hipStreamCreate(&s.st);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.ev_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.ev_append, hipEventDisableTiming);
+    if (e == hipSuccess)
+      e = hipHostMalloc(reinterpret_cast<void**>(&s.h_in),
+                        8 + (size_t)max_step_rows * 8 + (size_t)max_step_rows * d * 4, 0);
+    if (e == hipSuccess)
+      e = hipHostMalloc(reinterpret_cast<void**>(&s.h_out),
+                        (size_t)max_step_rows * 8 + 16 + CNT_WORDS * 4, 0);
+  }
+  hipStream_t st0 = ix->slots[0].st;
+  // resident codebook, its norms (and maximum norm in every slot's counters), packed records
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ix->C, C, (size_t)K * d * 4, hipMemcpyDefault, st0);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = launch_prep_codebook(ix->C, K, d, ix->cnorm, ix->slots[k].counters, st0);
+  if (e == hipSuccess && precision != SOAR_FP32)
+    e = launch_lowp_pack_codebook(fmt, ix->C, K, d, ix->cnorm, ix->crec, ix->slots[0].counters, st0);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(fill_i32, dim3((K + 255) / 256), dim3(256), 0, st0, L.len, (int64_t)K, 0);
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st0, L.meta, (int64_t)16, 0);
+    e = hipGetLastError();
+  }
+  unsigned cflags[CNT_WORDS] = {0};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(cflags, ix->slots[0].counters, CNT_WORDS * 4, hipMemcpyDeviceToHost, st0);
+  if (e == hipSuccess) e = hipStreamSynchronize(st0);
+  if (e != hipSuccess) { free_index(ix); return SOAR_E_DEVICE; }
+  if (cflags[CNT_NONFINITE]) { free_index(ix); return SOAR_E_NONFINITE; }
+  // graphs of the two slots
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    Slot& s = ix->slots[k];
+    e = capture(s.st, &s.g_compute, [&] { return enqueue_compute(ix, s); });
+    if (e == hipSuccess) e = capture(s.st, &s.g_append, [&] { return enqueue_append(ix, s); });
+  }
+  if (e != hipSuccess) { free_index(ix); return SOAR_E_DEVICE; }
+  ix->worker = std::thread(worker_loop, ix);
+  *out = ix;
+  return SOAR_OK;
+}
+
+soar_status soar_insert(soar_index* ix, const float* X_host, int64_t n, int64_t first_id,
+                        uint64_t* ticket) {
+  if (!ix || !X_host || !ticket || n < 1) return SOAR_E_INVAL;
+  if (2 * n > (int64_t)ix->L.chunks * LIST_CH) return SOAR_E_NOMEM;   // can never fit
+  auto r = std::make_shared<Request>();
+  r->n = n;
+  r->first_id = first_id;
+  r->X.assign(X_host, X_host + n * ix->d);
+  r->prim.assign(n, -1);
+  r->spill.assign(n, -1);
+  {
+    std::lock_guard<std::mutex> g(ix->mu);
+    if (ix->shutdown) return SOAR_E_SHUTDOWN;
+    r->ticket = ix->next_ticket++;
+    ix->tickets[r->ticket] = r;
+    ix->queue.push_back(r);
+  }
+  ix->cv_work.notify_one();
+  *ticket = r->ticket;
+  return SOAR_OK;
+}
+
+soar_status soar_wait(soar_index* ix, uint64_t ticket, int32_t* primary_host, int32_t* spill_host,
+                      double timeout_s) {
+  if (!ix) return SOAR_E_INVAL;
+  std::unique_lock<std::mutex> lk(ix->mu);
+  auto it = ix->tickets.find(ticket);
+  if (it == ix->tickets.end()) return SOAR_E_INVAL;
+  std::shared_ptr<Request> r = it->second;
+  auto done = [&] { return r->complete; };
+  if (timeout_s < 0) ix->cv_done.wait(lk, done);
+  else if (!ix->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done))
+    return SOAR_E_TIMEOUT;
+  if (primary_host) std::memcpy(primary_host, r->prim.data(), r->n * 4);
+  if (spill_host) std::memcpy(spill_host, r->spill.data(), r->n * 4);
+  const soar_status s = r->status;
+  ix->tickets.erase(ticket);
+  return s;
+}
+
+soar_status soar_index_list(soar_index* ix, int32_t part, int64_t* ids_host, int64_t cap,
+                            int64_t* len) {
+  if (!ix || !len || part < 0 || part >= ix->K || cap < 0 || (cap > 0 && !ids_host))
+    return SOAR_E_INVAL;
+  std::unique_lock<std::mutex> lk(ix->mu);
+  // hold new steps and let the ones in flight finish
+  ix->paused = true;
+  ix->cv_done.wait(lk, [&] { return ix->in_flight == 0; });
+  hipStream_t st = ix->slots[0].st;
+  int32_t n = 0;
+  std::vector<int32_t> dir;
+  hipError_t e = hipMemcpyAsync(&n, ix->L.len + part, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && n > 0) {
+    const int nch = (n + LIST_CH - 1) / LIST_CH;
+    dir.resize(nch);
+    e = hipMemcpyAsync(dir.data(), ix->L.dir + (int64_t)part * LIST_MAXC, nch * 4,
+                       hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    const int64_t want = std::min<int64_t>(n, cap);
+    for (int c = 0; c < nch && e == hipSuccess && c * LIST_CH < want; ++c) {
+      const int64_t k = std::min<int64_t>(LIST_CH, want - (int64_t)c * LIST_CH);
+      e = hipMemcpyAsync(ids_host + (int64_t)c * LIST_CH, ix->L.pool + (int64_t)dir[c] * LIST_CH,
+                         k * 8, hipMemcpyDeviceToHost, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  ix->paused = false;
+  lk.unlock();
+  ix->cv_work.notify_one();
+  *len = n;
+  return e == hipSuccess ? SOAR_OK : SOAR_E_DEVICE;
+}
+
+void soar_index_destroy(soar_index* ix) {
+  if (!ix) return;
+  {
+    std::lock_guard<std::mutex> g(ix->mu);
+    ix->shutdown = true;
+  }
+  ix->cv_work.notify_all();
+  if (ix->worker.joinable()) ix->worker.join();
+  free_index(ix);
+}
+
+}  // extern "C"
