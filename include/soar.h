@@ -91,7 +91,8 @@ soar_status soar_assign_workspace_size(int64_t n, int32_t d, int32_t K,
  *   spill_loss [n]                nullable output: the SOAR loss at pi'
  *   workspace / ws_bytes          device scratch of at least soar_assign_workspace_size bytes
  *   stats                         nullable host struct, filled by blocking calls
- * Requires n >= 1, d >= 1, K >= 2.  FP32: any d <= 256.
+ * Requires n >= 1, d >= 1, K >= 2.  FP32: d <= 1024 (rows above 256 are processed in chunks of
+ * 128 dimensions); BF16: d <= 1024; FP8: d <= 1024.  Larger d: SOAR_E_UNSUPPORTED.
  * Accuracy (FP32): indices are exact arg-mins up to near-ties of 1e-6 relative; reported values
  * are within 1e-5 relative of the exact value at the reported index.
  */
@@ -134,7 +135,7 @@ soar_status soar_lloyd_update(const float* X, int64_t n, int32_t d, const int32_
  *   labels [n]            nullable device output: nearest centroid of every row in C_out
  *   inertia [iters + 1]   nullable HOST output: sum of squared distances before each update and,
  *                         last, against C_out
- * Requires 1 <= K <= n (K >= 2 when the codebook is meant for soar_assign), iters >= 0, d <= 256.
+ * Requires 1 <= K <= n (K >= 2 when the codebook is meant for soar_assign), iters >= 0, d <= 1024.
  */
 soar_status soar_train_codebook(const float* X, int64_t n, int32_t d, int32_t K, int32_t iters,
                                 uint64_t seed, const float* C_init, float* C_out, int32_t* labels,

@@ -2,11 +2,14 @@
 // Theorem 3.1) for a block of rows in one kernel.
 //
 // Layout of the work.  A workgroup of 4 waves owns 64 consecutive rows (16 per wave).  Each wave
-// keeps its 16 rows of X -- and, for the spill, of R = X - C[pi] -- resident in VGPRs in the
-// A-operand layout of v_mfma_f32_16x16x4_f32, and the workgroup streams the codebook through
-// double-buffered LDS tiles of BN centroids.  The contraction dimension is permuted so that lane
-// group q = lane/16 holds the contiguous quarter [q*DP/4, (q+1)*DP/4) of every row: at MFMA step
-// s lane (q, i) supplies X[i][q*DP/4 + s] and C[j][q*DP/4 + s], so both operands load as float4.
+// keeps its 16 rows of X -- and, for the spill, of R = X - C[pi] -- in VGPRs in the A-operand
+// layout of v_mfma_f32_16x16x4_f32, and the workgroup streams the codebook through a two-stage
+// LDS ring filled by direct global->LDS copies of packed tile records (no register staging).
+// The contraction dimension is permuted so that lane group q = lane/16 holds the contiguous
+// quarter [q*DP/4, (q+1)*DP/4) of every row: at MFMA step s lane (q, i) supplies X[i][q*DP/4 + s]
+// and C[j][q*DP/4 + s], so both operands load as float4.  Rows longer than 256 are cut into
+// chunks of DP = 128: the ring then carries one (tile, chunk) record per step, the accumulators
+// run across the chunks of a tile, and each wave reloads its rows' chunk from L2 one step ahead.
 //
 // Exactness.  The tile epilogue ranks centroids by the expanded value (constants of the row
 // dropped)
@@ -16,18 +19,41 @@
 // over the columns it sees.  With delta a proven bound on the expansion's rounding error, every
 // centroid whose value lies within 2*delta of the row minimum is a candidate for the exact
 // arg-min; the lanes' two bests cover all of them unless some lane's third best is itself inside
-// that band, in which case the row is handed to the exact full scan.  Candidates are re-scored by direct differences
-// in FP32 (16 partial sums per row), and candidates within the near-tie gap of the best are
-// re-decided in FP64.  Ties go to the lowest index.
+// that band, in which case the row is handed to the exact full scan.  Candidates are re-scored by
+// direct differences in FP32 (16 partial sums per row), and candidates within the near-tie gap of
+// the best are re-decided in FP64.  Ties go to the lowest index.
 #include "common.h"
 #include "kernels.h"
 
 namespace soar {
 
+// Packed codebook record of tile t (centroids [t*BN, t*BN + BN)) and chunk ch (dimensions
+// [ch*DP, ch*DP + DP)), records ordered by (t, ch):
+//   [BN rows of DP floats, row stride LDW = DP + 4 (the pad keeps the B-operand reads of the 16
+//    lanes of a group on distinct banks); zeros past d and past K]
+//   [BN floats ||c_j||^2, +inf past K]
+// Each record is copied with NI whole wave-group copies (4 waves x 64 lanes x 16 bytes).
+template <int DP, int BN>
+struct F32Rec {
+  static constexpr int LDW = DP + 4;
+  static constexpr int CN_OFF = BN * LDW * 4;
+  static constexpr int BYTES = CN_OFF + BN * 4;
+  static constexpr int NI = (BYTES + 4095) / 4096;
+  static constexpr int STAGE = NI * 4096;
+};
+
+template <int DP, int BN>
+__device__ __forceinline__ const float* rec_row(const char* recs, int nch, int j, int ch) {
+  using R = F32Rec<DP, BN>;
+  return reinterpret_cast<const float*>(recs + ((int64_t)(j / BN) * nch + ch) * R::BYTES) +
+         (j % BN) * R::LDW;
+}
+
+// KS consecutive values of row `row` of a row-major [* x d] matrix from column k0 (zeros past d
+// and for rows that do not exist).
 template <int KS, bool VEC>
-__device__ __forceinline__ void load_quarter(const float* __restrict__ base, int64_t row, int d,
-                                             int q, bool ok, float (&v)[KS]) {
-  const int k0 = q * KS;
+__device__ __forceinline__ void load_seg(const float* __restrict__ base, int64_t row, int d,
+                                         int k0, bool ok, float (&v)[KS]) {
   const float* p = base + row * (int64_t)d + k0;
   if constexpr (VEC) {
 #pragma unroll
@@ -42,22 +68,47 @@ __device__ __forceinline__ void load_quarter(const float* __restrict__ base, int
   }
 }
 
-// Direct ||x - c_j||^2 (and <r, x - c_j>) over this lane's quarter, 4 partial sums per lane.
-template <int KS, bool VEC, bool SP>
-__device__ __forceinline__ void direct32(const float* __restrict__ C, int d, int j, int q,
-                                         const float (&xa)[KS], const float (&ra)[KS], float& sq,
-                                         float& pj) {
-  float c[KS];
-  load_quarter<KS, VEC>(C, j, d, q, true, c);
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+// KS consecutive values of a record row (16-byte aligned, zero padded).
+template <int KS>
+__device__ __forceinline__ void load_rec(const float* p, float (&v)[KS]) {
 #pragma unroll
   for (int s = 0; s < KS; s += 4) {
-    const float e0 = xa[s] - c[s], e1 = xa[s + 1] - c[s + 1];
-    const float e2 = xa[s + 2] - c[s + 2], e3 = xa[s + 3] - c[s + 3];
-    s0 = fmaf(e0, e0, s0); s1 = fmaf(e1, e1, s1); s2 = fmaf(e2, e2, s2); s3 = fmaf(e3, e3, s3);
-    if constexpr (SP) {
-      p0 = fmaf(ra[s], e0, p0); p1 = fmaf(ra[s + 1], e1, p1);
-      p2 = fmaf(ra[s + 2], e2, p2); p3 = fmaf(ra[s + 3], e3, p3);
+    const v4f t = *reinterpret_cast<const v4f*>(p + s);
+    v[s] = t.x; v[s + 1] = t.y; v[s + 2] = t.z; v[s + 3] = t.w;
+  }
+}
+
+// Direct ||x - c_j||^2 (and <r, x - c_j>) over this lane's share of the dimensions, 4 partial
+// sums per lane; with CH the rows' chunks are read again from X and the record of C[pi].
+template <int DP, int BN, bool CH, bool VEC, bool SP>
+__device__ __forceinline__ void direct32(const AssignParams& P, int nch, int64_t row, bool ok,
+                                         int pi, int j, int q, const float (&xa)[DP / 4],
+                                         const float (&ra)[DP / 4], float& sq, float& pj) {
+  constexpr int KS = DP / 4;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+  for (int ch = 0; ch < (CH ? nch : 1); ++ch) {
+    float c[KS], xs[KS], rs[KS];
+    load_rec<KS>(rec_row<DP, BN>(P.Crec, nch, j, ch) + q * KS, c);
+    if constexpr (CH) {
+      load_seg<KS, VEC>(P.X, row, P.d, ch * DP + q * KS, ok, xs);
+      if constexpr (SP) {
+        load_rec<KS>(rec_row<DP, BN>(P.Crec, nch, pi, ch) + q * KS, rs);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) rs[s] = xs[s] - rs[s];
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) { xs[s] = xa[s]; rs[s] = ra[s]; }
+    }
+#pragma unroll
+    for (int s = 0; s < KS; s += 4) {
+      const float e0 = xs[s] - c[s], e1 = xs[s + 1] - c[s + 1];
+      const float e2 = xs[s + 2] - c[s + 2], e3 = xs[s + 3] - c[s + 3];
+      s0 = fmaf(e0, e0, s0); s1 = fmaf(e1, e1, s1); s2 = fmaf(e2, e2, s2); s3 = fmaf(e3, e3, s3);
+      if constexpr (SP) {
+        p0 = fmaf(rs[s], e0, p0); p1 = fmaf(rs[s + 1], e1, p1);
+        p2 = fmaf(rs[s + 2], e2, p2); p3 = fmaf(rs[s + 3], e3, p3);
+      }
     }
   }
   sq = sum_quad_f((s0 + s1) + (s2 + s3));
@@ -65,98 +116,92 @@ __device__ __forceinline__ void direct32(const float* __restrict__ C, int d, int
 }
 
 // The same in FP64 with the residual formed exactly from C[pi] (near-tie decisions only).
-template <int KS, bool VEC, bool SP>
-__device__ __forceinline__ double direct64(const float* __restrict__ C, int d, int j, int pi,
-                                           int q, const float (&xa)[KS], float lam) {
-  float c[KS], cp[KS];
-  load_quarter<KS, VEC>(C, j, d, q, true, c);
-  if constexpr (SP) load_quarter<KS, VEC>(C, pi, d, q, true, cp);
+template <int DP, int BN, bool CH, bool VEC, bool SP>
+__device__ __forceinline__ double direct64(const AssignParams& P, int nch, int64_t row, bool ok,
+                                           int pi, int j, int q, const float (&xa)[DP / 4]) {
+  constexpr int KS = DP / 4;
   double sq0 = 0.0, sq1 = 0.0, pj0 = 0.0, pj1 = 0.0, rr0 = 0.0, rr1 = 0.0;
+  for (int ch = 0; ch < (CH ? nch : 1); ++ch) {
+    float c[KS], cp[KS], xs[KS];
+    load_rec<KS>(rec_row<DP, BN>(P.Crec, nch, j, ch) + q * KS, c);
+    if constexpr (SP) load_rec<KS>(rec_row<DP, BN>(P.Crec, nch, pi, ch) + q * KS, cp);
+    if constexpr (CH) {
+      load_seg<KS, VEC>(P.X, row, P.d, ch * DP + q * KS, ok, xs);
+    } else {
 #pragma unroll
-  for (int s = 0; s < KS; s += 2) {
-    const double e0 = (double)xa[s] - (double)c[s], e1 = (double)xa[s + 1] - (double)c[s + 1];
-    sq0 = fma(e0, e0, sq0); sq1 = fma(e1, e1, sq1);
-    if constexpr (SP) {
-      const double r0 = (double)xa[s] - (double)cp[s], r1 = (double)xa[s + 1] - (double)cp[s + 1];
-      pj0 = fma(r0, e0, pj0); pj1 = fma(r1, e1, pj1);
-      rr0 = fma(r0, r0, rr0); rr1 = fma(r1, r1, rr1);
+      for (int s = 0; s < KS; ++s) xs[s] = xa[s];
+    }
+#pragma unroll
+    for (int s = 0; s < KS; s += 2) {
+      const double e0 = (double)xs[s] - (double)c[s], e1 = (double)xs[s + 1] - (double)c[s + 1];
+      sq0 = fma(e0, e0, sq0); sq1 = fma(e1, e1, sq1);
+      if constexpr (SP) {
+        const double r0 = (double)xs[s] - (double)cp[s], r1 = (double)xs[s + 1] - (double)cp[s + 1];
+        pj0 = fma(r0, e0, pj0); pj1 = fma(r1, e1, pj1);
+        rr0 = fma(r0, r0, rr0); rr1 = fma(r1, r1, rr1);
+      }
     }
   }
   const double sq = sum_quad_d(sq0 + sq1);
   if constexpr (!SP) return sq;
   const double pj = sum_quad_d(pj0 + pj1);
   const double rr = sum_quad_d(rr0 + rr1);
-  return rr > 0.0 ? sq + (double)lam * (pj * pj) / rr : sq;
+  return rr > 0.0 ? sq + (double)P.lam * (pj * pj) / rr : sq;
 }
 
-template <int DP, int BN, bool VEC>
-struct TileLoader {
-  static constexpr int KS = DP / 4;
-  static constexpr int LDW = DP + 4;
-  static constexpr int F4_PER_ROW = DP / 4;
-  static constexpr int NLD = (BN * DP / 4) / 256;
-  static_assert((BN * DP / 4) % 256 == 0, "tile must split evenly over 256 threads");
-  v4f reg[NLD];
-  float cn;
-
-  __device__ __forceinline__ void load(const float* __restrict__ C, const float* __restrict__ cnorm,
-                                       int K, int d, int t, int tid) {
+// One sweep over all K centroids for the wave's 16 rows.  Output-layout lane (q, c16) sees rows
+// 4q+v (v = 0..3) at column c16 of every 16-column block.  A-layout lane (q, c16) holds row
+// `row` (primary pia).  Ends with a workgroup barrier: the ring is free afterwards.
+template <int DP, int BN, bool CH, bool VEC, bool SP>
+__device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch, int tid,
+                                      int64_t row, bool ok, int pia, float (&xa)[DP / 4],
+                                      float (&ra)[DP / 4], const float (&lp)[4],
+                                      const float (&av)[4], const int (&pr)[4], float (&b1)[4],
+                                      int (&i1)[4], float (&b2)[4], int (&i2)[4],
+                                      float (&b3)[4]) {
+  using R = F32Rec<DP, BN>;
+  constexpr int KS = DP / 4, LDW = R::LDW, NB = BN / 16;
+  const int lane = tid & 63, w = tid >> 6, q = lane >> 4, c16 = lane & 15;
+  const int ntiles = (P.K + BN - 1) / BN;
+  const int nsteps = ntiles * (CH ? nch : 1);
+  const char* recs = P.Crec;
+  // chunked rows: chunk 0 now, chunk u+1 during step u
+  float xn[CH ? KS : 1], cn[CH && SP ? KS : 1];
+  if constexpr (CH) {
+    load_seg<KS, VEC>(P.X, row, P.d, q * KS, ok, xa);
+    if constexpr (SP) {
+      if (pia >= 0) {
+        load_rec<KS>(rec_row<DP, BN>(recs, nch, pia, 0) + q * KS, cn);
 #pragma unroll
-    for (int i = 0; i < NLD; ++i) {
-      const int f = tid + i * 256;
-      const int row = f / F4_PER_ROW, k = (f % F4_PER_ROW) * 4;
-      const int j = t * BN + row;
-      v4f v = {0.f, 0.f, 0.f, 0.f};
-      if (j < K) {
-        const float* p = C + (int64_t)j * d + k;
-        if constexpr (VEC) {
-          if (k < d) v = *reinterpret_cast<const v4f*>(p);
-        } else {
-          if (k + 0 < d) v.x = p[0];
-          if (k + 1 < d) v.y = p[1];
-          if (k + 2 < d) v.z = p[2];
-          if (k + 3 < d) v.w = p[3];
+        for (int s = 0; s < KS; ++s) ra[s] = xa[s] - cn[s];
+      }
+    }
+  }
+  issue_record<R::BYTES, R::STAGE, R::NI, 2>(recs, ring, 0, w, lane);
+  v4f accS[NB], accT[NB];
+  for (int u = 0; u < nsteps; ++u) {
+    const int ch = CH ? u % nch : 0, t = CH ? u / nch : u;
+    // record u has landed for this wave, then for every wave; every wave is also done reading
+    // the stage refilled next (the one step u - 1 used)
+    wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    if constexpr (CH) {
+      if (u + 1 < nsteps) {
+        const int cnx = (u + 1) % nch;
+        load_seg<KS, VEC>(P.X, row, P.d, cnx * DP + q * KS, ok, xn);
+        if constexpr (SP) {
+          if (pia >= 0) load_rec<KS>(rec_row<DP, BN>(recs, nch, pia, cnx) + q * KS, cn);
         }
       }
-      reg[i] = v;
     }
-    if (tid < BN) cn = (t * BN + tid < K) ? cnorm[t * BN + tid] : kInf;
-  }
-  __device__ __forceinline__ void store(float* s_c, float* s_cn, int tid) const {
+    if (u + 1 < nsteps) issue_record<R::BYTES, R::STAGE, R::NI, 2>(recs, ring, u + 1, w, lane);
+    const float* sb = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE);
+    if (ch == 0) {
 #pragma unroll
-    for (int i = 0; i < NLD; ++i) {
-      const int f = tid + i * 256;
-      const int row = f / F4_PER_ROW, k = (f % F4_PER_ROW) * 4;
-      *reinterpret_cast<v4f*>(s_c + row * LDW + k) = reg[i];
-    }
-    if (tid < BN) s_cn[tid] = cn;
-  }
-};
-
-// One sweep over all K centroids for the wave's 16 rows.  Output-layout lane (q, c16) sees rows
-// 4q+v (v = 0..3) at column c16 of every 16-column block.
-template <int DP, int BN, bool VEC, bool SP>
-__device__ __forceinline__ void sweep(const AssignParams& P, float* s_c, float* s_cn, int tid,
-                                      const float (&xa)[DP / 4], const float (&ra)[DP / 4],
-                                      const float (&lp)[4], const float (&av)[4],
-                                      const int (&pr)[4], float (&b1)[4], int (&i1)[4],
-                                      float (&b2)[4], int (&i2)[4], float (&b3)[4]) {
-  constexpr int KS = DP / 4, LDW = DP + 4, NB = BN / 16;
-  const int lane = tid & 63, q = lane >> 4, c16 = lane & 15;
-  const int ntiles = (P.K + BN - 1) / BN;
-  TileLoader<DP, BN, VEC> ld;
-  ld.load(P.C, P.cnorm, P.K, P.d, 0, tid);
-  ld.store(s_c, s_cn, tid);
-  __syncthreads();
-  for (int t = 0; t < ntiles; ++t) {
-    const int buf = t & 1;
-    const float* sb = s_c + buf * (BN * LDW);
-    if (t + 1 < ntiles) ld.load(P.C, P.cnorm, P.K, P.d, t + 1, tid);
-    v4f accS[NB], accT[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      accS[b] = v4f{0.f, 0.f, 0.f, 0.f};
-      accT[b] = v4f{0.f, 0.f, 0.f, 0.f};
+      for (int b = 0; b < NB; ++b) {
+        accS[b] = v4f{0.f, 0.f, 0.f, 0.f};
+        accT[b] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
     }
 #pragma unroll
     for (int s = 0; s < KS; s += 4) {
@@ -175,34 +220,44 @@ __device__ __forceinline__ void sweep(const AssignParams& P, float* s_c, float* 
         }
       }
     }
-    const float* scn = s_cn + buf * BN;
+    if (!CH || ch == nch - 1) {
+      const float* scn = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE + R::CN_OFF);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int j = t * BN + b * 16 + c16;
-      const float cn = scn[b * 16 + c16];
+      for (int b = 0; b < NB; ++b) {
+        const int j = t * BN + b * 16 + c16;
+        const float cnv = scn[b * 16 + c16];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        float val;
-        if constexpr (SP) {
-          const float e = accT[b][v] - av[v];
-          const float w = fmaf(-2.f, accS[b][v], cn);
-          val = fmaf(lp[v] * e, e, w);
-          if (j == pr[v]) val = kInf;
-        } else {
-          val = fmaf(-2.f, accS[b][v], cn);
+        for (int v = 0; v < 4; ++v) {
+          float val;
+          if constexpr (SP) {
+            const float e = accT[b][v] - av[v];
+            const float wv = fmaf(-2.f, accS[b][v], cnv);
+            val = fmaf(lp[v] * e, e, wv);
+            if (j == pr[v]) val = kInf;
+          } else {
+            val = fmaf(-2.f, accS[b][v], cnv);
+          }
+          // keep (b1, i1) <= (b2, i2) <= b3 over the columns seen so far
+          const bool lt1 = val < b1[v], lt2 = val < b2[v];
+          b3[v] = fminf(b3[v], fmaxf(b2[v], val));
+          i2[v] = lt1 ? i1[v] : (lt2 ? j : i2[v]);
+          b2[v] = fminf(b2[v], fmaxf(b1[v], val));
+          i1[v] = lt1 ? j : i1[v];
+          b1[v] = fminf(b1[v], val);
         }
-        // keep (b1, i1) <= (b2, i2) <= b3 over the columns seen so far
-        const bool lt1 = val < b1[v], lt2 = val < b2[v];
-        b3[v] = fminf(b3[v], fmaxf(b2[v], val));
-        i2[v] = lt1 ? i1[v] : (lt2 ? j : i2[v]);
-        b2[v] = fminf(b2[v], fmaxf(b1[v], val));
-        i1[v] = lt1 ? j : i1[v];
-        b1[v] = fminf(b1[v], val);
       }
     }
-    if (t + 1 < ntiles) ld.store(s_c + (buf ^ 1) * (BN * LDW), s_cn + (buf ^ 1) * BN, tid);
-    __syncthreads();
+    if constexpr (CH) {
+      if (u + 1 < nsteps) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          xa[s] = xn[s];
+          if constexpr (SP) ra[s] = pia >= 0 ? xn[s] - cn[s] : 0.f;
+        }
+      }
+    }
   }
+  __syncthreads();
 }
 
 struct RowShared {
@@ -212,12 +267,15 @@ struct RowShared {
   int pi[4][16];       // primary (-1: the row went to the full scan)
   int nc[4][16];       // number of candidates
   int sat[4][16];      // candidate set not proven complete
+};
+// Candidate lists; they live in the codebook ring, which is idle between the sweeps.
+struct CandShared {
   int cand[4][16][32];
   float cv[4][16][32];
 };
 
 // Reduce the lane-level state to per-row candidate lists in LDS (output layout -> LDS).
-__device__ __forceinline__ void publish_candidates(RowShared& S, int w, int lane,
+__device__ __forceinline__ void publish_candidates(RowShared& S, CandShared& CS, int w, int lane,
                                                    const float (&b1)[4], const int (&i1)[4],
                                                    const float (&b2)[4], const int (&i2)[4],
                                                    const float (&b3)[4]) {
@@ -243,37 +301,38 @@ __device__ __forceinline__ void publish_candidates(RowShared& S, int w, int lane
     }
     const unsigned below = (1u << c16) - 1u;
     const int pos = __popc(g1 & below) + __popc(g2 & below);
-    if (c1) S.cand[w][r][pos] = i1[v];
-    if (c2) S.cand[w][r][pos + 1] = i2[v];
+    if (c1) CS.cand[w][r][pos] = i1[v];
+    if (c2) CS.cand[w][r][pos + 1] = i2[v];
   }
 }
 
 // Exact decision among a row's candidates (A layout: lane (q, c16) holds row c16's quarter q).
-template <int KS, bool VEC, bool SP>
-__device__ __forceinline__ void decide(const AssignParams& P, RowShared& S, int w, int c16, int q,
-                                       const float (&xa)[KS], const float (&ra)[KS], float rr,
-                                       int pi, int& best_j, float& best_v) {
+template <int DP, int BN, bool CH, bool VEC, bool SP>
+__device__ __forceinline__ void decide(const AssignParams& P, RowShared& S, CandShared& CS, int nch,
+                                       int w, int c16, int q, int64_t row, bool ok,
+                                       const float (&xa)[DP / 4], const float (&ra)[DP / 4],
+                                       float rr, int pi, int& best_j, float& best_v) {
   const int nc = S.nc[w][c16];
   float best = kInf;
   int bj = 0x7fffffff;
   for (int k = 0; k < nc; ++k) {
-    const int j = S.cand[w][c16][k];
+    const int j = CS.cand[w][c16][k];
     float sq, pj;
-    direct32<KS, VEC, SP>(P.C, P.d, j, q, xa, ra, sq, pj);
+    direct32<DP, BN, CH, VEC, SP>(P, nch, row, ok, pi, j, q, xa, ra, sq, pj);
     const float val = (SP && rr > 0.f) ? sq + P.lam * (pj * pj) / rr : sq;
-    S.cv[w][c16][k] = val;
+    CS.cv[w][c16][k] = val;
     if (val < best || (val == best && j < bj)) { best = val; bj = j; }
   }
   const float lim = best + best * P.tie_rel;
   int ntie = 0;
-  for (int k = 0; k < nc; ++k) ntie += S.cv[w][c16][k] <= lim;
+  for (int k = 0; k < nc; ++k) ntie += CS.cv[w][c16][k] <= lim;
   if (ntie >= 2) {
     double bd = __builtin_inf();
     int bdj = 0x7fffffff;
     for (int k = 0; k < nc; ++k) {
-      if (S.cv[w][c16][k] <= lim) {
-        const int j = S.cand[w][c16][k];
-        argmin_d(bd, bdj, direct64<KS, VEC, SP>(P.C, P.d, j, pi, q, xa, P.lam), j);
+      if (CS.cv[w][c16][k] <= lim) {
+        const int j = CS.cand[w][c16][k];
+        argmin_d(bd, bdj, direct64<DP, BN, CH, VEC, SP>(P, nch, row, ok, pi, j, q, xa), j);
       }
     }
     best = (float)bd;
@@ -284,30 +343,43 @@ __device__ __forceinline__ void decide(const AssignParams& P, RowShared& S, int 
   best_v = best;
 }
 
-template <int DP, int BN, bool SPILL, bool VEC>
-__global__ __launch_bounds__(256) void assign_f32_kernel(AssignParams P) {
-  constexpr int KS = DP / 4, LDW = DP + 4;
-  __shared__ __attribute__((aligned(16))) float s_c[2 * BN * LDW];
-  __shared__ float s_cn[2 * BN];
-  __shared__ RowShared S;
+// Two waves per SIMD (at most 256 registers, two workgroups' rings per CU) for rows that stay
+// resident up to 128 dimensions; the wider shapes run one.
+template <int DP, bool CH>
+constexpr int f32_waves() { return (!CH && DP <= 128) ? 2 : 1; }
+
+template <int DP, int BN, bool CH, bool SPILL, bool VEC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(f32_waves<DP, CH>(), 2)))
+void assign_f32_kernel(AssignParams P) {
+  using R = F32Rec<DP, BN>;
+  constexpr int KS = DP / 4;
+  static_assert(2 * R::STAGE >= (int)sizeof(CandShared), "candidate lists must fit in the ring");
+  // one LDS object: [ring of two record stages | per-row state]
+  __shared__ __attribute__((aligned(16))) char lds[2 * R::STAGE + sizeof(RowShared)];
+  char* ring = lds;
+  RowShared& S = *reinterpret_cast<RowShared*>(lds + 2 * R::STAGE);
+  CandShared& CS = *reinterpret_cast<CandShared*>(ring);
 
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, c16 = lane & 15;
   const int64_t n = live_rows(P.n, P.live_n);
   if ((int64_t)blockIdx.x * 64 >= n) return;   // whole block past the live rows
   const int64_t row = (int64_t)blockIdx.x * 64 + w * 16 + c16;  // A-layout row of this lane
   const bool ok = row < n;
+  const int nch = CH ? (P.d + DP - 1) / DP : 1;
   const float cmax = sqrtf(__uint_as_float(P.counters[CNT_CMAX2]));
 
   float xa[KS], ra[KS];
-  load_quarter<KS, VEC>(P.X, row, P.d, q, ok, xa);
   bool fin = true;
   float n0 = 0.f, n1 = 0.f, n2 = 0.f, n3 = 0.f;
+  for (int ch = 0; ch < nch; ++ch) {
+    load_seg<KS, VEC>(P.X, row, P.d, ch * DP + q * KS, ok, xa);
 #pragma unroll
-  for (int s = 0; s < KS; s += 4) {
-    fin = fin && all_finite4(v4f{xa[s], xa[s + 1], xa[s + 2], xa[s + 3]});
-    n0 = fmaf(xa[s], xa[s], n0); n1 = fmaf(xa[s + 1], xa[s + 1], n1);
-    n2 = fmaf(xa[s + 2], xa[s + 2], n2); n3 = fmaf(xa[s + 3], xa[s + 3], n3);
-    ra[s] = ra[s + 1] = ra[s + 2] = ra[s + 3] = 0.f;
+    for (int s = 0; s < KS; s += 4) {
+      fin = fin && all_finite4(v4f{xa[s], xa[s + 1], xa[s + 2], xa[s + 3]});
+      n0 = fmaf(xa[s], xa[s], n0); n1 = fmaf(xa[s + 1], xa[s + 1], n1);
+      n2 = fmaf(xa[s + 2], xa[s + 2], n2); n3 = fmaf(xa[s + 3], xa[s + 3], n3);
+      ra[s] = ra[s + 1] = ra[s + 2] = ra[s + 3] = 0.f;
+    }
   }
   if (!fin) atomicOr(&P.counters[CNT_NONFINITE], 1u);
   const float xnorm = sqrtf(sum_quad_f((n0 + n1) + (n2 + n3)));
@@ -323,14 +395,15 @@ __global__ __launch_bounds__(256) void assign_f32_kernel(AssignParams P) {
     b1[v] = b2[v] = b3[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
     lp[v] = av[v] = 0.f; pr[v] = -1;
   }
-  sweep<DP, BN, VEC, false>(P, s_c, s_cn, tid, xa, ra, lp, av, pr, b1, i1, b2, i2, b3);
-  publish_candidates(S, w, lane, b1, i1, b2, i2, b3);
+  sweep<DP, BN, CH, VEC, false>(P, ring, nch, tid, row, ok, -1, xa, ra, lp, av, pr, b1, i1, b2,
+                                i2, b3);
+  publish_candidates(S, CS, w, lane, b1, i1, b2, i2, b3);
   __syncthreads();
 
   int pi = -1;
   float pdist = 0.f;
   bool psat = S.sat[w][c16] != 0;
-  if (!psat) decide<KS, VEC, false>(P, S, w, c16, q, xa, ra, 0.f, 0, pi, pdist);
+  if (!psat) decide<DP, BN, CH, VEC, false>(P, S, CS, nch, w, c16, q, row, ok, xa, ra, 0.f, 0, pi, pdist);
   if (pi < 0 || pi >= P.K) psat = true;
   if (ok && q == 0) {
     if (psat) {
@@ -347,17 +420,20 @@ __global__ __launch_bounds__(256) void assign_f32_kernel(AssignParams P) {
   if (psat) pi = -1;
   float rr = 0.f, a = 0.f;
   if (pi >= 0) {
-    float cp[KS];
-    load_quarter<KS, VEC>(P.C, pi, P.d, q, true, cp);
     float r0 = 0.f, r1 = 0.f, r2 = 0.f, r3 = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    for (int ch = 0; ch < nch; ++ch) {
+      float cp[KS];
+      load_rec<KS>(rec_row<DP, BN>(P.Crec, nch, pi, ch) + q * KS, cp);
+      if constexpr (CH) load_seg<KS, VEC>(P.X, row, P.d, ch * DP + q * KS, ok, xa);
 #pragma unroll
-    for (int s = 0; s < KS; s += 4) {
-      ra[s] = xa[s] - cp[s]; ra[s + 1] = xa[s + 1] - cp[s + 1];
-      ra[s + 2] = xa[s + 2] - cp[s + 2]; ra[s + 3] = xa[s + 3] - cp[s + 3];
-      r0 = fmaf(ra[s], ra[s], r0); r1 = fmaf(ra[s + 1], ra[s + 1], r1);
-      r2 = fmaf(ra[s + 2], ra[s + 2], r2); r3 = fmaf(ra[s + 3], ra[s + 3], r3);
-      a0 = fmaf(ra[s], xa[s], a0); a1 = fmaf(ra[s + 1], xa[s + 1], a1);
-      a2 = fmaf(ra[s + 2], xa[s + 2], a2); a3 = fmaf(ra[s + 3], xa[s + 3], a3);
+      for (int s = 0; s < KS; s += 4) {
+        ra[s] = xa[s] - cp[s]; ra[s + 1] = xa[s + 1] - cp[s + 1];
+        ra[s + 2] = xa[s + 2] - cp[s + 2]; ra[s + 3] = xa[s + 3] - cp[s + 3];
+        r0 = fmaf(ra[s], ra[s], r0); r1 = fmaf(ra[s + 1], ra[s + 1], r1);
+        r2 = fmaf(ra[s + 2], ra[s + 2], r2); r3 = fmaf(ra[s + 3], ra[s + 3], r3);
+        a0 = fmaf(ra[s], xa[s], a0); a1 = fmaf(ra[s + 1], xa[s + 1], a1);
+        a2 = fmaf(ra[s + 2], xa[s + 2], a2); a3 = fmaf(ra[s + 3], xa[s + 3], a3);
+      }
     }
     rr = sum_quad_f((r0 + r1) + (r2 + r3));
     a = sum_quad_f((a0 + a1) + (a2 + a3));
@@ -377,14 +453,15 @@ __global__ __launch_bounds__(256) void assign_f32_kernel(AssignParams P) {
   }
 
   // ---------------- spill pass ----------------
-  sweep<DP, BN, VEC, true>(P, s_c, s_cn, tid, xa, ra, lp, av, pr, b1, i1, b2, i2, b3);
-  publish_candidates(S, w, lane, b1, i1, b2, i2, b3);
+  sweep<DP, BN, CH, VEC, true>(P, ring, nch, tid, row, ok, pi, xa, ra, lp, av, pr, b1, i1, b2,
+                               i2, b3);
+  publish_candidates(S, CS, w, lane, b1, i1, b2, i2, b3);
   __syncthreads();
   if (pi < 0) return;  // full-scan rows are finished by the full-scan kernel
   bool ssat = S.sat[w][c16] != 0;
   int sj = -1;
   float sl = 0.f;
-  if (!ssat) decide<KS, VEC, true>(P, S, w, c16, q, xa, ra, rr, pi, sj, sl);
+  if (!ssat) decide<DP, BN, CH, VEC, true>(P, S, CS, nch, w, c16, q, row, ok, xa, ra, rr, pi, sj, sl);
   if (sj < 0 || sj >= P.K) ssat = true;
   if (ok && q == 0) {
     if (ssat) {
@@ -592,23 +669,99 @@ __global__ __launch_bounds__(256) void prep_codebook_kernel(const float* __restr
 // Host-side launchers
 // ------------------------------------------------------------------------------------------------
 template <int DP, int BN>
-static hipError_t launch_dp(const AssignParams& P, bool spill, bool vec, hipStream_t st) {
-  const dim3 grid((unsigned)((P.n + 63) / 64)), block(256);
-  if (spill) {
-    if (vec) hipLaunchKernelGGL((assign_f32_kernel<DP, BN, true, true>), grid, block, 0, st, P);
-    else hipLaunchKernelGGL((assign_f32_kernel<DP, BN, true, false>), grid, block, 0, st, P);
-  } else {
-    if (vec) hipLaunchKernelGGL((assign_f32_kernel<DP, BN, false, true>), grid, block, 0, st, P);
-    else hipLaunchKernelGGL((assign_f32_kernel<DP, BN, false, false>), grid, block, 0, st, P);
+__global__ __launch_bounds__(256) void pack_f32_kernel(const float* __restrict__ C, int K, int d,
+                                                       int nch, const float* __restrict__ cnorm,
+                                                       char* __restrict__ rec, int64_t total) {
+  using R = F32Rec<DP, BN>;
+  constexpr int F4 = R::LDW / 4;   // float4 per record row (the last one is the pad)
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= total) return;
+  const int f = (int)(g % F4);
+  const int64_t jc = g / F4;
+  const int ch = (int)(jc % nch), j = (int)(jc / nch);
+  char* base = rec + ((int64_t)(j / BN) * nch + ch) * R::BYTES;
+  const int jl = j % BN, k = ch * DP + f * 4;
+  v4f v = {0.f, 0.f, 0.f, 0.f};
+  if (j < K && f * 4 < DP) {
+    const float* c = C + (int64_t)j * d;
+    if (k < d) v.x = c[k];
+    if (k + 1 < d) v.y = c[k + 1];
+    if (k + 2 < d) v.z = c[k + 2];
+    if (k + 3 < d) v.w = c[k + 3];
   }
-  return hipGetLastError();
+  *reinterpret_cast<v4f*>(base + (jl * R::LDW + f * 4) * 4) = v;
+  if (f == 0) *reinterpret_cast<float*>(base + R::CN_OFF + jl * 4) = j < K ? cnorm[j] : kInf;
 }
+
+// Padded widths: rows of up to 256 stay resident; longer rows go in chunks of 128.
+constexpr int kF32ChunkDP = 128, kF32ChunkBN = 64, kF32MaxD = 1024;
 
 int fp32_padded_dim(int d) {
   static const int dps[] = {16, 32, 48, 64, 96, 128, 192, 256};
   for (int dp : dps)
     if (d <= dp) return dp;
+  if (d <= kF32MaxD) return (d + kF32ChunkDP - 1) / kF32ChunkDP * kF32ChunkDP;
   return -1;
+}
+
+template <int DP, int BN>
+static size_t rec_bytes(int d, int K) {
+  const int nch = (d + DP - 1) / DP;
+  return (size_t)((K + BN - 1) / BN) * nch * F32Rec<DP, BN>::BYTES;
+}
+
+template <int DP, int BN>
+static hipError_t pack_dp(const float* C, int K, int d, const float* cnorm, void* rec,
+                          hipStream_t st) {
+  const int nch = (d + DP - 1) / DP;
+  const int64_t total = (int64_t)((K + BN - 1) / BN) * BN * nch * (F32Rec<DP, BN>::LDW / 4);
+  hipLaunchKernelGGL((pack_f32_kernel<DP, BN>), dim3((unsigned)((total + 255) / 256)), dim3(256),
+                     0, st, C, K, d, nch, cnorm, static_cast<char*>(rec), total);
+  return hipGetLastError();
+}
+
+template <int DP, int BN, bool CH>
+static hipError_t launch_dp(const AssignParams& P, bool spill, bool vec, hipStream_t st) {
+  const dim3 grid((unsigned)((P.n + 63) / 64)), block(256);
+  if (spill) {
+    if (vec) hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, true, true>), grid, block, 0, st, P);
+    else hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, true, false>), grid, block, 0, st, P);
+  } else {
+    if (vec) hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, false, true>), grid, block, 0, st, P);
+    else hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, false, false>), grid, block, 0, st, P);
+  }
+  return hipGetLastError();
+}
+
+// Plain switches over the padded width (the shapes below and in the launcher must agree).
+#define SOAR_F32_SHAPES(X)                \
+  case 16: X(16, 64, false); break;       \
+  case 32: X(32, 64, false); break;       \
+  case 48: X(48, 64, false); break;       \
+  case 64: X(64, 64, false); break;       \
+  case 96: X(96, 64, false); break;       \
+  case 128: X(128, 64, false); break;     \
+  case 192: X(192, 32, false); break;     \
+  case 256: X(256, 32, false); break;     \
+  default: X(kF32ChunkDP, kF32ChunkBN, true); break;
+
+size_t fp32_codebook_bytes(int d, int K) {
+  const int dp = fp32_padded_dim(d);
+  if (dp < 0) return 0;
+#define SOAR_X(DP, BN, CH) return rec_bytes<DP, BN>(d, K)
+  switch (dp) { SOAR_F32_SHAPES(SOAR_X) }
+#undef SOAR_X
+  return 0;
+}
+
+hipError_t launch_pack_fp32(const float* C, int K, int d, const float* cnorm, void* rec,
+                            hipStream_t st) {
+  const int dp = fp32_padded_dim(d);
+  if (dp < 0) return hipErrorInvalidValue;
+#define SOAR_X(DP, BN, CH) return pack_dp<DP, BN>(C, K, d, cnorm, rec, st)
+  switch (dp) { SOAR_F32_SHAPES(SOAR_X) }
+#undef SOAR_X
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_prep_codebook(const float* C, int K, int d, float* cnorm, unsigned* counters,
@@ -629,17 +782,11 @@ hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipSt
                               hipEvent_t ev_begin, hipEvent_t ev_end) {
   hipError_t e;
   if (ev_begin) (void)hipEventRecord(ev_begin, st);
-  switch (fp32_padded_dim(P.d)) {
-    case 16: e = launch_dp<16, 64>(P, spill, vec, st); break;
-    case 32: e = launch_dp<32, 64>(P, spill, vec, st); break;
-    case 48: e = launch_dp<48, 64>(P, spill, vec, st); break;
-    case 64: e = launch_dp<64, 64>(P, spill, vec, st); break;
-    case 96: e = launch_dp<96, 64>(P, spill, vec, st); break;
-    case 128: e = launch_dp<128, 64>(P, spill, vec, st); break;
-    case 192: e = launch_dp<192, 32>(P, spill, vec, st); break;
-    case 256: e = launch_dp<256, 32>(P, spill, vec, st); break;
-    default: return hipErrorInvalidValue;
-  }
+  const int dp = fp32_padded_dim(P.d);
+  if (dp < 0 || !P.Crec) return hipErrorInvalidValue;
+#define SOAR_X(DP, BN, CH) e = launch_dp<DP, BN, CH>(P, spill, vec, st)
+  switch (dp) { SOAR_F32_SHAPES(SOAR_X) }
+#undef SOAR_X
   if (e != hipSuccess) return e;
   if (ev_end) (void)hipEventRecord(ev_end, st);
   const size_t smem = (size_t)3 * P.d * sizeof(float);

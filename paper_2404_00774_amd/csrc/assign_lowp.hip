@@ -211,25 +211,6 @@ __global__ __launch_bounds__(256) void pack_codebook_kernel(const float* __restr
   if (!fin) atomicOr(&counters[CNT_NONFINITE], 1u);
 }
 
-#define LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
-
-// Copy record t into ring stage t % STG with direct global->LDS loads: every wave issues exactly
-// NI copies of 64 x 16 bytes (source addresses past the record end are clamped to its last
-// chunk), so the number of outstanding copies is the same in every wave.
-template <int BYTES, int STAGE, int NI, int STG>
-__device__ __forceinline__ void issue_record(const char* recs, char* ring, int t, int w,
-                                             int lane) {
-  const char* src = recs + (int64_t)t * BYTES;
-  char* dst = ring + (t % STG) * STAGE;
-#pragma unroll
-  for (int k = 0; k < NI; ++k) {
-    const int off = (k * 256 + w * 64) * 16;
-    const int c = off + lane * 16;
-    __builtin_amdgcn_global_load_lds(src + (c < BYTES ? c : BYTES - 16), LDS_PTR(dst + off), 16,
-                                     0, 0);
-  }
-}
-
 // Ranking values in the epilogue (row constants of the loss dropped):
 //   BF16: the record holds -2 c (exact), the S accumulator starts at ||c_j||^2 and the T
 //         accumulator at 2 <r_i, x_i>, so S = ||c||^2 - 2<x,c> and T = -2 (<r,c> - <r,x>); the
@@ -303,9 +284,9 @@ void lowp_sweep_kernel(LowpParams P) {
     // (vmcnt counts VMEM operations of this wave in order: with a later record in flight, at most
     // its NI copies may remain outstanding)
     if (STG > 2 && t + 1 < ntiles)
-      __builtin_amdgcn_s_waitcnt((R::NI & 15) | (7 << 4) | (15 << 8) | ((R::NI >> 4) << 14));
+      wait_vmcnt<R::NI>();
     else
-      __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));
+      wait_vmcnt<0>();
     // ... and for every wave; every wave is also done reading the stage refilled next
     __builtin_amdgcn_s_barrier();
     if (t + STG - 1 < ntiles) issue_record<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, t + STG - 1, w, lane);

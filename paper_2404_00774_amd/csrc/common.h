@@ -63,4 +63,32 @@ __device__ __forceinline__ void argmin_d(double& v, int& j, double ov, int oj) {
   if (ov < v || (ov == v && oj < j)) { v = ov; j = oj; }
 }
 
+// s_waitcnt on the vector-memory counter alone (gfx9 encoding: vmcnt in bits [3:0] and [15:14];
+// expcnt [6:4] and lgkmcnt [11:8] left at their maxima, i.e. not waited on).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Direct global->LDS copies (gfx950 global_load_lds, 16 bytes per lane).
+#define LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+
+// Copy record t into ring stage t % STG with direct global->LDS loads: every wave issues exactly
+// NI copies of 64 x 16 bytes (source addresses past the record end are clamped to its last
+// chunk), so the number of outstanding copies is the same in every wave.
+template <int BYTES, int STAGE, int NI, int STG>
+__device__ __forceinline__ void issue_record(const char* recs, char* ring, int t, int w,
+                                             int lane) {
+  const char* src = recs + (int64_t)t * BYTES;
+  char* dst = ring + (t % STG) * STAGE;
+#pragma unroll
+  for (int k = 0; k < NI; ++k) {
+    const int off = (k * 256 + w * 64) * 16;
+    const int c = off + lane * 16;
+    __builtin_amdgcn_global_load_lds(src + (c < BYTES ? c : BYTES - 16), LDS_PTR(dst + off), 16,
+                                     0, 0);
+  }
+}
+
 }  // namespace soar

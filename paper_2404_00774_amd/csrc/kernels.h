@@ -11,6 +11,7 @@ struct AssignParams {
   int d;
   const float* C;
   int K;
+  const char* Crec;     // packed tile records of C (launch_pack_fp32)
   const float* cnorm;   // [K] ||c_j||^2
   unsigned* counters;   // CNT_* words
   float lam;
@@ -25,7 +26,13 @@ struct AssignParams {
   const int64_t* live_n = nullptr;   // device row count <= n (serving steps), or null
 };
 
+// Padded row length of the FP32 path (-1: unsupported); rows above 256 are processed in chunks.
 int fp32_padded_dim(int d);
+// Bytes of the packed codebook records read by the FP32 sweeps, and the kernel that writes them
+// (after launch_prep_codebook, whose norms it copies).
+size_t fp32_codebook_bytes(int d, int K);
+hipError_t launch_pack_fp32(const float* C, int K, int d, const float* cnorm, void* rec,
+                            hipStream_t st);
 // Screening bands and near-tie threshold of the FP32 path (defined with the C ABI).
 float band_coef_primary(int d);
 float band_coef_spill(int d, float lam);

@@ -164,7 +164,7 @@ struct soar_index {
   // codebook (device, inside the arena)
   float* C = nullptr;
   float* cnorm = nullptr;
-  void* crec = nullptr;          // packed codebook records (BF16 / FP8)
+  void* crec = nullptr;          // packed codebook records of the sweeps
   ListDev L{};
   Slot slots[2];
   hipEvent_t last_append = nullptr;   // append event of the latest launched step
@@ -210,7 +210,7 @@ ArenaPlan plan_arena(int K, int d, int precision, int cap, size_t arena_bytes) {
   auto take = [&](size_t b) { size_t o = off; off = al(off + b); return o; };
   P.C = take((size_t)K * d * 4);
   P.cnorm = take((size_t)K * 4);
-  P.crec = take(lowp ? lowp_codebook_bytes(fmt, d, K) : 0);
+  P.crec = take(lowp ? lowp_codebook_bytes(fmt, d, K) : fp32_codebook_bytes(d, K));
   P.L_len = take((size_t)K * 4);
   P.L_cursor = take((size_t)K * 4);
   P.L_cnt = take((size_t)K * 4);
@@ -241,6 +241,7 @@ hipError_t enqueue_compute(soar_index* ix, Slot& s) {
   if (!lowp) {
     AssignParams P;
     P.X = s.X; P.n = ix->cap; P.d = ix->d; P.C = ix->C; P.K = ix->K;
+    P.Crec = static_cast<const char*>(ix->crec);
     P.cnorm = ix->cnorm; P.counters = s.counters;
     P.lam = ix->lambda;
     P.tie_rel = tie_threshold(ix->d, ix->lambda, 0.f);
@@ -533,6 +534,8 @@ soar_status soar_index_create(const float* C, int32_t K, int32_t d, float lambda
     e = launch_prep_codebook(ix->C, K, d, ix->cnorm, ix->slots[k].counters, st0);
   if (e == hipSuccess && precision != SOAR_FP32)
     e = launch_lowp_pack_codebook(fmt, ix->C, K, d, ix->cnorm, ix->crec, ix->slots[0].counters, st0);
+  if (e == hipSuccess && precision == SOAR_FP32)
+    e = launch_pack_fp32(ix->C, K, d, ix->cnorm, ix->crec, st0);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(fill_i32, dim3((K + 255) / 256), dim3(256), 0, st0, L.len, (int64_t)K, 0);
     hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st0, L.meta, (int64_t)16, 0);

@@ -104,15 +104,17 @@ inline int lowp_topk(const OptsView& o) { return o.topk > 0 ? o.topk : 8; }
 struct AssignLayout {
   unsigned* counters;
   float* cnorm;
+  char* crec;
   int32_t* full_rows;
   size_t bytes;
 };
 
-AssignLayout layout_assign(void* ws, int64_t n, int32_t K) {
+AssignLayout layout_assign(void* ws, int64_t n, int32_t d, int32_t K) {
   Carver c(ws);
   AssignLayout L;
   L.counters = c.take<unsigned>(soar::CNT_WORDS);
   L.cnorm = c.take<float>((size_t)K);
+  L.crec = c.take<char>(soar::fp32_codebook_bytes(d, K));
   L.full_rows = c.take<int32_t>((size_t)n);
   L.bytes = c.off;
   return L;
@@ -144,9 +146,9 @@ soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C
                             int32_t* spill_out, float* pdist, float* sloss, void* ws,
                             hipStream_t st, unsigned* counters_out_host,
                             hipEvent_t ev_kernel_begin, hipEvent_t ev_kernel_end) {
-  AssignLayout L = layout_assign(ws, n, K);
+  AssignLayout L = layout_assign(ws, n, d, K);
   AssignParams P;
-  P.X = X; P.n = n; P.d = d; P.C = C; P.K = K;
+  P.X = X; P.n = n; P.d = d; P.C = C; P.K = K; P.Crec = L.crec;
   P.cnorm = L.cnorm; P.counters = L.counters;
   P.lam = lam;
   P.tie_rel = tie_threshold(d, lam, near_tie_rel);
@@ -156,6 +158,7 @@ soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C
   P.full_rows = L.full_rows;
   const bool vec = (d % 4 == 0) && aligned(X, 16) && aligned(C, 16);
   hipError_t e = launch_prep_codebook(C, K, d, L.cnorm, L.counters, st);
+  if (e == hipSuccess) e = launch_pack_fp32(C, K, d, L.cnorm, L.crec, st);
   if (e == hipSuccess) e = launch_assign_fp32(P, spill, vec, st, ev_kernel_begin, ev_kernel_end);
   if (e != hipSuccess) return SOAR_E_DEVICE;
   if (counters_out_host) {
@@ -166,7 +169,9 @@ soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C
   return SOAR_OK;
 }
 
-size_t assign_workspace_bytes(int64_t n, int32_t K) { return layout_assign(nullptr, n, K).bytes; }
+size_t assign_workspace_bytes(int64_t n, int32_t d, int32_t K) {
+  return layout_assign(nullptr, n, d, K).bytes;
+}
 
 // BF16 / FP8 pipeline: quantize, primary sweep + re-score, spill sweep + re-score.
 // ev (nullable, 4 events) brackets the primary sweep [0, 1] and the spill sweep [2, 3].
@@ -229,7 +234,7 @@ soar_status soar_assign_workspace_size(int64_t n, int32_t d, int32_t K,
   const soar_status s = validate_assign(n, d, K, o);
   if (s != SOAR_OK) return s;
   *bytes = o.precision == SOAR_FP32
-               ? soar::assign_workspace_bytes(n, K)
+               ? soar::assign_workspace_bytes(n, d, K)
                : layout_lowp(nullptr, n, d, K, lowp_fmt(o), lowp_topk(o)).bytes;
   return SOAR_OK;
 }

@@ -358,7 +358,7 @@ TrainLayout layout_train(void* ws, int64_t n, int d, int K) {
     return p;
   };
   TrainLayout L;
-  const size_t aws = assign_workspace_bytes(n, K);
+  const size_t aws = assign_workspace_bytes(n, d, K);
   L.assign_ws = take(aws);
   L.labels = (int32_t*)take(n * 4);
   L.dist = (float*)take(n * 4);
@@ -527,7 +527,7 @@ soar_status soar_train_codebook(const float* X, int64_t n, int32_t d, int32_t K,
                                 double* inertia, void* workspace, size_t ws_bytes, void* stream) {
   soar_status s = check_train_args(X, n, d, K, workspace, ws_bytes, false);
   if (s != SOAR_OK) return s;
-  if (!C_out || iters < 0 || fp32_padded_dim(d) < 0) return d > 256 ? SOAR_E_UNSUPPORTED
+  if (!C_out || iters < 0 || fp32_padded_dim(d) < 0) return d > 1024 ? SOAR_E_UNSUPPORTED
                                                                     : SOAR_E_INVAL;
   if (K < 2 && iters > 0) return SOAR_E_INVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);

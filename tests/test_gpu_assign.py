@@ -56,7 +56,9 @@ def test_small_workload_parity(small_workload, lam):
 @pytest.mark.parametrize("n,d,K", [
     (1, 64, 2), (63, 16, 3), (64, 2, 63), (65, 1, 64), (4097, 64, 65), (300, 3, 17),
     (257, 96, 1000), (129, 128, 257), (200, 200, 130), (70, 256, 66), (100, 48, 90),
-    (130, 5, 40), (1000, 32, 129)])
+    (130, 5, 40), (1000, 32, 129),
+    # rows above 256 dimensions: chunks of 128 (ragged last chunk, several tiles, one tile)
+    (300, 257, 70), (129, 300, 65), (200, 768, 130), (70, 1024, 33), (65, 513, 3)])
 @pytest.mark.parametrize("lam", [0.0, 1.0])
 def test_edge_shapes(n, d, K, lam):
     print(f"edge n={n} d={d} K={K} lam={lam}", flush=True)
@@ -135,8 +137,8 @@ def test_validation_and_errors():
             soar.assign(X, C, lam)
         assert e.value.status == -1
     with pytest.raises(soar.SoarError) as e:
-        soar.assign(_t(np.zeros((10, 300))), _t(np.zeros((3, 300))), 1.0)
-    assert e.value.status == -4               # d > 256 not supported in FP32
+        soar.assign(_t(np.zeros((10, 1025))), _t(np.zeros((3, 1025))), 1.0)
+    assert e.value.status == -4               # d > 1024 not supported
     Xn = np.zeros((10, 4), np.float32)
     Xn[3, 2] = np.nan
     with pytest.raises(soar.SoarError) as e:
