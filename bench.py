@@ -50,6 +50,20 @@ def parse():
     ap.add_argument("--codebook", default="train", choices=["train", "sample"],
                     help="sample: K uniformly sampled rows, no training (for short profiling runs)")
     ap.add_argument("--rows", type=int, default=0, help="use only the first N rows (profiling)")
+    ap.add_argument("--mode", default="assign", choices=["assign", "serve"],
+                    help="serve: the serving form (resident index, open-loop Poisson inserts)")
+    ap.add_argument("--serve-base", type=int, default=20_000_000, help="rows of the base index")
+    ap.add_argument("--serve-K", type=int, default=50_000)
+    ap.add_argument("--serve-rates", default="5000,20000,50000,100000,200000",
+                    help="offered insert rates, vectors/s")
+    ap.add_argument("--serve-seconds", type=float, default=8.0, help="arrival window per rate")
+    ap.add_argument("--serve-step-rows", type=int, default=16384, help="rows per step slot")
+    ap.add_argument("--serve-train-rows", type=int, default=2_000_000,
+                    help="rows (a prefix of the base) the serving codebook is trained on")
+    ap.add_argument("--serve-kpp-rows", type=int, default=500_000,
+                    help="rows (a prefix of the base) k-means++ seeds the serving codebook on")
+    ap.add_argument("--serve-lloyd", type=int, default=3, help="Lloyd iterations of that codebook")
+    ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     return ap.parse_args()
 
 
@@ -118,6 +132,158 @@ def judge_form(O, X, C, lam, idx, outs):
             "values_exact_at_index": bool(j["pdist_ok"].all() and j["sloss_ok"].all())}
 
 
+def request_sizes(rng, count):
+    """Insert request sizes floor(exp(U ln 4097)) clamped to [1, 4096] (log-uniform)."""
+    return np.clip(np.floor(np.exp(rng.uniform(0.0, np.log(4097.0), count))), 1, 4096).astype(int)
+
+
+def serve_main(args):
+    """The serving form: a resident BF16 index (codebook + inverted lists of a base set) takes
+    open-loop Poisson streams of insert requests; per offered rate, the achieved vectors/s and the
+    latency from arrival to results in host memory."""
+    import dataclasses
+    import threading
+    import queue
+    from concurrent.futures import ThreadPoolExecutor
+    from synth import WORKLOADS, gen_mixture, gen_queries
+
+    spec = dataclasses.replace(WORKLOADS["mix4096_n1m_d128"]["spec"], n=args.serve_base)
+    K, prec, lam = args.serve_K, args.serve_precision, args.lam
+    rates = [float(r) for r in args.serve_rates.split(",") if r.strip()]
+    CH = 1 << 20
+    nch = (spec.n + CH - 1) // CH
+    # all inputs are drawn before the GPU is touched (threads: numpy releases the GIL)
+    print(f"[serve] generating base n={spec.n} d={spec.d} ({nch} chunks)", file=sys.stderr,
+          flush=True)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        base = list(ex.map(lambda k: gen_mixture(spec, k * CH, min(spec.n, (k + 1) * CH)),
+                           range(nch)))
+    rng = np.random.default_rng(12345)
+    mean_size = float(np.mean(request_sizes(np.random.default_rng(7), 200_000)))
+    plans = []
+    for rate in rates:
+        req_rate = rate / mean_size
+        nreq = max(1, int(np.ceil(req_rate * args.serve_seconds * 1.2)) + 8)
+        arr = np.cumsum(rng.exponential(1.0 / req_rate, nreq))
+        arr = arr[arr < args.serve_seconds]
+        plans.append((rate, arr, request_sizes(rng, len(arr))))
+    # request rows: windows of a pool of new rows from the same mixture (a stream separate from
+    # the base), reused cyclically; every inserted vector still gets its own id
+    pool_rows = 1 << 18
+    pool = gen_queries(spec, pool_rows)
+    print(f"[serve] inputs ready in {time.perf_counter() - t0:.1f} s; request pool {pool_rows} rows",
+          file=sys.stderr, flush=True)
+
+    import torch
+    import paper_2404_00774_amd as soar
+    dev = torch.device("cuda:0")
+    # codebook: k-means++ on a prefix of the base, then Lloyd on a longer prefix
+    ktr = min(args.serve_train_rows, spec.n)
+    Xtr = torch.from_numpy(np.concatenate(base[:(ktr + CH - 1) // CH])[:ktr]).to(dev)
+    t1 = time.perf_counter()
+    C0, _ = soar.kmeanspp(Xtr[:min(args.serve_kpp_rows, ktr)].contiguous(), K, 0)
+    Cg, _, _ = soar.train_codebook(Xtr, K, args.serve_lloyd, C_init=C0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    del Xtr, C0
+    total_new = sum(int(sz.sum()) for _, _, sz in plans)
+    cap = int(2 * (spec.n + total_new) * 1.05) + 64 * K
+    ix = soar.SoarIndex(Cg, lam, precision=prec, max_step_rows=args.serve_step_rows,
+                        list_capacity=cap)
+    print(f"[serve] codebook K={K} in {t_train:.1f} s; arena {ix.arena.numel() / 2**30:.2f} GiB; "
+          "building base lists", file=sys.stderr, flush=True)
+    # base lists: the base rows go in through the same insert path, two requests in flight
+    t2 = time.perf_counter()
+    pend = []
+    for k, Xc in enumerate(base):
+        pend.append(ix.insert(Xc, k * CH))
+        if len(pend) > 2:
+            ix.wait(pend.pop(0))
+    for t in pend:
+        ix.wait(t)
+    t_base = time.perf_counter() - t2
+    base_rate = spec.n / t_base
+    print(f"[serve] base {spec.n} rows in {t_base:.2f} s ({base_rate:.3g} vectors/s)",
+          file=sys.stderr, flush=True)
+    del base
+
+    results = []
+    next_id = spec.n
+    for rate, arr, sizes in plans:
+        q = queue.Queue()
+        lat = np.zeros(len(arr))
+        done_t = np.zeros(len(arr))
+        offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]) % (pool_rows - 4096)
+
+        def waiter():
+            while True:
+                item = q.get()
+                if item is None:
+                    return
+                i, tk, t_arr = item
+                ix.wait(tk)
+                now = time.perf_counter()
+                done_t[i] = now
+                lat[i] = now - t_arr
+
+        ws = [threading.Thread(target=waiter, daemon=True) for _ in range(4)]
+        for w in ws:
+            w.start()
+        late = 0.0
+        start = time.perf_counter() + 0.05
+        for i, (ta, sz) in enumerate(zip(arr, sizes)):
+            t_arr = start + ta
+            dt = t_arr - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            else:
+                late = max(late, -dt)
+            o = int(offs[i])
+            tk = ix.insert(pool[o:o + sz], next_id)
+            next_id += int(sz)
+            q.put((i, tk, t_arr))
+        for _ in ws:
+            q.put(None)
+        for w in ws:
+            w.join()
+        nvec = int(sizes.sum())
+        span = float(done_t.max() - start) if len(arr) else 0.0
+        r = {"offered_vectors_per_s": rate, "requests": int(len(arr)), "vectors": nvec,
+             "achieved_vectors_per_s": nvec / span if span > 0 else 0.0,
+             "p50_ms": float(np.quantile(lat, 0.5) * 1e3), "p99_ms": float(np.quantile(lat, 0.99) * 1e3),
+             "max_ms": float(lat.max() * 1e3), "mean_request_rows": float(sizes.mean()),
+             "max_submit_lag_ms": late * 1e3}
+        results.append(r)
+        print(f"[serve] rate {rate:.0f}/s: {r['requests']} requests, p50 {r['p50_ms']:.3f} ms, "
+              f"p99 {r['p99_ms']:.3f} ms, achieved {r['achieved_vectors_per_s']:.4g}/s",
+              file=sys.stderr, flush=True)
+    # every inserted vector sits in exactly two lists
+    lens = np.array([ix.list_len(p) for p in range(K)], dtype=np.int64)
+    ix.close()
+    head = results[-1]
+    rec = {
+        "metric": "SOAR serving inserts: vectors/s with p50/p99 latency (arrival to results in "
+                  "host memory)",
+        "value": head["achieved_vectors_per_s"], "unit": "vectors/s", "n_gpus": 1,
+        "steps": int(sum(r["requests"] for r in results)), "warmup": 0,
+        "ms_per_step": head["p50_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
+        "config": {"workload": f"serve_mix4096_base{spec.n}_d128_K{K}", "n_base": spec.n, "d": spec.d,
+                   "K": K, "lambda": lam, "precision": prec, "step_rows": args.serve_step_rows,
+                   "arrivals": "open-loop Poisson per rate, request rows floor(exp(U ln 4097)) "
+                               f"in [1, 4096], {args.serve_seconds} s window per rate",
+                   "codebook": f"k-means++ on {min(args.serve_kpp_rows, ktr)} rows, "
+                               f"{args.serve_lloyd} Lloyd iterations on {ktr} rows (same GPU)"},
+        "base_build": {"rows": spec.n, "seconds": t_base, "vectors_per_s": base_rate},
+        "rates": results,
+        "lists": {"total_ids": int(lens.sum()), "expected": int(2 * next_id),
+                  "max_list": int(lens.max())},
+        "train_s": t_train,
+    }
+    print(json.dumps(rec))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -125,6 +291,9 @@ def main():
               "has one GPU and the path's multi-GPU sharding is described, not run.",
               file=sys.stderr)
         sys.exit(2)
+    if args.mode == "serve":
+        serve_main(args)
+        return
     import torch
     import paper_2404_00774_amd as soar
     from synth import WORKLOADS, gen_mixture, sample_rows

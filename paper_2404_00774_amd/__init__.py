@@ -262,6 +262,12 @@ class SoarIndex:
         _check(st, "soar_wait")
         return p, s
 
+    def list_len(self, part):
+        ln = _i64()
+        _check(_lib.soar_index_list(self._h, int(part), None, 0, ctypes.byref(ln)),
+               "soar_index_list")
+        return ln.value
+
     def list(self, part):
         import numpy as np
         ln = _i64()

@@ -152,7 +152,9 @@ __device__ __forceinline__ double direct64(const AssignParams& P, int nch, int64
 // One sweep over all K centroids for the wave's 16 rows.  Output-layout lane (q, c16) sees rows
 // 4q+v (v = 0..3) at column c16 of every 16-column block.  A-layout lane (q, c16) holds row
 // `row` (primary pia).  Ends with a workgroup barrier: the ring is free afterwards.
-template <int DP, int BN, bool CH, bool VEC, bool SP>
+// GR (spill only): <r, c_j> comes from <x, c_j> - G[pi][j], one MFMA stream instead of two; the
+// G values of tile t+1 are loaded during tile t.
+template <int DP, int BN, bool CH, bool VEC, bool SP, bool GR = false>
 __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch, int tid,
                                       int64_t row, bool ok, int pia, float (&xa)[DP / 4],
                                       float (&ra)[DP / 4], const float (&lp)[4],
@@ -161,10 +163,24 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
                                       float (&b3)[4]) {
   using R = F32Rec<DP, BN>;
   constexpr int KS = DP / 4, LDW = R::LDW, NB = BN / 16;
+  static_assert(!GR || (SP && !CH), "Gram form: spill sweep of resident rows only");
   const int lane = tid & 63, w = tid >> 6, q = lane >> 4, c16 = lane & 15;
   const int ntiles = (P.K + BN - 1) / BN;
   const int nsteps = ntiles * (CH ? nch : 1);
   const char* recs = P.Crec;
+  // Gram rows of the lane's output rows (row 0 stands in for rows without a primary)
+  const float* grow[4];
+  float gcur[GR ? NB : 1][4], gnxt[GR ? NB : 1][4];
+  if constexpr (GR) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) grow[v] = P.G + (int64_t)(pr[v] >= 0 ? pr[v] : 0) * P.K;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = b * 16 + c16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) gcur[b][v] = j < P.K ? grow[v][j] : 0.f;
+    }
+  }
   // chunked rows: chunk 0 now, chunk u+1 during step u
   float xn[CH ? KS : 1], cn[CH && SP ? KS : 1];
   if constexpr (CH) {
@@ -195,6 +211,16 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
       }
     }
     if (u + 1 < nsteps) issue_record<R::BYTES, R::STAGE, R::NI, 2>(recs, ring, u + 1, w, lane);
+    if constexpr (GR) {
+      if (u + 1 < nsteps) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int j = (t + 1) * BN + b * 16 + c16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) gnxt[b][v] = j < P.K ? grow[v][j] : 0.f;
+        }
+      }
+    }
     const float* sb = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE);
     if (ch == 0) {
 #pragma unroll
@@ -215,7 +241,7 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           accS[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[s + e], bv[b][e], accS[b], 0, 0, 0);
-          if constexpr (SP)
+          if constexpr (SP && !GR)
             accT[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[s + e], bv[b][e], accT[b], 0, 0, 0);
         }
       }
@@ -230,7 +256,8 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
         for (int v = 0; v < 4; ++v) {
           float val;
           if constexpr (SP) {
-            const float e = accT[b][v] - av[v];
+            // <r, c_j> - <r, x>, directly or as (<x, c_j> - G[pi][j]) - <r, x>
+            const float e = GR ? (accS[b][v] - gcur[b][v]) - av[v] : accT[b][v] - av[v];
             const float wv = fmaf(-2.f, accS[b][v], cnv);
             val = fmaf(lp[v] * e, e, wv);
             if (j == pr[v]) val = kInf;
@@ -246,6 +273,12 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
           b1[v] = fminf(b1[v], val);
         }
       }
+    }
+    if constexpr (GR) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gcur[b][v] = gnxt[b][v];
     }
     if constexpr (CH) {
       if (u + 1 < nsteps) {
@@ -348,7 +381,7 @@ __device__ __forceinline__ void decide(const AssignParams& P, RowShared& S, Cand
 template <int DP, bool CH>
 constexpr int f32_waves() { return (!CH && DP <= 128) ? 2 : 1; }
 
-template <int DP, int BN, bool CH, bool SPILL, bool VEC>
+template <int DP, int BN, bool CH, bool SPILL, bool VEC, bool GR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(f32_waves<DP, CH>(), 2)))
 void assign_f32_kernel(AssignParams P) {
   using R = F32Rec<DP, BN>;
@@ -442,7 +475,12 @@ void assign_f32_kernel(AssignParams P) {
     S.pi[w][c16] = pi;
     S.lp[w][c16] = rr > 0.f ? P.lam / rr : 0.f;
     S.av[w][c16] = a;
-    S.band[w][c16] = P.band_s * scale2;
+    float band = P.band_s * scale2;
+    if (GR && rr > 0.f) {
+      const float inv = 1.f / sqrtf(rr);
+      band += P.band_g1 * scale2 * (xnorm + cmax) * inv + P.band_g2 * scale2 * scale2 * inv * inv;
+    }
+    S.band[w][c16] = band;
   }
   __syncthreads();
 #pragma unroll
@@ -453,8 +491,8 @@ void assign_f32_kernel(AssignParams P) {
   }
 
   // ---------------- spill pass ----------------
-  sweep<DP, BN, CH, VEC, true>(P, ring, nch, tid, row, ok, pi, xa, ra, lp, av, pr, b1, i1, b2,
-                               i2, b3);
+  sweep<DP, BN, CH, VEC, true, GR>(P, ring, nch, tid, row, ok, pi, xa, ra, lp, av, pr, b1, i1,
+                                   b2, i2, b3);
   publish_candidates(S, CS, w, lane, b1, i1, b2, i2, b3);
   __syncthreads();
   if (pi < 0) return;  // full-scan rows are finished by the full-scan kernel
@@ -476,45 +514,57 @@ void assign_f32_kernel(AssignParams P) {
 
 // ------------------------------------------------------------------------------------------------
 // Exact full scan over all K for the rows listed by the assignment kernel (one workgroup a row).
-// Each wave takes one centroid at a time with its lanes across the dimensions (coalesced loads),
-// and a 64-lane tree gives the sum (at most 4 sequential terms per lane for d <= 256).
+// The 256 threads form 16 groups of 16 lanes; a group takes one centroid at a time with its lanes
+// across the dimensions, and a 16-lane tree gives the sum.  The row (and its residual) sit in LDS.
 // ------------------------------------------------------------------------------------------------
 constexpr int FS_THREADS = 256;
 constexpr int FS_WAVES = FS_THREADS / 64;
+constexpr int FS_GROUPS = FS_THREADS / 16;
 
 __device__ __forceinline__ float wave_sum_f(float v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
   return v;
 }
-__device__ __forceinline__ double wave_sum_d(double v) {
+__device__ __forceinline__ float sum16_f(float v) {
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ __forceinline__ double sum16_d(double v) {
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off);
   return v;
 }
 
 // FP32 value of centroid j for this row: ||x - c||^2, or the SOAR loss given r and ||r||^2.
 template <bool SP>
 __device__ __forceinline__ float fs_value32(const float* __restrict__ c, const float* sx,
-                                            const float* sr, float rr, float lam, int d, int lane) {
-  float sq = 0.f, pj = 0.f;
-  for (int k = lane; k < d; k += 64) {
-    const float e = sx[k] - c[k];
-    sq = fmaf(e, e, sq);
-    if (SP) pj = fmaf(sr[k], e, pj);
+                                            const float* sr, float rr, float lam, int d, int l) {
+  float sq0 = 0.f, sq1 = 0.f, pj0 = 0.f, pj1 = 0.f;
+  int k = l;
+  for (; k + 16 < d; k += 32) {
+    const float e0 = sx[k] - c[k], e1 = sx[k + 16] - c[k + 16];
+    sq0 = fmaf(e0, e0, sq0); sq1 = fmaf(e1, e1, sq1);
+    if (SP) { pj0 = fmaf(sr[k], e0, pj0); pj1 = fmaf(sr[k + 16], e1, pj1); }
   }
-  sq = wave_sum_f(sq);
+  if (k < d) {
+    const float e0 = sx[k] - c[k];
+    sq0 = fmaf(e0, e0, sq0);
+    if (SP) pj0 = fmaf(sr[k], e0, pj0);
+  }
+  const float sq = sum16_f(sq0 + sq1);
   if (!SP) return sq;
-  pj = wave_sum_f(pj);
+  const float pj = sum16_f(pj0 + pj1);
   return rr > 0.f ? sq + lam * (pj * pj) / rr : sq;
 }
 
 // FP64 value with the residual formed exactly from C[pi] (near-tie decisions).
 template <bool SP>
 __device__ __forceinline__ double fs_value64(const float* __restrict__ c, const float* sx,
-                                             const float* scp, float lam, int d, int lane) {
+                                             const float* scp, float lam, int d, int l) {
   double sq = 0.0, pj = 0.0, rr = 0.0;
-  for (int k = lane; k < d; k += 64) {
+  for (int k = l; k < d; k += 16) {
     const double e = (double)sx[k] - (double)c[k];
     sq = fma(e, e, sq);
     if (SP) {
@@ -523,16 +573,23 @@ __device__ __forceinline__ double fs_value64(const float* __restrict__ c, const 
       rr = fma(rk, rk, rr);
     }
   }
-  sq = wave_sum_d(sq);
+  sq = sum16_d(sq);
   if (!SP) return sq;
-  pj = wave_sum_d(pj);
-  rr = wave_sum_d(rr);
+  pj = sum16_d(pj);
+  rr = sum16_d(rr);
   return rr > 0.0 ? sq + (double)lam * (pj * pj) / rr : sq;
 }
 
+// Workgroup (value, index) minimum; every 16-lane group enters with its own candidate.
 template <typename T>
 __device__ __forceinline__ void wg_argmin(T& v, int& j, T* sv, int* sj) {
   const int tid = threadIdx.x, w = tid >> 6;
+#pragma unroll
+  for (int off = 16; off <= 32; off <<= 1) {
+    const T ov = __shfl_xor(v, off);
+    const int oj = __shfl_xor(j, off);
+    if (ov < v || (ov == v && oj < j)) { v = ov; j = oj; }
+  }
   if ((tid & 63) == 0) { sv[w] = v; sj[w] = j; }
   __syncthreads();
   if (tid == 0) {
@@ -545,31 +602,47 @@ __device__ __forceinline__ void wg_argmin(T& v, int& j, T* sv, int* sj) {
   __syncthreads();
 }
 
-// Exact arg-min over all columns j != skip; FP32 direct values, then FP64 among near-ties.
+// Exact arg-min over all columns j != skip; FP32 direct values, then FP64 among near-ties.  A
+// group evaluates 4 centroids per iteration (their loads in flight together); with sv non-null
+// (K <= FS_LDS_K) the FP32 values are kept in LDS for the near-tie pass.
+constexpr int FS_UNROLL = 4;
+constexpr int FS_LDS_K = 8192;
+
 template <bool SP>
 __device__ void fs_argmin(const AssignParams& P, const float* sx, const float* sr, float rr,
-                          const float* scp, int skip, int& out_j, float& out_v) {
+                          const float* scp, int skip, float* sv, int& out_j, float& out_v) {
   __shared__ float rv[FS_WAVES];
   __shared__ int rj[FS_WAVES];
   __shared__ double rd[FS_WAVES];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, K = P.K, d = P.d;
+  const int l = threadIdx.x & 15, g = threadIdx.x >> 4, K = P.K, d = P.d;
   float bv = kInf;
   int bj = 0x7fffffff;
-  for (int j = w; j < K; j += FS_WAVES) {
-    if (j == skip) continue;
-    const float v = fs_value32<SP>(P.C + (int64_t)j * d, sx, sr, rr, P.lam, d, lane);
-    if (v < bv) { bv = v; bj = j; }
+  for (int j0 = g; j0 < K; j0 += FS_UNROLL * FS_GROUPS) {
+    float v[FS_UNROLL];
+#pragma unroll
+    for (int u = 0; u < FS_UNROLL; ++u) {
+      const int j = j0 + u * FS_GROUPS;
+      const int jj = j < K ? j : K - 1;     // in-bounds address; the value is masked below
+      v[u] = fs_value32<SP>(P.C + (int64_t)jj * d, sx, sr, rr, P.lam, d, l);
+      if (j >= K || j == skip) v[u] = kInf;
+    }
+#pragma unroll
+    for (int u = 0; u < FS_UNROLL; ++u) {
+      const int j = j0 + u * FS_GROUPS;
+      if (sv && j < K && l == 0) sv[j] = v[u];
+      if (v[u] < bv) { bv = v[u]; bj = j; }
+    }
   }
-  wg_argmin<float>(bv, bj, rv, rj);
+  wg_argmin<float>(bv, bj, rv, rj);   // (its barriers also publish sv)
   if (!(bv < kInf)) { out_j = -1; out_v = kInf; return; }
   const float lim = bv + bv * P.tie_rel;
   double dv = __builtin_inf();
   int dj = 0x7fffffff;
-  for (int j = w; j < K; j += FS_WAVES) {
+  for (int j = g; j < K; j += FS_GROUPS) {
     if (j == skip) continue;
     const float* c = P.C + (int64_t)j * d;
-    const float v = fs_value32<SP>(c, sx, sr, rr, P.lam, d, lane);
-    if (v <= lim) argmin_d(dv, dj, fs_value64<SP>(c, sx, scp, P.lam, d, lane), j);
+    const float v = sv ? sv[j] : fs_value32<SP>(c, sx, sr, rr, P.lam, d, l);
+    if (v <= lim) argmin_d(dv, dj, fs_value64<SP>(c, sx, scp, P.lam, d, l), j);
   }
   wg_argmin<double>(dv, dj, rd, rj);
   out_j = dj;
@@ -582,6 +655,7 @@ __global__ __launch_bounds__(FS_THREADS) void full_scan_kernel(AssignParams P) {
   float* sx = fs_smem;
   float* sr = fs_smem + P.d;
   float* scp = fs_smem + 2 * P.d;
+  float* sv = P.K <= FS_LDS_K ? fs_smem + 3 * P.d : nullptr;
   __shared__ float s_rr;
   const unsigned count = P.counters[CNT_FULLSCAN];
   const int d = P.d, tid = threadIdx.x, lane = tid & 63;
@@ -591,7 +665,7 @@ __global__ __launch_bounds__(FS_THREADS) void full_scan_kernel(AssignParams P) {
     __syncthreads();
     int pi;
     float pd;
-    fs_argmin<false>(P, sx, sr, 0.f, scp, -1, pi, pd);
+    fs_argmin<false>(P, sx, sr, 0.f, scp, -1, sv, pi, pd);
     if (pi >= P.K) pi = -1;
     if (tid == 0) {
       P.primary[row] = pi;
@@ -616,7 +690,7 @@ __global__ __launch_bounds__(FS_THREADS) void full_scan_kernel(AssignParams P) {
       int sj = -1;
       float sl = kInf;
       if (pi >= 0) {
-        fs_argmin<true>(P, sx, sr, s_rr, scp, pi, sj, sl);
+        fs_argmin<true>(P, sx, sr, s_rr, scp, pi, sv, sj, sl);
         if (sj >= P.K) sj = -1;
       }
       if (tid == 0) {
@@ -693,6 +767,46 @@ __global__ __launch_bounds__(256) void pack_f32_kernel(const float* __restrict__
   if (f == 0) *reinterpret_cast<float*>(base + R::CN_OFF + jl * 4) = j < K ? cnorm[j] : kInf;
 }
 
+// G = C C^T: a 64 x 64 block of G per workgroup, 4 x 4 outputs per thread, the two 64-row
+// slices of C staged through LDS 16 dimensions at a time.
+__global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ C, int K, int d,
+                                                   float* __restrict__ G) {
+  __shared__ float sa[16][65], sb[16][65];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < d; k0 += 16) {
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int r = e >> 4, k = e & 15;
+      sa[k][r] = (i0 + r < K && k0 + k < d) ? C[(int64_t)(i0 + r) * d + k0 + k] : 0.f;
+      sb[k][r] = (j0 + r < K && k0 + k < d) ? C[(int64_t)(j0 + r) * d + k0 + k] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(sa[k][ty + 16 * a], sb[k][tx + 16 * b], acc[a][b]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
+      if (i < K && j < K) G[(int64_t)i * K + j] = acc[a][b];
+    }
+}
+
+bool fp32_uses_gram(int d, int K) { return K <= kGramMaxK && d <= 256; }
+
+hipError_t launch_gram(const float* C, int K, int d, float* G, hipStream_t st) {
+  const unsigned nb = (unsigned)((K + 63) / 64);
+  hipLaunchKernelGGL(gram_kernel, dim3(nb, nb), dim3(256), 0, st, C, K, d, G);
+  return hipGetLastError();
+}
+
 // Padded widths: rows of up to 256 stay resident; longer rows go in chunks of 128.
 constexpr int kF32ChunkDP = 128, kF32ChunkBN = 64, kF32MaxD = 1024;
 
@@ -723,12 +837,19 @@ static hipError_t pack_dp(const float* C, int K, int d, const float* cnorm, void
 template <int DP, int BN, bool CH>
 static hipError_t launch_dp(const AssignParams& P, bool spill, bool vec, hipStream_t st) {
   const dim3 grid((unsigned)((P.n + 63) / 64)), block(256);
-  if (spill) {
-    if (vec) hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, true, true>), grid, block, 0, st, P);
-    else hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, true, false>), grid, block, 0, st, P);
+  if (spill && P.G) {
+    if constexpr (!CH) {
+      if (vec) hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, true, true, true>), grid, block, 0, st, P);
+      else hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, true, false, true>), grid, block, 0, st, P);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else if (spill) {
+    if (vec) hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, true, true, false>), grid, block, 0, st, P);
+    else hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, true, false, false>), grid, block, 0, st, P);
   } else {
-    if (vec) hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, false, true>), grid, block, 0, st, P);
-    else hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, false, false>), grid, block, 0, st, P);
+    if (vec) hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, false, true, false>), grid, block, 0, st, P);
+    else hipLaunchKernelGGL((assign_f32_kernel<DP, BN, CH, false, false, false>), grid, block, 0, st, P);
   }
   return hipGetLastError();
 }
@@ -789,7 +910,7 @@ hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipSt
 #undef SOAR_X
   if (e != hipSuccess) return e;
   if (ev_end) (void)hipEventRecord(ev_end, st);
-  const size_t smem = (size_t)3 * P.d * sizeof(float);
+  const size_t smem = ((size_t)3 * P.d + (P.K <= FS_LDS_K ? (size_t)P.K : 0)) * sizeof(float);
   if (spill)
     hipLaunchKernelGGL(full_scan_kernel<true>, dim3(1024), dim3(FS_THREADS), smem, st, P);
   else

@@ -18,6 +18,10 @@ struct AssignParams {
   float tie_rel;        // relative gap under which FP32 re-scores are re-decided in FP64
   float band_p;         // primary screen: band = band_p * (||x|| + max||c||)^2
   float band_s;         // spill screen:   band = band_s * (||x|| + max||c||)^2
+  // Gram form of the spill screen (G non-null): <r, c_j> = <x, c_j> - G[pi][j], band widened by
+  // band_g1 * E^1.5 / ||r|| + band_g2 * E^2 / ||r||^2 with E = (||x|| + max||c||)^2
+  const float* G = nullptr;   // [K x K] C C^T, or null
+  float band_g1 = 0.f, band_g2 = 0.f;
   int32_t* primary;
   int32_t* spill;
   float* pdist;
@@ -37,6 +41,13 @@ hipError_t launch_pack_fp32(const float* C, int K, int d, const float* cnorm, vo
 float band_coef_primary(int d);
 float band_coef_spill(int d, float lam);
 float tie_threshold(int d, float lam, float near_tie_rel);
+// Largest K for which the spill sweep uses the Gram form (G = C C^T in the workspace).
+constexpr int kGramMaxK = 4096;
+bool fp32_uses_gram(int d, int K);
+float band_coef_gram1(int d, float lam);
+float band_coef_gram2(int d, float lam);
+// G = C C^T (K x K, FP32, any summation order).
+hipError_t launch_gram(const float* C, int K, int d, float* G, hipStream_t st);
 // Clears all counters, then ||c_j||^2, max ||c||^2 and the finiteness flag of the codebook.
 hipError_t launch_prep_codebook(const float* C, int K, int d, float* cnorm, unsigned* counters,
                                 hipStream_t st);

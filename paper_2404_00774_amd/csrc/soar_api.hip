@@ -105,6 +105,7 @@ struct AssignLayout {
   unsigned* counters;
   float* cnorm;
   char* crec;
+  float* gram;          // [K x K] when the spill sweep uses the Gram form
   int32_t* full_rows;
   size_t bytes;
 };
@@ -115,6 +116,7 @@ AssignLayout layout_assign(void* ws, int64_t n, int32_t d, int32_t K) {
   L.counters = c.take<unsigned>(soar::CNT_WORDS);
   L.cnorm = c.take<float>((size_t)K);
   L.crec = c.take<char>(soar::fp32_codebook_bytes(d, K));
+  L.gram = soar::fp32_uses_gram(d, K) ? c.take<float>((size_t)K * K) : nullptr;
   L.full_rows = c.take<int32_t>((size_t)n);
   L.bytes = c.off;
   return L;
@@ -133,6 +135,15 @@ namespace soar {
 float band_coef_primary(int d) { return 2.2f * (float)(d + 2) * kU32; }
 float band_coef_spill(int d, float lam) {
   return 2.2f * (1.f + 3.f * lam) * (float)(d + 5) * kU32;
+}
+// Gram form of the spill screen: <r, c> is formed as <x, c> - <c_pi, c>, whose error is
+// gamma_{d+2} E with E = (||x|| + max||c||)^2 instead of gamma_{d+2} ||r|| sqrt(E).  Through
+// lambda/||r||^2 * e^2 with |e| <= ||r|| sqrt(E) that adds 2 lambda gamma_{d+2} E^1.5 / ||r|| and
+// lambda gamma_{d+2}^2 E^2 / ||r||^2 to the error bound (again doubled, with a 10% margin).
+float band_coef_gram1(int d, float lam) { return 2.2f * 2.f * lam * (float)(d + 2) * kU32; }
+float band_coef_gram2(int d, float lam) {
+  const float g = (float)(d + 2) * kU32;
+  return 2.2f * lam * g * g;
 }
 float tie_threshold(int d, float lam, float near_tie_rel) {
   const float rel = near_tie_rel > 0.f ? near_tie_rel : 1e-5f;
@@ -156,9 +167,16 @@ soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C
   P.band_s = band_coef_spill(d, lam);
   P.primary = primary; P.spill = spill_out; P.pdist = pdist; P.sloss = sloss;
   P.full_rows = L.full_rows;
+  const bool gram = spill && L.gram != nullptr;
+  if (gram) {
+    P.G = L.gram;
+    P.band_g1 = band_coef_gram1(d, lam);
+    P.band_g2 = band_coef_gram2(d, lam);
+  }
   const bool vec = (d % 4 == 0) && aligned(X, 16) && aligned(C, 16);
   hipError_t e = launch_prep_codebook(C, K, d, L.cnorm, L.counters, st);
   if (e == hipSuccess) e = launch_pack_fp32(C, K, d, L.cnorm, L.crec, st);
+  if (e == hipSuccess && gram) e = launch_gram(C, K, d, L.gram, st);
   if (e == hipSuccess) e = launch_assign_fp32(P, spill, vec, st, ev_kernel_begin, ev_kernel_end);
   if (e != hipSuccess) return SOAR_E_DEVICE;
   if (counters_out_host) {

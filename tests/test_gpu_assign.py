@@ -30,6 +30,7 @@ def _run(X, C, lam, **kw):
 
 def _check(X, C, lam, res, fast=True):
     p, s, dp, ls, st = res
+    print("  stats", {k: st[k] for k in ("rows_full_scan", "rows_fp64")}, flush=True)
     j = O.judge(X, C, lam, p, s, dp, ls, fast=fast)
     bad = np.flatnonzero(~(j["primary_ok"] & j["spill_ok"] & j["pdist_ok"] & j["sloss_ok"]))
     assert bad.size == 0, (f"{bad.size} rows fail, first {bad[:5]}: gpu p={p[bad[:5]]} "
@@ -58,7 +59,9 @@ def test_small_workload_parity(small_workload, lam):
     (257, 96, 1000), (129, 128, 257), (200, 200, 130), (70, 256, 66), (100, 48, 90),
     (130, 5, 40), (1000, 32, 129),
     # rows above 256 dimensions: chunks of 128 (ragged last chunk, several tiles, one tile)
-    (300, 257, 70), (129, 300, 65), (200, 768, 130), (70, 1024, 33), (65, 513, 3)])
+    (300, 257, 70), (129, 300, 65), (200, 768, 130), (70, 1024, 33), (65, 513, 3),
+    # the spill sweep's Gram form holds up to K = 4096; above it <r, c> is formed directly
+    (1000, 128, 4096), (129, 96, 4097), (300, 64, 5000)])
 @pytest.mark.parametrize("lam", [0.0, 1.0])
 def test_edge_shapes(n, d, K, lam):
     print(f"edge n={n} d={d} K={K} lam={lam}", flush=True)
@@ -83,6 +86,22 @@ def test_integer_ties_duplicates_and_zero_residual():
         # integer data: distances are exact, so the primary must be the lowest-index arg-min
         assert np.array_equal(res[0], j["p_star"])
         assert res[4]["rows_full_scan"] > 0       # the duplicates force the exact full scan
+
+
+@pytest.mark.parametrize("lam", [1.0, 1.5])
+def test_small_residuals(lam):
+    """Rows at distances 1e-2 .. 1e-6 from their centroid: the Gram form's screening band grows
+    like 1/||r||, so such rows exercise the widened band and the exact full scan."""
+    rng = np.random.default_rng(21)
+    n, d, K = 4000, 64, 300
+    C = rng.standard_normal((K, d)).astype(np.float32)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    src = rng.integers(0, K, n)
+    for k, eps in enumerate((1e-2, 1e-3, 1e-4, 1e-6)):
+        sl = slice(k * 800, (k + 1) * 800)
+        X[sl] = C[src[sl]] + eps * rng.standard_normal((800, d)).astype(np.float32)
+    print(f"small residuals lam={lam}", flush=True)
+    _check(X, C, lam, _run(X, C, lam), fast=False)
 
 
 def test_deterministic_and_metamorphic(small_workload):
