@@ -50,8 +50,11 @@ def parse():
     ap.add_argument("--codebook", default="train", choices=["train", "sample"],
                     help="sample: K uniformly sampled rows, no training (for short profiling runs)")
     ap.add_argument("--rows", type=int, default=0, help="use only the first N rows (profiling)")
-    ap.add_argument("--mode", default="assign", choices=["assign", "serve"],
-                    help="serve: the serving form (resident index, open-loop Poisson inserts)")
+    ap.add_argument("--mode", default="assign", choices=["assign", "serve", "copy"],
+                    help="serve: the serving form (resident index, open-loop Poisson inserts); "
+                         "copy: a plain device copy of --copy-mib MiB (calibrates the HBM byte "
+                         "counters of a profiler)")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--serve-base", type=int, default=20_000_000, help="rows of the base index")
     ap.add_argument("--serve-K", type=int, default=50_000)
     ap.add_argument("--serve-rates", default="5000,20000,50000,100000,200000",
@@ -293,6 +296,17 @@ def main():
         sys.exit(2)
     if args.mode == "serve":
         serve_main(args)
+        return
+    if args.mode == "copy":
+        import torch
+        nbytes = args.copy_mib << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read_per_copy": nbytes,
+                          "bytes_written_per_copy": nbytes, "copies": args.steps}))
         return
     import torch
     import paper_2404_00774_amd as soar

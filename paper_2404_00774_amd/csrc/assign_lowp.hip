@@ -17,9 +17,10 @@
 //
 // Candidates.  In the 16x16 MFMA result a lane sees one column of every 16-column block, so per
 // row the 16 lanes of a lane group see the 16 residue classes of j mod 16.  Each lane keeps the
-// minimum of its class: the block index within the tile is packed into the three low mantissa
-// bits of the value (a 2^-20 relative perturbation) and the tile index is recorded when the
-// minimum improves.
+// minimum of its class: (tile mod TG, block) is packed into the four low mantissa bits of the
+// value (at most a 2^-19 relative perturbation; the mask ~15 is an inline constant, so packing is
+// one v_and_or) and the tile group (tile / TG) is recorded when the minimum has improved over a
+// group.
 // The topk (<= 8) smallest of the 16 class minima are re-scored.
 #include <type_traits>
 
@@ -49,11 +50,12 @@ struct FmtTraits<LOWP_FP8> {
   static constexpr int LANE_B = 32;
 };
 
-__device__ __forceinline__ float pack_block(float v, unsigned b) {
-  return __builtin_bit_cast(float, (__builtin_bit_cast(unsigned, v) & ~7u) | b);
+// Four low mantissa bits carry a code < 16 (tile within its group, block within the tile).
+__device__ __forceinline__ float pack_code(float v, unsigned c) {
+  return __builtin_bit_cast(float, (__builtin_bit_cast(unsigned, v) & ~15u) | c);
 }
-__device__ __forceinline__ unsigned packed_block(float v) {
-  return __builtin_bit_cast(unsigned, v) & 7u;
+__device__ __forceinline__ unsigned packed_code(float v) {
+  return __builtin_bit_cast(unsigned, v) & 15u;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -212,13 +214,14 @@ __global__ __launch_bounds__(256) void pack_codebook_kernel(const float* __restr
 }
 
 // Ranking values in the epilogue (row constants of the loss dropped):
-//   BF16: the record holds -2 c (exact), the S accumulator starts at ||c_j||^2 and the T
-//         accumulator at 2 <r_i, x_i>, so S = ||c||^2 - 2<x,c> and T = -2 (<r,c> - <r,x>); the
-//         spill value is S + lambda/(4 ||r||^2) T^2.
+//   BF16: the record holds -2 c (exact) and the residual rows are stored pre-scaled by
+//         sigma = sqrt(lambda) / (2 ||r||); the S accumulator starts at ||c_j||^2 and the T
+//         accumulator at 2 sigma <r_i, x_i>, so S = ||c||^2 - 2<x,c>,
+//         T = -2 sigma (<r,c> - <r,x>) and the spill value is S + T^2 (one fma).
 //   FP8:  rows carry scales, so S and T are rescaled per (row, column) in the epilogue.
 // The codebook records flow through an LDS ring of STG stages filled STG-1 tiles ahead.
 template <int FMT, int DP, int SPW, int BN, int STG, int WPE, bool SP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 2)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE > 2 ? WPE : 2)))
 void lowp_sweep_kernel(LowpParams P) {
   using T = FmtTraits<FMT>;
   using R = TileRec<FMT, DP, BN>;
@@ -269,15 +272,22 @@ void lowp_sweep_kernel(LowpParams P) {
           kt[i] = rc.x;                      // inverse scale of the quantized residual row
           ka[i] = rc.y;                      // <r, x>
         }
-        kl[i] = BF ? 0.25f * rc.z : rc.z;    // lambda / ||r||^2 (BF16: / 4 for T = -2e)
+        kl[i] = rc.z;                        // lambda / ||r||^2 (FP8)
         kp[i] = ok ? P.primary[r] : -1;
-        a2[st][v] = 2.f * rc.y;
+        a2[st][v] = 2.f * rc.w * rc.y;       // BF16: 2 sigma <r, x>
       }
     }
-  float b1[NR];
+  // (tile mod TG, block) codes fill the four packed bits; the group t / TG is tracked per row
+  constexpr int TG = 16 / NB;
+  static_assert(TG >= 1, "at most 16 blocks per tile");
+  float b1[NR], old[NR];
   int bt[NR];
 #pragma unroll
-  for (int i = 0; i < NR; ++i) { b1[i] = kBig; bt[i] = 0; }
+  for (int i = 0; i < NR; ++i) { b1[i] = kBig; old[i] = kBig; bt[i] = 0; }
+  // lane's base addresses inside a ring stage: B operand rows and the norms
+  const int lane_b = c16 * R::LDWB + (q * (DP / 4)) * T::BYTES;
+  const int lane_cn = R::CN_OFF + c16 * 16;
+  int stage = 0;
 
   for (int t = 0; t < ntiles; ++t) {
     // record t has landed in LDS for this wave (later records may still be in flight) ...
@@ -290,11 +300,11 @@ void lowp_sweep_kernel(LowpParams P) {
     // ... and for every wave; every wave is also done reading the stage refilled next
     __builtin_amdgcn_s_barrier();
     if (t + STG - 1 < ntiles) issue_record<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, t + STG - 1, w, lane);
-    const char* tile = s_ring + (t % STG) * R::STAGE;
-
-    float old[NR];
-#pragma unroll
-    for (int i = 0; i < NR; ++i) old[i] = b1[i];
+    const char* tile = s_ring + stage * R::STAGE;
+    const char* tb = tile + lane_b;
+    const char* tcn = tile + lane_cn;
+    stage = stage + 1 == STG ? 0 : stage + 1;
+    const unsigned tcode = (unsigned)((t % TG) * NB);
     // does this tile hold the primary of any row of the wave?
     bool masked = false;
     if constexpr (SP) {
@@ -308,8 +318,7 @@ void lowp_sweep_kernel(LowpParams P) {
       v4f accS[SPW][GB], accT[SP ? SPW : 1][GB];
 #pragma unroll
       for (int b = 0; b < GB; ++b) {
-        const v4f init = BF ? *reinterpret_cast<const v4f*>(tile + R::CN_OFF +
-                                                             ((g * GB + b) * 16 + c16) * 16)
+        const v4f init = BF ? *reinterpret_cast<const v4f*>(tcn + (g * GB + b) * 256)
                             : v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int st = 0; st < SPW; ++st) {
@@ -325,8 +334,7 @@ void lowp_sweep_kernel(LowpParams P) {
 #pragma unroll
           for (int ww = 0; ww < W4; ++ww)
             bv[b][ww] = *reinterpret_cast<const u32x4*>(
-                tile + ((g * GB + b) * 16 + c16) * R::LDWB + (q * (DP / 4)) * T::BYTES +
-                s * T::LANE_B + ww * 16);
+                tb + (g * GB + b) * 16 * R::LDWB + s * T::LANE_B + ww * 16);
 #pragma unroll
         for (int b = 0; b < GB; ++b)
 #pragma unroll
@@ -350,7 +358,7 @@ void lowp_sweep_kernel(LowpParams P) {
               float val;
               if constexpr (BF) {
                 val = accS[st][b][v];
-                if constexpr (SP) val = fmaf(kl[i] * accT[st][b][v], accT[st][b][v], val);
+                if constexpr (SP) val = fmaf(accT[st][b][v], accT[st][b][v], val);
               } else {
                 const float cs = *reinterpret_cast<const float*>(tile + R::CS_OFF + jl * 4);
                 const float cn = *reinterpret_cast<const float*>(tile + R::CN_OFF + jl * 16);
@@ -362,7 +370,7 @@ void lowp_sweep_kernel(LowpParams P) {
               }
               if constexpr (SP && decltype(with_mask)::value)
                 val = (t * BN + jl == kp[i]) ? kBig : val;
-              pv[b] = pack_block(val, (unsigned)(g * GB + b));
+              pv[b] = pack_code(val, tcode + (unsigned)(g * GB + b));
             }
             float m = pv[0];
 #pragma unroll
@@ -373,8 +381,13 @@ void lowp_sweep_kernel(LowpParams P) {
       if (__builtin_expect(SP && masked, 0)) epilogue(std::true_type{});
       else epilogue(std::false_type{});
     }
+    if ((t + 1) % TG == 0 || t + 1 == ntiles) {
 #pragma unroll
-    for (int i = 0; i < NR; ++i) bt[i] = b1[i] < old[i] ? t : bt[i];
+      for (int i = 0; i < NR; ++i) {
+        bt[i] = b1[i] < old[i] ? t / TG : bt[i];
+        old[i] = b1[i];
+      }
+    }
   }
 
   // candidates: rank the 16 class minima of every row, keep the topk smallest
@@ -387,7 +400,9 @@ void lowp_sweep_kernel(LowpParams P) {
       const int64_t r = row0 + st * 16 + 4 * q + v;
       const float bv = b1[i];
       const bool valid = bv < 1.0e38f;
-      const int j = valid ? bt[i] * BN + (int)packed_block(bv) * 16 + c16 : 0x7fffffff;
+      const unsigned code = packed_code(bv);
+      const int j = valid ? (bt[i] * TG + (int)(code / NB)) * BN + (int)(code % NB) * 16 + c16
+                          : 0x7fffffff;
       int rank = 0;
 #pragma unroll
       for (int o = 1; o < 16; ++o) {
@@ -555,7 +570,10 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
       inv = 1.f / scale;
     }
   }
-  if (l16 == 0) P.rowc_out[row] = float4{inv, a, r2 > 0.f ? P.lam / r2 : 0.f, 0.f};
+  // BF16 stores the residual pre-scaled by sigma = sqrt(lambda) / (2 ||r||)
+  const float rn = sqrtf(r2);
+  const float sigma = (FMT == LOWP_BF16 && rn > 0.f) ? 0.5f * sqrtf(P.lam) / rn : 0.f;
+  if (l16 == 0) P.rowc_out[row] = float4{inv, a, r2 > 0.f ? P.lam / r2 : 0.f, sigma};
   // the whole padded row is written: the padding must hold zeros, not old workspace bytes
   const int dp = P.dp;
   if constexpr (FMT == LOWP_FP8) {
@@ -568,7 +586,7 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
     __bf16* o = static_cast<__bf16*>(P.Rq_out) + row * dp;
 #pragma unroll
     for (int m = 0; m < RS_MAXD; ++m)
-      if (m < nd) o[l16 + 16 * m] = (__bf16)r[m];
+      if (m < nd) o[l16 + 16 * m] = (__bf16)(sigma * r[m]);
     for (int k = d + l16; k < dp; k += 16) o[k] = (__bf16)0.f;
   }
 }
@@ -610,11 +628,19 @@ struct SweepShape;
     static constexpr int SPW_P = SP_P, WPE_P = W_P, SPW_S = SP_S, WPE_S = W_S;      \
     static constexpr int BN = B, STG = S;                                           \
   };
+#define SOAR_SHAPE_X(...) SOAR_SHAPE(__VA_ARGS__)
+// (the two most used widths can be set at build time, e.g. -DSOAR_SHAPE_BF16_96=4,2,2,2,64,3)
+#ifndef SOAR_SHAPE_BF16_96
+#define SOAR_SHAPE_BF16_96 4, 2, 2, 2, 64, 3
+#endif
+#ifndef SOAR_SHAPE_BF16_128
+#define SOAR_SHAPE_BF16_128 4, 2, 2, 1, 64, 3
+#endif
 //         format     DP  primary  spill   BN  stages   (SPW stripes, waves per SIMD)
 SOAR_SHAPE(LOWP_BF16, 32, 4, 2, 2, 2, 64, 3)
 SOAR_SHAPE(LOWP_BF16, 64, 4, 2, 2, 2, 64, 3)
-SOAR_SHAPE(LOWP_BF16, 96, 4, 2, 2, 2, 64, 3)
-SOAR_SHAPE(LOWP_BF16, 128, 4, 2, 2, 1, 64, 3)
+SOAR_SHAPE_X(LOWP_BF16, 96, SOAR_SHAPE_BF16_96)
+SOAR_SHAPE_X(LOWP_BF16, 128, SOAR_SHAPE_BF16_128)
 SOAR_SHAPE(LOWP_BF16, 192, 2, 1, 2, 1, 64, 3)
 SOAR_SHAPE(LOWP_BF16, 256, 2, 1, 1, 1, 64, 3)
 SOAR_SHAPE(LOWP_BF16, 384, 1, 1, 1, 1, 64, 2)
