@@ -27,6 +27,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2516.0, "fp8": 5032.0}   # MI355X dense MFMA peaks
+
+# HBM bytes per launch of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
+# (KiB per dispatch), each scaled by what the same counter reads for a plain 1 GiB device copy
+# (bench.py --mode copy: FETCH_SIZE reads 524302.5 KiB, WRITE_SIZE 1048576 KiB, so the factors
+# are 2.0 and 1.0).  A figure holds only for the kernel source it was taken on (sha256 below);
+# after any change to that file the traffic is reported as null until it is measured again.
+COPY_SCALE = {"fetch": 1048576.0 / 524302.5, "write": 1.0}
+TRAFFIC = {
+    ("fp32", "mix4096_n1m_d128"): dict(
+        fetch_kib=2846965.8, write_kib=15648.1,
+        source="paper_2404_00774_amd/csrc/assign_fp32.hip",
+        sha256="81777218c670ce0f7080c5fab4e5f4afe06fa460330b0549923743f37a1253db"),
+}
+
+
+def measured_traffic(prec, workload):
+    """Bytes per launch, or None when not measured for this kernel source."""
+    import hashlib
+    t = TRAFFIC.get((prec, workload))
+    if not t:
+        return None
+    path = os.path.join(ROOT, t["source"])
+    if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != t["sha256"]:
+        return None
+    return (t["fetch_kib"] * COPY_SCALE["fetch"] + t["write_kib"] * COPY_SCALE["write"]) * 1024.0
 METRIC = "SOAR-assigned points/sec and % MFMA peak, BF16/FP8 vs FP32 at ≤1e-3 regret"
 DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8_e4m3"}
 KERNEL = {"fp32": "assign_f32_kernel (primary + residual + spill, one kernel)",
@@ -372,7 +397,8 @@ def main():
     alg_flops = 4.0 * n * K * d
     roofline = {"bound": "mfma", "achieved": head["algorithmic_tflops"],
                 "peak": PEAKS_TFLOPS[precs[0]], "unit": "TFLOP/s", "frac": head["mfma_peak_frac"],
-                "traffic": None, "kernel": KERNEL[precs[0]], "kernel_ms": head["kernel_ms"],
+                "traffic": measured_traffic(precs[0], args.workload) if not args.rows else None,
+                "kernel": KERNEL[precs[0]], "kernel_ms": head["kernel_ms"],
                 "algorithmic_flops_per_launch": alg_flops}
 
     print(f"[bench] oracle leg: judging {len(idx)} rows per form"
