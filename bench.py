@@ -65,7 +65,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mix4096_n1m_d128")
-    ap.add_argument("--lam", type=float, default=1.0)
+    ap.add_argument("--lam", default=None,
+                    help="comma list of lambdas (default: the workload's, 1.0 first); the first "
+                         "is the headline, every one is timed and judged")
+    ap.add_argument("--recall-queries", type=int, default=1000,
+                    help="queries of the recall@10 check (workloads that define queries; 0: off)")
     ap.add_argument("--precision", default="fp32,bf16,fp8")
     ap.add_argument("--form-steps", type=int, default=5, help="timed steps of the extra forms")
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -95,28 +99,64 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline_leg(X, C, lam, spec, cpu_sample, judge_idx, forms):
+def cpu_baseline_leg(X, C, lams, spec, cpu_sample, judge_idx, sweep, recall):
     """The oracle leg: the FP64 oracle timed on a bounded sample of the workload (the CPU
-    baseline), and the oracle's answers on a second sample compared with every GPU form."""
+    baseline); the oracle's answers on a second sample compared with every GPU form at every
+    lambda; the lambda trend of the spilled residuals (Figure 9); and, with queries, recall@10 of
+    top-t partition probing with and without the spilled assignment (Eq. 1) against brute force."""
     import oracle as O
     from synth import sample_rows as sr
-    for prec, r in forms.items():
-        r["oracle_check"] = judge_form(O, X, C, lam, judge_idx, r.pop("out"))
-    if not cpu_sample:
-        return None
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:  # noqa: BLE001
-        threads = os.cpu_count() or 1
-    Xs = X[sr(spec, cpu_sample)]
-    O.assign(Xs[:2000], C, lam)                     # warm-up (BLAS threads, page faults)
-    t0 = time.perf_counter()
-    O.assign(Xs, C, lam)
-    dt = time.perf_counter() - t0
-    return {"value": len(Xs) / dt, "unit": "points/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{len(Xs)} uniformly sampled rows of the workload, FP64 screened oracle, "
-                      f"{dt:.2f} s wall"}
+    X64, C64 = X[judge_idx].astype(np.float64), C.astype(np.float64)
+    trend = {}
+    for lam, forms in sweep.items():
+        for prec, r in forms.items():
+            outs = r.pop("out")
+            r["oracle_check"] = judge_form(O, X, C, lam, judge_idx, outs)
+            if prec == next(iter(forms)):
+                p, s_ = outs[0].astype(np.int64), outs[1].astype(np.int64)
+                Rr, Rs = X64 - C64[p], X64 - C64[s_]
+                rr, ss = (Rr * Rr).sum(1), (Rs * Rs).sum(1)
+                ok = rr > 0
+                cos2 = (Rr * Rs).sum(1)[ok] ** 2 / (rr[ok] * ss[ok])
+                trend[lam] = {"form": prec, "mean_cos2_r_rspill": float(cos2.mean()),
+                              "mean_rspill_sq": float(ss.mean())}
+    lam_sorted = sorted(trend)
+    trend_out = {"per_lambda": {str(l): trend[l] for l in lam_sorted},
+                 "cos2_nonincreasing": all(trend[a]["mean_cos2_r_rspill"] >=
+                                           trend[b]["mean_cos2_r_rspill"] - 1e-12
+                                           for a, b in zip(lam_sorted, lam_sorted[1:])),
+                 "rspill_nondecreasing": all(trend[a]["mean_rspill_sq"] <=
+                                             trend[b]["mean_rspill_sq"] + 1e-12
+                                             for a, b in zip(lam_sorted, lam_sorted[1:]))}
+    rec = None
+    if recall:
+        Q, ts, full = recall["queries"], recall["ts"], recall["assign"]
+        gt = O.mips_topk(Q, X, 10)
+        rec = {"queries": int(len(Q)), "k": 10, "t": list(ts), "per_lambda": {}}
+        for lam, (p, s_) in full.items():
+            k0, n0 = O.kmr_curve(Q, X, C, [p], 10, ts, gt=gt)
+            k1, n1 = O.kmr_curve(Q, X, C, [p, s_], 10, ts, gt=gt)
+            rec["per_lambda"][str(lam)] = {
+                "recall_unspilled": [float(v) for v in k0], "recall_spilled": [float(v) for v in k1],
+                "points_searched_unspilled": [float(v) for v in n0],
+                "points_searched_spilled": [float(v) for v in n1]}
+    cpu = None
+    if cpu_sample:
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        except Exception:  # noqa: BLE001
+            threads = os.cpu_count() or 1
+        lam = lams[0]
+        Xs = X[sr(spec, cpu_sample)]
+        O.assign(Xs[:2000], C, lam)                     # warm-up (BLAS threads, page faults)
+        t0 = time.perf_counter()
+        O.assign(Xs, C, lam)
+        dt = time.perf_counter() - t0
+        cpu = {"value": len(Xs) / dt, "unit": "points/s", "cores": int(threads), "kind": "oracle",
+               "sample": f"{len(Xs)} uniformly sampled rows of the workload, FP64 screened oracle, "
+                         f"lambda {lam}, {dt:.2f} s wall"}
+    return cpu, trend_out, rec
 
 
 def time_form(soar, torch, Xg, Cg, lam, prec, steps, warmup, n, d, K):
@@ -176,7 +216,8 @@ def serve_main(args):
     from synth import WORKLOADS, gen_mixture, gen_queries
 
     spec = dataclasses.replace(WORKLOADS["mix4096_n1m_d128"]["spec"], n=args.serve_base)
-    K, prec, lam = args.serve_K, args.serve_precision, args.lam
+    K, prec = args.serve_K, args.serve_precision
+    lam = float(args.lam.split(",")[0]) if args.lam else 1.0
     rates = [float(r) for r in args.serve_rates.split(",") if r.strip()]
     CH = 1 << 20
     nch = (spec.n + CH - 1) // CH
@@ -333,9 +374,8 @@ def main():
         print(json.dumps({"mode": "copy", "bytes_read_per_copy": nbytes,
                           "bytes_written_per_copy": nbytes, "copies": args.steps}))
         return
-    import torch
-    import paper_2404_00774_amd as soar
-    from synth import WORKLOADS, gen_mixture, sample_rows
+    from concurrent.futures import ThreadPoolExecutor
+    from synth import WORKLOADS, gen_mixture, gen_queries, sample_rows
 
     w = WORKLOADS[args.workload]
     spec, K, iters = w["spec"], w["K"], w["iters"]
@@ -344,8 +384,21 @@ def main():
         spec = dataclasses.replace(spec, n=min(args.rows, spec.n))
     n, d = spec.n, spec.d
     precs = [p.strip() for p in args.precision.split(",") if p.strip()]
+    if args.lam:
+        lams = [float(v) for v in args.lam.split(",") if v.strip()]
+    else:
+        lams = sorted(w["lambdas"], key=lambda v: (v != 1.0, v))
+    # inputs are drawn before the GPU is touched (threads: numpy releases the GIL)
     print(f"[bench] generating {args.workload}: n={n} d={d} K={K}", file=sys.stderr, flush=True)
-    X = gen_mixture(spec)
+    CH = 1 << 20
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        X = np.concatenate(list(ex.map(lambda k: gen_mixture(spec, k * CH, min(n, (k + 1) * CH)),
+                                       range((n + CH - 1) // CH))))
+    nq = min(args.recall_queries, w.get("queries", 0))
+    Q = gen_queries(spec, nq) if nq else None
+
+    import torch
+    import paper_2404_00774_amd as soar
     dev = torch.device("cuda:0")
     Xg = torch.from_numpy(X).to(dev)
     torch.cuda.synchronize()
@@ -376,43 +429,53 @@ def main():
     C = Cg.cpu().numpy()
     idx = sample_rows(spec, args.judge_sample)
 
-    forms = {}
-    for k, prec in enumerate(precs):
-        steps, warm = (args.steps, args.warmup) if k == 0 else (args.form_steps, 1)
-        print(f"[bench] {prec}: warmup {warm}, timing {steps} steps", file=sys.stderr, flush=True)
-        r = time_form(soar, torch, Xg, Cg, args.lam, prec, steps, warm, n, d, K)
-        r["out"] = tuple(a[idx] for a in r["out"])
-        print(f"[bench] {prec}: {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-        alg = 4.0 * n * K * d
-        r["value"] = n / (r["ms_per_step"] / 1e3)
-        r["algorithmic_tflops"] = alg / (r["kernel_ms"] / 1e3) / 1e12
-        r["mfma_peak_frac"] = r["algorithmic_tflops"] / PEAKS_TFLOPS[prec]
-        r["steps"] = steps
-        forms[prec] = r
-    if "fp32" in forms:
-        for prec, r in forms.items():
-            r["speedup_vs_fp32"] = forms["fp32"]["ms_per_step"] / r["ms_per_step"]
+    sweep, full = {}, {}
+    alg = 4.0 * n * K * d
+    for li, lam in enumerate(lams):
+        forms = {}
+        for k, prec in enumerate(precs):
+            first = li == 0 and k == 0
+            steps, warm = (args.steps, args.warmup) if first else (args.form_steps, 1)
+            print(f"[bench] lambda {lam} {prec}: warmup {warm}, timing {steps} steps",
+                  file=sys.stderr, flush=True)
+            r = time_form(soar, torch, Xg, Cg, lam, prec, steps, warm, n, d, K)
+            outs = r.pop("out")
+            if k == 0 and Q is not None:
+                full[lam] = (outs[0].copy(), outs[1].copy())
+            r["out"] = tuple(a[idx] for a in outs)
+            print(f"[bench] lambda {lam} {prec}: {r['ms_per_step']:.3f} ms/step", file=sys.stderr,
+                  flush=True)
+            r["value"] = n / (r["ms_per_step"] / 1e3)
+            r["algorithmic_tflops"] = alg / (r["kernel_ms"] / 1e3) / 1e12
+            r["mfma_peak_frac"] = r["algorithmic_tflops"] / PEAKS_TFLOPS[prec]
+            r["steps"] = steps
+            forms[prec] = r
+        if "fp32" in forms:
+            for prec, r in forms.items():
+                r["speedup_vs_fp32"] = forms["fp32"]["ms_per_step"] / r["ms_per_step"]
+        sweep[lams[li]] = forms
 
-    head = forms[precs[0]]
-    alg_flops = 4.0 * n * K * d
+    head = sweep[lams[0]][precs[0]]
     roofline = {"bound": "mfma", "achieved": head["algorithmic_tflops"],
                 "peak": PEAKS_TFLOPS[precs[0]], "unit": "TFLOP/s", "frac": head["mfma_peak_frac"],
                 "traffic": measured_traffic(precs[0], args.workload) if not args.rows else None,
                 "kernel": KERNEL[precs[0]], "kernel_ms": head["kernel_ms"],
-                "algorithmic_flops_per_launch": alg_flops}
+                "algorithmic_flops_per_launch": alg}
 
-    print(f"[bench] oracle leg: judging {len(idx)} rows per form"
-          + ("" if args.no_cpu_baseline else f", timing {args.cpu_sample} rows"),
-          file=sys.stderr, flush=True)
-    cpu = cpu_baseline_leg(X, C, args.lam, spec, 0 if args.no_cpu_baseline else args.cpu_sample,
-                           idx, forms)
+    print(f"[bench] oracle leg: judging {len(idx)} rows per form and lambda"
+          + ("" if args.no_cpu_baseline else f", timing {args.cpu_sample} rows")
+          + (f", recall@10 over {nq} queries" if nq else ""), file=sys.stderr, flush=True)
+    recall = {"queries": Q, "ts": (1, 2, 4, 8, 16, 32, 64, 128), "assign": full} if nq else None
+    cpu, trend, rec = cpu_baseline_leg(X, C, lams, spec,
+                                       0 if args.no_cpu_baseline else args.cpu_sample, idx,
+                                       sweep, recall)
 
-    rec = {
+    rec_out = {
         "metric": METRIC, "value": head["value"], "unit": "points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[precs[0]], "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "d": d, "K": K, "lambda": args.lam,
+        "config": {"workload": args.workload, "n": n, "d": d, "K": K, "lambda": lams[0],
                    "precision": precs[0], "mixture_components": spec.components,
                    "lloyd_iters": iters,
                    "codebook": ("k-means++ + Lloyd on the same GPU" if args.codebook == "train"
@@ -420,11 +483,14 @@ def main():
         "mfma_peak_frac_algorithmic": head["mfma_peak_frac"],
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "forms": forms,
+        "forms": sweep[lams[0]],
+        "lambda_sweep": {str(l): sweep[l] for l in lams[1:]},
+        "lambda_trend": trend,
+        "recall_at_10": rec,
         "train": {"kmeanspp_s": t_kpp, "kmeanspp_rows": int(sub if sub and sub < n else n),
                   "lloyd_s": t_lloyd, "inertia_first": inertia[0], "inertia_last": inertia[-1]},
     }
-    print(json.dumps(rec))
+    print(json.dumps(rec_out))
 
 
 if __name__ == "__main__":

@@ -15,13 +15,15 @@
 // dropped)
 //     primary: ||c||^2 - 2<x,c>
 //     spill:   ||c||^2 - 2<x,c> + lambda/||r||^2 * (<r,c> - <r,x>)^2,  masked at j = pi
-// and every lane keeps, per row, its two best values with their indices and its third-best value
-// over the columns it sees.  With delta a proven bound on the expansion's rounding error, every
-// centroid whose value lies within 2*delta of the row minimum is a candidate for the exact
-// arg-min; the lanes' two bests cover all of them unless some lane's third best is itself inside
-// that band, in which case the row is handed to the exact full scan.  Candidates are re-scored by
-// direct differences in FP32 (16 partial sums per row), and candidates within the near-tie gap of
-// the best are re-decided in FP64.  Ties go to the lowest index.
+// With delta_j = A_row (||x|| + ||c_j||)^2 a proven bound on the rounding error of centroid j's
+// expanded value v_j (A_row from d, lambda and, in the Gram form, ||x|| + ||c_pi|| and ||r||),
+// lo_j = v_j - delta_j and hi_j = v_j + delta_j bracket the exact value, so the exact arg-min has
+// lo_j <= U = min_j hi_j.  Every lane keeps, per row, the two smallest lo with their indices, the
+// third smallest lo, and the smallest hi over the columns it sees; the candidates are the
+// tracked entries with lo <= U, and they are complete unless some lane's third smallest lo is
+// also <= U, in which case the row is handed to the exact full scan.  Candidates are re-scored
+// by direct differences in FP32 (16 partial sums per row), and candidates within the near-tie
+// gap of the best are re-decided in FP64.  Ties go to the lowest index.
 #include "common.h"
 #include "kernels.h"
 
@@ -32,12 +34,14 @@ namespace soar {
 //   [BN rows of DP floats, row stride LDW = DP + 4 (the pad keeps the B-operand reads of the 16
 //    lanes of a group on distinct banks); zeros past d and past K]
 //   [BN floats ||c_j||^2, +inf past K]
+//   [BN floats ||c_j||, 0 past K]
 // Each record is copied with NI whole wave-group copies (4 waves x 64 lanes x 16 bytes).
 template <int DP, int BN>
 struct F32Rec {
   static constexpr int LDW = DP + 4;
   static constexpr int CN_OFF = BN * LDW * 4;
-  static constexpr int BYTES = CN_OFF + BN * 4;
+  static constexpr int SN_OFF = CN_OFF + BN * 4;
+  static constexpr int BYTES = SN_OFF + BN * 4;
   static constexpr int NI = (BYTES + 4095) / 4096;
   static constexpr int STAGE = NI * 4096;
 };
@@ -158,9 +162,10 @@ template <int DP, int BN, bool CH, bool VEC, bool SP, bool GR = false>
 __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch, int tid,
                                       int64_t row, bool ok, int pia, float (&xa)[DP / 4],
                                       float (&ra)[DP / 4], const float (&lp)[4],
-                                      const float (&av)[4], const int (&pr)[4], float (&b1)[4],
+                                      const float (&av)[4], const int (&pr)[4],
+                                      const float (&xv)[4], const float (&Av)[4], float (&b1)[4],
                                       int (&i1)[4], float (&b2)[4], int (&i2)[4],
-                                      float (&b3)[4]) {
+                                      float (&b3)[4], float (&U)[4]) {
   using R = F32Rec<DP, BN>;
   constexpr int KS = DP / 4, LDW = R::LDW, NB = BN / 16;
   static_assert(!GR || (SP && !CH), "Gram form: spill sweep of resident rows only");
@@ -248,10 +253,12 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
     }
     if (!CH || ch == nch - 1) {
       const float* scn = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE + R::CN_OFF);
+      const float* ssn = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE + R::SN_OFF);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = t * BN + b * 16 + c16;
         const float cnv = scn[b * 16 + c16];
+        const float snv = ssn[b * 16 + c16];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           float val;
@@ -264,13 +271,18 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
           } else {
             val = fmaf(-2.f, accS[b][v], cnv);
           }
-          // keep (b1, i1) <= (b2, i2) <= b3 over the columns seen so far
-          const bool lt1 = val < b1[v], lt2 = val < b2[v];
-          b3[v] = fminf(b3[v], fmaxf(b2[v], val));
+          // bracket the exact value, keep the smallest upper end and, on the lower ends,
+          // (b1, i1) <= (b2, i2) <= b3 over the columns seen so far
+          const float tt = xv[v] + snv;
+          const float dl = Av[v] * tt * tt;
+          const float lo = val - dl;
+          U[v] = fminf(U[v], val + dl);
+          const bool lt1 = lo < b1[v], lt2 = lo < b2[v];
+          b3[v] = fminf(b3[v], fmaxf(b2[v], lo));
           i2[v] = lt1 ? i1[v] : (lt2 ? j : i2[v]);
-          b2[v] = fminf(b2[v], fmaxf(b1[v], val));
+          b2[v] = fminf(b2[v], fmaxf(b1[v], lo));
           i1[v] = lt1 ? j : i1[v];
-          b1[v] = fminf(b1[v], val);
+          b1[v] = fminf(b1[v], lo);
         }
       }
     }
@@ -294,7 +306,8 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
 }
 
 struct RowShared {
-  float band[4][16];   // per wave, per row: 2*delta for the current pass
+  float xn[4][16];     // per wave, per row: ||x||
+  float A[4][16];      // error coefficient of the current pass: delta_j = A (||x|| + ||c_j||)^2
   float lp[4][16];     // lambda / ||r||^2 (0 when r = 0)
   float av[4][16];     // <r, x>
   int pi[4][16];       // primary (-1: the row went to the full scan)
@@ -311,16 +324,16 @@ struct CandShared {
 __device__ __forceinline__ void publish_candidates(RowShared& S, CandShared& CS, int w, int lane,
                                                    const float (&b1)[4], const int (&i1)[4],
                                                    const float (&b2)[4], const int (&i2)[4],
-                                                   const float (&b3)[4]) {
+                                                   const float (&b3)[4], const float (&U)[4]) {
   const int q = lane >> 4, c16 = lane & 15;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int r = 4 * q + v;
-    float m = b1[v];
-    int mj = i1[v];
-    argmin16(m, mj);
-    const float thr = m + S.band[w][r];
-    const bool finite_min = m < kInf;
+    // the row's smallest upper end: no centroid with a larger lower end can be the arg-min
+    float thr = U[v];
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) thr = fminf(thr, __shfl_xor(thr, off));
+    const bool finite_min = thr < kInf;
     const bool sat = b3[v] <= thr;
     const bool c1 = finite_min && b1[v] <= thr;
     const bool c2 = finite_min && b2[v] <= thr;   // implies c1
@@ -399,7 +412,6 @@ void assign_f32_kernel(AssignParams P) {
   const int64_t row = (int64_t)blockIdx.x * 64 + w * 16 + c16;  // A-layout row of this lane
   const bool ok = row < n;
   const int nch = CH ? (P.d + DP - 1) / DP : 1;
-  const float cmax = sqrtf(__uint_as_float(P.counters[CNT_CMAX2]));
 
   float xa[KS], ra[KS];
   bool fin = true;
@@ -416,21 +428,25 @@ void assign_f32_kernel(AssignParams P) {
   }
   if (!fin) atomicOr(&P.counters[CNT_NONFINITE], 1u);
   const float xnorm = sqrtf(sum_quad_f((n0 + n1) + (n2 + n3)));
-  const float scale2 = (xnorm + cmax) * (xnorm + cmax);
-  if (q == 0) S.band[w][c16] = P.band_p * scale2;
+  if (q == 0) {
+    S.xn[w][c16] = xnorm;
+    S.A[w][c16] = 0.5f * P.band_p;
+  }
   __syncthreads();
 
   // ---------------- primary pass ----------------
-  float b1[4], b2[4], b3[4], lp[4], av[4];
+  float b1[4], b2[4], b3[4], U[4], lp[4], av[4], xv[4], Av[4];
   int i1[4], i2[4], pr[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    b1[v] = b2[v] = b3[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
+    b1[v] = b2[v] = b3[v] = U[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
     lp[v] = av[v] = 0.f; pr[v] = -1;
+    xv[v] = S.xn[w][4 * q + v];
+    Av[v] = S.A[w][4 * q + v];
   }
-  sweep<DP, BN, CH, VEC, false>(P, ring, nch, tid, row, ok, -1, xa, ra, lp, av, pr, b1, i1, b2,
-                                i2, b3);
-  publish_candidates(S, CS, w, lane, b1, i1, b2, i2, b3);
+  sweep<DP, BN, CH, VEC, false>(P, ring, nch, tid, row, ok, -1, xa, ra, lp, av, pr, xv, Av, b1,
+                                i1, b2, i2, b3, U);
+  publish_candidates(S, CS, w, lane, b1, i1, b2, i2, b3, U);
   __syncthreads();
 
   int pi = -1;
@@ -475,27 +491,36 @@ void assign_f32_kernel(AssignParams P) {
     S.pi[w][c16] = pi;
     S.lp[w][c16] = rr > 0.f ? P.lam / rr : 0.f;
     S.av[w][c16] = a;
-    float band = P.band_s * scale2;
+    float A = 0.5f * P.band_s;
     if (GR && rr > 0.f) {
+      // Gram form: <r, c_j> carries an error of gamma (||x|| + ||c_pi||) (||x|| + ||c_j||)
+      const float Pn = xnorm + sqrtf(P.cnorm[pi]);
       const float inv = 1.f / sqrtf(rr);
-      band += P.band_g1 * scale2 * (xnorm + cmax) * inv + P.band_g2 * scale2 * scale2 * inv * inv;
+      A += 0.5f * (P.band_g1 * Pn * inv + P.band_g2 * Pn * Pn * inv * inv);
     }
-    S.band[w][c16] = band;
+    S.A[w][c16] = A;
   }
   __syncthreads();
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int r = 4 * q + v;
-    lp[v] = S.lp[w][r]; av[v] = S.av[w][r]; pr[v] = S.pi[w][r];
-    b1[v] = b2[v] = b3[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
+    lp[v] = S.lp[w][r]; av[v] = S.av[w][r]; pr[v] = S.pi[w][r]; Av[v] = S.A[w][r];
+    b1[v] = b2[v] = b3[v] = U[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
   }
 
   // ---------------- spill pass ----------------
-  sweep<DP, BN, CH, VEC, true, GR>(P, ring, nch, tid, row, ok, pi, xa, ra, lp, av, pr, b1, i1,
-                                   b2, i2, b3);
-  publish_candidates(S, CS, w, lane, b1, i1, b2, i2, b3);
+  sweep<DP, BN, CH, VEC, true, GR>(P, ring, nch, tid, row, ok, pi, xa, ra, lp, av, pr, xv, Av,
+                                   b1, i1, b2, i2, b3, U);
+  publish_candidates(S, CS, w, lane, b1, i1, b2, i2, b3, U);
   __syncthreads();
   if (pi < 0) return;  // full-scan rows are finished by the full-scan kernel
+  if constexpr (GR) {
+    // the Gram sweep does not read R: form it again here rather than hold it across the sweep
+    float cp[KS];
+    load_rec<KS>(rec_row<DP, BN>(P.Crec, nch, pi, 0) + q * KS, cp);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) ra[s] = xa[s] - cp[s];
+  }
   bool ssat = S.sat[w][c16] != 0;
   int sj = -1;
   float sl = 0.f;
@@ -764,7 +789,10 @@ __global__ __launch_bounds__(256) void pack_f32_kernel(const float* __restrict__
     if (k + 3 < d) v.w = c[k + 3];
   }
   *reinterpret_cast<v4f*>(base + (jl * R::LDW + f * 4) * 4) = v;
-  if (f == 0) *reinterpret_cast<float*>(base + R::CN_OFF + jl * 4) = j < K ? cnorm[j] : kInf;
+  if (f == 0) {
+    *reinterpret_cast<float*>(base + R::CN_OFF + jl * 4) = j < K ? cnorm[j] : kInf;
+    *reinterpret_cast<float*>(base + R::SN_OFF + jl * 4) = j < K ? sqrtf(cnorm[j]) : 0.f;
+  }
 }
 
 // G = C C^T: a 64 x 64 block of G per workgroup, 4 x 4 outputs per thread, the two 64-row

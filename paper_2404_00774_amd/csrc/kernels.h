@@ -16,10 +16,12 @@ struct AssignParams {
   unsigned* counters;   // CNT_* words
   float lam;
   float tie_rel;        // relative gap under which FP32 re-scores are re-decided in FP64
-  float band_p;         // primary screen: band = band_p * (||x|| + max||c||)^2
-  float band_s;         // spill screen:   band = band_s * (||x|| + max||c||)^2
-  // Gram form of the spill screen (G non-null): <r, c_j> = <x, c_j> - G[pi][j], band widened by
-  // band_g1 * E^1.5 / ||r|| + band_g2 * E^2 / ||r||^2 with E = (||x|| + max||c||)^2
+  // Screens: twice the rounding-error bound of centroid j's expanded value is
+  //   primary band_p * (||x|| + ||c_j||)^2,   spill band_s * (||x|| + ||c_j||)^2
+  float band_p;
+  float band_s;
+  // Gram form of the spill screen (G non-null): <r, c_j> = <x, c_j> - G[pi][j]; the spill band
+  // gains (band_g1 P / ||r|| + band_g2 P^2 / ||r||^2) (||x|| + ||c_j||)^2, P = ||x|| + ||c_pi||
   const float* G = nullptr;   // [K x K] C C^T, or null
   float band_g1 = 0.f, band_g2 = 0.f;
   int32_t* primary;

@@ -126,20 +126,21 @@ AssignLayout layout_assign(void* ws, int64_t n, int32_t d, int32_t K) {
 
 namespace soar {
 
-// Screening bands: twice the rounding-error bound of the expanded ranking values, with a 10%
-// margin.  With scale = ||x|| + max||c||:
-//   primary  |(||c||^2 - 2<x,c>)~ - exact| <= gamma_{d+2} scale^2 (norm, dot product, fma);
-//   spill    adds the penalty: lambda/||r||^2 * e^2 with |e| <= ||r|| ||x - c|| and |e~ - e| <=
-//            gamma_{d+2} ||r|| scale, so its error is <= 3 lambda gamma_{d+4} scale^2, plus the
-//            final roundings; in all <= (1 + 3 lambda) gamma_{d+5} scale^2.
+// Screening bands: twice the rounding-error bound of centroid j's expanded ranking value, with a
+// 10% margin.  With T_j = ||x|| + ||c_j||:
+//   primary  |(||c||^2 - 2<x,c>)~ - exact| <= gamma_{d+2} T_j^2 (norm, dot product, fma);
+//   spill    adds the penalty: lambda/||r||^2 * e^2 with |e| <= ||r|| ||x - c_j|| <= ||r|| T_j
+//            and |e~ - e| <= gamma_{d+2} ||r|| T_j, so its error is <= 3 lambda gamma_{d+4} T_j^2,
+//            plus the final roundings; in all <= (1 + 3 lambda) gamma_{d+5} T_j^2.
 float band_coef_primary(int d) { return 2.2f * (float)(d + 2) * kU32; }
 float band_coef_spill(int d, float lam) {
   return 2.2f * (1.f + 3.f * lam) * (float)(d + 5) * kU32;
 }
-// Gram form of the spill screen: <r, c> is formed as <x, c> - <c_pi, c>, whose error is
-// gamma_{d+2} E with E = (||x|| + max||c||)^2 instead of gamma_{d+2} ||r|| sqrt(E).  Through
-// lambda/||r||^2 * e^2 with |e| <= ||r|| sqrt(E) that adds 2 lambda gamma_{d+2} E^1.5 / ||r|| and
-// lambda gamma_{d+2}^2 E^2 / ||r||^2 to the error bound (again doubled, with a 10% margin).
+// Gram form of the spill screen: <r, c_j> is formed as <x, c_j> - <c_pi, c_j>, whose error (with
+// that of <r, x>) is gamma_{d+2} P T_j, P = ||x|| + ||c_pi|| (>= ||r||), instead of
+// gamma_{d+2} ||r|| T_j.  Through lambda/||r||^2 * e^2 with |e| <= ||r|| T_j that adds
+// 2 lambda gamma_{d+2} P T_j^2 / ||r|| and lambda gamma_{d+2}^2 P^2 T_j^2 / ||r||^2 to the error
+// bound (again doubled, with a 10% margin).
 float band_coef_gram1(int d, float lam) { return 2.2f * 2.f * lam * (float)(d + 2) * kU32; }
 float band_coef_gram2(int d, float lam) {
   const float g = (float)(d + 2) * kU32;

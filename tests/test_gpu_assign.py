@@ -88,6 +88,19 @@ def test_integer_ties_duplicates_and_zero_residual():
         assert res[4]["rows_full_scan"] > 0       # the duplicates force the exact full scan
 
 
+@pytest.mark.parametrize("lam", [0.5, 1.5])
+def test_heavy_tailed_norms_d768(lam):
+    """Unnormalised rows with lognormal norms at d = 768 (chunked rows, direct spill form): the
+    screening bounds are per centroid, so rows far from the largest centroids stay screened."""
+    spec = MixtureSpec(6000, 768, 512, ("loguniform", 0.05, 0.5), ("lognormal", 0.5), 4)
+    X = gen_mixture(spec)
+    C = X[np.random.default_rng(2).choice(len(X), 5000, replace=False)] * 0.97
+    print(f"heavy tails d768 lam={lam}", flush=True)
+    res = _run(X, C, lam)
+    _check(X, C, lam, res)
+    assert res[4]["rows_full_scan"] <= len(X) // 100, res[4]
+
+
 @pytest.mark.parametrize("lam", [1.0, 1.5])
 def test_small_residuals(lam):
     """Rows at distances 1e-2 .. 1e-6 from their centroid: the Gram form's screening band grows
