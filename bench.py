@@ -36,9 +36,9 @@ PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2516.0, "fp8": 5032.0}   # MI355X dense M
 COPY_SCALE = {"fetch": 1048576.0 / 524302.5, "write": 1.0}
 TRAFFIC = {
     ("fp32", "mix4096_n1m_d128"): dict(
-        fetch_kib=2846965.8, write_kib=15648.1,
+        fetch_kib=2901296.8, write_kib=15648.0,
         source="paper_2404_00774_amd/csrc/assign_fp32.hip",
-        sha256="81777218c670ce0f7080c5fab4e5f4afe06fa460330b0549923743f37a1253db"),
+        sha256="476a4b353230aca8f3a42e08c9542bb3459ac4787f6b67d04a05a1437f1cc5b4"),
 }
 
 

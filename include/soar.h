@@ -111,7 +111,7 @@ soar_status soar_train_workspace_size(int64_t n, int32_t d, int32_t K, size_t* b
  * (m, 0, 0, 0) and key (seed mod 2^32, seed >> 32).  If sum(D^2) = 0 the lowest-index row not yet
  * chosen is taken.
  *   C_out [K x d] (device), rows_out [K] (device, nullable): the chosen rows.
- * Requires 1 <= K <= n.
+ * Requires 1 <= K <= n and d <= 1024 (larger d: SOAR_E_UNSUPPORTED).
  */
 soar_status soar_kmeanspp(const float* X, int64_t n, int32_t d, int32_t K, uint64_t seed,
                           float* C_out, int32_t* rows_out, void* workspace, size_t ws_bytes,

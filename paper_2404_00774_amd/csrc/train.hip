@@ -136,37 +136,60 @@ __global__ __launch_bounds__(256) void scatter_rows_kernel(const int32_t* __rest
   }
 }
 
-// One workgroup per cluster: exact fixed-point sums of its member rows, then the mean.
+// One workgroup per cluster: exact fixed-point sums of its member rows, then the mean.  Threads
+// take 4 consecutive dimensions each (float4 loads when the
+// rows allow), `slots` member rows are summed side by side and every thread keeps four rows'
+// loads in flight; the int64 fixed-point sums make the result independent of that order.
 __global__ __launch_bounds__(256) void segment_mean_kernel(
     const float* __restrict__ X, int d, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ members, const float* C_prev, float* C_out, int32_t* counts_out,
-    int fbits) {
-  __shared__ long long part[256];
+    int fbits, bool vec) {
+  __shared__ long long part[256][4];
   const int j = blockIdx.x;
   const int beg = offsets[j], end = offsets[j + 1];
   const int cnt = end - beg;
-  const int tpr = d < 256 ? d : 256;            // threads per row
+  const int q4 = (d + 3) / 4;                    // 4-dimension groups per row
+  const int tpr = q4 < 256 ? q4 : 256;           // threads per row
   const int slots = 256 / tpr;                   // rows summed side by side
   const int t = threadIdx.x, slot = t / tpr, kk = t % tpr;
   const bool active = slot < slots;
   if (t == 0 && counts_out) counts_out[j] = cnt;
-  for (int k0 = 0; k0 < d; k0 += tpr) {
-    const int k = k0 + kk;
-    long long acc = 0;
+  for (int g0 = 0; g0 < q4; g0 += tpr) {
+    const int k = (g0 + kk) * 4;
+    long long acc[4] = {0, 0, 0, 0};
     if (active && k < d && cnt > 0) {
-      for (int m = beg + slot; m < end; m += slots) {
-        const float v = X[(int64_t)members[m] * d + k];
-        acc += __float2ll_rn(ldexpf(v, fbits));
+      auto add_row = [&](int m) {
+        const float* xr = X + (int64_t)members[m] * d + k;
+        float v[4];
+        if (vec) {
+          const v4f t4 = *reinterpret_cast<const v4f*>(xr);
+          v[0] = t4.x; v[1] = t4.y; v[2] = t4.z; v[3] = t4.w;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = k + e < d ? xr[e] : 0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] += __float2ll_rn(ldexpf(v[e], fbits));
+      };
+      int m = beg + slot;
+      for (; m + 3 * slots < end; m += 4 * slots) {
+        add_row(m); add_row(m + slots); add_row(m + 2 * slots); add_row(m + 3 * slots);
       }
+      for (; m < end; m += slots) add_row(m);
     }
-    part[t] = acc;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) part[t][e] = acc[e];
     __syncthreads();
     if (active && slot == 0 && k < d) {
-      long long s = 0;
-      for (int sl = 0; sl < slots; ++sl) s += part[sl * tpr + kk];
-      const float c = cnt > 0 ? ldexpf(__ll2float_rn(s) / (float)cnt, -fbits)
-                              : C_prev[(int64_t)j * d + k];
-      C_out[(int64_t)j * d + k] = c;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (k + e >= d) break;
+        long long s = 0;
+        for (int sl = 0; sl < slots; ++sl) s += part[sl * tpr + kk][e];
+        const float c = cnt > 0 ? ldexpf(__ll2float_rn(s) / (float)cnt, -fbits)
+                                : C_prev[(int64_t)j * d + k + e];
+        C_out[(int64_t)j * d + k + e] = c;
+      }
     }
     __syncthreads();
   }
@@ -175,40 +198,61 @@ __global__ __launch_bounds__(256) void segment_mean_kernel(
 // ---------------------------------------------------------------------------------------------
 // k-means++
 // ---------------------------------------------------------------------------------------------
-constexpr int KPP_ROWS = 1024;   // rows per block in the D^2 update / prefix search
+constexpr int KPP_ROWS = 1024;     // rows per block in the D^2 update / prefix search
+constexpr int kMaxTrainD = 1024;   // widest rows k-means++ takes (its chosen row sits in LDS)
 
-// D2[i] = min(D2[i], ||x_i - x_c||^2) (or = when first) and per-block partial sums.
-// 16 lanes per row, each lane a strided slice of the dimensions.
+// D2[i] = min(D2[i], ||x_i - x_c||^2) (or = when first) for the row chosen last, and per-block partial sums of D^2 (fixed order: each
+// thread adds its rows grp, grp + 16, ... in turn, then a tree over the block).  A 16-lane group
+// takes a row with its lanes across the dimensions (float4 loads when the rows allow) and keeps
+// four rows in flight; the chosen row sits in LDS.
 __global__ __launch_bounds__(256) void kpp_update_kernel(const float* __restrict__ X, int64_t n,
                                                          int d, const int32_t* cur, bool first,
                                                          float* __restrict__ D2,
-                                                         float* __restrict__ partial) {
+                                                         float* __restrict__ partial, bool vec) {
   __shared__ float red[256];
+  __shared__ __attribute__((aligned(16))) float sxc[kMaxTrainD];
   const int c = *cur;
-  const float* xc = X + (int64_t)c * d;
+  for (int k = threadIdx.x; k < d; k += 256) sxc[k] = X[(int64_t)c * d + k];
+  __syncthreads();
   const int lane16 = threadIdx.x & 15, grp = threadIdx.x >> 4;   // 16 row groups per block
   const int64_t base = (int64_t)blockIdx.x * KPP_ROWS;
-  float local = 0.f;
-  for (int r = grp; r < KPP_ROWS; r += 16) {
-    const int64_t i = base + r;
-    const bool ok = i < n;
+  auto row_d2 = [&](int64_t i) -> float {
     float a0 = 0.f, a1 = 0.f;
-    if (ok) {
+    if (i < n) {
       const float* xi = X + i * d;
-      int k = lane16;
-      for (; k + 16 < d; k += 32) {
-        const float e0 = xi[k] - xc[k], e1 = xi[k + 16] - xc[k + 16];
-        a0 = fmaf(e0, e0, a0); a1 = fmaf(e1, e1, a1);
+      if (vec) {
+        for (int k = 4 * lane16; k < d; k += 64) {
+          const v4f xv = *reinterpret_cast<const v4f*>(xi + k);
+          const v4f cv = *reinterpret_cast<const v4f*>(sxc + k);
+          const float e0 = xv.x - cv.x, e1 = xv.y - cv.y, e2 = xv.z - cv.z, e3 = xv.w - cv.w;
+          a0 = fmaf(e0, e0, a0); a1 = fmaf(e1, e1, a1);
+          a0 = fmaf(e2, e2, a0); a1 = fmaf(e3, e3, a1);
+        }
+      } else {
+        for (int k = lane16; k < d; k += 16) {
+          const float e0 = xi[k] - sxc[k];
+          a0 = fmaf(e0, e0, a0);
+        }
       }
-      if (k < d) { const float e0 = xi[k] - xc[k]; a0 = fmaf(e0, e0, a0); }
     }
     float s = a0 + a1;
 #pragma unroll
     for (int off = 1; off < 16; off <<= 1) s += __shfl_xor(s, off);
-    if (ok && lane16 == 0) {
-      const float v = first ? s : fminf(D2[i], s);
-      D2[i] = v;
-      local += v;
+    return s;
+  };
+  float local = 0.f;
+  for (int r0 = grp; r0 < KPP_ROWS; r0 += 64) {
+    float sv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sv[u] = row_d2(base + r0 + 16 * u);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = base + r0 + 16 * u;
+      if (i < n && lane16 == 0) {
+        const float v = first ? sv[u] : fminf(D2[i], sv[u]);
+        D2[i] = v;
+        local += v;
+      }
     }
   }
   red[threadIdx.x] = local;
@@ -403,8 +447,9 @@ static soar_status lloyd_update_impl(const float* X, int64_t n, int d, const int
                      L.cursor);
   hipLaunchKernelGGL(scatter_rows_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, labels,
                      n, K, L.cursor, L.members);
+  const bool vec = d % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
   hipLaunchKernelGGL(segment_mean_kernel, dim3((unsigned)K), dim3(256), 0, st, X, d, L.offsets,
-                     L.members, C_prev, C_out, counts, fbits);
+                     L.members, C_prev, C_out, counts, fbits, vec);
   return hipGetLastError() == hipSuccess ? SOAR_OK : SOAR_E_DEVICE;
 }
 
@@ -427,6 +472,7 @@ static soar_status kmeanspp_impl(const float* X, int64_t n, int d, int K, uint64
                                  float* C_out, int32_t* rows_out, const TrainLayout& L,
                                  hipStream_t st) {
   const int nblocks = (int)((n + KPP_ROWS - 1) / KPP_ROWS);
+  const bool vec = d % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
   float* partial = L.partial;
   hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n, 1024, 4096)), dim3(256), 0, st,
                      (int32_t*)L.chosen, (int64_t)((n + 3) / 4), 0);
@@ -434,7 +480,7 @@ static soar_status kmeanspp_impl(const float* X, int64_t n, int d, int K, uint64
   for (int m = 0; m < K; ++m) {
     if (m > 0)
       hipLaunchKernelGGL(kpp_update_kernel, dim3((unsigned)nblocks), dim3(256), 0, st, X, n, d,
-                         L.cur, m == 1, L.dist, partial);
+                         L.cur, m == 1, L.dist, partial, vec);
     hipLaunchKernelGGL(kpp_select_kernel, dim3(1), dim3(1024), 0, st, X, n, d, L.dist, partial,
                        nblocks, m, seed, L.cur, L.chosen, C_out, rows);
   }
@@ -488,6 +534,7 @@ soar_status soar_kmeanspp(const float* X, int64_t n, int32_t d, int32_t K, uint6
   soar_status s = check_train_args(X, n, d, K, workspace, ws_bytes, false);
   if (s != SOAR_OK) return s;
   if (!C_out) return SOAR_E_INVAL;
+  if (d > kMaxTrainD) return SOAR_E_UNSUPPORTED;   // the chosen row is staged in LDS
   hipStream_t st = static_cast<hipStream_t>(stream);
   TrainLayout L = layout_train(workspace, n, d, K);
   int fb;
