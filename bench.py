@@ -54,7 +54,8 @@ def measured_traffic(prec, workload):
     return (t["fetch_kib"] * COPY_SCALE["fetch"] + t["write_kib"] * COPY_SCALE["write"]) * 1024.0
 METRIC = "SOAR-assigned points/sec and % MFMA peak, BF16/FP8 vs FP32 at ≤1e-3 regret"
 DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8_e4m3"}
-KERNEL = {"fp32": "assign_f32_kernel (primary + residual + spill, one kernel)",
+KERNEL = {"fp32": "assign_f32_kernel (primary) + grouping by primary + assign_f32_spill_grouped "
+                  "(spill); the direct form runs primary and spill in assign_f32_kernel",
           "bf16": "lowp_sweep_kernel x2 (primary sweep + spill sweep)",
           "fp8": "lowp_sweep_kernel x2 (primary sweep + spill sweep)"}
 

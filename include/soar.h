@@ -56,6 +56,12 @@ typedef enum soar_precision {
 } soar_precision;
 
 #define SOAR_ASYNC 1u       /* flags bit: enqueue only; errors surface on the next blocking call */
+/* Form of the spill sweep (results are the same; only the work differs).  The grouped form sorts
+   the rows by primary and takes <c_pi, c_j> from the same MFMA stream as <x, c_j>; the direct
+   form runs a second stream over R = X - C[pi].  Without either bit the library picks grouped
+   when n >= 8 K (FP32: rows of at most 256 dimensions).  Both bits: SOAR_E_INVAL. */
+#define SOAR_SPILL_GROUPED 2u
+#define SOAR_SPILL_DIRECT 4u
 
 /* Options of soar_assign.  Set struct_size = sizeof(soar_assign_opts). */
 typedef struct soar_assign_opts {
@@ -65,14 +71,16 @@ typedef struct soar_assign_opts {
   int32_t topk;             /* BF16/FP8: candidates re-scored in FP32 per row (0 = 8, max 8)     */
   float near_tie_rel;       /* relative gap under which FP32 re-scores are decided in FP64
                                (0 = 1e-5)                                                        */
-  uint32_t flags;           /* SOAR_ASYNC                                                        */
+  uint32_t flags;           /* SOAR_ASYNC | SOAR_SPILL_GROUPED or SOAR_SPILL_DIRECT             */
 } soar_assign_opts;
 
 /* Optional statistics of one blocking call (host struct).  Set struct_size. */
 typedef struct soar_stats {
   uint32_t struct_size;
   float device_ms;          /* device time from the first to the last kernel of the call         */
-  float assign_kernel_ms;   /* device time of the main assignment kernel alone (HIP events)      */
+  float assign_kernel_ms;   /* device time of the assignment kernels alone (HIP events): both
+                               sweeps and, in the grouped form, the grouping (not quantization,
+                               re-scores or the exact full scan)                                 */
   int64_t rows_full_scan;   /* rows whose candidate set could not be proven complete and were
                                re-done by an exact scan over all K                               */
   int64_t rows_fp64;        /* rows whose decision was taken in FP64 (near-ties)                 */

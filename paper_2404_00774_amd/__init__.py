@@ -23,6 +23,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 FP32, BF16, FP8_E4M3 = 0, 1, 2
 _PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
 ASYNC = 1
+SPILL_GROUPED, SPILL_DIRECT = 2, 4
+_SPILL_FORM = {"auto": 0, "grouped": SPILL_GROUPED, "direct": SPILL_DIRECT}
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error",
            -4: "unsupported", -5: "non-finite input", -6: "timeout", -7: "shutdown"}
@@ -128,11 +130,13 @@ def assign_workspace_size(n, d, K, lam=1.0, precision="fp32", topk=0, near_tie_r
 
 
 def assign(X, C, lam, precision="fp32", topk=0, near_tie_rel=0.0, stream=None, out=None,
-           workspace=None, flags=0, stats=False):
+           workspace=None, flags=0, stats=False, spill_form="auto"):
     """SOAR assignment of every row of X against codebook C (both float32 on the GPU).
 
+    ``spill_form``: "auto", "grouped" or "direct" (the form of the spill sweep; same results).
     Returns (primary int32[n], spill int32[n], primary_dist float32[n], spill_loss float32[n])
     and, with ``stats=True``, a dict of call statistics as a fifth element."""
+    flags = int(flags) | _SPILL_FORM[spill_form]
     X, C = _f32_matrix(X, "X"), _f32_matrix(C, "C")
     n, d = X.shape
     K = C.shape[0]

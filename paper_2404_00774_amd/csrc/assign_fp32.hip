@@ -158,7 +158,7 @@ __device__ __forceinline__ double direct64(const AssignParams& P, int nch, int64
 // `row` (primary pia).  Ends with a workgroup barrier: the ring is free afterwards.
 // GR (spill only): <r, c_j> comes from <x, c_j> - G[pi][j], one MFMA stream instead of two; the
 // G values of tile t+1 are loaded during tile t.
-template <int DP, int BN, bool CH, bool VEC, bool SP, bool GR = false>
+template <int DP, int BN, bool CH, bool VEC, bool SP, bool GR = false, bool GP = false>
 __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch, int tid,
                                       int64_t row, bool ok, int pia, float (&xa)[DP / 4],
                                       float (&ra)[DP / 4], const float (&lp)[4],
@@ -169,6 +169,7 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
   using R = F32Rec<DP, BN>;
   constexpr int KS = DP / 4, LDW = R::LDW, NB = BN / 16;
   static_assert(!GR || (SP && !CH), "Gram form: spill sweep of resident rows only");
+  static_assert(!GP || (SP && !CH && !GR), "grouped form: spill sweep of resident rows only");
   const int lane = tid & 63, w = tid >> 6, q = lane >> 4, c16 = lane & 15;
   const int ntiles = (P.K + BN - 1) / BN;
   const int nsteps = ntiles * (CH ? nch : 1);
@@ -246,7 +247,7 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           accS[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[s + e], bv[b][e], accS[b], 0, 0, 0);
-          if constexpr (SP && !GR)
+          if constexpr (SP && !GR && !GP)
             accT[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[s + e], bv[b][e], accT[b], 0, 0, 0);
         }
       }
@@ -259,12 +260,16 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
         const int j = t * BN + b * 16 + c16;
         const float cnv = scn[b * 16 + c16];
         const float snv = ssn[b * 16 + c16];
+        // grouped form: row 15 of the stripe is the centroid c_p (lane group 3, register 3)
+        const float spv = GP ? __shfl(accS[b][3], 48 + c16) : 0.f;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           float val;
           if constexpr (SP) {
-            // <r, c_j> - <r, x>, directly or as (<x, c_j> - G[pi][j]) - <r, x>
-            const float e = GR ? (accS[b][v] - gcur[b][v]) - av[v] : accT[b][v] - av[v];
+            // <r, c_j> - <r, x>: directly, as (<x, c_j> - G[pi][j]) - <r, x>, or with
+            // <c_pi, c_j> from the stripe's centroid row
+            const float e = GP ? (accS[b][v] - spv) - av[v]
+                               : (GR ? (accS[b][v] - gcur[b][v]) - av[v] : accT[b][v] - av[v]);
             const float wv = fmaf(-2.f, accS[b][v], cnv);
             val = fmaf(lp[v] * e, e, wv);
             if (j == pr[v]) val = kInf;
@@ -313,6 +318,7 @@ struct RowShared {
   int pi[4][16];       // primary (-1: the row went to the full scan)
   int nc[4][16];       // number of candidates
   int sat[4][16];      // candidate set not proven complete
+  int valid[4][16];    // grouped form: the stripe row is a data row
 };
 // Candidate lists; they live in the codebook ring, which is idle between the sweeps.
 struct CandShared {
@@ -458,6 +464,7 @@ void assign_f32_kernel(AssignParams P) {
     if (psat) {
       const unsigned slot = atomicAdd(&P.counters[CNT_FULLSCAN], 1u);
       P.full_rows[slot] = (int32_t)row;
+      P.primary[row] = -1;   // finished by the full scan; left out of a grouped spill
     } else {
       P.primary[row] = pi;
       if (P.pdist) P.pdist[row] = pdist;
@@ -527,6 +534,100 @@ void assign_f32_kernel(AssignParams P) {
   if (!ssat) decide<DP, BN, CH, VEC, true>(P, S, CS, nch, w, c16, q, row, ok, xa, ra, rr, pi, sj, sl);
   if (sj < 0 || sj >= P.K) ssat = true;
   if (ok && q == 0) {
+    if (ssat) {
+      const unsigned slot = atomicAdd(&P.counters[CNT_FULLSCAN], 1u);
+      P.full_rows[slot] = (int32_t)row;
+    } else {
+      P.spill[row] = sj;
+      if (P.sloss) P.sloss[row] = sl;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Grouped form of the spill pass.  A wave takes one stripe: up to 15 rows sharing the primary p
+// (A-layout rows 0..14) and c_p itself as row 15, so the single MFMA stream X C^T also yields
+// <c_p, c_j> and <r_i, c_j> = <x_i, c_j> - <c_p, c_j> needs no second stream and no Gram table.
+// The error bound is the Gram form's.  Stripe rows past the stripe's size are zero and, like
+// row 15, produce no output.
+// ------------------------------------------------------------------------------------------------
+template <int DP, int BN, bool VEC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(f32_waves<DP, false>(), 2)))
+void assign_f32_spill_grouped(AssignParams P) {
+  using R = F32Rec<DP, BN>;
+  constexpr int KS = DP / 4;
+  static_assert(2 * R::STAGE >= (int)sizeof(CandShared), "candidate lists must fit in the ring");
+  __shared__ __attribute__((aligned(16))) char lds[2 * R::STAGE + sizeof(RowShared)];
+  char* ring = lds;
+  RowShared& S = *reinterpret_cast<RowShared*>(lds + 2 * R::STAGE);
+  CandShared& CS = *reinterpret_cast<CandShared*>(ring);
+
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, c16 = lane & 15;
+  const int ns = *P.nstripes;
+  if (blockIdx.x * 4 >= ns) return;             // whole block past the stripes
+  const int sidx = blockIdx.x * 4 + w;
+  const int4 sd = sidx < ns ? P.stripes[sidx] : int4{0, 0, 0, 0};   // {p, first, rows, -}
+  const int p = sd.x, nrows = sd.z;
+  const bool data = c16 < nrows;
+  const int64_t row = data ? (int64_t)P.perm[sd.y + c16] : 0;
+
+  float xa[KS], ra[KS];
+  if (c16 == 15) {
+    load_rec<KS>(rec_row<DP, BN>(P.Crec, 1, p, 0) + q * KS, xa);   // the centroid row c_p
+  } else {
+    load_seg<KS, VEC>(P.X, row, P.d, q * KS, data, xa);
+  }
+  float cp[KS];
+  load_rec<KS>(rec_row<DP, BN>(P.Crec, 1, p, 0) + q * KS, cp);
+  float n0 = 0.f, n1 = 0.f, r0 = 0.f, r1 = 0.f, a0 = 0.f, a1 = 0.f;
+#pragma unroll
+  for (int s = 0; s < KS; s += 2) {
+    ra[s] = xa[s] - cp[s];
+    ra[s + 1] = xa[s + 1] - cp[s + 1];
+    n0 = fmaf(xa[s], xa[s], n0); n1 = fmaf(xa[s + 1], xa[s + 1], n1);
+    r0 = fmaf(ra[s], ra[s], r0); r1 = fmaf(ra[s + 1], ra[s + 1], r1);
+    a0 = fmaf(ra[s], xa[s], a0); a1 = fmaf(ra[s + 1], xa[s + 1], a1);
+  }
+  const float xnorm = sqrtf(sum_quad_f(n0 + n1));
+  const float rr = sum_quad_f(r0 + r1);
+  const float a = sum_quad_f(a0 + a1);
+  if (q == 0) {
+    float A = 0.5f * P.band_s;
+    if (rr > 0.f) {
+      const float Pn = xnorm + sqrtf(P.cnorm[p]);
+      const float inv = 1.f / sqrtf(rr);
+      A += 0.5f * (P.band_g1 * Pn * inv + P.band_g2 * Pn * Pn * inv * inv);
+    }
+    S.xn[w][c16] = xnorm;
+    S.A[w][c16] = A;
+    S.lp[w][c16] = (data && rr > 0.f) ? P.lam / rr : 0.f;
+    S.av[w][c16] = a;
+    S.pi[w][c16] = p;
+    S.valid[w][c16] = data;
+  }
+  __syncthreads();
+  float b1[4], b2[4], b3[4], U[4], lp[4], av[4], xv[4], Av[4];
+  int i1[4], i2[4], pr[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = 4 * q + v;
+    b1[v] = b2[v] = b3[v] = U[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
+    lp[v] = S.lp[w][r]; av[v] = S.av[w][r]; pr[v] = p; xv[v] = S.xn[w][r]; Av[v] = S.A[w][r];
+  }
+  sweep<DP, BN, false, VEC, true, false, true>(P, ring, 1, tid, row, data, p, xa, ra, lp, av, pr,
+                                               xv, Av, b1, i1, b2, i2, b3, U);
+  publish_candidates(S, CS, w, lane, b1, i1, b2, i2, b3, U);
+  __syncthreads();
+  if (!data) return;
+  // R again (the sweep did not hold it)
+#pragma unroll
+  for (int s = 0; s < KS; ++s) ra[s] = xa[s] - cp[s];
+  bool ssat = S.sat[w][c16] != 0;
+  int sj = -1;
+  float sl = 0.f;
+  if (!ssat) decide<DP, BN, false, VEC, true>(P, S, CS, 1, w, c16, q, row, true, xa, ra, rr, p, sj, sl);
+  if (sj < 0 || sj >= P.K) ssat = true;
+  if (q == 0) {
     if (ssat) {
       const unsigned slot = atomicAdd(&P.counters[CNT_FULLSCAN], 1u);
       P.full_rows[slot] = (int32_t)row;
@@ -927,15 +1028,48 @@ hipError_t launch_reset_step_counters(unsigned* counters, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int DP, int BN>
+static hipError_t launch_grouped_dp(const AssignParams& P, bool vec, hipStream_t st) {
+  const int64_t ms = group_max_stripes(P.n, P.K);
+  const dim3 grid((unsigned)((ms + 3) / 4)), block(256);
+  if (vec) hipLaunchKernelGGL((assign_f32_spill_grouped<DP, BN, true>), grid, block, 0, st, P);
+  else hipLaunchKernelGGL((assign_f32_spill_grouped<DP, BN, false>), grid, block, 0, st, P);
+  return hipGetLastError();
+}
+
 hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipStream_t st,
-                              hipEvent_t ev_begin, hipEvent_t ev_end) {
+                              hipEvent_t ev_begin, hipEvent_t ev_end, const GroupLayout* grouped) {
   hipError_t e;
-  if (ev_begin) (void)hipEventRecord(ev_begin, st);
   const int dp = fp32_padded_dim(P.d);
   if (dp < 0 || !P.Crec) return hipErrorInvalidValue;
-#define SOAR_X(DP, BN, CH) e = launch_dp<DP, BN, CH>(P, spill, vec, st)
-  switch (dp) { SOAR_F32_SHAPES(SOAR_X) }
+  if (ev_begin) (void)hipEventRecord(ev_begin, st);
+  if (spill && grouped && dp <= 256) {
+    // primary pass, rows grouped by primary, grouped spill pass
+#define SOAR_X(DP, BN, CH) e = launch_dp<DP, BN, CH>(P, false, vec, st)
+    switch (dp) { SOAR_F32_SHAPES(SOAR_X) }
 #undef SOAR_X
+    if (e != hipSuccess) return e;
+    e = launch_group_by_primary(P.primary, P.n, P.live_n, P.K, *grouped, st);
+    if (e != hipSuccess) return e;
+    AssignParams Q = P;
+    Q.perm = grouped->perm;
+    Q.stripes = grouped->stripes;
+    Q.nstripes = grouped->meta;
+    switch (dp) {
+      case 16: e = launch_grouped_dp<16, 64>(Q, vec, st); break;
+      case 32: e = launch_grouped_dp<32, 64>(Q, vec, st); break;
+      case 48: e = launch_grouped_dp<48, 64>(Q, vec, st); break;
+      case 64: e = launch_grouped_dp<64, 64>(Q, vec, st); break;
+      case 96: e = launch_grouped_dp<96, 64>(Q, vec, st); break;
+      case 128: e = launch_grouped_dp<128, 64>(Q, vec, st); break;
+      case 192: e = launch_grouped_dp<192, 32>(Q, vec, st); break;
+      default: e = launch_grouped_dp<256, 32>(Q, vec, st); break;
+    }
+  } else {
+#define SOAR_X(DP, BN, CH) e = launch_dp<DP, BN, CH>(P, spill, vec, st)
+    switch (dp) { SOAR_F32_SHAPES(SOAR_X) }
+#undef SOAR_X
+  }
   if (e != hipSuccess) return e;
   if (ev_end) (void)hipEventRecord(ev_end, st);
   const size_t smem = ((size_t)3 * P.d + (P.K <= FS_LDS_K ? (size_t)P.K : 0)) * sizeof(float);

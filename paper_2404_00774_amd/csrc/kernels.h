@@ -5,6 +5,8 @@
 
 namespace soar {
 
+struct GroupLayout;
+
 struct AssignParams {
   const float* X;
   int64_t n;
@@ -24,6 +26,10 @@ struct AssignParams {
   // gains (band_g1 P / ||r|| + band_g2 P^2 / ||r||^2) (||x|| + ||c_j||)^2, P = ||x|| + ||c_pi||
   const float* G = nullptr;   // [K x K] C C^T, or null
   float band_g1 = 0.f, band_g2 = 0.f;
+  // grouped form of the spill sweep (launch_assign_fp32 with a GroupLayout): rows by primary
+  const int32_t* perm = nullptr;
+  const int4* stripes = nullptr;
+  const int32_t* nstripes = nullptr;
   int32_t* primary;
   int32_t* spill;
   float* pdist;
@@ -55,9 +61,32 @@ hipError_t launch_prep_codebook(const float* C, int K, int d, float* cnorm, unsi
                                 hipStream_t st);
 // Clears the per-assignment counters only (the codebook's maximum norm is kept).
 hipError_t launch_reset_step_counters(unsigned* counters, hipStream_t st);
-// ev_begin / ev_end (nullable) are recorded around the main assignment kernel alone.
+// ev_begin / ev_end (nullable) are recorded around the assignment kernels (without the exact
+// full scan).  With `grouped` (rows of up to 256 dimensions only) the spill runs in its grouped
+// form: primary pass, grouping of the rows by primary into G, grouped spill pass.
 hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipStream_t st,
-                              hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
+                              hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr,
+                              const GroupLayout* grouped = nullptr);
+
+// ---- grouping rows by primary (grouped form of the spill sweep) ----
+constexpr int GROUP_ROWS = 15;   // data rows per 16-row MFMA stripe; the 16th row is the centroid
+struct GroupLayout {
+  int32_t* cnt;      // [K]
+  int32_t* cursor;   // [K]
+  int32_t* off;      // [K + 1]
+  int32_t* sbeg;     // [K + 1]
+  int32_t* meta;     // [0]: number of stripes
+  int32_t* perm;     // [n] row ids grouped by primary
+  int4* stripes;     // [group_max_stripes]: {partition, first position in perm, rows, 0}
+  size_t bytes;
+};
+int64_t group_max_stripes(int64_t n, int K);
+GroupLayout group_layout(void* ws, int64_t n, int K);   // ws may be null (sizes only)
+// Groups the live rows (prim[i] outside [0, K) are left out).  Stream-ordered; no host sync.
+hipError_t launch_group_by_primary(const int32_t* prim, int64_t cap, const int64_t* live_n, int K,
+                                   const GroupLayout& L, hipStream_t st);
+// The grouped form pays when partitions hold several rows on average.
+inline bool grouped_spill_pays(int64_t n, int K) { return n >= 8 * (int64_t)K; }
 
 // ---- low-precision (BF16 / FP8-e4m3) path ----
 enum LowpFormat : int { LOWP_BF16 = 0, LOWP_FP8 = 1 };

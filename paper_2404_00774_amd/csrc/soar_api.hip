@@ -56,6 +56,7 @@ bool read_opts(const soar_assign_opts* o, OptsView* v) {
 soar_status validate_assign(int64_t n, int32_t d, int32_t K, const OptsView& o) {
   if (n < 1 || n > INT32_MAX || d < 1 || K < 2) return SOAR_E_INVAL;
   if (!std::isfinite(o.lambda) || o.lambda < 0.f) return SOAR_E_INVAL;
+  if ((o.flags & SOAR_SPILL_GROUPED) && (o.flags & SOAR_SPILL_DIRECT)) return SOAR_E_INVAL;
   if (!(o.near_tie_rel >= 0.f) || !std::isfinite(o.near_tie_rel)) return SOAR_E_INVAL;
   if (o.precision == SOAR_FP32) return soar::fp32_padded_dim(d) < 0 ? SOAR_E_UNSUPPORTED : SOAR_OK;
   if (o.precision != SOAR_BF16 && o.precision != SOAR_FP8_E4M3) return SOAR_E_INVAL;
@@ -107,6 +108,7 @@ struct AssignLayout {
   char* crec;
   float* gram;          // [K x K] when the spill sweep uses the Gram form
   int32_t* full_rows;
+  void* group;          // grouping of rows by primary (grouped form of the spill sweep)
   size_t bytes;
 };
 
@@ -118,6 +120,7 @@ AssignLayout layout_assign(void* ws, int64_t n, int32_t d, int32_t K) {
   L.crec = c.take<char>(soar::fp32_codebook_bytes(d, K));
   L.gram = soar::fp32_uses_gram(d, K) ? c.take<float>((size_t)K * K) : nullptr;
   L.full_rows = c.take<int32_t>((size_t)n);
+  L.group = c.take<char>(soar::group_layout(nullptr, n, K).bytes);
   L.bytes = c.off;
   return L;
 }
@@ -153,11 +156,13 @@ float tie_threshold(int d, float lam, float near_tie_rel) {
 }
 
 // Shared by soar_assign and the training loop: primary-only (labels) or full SOAR.
+// spill_form: 0 = chosen here, SOAR_SPILL_GROUPED or SOAR_SPILL_DIRECT.
 soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
                             float lam, float near_tie_rel, bool spill, int32_t* primary,
                             int32_t* spill_out, float* pdist, float* sloss, void* ws,
                             hipStream_t st, unsigned* counters_out_host,
-                            hipEvent_t ev_kernel_begin, hipEvent_t ev_kernel_end) {
+                            hipEvent_t ev_kernel_begin, hipEvent_t ev_kernel_end,
+                            uint32_t spill_form) {
   AssignLayout L = layout_assign(ws, n, d, K);
   AssignParams P;
   P.X = X; P.n = n; P.d = d; P.C = C; P.K = K; P.Crec = L.crec;
@@ -168,17 +173,23 @@ soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C
   P.band_s = band_coef_spill(d, lam);
   P.primary = primary; P.spill = spill_out; P.pdist = pdist; P.sloss = sloss;
   P.full_rows = L.full_rows;
-  const bool gram = spill && L.gram != nullptr;
-  if (gram) {
-    P.G = L.gram;
+  const bool grouped = spill && d <= 256 &&
+                       (spill_form == SOAR_SPILL_GROUPED ||
+                        (spill_form == 0 && grouped_spill_pays(n, K)));
+  const bool gram = spill && !grouped && L.gram != nullptr;
+  if (gram) P.G = L.gram;
+  if (gram || grouped) {
     P.band_g1 = band_coef_gram1(d, lam);
     P.band_g2 = band_coef_gram2(d, lam);
   }
+  const GroupLayout GL = group_layout(L.group, n, K);
   const bool vec = (d % 4 == 0) && aligned(X, 16) && aligned(C, 16);
   hipError_t e = launch_prep_codebook(C, K, d, L.cnorm, L.counters, st);
   if (e == hipSuccess) e = launch_pack_fp32(C, K, d, L.cnorm, L.crec, st);
   if (e == hipSuccess && gram) e = launch_gram(C, K, d, L.gram, st);
-  if (e == hipSuccess) e = launch_assign_fp32(P, spill, vec, st, ev_kernel_begin, ev_kernel_end);
+  if (e == hipSuccess)
+    e = launch_assign_fp32(P, spill, vec, st, ev_kernel_begin, ev_kernel_end,
+                           grouped ? &GL : nullptr);
   if (e != hipSuccess) return SOAR_E_DEVICE;
   if (counters_out_host) {
     e = hipMemcpyAsync(counters_out_host, L.counters, CNT_WORDS * sizeof(unsigned),
@@ -290,7 +301,7 @@ soar_status soar_assign(const float* X, int64_t n, int32_t d, const float* C, in
   if (!lowp)
     s = soar::run_assign_fp32(X, n, d, C, K, o.lambda, o.near_tie_rel, true, primary, spill,
                               primary_dist, spill_loss, workspace, st, async ? nullptr : cnt,
-                              ev[1], ev[2]);
+                              ev[1], ev[2], o.flags & (SOAR_SPILL_GROUPED | SOAR_SPILL_DIRECT));
   else
     s = soar::run_assign_lowp(X, n, d, C, K, o.lambda, o.near_tie_rel, lowp_fmt(o), lowp_topk(o),
                               primary, spill, primary_dist, spill_loss, workspace, st,

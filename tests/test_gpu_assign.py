@@ -47,11 +47,12 @@ def small_workload():
     return X, C.astype(np.float32)
 
 
+@pytest.mark.parametrize("form", ["grouped", "direct"])
 @pytest.mark.parametrize("lam", [0.0, 0.5, 1.0, 1.5])
-def test_small_workload_parity(small_workload, lam):
+def test_small_workload_parity(small_workload, lam, form):
     X, C = small_workload
-    print(f"assign n={len(X)} d={X.shape[1]} K={len(C)} lam={lam}", flush=True)
-    _check(X, C, lam, _run(X, C, lam))
+    print(f"assign n={len(X)} d={X.shape[1]} K={len(C)} lam={lam} {form}", flush=True)
+    _check(X, C, lam, _run(X, C, lam, spill_form=form))
 
 
 @pytest.mark.parametrize("n,d,K", [
@@ -63,12 +64,13 @@ def test_small_workload_parity(small_workload, lam):
     # the spill sweep's Gram form holds up to K = 4096; above it <r, c> is formed directly
     (1000, 128, 4096), (129, 96, 4097), (300, 64, 5000)])
 @pytest.mark.parametrize("lam", [0.0, 1.0])
-def test_edge_shapes(n, d, K, lam):
-    print(f"edge n={n} d={d} K={K} lam={lam}", flush=True)
+@pytest.mark.parametrize("form", ["grouped", "direct"])
+def test_edge_shapes(n, d, K, lam, form):
+    print(f"edge n={n} d={d} K={K} lam={lam} {form}", flush=True)
     rng = np.random.default_rng(n * 7 + d * 13 + K)
     X = rng.standard_normal((n, d)).astype(np.float32)
     C = (rng.standard_normal((K, d)) * 0.7).astype(np.float32)
-    _check(X, C, lam, _run(X, C, lam), fast=False)
+    _check(X, C, lam, _run(X, C, lam, spill_form=form), fast=False)
 
 
 def test_integer_ties_duplicates_and_zero_residual():
@@ -79,9 +81,10 @@ def test_integer_ties_duplicates_and_zero_residual():
     C[33] = C[1]
     X = rng.integers(-2, 3, size=(n, d)).astype(np.float32)
     X[:50] = C[rng.integers(0, K, 50)]  # r = 0 rows
-    for lam in (0.0, 0.5, 1.0, 1.5):
-        print(f"ties lam={lam}", flush=True)
-        res = _run(X, C, lam)
+    for lam, form in ((0.0, "grouped"), (0.5, "direct"), (1.0, "grouped"), (1.5, "direct"),
+                      (1.5, "grouped")):
+        print(f"ties lam={lam} {form}", flush=True)
+        res = _run(X, C, lam, spill_form=form)
         j = _check(X, C, lam, res, fast=False)
         # integer data: distances are exact, so the primary must be the lowest-index arg-min
         assert np.array_equal(res[0], j["p_star"])
@@ -101,8 +104,9 @@ def test_heavy_tailed_norms_d768(lam):
     assert res[4]["rows_full_scan"] <= len(X) // 100, res[4]
 
 
+@pytest.mark.parametrize("form", ["grouped", "direct"])
 @pytest.mark.parametrize("lam", [1.0, 1.5])
-def test_small_residuals(lam):
+def test_small_residuals(lam, form):
     """Rows at distances 1e-2 .. 1e-6 from their centroid: the Gram form's screening band grows
     like 1/||r||, so such rows exercise the widened band and the exact full scan."""
     rng = np.random.default_rng(21)
@@ -113,8 +117,8 @@ def test_small_residuals(lam):
     for k, eps in enumerate((1e-2, 1e-3, 1e-4, 1e-6)):
         sl = slice(k * 800, (k + 1) * 800)
         X[sl] = C[src[sl]] + eps * rng.standard_normal((800, d)).astype(np.float32)
-    print(f"small residuals lam={lam}", flush=True)
-    _check(X, C, lam, _run(X, C, lam), fast=False)
+    print(f"small residuals lam={lam} {form}", flush=True)
+    _check(X, C, lam, _run(X, C, lam, spill_form=form), fast=False)
 
 
 def test_deterministic_and_metamorphic(small_workload):
@@ -149,9 +153,10 @@ def test_full_size_sampled_parity():
     C, _, _ = O.train_codebook(sub, w["K"], 2, seed=0, C_init=C0)
     C = C.astype(np.float32)
     idx = sample_rows(spec, 20_000)
-    for lam in w["lambdas"]:
-        print(f"full-size lam={lam}", flush=True)
-        p, s, dp, ls, st = _run(X, C, lam)
+    runs = [(lam, "auto") for lam in w["lambdas"]] + [(1.0, "direct")]
+    for lam, form in runs:
+        print(f"full-size lam={lam} {form}", flush=True)
+        p, s, dp, ls, st = _run(X, C, lam, spill_form=form)
         _check(X[idx], C, lam, (p[idx], s[idx], dp[idx], ls[idx], st))
         assert st["rows_full_scan"] < 0.02 * len(X)
 
@@ -171,6 +176,9 @@ def test_validation_and_errors():
     with pytest.raises(soar.SoarError) as e:
         soar.assign(_t(np.zeros((10, 1025))), _t(np.zeros((3, 1025))), 1.0)
     assert e.value.status == -4               # d > 1024 not supported
+    with pytest.raises(soar.SoarError) as e:  # both spill forms asked for
+        soar.assign(X, C, 1.0, flags=soar.SPILL_GROUPED | soar.SPILL_DIRECT)
+    assert e.value.status == -1
     Xn = np.zeros((10, 4), np.float32)
     Xn[3, 2] = np.nan
     with pytest.raises(soar.SoarError) as e:
