@@ -58,8 +58,9 @@ typedef enum soar_precision {
 #define SOAR_ASYNC 1u       /* flags bit: enqueue only; errors surface on the next blocking call */
 /* Form of the spill sweep (results are the same; only the work differs).  The grouped form sorts
    the rows by primary and takes <c_pi, c_j> from the same MFMA stream as <x, c_j>; the direct
-   form runs a second stream over R = X - C[pi].  Without either bit the library picks grouped
-   when n >= 8 K (FP32: rows of at most 256 dimensions).  Both bits: SOAR_E_INVAL. */
+   form runs a second stream over R = X - C[pi].  Without either bit: FP32 takes the grouped form
+   when n >= 8 K and d <= 256, BF16 / FP8 take the direct form (their sweeps are not bound by the
+   MFMA work the grouped form saves).  Both bits: SOAR_E_INVAL. */
 #define SOAR_SPILL_GROUPED 2u
 #define SOAR_SPILL_DIRECT 4u
 

@@ -220,7 +220,11 @@ __global__ __launch_bounds__(256) void pack_codebook_kernel(const float* __restr
 //         T = -2 sigma (<r,c> - <r,x>) and the spill value is S + T^2 (one fma).
 //   FP8:  rows carry scales, so S and T are rescaled per (row, column) in the epilogue.
 // The codebook records flow through an LDS ring of STG stages filled STG-1 tiles ahead.
-template <int FMT, int DP, int SPW, int BN, int STG, int WPE, bool SP>
+// GPD (grouped spill form): each 16-row stripe holds up to 15 rows sharing the primary p and, as
+// row 15, c_p quantized like the rows; with S the rescaled ||c||^2 - 2<., c> of a row,
+// <r_i, c_j> - <r_i, x_i> = (S_pj - S_ij) / 2 - <r_i, x_i>, so one MFMA stream serves the spill:
+// T = sigma (S_pj - S_ij) - 2 sigma <r_i, x_i> and the value is S_ij + T^2.
+template <int FMT, int DP, int SPW, int BN, int STG, int WPE, bool SP, bool GPD = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE > 2 ? WPE : 2)))
 void lowp_sweep_kernel(LowpParams P) {
   using T = FmtTraits<FMT>;
@@ -233,29 +237,47 @@ void lowp_sweep_kernel(LowpParams P) {
   constexpr int NR = SPW * 4;                      // rows per lane in the output layout
   __shared__ __attribute__((aligned(16))) char s_ring[STG * R::STAGE];
 
+  static_assert(!GPD || SP, "the grouped form is a spill sweep");
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, c16 = lane & 15;
   const int64_t n = live_rows(P.n, P.live_n);
-  if ((int64_t)blockIdx.x * 64 * SPW >= n) return;   // whole block past the live rows
+  // GPD: stripes (blockIdx.x * 4 + w) * SPW + st; each is {p, first in perm, rows}
+  const int ns = GPD ? *P.nstripes : 0;
+  if (GPD ? (int64_t)blockIdx.x * 4 * SPW >= ns : (int64_t)blockIdx.x * 64 * SPW >= n) return;
   const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * (16 * SPW);
   const int ntiles = (P.K + BN - 1) / BN;
   const char* recs = static_cast<const char*>(P.Cq);
+  int4 sd[GPD ? SPW : 1];
+  if constexpr (GPD) {
+#pragma unroll
+    for (int st = 0; st < SPW; ++st) {
+      const int sidx = (blockIdx.x * 4 + w) * SPW + st;
+      sd[st] = sidx < ns ? P.stripes[sidx] : int4{0, 0, 0, 0};
+    }
+  }
+  // row id of stripe-row lr of stripe st (-1: no data row there)
+  auto row_of = [&](int st, int lr) -> int64_t {
+    if constexpr (GPD) return lr < sd[st].z ? (int64_t)P.perm[sd[st].y + lr] : -1;
+    else { const int64_t r = row0 + st * 16 + lr; return r < n ? r : -1; }
+  };
 
   issue_record<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, 0, w, lane);
   if constexpr (STG > 2) { if (ntiles > 1) issue_record<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, 1, w, lane); }
 
   // A operands (A layout: lane (q, c16) holds row c16 of each stripe, quarter q of the dims)
   OperandRegs<FMT, DP> xa[SPW];
-  OperandRegs<FMT, DP> ra[SP ? SPW : 1];
+  OperandRegs<FMT, DP> ra[SP && !GPD ? SPW : 1];
 #pragma unroll
   for (int st = 0; st < SPW; ++st) {
-    const int64_t r = row0 + st * 16 + c16;
-    load_operand<FMT, DP>(P.Xq, r, r < n, q, xa[st]);
-    if constexpr (SP) load_operand<FMT, DP>(P.Rq, r, r < n, q, ra[st]);
+    const int64_t r = row_of(st, c16);
+    if (GPD && c16 == 15) load_operand<FMT, DP>(P.Cp, sd[st].x, true, q, xa[st]);   // c_p
+    else load_operand<FMT, DP>(P.Xq, r, r >= 0, q, xa[st]);
+    if constexpr (SP && !GPD) load_operand<FMT, DP>(P.Rq, r, r >= 0, q, ra[st]);
   }
   // row constants in the output layout: row (st, 4q + v)
   constexpr int NRF = BF ? 1 : NR;                 // FP8-only row constants
   constexpr int NRS = SP ? NR : 1;                 // spill-only row constants
   float ks[NRF], kt[SP ? NRF : 1], ka[SP ? NRF : 1], kl[NRS];
+  float gs[GPD ? NR : 1], gm[GPD ? NR : 1];       // GPD: sigma and -2 sigma <r, x>
   int kp[NRS];
   v4f a2[SP ? SPW : 1];
 #pragma unroll
@@ -263,10 +285,18 @@ void lowp_sweep_kernel(LowpParams P) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = st * 4 + v;
-      const int64_t r = row0 + st * 16 + 4 * q + v;
-      const bool ok = r < n;
-      if constexpr (!BF) ks[i] = -2.f * (ok ? P.xs[r] : 1.f);
-      if constexpr (SP) {
+      const int64_t r = row_of(st, 4 * q + v);
+      const bool ok = r >= 0;
+      if constexpr (!BF) {
+        if (GPD && 4 * q + v == 15) ks[i] = -2.f * P.cps[sd[st].x];   // the centroid row's scale
+        else ks[i] = -2.f * (ok ? P.xs[r] : 1.f);
+      }
+      if constexpr (GPD) {
+        const float4 rc = ok ? P.rowc[r] : float4{0.f, 0.f, 0.f, 0.f};
+        gs[i] = rc.w;
+        gm[i] = -2.f * rc.w * rc.y;
+        kp[i] = sd[st].x;
+      } else if constexpr (SP) {
         const float4 rc = ok ? P.rowc[r] : float4{0.f, 0.f, 0.f, 0.f};
         if constexpr (!BF) {
           kt[i] = rc.x;                      // inverse scale of the quantized residual row
@@ -315,7 +345,7 @@ void lowp_sweep_kernel(LowpParams P) {
     }
 #pragma unroll
     for (int g = 0; g < NB / GB; ++g) {
-      v4f accS[SPW][GB], accT[SP ? SPW : 1][GB];
+      v4f accS[SPW][GB], accT[SP && !GPD ? SPW : 1][GB];
 #pragma unroll
       for (int b = 0; b < GB; ++b) {
         const v4f init = BF ? *reinterpret_cast<const v4f*>(tcn + (g * GB + b) * 256)
@@ -323,7 +353,7 @@ void lowp_sweep_kernel(LowpParams P) {
 #pragma unroll
         for (int st = 0; st < SPW; ++st) {
           accS[st][b] = init;
-          if constexpr (SP) accT[st][b] = BF ? a2[st] : v4f{0.f, 0.f, 0.f, 0.f};
+          if constexpr (SP && !GPD) accT[st][b] = BF ? a2[st] : v4f{0.f, 0.f, 0.f, 0.f};
         }
       }
 #pragma unroll
@@ -340,11 +370,31 @@ void lowp_sweep_kernel(LowpParams P) {
 #pragma unroll
           for (int st = 0; st < SPW; ++st) {
             accS[st][b] = mfma_step<FMT>(xa[st].v[s], bv[b], accS[st][b]);
-            if constexpr (SP) accT[st][b] = mfma_step<FMT>(ra[st].v[s], bv[b], accT[st][b]);
+            if constexpr (SP && !GPD)
+              accT[st][b] = mfma_step<FMT>(ra[st].v[s], bv[b], accT[st][b]);
           }
       }
       // epilogue: ranking values, class minima (block index packed in the low mantissa bits);
       // the compare against each row's primary only runs in tiles that hold one
+      // S = ||c_j||^2 - 2 <row, c_j> of every lane's rows (BF16: the accumulator itself)
+      auto s_val = [&](int st, int b, int v) -> float {
+        if constexpr (BF) {
+          return accS[st][b][v];
+        } else {
+          const int jl = (g * GB + b) * 16 + c16;
+          const float cs = *reinterpret_cast<const float*>(tile + R::CS_OFF + jl * 4);
+          const float cn = *reinterpret_cast<const float*>(tile + R::CN_OFF + jl * 16);
+          return fmaf(accS[st][b][v], ks[st * 4 + v] * cs, cn);
+        }
+      };
+      // GPD: S of the stripe's centroid row (stripe row 15: lane group 3, register 3)
+      float spv[GPD ? SPW : 1][GB];
+      if constexpr (GPD) {
+#pragma unroll
+        for (int st = 0; st < SPW; ++st)
+#pragma unroll
+          for (int b = 0; b < GB; ++b) spv[st][b] = __shfl(s_val(st, b, 3), 48 + c16);
+      }
       auto epilogue = [&](auto with_mask) {
 #pragma unroll
         for (int st = 0; st < SPW; ++st)
@@ -355,18 +405,16 @@ void lowp_sweep_kernel(LowpParams P) {
 #pragma unroll
             for (int b = 0; b < GB; ++b) {
               const int jl = (g * GB + b) * 16 + c16;
-              float val;
-              if constexpr (BF) {
-                val = accS[st][b][v];
-                if constexpr (SP) val = fmaf(accT[st][b][v], accT[st][b][v], val);
-              } else {
+              float val = s_val(st, b, v);
+              if constexpr (GPD) {
+                const float tt = fmaf(gs[i], spv[st][b] - val, gm[i]);
+                val = fmaf(tt, tt, val);
+              } else if constexpr (SP && BF) {
+                val = fmaf(accT[st][b][v], accT[st][b][v], val);
+              } else if constexpr (SP) {
                 const float cs = *reinterpret_cast<const float*>(tile + R::CS_OFF + jl * 4);
-                const float cn = *reinterpret_cast<const float*>(tile + R::CN_OFF + jl * 16);
-                val = fmaf(accS[st][b][v], ks[i] * cs, cn);
-                if constexpr (SP) {
-                  const float e = accT[st][b][v] * (kt[i] * cs) - ka[i];
-                  val = fmaf(kl[i] * e, e, val);
-                }
+                const float e = accT[st][b][v] * (kt[i] * cs) - ka[i];
+                val = fmaf(kl[i] * e, e, val);
               }
               if constexpr (SP && decltype(with_mask)::value)
                 val = (t * BN + jl == kp[i]) ? kBig : val;
@@ -397,7 +445,7 @@ void lowp_sweep_kernel(LowpParams P) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = st * 4 + v;
-      const int64_t r = row0 + st * 16 + 4 * q + v;
+      const int64_t r = row_of(st, 4 * q + v);
       const float bv = b1[i];
       const bool valid = bv < 1.0e38f;
       const unsigned code = packed_code(bv);
@@ -411,7 +459,7 @@ void lowp_sweep_kernel(LowpParams P) {
         const int oj = __shfl(j, src);
         rank += (ov < bv || (ov == bv && oj < j)) ? 1 : 0;
       }
-      if (r < n && rank < topk) P.cand[r * topk + rank] = (valid && j < P.K) ? j : -1;
+      if (r >= 0 && rank < topk) P.cand[r * topk + rank] = (valid && j < P.K) ? j : -1;
     }
 }
 
@@ -570,10 +618,12 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
       inv = 1.f / scale;
     }
   }
-  // BF16 stores the residual pre-scaled by sigma = sqrt(lambda) / (2 ||r||)
+  // sigma = sqrt(lambda) / (2 ||r||): BF16 stores the residual pre-scaled by it, and the grouped
+  // spill form uses it in every format
   const float rn = sqrtf(r2);
-  const float sigma = (FMT == LOWP_BF16 && rn > 0.f) ? 0.5f * sqrtf(P.lam) / rn : 0.f;
+  const float sigma = rn > 0.f ? 0.5f * sqrtf(P.lam) / rn : 0.f;
   if (l16 == 0) P.rowc_out[row] = float4{inv, a, r2 > 0.f ? P.lam / r2 : 0.f, sigma};
+  if (!P.Rq_out) return;   // grouped spill form: no residual rows
   // the whole padded row is written: the padding must hold zeros, not old workspace bytes
   const int dp = P.dp;
   if constexpr (FMT == LOWP_FP8) {
@@ -669,6 +719,18 @@ static void sweep_dp(const LowpParams& P, bool spill, hipStream_t st) {
   }
 }
 
+// The grouped spill runs one MFMA stream but keeps more row constants than the primary sweep:
+// the spill's stripes per wave at the primary's waves per SIMD.
+template <int FMT, int DP>
+static void sweep_grouped_dp(const LowpParams& P, hipStream_t st) {
+  using S = SweepShape<FMT, DP>;
+  const int64_t ms = group_max_stripes(P.n, P.K);
+  const dim3 grid((unsigned)((ms + 4 * S::SPW_S - 1) / (4 * S::SPW_S)));
+  hipLaunchKernelGGL(
+      (lowp_sweep_kernel<FMT, DP, S::SPW_S, S::BN, S::STG, S::WPE_P, true, true>), grid,
+      dim3(256), 0, st, P);
+}
+
 template <int FMT, int DP>
 static void pack_dp(const float* C, int K, int d, const float* cnorm, void* rec,
                     unsigned* counters, hipStream_t st) {
@@ -709,6 +771,20 @@ static void sweep_fmt(const LowpParams& P, bool spill, hipStream_t st) {
 hipError_t launch_lowp_sweep(int fmt, const LowpParams& P, bool spill, hipStream_t st) {
   if (fmt == LOWP_BF16) sweep_fmt<LOWP_BF16>(P, spill, st);
   else sweep_fmt<LOWP_FP8>(P, spill, st);
+  return hipGetLastError();
+}
+
+template <int FMT>
+static void sweep_grouped_fmt(const LowpParams& P, hipStream_t st) {
+#define X(D) sweep_grouped_dp<FMT, D>(P, st)
+  switch (P.dp) { SOAR_DP_CASES(FMT, X) }
+#undef X
+}
+
+hipError_t launch_lowp_sweep_grouped(int fmt, const LowpParams& P, hipStream_t st) {
+  if (!P.perm || !P.stripes || !P.nstripes || !P.Cp) return hipErrorInvalidValue;
+  if (fmt == LOWP_BF16) sweep_grouped_fmt<LOWP_BF16>(P, st);
+  else sweep_grouped_fmt<LOWP_FP8>(P, st);
   return hipGetLastError();
 }
 

@@ -115,7 +115,13 @@ struct LowpParams {
   float* sloss;
   unsigned* counters;
   float4* rowc_out;       // written by the primary re-score
-  void* Rq_out;
+  void* Rq_out;           // null: the residual rows are not needed (grouped spill form)
+  // grouped spill form: rows grouped by primary, the centroid as the 16th row of every stripe
+  const int32_t* perm = nullptr;
+  const int4* stripes = nullptr;
+  const int32_t* nstripes = nullptr;
+  const void* Cp = nullptr;      // [K x dp] codebook rows quantized like X (not -2 c)
+  const float* cps = nullptr;    // FP8: their inverse row scales
   const int64_t* live_n = nullptr;   // device row count <= n (serving steps), or null
 };
 
@@ -125,6 +131,8 @@ hipError_t launch_lowp_quantize(int fmt, const float* A, int64_t rows, int d, in
                                 bool codebook, void* out, float* inv_scale, unsigned* counters,
                                 hipStream_t st, const int64_t* live_n = nullptr);
 hipError_t launch_lowp_sweep(int fmt, const LowpParams& P, bool spill, hipStream_t st);
+// Spill sweep in grouped form (P.perm, P.stripes, P.nstripes, P.Cp set; rowc from the re-score).
+hipError_t launch_lowp_sweep_grouped(int fmt, const LowpParams& P, hipStream_t st);
 // The sweep reads the codebook from packed per-tile records (see assign_lowp.hip).
 size_t lowp_codebook_bytes(int fmt, int d, int K);
 hipError_t launch_lowp_pack_codebook(int fmt, const float* C, int K, int d, const float* cnorm,

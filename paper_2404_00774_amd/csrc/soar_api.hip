@@ -76,6 +76,9 @@ struct LowpLayout {
   float* cs;
   float4* rowc;
   int32_t* cand;
+  void* Cp;             // codebook rows quantized like X (grouped spill form)
+  float* cps;
+  void* group;
   size_t bytes;
 };
 
@@ -93,6 +96,9 @@ LowpLayout layout_lowp(void* ws, int64_t n, int32_t d, int32_t K, int fmt, int t
   L.cs = c.take<float>((size_t)K);
   L.rowc = c.take<float4>((size_t)n);
   L.cand = c.take<int32_t>((size_t)n * topk);
+  L.Cp = c.take<char>((size_t)K * dp * eb);
+  L.cps = c.take<float>((size_t)K);
+  L.group = c.take<char>(soar::group_layout(nullptr, n, K).bytes);
   L.bytes = c.off;
   return L;
 }
@@ -208,8 +214,13 @@ size_t assign_workspace_bytes(int64_t n, int32_t d, int32_t K) {
 soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
                             float lam, float near_tie_rel, int fmt, int topk, int32_t* primary,
                             int32_t* spill_out, float* pdist, float* sloss, void* ws,
-                            hipStream_t st, unsigned* counters_out_host, hipEvent_t* ev) {
+                            hipStream_t st, unsigned* counters_out_host, hipEvent_t* ev,
+                            uint32_t spill_form) {
   LowpLayout L = layout_lowp(ws, n, d, K, fmt, topk);
+  // The grouped form trades the second MFMA stream for about two VALU operations per element;
+  // the BF16 / FP8 sweeps are not MFMA-bound, so it is taken only when asked for.
+  const bool grouped = spill_form == SOAR_SPILL_GROUPED;
+  const GroupLayout GL = group_layout(L.group, n, K);
   LowpParams P;
   P.n = n; P.d = d; P.dp = lowp_padded_dim(fmt, d); P.K = K; P.topk = topk;
   P.lam = lam;
@@ -217,10 +228,16 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
   P.X = X; P.C = C; P.Xq = L.Xq; P.Cq = L.Cq; P.Rq = L.Rq;
   P.xs = L.xs; P.cs = L.cs; P.cnorm = L.cnorm; P.rowc = L.rowc; P.cand = L.cand;
   P.primary = primary; P.spill = spill_out; P.pdist = pdist; P.sloss = sloss;
-  P.counters = L.counters; P.rowc_out = L.rowc; P.Rq_out = L.Rq;
+  P.counters = L.counters; P.rowc_out = L.rowc; P.Rq_out = grouped ? nullptr : L.Rq;
+  if (grouped) {
+    P.perm = GL.perm; P.stripes = GL.stripes; P.nstripes = GL.meta;
+    P.Cp = L.Cp; P.cps = L.cps;
+  }
   hipError_t e = launch_prep_codebook(C, K, d, L.cnorm, L.counters, st);
   if (e == hipSuccess)
     e = launch_lowp_pack_codebook(fmt, C, K, d, L.cnorm, L.Cq, L.counters, st);
+  if (e == hipSuccess && grouped)
+    e = launch_lowp_quantize(fmt, C, K, d, P.dp, false, L.Cp, L.cps, L.counters, st);
   if (e == hipSuccess)
     e = launch_lowp_quantize(fmt, X, n, d, P.dp, false, L.Xq, L.xs, L.counters, st);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[0], st);
@@ -228,7 +245,12 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
   if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
   if (e == hipSuccess) e = launch_lowp_rescore(fmt, P, false, st);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
-  if (e == hipSuccess) e = launch_lowp_sweep(fmt, P, true, st);
+  if (grouped) {
+    if (e == hipSuccess) e = launch_group_by_primary(primary, n, nullptr, K, GL, st);
+    if (e == hipSuccess) e = launch_lowp_sweep_grouped(fmt, P, st);
+  } else {
+    if (e == hipSuccess) e = launch_lowp_sweep(fmt, P, true, st);
+  }
   if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
   if (e == hipSuccess) e = launch_lowp_rescore(fmt, P, true, st);
   if (e != hipSuccess) return SOAR_E_DEVICE;
@@ -305,7 +327,8 @@ soar_status soar_assign(const float* X, int64_t n, int32_t d, const float* C, in
   else
     s = soar::run_assign_lowp(X, n, d, C, K, o.lambda, o.near_tie_rel, lowp_fmt(o), lowp_topk(o),
                               primary, spill, primary_dist, spill_loss, workspace, st,
-                              async ? nullptr : cnt, ev[0] ? ev + 1 : nullptr);
+                              async ? nullptr : cnt, ev[0] ? ev + 1 : nullptr,
+                              o.flags & (SOAR_SPILL_GROUPED | SOAR_SPILL_DIRECT));
   if (s != SOAR_OK || async) {
     destroy();
     return s;

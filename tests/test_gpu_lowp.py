@@ -24,9 +24,10 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-def _run(X, C, lam, prec, topk=0):
+def _run(X, C, lam, prec, topk=0, form="auto"):
     soar = _soar()
-    p, s, dp, ls, st = soar.assign(_t(X), _t(C), lam, precision=prec, topk=topk, stats=True)
+    p, s, dp, ls, st = soar.assign(_t(X), _t(C), lam, precision=prec, topk=topk, stats=True,
+                                   spill_form=form)
     return p.cpu().numpy(), s.cpu().numpy(), dp.cpu().numpy(), ls.cpu().numpy(), st
 
 
@@ -60,21 +61,23 @@ def small():
     return X, C.astype(np.float32)
 
 
+@pytest.mark.parametrize("form", ["grouped", "direct"])
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 @pytest.mark.parametrize("lam", [0.0, 1.0, 1.5])
-def test_small_workload(small, prec, lam):
+def test_small_workload(small, prec, lam, form):
     X, C = small
-    r = _report(X, C, lam, _run(X, C, lam, prec), f"{prec} lam={lam}")
+    r = _report(X, C, lam, _run(X, C, lam, prec, form=form), f"{prec} lam={lam} {form}")
     bound = 1e-3 if prec == "bf16" else 1e-2
     assert r["primary_regret_mean"] <= bound and r["spill_regret_mean"] <= bound
 
 
-def test_bf16_d96_many_centroids():
+@pytest.mark.parametrize("form", ["grouped", "direct"])
+def test_bf16_d96_many_centroids(form):
     """Config-3 shapes scaled down: d = 96, K = 4000, loguniform mixture."""
     spec = MixtureSpec(20_000, 96, 2048, ("loguniform", 0.05, 0.5), "unit", 3)
     X = gen_mixture(spec)
     C = X[np.random.default_rng(0).choice(len(X), 4000, replace=False)]
-    r = _report(X, C, 1.0, _run(X, C, 1.0, "bf16"), "bf16 d96 K4000")
+    r = _report(X, C, 1.0, _run(X, C, 1.0, "bf16", form=form), f"bf16 d96 K4000 {form}")
     assert r["primary_regret_mean"] <= 1e-3 and r["spill_regret_mean"] <= 1e-3
 
 
@@ -84,19 +87,21 @@ def test_fp8_d768_lognormal():
     X = gen_mixture(spec)
     C = X[np.random.default_rng(1).choice(len(X), 500, replace=False)] * 0.97
     for prec in ("fp8", "bf16"):
-        r = _report(X, C, 1.0, _run(X, C, 1.0, prec), f"{prec} d768")
-        assert r["spill_regret_mean"] <= (1e-2 if prec == "fp8" else 1e-3)
+        for form in ("grouped", "direct"):
+            r = _report(X, C, 1.0, _run(X, C, 1.0, prec, form=form), f"{prec} d768 {form}")
+            assert r["spill_regret_mean"] <= (1e-2 if prec == "fp8" else 1e-3)
 
 
+@pytest.mark.parametrize("form", ["grouped", "direct"])
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 @pytest.mark.parametrize("n,d,K,topk", [(1, 8, 2, 0), (37, 1, 3, 0), (300, 5, 9, 4), (513, 33, 17, 8),
-                                        (200, 100, 70, 2), (129, 300, 40, 0)])
-def test_edge_shapes(prec, n, d, K, topk):
-    print(f"{prec} edge n={n} d={d} K={K} topk={topk}", flush=True)
+                                        (200, 100, 70, 2), (129, 300, 40, 0), (4000, 64, 7, 8)])
+def test_edge_shapes(prec, n, d, K, topk, form):
+    print(f"{prec} edge n={n} d={d} K={K} topk={topk} {form}", flush=True)
     rng = np.random.default_rng(n + d + K)
     X = rng.standard_normal((n, d)).astype(np.float32)
     C = (rng.standard_normal((K, d)) * 0.8).astype(np.float32)
-    res = _run(X, C, 1.0, prec, topk)
+    res = _run(X, C, 1.0, prec, topk, form)
     _report(X, C, 1.0, res, f"{prec} edge")
     if K <= 16 and (topk == 0 or topk >= min(K, 8)):
         # every class minimum is a candidate, so the answers are exact
@@ -108,10 +113,11 @@ def test_edge_shapes(prec, n, d, K, topk):
 def test_deterministic(small):
     X, C = small
     for prec in ("bf16", "fp8"):
-        a = _run(X, C, 1.0, prec)
-        b = _run(X, C, 1.0, prec)
-        for u, v in zip(a[:4], b[:4]):
-            assert np.array_equal(u, v)
+        for form in ("grouped", "direct"):
+            a = _run(X, C, 1.0, prec, form=form)
+            b = _run(X, C, 1.0, prec, form=form)
+            for u, v in zip(a[:4], b[:4]):
+                assert np.array_equal(u, v)
 
 
 def test_invalid_topk():
