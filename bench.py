@@ -31,14 +31,19 @@ PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2516.0, "fp8": 5032.0}   # MI355X dense M
 # HBM bytes per launch of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
 # (KiB per dispatch), each scaled by what the same counter reads for a plain 1 GiB device copy
 # (bench.py --mode copy: FETCH_SIZE reads 524302.5 KiB, WRITE_SIZE 1048576 KiB, so the factors
-# are 2.0 and 1.0).  A figure holds only for the kernel source it was taken on (sha256 below);
-# after any change to that file the traffic is reported as null until it is measured again.
+# are 2.0 and 1.0), summed over the kernels of one step.  A figure holds only for the kernel
+# sources it was taken on (sha256 below); after any change to them the traffic is reported as
+# null until it is measured again.
 COPY_SCALE = {"fetch": 1048576.0 / 524302.5, "write": 1.0}
 TRAFFIC = {
+    # grouped FP32 pipeline, per step: primary pass, grouping by primary, grouped spill pass
     ("fp32", "mix4096_n1m_d128"): dict(
-        fetch_kib=2901296.8, write_kib=15648.0,
-        source="paper_2404_00774_amd/csrc/assign_fp32.hip",
-        sha256="476a4b353230aca8f3a42e08c9542bb3459ac4787f6b67d04a05a1437f1cc5b4"),
+        fetch_kib=255858.7 + 1964.1 + 6.8 + 2296.7 + 20.3 + 2 * 10.2 + 260955.2,
+        write_kib=7819.7 + 28148.3 + 15.7 + 47574.8 + 1056.4 + 2 * 7.8 + 65576.7,
+        sources={"paper_2404_00774_amd/csrc/assign_fp32.hip":
+                 "3746d1f237284d3f7a0d1573231315cf27436bc0a40b9600642d6662d306f40f",
+                 "paper_2404_00774_amd/csrc/group.hip":
+                 "63ab42f260ff6e77eac7f7e9d2145dfeafcf7513e60647e799b74fae44283f1a"}),
 }
 
 
@@ -48,9 +53,10 @@ def measured_traffic(prec, workload):
     t = TRAFFIC.get((prec, workload))
     if not t:
         return None
-    path = os.path.join(ROOT, t["source"])
-    if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != t["sha256"]:
-        return None
+    for src, sha in t["sources"].items():
+        path = os.path.join(ROOT, src)
+        if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != sha:
+            return None
     return (t["fetch_kib"] * COPY_SCALE["fetch"] + t["write_kib"] * COPY_SCALE["write"]) * 1024.0
 METRIC = "SOAR-assigned points/sec and % MFMA peak, BF16/FP8 vs FP32 at ≤1e-3 regret"
 DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8_e4m3"}
