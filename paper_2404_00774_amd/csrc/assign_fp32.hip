@@ -18,10 +18,11 @@
 // With delta_j = A_row (||x|| + ||c_j||)^2 a proven bound on the rounding error of centroid j's
 // expanded value v_j (A_row from d, lambda and, in the Gram form, ||x|| + ||c_pi|| and ||r||),
 // lo_j = v_j - delta_j and hi_j = v_j + delta_j bracket the exact value, so the exact arg-min has
-// lo_j <= U = min_j hi_j.  Every lane keeps, per row, the two smallest lo with their indices, the
-// third smallest lo, and the smallest hi over the columns it sees; the candidates are the
-// tracked entries with lo <= U, and they are complete unless some lane's third smallest lo is
-// also <= U, in which case the row is handed to the exact full scan.  Candidates are re-scored
+// lo_j <= U for any upper end U = hi_k.  Every lane keeps, per row, the two smallest lo with their
+// indices and the third smallest lo over the columns it sees; U is the smallest hi among the
+// lanes' best entries.  The candidates are the tracked entries with lo <= U, and they are
+// complete unless some lane's third smallest lo is also <= U, in which case the row is handed to
+// the exact full scan.  (lo and U are kept shifted by the row constant A_row ||x||^2.)  Candidates are re-scored
 // by direct differences in FP32 (16 partial sums per row), and candidates within the near-tie
 // gap of the best are re-decided in FP64.  Ties go to the lowest index.
 #include "common.h"
@@ -35,13 +36,16 @@ namespace soar {
 //    lanes of a group on distinct banks); zeros past d and past K]
 //   [BN floats ||c_j||^2, +inf past K]
 //   [BN floats ||c_j||, 0 past K]
+//   [BN floats ||c_j||^2 - A_p ||c_j||^2, +inf past K] (A_p: the primary pass's error
+//    coefficient, so the primary's lower ends need one fma per column term)
 // Each record is copied with NI whole wave-group copies (4 waves x 64 lanes x 16 bytes).
 template <int DP, int BN>
 struct F32Rec {
   static constexpr int LDW = DP + 4;
   static constexpr int CN_OFF = BN * LDW * 4;
   static constexpr int SN_OFF = CN_OFF + BN * 4;
-  static constexpr int BYTES = SN_OFF + BN * 4;
+  static constexpr int CA_OFF = SN_OFF + BN * 4;
+  static constexpr int BYTES = CA_OFF + BN * 4;
   static constexpr int NI = (BYTES + 4095) / 4096;
   static constexpr int STAGE = NI * 4096;
 };
@@ -165,7 +169,7 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
                                       const float (&av)[4], const int (&pr)[4],
                                       const float (&xv)[4], const float (&Av)[4], float (&b1)[4],
                                       int (&i1)[4], float (&b2)[4], int (&i2)[4],
-                                      float (&b3)[4], float (&U)[4]) {
+                                      float (&b3)[4]) {
   using R = F32Rec<DP, BN>;
   constexpr int KS = DP / 4, LDW = R::LDW, NB = BN / 16;
   static_assert(!GR || (SP && !CH), "Gram form: spill sweep of resident rows only");
@@ -174,6 +178,11 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
   const int ntiles = (P.K + BN - 1) / BN;
   const int nsteps = ntiles * (CH ? nch : 1);
   const char* recs = P.Crec;
+  // lower ends, shifted by A_row ||x||^2:
+  //   lo' = v - A_row (||c||^2 + 2 ||x|| ||c||)    (primary: (||c||^2 - A ||c||^2) from the record)
+  float kx[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) kx[v] = SP ? 2.f * xv[v] : -2.f * Av[v] * xv[v];
   // Gram rows of the lane's output rows (row 0 stands in for rows without a primary)
   const float* grow[4];
   float gcur[GR ? NB : 1][4], gnxt[GR ? NB : 1][4];
@@ -255,10 +264,11 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
     if (!CH || ch == nch - 1) {
       const float* scn = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE + R::CN_OFF);
       const float* ssn = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE + R::SN_OFF);
+      const float* sca = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE + R::CA_OFF);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = t * BN + b * 16 + c16;
-        const float cnv = scn[b * 16 + c16];
+        const float cnv = SP ? scn[b * 16 + c16] : sca[b * 16 + c16];
         const float snv = ssn[b * 16 + c16];
         // grouped form: row 15 of the stripe is the centroid c_p (lane group 3, register 3)
         const float spv = GP ? __shfl(accS[b][3], 48 + c16) : 0.f;
@@ -274,14 +284,10 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
             val = fmaf(lp[v] * e, e, wv);
             if (j == pr[v]) val = kInf;
           } else {
-            val = fmaf(-2.f, accS[b][v], cnv);
+            val = fmaf(-2.f, accS[b][v], cnv);   // here cnv = ||c||^2 - A ||c||^2
           }
-          // bracket the exact value, keep the smallest upper end and, on the lower ends,
-          // (b1, i1) <= (b2, i2) <= b3 over the columns seen so far
-          const float tt = xv[v] + snv;
-          const float dl = Av[v] * tt * tt;
-          const float lo = val - dl;
-          U[v] = fminf(U[v], val + dl);
+          // the lower end (shifted), then (b1, i1) <= (b2, i2) <= b3 over the columns seen
+          const float lo = SP ? fmaf(-(Av[v] * (snv + kx[v])), snv, val) : fmaf(kx[v], snv, val);
           const bool lt1 = lo < b1[v], lt2 = lo < b2[v];
           b3[v] = fminf(b3[v], fmaxf(b2[v], lo));
           i2[v] = lt1 ? i1[v] : (lt2 ? j : i2[v]);
@@ -327,16 +333,24 @@ struct CandShared {
 };
 
 // Reduce the lane-level state to per-row candidate lists in LDS (output layout -> LDS).
-__device__ __forceinline__ void publish_candidates(RowShared& S, CandShared& CS, int w, int lane,
+__device__ __forceinline__ void publish_candidates(const AssignParams& P, RowShared& S,
+                                                   CandShared& CS, int w, int lane,
+                                                   const float (&xv)[4], const float (&Av)[4],
                                                    const float (&b1)[4], const int (&i1)[4],
                                                    const float (&b2)[4], const int (&i2)[4],
-                                                   const float (&b3)[4], const float (&U)[4]) {
+                                                   const float (&b3)[4]) {
   const int q = lane >> 4, c16 = lane & 15;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int r = 4 * q + v;
-    // the row's smallest upper end: no centroid with a larger lower end can be the arg-min
-    float thr = U[v];
+    // an upper end of the exact minimum: the upper end hi' = lo' + 2 A_row (||x|| + ||c||)^2 of
+    // the lane's best entry, least over the row's lanes; no centroid with a larger lower end can
+    // be the arg-min
+    float thr = kInf;
+    if (b1[v] < kInf && i1[v] >= 0 && i1[v] < P.K) {
+      const float tt = xv[v] + sqrtf(P.cnorm[i1[v]]);
+      thr = fmaf(2.f * Av[v] * tt, tt, b1[v]);
+    }
 #pragma unroll
     for (int off = 1; off < 16; off <<= 1) thr = fminf(thr, __shfl_xor(thr, off));
     const bool finite_min = thr < kInf;
@@ -441,18 +455,18 @@ void assign_f32_kernel(AssignParams P) {
   __syncthreads();
 
   // ---------------- primary pass ----------------
-  float b1[4], b2[4], b3[4], U[4], lp[4], av[4], xv[4], Av[4];
+  float b1[4], b2[4], b3[4], lp[4], av[4], xv[4], Av[4];
   int i1[4], i2[4], pr[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    b1[v] = b2[v] = b3[v] = U[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
+    b1[v] = b2[v] = b3[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
     lp[v] = av[v] = 0.f; pr[v] = -1;
     xv[v] = S.xn[w][4 * q + v];
     Av[v] = S.A[w][4 * q + v];
   }
   sweep<DP, BN, CH, VEC, false>(P, ring, nch, tid, row, ok, -1, xa, ra, lp, av, pr, xv, Av, b1,
-                                i1, b2, i2, b3, U);
-  publish_candidates(S, CS, w, lane, b1, i1, b2, i2, b3, U);
+                                i1, b2, i2, b3);
+  publish_candidates(P, S, CS, w, lane, xv, Av, b1, i1, b2, i2, b3);
   __syncthreads();
 
   int pi = -1;
@@ -512,13 +526,13 @@ void assign_f32_kernel(AssignParams P) {
   for (int v = 0; v < 4; ++v) {
     const int r = 4 * q + v;
     lp[v] = S.lp[w][r]; av[v] = S.av[w][r]; pr[v] = S.pi[w][r]; Av[v] = S.A[w][r];
-    b1[v] = b2[v] = b3[v] = U[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
+    b1[v] = b2[v] = b3[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
   }
 
   // ---------------- spill pass ----------------
   sweep<DP, BN, CH, VEC, true, GR>(P, ring, nch, tid, row, ok, pi, xa, ra, lp, av, pr, xv, Av,
-                                   b1, i1, b2, i2, b3, U);
-  publish_candidates(S, CS, w, lane, b1, i1, b2, i2, b3, U);
+                                   b1, i1, b2, i2, b3);
+  publish_candidates(P, S, CS, w, lane, xv, Av, b1, i1, b2, i2, b3);
   __syncthreads();
   if (pi < 0) return;  // full-scan rows are finished by the full-scan kernel
   if constexpr (GR) {
@@ -606,17 +620,17 @@ void assign_f32_spill_grouped(AssignParams P) {
     S.valid[w][c16] = data;
   }
   __syncthreads();
-  float b1[4], b2[4], b3[4], U[4], lp[4], av[4], xv[4], Av[4];
+  float b1[4], b2[4], b3[4], lp[4], av[4], xv[4], Av[4];
   int i1[4], i2[4], pr[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int r = 4 * q + v;
-    b1[v] = b2[v] = b3[v] = U[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
+    b1[v] = b2[v] = b3[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
     lp[v] = S.lp[w][r]; av[v] = S.av[w][r]; pr[v] = p; xv[v] = S.xn[w][r]; Av[v] = S.A[w][r];
   }
   sweep<DP, BN, false, VEC, true, false, true>(P, ring, 1, tid, row, data, p, xa, ra, lp, av, pr,
-                                               xv, Av, b1, i1, b2, i2, b3, U);
-  publish_candidates(S, CS, w, lane, b1, i1, b2, i2, b3, U);
+                                               xv, Av, b1, i1, b2, i2, b3);
+  publish_candidates(P, S, CS, w, lane, xv, Av, b1, i1, b2, i2, b3);
   __syncthreads();
   if (!data) return;
   // R again (the sweep did not hold it)
@@ -871,7 +885,8 @@ __global__ __launch_bounds__(256) void prep_codebook_kernel(const float* __restr
 template <int DP, int BN>
 __global__ __launch_bounds__(256) void pack_f32_kernel(const float* __restrict__ C, int K, int d,
                                                        int nch, const float* __restrict__ cnorm,
-                                                       char* __restrict__ rec, int64_t total) {
+                                                       char* __restrict__ rec, int64_t total,
+                                                       float A_p) {
   using R = F32Rec<DP, BN>;
   constexpr int F4 = R::LDW / 4;   // float4 per record row (the last one is the pad)
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -893,6 +908,8 @@ __global__ __launch_bounds__(256) void pack_f32_kernel(const float* __restrict__
   if (f == 0) {
     *reinterpret_cast<float*>(base + R::CN_OFF + jl * 4) = j < K ? cnorm[j] : kInf;
     *reinterpret_cast<float*>(base + R::SN_OFF + jl * 4) = j < K ? sqrtf(cnorm[j]) : 0.f;
+    *reinterpret_cast<float*>(base + R::CA_OFF + jl * 4) =
+        j < K ? fmaf(-A_p, cnorm[j], cnorm[j]) : kInf;
   }
 }
 
@@ -959,7 +976,8 @@ static hipError_t pack_dp(const float* C, int K, int d, const float* cnorm, void
   const int nch = (d + DP - 1) / DP;
   const int64_t total = (int64_t)((K + BN - 1) / BN) * BN * nch * (F32Rec<DP, BN>::LDW / 4);
   hipLaunchKernelGGL((pack_f32_kernel<DP, BN>), dim3((unsigned)((total + 255) / 256)), dim3(256),
-                     0, st, C, K, d, nch, cnorm, static_cast<char*>(rec), total);
+                     0, st, C, K, d, nch, cnorm, static_cast<char*>(rec), total,
+                     0.5f * band_coef_primary(d));
   return hipGetLastError();
 }
 
