@@ -679,12 +679,18 @@ struct SweepShape;
     static constexpr int BN = B, STG = S;                                           \
   };
 #define SOAR_SHAPE_X(...) SOAR_SHAPE(__VA_ARGS__)
-// (the two most used widths can be set at build time, e.g. -DSOAR_SHAPE_BF16_96=4,2,2,2,64,3)
+// (the most used widths can be set at build time, e.g. -DSOAR_SHAPE_BF16_96=4,2,2,2,64,3)
 #ifndef SOAR_SHAPE_BF16_96
 #define SOAR_SHAPE_BF16_96 4, 2, 2, 2, 64, 3
 #endif
 #ifndef SOAR_SHAPE_BF16_128
 #define SOAR_SHAPE_BF16_128 4, 2, 2, 1, 64, 3
+#endif
+#ifndef SOAR_SHAPE_BF16_768
+#define SOAR_SHAPE_BF16_768 2, 1, 2, 1, 32, 2
+#endif
+#ifndef SOAR_SHAPE_FP8_768
+#define SOAR_SHAPE_FP8_768 2, 1, 2, 1, 32, 2
 #endif
 //         format     DP  primary  spill   BN  stages   (SPW stripes, waves per SIMD)
 SOAR_SHAPE(LOWP_BF16, 32, 4, 2, 2, 2, 64, 3)
@@ -695,13 +701,13 @@ SOAR_SHAPE(LOWP_BF16, 192, 2, 1, 2, 1, 64, 3)
 SOAR_SHAPE(LOWP_BF16, 256, 2, 1, 1, 1, 64, 3)
 SOAR_SHAPE(LOWP_BF16, 384, 1, 1, 1, 1, 64, 2)
 SOAR_SHAPE(LOWP_BF16, 512, 1, 2, 1, 1, 32, 2)
-SOAR_SHAPE(LOWP_BF16, 768, 1, 1, 1, 1, 32, 2)
+SOAR_SHAPE_X(LOWP_BF16, 768, SOAR_SHAPE_BF16_768)
 SOAR_SHAPE(LOWP_BF16, 1024, 1, 1, 1, 1, 16, 2)
 SOAR_SHAPE(LOWP_FP8, 128, 2, 2, 2, 2, 64, 3)
 SOAR_SHAPE(LOWP_FP8, 256, 2, 2, 2, 1, 64, 3)
 SOAR_SHAPE(LOWP_FP8, 384, 2, 1, 1, 1, 64, 3)
 SOAR_SHAPE(LOWP_FP8, 512, 2, 2, 1, 2, 64, 2)
-SOAR_SHAPE(LOWP_FP8, 768, 1, 1, 1, 1, 64, 2)
+SOAR_SHAPE_X(LOWP_FP8, 768, SOAR_SHAPE_FP8_768)
 SOAR_SHAPE(LOWP_FP8, 1024, 1, 2, 1, 2, 32, 2)
 #undef SOAR_SHAPE
 

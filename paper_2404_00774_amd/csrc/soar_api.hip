@@ -217,9 +217,12 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
                             hipStream_t st, unsigned* counters_out_host, hipEvent_t* ev,
                             uint32_t spill_form) {
   LowpLayout L = layout_lowp(ws, n, d, K, fmt, topk);
-  // The grouped form trades the second MFMA stream for about two VALU operations per element;
-  // the BF16 / FP8 sweeps are not MFMA-bound, so it is taken only when asked for.
-  const bool grouped = spill_form == SOAR_SPILL_GROUPED;
+  // The grouped form trades the second MFMA stream for about two VALU operations per element.
+  // Measured: it pays for FP8 rows of 512 dimensions and more (d=768: 4.55 vs 5.07 ms), not for
+  // narrower FP8 rows nor for BF16 (their sweeps are not bound by the MFMA work it saves).
+  const bool grouped = spill_form == SOAR_SPILL_GROUPED ||
+                       (spill_form == 0 && fmt == LOWP_FP8 && lowp_padded_dim(fmt, d) >= 512 &&
+                        grouped_spill_pays(n, K));
   const GroupLayout GL = group_layout(L.group, n, K);
   LowpParams P;
   P.n = n; P.d = d; P.dp = lowp_padded_dim(fmt, d); P.K = K; P.topk = topk;
