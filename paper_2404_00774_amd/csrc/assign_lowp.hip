@@ -482,18 +482,43 @@ __device__ __forceinline__ float max16(float v) {
   return v;
 }
 
-// RS_MAXD: dimensions held per lane (lane l16 holds l16, l16 + 16, ...), d <= 16 * RS_MAXD.
-template <int FMT, bool SP, int RS_MAXD>
+// RS_MAXD: dimensions held per lane.  Scalar layout: lane l16 holds l16, l16 + 16, ...
+// (d <= 16 RS_MAXD).  V4 layout (d % 4 == 0, 16-byte aligned rows): lane l16 holds the float4
+// chunks 4 l16 + 64 m (d <= 16 RS_MAXD), so every load is a 16-byte vector load.  Values past d
+// are zero in both layouts, so the loops need no guards.
+template <bool V4>
+__device__ __forceinline__ int rs_dim(int l16, int m) {
+  return V4 ? 4 * l16 + 64 * (m >> 2) + (m & 3) : l16 + 16 * m;
+}
+template <bool V4, int RS_MAXD>
+__device__ __forceinline__ void rs_load(const float* __restrict__ p, int d, int l16,
+                                        float (&v)[RS_MAXD]) {
+  if constexpr (V4) {
+#pragma unroll
+    for (int m = 0; m < RS_MAXD; m += 4) {
+      const int k = 4 * l16 + 16 * m;
+      v4f t = {0.f, 0.f, 0.f, 0.f};
+      if (k < d) t = *reinterpret_cast<const v4f*>(p + k);
+      v[m] = t.x; v[m + 1] = t.y; v[m + 2] = t.z; v[m + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < RS_MAXD; ++m) {
+      const int k = l16 + 16 * m;
+      v[m] = k < d ? p[k] : 0.f;
+    }
+  }
+}
+
+template <int FMT, bool SP, int RS_MAXD, bool V4>
 __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
+  static_assert(!V4 || RS_MAXD % 4 == 0, "V4 layout holds whole float4 chunks");
   const int l16 = threadIdx.x & 15;
   const int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
   if (row >= live_rows(P.n, P.live_n)) return;
   const int d = P.d, topk = P.topk;
-  const int nd = (d - l16 + 15) / 16;   // dims this lane holds: l16, l16 + 16, ...
   float x[RS_MAXD], r[RS_MAXD];
-  const float* xr = P.X + row * d;
-#pragma unroll
-  for (int m = 0; m < RS_MAXD; ++m) x[m] = m < nd ? xr[l16 + 16 * m] : 0.f;
+  rs_load<V4, RS_MAXD>(P.X + row * d, d, l16, x);
   int pi = -1;
   float rr = 0.f;
   if constexpr (SP) {
@@ -502,11 +527,11 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
       if (l16 == 0) { P.spill[row] = -1; if (P.sloss) P.sloss[row] = kInf; }
       return;
     }
-    const float* cp = P.C + (int64_t)pi * d;
+    rs_load<V4, RS_MAXD>(P.C + (int64_t)pi * d, d, l16, r);
     float a0 = 0.f, a1 = 0.f;
 #pragma unroll
     for (int m = 0; m < RS_MAXD; ++m) {
-      r[m] = m < nd ? x[m] - cp[l16 + 16 * m] : 0.f;
+      r[m] = x[m] - r[m];
       if (m & 1) a1 = fmaf(r[m], r[m], a1); else a0 = fmaf(r[m], r[m], a0);
     }
     rr = sum16(a0 + a1);
@@ -521,15 +546,14 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
     if (c >= topk) continue;
     const int j = P.cand[row * topk + c];
     if (j < 0 || j >= P.K || (SP && j == pi)) continue;
-    const float* cj = P.C + (int64_t)j * d;
+    float cv[RS_MAXD];
+    rs_load<V4, RS_MAXD>(P.C + (int64_t)j * d, d, l16, cv);
     float s0 = 0.f, s1 = 0.f, p0 = 0.f, p1 = 0.f;
 #pragma unroll
     for (int m = 0; m < RS_MAXD; ++m) {
-      if (m < nd) {
-        const float e = x[m] - cj[l16 + 16 * m];
-        if (m & 1) { s1 = fmaf(e, e, s1); if (SP) p1 = fmaf(r[m], e, p1); }
-        else { s0 = fmaf(e, e, s0); if (SP) p0 = fmaf(r[m], e, p0); }
-      }
+      const float e = x[m] - cv[m];
+      if (m & 1) { s1 = fmaf(e, e, s1); if (SP) p1 = fmaf(r[m], e, p1); }
+      else { s0 = fmaf(e, e, s0); if (SP) p0 = fmaf(r[m], e, p0); }
     }
     const float sq = sum16(s0 + s1);
     float val = sq;
@@ -555,24 +579,23 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
   if (ntie >= 2) {
     double bd = __builtin_inf();
     int bdj = 0x7fffffff;
-    const float* cp = SP ? P.C + (int64_t)pi * d : nullptr;
+    float cpv[SP ? RS_MAXD : 1];
+    if constexpr (SP) rs_load<V4, RS_MAXD>(P.C + (int64_t)pi * d, d, l16, cpv);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       if (!(vals[c] <= lim)) continue;
       const int j = P.cand[row * topk + c];
-      const float* cj = P.C + (int64_t)j * d;
+      float cv[RS_MAXD];
+      rs_load<V4, RS_MAXD>(P.C + (int64_t)j * d, d, l16, cv);
       double sq = 0.0, pj = 0.0, r2 = 0.0;
 #pragma unroll
       for (int m = 0; m < RS_MAXD; ++m) {
-        if (m < nd) {
-          const int k = l16 + 16 * m;
-          const double e = (double)x[m] - (double)cj[k];
-          sq = fma(e, e, sq);
-          if (SP) {
-            const double rk = (double)x[m] - (double)cp[k];
-            pj = fma(rk, e, pj);
-            r2 = fma(rk, rk, r2);
-          }
+        const double e = (double)x[m] - (double)cv[m];
+        sq = fma(e, e, sq);
+        if constexpr (SP) {
+          const double rk = (double)x[m] - (double)cpv[m];
+          pj = fma(rk, e, pj);
+          r2 = fma(rk, rk, r2);
         }
       }
       sq = sum16d(sq);
@@ -594,18 +617,14 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
   }
   if (l16 == 0) { P.primary[row] = bj; if (P.pdist) P.pdist[row] = best; }
   // residual of the chosen primary, quantized for the spill sweep, and its row constants
-  const float* cp = P.C + (int64_t)bj * d;
+  rs_load<V4, RS_MAXD>(P.C + (int64_t)bj * d, d, l16, r);
   float a0 = 0.f, r0 = 0.f, m0 = 0.f;
 #pragma unroll
   for (int m = 0; m < RS_MAXD; ++m) {
-    if (m < nd) {
-      r[m] = x[m] - cp[l16 + 16 * m];
-      a0 = fmaf(r[m], x[m], a0);
-      r0 = fmaf(r[m], r[m], r0);
-      m0 = fmaxf(m0, fabsf(r[m]));
-    } else {
-      r[m] = 0.f;
-    }
+    r[m] = x[m] - r[m];
+    a0 = fmaf(r[m], x[m], a0);
+    r0 = fmaf(r[m], r[m], r0);
+    m0 = fmaxf(m0, fabsf(r[m]));
   }
   const float a = sum16(a0), r2 = sum16(r0);
   float inv = 1.f, scale = 1.f;
@@ -629,14 +648,18 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
   if constexpr (FMT == LOWP_FP8) {
     unsigned char* o = static_cast<unsigned char*>(P.Rq_out) + row * dp;
 #pragma unroll
-    for (int m = 0; m < RS_MAXD; ++m)
-      if (m < nd) o[l16 + 16 * m] = fp8_of(r[m] * scale);
+    for (int m = 0; m < RS_MAXD; ++m) {
+      const int k = rs_dim<V4>(l16, m);
+      if (k < d) o[k] = fp8_of(r[m] * scale);
+    }
     for (int k = d + l16; k < dp; k += 16) o[k] = (unsigned char)0;
   } else {
     __bf16* o = static_cast<__bf16*>(P.Rq_out) + row * dp;
 #pragma unroll
-    for (int m = 0; m < RS_MAXD; ++m)
-      if (m < nd) o[l16 + 16 * m] = (__bf16)(sigma * r[m]);
+    for (int m = 0; m < RS_MAXD; ++m) {
+      const int k = rs_dim<V4>(l16, m);
+      if (k < d) o[k] = (__bf16)(sigma * r[m]);
+    }
     for (int k = d + l16; k < dp; k += 16) o[k] = (__bf16)0.f;
   }
 }
@@ -826,25 +849,35 @@ hipError_t launch_lowp_pack_codebook(int fmt, const float* C, int K, int d, cons
 #undef SOAR_DP_CASES
 
 template <int FMT, int M>
-static void rescore_m(const LowpParams& P, bool spill, hipStream_t st) {
+static void rescore_m(const LowpParams& P, bool spill, bool v4, hipStream_t st) {
   const dim3 grid((unsigned)((P.n + 15) / 16)), block(256);
-  if (spill) hipLaunchKernelGGL((lowp_rescore_kernel<FMT, true, M>), grid, block, 0, st, P);
-  else hipLaunchKernelGGL((lowp_rescore_kernel<FMT, false, M>), grid, block, 0, st, P);
+  if constexpr (M % 4 == 0) {
+    if (v4) {
+      if (spill) hipLaunchKernelGGL((lowp_rescore_kernel<FMT, true, M, true>), grid, block, 0, st, P);
+      else hipLaunchKernelGGL((lowp_rescore_kernel<FMT, false, M, true>), grid, block, 0, st, P);
+      return;
+    }
+  }
+  if (spill) hipLaunchKernelGGL((lowp_rescore_kernel<FMT, true, M, false>), grid, block, 0, st, P);
+  else hipLaunchKernelGGL((lowp_rescore_kernel<FMT, false, M, false>), grid, block, 0, st, P);
 }
 
 template <int FMT>
 static hipError_t rescore_fmt(const LowpParams& P, bool spill, hipStream_t st) {
-  const int m = (P.d + 15) / 16;
-  if (m <= 2) rescore_m<FMT, 2>(P, spill, st);
-  else if (m <= 4) rescore_m<FMT, 4>(P, spill, st);
-  else if (m <= 6) rescore_m<FMT, 6>(P, spill, st);
-  else if (m <= 8) rescore_m<FMT, 8>(P, spill, st);
-  else if (m <= 12) rescore_m<FMT, 12>(P, spill, st);
-  else if (m <= 16) rescore_m<FMT, 16>(P, spill, st);
-  else if (m <= 24) rescore_m<FMT, 24>(P, spill, st);
-  else if (m <= 32) rescore_m<FMT, 32>(P, spill, st);
-  else if (m <= 48) rescore_m<FMT, 48>(P, spill, st);
-  else if (m <= 64) rescore_m<FMT, 64>(P, spill, st);
+  // float4 layout when the rows allow it: ceil(d / 64) chunks of 4 per lane
+  const bool v4 = P.d % 4 == 0 && reinterpret_cast<uintptr_t>(P.X) % 16 == 0 &&
+                  reinterpret_cast<uintptr_t>(P.C) % 16 == 0;
+  const int m = v4 ? 4 * ((P.d + 63) / 64) : (P.d + 15) / 16;
+  if (m <= 2) rescore_m<FMT, 2>(P, spill, v4, st);
+  else if (m <= 4) rescore_m<FMT, 4>(P, spill, v4, st);
+  else if (m <= 6) rescore_m<FMT, 6>(P, spill, v4, st);
+  else if (m <= 8) rescore_m<FMT, 8>(P, spill, v4, st);
+  else if (m <= 12) rescore_m<FMT, 12>(P, spill, v4, st);
+  else if (m <= 16) rescore_m<FMT, 16>(P, spill, v4, st);
+  else if (m <= 24) rescore_m<FMT, 24>(P, spill, v4, st);
+  else if (m <= 32) rescore_m<FMT, 32>(P, spill, v4, st);
+  else if (m <= 48) rescore_m<FMT, 48>(P, spill, v4, st);
+  else if (m <= 64) rescore_m<FMT, 64>(P, spill, v4, st);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

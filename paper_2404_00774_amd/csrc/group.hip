@@ -84,16 +84,73 @@ __global__ __launch_bounds__(256) void group_scatter_kernel(const int32_t* __res
   }
 }
 
+// One thread per stripe; its partition is the last p with sbeg[p] <= s (binary search).
 __global__ __launch_bounds__(256) void group_stripes_kernel(const int32_t* __restrict__ cnt,
                                                             const int32_t* __restrict__ off,
                                                             const int32_t* __restrict__ sbeg,
-                                                            int K, int4* stripes) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= K) return;
-  const int c = cnt[p], o = off[p], s0 = sbeg[p];
-  for (int s = 0; s * GROUP_ROWS < c; ++s) {
-    const int rows = c - s * GROUP_ROWS < GROUP_ROWS ? c - s * GROUP_ROWS : GROUP_ROWS;
-    stripes[s0 + s] = int4{p, o + s * GROUP_ROWS, rows, 0};
+                                                            int K, const int32_t* meta,
+                                                            int64_t max_stripes, int4* stripes) {
+  const int ns = meta[0];
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < ns && s < max_stripes;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = K - 1;               // sbeg[lo] <= s < sbeg[hi + 1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sbeg[mid] <= s) lo = mid; else hi = mid - 1;
+    }
+    const int p = lo, k = (int)(s - sbeg[p]), c = cnt[p];
+    const int rows = c - k * GROUP_ROWS < GROUP_ROWS ? c - k * GROUP_ROWS : GROUP_ROWS;
+    stripes[s] = int4{p, off[p] + k * GROUP_ROWS, rows, 0};
+  }
+}
+
+// Histogram and scatter with per-block counts in LDS (K <= GROUP_LDS_K): one global atomic per
+// block and partition instead of one per row, so rows piling onto a few partitions do not
+// serialize on their counters.
+constexpr int GROUP_LDS_K = 16384;
+constexpr int GROUP_ROWS_PER_BLOCK = 8192;
+
+__global__ __launch_bounds__(1024) void group_hist_lds_kernel(const int32_t* __restrict__ prim,
+                                                              int64_t cap, const int64_t* live,
+                                                              int K, int32_t* cnt) {
+  __shared__ int32_t h[GROUP_LDS_K];
+  const int64_t n = live_rows(cap, live);
+  const int64_t r0 = (int64_t)blockIdx.x * GROUP_ROWS_PER_BLOCK;
+  if (r0 >= n) return;
+  for (int p = threadIdx.x; p < K; p += 1024) h[p] = 0;
+  __syncthreads();
+  const int64_t r1 = r0 + GROUP_ROWS_PER_BLOCK < n ? r0 + GROUP_ROWS_PER_BLOCK : n;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += 1024) {
+    const int p = prim[i];
+    if (p >= 0 && p < K) atomicAdd(&h[p], 1);
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < K; p += 1024)
+    if (h[p]) atomicAdd(&cnt[p], h[p]);
+}
+
+__global__ __launch_bounds__(1024) void group_scatter_lds_kernel(
+    const int32_t* __restrict__ prim, int64_t cap, const int64_t* live, int K,
+    const int32_t* __restrict__ off, int32_t* cursor, int32_t* perm) {
+  __shared__ int32_t h[GROUP_LDS_K];      // block counts, then the block's first position
+  __shared__ int32_t c2[GROUP_LDS_K];     // running position inside the block's range
+  const int64_t n = live_rows(cap, live);
+  const int64_t r0 = (int64_t)blockIdx.x * GROUP_ROWS_PER_BLOCK;
+  if (r0 >= n) return;
+  for (int p = threadIdx.x; p < K; p += 1024) { h[p] = 0; c2[p] = 0; }
+  __syncthreads();
+  const int64_t r1 = r0 + GROUP_ROWS_PER_BLOCK < n ? r0 + GROUP_ROWS_PER_BLOCK : n;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += 1024) {
+    const int p = prim[i];
+    if (p >= 0 && p < K) atomicAdd(&h[p], 1);
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < K; p += 1024)
+    if (h[p]) h[p] = off[p] + atomicAdd(&cursor[p], h[p]);
+  __syncthreads();
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += 1024) {
+    const int p = prim[i];
+    if (p >= 0 && p < K) perm[h[p] + atomicAdd(&c2[p], 1)] = (int32_t)i;
   }
 }
 
@@ -133,14 +190,25 @@ hipError_t launch_group_by_primary(const int32_t* prim, int64_t cap, const int64
   const unsigned gk = (unsigned)((K + 255) / 256);
   hipLaunchKernelGGL(group_fill_kernel, dim3(gk), dim3(256), 0, st, L.cnt, (int64_t)K, 0);
   hipLaunchKernelGGL(group_fill_kernel, dim3(gk), dim3(256), 0, st, L.cursor, (int64_t)K, 0);
-  hipLaunchKernelGGL(group_hist_kernel, dim3(grid_rows(cap)), dim3(256), 0, st, prim, cap, live_n,
-                     K, L.cnt);
+  const bool lds = K <= GROUP_LDS_K;
+  const unsigned gb = (unsigned)((cap + GROUP_ROWS_PER_BLOCK - 1) / GROUP_ROWS_PER_BLOCK);
+  if (lds)
+    hipLaunchKernelGGL(group_hist_lds_kernel, dim3(gb > 0 ? gb : 1), dim3(1024), 0, st, prim, cap,
+                       live_n, K, L.cnt);
+  else
+    hipLaunchKernelGGL(group_hist_kernel, dim3(grid_rows(cap)), dim3(256), 0, st, prim, cap,
+                       live_n, K, L.cnt);
   hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, st, L.cnt, K, L.off, L.sbeg,
                      L.meta);
-  hipLaunchKernelGGL(group_scatter_kernel, dim3(grid_rows(cap)), dim3(256), 0, st, prim, cap,
-                     live_n, K, L.off, L.cursor, L.perm);
-  hipLaunchKernelGGL(group_stripes_kernel, dim3(gk), dim3(256), 0, st, L.cnt, L.off, L.sbeg, K,
-                     L.stripes);
+  if (lds)
+    hipLaunchKernelGGL(group_scatter_lds_kernel, dim3(gb > 0 ? gb : 1), dim3(1024), 0, st, prim,
+                       cap, live_n, K, L.off, L.cursor, L.perm);
+  else
+    hipLaunchKernelGGL(group_scatter_kernel, dim3(grid_rows(cap)), dim3(256), 0, st, prim, cap,
+                       live_n, K, L.off, L.cursor, L.perm);
+  const int64_t ms = group_max_stripes(cap, K);
+  hipLaunchKernelGGL(group_stripes_kernel, dim3(grid_rows(ms)), dim3(256), 0, st, L.cnt, L.off,
+                     L.sbeg, K, L.meta, ms, L.stripes);
   return hipGetLastError();
 }
 
