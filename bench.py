@@ -38,12 +38,12 @@ COPY_SCALE = {"fetch": 1048576.0 / 524302.5, "write": 1.0}
 TRAFFIC = {
     # grouped FP32 pipeline, per step: primary pass, grouping by primary, grouped spill pass
     ("fp32", "mix4096_n1m_d128"): dict(
-        fetch_kib=255858.7 + 1964.1 + 6.8 + 2296.7 + 20.3 + 2 * 10.2 + 260955.2,
-        write_kib=7819.7 + 28148.3 + 15.7 + 47574.8 + 1056.4 + 2 * 7.8 + 65576.7,
+        fetch_kib=256081.3 + 1966.1 + 6.8 + 2040.1 + 85.3 + 2 * 10.2 + 261333.8,
+        write_kib=7819.7 + 960.1 + 15.7 + 10994.3 + 1056.3 + 2 * 7.8 + 65569.0,
         sources={"paper_2404_00774_amd/csrc/assign_fp32.hip":
-                 "3746d1f237284d3f7a0d1573231315cf27436bc0a40b9600642d6662d306f40f",
+                 "77e2aeb0b5788f42c7182332b4df958c66fa93e9f446b84e5c73b3cd7e61c915",
                  "paper_2404_00774_amd/csrc/group.hip":
-                 "63ab42f260ff6e77eac7f7e9d2145dfeafcf7513e60647e799b74fae44283f1a"}),
+                 "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198"}),
 }
 
 
