@@ -17,9 +17,9 @@
 //
 // Candidates.  In the 16x16 MFMA result a lane sees one column of every 16-column block, so per
 // row the 16 lanes of a lane group see the 16 residue classes of j mod 16.  Each lane keeps the
-// minimum of its class: (tile mod TG, block) is packed into the four low mantissa bits of the
-// value (at most a 2^-19 relative perturbation; the mask ~15 is an inline constant, so packing is
-// one v_and_or) and the tile group (tile / TG) is recorded when the minimum has improved over a
+// minimum of its class: (tile mod TG, block) is packed into the six low mantissa bits of the
+// value (at most a 2^-17 relative perturbation; with the mask held in a register, packing is one
+// v_and_or) and the tile group (tile / TG) is recorded when the minimum has improved over a
 // group.
 // The topk (<= 8) smallest of the 16 class minima are re-scored.
 #include <type_traits>
@@ -50,12 +50,20 @@ struct FmtTraits<LOWP_FP8> {
   static constexpr int LANE_B = 32;
 };
 
-// Four low mantissa bits carry a code < 16 (tile within its group, block within the tile).
-__device__ __forceinline__ float pack_code(float v, unsigned c) {
-  return __builtin_bit_cast(float, (__builtin_bit_cast(unsigned, v) & ~15u) | c);
+// Six low mantissa bits carry a code < 64 (tile within its group, block within the tile).  The
+// mask ~63 is not an inline constant, so the sweep keeps it in a register (code_mask) and packing
+// stays one v_and_or.
+constexpr int kCodes = 64;
+__device__ __forceinline__ unsigned code_mask() {
+  unsigned m;
+  asm volatile("v_mov_b32 %0, -64" : "=v"(m));   // ~63, opaque to constant folding
+  return m;
+}
+__device__ __forceinline__ float pack_code(float v, unsigned mask, unsigned c) {
+  return __builtin_bit_cast(float, (__builtin_bit_cast(unsigned, v) & mask) | c);
 }
 __device__ __forceinline__ unsigned packed_code(float v) {
-  return __builtin_bit_cast(unsigned, v) & 15u;
+  return __builtin_bit_cast(unsigned, v) & (unsigned)(kCodes - 1);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -231,8 +239,7 @@ void lowp_sweep_kernel(LowpParams P) {
   using R = TileRec<FMT, DP, BN>;
   constexpr bool BF = FMT == LOWP_BF16;
   constexpr int NB = BN / 16;                      // 16-column blocks per tile
-  constexpr int GB = NB < 4 ? NB : 4;              // blocks computed together
-  static_assert(NB % GB == 0 && NB <= 8, "tile of at most 8 blocks");
+  static_assert(NB <= 8 && (NB == 1 || NB % 2 == 0), "tile of 1, 2, 4 or 8 blocks");
   constexpr int NSTEP = OperandRegs<FMT, DP>::NSTEP, W4 = OperandRegs<FMT, DP>::W4;
   constexpr int NR = SPW * 4;                      // rows per lane in the output layout
   __shared__ __attribute__((aligned(16))) char s_ring[STG * R::STAGE];
@@ -260,8 +267,19 @@ void lowp_sweep_kernel(LowpParams P) {
     else { const int64_t r = row0 + st * 16 + lr; return r < n ? r : -1; }
   };
 
-  issue_record<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, 0, w, lane);
-  if constexpr (STG > 2) { if (ntiles > 1) issue_record<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, 1, w, lane); }
+  // copies of record t into its ring stage; short records keep their per-lane source offsets in
+  // registers, long ones (many copies per wave) recompute them
+  constexpr bool KEEP_OFF = R::NI <= 4;
+  unsigned roff[KEEP_OFF ? R::NI : 1];
+  if constexpr (KEEP_OFF) record_offsets<R::BYTES, R::NI>(w, lane, roff);
+  auto issue = [&](int t) __attribute__((always_inline)) {
+    if constexpr (KEEP_OFF) issue_record_at<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, t, w, roff);
+    else issue_record<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, t, w, lane);
+  };
+  issue(0);
+  if constexpr (STG > 2) {
+    if (ntiles > 1) issue(1);
+  }
 
   // A operands (A layout: lane (q, c16) holds row c16 of each stripe, quarter q of the dims)
   OperandRegs<FMT, DP> xa[SPW];
@@ -307,9 +325,10 @@ void lowp_sweep_kernel(LowpParams P) {
         a2[st][v] = 2.f * rc.w * rc.y;       // BF16: 2 sigma <r, x>
       }
     }
-  // (tile mod TG, block) codes fill the four packed bits; the group t / TG is tracked per row
-  constexpr int TG = 16 / NB;
-  static_assert(TG >= 1, "at most 16 blocks per tile");
+  // (tile mod TG, block) codes fill the packed bits; the group t / TG is tracked per row
+  constexpr int TG = kCodes / NB;
+  static_assert(TG >= 1, "at most 64 blocks per tile");
+  const unsigned cmask = code_mask();
   float b1[NR], old[NR];
   int bt[NR];
 #pragma unroll
@@ -317,125 +336,282 @@ void lowp_sweep_kernel(LowpParams P) {
   // lane's base addresses inside a ring stage: B operand rows and the norms
   const int lane_b = c16 * R::LDWB + (q * (DP / 4)) * T::BYTES;
   const int lane_cn = R::CN_OFF + c16 * 16;
-  int stage = 0;
 
-  for (int t = 0; t < ntiles; ++t) {
-    // record t has landed in LDS for this wave (later records may still be in flight) ...
-    // (vmcnt counts VMEM operations of this wave in order: with a later record in flight, at most
-    // its NI copies may remain outstanding)
-    if (STG > 2 && t + 1 < ntiles)
-      wait_vmcnt<R::NI>();
-    else
-      wait_vmcnt<0>();
-    // ... and for every wave; every wave is also done reading the stage refilled next
-    __builtin_amdgcn_s_barrier();
-    if (t + STG - 1 < ntiles) issue_record<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, t + STG - 1, w, lane);
-    const char* tile = s_ring + stage * R::STAGE;
+  // Software pipeline over units of GU blocks (two units per tile, or one tile per unit when the
+  // tile has a single block).  The MFMAs of unit u run interleaved with the epilogue of unit u - 1,
+  // whose results are complete by then, so the matrix core and the VALU work side by side instead
+  // of the epilogue waiting on the last MFMAs of its own unit.  Units alternate between two
+  // accumulator sets; an epilogue reads registers only (FP8 column scales and norms are copied out
+  // of LDS with the unit's operands), so the ring stage of a finished tile can be refilled while
+  // its last epilogue is still pending.
+  constexpr bool ST2 = SP && !GPD;                 // second MFMA stream (residual rows)
+  // The pipeline keeps two accumulator sets live; a direct spill over long rows (whose X and R
+  // operands fill most of the registers) runs each unit's epilogue right after its MFMAs instead.
+  constexpr bool PIPE = !(ST2 && DP * T::BYTES > 512);
+  constexpr int GU = PIPE ? (NB >= 2 ? NB / 2 : 1) : NB;   // blocks per unit
+  static_assert(PIPE || NB <= 4, "one unit per tile without the pipeline");
+  constexpr int NU = NB / GU;                      // units per tile
+  v4f accS[2][SPW][GU], accT[2][ST2 ? SPW : 1][GU];
+  float ucs[2][BF ? 1 : GU], ucn[2][BF ? 1 : GU];
+
+  auto mfma_unit = [&](auto set, const char* tile, int g) __attribute__((always_inline)) {
+    constexpr int S = decltype(set)::value;
     const char* tb = tile + lane_b;
-    const char* tcn = tile + lane_cn;
-    stage = stage + 1 == STG ? 0 : stage + 1;
-    const unsigned tcode = (unsigned)((t % TG) * NB);
-    // does this tile hold the primary of any row of the wave?
-    bool masked = false;
-    if constexpr (SP) {
+#pragma unroll
+    for (int b = 0; b < GU; ++b) {
+      const int blk = g * GU + b;
+      v4f init = v4f{0.f, 0.f, 0.f, 0.f};
+      if constexpr (BF) {
+        init = *reinterpret_cast<const v4f*>(tile + lane_cn + blk * 256);
+      } else {
+        const int jl = blk * 16 + c16;
+        ucs[S][b] = *reinterpret_cast<const float*>(tile + R::CS_OFF + jl * 4);
+        ucn[S][b] = *reinterpret_cast<const float*>(tile + R::CN_OFF + jl * 16);
+      }
+#pragma unroll
+      for (int st = 0; st < SPW; ++st) {
+        accS[S][st][b] = init;
+        if constexpr (ST2) accT[S][st][b] = BF ? a2[st] : v4f{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NSTEP; ++s) {
+      u32x4 bv[GU][W4];
+#pragma unroll
+      for (int b = 0; b < GU; ++b)
+#pragma unroll
+        for (int ww = 0; ww < W4; ++ww)
+          bv[b][ww] = *reinterpret_cast<const u32x4*>(tb + (g * GU + b) * 16 * R::LDWB +
+                                                      s * T::LANE_B + ww * 16);
+#pragma unroll
+      for (int b = 0; b < GU; ++b)
+#pragma unroll
+        for (int st = 0; st < SPW; ++st) {
+          accS[S][st][b] = mfma_step<FMT>(xa[st].v[s], bv[b], accS[S][st][b]);
+          if constexpr (ST2) accT[S][st][b] = mfma_step<FMT>(ra[st].v[s], bv[b], accT[S][st][b]);
+        }
+    }
+  };
+
+  // Epilogue of unit (ts, g) from accumulator set S: ranking values, class minima (block index
+  // packed in the low mantissa bits); with_mask compares the columns against each row's primary
+  // and only runs for tiles that hold one.  It is split into a preparation and one slot per row
+  // of the lane (i = st * 4 + v), so that the slots can be spread between MFMAs.
+  unsigned etc[GU];                               // the unit's block codes (wave-uniform)
+  float espv[GPD ? SPW : 1][GU];                  // GPD: S of each stripe's centroid row
+  auto epi_prep = [&](auto set, int ts, int g) __attribute__((always_inline)) {
+    constexpr int S = decltype(set)::value;
+    // each packing is then one v_and_or with an SGPR
+#pragma unroll
+    for (int b = 0; b < GU; ++b)
+      etc[b] = (unsigned)__builtin_amdgcn_readfirstlane((ts % TG) * NB + g * GU + b);
+    // GPD: stripe row 15 is lane group 3, register 3
+    if constexpr (GPD) {
+#pragma unroll
+      for (int st = 0; st < SPW; ++st)
+#pragma unroll
+        for (int b = 0; b < GU; ++b) {
+          const float v3 = BF ? accS[S][st][b][3]
+                              : fmaf(accS[S][st][b][3], ks[st * 4 + 3] * ucs[S][b], ucn[S][b]);
+          espv[st][b] = __shfl(v3, 48 + c16);
+        }
+    }
+  };
+  auto epi_slot = [&](auto set, auto with_mask, int i, int ts, int g)
+                      __attribute__((always_inline)) {
+    constexpr int S = decltype(set)::value;
+    const int st = i / 4, v = i % 4;
+    float pv[GU];
+#pragma unroll
+    for (int b = 0; b < GU; ++b) {
+      // S = ||c_j||^2 - 2 <row, c_j> (BF16: the accumulator itself)
+      float val = BF ? accS[S][st][b][v]
+                     : fmaf(accS[S][st][b][v], ks[st * 4 + v] * ucs[S][b], ucn[S][b]);
+      if constexpr (GPD) {
+        const float tt = fmaf(gs[i], espv[st][b] - val, gm[i]);
+        val = fmaf(tt, tt, val);
+      } else if constexpr (SP && BF) {
+        val = fmaf(accT[S][st][b][v], accT[S][st][b][v], val);
+      } else if constexpr (SP) {
+        const float e = accT[S][st][b][v] * (kt[i] * ucs[S][b]) - ka[i];
+        val = fmaf(kl[i] * e, e, val);
+      }
+      if constexpr (SP && decltype(with_mask)::value)
+        val = (ts * BN + (g * GU + b) * 16 + c16 == kp[i]) ? kBig : val;
+      pv[b] = pack_code(val, cmask, etc[b]);
+    }
+    float m = pv[0];
+#pragma unroll
+    for (int b = 1; b < GU; ++b) m = fminf(m, pv[b]);
+    b1[i] = fminf(b1[i], m);
+  };
+  auto epi_unit = [&](auto set, auto with_mask, int ts, int g) __attribute__((always_inline)) {
+    epi_prep(set, ts, g);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) epi_slot(set, with_mask, i, ts, g);
+  };
+
+  // The MFMAs of unit (t, g) into set S with the epilogue of the previous unit (set 1 - S) placed
+  // by hand between them: a few row slots while the first operands arrive from LDS, the rest
+  // spread evenly after the MFMAs; scheduling barriers keep that order, so the wave always has
+  // independent VALU work to issue while the matrix core runs.
+  auto fused_unit = [&](auto set, const char* tile, int g, int tsp, int gp)
+                        __attribute__((always_inline)) {
+    constexpr int S = decltype(set)::value;
+    const auto pset = std::integral_constant<int, 1 - S>{};
+    constexpr int NMI = NSTEP * GU * SPW * (ST2 ? 2 : 1);   // MFMAs of the unit
+    constexpr int PRE = NR / 4;                              // slots before the first MFMA
+    const char* tb = tile + lane_b;
+    v4f init[GU];
+#pragma unroll
+    for (int b = 0; b < GU; ++b) {
+      const int blk = g * GU + b;
+      if constexpr (BF) {
+        init[b] = *reinterpret_cast<const v4f*>(tile + lane_cn + blk * 256);
+      } else {
+        init[b] = v4f{0.f, 0.f, 0.f, 0.f};
+        const int jl = blk * 16 + c16;
+        ucs[S][b] = *reinterpret_cast<const float*>(tile + R::CS_OFF + jl * 4);
+        ucn[S][b] = *reinterpret_cast<const float*>(tile + R::CN_OFF + jl * 16);
+      }
+    }
+    u32x4 bv[2][GU][W4];
+    auto read_step = [&](int s, int k) __attribute__((always_inline)) {
+#pragma unroll
+      for (int b = 0; b < GU; ++b)
+#pragma unroll
+        for (int ww = 0; ww < W4; ++ww)
+          bv[k][b][ww] = *reinterpret_cast<const u32x4*>(tb + (g * GU + b) * 16 * R::LDWB +
+                                                         s * T::LANE_B + ww * 16);
+    };
+    read_step(0, 0);
+    if constexpr (NSTEP > 1) read_step(1, 1);
+    epi_prep(pset, tsp, gp);
+#pragma unroll
+    for (int i = 0; i < PRE; ++i) epi_slot(pset, std::false_type{}, i, tsp, gp);
+    __builtin_amdgcn_sched_barrier(0);
+    int mi = 0;                                    // MFMAs issued so far (compile-time)
+#pragma unroll
+    for (int s = 0; s < NSTEP; ++s) {
+#pragma unroll
+      for (int b = 0; b < GU; ++b)
+#pragma unroll
+        for (int st = 0; st < SPW; ++st)
+#pragma unroll
+          for (int x = 0; x < (ST2 ? 2 : 1); ++x) {
+            if (x == 0) {
+              accS[S][st][b] = mfma_step<FMT>(xa[st].v[s], bv[s & 1][b],
+                                              s == 0 ? init[b] : accS[S][st][b]);
+            } else {
+              const v4f c0 = BF ? a2[st] : v4f{0.f, 0.f, 0.f, 0.f};
+              accT[S][st][b] = mfma_step<FMT>(ra[st].v[s], bv[s & 1][b],
+                                              s == 0 ? c0 : accT[S][st][b]);
+            }
+            // row slots [lo, hi) follow MFMA mi
+            const int lo = PRE + mi * (NR - PRE) / NMI, hi = PRE + (mi + 1) * (NR - PRE) / NMI;
+#pragma unroll
+            for (int i = PRE; i < NR; ++i)
+              if (i >= lo && i < hi) epi_slot(pset, std::false_type{}, i, tsp, gp);
+            ++mi;
+            __builtin_amdgcn_sched_barrier(0);
+          }
+      if (s + 2 < NSTEP) read_step(s + 2, s & 1);
+    }
+  };
+
+  // does tile t hold the primary of any row of the wave? (wave-uniform)
+  auto tile_masked = [&](int t) __attribute__((always_inline)) -> bool {
+    if constexpr (!SP) {
+      return false;
+    } else {
       bool hit = false;
 #pragma unroll
       for (int i = 0; i < NRS; ++i) hit |= (unsigned)(kp[i] - t * BN) < (unsigned)BN;
-      masked = __builtin_amdgcn_readfirstlane((int)__any(hit)) != 0;   // wave-uniform
+      return __builtin_amdgcn_readfirstlane((int)__any(hit)) != 0;
     }
-#pragma unroll
-    for (int g = 0; g < NB / GB; ++g) {
-      v4f accS[SPW][GB], accT[SP && !GPD ? SPW : 1][GB];
-#pragma unroll
-      for (int b = 0; b < GB; ++b) {
-        const v4f init = BF ? *reinterpret_cast<const v4f*>(tcn + (g * GB + b) * 256)
-                            : v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int st = 0; st < SPW; ++st) {
-          accS[st][b] = init;
-          if constexpr (SP && !GPD) accT[st][b] = BF ? a2[st] : v4f{0.f, 0.f, 0.f, 0.f};
-        }
-      }
-#pragma unroll
-      for (int s = 0; s < NSTEP; ++s) {
-        u32x4 bv[GB][W4];
-#pragma unroll
-        for (int b = 0; b < GB; ++b)
-#pragma unroll
-          for (int ww = 0; ww < W4; ++ww)
-            bv[b][ww] = *reinterpret_cast<const u32x4*>(
-                tb + (g * GB + b) * 16 * R::LDWB + s * T::LANE_B + ww * 16);
-#pragma unroll
-        for (int b = 0; b < GB; ++b)
-#pragma unroll
-          for (int st = 0; st < SPW; ++st) {
-            accS[st][b] = mfma_step<FMT>(xa[st].v[s], bv[b], accS[st][b]);
-            if constexpr (SP && !GPD)
-              accT[st][b] = mfma_step<FMT>(ra[st].v[s], bv[b], accT[st][b]);
-          }
-      }
-      // epilogue: ranking values, class minima (block index packed in the low mantissa bits);
-      // the compare against each row's primary only runs in tiles that hold one
-      // S = ||c_j||^2 - 2 <row, c_j> of every lane's rows (BF16: the accumulator itself)
-      auto s_val = [&](int st, int b, int v) -> float {
-        if constexpr (BF) {
-          return accS[st][b][v];
-        } else {
-          const int jl = (g * GB + b) * 16 + c16;
-          const float cs = *reinterpret_cast<const float*>(tile + R::CS_OFF + jl * 4);
-          const float cn = *reinterpret_cast<const float*>(tile + R::CN_OFF + jl * 16);
-          return fmaf(accS[st][b][v], ks[st * 4 + v] * cs, cn);
-        }
-      };
-      // GPD: S of the stripe's centroid row (stripe row 15: lane group 3, register 3)
-      float spv[GPD ? SPW : 1][GB];
-      if constexpr (GPD) {
-#pragma unroll
-        for (int st = 0; st < SPW; ++st)
-#pragma unroll
-          for (int b = 0; b < GB; ++b) spv[st][b] = __shfl(s_val(st, b, 3), 48 + c16);
-      }
-      auto epilogue = [&](auto with_mask) {
-#pragma unroll
-        for (int st = 0; st < SPW; ++st)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = st * 4 + v;
-            float pv[GB];
-#pragma unroll
-            for (int b = 0; b < GB; ++b) {
-              const int jl = (g * GB + b) * 16 + c16;
-              float val = s_val(st, b, v);
-              if constexpr (GPD) {
-                const float tt = fmaf(gs[i], spv[st][b] - val, gm[i]);
-                val = fmaf(tt, tt, val);
-              } else if constexpr (SP && BF) {
-                val = fmaf(accT[st][b][v], accT[st][b][v], val);
-              } else if constexpr (SP) {
-                const float cs = *reinterpret_cast<const float*>(tile + R::CS_OFF + jl * 4);
-                const float e = accT[st][b][v] * (kt[i] * cs) - ka[i];
-                val = fmaf(kl[i] * e, e, val);
-              }
-              if constexpr (SP && decltype(with_mask)::value)
-                val = (t * BN + jl == kp[i]) ? kBig : val;
-              pv[b] = pack_code(val, tcode + (unsigned)(g * GB + b));
-            }
-            float m = pv[0];
-#pragma unroll
-            for (int b = 1; b < GB; ++b) m = fminf(m, pv[b]);
-            b1[i] = fminf(b1[i], m);
-          }
-      };
-      if (__builtin_expect(SP && masked, 0)) epilogue(std::true_type{});
-      else epilogue(std::false_type{});
-    }
-    if ((t + 1) % TG == 0 || t + 1 == ntiles) {
+  };
+  // after the last epilogue of tile ts: record the tile group of every improved minimum
+  auto close_tile = [&](int ts) __attribute__((always_inline)) {
+    // (a real branch: the updates run once per tile group, not as selects in every tile)
+    if (__builtin_expect((ts + 1) % TG == 0 || ts + 1 == ntiles, 0)) {
 #pragma unroll
       for (int i = 0; i < NR; ++i) {
-        bt[i] = b1[i] < old[i] ? t / TG : bt[i];
+        bt[i] = b1[i] < old[i] ? ts / TG : bt[i];
         old[i] = b1[i];
       }
     }
+  };
+
+  const char* tile = s_ring;
+  int stage = 0;
+  bool m_cur = false, m_last = false;             // masks of the current and the previous tile
+  // One pipeline step: unit u = (t, g) into set S, the epilogue of unit u - 1 from set 1 - S.
+  auto step = [&](auto set, int u) __attribute__((always_inline)) {
+    constexpr int S = decltype(set)::value;
+    constexpr int G = NU == 2 ? S : 0;             // unit u has g = u % NU = S when NU == 2
+    const int t = NU == 2 ? (u >> 1) : u;
+    if (G == 0) {
+      // record t has landed in LDS for this wave (later records may still be in flight) ...
+      // (vmcnt counts VMEM operations of this wave in order: with a later record in flight, at
+      // most its NI copies may remain outstanding)
+      if (STG > 2 && t + 1 < ntiles)
+        wait_vmcnt<R::NI>();
+      else
+        wait_vmcnt<0>();
+      // ... and for every wave; every wave is also done reading the stage refilled next (its
+      // last reads were the B operands of tile t - 1, issued before this barrier)
+      __builtin_amdgcn_s_barrier();
+      if (t + STG - 1 < ntiles)
+        issue(t + STG - 1);
+      tile = s_ring + stage * R::STAGE;
+      stage = stage + 1 == STG ? 0 : stage + 1;
+      m_last = m_cur;
+      m_cur = tile_masked(t);
+    }
+    if constexpr (!PIPE) {
+      const auto s0 = std::integral_constant<int, 0>{};
+      mfma_unit(s0, tile, G);
+      if (__builtin_expect(m_cur, 0)) epi_unit(s0, std::true_type{}, t, G);
+      else epi_unit(s0, std::false_type{}, t, G);
+      if (G == NU - 1) close_tile(t);
+      return;
+    }
+    constexpr int GP = NU == 2 ? 1 - S : 0;        // the previous unit's g
+    constexpr bool SAME_TILE = NU == 2 && S == 1;  // the previous unit is in tile t
+    const int tp = SAME_TILE ? t : t - 1;
+    const bool mp = SAME_TILE ? m_cur : m_last;
+    const auto prev = std::integral_constant<int, 1 - S>{};
+    if (u == 0) {
+      mfma_unit(set, tile, G);
+    } else if (__builtin_expect(mp, 0)) {
+      epi_unit(prev, std::true_type{}, tp, GP);
+      mfma_unit(set, tile, G);
+    } else {
+      fused_unit(set, tile, G, tp, GP);
+    }
+    if (u > 0 && GP == NU - 1) close_tile(tp);
+  };
+  const int nunits = ntiles * NU;
+  if constexpr (PIPE) {
+    for (int u = 0; u < nunits; u += 2) {
+      step(std::integral_constant<int, 0>{}, u);
+      if (u + 1 < nunits) step(std::integral_constant<int, 1>{}, u + 1);
+    }
+  } else {
+    for (int u = 0; u < nunits; ++u) step(std::integral_constant<int, 0>{}, u);
+  }
+  // drain: the epilogue of the last unit
+  if constexpr (PIPE) {
+    const int ul = nunits - 1;
+    const bool ml = m_cur;                       // the last unit is in the last tile
+    if (ul & 1) {
+      if (ml) epi_unit(std::integral_constant<int, 1>{}, std::true_type{}, ntiles - 1, NU - 1);
+      else epi_unit(std::integral_constant<int, 1>{}, std::false_type{}, ntiles - 1, NU - 1);
+    } else {
+      if (ml) epi_unit(std::integral_constant<int, 0>{}, std::true_type{}, ntiles - 1, NU - 1);
+      else epi_unit(std::integral_constant<int, 0>{}, std::false_type{}, ntiles - 1, NU - 1);
+    }
+    close_tile(ntiles - 1);
   }
 
   // candidates: rank the 16 class minima of every row, keep the topk smallest

@@ -77,17 +77,42 @@ __device__ __forceinline__ void wait_vmcnt() {
 // Copy record t into ring stage t % STG with direct global->LDS loads: every wave issues exactly
 // NI copies of 64 x 16 bytes (source addresses past the record end are clamped to its last
 // chunk), so the number of outstanding copies is the same in every wave.
+// The wave index and the LDS destination are wave-uniform (scalar registers); the per-lane source
+// offset is a 32-bit unsigned value added to a scalar base.
+// record_offsets: the per-lane source offsets of a record copy (the same for every record), so that
+// a loop can compute them once and issue each record with issue_record_at.
+template <int BYTES, int NI>
+__device__ __forceinline__ void record_offsets(int w, int lane, unsigned* offs) {
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+#pragma unroll
+  for (int k = 0; k < NI; ++k) {
+    const unsigned c = (unsigned)((k * 256 + wu * 64) * 16 + lane * 16);
+    offs[k] = c < (unsigned)BYTES ? c : (unsigned)BYTES - 16u;
+  }
+}
+template <int BYTES, int STAGE, int NI, int STG>
+__device__ __forceinline__ void issue_record_at(const char* recs, char* ring, int t, int w,
+                                                const unsigned* offs) {
+  const char* src = recs + (int64_t)t * BYTES;
+  char* dst = ring + (t % STG) * STAGE;
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+#pragma unroll
+  for (int k = 0; k < NI; ++k)
+    __builtin_amdgcn_global_load_lds(src + offs[k], LDS_PTR(dst + (k * 256 + wu * 64) * 16), 16,
+                                     0, 0);
+}
 template <int BYTES, int STAGE, int NI, int STG>
 __device__ __forceinline__ void issue_record(const char* recs, char* ring, int t, int w,
                                              int lane) {
   const char* src = recs + (int64_t)t * BYTES;
   char* dst = ring + (t % STG) * STAGE;
+  const int wu = __builtin_amdgcn_readfirstlane(w);
 #pragma unroll
   for (int k = 0; k < NI; ++k) {
-    const int off = (k * 256 + w * 64) * 16;
-    const int c = off + lane * 16;
-    __builtin_amdgcn_global_load_lds(src + (c < BYTES ? c : BYTES - 16), LDS_PTR(dst + off), 16,
-                                     0, 0);
+    const int off = (k * 256 + wu * 64) * 16;
+    const unsigned c = (unsigned)(off + lane * 16);
+    __builtin_amdgcn_global_load_lds(src + (c < (unsigned)BYTES ? c : (unsigned)BYTES - 16u),
+                                     LDS_PTR(dst + off), 16, 0, 0);
   }
 }
 
