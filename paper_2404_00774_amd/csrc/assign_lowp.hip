@@ -232,8 +232,14 @@ __global__ __launch_bounds__(256) void pack_codebook_kernel(const float* __restr
 // row 15, c_p quantized like the rows; with S the rescaled ||c||^2 - 2<., c> of a row,
 // <r_i, c_j> - <r_i, x_i> = (S_pj - S_ij) / 2 - <r_i, x_i>, so one MFMA stream serves the spill:
 // T = sigma (S_pj - S_ij) - 2 sigma <r_i, x_i> and the value is S_ij + T^2.
+// Waves per workgroup of the sweep: WPE workgroups of 4 waves share a CU.  (One workgroup of
+// 4 WPE waves per CU, which copies each record once instead of WPE times, measured no faster at
+// BF16 and slower at FP8: its waves meet at every barrier together.)
+constexpr int lowp_wg_waves(int) { return 4; }
+
 template <int FMT, int DP, int SPW, int BN, int STG, int WPE, bool SP, bool GPD = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE > 2 ? WPE : 2)))
+__global__ __launch_bounds__(64 * lowp_wg_waves(WPE))
+__attribute__((amdgpu_waves_per_eu(WPE, WPE > 2 ? WPE : 2)))
 void lowp_sweep_kernel(LowpParams P) {
   using T = FmtTraits<FMT>;
   using R = TileRec<FMT, DP, BN>;
@@ -242,22 +248,26 @@ void lowp_sweep_kernel(LowpParams P) {
   static_assert(NB <= 8 && (NB == 1 || NB % 2 == 0), "tile of 1, 2, 4 or 8 blocks");
   constexpr int NSTEP = OperandRegs<FMT, DP>::NSTEP, W4 = OperandRegs<FMT, DP>::W4;
   constexpr int NR = SPW * 4;                      // rows per lane in the output layout
-  __shared__ __attribute__((aligned(16))) char s_ring[STG * R::STAGE];
+  constexpr int NW = lowp_wg_waves(WPE);            // waves of the workgroup
+  constexpr int NI = (R::BYTES + NW * 1024 - 1) / (NW * 1024);   // record copies per wave
+  constexpr int STAGE = NI * NW * 1024;            // LDS bytes per ring stage
+  __shared__ __attribute__((aligned(16))) char s_ring[STG * STAGE];
 
   static_assert(!GPD || SP, "the grouped form is a spill sweep");
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, c16 = lane & 15;
   const int64_t n = live_rows(P.n, P.live_n);
-  // GPD: stripes (blockIdx.x * 4 + w) * SPW + st; each is {p, first in perm, rows}
+  // GPD: stripes (blockIdx.x * NW + w) * SPW + st; each is {p, first in perm, rows}
   const int ns = GPD ? *P.nstripes : 0;
-  if (GPD ? (int64_t)blockIdx.x * 4 * SPW >= ns : (int64_t)blockIdx.x * 64 * SPW >= n) return;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * (16 * SPW);
+  if (GPD ? (int64_t)blockIdx.x * NW * SPW >= ns : (int64_t)blockIdx.x * 16 * NW * SPW >= n)
+    return;
+  const int64_t row0 = ((int64_t)blockIdx.x * NW + w) * (16 * SPW);
   const int ntiles = (P.K + BN - 1) / BN;
   const char* recs = static_cast<const char*>(P.Cq);
   int4 sd[GPD ? SPW : 1];
   if constexpr (GPD) {
 #pragma unroll
     for (int st = 0; st < SPW; ++st) {
-      const int sidx = (blockIdx.x * 4 + w) * SPW + st;
+      const int sidx = (blockIdx.x * NW + w) * SPW + st;
       sd[st] = sidx < ns ? P.stripes[sidx] : int4{0, 0, 0, 0};
     }
   }
@@ -269,17 +279,19 @@ void lowp_sweep_kernel(LowpParams P) {
 
   // copies of record t into its ring stage; short records keep their per-lane source offsets in
   // registers, long ones (many copies per wave) recompute them
-  constexpr bool KEEP_OFF = R::NI <= 4;
-  unsigned roff[KEEP_OFF ? R::NI : 1];
-  if constexpr (KEEP_OFF) record_offsets<R::BYTES, R::NI>(w, lane, roff);
+  constexpr bool KEEP_OFF = NI <= 4;
+  unsigned roff[KEEP_OFF ? NI : 1];
+  if constexpr (KEEP_OFF) record_offsets<R::BYTES, NI, NW>(w, lane, roff);
   auto issue = [&](int t) __attribute__((always_inline)) {
-    if constexpr (KEEP_OFF) issue_record_at<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, t, w, roff);
-    else issue_record<R::BYTES, R::STAGE, R::NI, STG>(recs, s_ring, t, w, lane);
+    if constexpr (KEEP_OFF)
+      issue_record_at<R::BYTES, STAGE, NI, STG, NW>(recs, s_ring, t, w, roff);
+    else
+      issue_record<R::BYTES, STAGE, NI, STG, NW>(recs, s_ring, t, w, lane);
   };
-  issue(0);
-  if constexpr (STG > 2) {
-    if (ntiles > 1) issue(1);
-  }
+  // prologue: records 0 .. STG - 2 in flight
+#pragma unroll
+  for (int k = 0; k < STG - 1; ++k)
+    if (k < ntiles) issue(k);
 
   // A operands (A layout: lane (q, c16) holds row c16 of each stripe, quarter q of the dims)
   OperandRegs<FMT, DP> xa[SPW];
@@ -552,10 +564,10 @@ void lowp_sweep_kernel(LowpParams P) {
     const int t = NU == 2 ? (u >> 1) : u;
     if (G == 0) {
       // record t has landed in LDS for this wave (later records may still be in flight) ...
-      // (vmcnt counts VMEM operations of this wave in order: with a later record in flight, at
-      // most its NI copies may remain outstanding)
+      // (vmcnt counts VMEM operations of this wave in order: with later records in flight,
+      // leaving at most the last record's NI copies outstanding means record t is complete)
       if (STG > 2 && t + 1 < ntiles)
-        wait_vmcnt<R::NI>();
+        wait_vmcnt<NI>();
       else
         wait_vmcnt<0>();
       // ... and for every wave; every wave is also done reading the stage refilled next (its
@@ -563,7 +575,7 @@ void lowp_sweep_kernel(LowpParams P) {
       __builtin_amdgcn_s_barrier();
       if (t + STG - 1 < ntiles)
         issue(t + STG - 1);
-      tile = s_ring + stage * R::STAGE;
+      tile = s_ring + stage * STAGE;
       stage = stage + 1 == STG ? 0 : stage + 1;
       m_last = m_cur;
       m_cur = tile_masked(t);
@@ -914,13 +926,15 @@ template <int FMT, int DP>
 static void sweep_dp(const LowpParams& P, bool spill, hipStream_t st) {
   using S = SweepShape<FMT, DP>;
   if (spill) {
-    const dim3 grid((unsigned)((P.n + 64 * S::SPW_S - 1) / (64 * S::SPW_S)));
+    constexpr int NW = lowp_wg_waves(S::WPE_S);
+    const dim3 grid((unsigned)((P.n + 16 * NW * S::SPW_S - 1) / (16 * NW * S::SPW_S)));
     hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, S::SPW_S, S::BN, S::STG, S::WPE_S, true>),
-                       grid, dim3(256), 0, st, P);
+                       grid, dim3(64 * NW), 0, st, P);
   } else {
-    const dim3 grid((unsigned)((P.n + 64 * S::SPW_P - 1) / (64 * S::SPW_P)));
+    constexpr int NW = lowp_wg_waves(S::WPE_P);
+    const dim3 grid((unsigned)((P.n + 16 * NW * S::SPW_P - 1) / (16 * NW * S::SPW_P)));
     hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, S::SPW_P, S::BN, S::STG, S::WPE_P, false>),
-                       grid, dim3(256), 0, st, P);
+                       grid, dim3(64 * NW), 0, st, P);
   }
 }
 
@@ -930,10 +944,11 @@ template <int FMT, int DP>
 static void sweep_grouped_dp(const LowpParams& P, hipStream_t st) {
   using S = SweepShape<FMT, DP>;
   const int64_t ms = group_max_stripes(P.n, P.K);
-  const dim3 grid((unsigned)((ms + 4 * S::SPW_S - 1) / (4 * S::SPW_S)));
+  constexpr int NW = lowp_wg_waves(S::WPE_P);
+  const dim3 grid((unsigned)((ms + NW * S::SPW_S - 1) / (NW * S::SPW_S)));
   hipLaunchKernelGGL(
       (lowp_sweep_kernel<FMT, DP, S::SPW_S, S::BN, S::STG, S::WPE_P, true, true>), grid,
-      dim3(256), 0, st, P);
+      dim3(64 * NW), 0, st, P);
 }
 
 template <int FMT, int DP>

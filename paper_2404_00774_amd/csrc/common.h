@@ -81,16 +81,17 @@ __device__ __forceinline__ void wait_vmcnt() {
 // offset is a 32-bit unsigned value added to a scalar base.
 // record_offsets: the per-lane source offsets of a record copy (the same for every record), so that
 // a loop can compute them once and issue each record with issue_record_at.
-template <int BYTES, int NI>
+// NWG: waves of the workgroup that share the copies (each copy round moves NWG x 1 KiB).
+template <int BYTES, int NI, int NWG = 4>
 __device__ __forceinline__ void record_offsets(int w, int lane, unsigned* offs) {
   const int wu = __builtin_amdgcn_readfirstlane(w);
 #pragma unroll
   for (int k = 0; k < NI; ++k) {
-    const unsigned c = (unsigned)((k * 256 + wu * 64) * 16 + lane * 16);
+    const unsigned c = (unsigned)((k * NWG * 64 + wu * 64) * 16 + lane * 16);
     offs[k] = c < (unsigned)BYTES ? c : (unsigned)BYTES - 16u;
   }
 }
-template <int BYTES, int STAGE, int NI, int STG>
+template <int BYTES, int STAGE, int NI, int STG, int NWG = 4>
 __device__ __forceinline__ void issue_record_at(const char* recs, char* ring, int t, int w,
                                                 const unsigned* offs) {
   const char* src = recs + (int64_t)t * BYTES;
@@ -98,10 +99,10 @@ __device__ __forceinline__ void issue_record_at(const char* recs, char* ring, in
   const int wu = __builtin_amdgcn_readfirstlane(w);
 #pragma unroll
   for (int k = 0; k < NI; ++k)
-    __builtin_amdgcn_global_load_lds(src + offs[k], LDS_PTR(dst + (k * 256 + wu * 64) * 16), 16,
-                                     0, 0);
+    __builtin_amdgcn_global_load_lds(src + offs[k], LDS_PTR(dst + (k * NWG * 64 + wu * 64) * 16),
+                                     16, 0, 0);
 }
-template <int BYTES, int STAGE, int NI, int STG>
+template <int BYTES, int STAGE, int NI, int STG, int NWG = 4>
 __device__ __forceinline__ void issue_record(const char* recs, char* ring, int t, int w,
                                              int lane) {
   const char* src = recs + (int64_t)t * BYTES;
@@ -109,7 +110,7 @@ __device__ __forceinline__ void issue_record(const char* recs, char* ring, int t
   const int wu = __builtin_amdgcn_readfirstlane(w);
 #pragma unroll
   for (int k = 0; k < NI; ++k) {
-    const int off = (k * 256 + wu * 64) * 16;
+    const int off = (k * NWG * 64 + wu * 64) * 16;
     const unsigned c = (unsigned)(off + lane * 16);
     __builtin_amdgcn_global_load_lds(src + (c < (unsigned)BYTES ? c : (unsigned)BYTES - 16u),
                                      LDS_PTR(dst + off), 16, 0, 0);
