@@ -69,7 +69,7 @@ typedef struct soar_assign_opts {
   uint32_t struct_size;
   float lambda;             /* >= 0 and finite; the weight of the parallelism penalty           */
   int32_t precision;        /* a soar_precision                                                  */
-  int32_t topk;             /* BF16/FP8: candidates re-scored in FP32 per row (0 = 8, max 8)     */
+  int32_t topk;             /* BF16/FP8: candidates re-scored in FP32 per row (0 = 8, max 16)    */
   float near_tie_rel;       /* relative gap under which FP32 re-scores are decided in FP64
                                (0 = 1e-5)                                                        */
   uint32_t flags;           /* SOAR_ASYNC | SOAR_SPILL_GROUPED or SOAR_SPILL_DIRECT             */

@@ -21,7 +21,7 @@
 // value (at most a 2^-17 relative perturbation; with the mask held in a register, packing is one
 // v_and_or) and the tile group (tile / TG) is recorded when the minimum has improved over a
 // group.
-// The topk (<= 8) smallest of the 16 class minima are re-scored.
+// The topk (<= 16) smallest of the 16 class minima are re-scored.
 #include <type_traits>
 
 #include "common.h"
@@ -34,6 +34,7 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr float kBig = 3.0e38f;       // finite sentinel: never a candidate, survives the packing
+constexpr int kMaxTopk = 16;          // candidates re-scored per row: at most the 16 class minima
 
 template <int FMT>
 struct FmtTraits;
@@ -727,9 +728,9 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
   // FP32 pass
   float best = kInf;
   int bj = 0x7fffffff;
-  float vals[8];
+  float vals[kMaxTopk];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
+  for (int c = 0; c < kMaxTopk; ++c) {
     vals[c] = kInf;
     if (c >= topk) continue;
     const int j = P.cand[row * topk + c];
@@ -763,14 +764,14 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
   const float lim = best + best * P.tie_rel;
   int ntie = 0;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) ntie += vals[c] <= lim;
+  for (int c = 0; c < kMaxTopk; ++c) ntie += vals[c] <= lim;
   if (ntie >= 2) {
     double bd = __builtin_inf();
     int bdj = 0x7fffffff;
     float cpv[SP ? RS_MAXD : 1];
     if constexpr (SP) rs_load<V4, RS_MAXD>(P.C + (int64_t)pi * d, d, l16, cpv);
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < kMaxTopk; ++c) {
       if (!(vals[c] <= lim)) continue;
       const int j = P.cand[row * topk + c];
       float cv[RS_MAXD];
