@@ -418,7 +418,10 @@ void lowp_sweep_kernel(LowpParams P) {
 #pragma unroll
     for (int b = 0; b < GU; ++b)
       etc[b] = (unsigned)__builtin_amdgcn_readfirstlane((ts % TG) * NB + g * GU + b);
-    // GPD: stripe row 15 is lane group 3, register 3
+    // GPD: stripe row 15 is lane group 3 (lanes 48..63), register 3.  It is broadcast to every
+    // lane group with two lane swaps instead of an LDS permute: after the 32-lane swap of a
+    // register with itself the second result holds lanes 32..63 in both halves, and after the
+    // 16-lane swap of that with itself the second result holds lanes 48..63 in all four groups.
     if constexpr (GPD) {
 #pragma unroll
       for (int st = 0; st < SPW; ++st)
@@ -426,7 +429,10 @@ void lowp_sweep_kernel(LowpParams P) {
         for (int b = 0; b < GU; ++b) {
           const float v3 = BF ? accS[S][st][b][3]
                               : fmaf(accS[S][st][b][3], ks[st * 4 + 3] * ucs[S][b], ucn[S][b]);
-          espv[st][b] = __shfl(v3, 48 + c16);
+          const unsigned u3 = __builtin_bit_cast(unsigned, v3);
+          const auto h32 = __builtin_amdgcn_permlane32_swap(u3, u3, false, false);
+          const auto h16 = __builtin_amdgcn_permlane16_swap(h32[1], h32[1], false, false);
+          espv[st][b] = __builtin_bit_cast(float, (unsigned)h16[1]);
         }
     }
   };
