@@ -288,11 +288,13 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
           }
           // the lower end (shifted), then (b1, i1) <= (b2, i2) <= b3 over the columns seen
           const float lo = SP ? fmaf(-(Av[v] * (snv + kx[v])), snv, val) : fmaf(kx[v], snv, val);
+          // (selects, not branches: the conditions differ from lane to lane)
           const bool lt1 = lo < b1[v], lt2 = lo < b2[v];
           b3[v] = fminf(b3[v], fmaxf(b2[v], lo));
-          i2[v] = lt1 ? i1[v] : (lt2 ? j : i2[v]);
+          const int t2 = __builtin_unpredictable(lt2) ? j : i2[v];
+          i2[v] = __builtin_unpredictable(lt1) ? i1[v] : t2;
           b2[v] = fminf(b2[v], fmaxf(b1[v], lo));
-          i1[v] = lt1 ? j : i1[v];
+          i1[v] = __builtin_unpredictable(lt1) ? j : i1[v];
           b1[v] = fminf(b1[v], lo);
         }
       }
