@@ -288,12 +288,15 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
           }
           // the lower end (shifted), then (b1, i1) <= (b2, i2) <= b3 over the columns seen
           const float lo = SP ? fmaf(-(Av[v] * (snv + kx[v])), snv, val) : fmaf(kx[v], snv, val);
-          // (selects, not branches: the conditions differ from lane to lane)
+          // (selects, not branches: the conditions differ from lane to lane).  With
+          // b1 <= b2 <= b3, the new b3 is min(b3, max(b2, lo)) = med3(b2, lo, b3) and the new b2
+          // is med3(b1, lo, b2); a NaN lo leaves both unchanged (med3 then takes the min of the
+          // other two), as it leaves b1.
           const bool lt1 = lo < b1[v], lt2 = lo < b2[v];
-          b3[v] = fminf(b3[v], fmaxf(b2[v], lo));
+          b3[v] = __builtin_amdgcn_fmed3f(b2[v], lo, b3[v]);
           const int t2 = __builtin_unpredictable(lt2) ? j : i2[v];
           i2[v] = __builtin_unpredictable(lt1) ? i1[v] : t2;
-          b2[v] = fminf(b2[v], fmaxf(b1[v], lo));
+          b2[v] = __builtin_amdgcn_fmed3f(b1[v], lo, b2[v]);
           i1[v] = __builtin_unpredictable(lt1) ? j : i1[v];
           b1[v] = fminf(b1[v], lo);
         }
