@@ -25,6 +25,8 @@
 // the exact full scan.  (lo and U are kept shifted by the row constant A_row ||x||^2.)  Candidates are re-scored
 // by direct differences in FP32 (16 partial sums per row), and candidates within the near-tie
 // gap of the best are re-decided in FP64.  Ties go to the lowest index.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -180,9 +182,13 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
   const char* recs = P.Crec;
   // lower ends, shifted by A_row ||x||^2:
   //   lo' = v - A_row (||c||^2 + 2 ||x|| ||c||)    (primary: (||c||^2 - A ||c||^2) from the record)
+  //   (the spill forms ||c||^2 as ||c|| ||c||: ||c|| is 0 past K, where ||c||^2 is +inf)
   float kx[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) kx[v] = SP ? 2.f * xv[v] : -2.f * Av[v] * xv[v];
+  // grouped form: every row of the stripe has the primary pia, so only the tile holding it needs
+  // the mask
+  const int pia_tile = GP ? __builtin_amdgcn_readfirstlane(pia) / BN : -1;
   // Gram rows of the lane's output rows (row 0 stands in for rows without a primary)
   const float* grow[4];
   float gcur[GR ? NB : 1][4], gnxt[GR ? NB : 1][4];
@@ -265,42 +271,46 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
       const float* scn = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE + R::CN_OFF);
       const float* ssn = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE + R::SN_OFF);
       const float* sca = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE + R::CA_OFF);
+      auto epilogue = [&](auto with_mask) __attribute__((always_inline)) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int j = t * BN + b * 16 + c16;
-        const float cnv = SP ? scn[b * 16 + c16] : sca[b * 16 + c16];
-        const float snv = ssn[b * 16 + c16];
-        // grouped form: row 15 of the stripe is the centroid c_p (lane group 3, register 3)
-        const float spv = GP ? __shfl(accS[b][3], 48 + c16) : 0.f;
+        for (int b = 0; b < NB; ++b) {
+          const int j = t * BN + b * 16 + c16;
+          const float cnv = SP ? scn[b * 16 + c16] : sca[b * 16 + c16];
+          const float snv = ssn[b * 16 + c16];
+          // grouped form: row 15 of the stripe is the centroid c_p (lane group 3, register 3)
+          const float spv = GP ? __shfl(accS[b][3], 48 + c16) : 0.f;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          float val;
-          if constexpr (SP) {
-            // <r, c_j> - <r, x>: directly, as (<x, c_j> - G[pi][j]) - <r, x>, or with
-            // <c_pi, c_j> from the stripe's centroid row
-            const float e = GP ? (accS[b][v] - spv) - av[v]
-                               : (GR ? (accS[b][v] - gcur[b][v]) - av[v] : accT[b][v] - av[v]);
-            const float wv = fmaf(-2.f, accS[b][v], cnv);
-            val = fmaf(lp[v] * e, e, wv);
-            if (j == pr[v]) val = kInf;
-          } else {
-            val = fmaf(-2.f, accS[b][v], cnv);   // here cnv = ||c||^2 - A ||c||^2
+          for (int v = 0; v < 4; ++v) {
+            float val;
+            if constexpr (SP) {
+              // <r, c_j> - <r, x>: directly, as (<x, c_j> - G[pi][j]) - <r, x>, or with
+              // <c_pi, c_j> from the stripe's centroid row
+              const float e = GP ? (accS[b][v] - spv) - av[v]
+                                 : (GR ? (accS[b][v] - gcur[b][v]) - av[v] : accT[b][v] - av[v]);
+              const float wv = fmaf(-2.f, accS[b][v], cnv);
+              val = fmaf(lp[v] * e, e, wv);
+              if (decltype(with_mask)::value && j == pr[v]) val = kInf;
+            } else {
+              val = fmaf(-2.f, accS[b][v], cnv);   // here cnv = ||c||^2 - A ||c||^2
+            }
+            // the lower end (shifted), then (b1, i1) <= (b2, i2) <= b3 over the columns seen
+            // (selects, not branches: the conditions differ from lane to lane).  With
+            // b1 <= b2 <= b3, the new b3 is min(b3, max(b2, lo)) = med3(b2, lo, b3) and the
+            // new b2 is med3(b1, lo, b2).  A NaN lo (med3 then takes the min of the other two,
+            // as fminf/fmaxf would) pulls b3 down to b2, so the row reads as unscreened.
+            const float lo = SP ? fmaf(-(Av[v] * (snv + kx[v])), snv, val) : fmaf(kx[v], snv, val);
+            const bool lt1 = lo < b1[v], lt2 = lo < b2[v];
+            b3[v] = __builtin_amdgcn_fmed3f(b2[v], lo, b3[v]);
+            const int t2 = __builtin_unpredictable(lt2) ? j : i2[v];
+            i2[v] = __builtin_unpredictable(lt1) ? i1[v] : t2;
+            b2[v] = __builtin_amdgcn_fmed3f(b1[v], lo, b2[v]);
+            i1[v] = __builtin_unpredictable(lt1) ? j : i1[v];
+            b1[v] = fminf(b1[v], lo);
           }
-          // the lower end (shifted), then (b1, i1) <= (b2, i2) <= b3 over the columns seen
-          const float lo = SP ? fmaf(-(Av[v] * (snv + kx[v])), snv, val) : fmaf(kx[v], snv, val);
-          // (selects, not branches: the conditions differ from lane to lane).  With
-          // b1 <= b2 <= b3, the new b3 is min(b3, max(b2, lo)) = med3(b2, lo, b3) and the new b2
-          // is med3(b1, lo, b2); a NaN lo leaves both unchanged (med3 then takes the min of the
-          // other two), as it leaves b1.
-          const bool lt1 = lo < b1[v], lt2 = lo < b2[v];
-          b3[v] = __builtin_amdgcn_fmed3f(b2[v], lo, b3[v]);
-          const int t2 = __builtin_unpredictable(lt2) ? j : i2[v];
-          i2[v] = __builtin_unpredictable(lt1) ? i1[v] : t2;
-          b2[v] = __builtin_amdgcn_fmed3f(b1[v], lo, b2[v]);
-          i1[v] = __builtin_unpredictable(lt1) ? j : i1[v];
-          b1[v] = fminf(b1[v], lo);
         }
-      }
+      };
+      if (!GP || t == pia_tile) epilogue(std::true_type{});
+      else epilogue(std::false_type{});
     }
     if constexpr (GR) {
 #pragma unroll

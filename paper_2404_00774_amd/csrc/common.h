@@ -88,7 +88,8 @@ __device__ __forceinline__ void record_offsets(int w, int lane, unsigned* offs) 
 #pragma unroll
   for (int k = 0; k < NI; ++k) {
     const unsigned c = (unsigned)((k * NWG * 64 + wu * 64) * 16 + lane * 16);
-    offs[k] = c < (unsigned)BYTES ? c : (unsigned)BYTES - 16u;
+    // only the last copy round can reach past the record end
+    offs[k] = (k < NI - 1 || c < (unsigned)BYTES) ? c : (unsigned)BYTES - 16u;
   }
 }
 template <int BYTES, int STAGE, int NI, int STG, int NWG = 4>
@@ -112,8 +113,10 @@ __device__ __forceinline__ void issue_record(const char* recs, char* ring, int t
   for (int k = 0; k < NI; ++k) {
     const int off = (k * NWG * 64 + wu * 64) * 16;
     const unsigned c = (unsigned)(off + lane * 16);
-    __builtin_amdgcn_global_load_lds(src + (c < (unsigned)BYTES ? c : (unsigned)BYTES - 16u),
-                                     LDS_PTR(dst + off), 16, 0, 0);
+    // only the last copy round can reach past the record end
+    __builtin_amdgcn_global_load_lds(
+        src + ((k < NI - 1 || c < (unsigned)BYTES) ? c : (unsigned)BYTES - 16u),
+        LDS_PTR(dst + off), 16, 0, 0);
   }
 }
 
