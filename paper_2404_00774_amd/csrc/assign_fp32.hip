@@ -250,20 +250,31 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
         accT[b] = v4f{0.f, 0.f, 0.f, 0.f};
       }
     }
+    // B operands one step ahead: the reads of step s + 4 are in flight during the MFMAs of step s
+    v4f bv[2][NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      bv[0][b] = *reinterpret_cast<const v4f*>(sb + (b * 16 + c16) * LDW + q * KS);
 #pragma unroll
     for (int s = 0; s < KS; s += 4) {
-      v4f bv[NB];
+      const int cur = (s / 4) & 1;
+      if (s + 4 < KS) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
-        bv[b] = *reinterpret_cast<const v4f*>(sb + (b * 16 + c16) * LDW + q * KS + s);
+        for (int b = 0; b < NB; ++b)
+          bv[cur ^ 1][b] =
+              *reinterpret_cast<const v4f*>(sb + (b * 16 + c16) * LDW + q * KS + s + 4);
+      }
+      __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of this step's MFMAs
       // consecutive MFMAs write different accumulators so none waits on the one before
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          accS[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[s + e], bv[b][e], accS[b], 0, 0, 0);
+          accS[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[s + e], bv[cur][b][e], accS[b], 0, 0,
+                                                         0);
           if constexpr (SP && !GR && !GP)
-            accT[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[s + e], bv[b][e], accT[b], 0, 0, 0);
+            accT[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[s + e], bv[cur][b][e], accT[b], 0,
+                                                           0, 0);
         }
       }
     }
