@@ -38,12 +38,14 @@ COPY_SCALE = {"fetch": 1048576.0 / 524302.5, "write": 1.0}
 TRAFFIC = {
     # grouped FP32 pipeline, per step: primary pass, grouping by primary, grouped spill pass
     ("fp32", "mix4096_n1m_d128"): dict(
-        fetch_kib=256081.3 + 1966.1 + 6.8 + 2040.1 + 85.3 + 2 * 10.2 + 261333.8,
-        write_kib=7819.7 + 960.1 + 15.7 + 10994.3 + 1056.3 + 2 * 7.8 + 65569.0,
+        fetch_kib=256152.8 + 1966.1 + 6.8 + 2040.4 + 85.2 + 2 * 10.2 + 260659.5,
+        write_kib=7820.0 + 960.1 + 15.7 + 11159.3 + 1056.3 + 2 * 7.8 + 65633.9,
         sources={"paper_2404_00774_amd/csrc/assign_fp32.hip":
-                 "77e2aeb0b5788f42c7182332b4df958c66fa93e9f446b84e5c73b3cd7e61c915",
+                 "337959a065f29012db1a31f563d241d02de7ca1330efee69681e79884511af95",
                  "paper_2404_00774_amd/csrc/group.hip":
-                 "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198"}),
+                 "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198",
+                 "paper_2404_00774_amd/csrc/common.h":
+                 "30af1c3591c8e4aee3673658e5a9f1863ae422a598a1e02c2ad3f5bd7c1f02f5"}),
 }
 
 
