@@ -439,9 +439,20 @@ __device__ __forceinline__ void decide(const AssignParams& P, RowShared& S, Cand
 // resident up to 128 dimensions; the wider shapes run one.
 template <int DP, bool CH>
 constexpr int f32_waves() { return (!CH && DP <= 128) ? 2 : 1; }
+// The primary-only pass holds fewer registers (no residual rows): it runs three waves per SIMD
+// where three workgroups' rings fit in the 160 KB of LDS.
+template <int DP, int BN, bool CH, bool SPILL>
+constexpr int f32_kernel_waves() {
+  return (!SPILL && !CH && DP <= 128 &&
+          2 * F32Rec<DP, BN>::STAGE + (int)sizeof(RowShared) <= 53 * 1024)
+             ? 3
+             : f32_waves<DP, CH>();
+}
 
 template <int DP, int BN, bool CH, bool SPILL, bool VEC, bool GR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(f32_waves<DP, CH>(), 2)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    f32_kernel_waves<DP, BN, CH, SPILL>(),
+    f32_kernel_waves<DP, BN, CH, SPILL>() > 2 ? f32_kernel_waves<DP, BN, CH, SPILL>() : 2)))
 void assign_f32_kernel(AssignParams P) {
   using R = F32Rec<DP, BN>;
   constexpr int KS = DP / 4;
@@ -1034,7 +1045,7 @@ static hipError_t launch_dp(const AssignParams& P, bool spill, bool vec, hipStre
   case 48: X(48, 64, false); break;       \
   case 64: X(64, 64, false); break;       \
   case 96: X(96, 64, false); break;       \
-  case 128: X(128, 64, false); break;     \
+  case 128: X(128, 32, false); break;     \
   case 192: X(192, 32, false); break;     \
   case 256: X(256, 32, false); break;     \
   default: X(kF32ChunkDP, kF32ChunkBN, true); break;
@@ -1099,16 +1110,13 @@ hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipSt
     Q.perm = grouped->perm;
     Q.stripes = grouped->stripes;
     Q.nstripes = grouped->meta;
-    switch (dp) {
-      case 16: e = launch_grouped_dp<16, 64>(Q, vec, st); break;
-      case 32: e = launch_grouped_dp<32, 64>(Q, vec, st); break;
-      case 48: e = launch_grouped_dp<48, 64>(Q, vec, st); break;
-      case 64: e = launch_grouped_dp<64, 64>(Q, vec, st); break;
-      case 96: e = launch_grouped_dp<96, 64>(Q, vec, st); break;
-      case 128: e = launch_grouped_dp<128, 64>(Q, vec, st); break;
-      case 192: e = launch_grouped_dp<192, 32>(Q, vec, st); break;
-      default: e = launch_grouped_dp<256, 32>(Q, vec, st); break;
-    }
+    // the same shape table as the packing, so the kernel reads the records it was given (the
+    // chunked shapes do not occur here: dp <= 256)
+#define SOAR_X(DP, BN, CH)                                 \
+  if constexpr (!CH) e = launch_grouped_dp<DP, BN>(Q, vec, st); \
+  else e = hipErrorInvalidValue
+    switch (dp) { SOAR_F32_SHAPES(SOAR_X) }
+#undef SOAR_X
   } else {
 #define SOAR_X(DP, BN, CH) e = launch_dp<DP, BN, CH>(P, spill, vec, st)
     switch (dp) { SOAR_F32_SHAPES(SOAR_X) }
