@@ -439,8 +439,8 @@ __device__ __forceinline__ void decide(const AssignParams& P, RowShared& S, Cand
 // resident up to 128 dimensions; the wider shapes run one.
 template <int DP, bool CH>
 constexpr int f32_waves() { return (!CH && DP <= 128) ? 2 : 1; }
-// The primary-only pass holds fewer registers (no residual rows): it runs three waves per SIMD
-// where three workgroups' rings fit in the 160 KB of LDS.
+// The primary-only pass and the grouped spill pass hold no residual rows during the sweep: they
+// run three waves per SIMD where three workgroups' rings fit in the 160 KB of LDS.
 template <int DP, int BN, bool CH, bool SPILL>
 constexpr int f32_kernel_waves() {
   return (!SPILL && !CH && DP <= 128 &&
@@ -603,7 +603,9 @@ void assign_f32_kernel(AssignParams P) {
 // row 15, produce no output.
 // ------------------------------------------------------------------------------------------------
 template <int DP, int BN, bool VEC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(f32_waves<DP, false>(), 2)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    f32_kernel_waves<DP, BN, false, false>(),
+    f32_kernel_waves<DP, BN, false, false>() > 2 ? f32_kernel_waves<DP, BN, false, false>() : 2)))
 void assign_f32_spill_grouped(AssignParams P) {
   using R = F32Rec<DP, BN>;
   constexpr int KS = DP / 4;
