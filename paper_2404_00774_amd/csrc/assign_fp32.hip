@@ -1046,7 +1046,7 @@ static hipError_t launch_dp(const AssignParams& P, bool spill, bool vec, hipStre
   case 32: X(32, 64, false); break;       \
   case 48: X(48, 64, false); break;       \
   case 64: X(64, 64, false); break;       \
-  case 96: X(96, 64, false); break;       \
+  case 96: X(96, 32, false); break;       \
   case 128: X(128, 32, false); break;     \
   case 192: X(192, 32, false); break;     \
   case 256: X(256, 32, false); break;     \
