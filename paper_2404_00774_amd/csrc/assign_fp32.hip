@@ -125,30 +125,42 @@ __device__ __forceinline__ void direct32(const AssignParams& P, int nch, int64_t
   pj = SP ? sum_quad_f((p0 + p1) + (p2 + p3)) : 0.f;
 }
 
-// The same in FP64 with the residual formed exactly from C[pi] (near-tie decisions only).
+// The same in FP64 with the residual formed exactly from C[pi] (near-tie decisions only).  The
+// rows are taken 8 values at a time (a rolled loop), which keeps this rare path's registers low.
 template <int DP, int BN, bool CH, bool VEC, bool SP>
 __device__ __forceinline__ double direct64(const AssignParams& P, int nch, int64_t row, bool ok,
                                            int pi, int j, int q, const float (&xa)[DP / 4]) {
   constexpr int KS = DP / 4;
+  constexpr int G = KS % 8 == 0 ? 8 : 4;         // values per step (KS is a multiple of 4)
   double sq0 = 0.0, sq1 = 0.0, pj0 = 0.0, pj1 = 0.0, rr0 = 0.0, rr1 = 0.0;
   for (int ch = 0; ch < (CH ? nch : 1); ++ch) {
-    float c[KS], cp[KS], xs[KS];
-    load_rec<KS>(rec_row<DP, BN>(P.Crec, nch, j, ch) + q * KS, c);
-    if constexpr (SP) load_rec<KS>(rec_row<DP, BN>(P.Crec, nch, pi, ch) + q * KS, cp);
-    if constexpr (CH) {
-      load_seg<KS, VEC>(P.X, row, P.d, ch * DP + q * KS, ok, xs);
-    } else {
+    const float* cj = rec_row<DP, BN>(P.Crec, nch, j, ch) + q * KS;
+    const float* cpi = rec_row<DP, BN>(P.Crec, nch, pi, ch) + q * KS;
+    float xs[CH ? KS : 1];
+    if constexpr (CH) load_seg<KS, VEC>(P.X, row, P.d, ch * DP + q * KS, ok, xs);
+#pragma unroll 1
+    for (int s0 = 0; s0 < KS; s0 += G) {
+      float c[G], cp[G], xg[G];
+      load_rec<G>(cj + s0, c);
+      if constexpr (SP) load_rec<G>(cpi + s0, cp);
 #pragma unroll
-      for (int s = 0; s < KS; ++s) xs[s] = xa[s];
-    }
+      for (int s = 0; s < G; ++s) {
+        // (a rolled loop cannot index the register arrays: select the values explicitly)
+        float xv = 0.f;
 #pragma unroll
-    for (int s = 0; s < KS; s += 2) {
-      const double e0 = (double)xs[s] - (double)c[s], e1 = (double)xs[s + 1] - (double)c[s + 1];
-      sq0 = fma(e0, e0, sq0); sq1 = fma(e1, e1, sq1);
-      if constexpr (SP) {
-        const double r0 = (double)xs[s] - (double)cp[s], r1 = (double)xs[s + 1] - (double)cp[s + 1];
-        pj0 = fma(r0, e0, pj0); pj1 = fma(r1, e1, pj1);
-        rr0 = fma(r0, r0, rr0); rr1 = fma(r1, r1, rr1);
+        for (int k = 0; k < KS; k += G) xv = (k == s0) ? (CH ? xs[k + s] : xa[k + s]) : xv;
+        xg[s] = xv;
+      }
+#pragma unroll
+      for (int s = 0; s < G; s += 2) {
+        const double e0 = (double)xg[s] - (double)c[s], e1 = (double)xg[s + 1] - (double)c[s + 1];
+        sq0 = fma(e0, e0, sq0); sq1 = fma(e1, e1, sq1);
+        if constexpr (SP) {
+          const double r0 = (double)xg[s] - (double)cp[s];
+          const double r1 = (double)xg[s + 1] - (double)cp[s + 1];
+          pj0 = fma(r0, e0, pj0); pj1 = fma(r1, e1, pj1);
+          rr0 = fma(r0, r0, rr0); rr1 = fma(r1, r1, rr1);
+        }
       }
     }
   }
@@ -630,16 +642,19 @@ void assign_f32_spill_grouped(AssignParams P) {
   } else {
     load_seg<KS, VEC>(P.X, row, P.d, q * KS, data, xa);
   }
-  float cp[KS];
-  load_rec<KS>(rec_row<DP, BN>(P.Crec, 1, p, 0) + q * KS, cp);
+  // c_p and R are not kept through the sweep (registers for a third wave per SIMD): the row
+  // constants take r = x - c_p as it goes, and R is formed again afterwards
   float n0 = 0.f, n1 = 0.f, r0 = 0.f, r1 = 0.f, a0 = 0.f, a1 = 0.f;
+  {
+    float cp[KS];
+    load_rec<KS>(rec_row<DP, BN>(P.Crec, 1, p, 0) + q * KS, cp);
 #pragma unroll
-  for (int s = 0; s < KS; s += 2) {
-    ra[s] = xa[s] - cp[s];
-    ra[s + 1] = xa[s + 1] - cp[s + 1];
-    n0 = fmaf(xa[s], xa[s], n0); n1 = fmaf(xa[s + 1], xa[s + 1], n1);
-    r0 = fmaf(ra[s], ra[s], r0); r1 = fmaf(ra[s + 1], ra[s + 1], r1);
-    a0 = fmaf(ra[s], xa[s], a0); a1 = fmaf(ra[s + 1], xa[s + 1], a1);
+    for (int s = 0; s < KS; s += 2) {
+      const float e0 = xa[s] - cp[s], e1 = xa[s + 1] - cp[s + 1];
+      n0 = fmaf(xa[s], xa[s], n0); n1 = fmaf(xa[s + 1], xa[s + 1], n1);
+      r0 = fmaf(e0, e0, r0); r1 = fmaf(e1, e1, r1);
+      a0 = fmaf(e0, xa[s], a0); a1 = fmaf(e1, xa[s + 1], a1);
+    }
   }
   const float xnorm = sqrtf(sum_quad_f(n0 + n1));
   const float rr = sum_quad_f(r0 + r1);
@@ -672,9 +687,10 @@ void assign_f32_spill_grouped(AssignParams P) {
   publish_candidates(P, S, CS, w, lane, xv, Av, b1, i1, b2, i2, b3);
   __syncthreads();
   if (!data) return;
-  // R again (the sweep did not hold it)
+  // R again: c_p from its record
+  load_rec<KS>(rec_row<DP, BN>(P.Crec, 1, p, 0) + q * KS, ra);
 #pragma unroll
-  for (int s = 0; s < KS; ++s) ra[s] = xa[s] - cp[s];
+  for (int s = 0; s < KS; ++s) ra[s] = xa[s] - ra[s];
   bool ssat = S.sat[w][c16] != 0;
   int sj = -1;
   float sl = 0.f;

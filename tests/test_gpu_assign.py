@@ -161,6 +161,22 @@ def test_full_size_sampled_parity():
         assert st["rows_full_scan"] < 0.02 * len(X)
 
 
+@pytest.mark.parametrize("d,K", [(96, 3000), (200, 1000), (256, 1500)])
+def test_grouped_at_scale_matches_direct(d, K):
+    """n = 100,000 (well past the size where the grouped spill is chosen) for the wider whole-row
+    shapes: the grouped and direct forms agree row for row, and the oracle accepts a sample."""
+    n = 100_000
+    X = gen_mixture(MixtureSpec(n, d, 512, 0.3, "unit", 5))
+    rng = np.random.default_rng(d)
+    C = X[rng.choice(n, K, replace=False)].copy()
+    print(f"grouped vs direct n={n} d={d} K={K}", flush=True)
+    g = _run(X, C, 1.0, spill_form="grouped")
+    r = _run(X, C, 1.0, spill_form="direct")
+    assert np.array_equal(g[0], r[0]) and np.array_equal(g[1], r[1])
+    idx = rng.choice(n, 1500, replace=False)
+    _check(X[idx], C, 1.0, (g[0][idx], g[1][idx], g[2][idx], g[3][idx], g[4]))
+
+
 def test_validation_and_errors():
     soar = _soar()
     import torch
