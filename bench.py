@@ -38,10 +38,10 @@ COPY_SCALE = {"fetch": 1048576.0 / 524302.5, "write": 1.0}
 TRAFFIC = {
     # grouped FP32 pipeline, per step: primary pass, grouping by primary, grouped spill pass
     ("fp32", "mix4096_n1m_d128"): dict(
-        fetch_kib=256152.8 + 1966.1 + 6.8 + 2040.4 + 85.2 + 2 * 10.2 + 260659.5,
-        write_kib=7820.0 + 960.1 + 15.7 + 11159.3 + 1056.3 + 2 * 7.8 + 65633.9,
+        fetch_kib=256115.4 + 1966.1 + 6.8 + 2040.5 + 85.2 + 2 * 10.2 + 261049.6,
+        write_kib=7820.1 + 960.1 + 15.7 + 11359.9 + 1056.3 + 2 * 7.8 + 65632.4,
         sources={"paper_2404_00774_amd/csrc/assign_fp32.hip":
-                 "337959a065f29012db1a31f563d241d02de7ca1330efee69681e79884511af95",
+                 "bfbc64694415a721a17cd80455ee9bc42575f807d64182c99d6b868ad389332d",
                  "paper_2404_00774_amd/csrc/group.hip":
                  "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198",
                  "paper_2404_00774_amd/csrc/common.h":
