@@ -709,10 +709,12 @@ void assign_f32_spill_grouped(AssignParams P) {
 
 // ------------------------------------------------------------------------------------------------
 // Exact full scan over all K for the rows listed by the assignment kernel (one workgroup a row).
-// The 256 threads form 16 groups of 16 lanes; a group takes one centroid at a time with its lanes
+// The 1024 threads form 64 groups of 16 lanes; a group takes one centroid at a time with its lanes
 // across the dimensions, and a 16-lane tree gives the sum.  The row (and its residual) sit in LDS.
+// The scan is latency-bound (few rows, each a chain of dependent loads), so the workgroup is as
+// wide as possible: 256 centroid loads in flight per pass.
 // ------------------------------------------------------------------------------------------------
-constexpr int FS_THREADS = 256;
+constexpr int FS_THREADS = 1024;
 constexpr int FS_WAVES = FS_THREADS / 64;
 constexpr int FS_GROUPS = FS_THREADS / 16;
 
@@ -1144,9 +1146,9 @@ hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipSt
   if (ev_end) (void)hipEventRecord(ev_end, st);
   const size_t smem = ((size_t)3 * P.d + (P.K <= FS_LDS_K ? (size_t)P.K : 0)) * sizeof(float);
   if (spill)
-    hipLaunchKernelGGL(full_scan_kernel<true>, dim3(1024), dim3(FS_THREADS), smem, st, P);
+    hipLaunchKernelGGL(full_scan_kernel<true>, dim3(256), dim3(FS_THREADS), smem, st, P);
   else
-    hipLaunchKernelGGL(full_scan_kernel<false>, dim3(1024), dim3(FS_THREADS), smem, st, P);
+    hipLaunchKernelGGL(full_scan_kernel<false>, dim3(256), dim3(FS_THREADS), smem, st, P);
   return hipGetLastError();
 }
 
