@@ -38,10 +38,10 @@ COPY_SCALE = {"fetch": 1048576.0 / 524302.5, "write": 1.0}
 TRAFFIC = {
     # grouped FP32 pipeline, per step: primary pass, grouping by primary, grouped spill pass
     ("fp32", "mix4096_n1m_d128"): dict(
-        fetch_kib=256115.4 + 1966.1 + 6.8 + 2040.5 + 85.2 + 2 * 10.2 + 261049.6,
-        write_kib=7820.1 + 960.1 + 15.7 + 11359.9 + 1056.3 + 2 * 7.8 + 65632.4,
+        fetch_kib=255825.7 + 1966.1 + 6.8 + 2039.5 + 85.2 + 2 * 10.2 + 261111.0,
+        write_kib=7820.1 + 960.1 + 15.7 + 11349.3 + 1056.3 + 2 * 7.8 + 65651.9,
         sources={"paper_2404_00774_amd/csrc/assign_fp32.hip":
-                 "bfbc64694415a721a17cd80455ee9bc42575f807d64182c99d6b868ad389332d",
+                 "4a87372bd2ae3d68bfc31fc169bbd0b947cc0725726c1eb1b6477972277de292",
                  "paper_2404_00774_amd/csrc/group.hip":
                  "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198",
                  "paper_2404_00774_amd/csrc/common.h":
