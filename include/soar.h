@@ -56,11 +56,12 @@ typedef enum soar_precision {
 } soar_precision;
 
 #define SOAR_ASYNC 1u       /* flags bit: enqueue only; errors surface on the next blocking call */
-/* Form of the spill sweep (results are the same; only the work differs).  The grouped form sorts
-   the rows by primary and takes <c_pi, c_j> from the same MFMA stream as <x, c_j>; the direct
+/* Form of the spill sweep (results are the same up to the low-precision candidate ranking; only
+   the work differs).  The grouped form sorts the rows by primary and takes <c_pi, c_j> from the
+   same MFMA stream as the rows (x, or for BF16 with lambda >= 1/64 the residual r); the direct
    form runs a second stream over R = X - C[pi].  Without either bit the grouped form is taken when
-   n >= 8 K and, for FP32, d <= 256; for FP8, d > 384; never for BF16 (measured: there the sweeps
-   are not bound by the MFMA work it saves).  Both bits: SOAR_E_INVAL. */
+   n >= 8 K and, for FP32, d <= 256; for BF16, lambda >= 1/64; for FP8, d > 384.
+   Both bits: SOAR_E_INVAL. */
 #define SOAR_SPILL_GROUPED 2u
 #define SOAR_SPILL_DIRECT 4u
 

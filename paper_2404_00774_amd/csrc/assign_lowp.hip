@@ -233,12 +233,22 @@ __global__ __launch_bounds__(256) void pack_codebook_kernel(const float* __restr
 // row 15, c_p quantized like the rows; with S the rescaled ||c||^2 - 2<., c> of a row,
 // <r_i, c_j> - <r_i, x_i> = (S_pj - S_ij) / 2 - <r_i, x_i>, so one MFMA stream serves the spill:
 // T = sigma (S_pj - S_ij) - 2 sigma <r_i, x_i> and the value is S_ij + T^2.
+// GR (grouped form over residual rows, BF16, lambda > 0): the stripe rows are the pre-scaled
+// residuals sigma r_i instead of x_i, and row 15 is c_p with ||c_j||^2 added after the MFMA, so
+// row 15 gives D_j = ||c_j||^2 - 2<c_p, c_j>.  With m = -2 sigma <r, c_j> from the MFMA,
+// ||x - c_j||^2 = ||x||^2 + D_j + m / sigma and lambda <r, x - c_j>^2 / ||r||^2 =
+// (m + 2 sigma <r, x>)^2; completing the square in m leaves, up to row constants,
+// D_j + z^2 with z = m + 2 sigma <r, x> + 1 / (2 sigma): the accumulator starts at the row
+// constant beta = 2 sigma <r, x> + 1 / (2 sigma), and the value is one fma, as in the direct
+// form, from one MFMA stream.  The dropped row constant 1 / (4 sigma^2) = ||r||^2 / lambda stays
+// within a few powers of two of the loss for lambda >= kGroupedResidualMinLam.
 // Waves per workgroup of the sweep: WPE workgroups of 4 waves share a CU.  (One workgroup of
 // 4 WPE waves per CU, which copies each record once instead of WPE times, measured no faster at
 // BF16 and slower at FP8: its waves meet at every barrier together.)
 constexpr int lowp_wg_waves(int) { return 4; }
 
-template <int FMT, int DP, int SPW, int BN, int STG, int WPE, bool SP, bool GPD = false>
+template <int FMT, int DP, int SPW, int BN, int STG, int WPE, bool SP, bool GPD = false,
+          bool GR = false>
 __global__ __launch_bounds__(64 * lowp_wg_waves(WPE))
 __attribute__((amdgpu_waves_per_eu(WPE, WPE > 2 ? WPE : 2)))
 void lowp_sweep_kernel(LowpParams P) {
@@ -255,6 +265,7 @@ void lowp_sweep_kernel(LowpParams P) {
   __shared__ __attribute__((aligned(16))) char s_ring[STG * STAGE];
 
   static_assert(!GPD || SP, "the grouped form is a spill sweep");
+  static_assert(!GR || (GPD && BF), "residual rows: a BF16 grouped form");
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, c16 = lane & 15;
   const int64_t n = live_rows(P.n, P.live_n);
   // GPD: stripes (blockIdx.x * NW + w) * SPW + st; each is {p, first in perm, rows}
@@ -301,14 +312,14 @@ void lowp_sweep_kernel(LowpParams P) {
   for (int st = 0; st < SPW; ++st) {
     const int64_t r = row_of(st, c16);
     if (GPD && c16 == 15) load_operand<FMT, DP>(P.Cp, sd[st].x, true, q, xa[st]);   // c_p
-    else load_operand<FMT, DP>(P.Xq, r, r >= 0, q, xa[st]);
+    else load_operand<FMT, DP>(GR ? P.Rq : P.Xq, r, r >= 0, q, xa[st]);
     if constexpr (SP && !GPD) load_operand<FMT, DP>(P.Rq, r, r >= 0, q, ra[st]);
   }
   // row constants in the output layout: row (st, 4q + v)
   constexpr int NRF = BF ? 1 : NR;                 // FP8-only row constants
   constexpr int NRS = SP ? NR : 1;                 // spill-only row constants
   float ks[NRF], kt[SP ? NRF : 1], ka[SP ? NRF : 1], kl[NRS];
-  float gs[GPD ? NR : 1], gm[GPD ? NR : 1];       // GPD: sigma and -2 sigma <r, x>
+  float gs[GPD && !GR ? NR : 1], gm[GPD && !GR ? NR : 1];   // GPD: sigma, -2 sigma <r, x>
   int kp[NRS];
   v4f a2[SP ? SPW : 1];
 #pragma unroll
@@ -324,8 +335,14 @@ void lowp_sweep_kernel(LowpParams P) {
       }
       if constexpr (GPD) {
         const float4 rc = ok ? P.rowc[r] : float4{0.f, 0.f, 0.f, 0.f};
-        gs[i] = rc.w;
-        gm[i] = -2.f * rc.w * rc.y;
+        if constexpr (GR) {
+          // beta; zero for rows without a residual term (their operand row is zero too, so
+          // their value is D_j, the distance ranking), for empty rows and for row 15
+          a2[st][v] = rc.w > 0.f ? fmaf(2.f * rc.w, rc.y, 0.5f / rc.w) : 0.f;
+        } else {
+          gs[i] = rc.w;
+          gm[i] = -2.f * rc.w * rc.y;
+        }
         kp[i] = sd[st].x;
       } else if constexpr (SP) {
         const float4 rc = ok ? P.rowc[r] : float4{0.f, 0.f, 0.f, 0.f};
@@ -365,7 +382,7 @@ void lowp_sweep_kernel(LowpParams P) {
   static_assert(PIPE || NB <= 4, "one unit per tile without the pipeline");
   constexpr int NU = NB / GU;                      // units per tile
   v4f accS[2][SPW][GU], accT[2][ST2 ? SPW : 1][GU];
-  float ucs[2][BF ? 1 : GU], ucn[2][BF ? 1 : GU];
+  float ucs[2][BF ? 1 : GU], ucn[2][BF && !GR ? 1 : GU];   // GR: ||c_j||^2 for row 15
 
   auto mfma_unit = [&](auto set, const char* tile, int g) __attribute__((always_inline)) {
     constexpr int S = decltype(set)::value;
@@ -374,7 +391,9 @@ void lowp_sweep_kernel(LowpParams P) {
     for (int b = 0; b < GU; ++b) {
       const int blk = g * GU + b;
       v4f init = v4f{0.f, 0.f, 0.f, 0.f};
-      if constexpr (BF) {
+      if constexpr (GR) {
+        ucn[S][b] = *reinterpret_cast<const float*>(tile + lane_cn + blk * 256);
+      } else if constexpr (BF) {
         init = *reinterpret_cast<const v4f*>(tile + lane_cn + blk * 256);
       } else {
         const int jl = blk * 16 + c16;
@@ -383,7 +402,7 @@ void lowp_sweep_kernel(LowpParams P) {
       }
 #pragma unroll
       for (int st = 0; st < SPW; ++st) {
-        accS[S][st][b] = init;
+        accS[S][st][b] = GR ? a2[st] : init;
         if constexpr (ST2) accT[S][st][b] = BF ? a2[st] : v4f{0.f, 0.f, 0.f, 0.f};
       }
     }
@@ -427,8 +446,9 @@ void lowp_sweep_kernel(LowpParams P) {
       for (int st = 0; st < SPW; ++st)
 #pragma unroll
         for (int b = 0; b < GU; ++b) {
-          const float v3 = BF ? accS[S][st][b][3]
-                              : fmaf(accS[S][st][b][3], ks[st * 4 + 3] * ucs[S][b], ucn[S][b]);
+          const float v3 = GR   ? accS[S][st][b][3] + ucn[S][b]
+                           : BF ? accS[S][st][b][3]
+                                : fmaf(accS[S][st][b][3], ks[st * 4 + 3] * ucs[S][b], ucn[S][b]);
           const unsigned u3 = __builtin_bit_cast(unsigned, v3);
           const auto h32 = __builtin_amdgcn_permlane32_swap(u3, u3, false, false);
           const auto h16 = __builtin_amdgcn_permlane16_swap(h32[1], h32[1], false, false);
@@ -446,7 +466,9 @@ void lowp_sweep_kernel(LowpParams P) {
       // S = ||c_j||^2 - 2 <row, c_j> (BF16: the accumulator itself)
       float val = BF ? accS[S][st][b][v]
                      : fmaf(accS[S][st][b][v], ks[st * 4 + v] * ucs[S][b], ucn[S][b]);
-      if constexpr (GPD) {
+      if constexpr (GR) {
+        val = fmaf(val, val, espv[st][b]);             // D_j + z^2
+      } else if constexpr (GPD) {
         const float tt = fmaf(gs[i], espv[st][b] - val, gm[i]);
         val = fmaf(tt, tt, val);
       } else if constexpr (SP && BF) {
@@ -485,7 +507,10 @@ void lowp_sweep_kernel(LowpParams P) {
 #pragma unroll
     for (int b = 0; b < GU; ++b) {
       const int blk = g * GU + b;
-      if constexpr (BF) {
+      if constexpr (GR) {
+        init[b] = v4f{0.f, 0.f, 0.f, 0.f};
+        ucn[S][b] = *reinterpret_cast<const float*>(tile + lane_cn + blk * 256);
+      } else if constexpr (BF) {
         init[b] = *reinterpret_cast<const v4f*>(tile + lane_cn + blk * 256);
       } else {
         init[b] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -520,7 +545,8 @@ void lowp_sweep_kernel(LowpParams P) {
           for (int x = 0; x < (ST2 ? 2 : 1); ++x) {
             if (x == 0) {
               accS[S][st][b] = mfma_step<FMT>(xa[st].v[s], bv[s & 1][b],
-                                              s == 0 ? init[b] : accS[S][st][b]);
+                                              s == 0 ? (GR ? a2[st] : init[b])
+                                                     : accS[S][st][b]);
             } else {
               const v4f c0 = BF ? a2[st] : v4f{0.f, 0.f, 0.f, 0.f};
               accT[S][st][b] = mfma_step<FMT>(ra[st].v[s], bv[s & 1][b],
@@ -837,7 +863,7 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
   const float rn = sqrtf(r2);
   const float sigma = rn > 0.f ? 0.5f * sqrtf(P.lam) / rn : 0.f;
   if (l16 == 0) P.rowc_out[row] = float4{inv, a, r2 > 0.f ? P.lam / r2 : 0.f, sigma};
-  if (!P.Rq_out) return;   // grouped spill form: no residual rows
+  if (!P.Rq_out) return;   // grouped form over X rows: no residual rows
   // the whole padded row is written: the padding must hold zeros, not old workspace bytes
   const int dp = P.dp;
   if constexpr (FMT == LOWP_FP8) {
@@ -945,17 +971,19 @@ static void sweep_dp(const LowpParams& P, bool spill, hipStream_t st) {
   }
 }
 
-// The grouped spill runs one MFMA stream but keeps more row constants than the primary sweep:
-// the spill's stripes per wave at the primary's waves per SIMD.
-template <int FMT, int DP>
+// The grouped spill runs one MFMA stream at the primary's waves per SIMD.  Over X rows it keeps
+// two more row constants than the primary sweep and takes the spill's stripes per wave; over
+// residual rows (GR) it keeps one, and takes the primary's up to 96 dimensions (at 128 they
+// would spill registers).
+template <int FMT, int DP, bool GR>
 static void sweep_grouped_dp(const LowpParams& P, hipStream_t st) {
   using S = SweepShape<FMT, DP>;
+  constexpr int SPW = GR && DP <= 96 ? S::SPW_P : S::SPW_S;
   const int64_t ms = group_max_stripes(P.n, P.K);
   constexpr int NW = lowp_wg_waves(S::WPE_P);
-  const dim3 grid((unsigned)((ms + NW * S::SPW_S - 1) / (NW * S::SPW_S)));
-  hipLaunchKernelGGL(
-      (lowp_sweep_kernel<FMT, DP, S::SPW_S, S::BN, S::STG, S::WPE_P, true, true>), grid,
-      dim3(64 * NW), 0, st, P);
+  const dim3 grid((unsigned)((ms + NW * SPW - 1) / (NW * SPW)));
+  hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, SPW, S::BN, S::STG, S::WPE_P, true, true, GR>),
+                     grid, dim3(64 * NW), 0, st, P);
 }
 
 template <int FMT, int DP>
@@ -1003,7 +1031,15 @@ hipError_t launch_lowp_sweep(int fmt, const LowpParams& P, bool spill, hipStream
 
 template <int FMT>
 static void sweep_grouped_fmt(const LowpParams& P, hipStream_t st) {
-#define X(D) sweep_grouped_dp<FMT, D>(P, st)
+  if constexpr (FMT == LOWP_BF16) {
+    if (grouped_residual_rows(FMT, P.lam)) {
+#define X(D) sweep_grouped_dp<FMT, D, true>(P, st)
+      switch (P.dp) { SOAR_DP_CASES(FMT, X) }
+#undef X
+      return;
+    }
+  }
+#define X(D) sweep_grouped_dp<FMT, D, false>(P, st)
   switch (P.dp) { SOAR_DP_CASES(FMT, X) }
 #undef X
 }

@@ -96,7 +96,7 @@ struct LowpParams {
   int d;
   int dp;                 // padded row length of the quantized operands (elements)
   int K;
-  int topk;               // candidates re-scored per row (<= 8)
+  int topk;               // candidates re-scored per row (<= 16)
   float lam;
   float tie_rel;
   const float* X;         // FP32 originals
@@ -115,7 +115,7 @@ struct LowpParams {
   float* sloss;
   unsigned* counters;
   float4* rowc_out;       // written by the primary re-score
-  void* Rq_out;           // null: the residual rows are not needed (grouped spill form)
+  void* Rq_out;           // null: the residual rows are not needed (grouped form over X)
   // grouped spill form: rows grouped by primary, the centroid as the 16th row of every stripe
   const int32_t* perm = nullptr;
   const int4* stripes = nullptr;
@@ -132,7 +132,16 @@ hipError_t launch_lowp_quantize(int fmt, const float* A, int64_t rows, int d, in
                                 hipStream_t st, const int64_t* live_n = nullptr);
 hipError_t launch_lowp_sweep(int fmt, const LowpParams& P, bool spill, hipStream_t st);
 // Spill sweep in grouped form (P.perm, P.stripes, P.nstripes, P.Cp set; rowc from the re-score).
+// Where grouped_residual_rows() holds it also reads the residual rows P.Rq, so the primary
+// re-score must have written them (P.Rq_out set).
 hipError_t launch_lowp_sweep_grouped(int fmt, const LowpParams& P, hipStream_t st);
+// The BF16 grouped form runs over residual rows when lambda is at least this: the ranking value
+// then carries the row constant ||r||^2 / lambda, which must stay within a few powers of two of
+// the loss to keep the FP32 epilogue's resolution.
+constexpr float kGroupedResidualMinLam = 1.f / 64;
+inline bool grouped_residual_rows(int fmt, float lam) {
+  return fmt == LOWP_BF16 && lam >= kGroupedResidualMinLam;
+}
 // The sweep reads the codebook from packed per-tile records (see assign_lowp.hip).
 size_t lowp_codebook_bytes(int fmt, int d, int K);
 hipError_t launch_lowp_pack_codebook(int fmt, const float* C, int K, int d, const float* cnorm,

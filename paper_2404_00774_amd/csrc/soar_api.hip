@@ -219,12 +219,15 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
                             hipStream_t st, unsigned* counters_out_host, hipEvent_t* ev,
                             uint32_t spill_form) {
   LowpLayout L = layout_lowp(ws, n, d, K, fmt, topk);
-  // The grouped form trades the second MFMA stream for about two VALU operations per element.
-  // Measured: it pays for FP8 rows of 512 dimensions and more (d=768: 4.55 vs 5.07 ms), not for
-  // narrower FP8 rows nor for BF16 (their sweeps are not bound by the MFMA work it saves).
+  // The grouped form trades the second MFMA stream for epilogue work.  Over residual rows
+  // (BF16, lambda >= kGroupedResidualMinLam) that work is the direct form's one fma per element,
+  // so it pays wherever grouping does (BF16, n=10M, d=96, K=40,000: 142.7 vs 173.6 ms).  Over X
+  // rows it costs about two more VALU operations per element and pays only for FP8 rows of 512
+  // dimensions and more (d=768: 4.55 vs 5.07 ms).
   const bool grouped = spill_form == SOAR_SPILL_GROUPED ||
-                       (spill_form == 0 && fmt == LOWP_FP8 && lowp_padded_dim(fmt, d) >= 512 &&
-                        grouped_spill_pays(n, K));
+                       (spill_form == 0 && grouped_spill_pays(n, K) &&
+                        (grouped_residual_rows(fmt, lam) ||
+                         (fmt == LOWP_FP8 && lowp_padded_dim(fmt, d) >= 512)));
   const GroupLayout GL = group_layout(L.group, n, K);
   LowpParams P;
   P.n = n; P.d = d; P.dp = lowp_padded_dim(fmt, d); P.K = K; P.topk = topk;
@@ -233,7 +236,8 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
   P.X = X; P.C = C; P.Xq = L.Xq; P.Cq = L.Cq; P.Rq = L.Rq;
   P.xs = L.xs; P.cs = L.cs; P.cnorm = L.cnorm; P.rowc = L.rowc; P.cand = L.cand;
   P.primary = primary; P.spill = spill_out; P.pdist = pdist; P.sloss = sloss;
-  P.counters = L.counters; P.rowc_out = L.rowc; P.Rq_out = grouped ? nullptr : L.Rq;
+  P.counters = L.counters; P.rowc_out = L.rowc;
+  P.Rq_out = grouped && !grouped_residual_rows(fmt, lam) ? nullptr : L.Rq;
   if (grouped) {
     P.perm = GL.perm; P.stripes = GL.stripes; P.nstripes = GL.meta;
     P.Cp = L.Cp; P.cps = L.cps;

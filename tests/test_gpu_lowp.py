@@ -63,7 +63,7 @@ def small():
 
 @pytest.mark.parametrize("form", ["grouped", "direct"])
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
-@pytest.mark.parametrize("lam", [0.0, 1.0, 1.5])
+@pytest.mark.parametrize("lam", [0.0, 0.01, 0.05, 1.0, 1.5])
 def test_small_workload(small, prec, lam, form):
     X, C = small
     r = _report(X, C, lam, _run(X, C, lam, prec, form=form), f"{prec} lam={lam} {form}")
