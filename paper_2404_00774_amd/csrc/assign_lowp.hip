@@ -431,6 +431,15 @@ void lowp_sweep_kernel(LowpParams P) {
   // of the lane (i = st * 4 + v), so that the slots can be spread between MFMAs.
   unsigned etc[GU];                               // the unit's block codes (wave-uniform)
   float espv[GPD ? SPW : 1][GU];                  // GPD: S of each stripe's centroid row
+  // GR: do all stripes of the wave share their primary?  (Stripes are ordered by primary, so
+  // most waves' stripes do.)  Wave-uniform.
+  bool samep = false;
+  if constexpr (GR && SPW > 1) {
+    bool same = true;
+#pragma unroll
+    for (int st = 1; st < SPW; ++st) same = same && sd[st].x == sd[0].x;
+    samep = __builtin_amdgcn_readfirstlane((int)same) != 0;
+  }
   auto epi_prep = [&](auto set, int ts, int g) __attribute__((always_inline)) {
     constexpr int S = decltype(set)::value;
     // each packing is then one v_and_or with an SGPR
@@ -442,18 +451,29 @@ void lowp_sweep_kernel(LowpParams P) {
     // register with itself the second result holds lanes 32..63 in both halves, and after the
     // 16-lane swap of that with itself the second result holds lanes 48..63 in all four groups.
     if constexpr (GPD) {
-#pragma unroll
-      for (int st = 0; st < SPW; ++st)
+      auto bcast = [&](int st, int b) __attribute__((always_inline)) -> float {
+        const float v3 = GR   ? accS[S][st][b][3] + ucn[S][b]
+                         : BF ? accS[S][st][b][3]
+                              : fmaf(accS[S][st][b][3], ks[st * 4 + 3] * ucs[S][b], ucn[S][b]);
+        const unsigned u3 = __builtin_bit_cast(unsigned, v3);
+        const auto h32 = __builtin_amdgcn_permlane32_swap(u3, u3, false, false);
+        const auto h16 = __builtin_amdgcn_permlane16_swap(h32[1], h32[1], false, false);
+        return __builtin_bit_cast(float, (unsigned)h16[1]);
+      };
+      if (GR && samep) {
+        // every stripe of the wave has the same centroid row: one broadcast serves them all
 #pragma unroll
         for (int b = 0; b < GU; ++b) {
-          const float v3 = GR   ? accS[S][st][b][3] + ucn[S][b]
-                           : BF ? accS[S][st][b][3]
-                                : fmaf(accS[S][st][b][3], ks[st * 4 + 3] * ucs[S][b], ucn[S][b]);
-          const unsigned u3 = __builtin_bit_cast(unsigned, v3);
-          const auto h32 = __builtin_amdgcn_permlane32_swap(u3, u3, false, false);
-          const auto h16 = __builtin_amdgcn_permlane16_swap(h32[1], h32[1], false, false);
-          espv[st][b] = __builtin_bit_cast(float, (unsigned)h16[1]);
+          const float e = bcast(0, b);
+#pragma unroll
+          for (int st = 0; st < SPW; ++st) espv[st][b] = e;
         }
+      } else {
+#pragma unroll
+        for (int st = 0; st < SPW; ++st)
+#pragma unroll
+          for (int b = 0; b < GU; ++b) espv[st][b] = bcast(st, b);
+      }
     }
   };
   auto epi_slot = [&](auto set, auto with_mask, int i, int ts, int g)
@@ -687,20 +707,40 @@ void lowp_sweep_kernel(LowpParams P) {
 // ------------------------------------------------------------------------------------------------
 // Re-score: 16 lanes per row (4 rows per wave), FP32 direct differences, FP64 among near-ties.
 // ------------------------------------------------------------------------------------------------
+// A row's 16 lanes are one DPP row (lanes 16k .. 16k + 15), so its sums and maxima take four
+// rotate-and-combine steps on the VALU (row_ror by 8, 4, 2, 1) instead of chains of LDS permutes.
+// Each step combines the same two partial results in both lanes of a pair, so all 16 lanes end
+// with the bitwise-same value.
+template <int N>
+__device__ __forceinline__ int row_ror(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x120 + N, 0xf, 0xf, false);
+}
+template <int N>
+__device__ __forceinline__ float row_ror(float v) {
+  return __builtin_bit_cast(float, row_ror<N>(__builtin_bit_cast(int, v)));
+}
+template <int N>
+__device__ __forceinline__ double row_ror(double v) {
+  const auto w = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, int2{row_ror<N>(w.x), row_ror<N>(w.y)});
+}
 __device__ __forceinline__ float sum16(float v) {
-#pragma unroll
-  for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off);
-  return v;
+  v += row_ror<8>(v);
+  v += row_ror<4>(v);
+  v += row_ror<2>(v);
+  return v + row_ror<1>(v);
 }
 __device__ __forceinline__ double sum16d(double v) {
-#pragma unroll
-  for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off);
-  return v;
+  v += row_ror<8>(v);
+  v += row_ror<4>(v);
+  v += row_ror<2>(v);
+  return v + row_ror<1>(v);
 }
 __device__ __forceinline__ float max16(float v) {
-#pragma unroll
-  for (int off = 1; off < 16; off <<= 1) v = fmaxf(v, __shfl_xor(v, off));
-  return v;
+  v = fmaxf(v, row_ror<8>(v));
+  v = fmaxf(v, row_ror<4>(v));
+  v = fmaxf(v, row_ror<2>(v));
+  return fmaxf(v, row_ror<1>(v));
 }
 
 // RS_MAXD: dimensions held per lane.  Scalar layout: lane l16 holds l16, l16 + 16, ...
@@ -757,33 +797,49 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
     }
     rr = sum16(a0 + a1);
   }
-  // FP32 pass
+  // FP32 pass, CB candidates at a time so that their row loads are in flight together (an
+  // invalid candidate reads row 0 and is then ignored); fewer at a time for long rows, whose
+  // copies would not fit in registers
+  constexpr int CB = RS_MAXD <= 16 ? 4 : RS_MAXD <= 32 ? 2 : 1;
+  static_assert(kMaxTopk % CB == 0, "whole batches");
   float best = kInf;
   int bj = 0x7fffffff;
   float vals[kMaxTopk];
 #pragma unroll
-  for (int c = 0; c < kMaxTopk; ++c) {
-    vals[c] = kInf;
-    if (c >= topk) continue;
-    const int j = P.cand[row * topk + c];
-    if (j < 0 || j >= P.K || (SP && j == pi)) continue;
-    float cv[RS_MAXD];
-    rs_load<V4, RS_MAXD>(P.C + (int64_t)j * d, d, l16, cv);
-    float s0 = 0.f, s1 = 0.f, p0 = 0.f, p1 = 0.f;
+  for (int c = 0; c < kMaxTopk; ++c) vals[c] = kInf;
 #pragma unroll
-    for (int m = 0; m < RS_MAXD; ++m) {
-      const float e = x[m] - cv[m];
-      if (m & 1) { s1 = fmaf(e, e, s1); if (SP) p1 = fmaf(r[m], e, p1); }
-      else { s0 = fmaf(e, e, s0); if (SP) p0 = fmaf(r[m], e, p0); }
+  for (int c0 = 0; c0 < kMaxTopk; c0 += CB) {
+    if (c0 >= topk) continue;                    // wave-uniform
+    int jc[CB];
+    bool okc[CB];
+    float cv[CB][RS_MAXD];
+#pragma unroll
+    for (int u = 0; u < CB; ++u) {
+      const int j = c0 + u < topk ? P.cand[row * topk + c0 + u] : -1;
+      okc[u] = j >= 0 && j < P.K && !(SP && j == pi);
+      jc[u] = j;
+      rs_load<V4, RS_MAXD>(P.C + (int64_t)(okc[u] ? j : 0) * d, d, l16, cv[u]);
     }
-    const float sq = sum16(s0 + s1);
-    float val = sq;
-    if constexpr (SP) {
-      const float pj = sum16(p0 + p1);
-      if (rr > 0.f) val = sq + P.lam * (pj * pj) / rr;
+#pragma unroll
+    for (int u = 0; u < CB; ++u) {
+      float s0 = 0.f, s1 = 0.f, p0 = 0.f, p1 = 0.f;
+#pragma unroll
+      for (int m = 0; m < RS_MAXD; ++m) {
+        const float e = x[m] - cv[u][m];
+        if (m & 1) { s1 = fmaf(e, e, s1); if (SP) p1 = fmaf(r[m], e, p1); }
+        else { s0 = fmaf(e, e, s0); if (SP) p0 = fmaf(r[m], e, p0); }
+      }
+      const float sq = sum16(s0 + s1);
+      float val = sq;
+      if constexpr (SP) {
+        const float pj = sum16(p0 + p1);
+        if (rr > 0.f) val = sq + P.lam * (pj * pj) / rr;
+      }
+      if (okc[u]) {
+        vals[c0 + u] = val;
+        if (val < best || (val == best && jc[u] < bj)) { best = val; bj = jc[u]; }
+      }
     }
-    vals[c] = val;
-    if (val < best || (val == best && j < bj)) { best = val; bj = j; }
   }
   if (bj == 0x7fffffff) {
     if (l16 == 0) {
