@@ -58,7 +58,7 @@ typedef enum soar_precision {
 #define SOAR_ASYNC 1u       /* flags bit: enqueue only; errors surface on the next blocking call */
 /* Form of the spill sweep (results are the same up to the low-precision candidate ranking; only
    the work differs).  The grouped form sorts the rows by primary and takes <c_pi, c_j> from the
-   same MFMA stream as the rows (x, or for BF16 with lambda >= 1/64 the residual r); the direct
+   same MFMA stream as the rows (x, or with lambda >= 1/64 the residual r); the direct
    form runs a second stream over R = X - C[pi].  Without either bit the grouped form is taken when
    n >= 8 K and, for FP32, d <= 256; for BF16, lambda >= 1/64; for FP8, d > 384.
    Both bits: SOAR_E_INVAL. */

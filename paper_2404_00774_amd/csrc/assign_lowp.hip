@@ -142,8 +142,12 @@ __device__ __forceinline__ void load_operand(const void* __restrict__ base, int6
                      : u32x4{0u, 0u, 0u, 0u};
 }
 
+// FP8: sa and sb are E8M0 block scales (the factor 2^(s - 127)) of the lane's A row and B column.
+// Lane (q, c) supplies the scales of row c and of column c for contraction block q; every block
+// of a row (column) carries the same one, so the MFMA applies the per-row and per-column
+// power-of-two scales of the quantized operands itself.
 template <int FMT>
-__device__ __forceinline__ v4f mfma_step(const u32x4* a, const u32x4* b, v4f acc) {
+__device__ __forceinline__ v4f mfma_step(const u32x4* a, const u32x4* b, v4f acc, int sa, int sb) {
   if constexpr (FMT == LOWP_BF16) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[0]),
                                                    __builtin_bit_cast(bf16x8, b[0]), acc, 0, 0, 0);
@@ -152,8 +156,13 @@ __device__ __forceinline__ v4f mfma_step(const u32x4* a, const u32x4* b, v4f acc
                       (int)a[1].x, (int)a[1].y, (int)a[1].z, (int)a[1].w};
     const i32x8 bv = {(int)b[0].x, (int)b[0].y, (int)b[0].z, (int)b[0].w,
                       (int)b[1].x, (int)b[1].y, (int)b[1].z, (int)b[1].w};
-    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc, 0, 0, 0, 127, 0, 127);
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc, 0, 0, 0, sa, 0, sb);
   }
+}
+
+// E8M0 code of a power of two: its biased exponent field.
+__device__ __forceinline__ int e8m0_of(float pow2) {
+  return (int)((__builtin_bit_cast(unsigned, pow2) >> 23) & 0xffu);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -161,7 +170,7 @@ __device__ __forceinline__ v4f mfma_step(const u32x4* a, const u32x4* b, v4f acc
 // contiguous record in HBM so that the waves can copy it to LDS with direct global->LDS loads:
 //   [BN quantized rows, row stride DP*BYTES + 16 (padding keeps the B reads conflict-free)]
 //   [BN x float4: ||c_j||^2 four times (a finite 3e38 beyond K)]
-//   [BN x float: inverse row scale (FP8) or 1]
+//   [BN x 4 bytes: FP8: E8M0 block scale of the row, 2 / its quantization scale; BF16: 1.f]
 // Rows beyond K are zero.  A record is read with NI whole 4 KiB wave-group copies.
 // ------------------------------------------------------------------------------------------------
 template <int FMT, int DP, int BN>
@@ -203,9 +212,11 @@ __global__ __launch_bounds__(256) void pack_codebook_kernel(const float* __restr
       (void)frexpf(m, &e);
       scale = ldexpf(1.f, 8 - e);
     }
+    // -c (a sign flip, exact); the column's block scale carries 2 / scale, so the MFMA
+    // accumulates -2 <x, c> onto ||c||^2 as in BF16
     unsigned char* o = reinterpret_cast<unsigned char*>(base + jl * R::LDWB);
     for (int k = l16; k < R::LDWB; k += 16)
-      o[k] = (ok && k < d) ? fp8_of(c[k] * scale) : (unsigned char)0;
+      o[k] = (ok && k < d) ? fp8_of(-c[k] * scale) : (unsigned char)0;
   } else {
     __bf16* o = reinterpret_cast<__bf16*>(base + jl * R::LDWB);
     for (int k = l16; k < R::LDWB / 2; k += 16) {
@@ -217,17 +228,20 @@ __global__ __launch_bounds__(256) void pack_codebook_kernel(const float* __restr
   if (l16 == 0) {
     const float cn = ok ? cnorm[j] : kBig;
     *reinterpret_cast<v4f*>(base + R::CN_OFF + jl * 16) = v4f{cn, cn, cn, cn};
-    *reinterpret_cast<float*>(base + R::CS_OFF + jl * 4) = 1.f / scale;
+    if constexpr (FMT == LOWP_FP8)
+      *reinterpret_cast<int*>(base + R::CS_OFF + jl * 4) = e8m0_of(2.f / scale);
+    else
+      *reinterpret_cast<float*>(base + R::CS_OFF + jl * 4) = 1.f;
   }
   if (!fin) atomicOr(&counters[CNT_NONFINITE], 1u);
 }
 
-// Ranking values in the epilogue (row constants of the loss dropped):
-//   BF16: the record holds -2 c (exact) and the residual rows are stored pre-scaled by
-//         sigma = sqrt(lambda) / (2 ||r||); the S accumulator starts at ||c_j||^2 and the T
-//         accumulator at 2 sigma <r_i, x_i>, so S = ||c||^2 - 2<x,c>,
-//         T = -2 sigma (<r,c> - <r,x>) and the spill value is S + T^2 (one fma).
-//   FP8:  rows carry scales, so S and T are rescaled per (row, column) in the epilogue.
+// Ranking values in the epilogue (row constants of the loss dropped): the record holds -2 c
+// (BF16: exact; FP8: -c with the factor 2 in the column's block scale, and every FP8 row's
+// power-of-two scale applied by the MFMA) and the residual rows are stored pre-scaled by
+// sigma = sqrt(lambda) / (2 ||r||); the S accumulator starts at ||c_j||^2 and the T
+// accumulator at 2 sigma <r_i, x_i>, so S = ||c||^2 - 2<x,c>, T = -2 sigma (<r,c> - <r,x>) and
+// the spill value is S + T^2 (one fma).  Both formats share this epilogue.
 // The codebook records flow through an LDS ring of STG stages filled STG-1 tiles ahead.
 // GPD (grouped spill form): each 16-row stripe holds up to 15 rows sharing the primary p and, as
 // row 15, c_p quantized like the rows; with S the rescaled ||c||^2 - 2<., c> of a row,
@@ -265,7 +279,7 @@ void lowp_sweep_kernel(LowpParams P) {
   __shared__ __attribute__((aligned(16))) char s_ring[STG * STAGE];
 
   static_assert(!GPD || SP, "the grouped form is a spill sweep");
-  static_assert(!GR || (GPD && BF), "residual rows: a BF16 grouped form");
+  static_assert(!GR || GPD, "residual rows: a grouped form");
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, c16 = lane & 15;
   const int64_t n = live_rows(P.n, P.live_n);
   // GPD: stripes (blockIdx.x * NW + w) * SPW + st; each is {p, first in perm, rows}
@@ -308,17 +322,27 @@ void lowp_sweep_kernel(LowpParams P) {
   // A operands (A layout: lane (q, c16) holds row c16 of each stripe, quarter q of the dims)
   OperandRegs<FMT, DP> xa[SPW];
   OperandRegs<FMT, DP> ra[SP && !GPD ? SPW : 1];
+  // FP8: E8M0 scales of the lane's A rows (row c16 of each stripe) for xa and ra
+  int xsc[SPW], rsc[SP && !GPD ? SPW : 1];
 #pragma unroll
   for (int st = 0; st < SPW; ++st) {
     const int64_t r = row_of(st, c16);
+    const bool ok = r >= 0;
     if (GPD && c16 == 15) load_operand<FMT, DP>(P.Cp, sd[st].x, true, q, xa[st]);   // c_p
-    else load_operand<FMT, DP>(GR ? P.Rq : P.Xq, r, r >= 0, q, xa[st]);
-    if constexpr (SP && !GPD) load_operand<FMT, DP>(P.Rq, r, r >= 0, q, ra[st]);
+    else load_operand<FMT, DP>(GR ? P.Rq : P.Xq, r, ok, q, xa[st]);
+    if constexpr (SP && !GPD) load_operand<FMT, DP>(P.Rq, r, ok, q, ra[st]);
+    if constexpr (BF) {
+      xsc[st] = 127;
+      if constexpr (SP && !GPD) rsc[st] = 127;
+    } else {
+      // inverse row scales: x (xs), the centroid row (cps), residual rows (rowc.x)
+      if (GPD && c16 == 15) xsc[st] = e8m0_of(P.cps[sd[st].x]);
+      else xsc[st] = ok ? e8m0_of(GR ? P.rowc[r].x : P.xs[r]) : 127;
+      if constexpr (SP && !GPD) rsc[st] = ok ? e8m0_of(P.rowc[r].x) : 127;
+    }
   }
   // row constants in the output layout: row (st, 4q + v)
-  constexpr int NRF = BF ? 1 : NR;                 // FP8-only row constants
   constexpr int NRS = SP ? NR : 1;                 // spill-only row constants
-  float ks[NRF], kt[SP ? NRF : 1], ka[SP ? NRF : 1], kl[NRS];
   float gs[GPD && !GR ? NR : 1], gm[GPD && !GR ? NR : 1];   // GPD: sigma, -2 sigma <r, x>
   int kp[NRS];
   v4f a2[SP ? SPW : 1];
@@ -329,10 +353,6 @@ void lowp_sweep_kernel(LowpParams P) {
       const int i = st * 4 + v;
       const int64_t r = row_of(st, 4 * q + v);
       const bool ok = r >= 0;
-      if constexpr (!BF) {
-        if (GPD && 4 * q + v == 15) ks[i] = -2.f * P.cps[sd[st].x];   // the centroid row's scale
-        else ks[i] = -2.f * (ok ? P.xs[r] : 1.f);
-      }
       if constexpr (GPD) {
         const float4 rc = ok ? P.rowc[r] : float4{0.f, 0.f, 0.f, 0.f};
         if constexpr (GR) {
@@ -346,13 +366,8 @@ void lowp_sweep_kernel(LowpParams P) {
         kp[i] = sd[st].x;
       } else if constexpr (SP) {
         const float4 rc = ok ? P.rowc[r] : float4{0.f, 0.f, 0.f, 0.f};
-        if constexpr (!BF) {
-          kt[i] = rc.x;                      // inverse scale of the quantized residual row
-          ka[i] = rc.y;                      // <r, x>
-        }
-        kl[i] = rc.z;                        // lambda / ||r||^2 (FP8)
         kp[i] = ok ? P.primary[r] : -1;
-        a2[st][v] = 2.f * rc.w * rc.y;       // BF16: 2 sigma <r, x>
+        a2[st][v] = 2.f * rc.w * rc.y;       // 2 sigma <r, x>
       }
     }
   // (tile mod TG, block) codes fill the packed bits; the group t / TG is tracked per row
@@ -382,7 +397,9 @@ void lowp_sweep_kernel(LowpParams P) {
   static_assert(PIPE || NB <= 4, "one unit per tile without the pipeline");
   constexpr int NU = NB / GU;                      // units per tile
   v4f accS[2][SPW][GU], accT[2][ST2 ? SPW : 1][GU];
-  float ucs[2][BF ? 1 : GU], ucn[2][BF && !GR ? 1 : GU];   // GR: ||c_j||^2 for row 15
+  // GR: ||c_j||^2 for row 15; FP8: E8M0 scale of the lane's column (2 / its quantization scale)
+  float ucn[2][GR ? GU : 1];
+  int usc[2][GU];
 
   auto mfma_unit = [&](auto set, const char* tile, int g) __attribute__((always_inline)) {
     constexpr int S = decltype(set)::value;
@@ -391,19 +408,13 @@ void lowp_sweep_kernel(LowpParams P) {
     for (int b = 0; b < GU; ++b) {
       const int blk = g * GU + b;
       v4f init = v4f{0.f, 0.f, 0.f, 0.f};
-      if constexpr (GR) {
-        ucn[S][b] = *reinterpret_cast<const float*>(tile + lane_cn + blk * 256);
-      } else if constexpr (BF) {
-        init = *reinterpret_cast<const v4f*>(tile + lane_cn + blk * 256);
-      } else {
-        const int jl = blk * 16 + c16;
-        ucs[S][b] = *reinterpret_cast<const float*>(tile + R::CS_OFF + jl * 4);
-        ucn[S][b] = *reinterpret_cast<const float*>(tile + R::CN_OFF + jl * 16);
-      }
+      if constexpr (GR) ucn[S][b] = *reinterpret_cast<const float*>(tile + lane_cn + blk * 256);
+      else init = *reinterpret_cast<const v4f*>(tile + lane_cn + blk * 256);
+      usc[S][b] = BF ? 127 : *reinterpret_cast<const int*>(tile + R::CS_OFF + (blk * 16 + c16) * 4);
 #pragma unroll
       for (int st = 0; st < SPW; ++st) {
         accS[S][st][b] = GR ? a2[st] : init;
-        if constexpr (ST2) accT[S][st][b] = BF ? a2[st] : v4f{0.f, 0.f, 0.f, 0.f};
+        if constexpr (ST2) accT[S][st][b] = a2[st];
       }
     }
 #pragma unroll
@@ -419,8 +430,11 @@ void lowp_sweep_kernel(LowpParams P) {
       for (int b = 0; b < GU; ++b)
 #pragma unroll
         for (int st = 0; st < SPW; ++st) {
-          accS[S][st][b] = mfma_step<FMT>(xa[st].v[s], bv[b], accS[S][st][b]);
-          if constexpr (ST2) accT[S][st][b] = mfma_step<FMT>(ra[st].v[s], bv[b], accT[S][st][b]);
+          accS[S][st][b] =
+              mfma_step<FMT>(xa[st].v[s], bv[b], accS[S][st][b], xsc[st], usc[S][b]);
+          if constexpr (ST2)
+            accT[S][st][b] =
+                mfma_step<FMT>(ra[st].v[s], bv[b], accT[S][st][b], rsc[st], usc[S][b]);
         }
     }
   };
@@ -452,9 +466,7 @@ void lowp_sweep_kernel(LowpParams P) {
     // 16-lane swap of that with itself the second result holds lanes 48..63 in all four groups.
     if constexpr (GPD) {
       auto bcast = [&](int st, int b) __attribute__((always_inline)) -> float {
-        const float v3 = GR   ? accS[S][st][b][3] + ucn[S][b]
-                         : BF ? accS[S][st][b][3]
-                              : fmaf(accS[S][st][b][3], ks[st * 4 + 3] * ucs[S][b], ucn[S][b]);
+        const float v3 = GR ? accS[S][st][b][3] + ucn[S][b] : accS[S][st][b][3];
         const unsigned u3 = __builtin_bit_cast(unsigned, v3);
         const auto h32 = __builtin_amdgcn_permlane32_swap(u3, u3, false, false);
         const auto h16 = __builtin_amdgcn_permlane16_swap(h32[1], h32[1], false, false);
@@ -483,19 +495,15 @@ void lowp_sweep_kernel(LowpParams P) {
     float pv[GU];
 #pragma unroll
     for (int b = 0; b < GU; ++b) {
-      // S = ||c_j||^2 - 2 <row, c_j> (BF16: the accumulator itself)
-      float val = BF ? accS[S][st][b][v]
-                     : fmaf(accS[S][st][b][v], ks[st * 4 + v] * ucs[S][b], ucn[S][b]);
+      // S = ||c_j||^2 - 2 <row, c_j>: the accumulator itself
+      float val = accS[S][st][b][v];
       if constexpr (GR) {
         val = fmaf(val, val, espv[st][b]);             // D_j + z^2
       } else if constexpr (GPD) {
         const float tt = fmaf(gs[i], espv[st][b] - val, gm[i]);
         val = fmaf(tt, tt, val);
-      } else if constexpr (SP && BF) {
-        val = fmaf(accT[S][st][b][v], accT[S][st][b][v], val);
       } else if constexpr (SP) {
-        const float e = accT[S][st][b][v] * (kt[i] * ucs[S][b]) - ka[i];
-        val = fmaf(kl[i] * e, e, val);
+        val = fmaf(accT[S][st][b][v], accT[S][st][b][v], val);
       }
       if constexpr (SP && decltype(with_mask)::value)
         val = (ts * BN + (g * GU + b) * 16 + c16 == kp[i]) ? kBig : val;
@@ -530,14 +538,10 @@ void lowp_sweep_kernel(LowpParams P) {
       if constexpr (GR) {
         init[b] = v4f{0.f, 0.f, 0.f, 0.f};
         ucn[S][b] = *reinterpret_cast<const float*>(tile + lane_cn + blk * 256);
-      } else if constexpr (BF) {
-        init[b] = *reinterpret_cast<const v4f*>(tile + lane_cn + blk * 256);
       } else {
-        init[b] = v4f{0.f, 0.f, 0.f, 0.f};
-        const int jl = blk * 16 + c16;
-        ucs[S][b] = *reinterpret_cast<const float*>(tile + R::CS_OFF + jl * 4);
-        ucn[S][b] = *reinterpret_cast<const float*>(tile + R::CN_OFF + jl * 16);
+        init[b] = *reinterpret_cast<const v4f*>(tile + lane_cn + blk * 256);
       }
+      usc[S][b] = BF ? 127 : *reinterpret_cast<const int*>(tile + R::CS_OFF + (blk * 16 + c16) * 4);
     }
     u32x4 bv[2][GU][W4];
     auto read_step = [&](int s, int k) __attribute__((always_inline)) {
@@ -566,11 +570,12 @@ void lowp_sweep_kernel(LowpParams P) {
             if (x == 0) {
               accS[S][st][b] = mfma_step<FMT>(xa[st].v[s], bv[s & 1][b],
                                               s == 0 ? (GR ? a2[st] : init[b])
-                                                     : accS[S][st][b]);
+                                                     : accS[S][st][b],
+                                              xsc[st], usc[S][b]);
             } else {
-              const v4f c0 = BF ? a2[st] : v4f{0.f, 0.f, 0.f, 0.f};
               accT[S][st][b] = mfma_step<FMT>(ra[st].v[s], bv[s & 1][b],
-                                              s == 0 ? c0 : accT[S][st][b]);
+                                              s == 0 ? a2[st] : accT[S][st][b],
+                                              rsc[st], usc[S][b]);
             }
             // row slots [lo, hi) follow MFMA mi
             const int lo = PRE + mi * (NR - PRE) / NMI, hi = PRE + (mi + 1) * (NR - PRE) / NMI;
@@ -797,49 +802,33 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
     }
     rr = sum16(a0 + a1);
   }
-  // FP32 pass, CB candidates at a time so that their row loads are in flight together (an
-  // invalid candidate reads row 0 and is then ignored); fewer at a time for long rows, whose
-  // copies would not fit in registers
-  constexpr int CB = RS_MAXD <= 16 ? 4 : RS_MAXD <= 32 ? 2 : 1;
-  static_assert(kMaxTopk % CB == 0, "whole batches");
+  // FP32 pass
   float best = kInf;
   int bj = 0x7fffffff;
   float vals[kMaxTopk];
 #pragma unroll
-  for (int c = 0; c < kMaxTopk; ++c) vals[c] = kInf;
+  for (int c = 0; c < kMaxTopk; ++c) {
+    vals[c] = kInf;
+    if (c >= topk) continue;
+    const int j = P.cand[row * topk + c];
+    if (j < 0 || j >= P.K || (SP && j == pi)) continue;
+    float cv[RS_MAXD];
+    rs_load<V4, RS_MAXD>(P.C + (int64_t)j * d, d, l16, cv);
+    float s0 = 0.f, s1 = 0.f, p0 = 0.f, p1 = 0.f;
 #pragma unroll
-  for (int c0 = 0; c0 < kMaxTopk; c0 += CB) {
-    if (c0 >= topk) continue;                    // wave-uniform
-    int jc[CB];
-    bool okc[CB];
-    float cv[CB][RS_MAXD];
-#pragma unroll
-    for (int u = 0; u < CB; ++u) {
-      const int j = c0 + u < topk ? P.cand[row * topk + c0 + u] : -1;
-      okc[u] = j >= 0 && j < P.K && !(SP && j == pi);
-      jc[u] = j;
-      rs_load<V4, RS_MAXD>(P.C + (int64_t)(okc[u] ? j : 0) * d, d, l16, cv[u]);
+    for (int m = 0; m < RS_MAXD; ++m) {
+      const float e = x[m] - cv[m];
+      if (m & 1) { s1 = fmaf(e, e, s1); if (SP) p1 = fmaf(r[m], e, p1); }
+      else { s0 = fmaf(e, e, s0); if (SP) p0 = fmaf(r[m], e, p0); }
     }
-#pragma unroll
-    for (int u = 0; u < CB; ++u) {
-      float s0 = 0.f, s1 = 0.f, p0 = 0.f, p1 = 0.f;
-#pragma unroll
-      for (int m = 0; m < RS_MAXD; ++m) {
-        const float e = x[m] - cv[u][m];
-        if (m & 1) { s1 = fmaf(e, e, s1); if (SP) p1 = fmaf(r[m], e, p1); }
-        else { s0 = fmaf(e, e, s0); if (SP) p0 = fmaf(r[m], e, p0); }
-      }
-      const float sq = sum16(s0 + s1);
-      float val = sq;
-      if constexpr (SP) {
-        const float pj = sum16(p0 + p1);
-        if (rr > 0.f) val = sq + P.lam * (pj * pj) / rr;
-      }
-      if (okc[u]) {
-        vals[c0 + u] = val;
-        if (val < best || (val == best && jc[u] < bj)) { best = val; bj = jc[u]; }
-      }
+    const float sq = sum16(s0 + s1);
+    float val = sq;
+    if constexpr (SP) {
+      const float pj = sum16(p0 + p1);
+      if (rr > 0.f) val = sq + P.lam * (pj * pj) / rr;
     }
+    vals[c] = val;
+    if (val < best || (val == best && j < bj)) { best = val; bj = j; }
   }
   if (bj == 0x7fffffff) {
     if (l16 == 0) {
@@ -904,9 +893,13 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
     m0 = fmaxf(m0, fabsf(r[m]));
   }
   const float a = sum16(a0), r2 = sum16(r0);
+  // sigma = sqrt(lambda) / (2 ||r||): the residual rows are stored pre-scaled by it, FP8 ones
+  // with a power-of-two scale of their own
+  const float rn = sqrtf(r2);
+  const float sigma = rn > 0.f ? 0.5f * sqrtf(P.lam) / rn : 0.f;
   float inv = 1.f, scale = 1.f;
   if constexpr (FMT == LOWP_FP8) {
-    const float mx = max16(m0);
+    const float mx = max16(m0) * sigma;
     if (mx > 0.f) {
       int e;
       (void)frexpf(mx, &e);
@@ -914,10 +907,6 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
       inv = 1.f / scale;
     }
   }
-  // sigma = sqrt(lambda) / (2 ||r||): BF16 stores the residual pre-scaled by it, and the grouped
-  // spill form uses it in every format
-  const float rn = sqrtf(r2);
-  const float sigma = rn > 0.f ? 0.5f * sqrtf(P.lam) / rn : 0.f;
   if (l16 == 0) P.rowc_out[row] = float4{inv, a, r2 > 0.f ? P.lam / r2 : 0.f, sigma};
   if (!P.Rq_out) return;   // grouped form over X rows: no residual rows
   // the whole padded row is written: the padding must hold zeros, not old workspace bytes
@@ -927,7 +916,7 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
 #pragma unroll
     for (int m = 0; m < RS_MAXD; ++m) {
       const int k = rs_dim<V4>(l16, m);
-      if (k < d) o[k] = fp8_of(r[m] * scale);
+      if (k < d) o[k] = fp8_of(sigma * r[m] * scale);
     }
     for (int k = d + l16; k < dp; k += 16) o[k] = (unsigned char)0;
   } else {
@@ -1087,13 +1076,11 @@ hipError_t launch_lowp_sweep(int fmt, const LowpParams& P, bool spill, hipStream
 
 template <int FMT>
 static void sweep_grouped_fmt(const LowpParams& P, hipStream_t st) {
-  if constexpr (FMT == LOWP_BF16) {
-    if (grouped_residual_rows(FMT, P.lam)) {
+  if (grouped_residual_rows(FMT, P.lam)) {
 #define X(D) sweep_grouped_dp<FMT, D, true>(P, st)
-      switch (P.dp) { SOAR_DP_CASES(FMT, X) }
+    switch (P.dp) { SOAR_DP_CASES(FMT, X) }
 #undef X
-      return;
-    }
+    return;
   }
 #define X(D) sweep_grouped_dp<FMT, D, false>(P, st)
   switch (P.dp) { SOAR_DP_CASES(FMT, X) }

@@ -107,7 +107,7 @@ struct LowpParams {
   const float* xs;        // FP8: inverse power-of-two row scales of Xq, Cq
   const float* cs;
   const float* cnorm;     // [K] ||c_j||^2 (FP32)
-  const float4* rowc;     // [n] residual rows: {inverse scale, <r, x>, lambda / ||r||^2, 0}
+  const float4* rowc;     // [n] residual rows: {inverse scale, <r, x>, lambda / ||r||^2, sigma}
   int32_t* cand;          // [n * topk]
   int32_t* primary;
   int32_t* spill;
@@ -135,13 +135,11 @@ hipError_t launch_lowp_sweep(int fmt, const LowpParams& P, bool spill, hipStream
 // Where grouped_residual_rows() holds it also reads the residual rows P.Rq, so the primary
 // re-score must have written them (P.Rq_out set).
 hipError_t launch_lowp_sweep_grouped(int fmt, const LowpParams& P, hipStream_t st);
-// The BF16 grouped form runs over residual rows when lambda is at least this: the ranking value
-// then carries the row constant ||r||^2 / lambda, which must stay within a few powers of two of
-// the loss to keep the FP32 epilogue's resolution.
+// The grouped form runs over residual rows when lambda is at least this: the ranking value then
+// carries the row constant ||r||^2 / lambda, which must stay within a few powers of two of the
+// loss to keep the FP32 epilogue's resolution.
 constexpr float kGroupedResidualMinLam = 1.f / 64;
-inline bool grouped_residual_rows(int fmt, float lam) {
-  return fmt == LOWP_BF16 && lam >= kGroupedResidualMinLam;
-}
+inline bool grouped_residual_rows(int /*fmt*/, float lam) { return lam >= kGroupedResidualMinLam; }
 // The sweep reads the codebook from packed per-tile records (see assign_lowp.hip).
 size_t lowp_codebook_bytes(int fmt, int d, int K);
 hipError_t launch_lowp_pack_codebook(int fmt, const float* C, int K, int d, const float* cnorm,

@@ -220,14 +220,16 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
                             uint32_t spill_form) {
   LowpLayout L = layout_lowp(ws, n, d, K, fmt, topk);
   // The grouped form trades the second MFMA stream for epilogue work.  Over residual rows
-  // (BF16, lambda >= kGroupedResidualMinLam) that work is the direct form's one fma per element,
-  // so it pays wherever grouping does (BF16, n=10M, d=96, K=40,000: 142.7 vs 173.6 ms).  Over X
-  // rows it costs about two more VALU operations per element and pays only for FP8 rows of 512
-  // dimensions and more (d=768: 4.55 vs 5.07 ms).
+  // (lambda >= kGroupedResidualMinLam) that work is the direct form's one fma per element, so for
+  // BF16 it pays wherever grouping does (n=10M, d=96, K=40,000: 142.7 vs 173.6 ms).  An FP8
+  // MFMA does four times the work of a BF16 one, so below 512 dimensions the second stream
+  // costs less than the stripes' padding (d=96: 144.3 vs 141.5 ms); at d=768 grouping pays
+  // (7.5 vs 10.3 ms at n=500K).  Over X rows (small lambda) the form costs about two more VALU
+  // operations per element.
   const bool grouped = spill_form == SOAR_SPILL_GROUPED ||
                        (spill_form == 0 && grouped_spill_pays(n, K) &&
-                        (grouped_residual_rows(fmt, lam) ||
-                         (fmt == LOWP_FP8 && lowp_padded_dim(fmt, d) >= 512)));
+                        (fmt == LOWP_BF16 ? grouped_residual_rows(fmt, lam)
+                                          : lowp_padded_dim(fmt, d) >= 512));
   const GroupLayout GL = group_layout(L.group, n, K);
   LowpParams P;
   P.n = n; P.d = d; P.dp = lowp_padded_dim(fmt, d); P.K = K; P.topk = topk;
