@@ -287,8 +287,12 @@ void lowp_sweep_kernel(LowpParams P) {
   if (GPD ? (int64_t)blockIdx.x * NW * SPW >= ns : (int64_t)blockIdx.x * 16 * NW * SPW >= n)
     return;
   const int64_t row0 = ((int64_t)blockIdx.x * NW + w) * (16 * SPW);
-  const int ntiles = (P.K + BN - 1) / BN;
-  const char* recs = static_cast<const char*>(P.Cq);
+  // codebook split (blockIdx.y of gridDim.y, at most one split per tile): tiles [t0, t0 + ntiles)
+  const int ntiles_all = (P.K + BN - 1) / BN;
+  const int t0 = (int)((int64_t)ntiles_all * blockIdx.y / gridDim.y);
+  const int ntiles = (int)((int64_t)ntiles_all * (blockIdx.y + 1) / gridDim.y) - t0;
+  const int kbase = t0 * BN;                       // first column of the split
+  const char* recs = static_cast<const char*>(P.Cq) + (size_t)t0 * R::BYTES;
   int4 sd[GPD ? SPW : 1];
   if constexpr (GPD) {
 #pragma unroll
@@ -370,6 +374,9 @@ void lowp_sweep_kernel(LowpParams P) {
         a2[st][v] = 2.f * rc.w * rc.y;       // 2 sigma <r, x>
       }
     }
+  // primaries relative to the split (a row without one stays negative and matches no column)
+#pragma unroll
+  for (int i = 0; i < NRS; ++i) kp[i] -= kbase;
   // (tile mod TG, block) codes fill the packed bits; the group t / TG is tracked per row
   constexpr int TG = kCodes / NB;
   static_assert(TG >= 1, "at most 64 blocks per tile");
@@ -695,8 +702,11 @@ void lowp_sweep_kernel(LowpParams P) {
       const float bv = b1[i];
       const bool valid = bv < 1.0e38f;
       const unsigned code = packed_code(bv);
-      const int j = valid ? (bt[i] * TG + (int)(code / NB)) * BN + (int)(code % NB) * 16 + c16
-                          : 0x7fffffff;
+      // (lanes without a valid minimum get distinct keys past every column, so the ranks are a
+      // permutation and every one of the topk slots is written)
+      const int j = valid ? kbase + (bt[i] * TG + (int)(code / NB)) * BN + (int)(code % NB) * 16 +
+                                c16
+                          : 0x7fffff00 + c16;
       int rank = 0;
 #pragma unroll
       for (int o = 1; o < 16; ++o) {
@@ -705,8 +715,51 @@ void lowp_sweep_kernel(LowpParams P) {
         const int oj = __shfl(j, src);
         rank += (ov < bv || (ov == bv && oj < j)) ? 1 : 0;
       }
-      if (r >= 0 && rank < topk) P.cand[r * topk + rank] = (valid && j < P.K) ? j : -1;
+      if (r >= 0 && rank < topk) {
+        const int jj = (valid && j < P.K) ? j : -1;
+        if (gridDim.y == 1) {
+          P.cand[r * topk + rank] = jj;
+        } else {                                   // per split, with values, for the merge
+          const int64_t o = (r * gridDim.y + blockIdx.y) * topk + rank;
+          P.cand_split[o] = jj;
+          P.cand_val[o] = jj >= 0 ? bv : kInf;
+        }
+      }
     }
+}
+
+// Candidates of a codebook swept in S splits: per row, the topk smallest (value, column) pairs
+// of the S * topk the splits kept, in order.  The splits partition the columns, so every column
+// appears at most once.
+__global__ __launch_bounds__(256) void lowp_merge_kernel(LowpParams P, int S) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= live_rows(P.n, P.live_n)) return;
+  const int topk = P.topk, m = S * topk;
+  const int32_t* cj = P.cand_split + r * m;
+  const float* cv = P.cand_val + r * m;
+  float pv = -kInf;                                // the previous pick: (pv, pj)
+  int pj = -1;
+  for (int k = 0; k < topk; ++k) {
+    float bv = kInf;
+    int bj = -1;
+    for (int e = 0; e < m; ++e) {
+      const int j = cj[e];
+      const float v = cv[e];
+      const bool after = v > pv || (v == pv && j > pj);
+      const bool better = bj < 0 || v < bv || (v == bv && j < bj);
+      if (j >= 0 && after && better) { bv = v; bj = j; }
+    }
+    P.cand[r * topk + k] = bj;
+    if (bj >= 0) { pv = bv; pj = bj; }
+  }
+}
+
+hipError_t launch_lowp_merge(const LowpParams& P, hipStream_t st) {
+  if (P.ksplit <= 1) return hipSuccess;
+  if (!P.cand_split || !P.cand_val) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(lowp_merge_kernel, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P,
+                     P.ksplit);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1000,17 +1053,27 @@ SOAR_SHAPE_X(LOWP_FP8, 768, SOAR_SHAPE_FP8_768)
 SOAR_SHAPE(LOWP_FP8, 1024, 1, 2, 1, 2, 32, 2)
 #undef SOAR_SHAPE
 
+// Codebook splits of a sweep: P.ksplit, at most one per tile (the host checks P.ksplit <= K / 64
+// and every tile holds at most 64 columns, so this never lowers it).
+template <int FMT, int DP>
+static int ksplit_tiles(const LowpParams& P) {
+  const int nt = (P.K + SweepShape<FMT, DP>::BN - 1) / SweepShape<FMT, DP>::BN;
+  return P.ksplit < 1 ? 1 : P.ksplit > nt ? nt : P.ksplit;
+}
+
 template <int FMT, int DP>
 static void sweep_dp(const LowpParams& P, bool spill, hipStream_t st) {
   using S = SweepShape<FMT, DP>;
   if (spill) {
     constexpr int NW = lowp_wg_waves(S::WPE_S);
-    const dim3 grid((unsigned)((P.n + 16 * NW * S::SPW_S - 1) / (16 * NW * S::SPW_S)));
+    const dim3 grid((unsigned)((P.n + 16 * NW * S::SPW_S - 1) / (16 * NW * S::SPW_S)),
+                    (unsigned)ksplit_tiles<FMT, DP>(P));
     hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, S::SPW_S, S::BN, S::STG, S::WPE_S, true>),
                        grid, dim3(64 * NW), 0, st, P);
   } else {
     constexpr int NW = lowp_wg_waves(S::WPE_P);
-    const dim3 grid((unsigned)((P.n + 16 * NW * S::SPW_P - 1) / (16 * NW * S::SPW_P)));
+    const dim3 grid((unsigned)((P.n + 16 * NW * S::SPW_P - 1) / (16 * NW * S::SPW_P)),
+                    (unsigned)ksplit_tiles<FMT, DP>(P));
     hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, S::SPW_P, S::BN, S::STG, S::WPE_P, false>),
                        grid, dim3(64 * NW), 0, st, P);
   }

@@ -123,6 +123,12 @@ struct LowpParams {
   const void* Cp = nullptr;      // [K x dp] codebook rows quantized like X (not -2 c)
   const float* cps = nullptr;    // FP8: their inverse row scales
   const int64_t* live_n = nullptr;   // device row count <= n (serving steps), or null
+  // codebook split of the direct sweeps (1: none).  With S > 1 each sweep writes, per row and
+  // split, topk candidates and their ranking values to cand_split / cand_val ([n][S][topk]), and
+  // launch_lowp_merge reduces them to cand before the re-score.  S <= K / 64.
+  int ksplit = 1;
+  int32_t* cand_split = nullptr;
+  float* cand_val = nullptr;
 };
 
 int lowp_padded_dim(int fmt, int d);
@@ -145,5 +151,7 @@ size_t lowp_codebook_bytes(int fmt, int d, int K);
 hipError_t launch_lowp_pack_codebook(int fmt, const float* C, int K, int d, const float* cnorm,
                                      void* rec, unsigned* counters, hipStream_t st);
 hipError_t launch_lowp_rescore(int fmt, const LowpParams& P, bool spill, hipStream_t st);
+// Merges the split candidates of a sweep (no-op for P.ksplit <= 1).
+hipError_t launch_lowp_merge(const LowpParams& P, hipStream_t st);
 
 }  // namespace soar

@@ -186,14 +186,22 @@ struct soar_index {
 
 namespace {
 
+// Codebook splits of a serving step's sweeps.  A step of few rows fills few workgroups, and
+// each would sweep every centroid tile in turn; splitting the codebook into S parts runs S
+// workgroups per row group, each over an S-th of the tiles, and a merge keeps the best
+// candidates.  One split per 4096 centroids, at most 8, so every split covers at least 4096
+// columns.  Fixed per index, so a row's result does not depend on the step it runs in.
+int serving_ksplit(int K) { return std::max(1, std::min(8, K / 4096)); }
+
 size_t step_ws_bytes(int fmt_or_fp32, int64_t cap, int d, int K, bool lowp, int fmt) {
   if (!lowp) return al(CNT_WORDS * 4) + al((size_t)cap * 4);   // counters + full-scan rows
   const int dp = lowp_padded_dim(fmt, d);
   const size_t eb = fmt == LOWP_BF16 ? 2 : 1;
+  const int S = serving_ksplit(K);
   (void)fmt_or_fp32;
-  (void)K;
   return al(CNT_WORDS * 4) + 2 * al((size_t)cap * dp * eb) + al((size_t)cap * 4) +
-         al((size_t)cap * 16) + al((size_t)cap * 8 * 4);
+         al((size_t)cap * 16) + al((size_t)cap * 8 * 4) +
+         (S > 1 ? 2 * al((size_t)cap * S * 8 * 4) : 0);
 }
 
 struct ArenaPlan {
@@ -266,7 +274,12 @@ hipError_t enqueue_compute(soar_index* ix, Slot& s) {
   P.xs = reinterpret_cast<float*>(w); w += al((size_t)ix->cap * 4);
   P.rowc = reinterpret_cast<float4*>(w); P.rowc_out = reinterpret_cast<float4*>(w);
   w += al((size_t)ix->cap * 16);
-  P.cand = reinterpret_cast<int32_t*>(w);
+  P.cand = reinterpret_cast<int32_t*>(w); w += al((size_t)ix->cap * 8 * 4);
+  P.ksplit = serving_ksplit(ix->K);
+  if (P.ksplit > 1) {
+    P.cand_split = reinterpret_cast<int32_t*>(w); w += al((size_t)ix->cap * P.ksplit * 8 * 4);
+    P.cand_val = reinterpret_cast<float*>(w); w += al((size_t)ix->cap * P.ksplit * 8 * 4);
+  }
   P.Cq = ix->crec; P.cs = nullptr; P.cnorm = ix->cnorm;
   P.primary = s.prim; P.spill = s.spill; P.pdist = nullptr; P.sloss = nullptr;
   P.counters = s.counters;
@@ -274,8 +287,10 @@ hipError_t enqueue_compute(soar_index* ix, Slot& s) {
   e = launch_lowp_quantize(fmt, s.X, ix->cap, ix->d, dp, false, const_cast<void*>(P.Xq),
                            const_cast<float*>(P.xs), s.counters, s.st, s.live);
   if (e == hipSuccess) e = launch_lowp_sweep(fmt, P, false, s.st);
+  if (e == hipSuccess) e = launch_lowp_merge(P, s.st);
   if (e == hipSuccess) e = launch_lowp_rescore(fmt, P, false, s.st);
   if (e == hipSuccess) e = launch_lowp_sweep(fmt, P, true, s.st);
+  if (e == hipSuccess) e = launch_lowp_merge(P, s.st);
   if (e == hipSuccess) e = launch_lowp_rescore(fmt, P, true, s.st);
   return e;
 }

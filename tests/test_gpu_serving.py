@@ -87,6 +87,36 @@ def test_alone_and_in_concurrent_mix(data):
     ix.close()
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_split_codebook_steps(prec):
+    """With K = 8192 every serving sweep runs as two codebook splits (one per 4096 centroids)
+    whose candidates are merged: the answers are the oracle's within the low-precision bound,
+    the same alone and in a mix of request sizes, and the lists hold exactly them."""
+    soar = _soar()
+    X = gen_mixture(MixtureSpec(12_000, 32, 256, 0.3, "unit", 11))
+    C = (X[np.random.default_rng(5).choice(len(X), 8192, replace=False)] * 0.97).astype(np.float32)
+    ix = soar.SoarIndex(_t(C), 1.0, precision=prec, max_step_rows=1024, list_capacity=100_000)
+    n, lo, tickets = 6000, 0, []
+    for sz in (1, 37, 500, 1024, 2000, 2438):
+        tickets.append((ix.insert(X[lo:lo + sz], lo), lo, sz))
+        lo += sz
+    p, s = np.empty(n, np.int32), np.empty(n, np.int32)
+    for t, a, sz in tickets:
+        p[a:a + sz], s[a:a + sz] = ix.wait(t, timeout=60.0)
+    pa, sa = ix.wait(ix.insert(X[:500], 50_000), timeout=60.0)
+    assert np.array_equal(pa, p[:500]) and np.array_equal(sa, s[:500])
+    got = sorted((int(i), k) for k in range(len(C)) for i in ix.list(k) if i < n)
+    want = sorted([(i, int(p[i])) for i in range(n)] + [(i, int(s[i])) for i in range(n)])
+    assert got == want
+    ix.close()
+    j = O.judge(X[:n], C, 1.0, p, s)
+    bound = 1e-3 if prec == "bf16" else 1e-2
+    print(prec, "split serving: primary regret", float(j["primary_regret"].mean()),
+          "spill regret", float(j["spill_regret"].mean()), flush=True)
+    assert np.all(s != p) and np.all((p >= 0) & (p < len(C))) and np.all((s >= 0) & (s < len(C)))
+    assert j["primary_regret"].mean() <= bound and j["spill_regret"].mean() <= bound
+
+
 def test_admission_waits_for_memory_and_rejects_too_large(data):
     soar = _soar()
     X, C = data
