@@ -51,6 +51,21 @@ struct FmtTraits<LOWP_FP8> {
   static constexpr int LANE_B = 32;
 };
 
+// Rotations within a DPP row (16 lanes: 16k .. 16k + 15) by N lanes, on the VALU.
+template <int N>
+__device__ __forceinline__ int row_ror(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x120 + N, 0xf, 0xf, false);
+}
+template <int N>
+__device__ __forceinline__ float row_ror(float v) {
+  return __builtin_bit_cast(float, row_ror<N>(__builtin_bit_cast(int, v)));
+}
+template <int N>
+__device__ __forceinline__ double row_ror(double v) {
+  const auto w = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, int2{row_ror<N>(w.x), row_ror<N>(w.y)});
+}
+
 // Six low mantissa bits carry a code < 64 (tile within its group, block within the tile).  The
 // mask ~63 is not an inline constant, so the sweep keeps it in a register (code_mask) and packing
 // stays one v_and_or.
@@ -262,7 +277,7 @@ __global__ __launch_bounds__(256) void pack_codebook_kernel(const float* __restr
 constexpr int lowp_wg_waves(int) { return 4; }
 
 template <int FMT, int DP, int SPW, int BN, int STG, int WPE, bool SP, bool GPD = false,
-          bool GR = false>
+          bool GR = false, bool KS = false>
 __global__ __launch_bounds__(64 * lowp_wg_waves(WPE))
 __attribute__((amdgpu_waves_per_eu(WPE, WPE > 2 ? WPE : 2)))
 void lowp_sweep_kernel(LowpParams P) {
@@ -280,6 +295,7 @@ void lowp_sweep_kernel(LowpParams P) {
 
   static_assert(!GPD || SP, "the grouped form is a spill sweep");
   static_assert(!GR || GPD, "residual rows: a grouped form");
+  static_assert(!(KS && GPD), "codebook splits: direct sweeps only");
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, c16 = lane & 15;
   const int64_t n = live_rows(P.n, P.live_n);
   // GPD: stripes (blockIdx.x * NW + w) * SPW + st; each is {p, first in perm, rows}
@@ -287,10 +303,12 @@ void lowp_sweep_kernel(LowpParams P) {
   if (GPD ? (int64_t)blockIdx.x * NW * SPW >= ns : (int64_t)blockIdx.x * 16 * NW * SPW >= n)
     return;
   const int64_t row0 = ((int64_t)blockIdx.x * NW + w) * (16 * SPW);
-  // codebook split (blockIdx.y of gridDim.y, at most one split per tile): tiles [t0, t0 + ntiles)
+  // KS: codebook split blockIdx.y of gridDim.y (at most one split per tile): tiles
+  // [t0, t0 + ntiles).  (A separate instantiation: the split bookkeeping costs registers.)
   const int ntiles_all = (P.K + BN - 1) / BN;
-  const int t0 = (int)((int64_t)ntiles_all * blockIdx.y / gridDim.y);
-  const int ntiles = (int)((int64_t)ntiles_all * (blockIdx.y + 1) / gridDim.y) - t0;
+  const int t0 = KS ? (int)((int64_t)ntiles_all * blockIdx.y / gridDim.y) : 0;
+  const int ntiles =
+      KS ? (int)((int64_t)ntiles_all * (blockIdx.y + 1) / gridDim.y) - t0 : ntiles_all;
   const int kbase = t0 * BN;                       // first column of the split
   const char* recs = static_cast<const char*>(P.Cq) + (size_t)t0 * R::BYTES;
   int4 sd[GPD ? SPW : 1];
@@ -375,8 +393,10 @@ void lowp_sweep_kernel(LowpParams P) {
       }
     }
   // primaries relative to the split (a row without one stays negative and matches no column)
+  if constexpr (KS) {
 #pragma unroll
-  for (int i = 0; i < NRS; ++i) kp[i] -= kbase;
+    for (int i = 0; i < NRS; ++i) kp[i] -= kbase;
+  }
   // (tile mod TG, block) codes fill the packed bits; the group t / TG is tracked per row
   constexpr int TG = kCodes / NB;
   static_assert(TG >= 1, "at most 64 blocks per tile");
@@ -717,7 +737,7 @@ void lowp_sweep_kernel(LowpParams P) {
       }
       if (r >= 0 && rank < topk) {
         const int jj = (valid && j < P.K) ? j : -1;
-        if (gridDim.y == 1) {
+        if constexpr (!KS) {
           P.cand[r * topk + rank] = jj;
         } else {                                   // per split, with values, for the merge
           const int64_t o = (r * gridDim.y + blockIdx.y) * topk + rank;
@@ -765,23 +785,9 @@ hipError_t launch_lowp_merge(const LowpParams& P, hipStream_t st) {
 // ------------------------------------------------------------------------------------------------
 // Re-score: 16 lanes per row (4 rows per wave), FP32 direct differences, FP64 among near-ties.
 // ------------------------------------------------------------------------------------------------
-// A row's 16 lanes are one DPP row (lanes 16k .. 16k + 15), so its sums and maxima take four
-// rotate-and-combine steps on the VALU (row_ror by 8, 4, 2, 1) instead of chains of LDS permutes.
-// Each step combines the same two partial results in both lanes of a pair, so all 16 lanes end
-// with the bitwise-same value.
-template <int N>
-__device__ __forceinline__ int row_ror(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x120 + N, 0xf, 0xf, false);
-}
-template <int N>
-__device__ __forceinline__ float row_ror(float v) {
-  return __builtin_bit_cast(float, row_ror<N>(__builtin_bit_cast(int, v)));
-}
-template <int N>
-__device__ __forceinline__ double row_ror(double v) {
-  const auto w = __builtin_bit_cast(int2, v);
-  return __builtin_bit_cast(double, int2{row_ror<N>(w.x), row_ror<N>(w.y)});
-}
+// A row's 16 lanes are one DPP row, so its sums and maxima take four rotate-and-combine steps
+// (row_ror by 8, 4, 2, 1) instead of chains of LDS permutes.  Each step combines the same two
+// partial results in both lanes of a pair, so all 16 lanes end with the bitwise-same value.
 __device__ __forceinline__ float sum16(float v) {
   v += row_ror<8>(v);
   v += row_ror<4>(v);
@@ -1053,12 +1059,12 @@ SOAR_SHAPE_X(LOWP_FP8, 768, SOAR_SHAPE_FP8_768)
 SOAR_SHAPE(LOWP_FP8, 1024, 1, 2, 1, 2, 32, 2)
 #undef SOAR_SHAPE
 
-// Codebook splits of a sweep: P.ksplit, at most one per tile (the host checks P.ksplit <= K / 64
-// and every tile holds at most 64 columns, so this never lowers it).
+// Codebook splits of a sweep: P.ksplit (launch_lowp_sweep checks P.ksplit <= K / 64; every tile
+// holds at most 64 columns, so each split gets at least one tile and the merge's S matches).
 template <int FMT, int DP>
 static int ksplit_tiles(const LowpParams& P) {
-  const int nt = (P.K + SweepShape<FMT, DP>::BN - 1) / SweepShape<FMT, DP>::BN;
-  return P.ksplit < 1 ? 1 : P.ksplit > nt ? nt : P.ksplit;
+  static_assert(SweepShape<FMT, DP>::BN <= 64, "a split per 64 columns covers a tile");
+  return P.ksplit < 1 ? 1 : P.ksplit;
 }
 
 template <int FMT, int DP>
@@ -1066,16 +1072,28 @@ static void sweep_dp(const LowpParams& P, bool spill, hipStream_t st) {
   using S = SweepShape<FMT, DP>;
   if (spill) {
     constexpr int NW = lowp_wg_waves(S::WPE_S);
+    const int ks = ksplit_tiles<FMT, DP>(P);
     const dim3 grid((unsigned)((P.n + 16 * NW * S::SPW_S - 1) / (16 * NW * S::SPW_S)),
-                    (unsigned)ksplit_tiles<FMT, DP>(P));
-    hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, S::SPW_S, S::BN, S::STG, S::WPE_S, true>),
-                       grid, dim3(64 * NW), 0, st, P);
+                    (unsigned)ks);
+    if (ks > 1)
+      hipLaunchKernelGGL(
+          (lowp_sweep_kernel<FMT, DP, S::SPW_S, S::BN, S::STG, S::WPE_S, true, false, false, true>),
+          grid, dim3(64 * NW), 0, st, P);
+    else
+      hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, S::SPW_S, S::BN, S::STG, S::WPE_S, true>),
+                         grid, dim3(64 * NW), 0, st, P);
   } else {
     constexpr int NW = lowp_wg_waves(S::WPE_P);
+    const int ks = ksplit_tiles<FMT, DP>(P);
     const dim3 grid((unsigned)((P.n + 16 * NW * S::SPW_P - 1) / (16 * NW * S::SPW_P)),
-                    (unsigned)ksplit_tiles<FMT, DP>(P));
-    hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, S::SPW_P, S::BN, S::STG, S::WPE_P, false>),
-                       grid, dim3(64 * NW), 0, st, P);
+                    (unsigned)ks);
+    if (ks > 1)
+      hipLaunchKernelGGL(
+          (lowp_sweep_kernel<FMT, DP, S::SPW_P, S::BN, S::STG, S::WPE_P, false, false, false, true>),
+          grid, dim3(64 * NW), 0, st, P);
+    else
+      hipLaunchKernelGGL((lowp_sweep_kernel<FMT, DP, S::SPW_P, S::BN, S::STG, S::WPE_P, false>),
+                         grid, dim3(64 * NW), 0, st, P);
   }
 }
 
@@ -1133,6 +1151,8 @@ static void sweep_fmt(const LowpParams& P, bool spill, hipStream_t st) {
 }
 
 hipError_t launch_lowp_sweep(int fmt, const LowpParams& P, bool spill, hipStream_t st) {
+  if (P.ksplit > 1 && ((int64_t)P.ksplit * 64 > P.K || !P.cand_split || !P.cand_val))
+    return hipErrorInvalidValue;
   if (fmt == LOWP_BF16) sweep_fmt<LOWP_BF16>(P, spill, st);
   else sweep_fmt<LOWP_FP8>(P, spill, st);
   return hipGetLastError();
