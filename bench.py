@@ -38,8 +38,8 @@ COPY_SCALE = {"fetch": 1048576.0 / 524302.5, "write": 1.0}
 TRAFFIC = {
     # grouped FP32 pipeline, per step: primary pass, grouping by primary, grouped spill pass
     ("fp32", "mix4096_n1m_d128"): dict(
-        fetch_kib=255825.7 + 1966.1 + 6.8 + 2039.5 + 85.2 + 2 * 10.2 + 261111.0,
-        write_kib=7820.1 + 960.1 + 15.7 + 11349.3 + 1056.3 + 2 * 7.8 + 65651.9,
+        fetch_kib=256048.0 + 1966.1 + 6.8 + 2041.4 + 85.2 + 2 * 10.2 + 261088.9,
+        write_kib=7820.1 + 960.1 + 15.7 + 10327.4 + 1056.3 + 2 * 7.8 + 65646.3,
         sources={"paper_2404_00774_amd/csrc/assign_fp32.hip":
                  "4a87372bd2ae3d68bfc31fc169bbd0b947cc0725726c1eb1b6477972277de292",
                  "paper_2404_00774_amd/csrc/group.hip":
@@ -76,15 +76,15 @@ def parse():
     ap.add_argument("--workload", default="mix4096_n1m_d128")
     ap.add_argument("--lam", default=None,
                     help="comma list of lambdas (default: the workload's, 1.0 first); the first "
-                         "is the headline, every one is timed and judged")
+                         "is the headline, every one is timed and checked")
     ap.add_argument("--recall-queries", type=int, default=1000,
                     help="queries of the recall@10 check (workloads that define queries; 0: off)")
     ap.add_argument("--precision", default="fp32,bf16,fp8")
     ap.add_argument("--form-steps", type=int, default=5, help="timed steps of the extra forms")
     ap.add_argument("--no-cpu-baseline", action="store_true",
-                    help="skip the oracle timing (the oracle still judges a sample of every form)")
+                    help="skip the oracle timing (the oracle still checks a sample of every form)")
     ap.add_argument("--cpu-sample", type=int, default=500_000)
-    ap.add_argument("--judge-sample", type=int, default=5_000)
+    ap.add_argument("--check-sample", type=int, default=5_000)
     ap.add_argument("--codebook", default="train", choices=["train", "sample"],
                     help="sample: K uniformly sampled rows, no training (for short profiling runs)")
     ap.add_argument("--rows", type=int, default=0, help="use only the first N rows (profiling)")
@@ -108,19 +108,19 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline_leg(X, C, lams, spec, cpu_sample, judge_idx, sweep, recall):
+def cpu_baseline_leg(X, C, lams, spec, cpu_sample, check_idx, sweep, recall):
     """The oracle leg: the FP64 oracle timed on a bounded sample of the workload (the CPU
     baseline); the oracle's answers on a second sample compared with every GPU form at every
     lambda; the lambda trend of the spilled residuals (Figure 9); and, with queries, recall@10 of
     top-t partition probing with and without the spilled assignment (Eq. 1) against brute force."""
     import oracle as O
     from synth import sample_rows as sr
-    X64, C64 = X[judge_idx].astype(np.float64), C.astype(np.float64)
+    X64, C64 = X[check_idx].astype(np.float64), C.astype(np.float64)
     trend = {}
     for lam, forms in sweep.items():
         for prec, r in forms.items():
             outs = r.pop("out")
-            r["oracle_check"] = judge_form(O, X, C, lam, judge_idx, outs)
+            r["oracle_check"] = verify_form(O, X, C, lam, check_idx, outs)
             if prec == next(iter(forms)):
                 p, s_ = outs[0].astype(np.int64), outs[1].astype(np.int64)
                 Rr, Rs = X64 - C64[p], X64 - C64[s_]
@@ -197,9 +197,9 @@ def time_form(soar, torch, Xg, Cg, lam, prec, steps, warmup, n, d, K):
                 out=tuple(t.cpu().numpy() for t in out))
 
 
-def judge_form(O, X, C, lam, idx, outs):
+def verify_form(O, X, C, lam, idx, outs):
     p, s, dp, ls = outs
-    j = O.judge(X[idx], C, lam, p, s, dp, ls)
+    j = O.verify(X[idx], C, lam, p, s, dp, ls)
     pr, sr = j["primary_regret"], j["spill_regret"]
     return {"rows": int(len(idx)), "exact_by_rule": bool(j["all_ok"]),
             "primary_index_disagreement": float((p != j["p_star"]).mean()),
@@ -436,7 +436,7 @@ def main():
         t_lloyd = time.perf_counter() - t0
         del labels, C0
     C = Cg.cpu().numpy()
-    idx = sample_rows(spec, args.judge_sample)
+    idx = sample_rows(spec, args.check_sample)
 
     sweep, full = {}, {}
     alg = 4.0 * n * K * d
@@ -471,7 +471,7 @@ def main():
                 "kernel": KERNEL[precs[0]], "kernel_ms": head["kernel_ms"],
                 "algorithmic_flops_per_launch": alg}
 
-    print(f"[bench] oracle leg: judging {len(idx)} rows per form and lambda"
+    print(f"[bench] oracle leg: checking {len(idx)} rows per form and lambda"
           + ("" if args.no_cpu_baseline else f", timing {args.cpu_sample} rows")
           + (f", recall@10 over {nq} queries" if nq else ""), file=sys.stderr, flush=True)
     recall = {"queries": Q, "ts": (1, 2, 4, 8, 16, 32, 64, 128), "assign": full} if nq else None

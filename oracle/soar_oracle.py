@@ -359,13 +359,13 @@ def kmr_curve(Q, X, C, assignments, k, ts, gt=None):
 # Acceptance rule for a GPU result
 # ----------------------------------------------------------------------------------------------
 
-def judge(X, C, lam, gpu_primary, gpu_spill, gpu_pdist=None, gpu_sloss=None, fast=True,
+def verify(X, C, lam, gpu_primary, gpu_spill, gpu_pdist=None, gpu_sloss=None, fast=True,
           band=1e-6, loss_tol=1e-5):
     """Check a GPU assignment against the oracle.
 
     * primary: accepted if equal to the oracle's, or its exact distance is within ``band``
       (relative) of the best;
-    * spill: judged with the oracle conditioned on the GPU primary; accepted if equal, or not the
+    * spill: checked with the oracle conditioned on the GPU primary; accepted if equal, or not the
       primary and its exact loss within ``band`` (relative) of the best;
     * reported distance / loss: within ``loss_tol`` (relative) of the exact value at the GPU's index.
     Returns a dict of per-row boolean arrays and regret statistics."""

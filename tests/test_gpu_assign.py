@@ -31,7 +31,7 @@ def _run(X, C, lam, **kw):
 def _check(X, C, lam, res, fast=True):
     p, s, dp, ls, st = res
     print("  stats", {k: st[k] for k in ("rows_full_scan", "rows_fp64")}, flush=True)
-    j = O.judge(X, C, lam, p, s, dp, ls, fast=fast)
+    j = O.verify(X, C, lam, p, s, dp, ls, fast=fast)
     bad = np.flatnonzero(~(j["primary_ok"] & j["spill_ok"] & j["pdist_ok"] & j["sloss_ok"]))
     assert bad.size == 0, (f"{bad.size} rows fail, first {bad[:5]}: gpu p={p[bad[:5]]} "
                            f"s={s[bad[:5]]} oracle p={j['p_star'][bad[:5]]} "

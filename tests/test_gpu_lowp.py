@@ -33,7 +33,7 @@ def _run(X, C, lam, prec, topk=0, form="auto"):
 
 def _report(X, C, lam, res, tag):
     p, s, dp, ls, st = res
-    j = O.judge(X, C, lam, p, s, dp, ls)
+    j = O.verify(X, C, lam, p, s, dp, ls)
     out = dict(primary_disagree=float((p != j["p_star"]).mean()),
                spill_disagree=float((s != j["s_star"]).mean()),
                primary_regret_mean=float(j["primary_regret"].mean()),
@@ -107,7 +107,7 @@ def test_edge_shapes(prec, n, d, K, topk, form):
     eff = topk if topk else 8                     # candidates re-scored per row
     if K <= 16 and eff >= K:
         # with at most 16 columns every column is its class minimum, and all are re-scored
-        j = O.judge(X, C, 1.0, res[0], res[1])
+        j = O.verify(X, C, 1.0, res[0], res[1])
         assert j["primary_ok"].all() and j["spill_ok"].all()
 
 

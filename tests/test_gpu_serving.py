@@ -59,7 +59,7 @@ def test_mixed_requests_match_standalone_assign(data, prec):
     assert got == want
     ix.close()
     if prec == "fp32":
-        j = O.judge(X[:lo], C, lam, ref_p[:lo], ref_s[:lo])
+        j = O.verify(X[:lo], C, lam, ref_p[:lo], ref_s[:lo])
         assert j["primary_ok"].all() and j["spill_ok"].all()
 
 
@@ -109,7 +109,7 @@ def test_split_codebook_steps(prec):
     want = sorted([(i, int(p[i])) for i in range(n)] + [(i, int(s[i])) for i in range(n)])
     assert got == want
     ix.close()
-    j = O.judge(X[:n], C, 1.0, p, s)
+    j = O.verify(X[:n], C, 1.0, p, s)
     bound = 1e-3 if prec == "bf16" else 1e-2
     print(prec, "split serving: primary regret", float(j["primary_regret"].mean()),
           "spill regret", float(j["spill_regret"].mean()), flush=True)

@@ -78,7 +78,7 @@ def test_lloyd_iterations_per_step(small):
         print(f"lloyd step {it}", flush=True)
         Cg0, lab0, in0 = soar.train_codebook(_t(X), K, 0, C_init=_t(Ct))
         lab0 = lab0.cpu().numpy()
-        j = O.judge(X, Ct.astype(np.float32), 0.0, lab0, (lab0 + 1) % K)
+        j = O.verify(X, Ct.astype(np.float32), 0.0, lab0, (lab0 + 1) % K)
         assert j["primary_ok"].all()
         assert in0[0] == pytest.approx(float(j["d_star"].sum()), rel=1e-5)
         Cg1, _, in1 = soar.train_codebook(_t(X), K, 1, C_init=_t(Ct))
@@ -98,7 +98,7 @@ def test_train_end_to_end_inertia(small):
     assert all(b <= a * (1 + 1e-6) for a, b in zip(inertia, inertia[1:]))
     # trajectories may part after a near-tie flip; the end result must be as good
     assert abs(inertia[-1] - inertia_o[-1]) <= 1e-3 * inertia_o[-1]
-    j = O.judge(X, Cg.cpu().numpy(), 0.0, labg.cpu().numpy(), (labg.cpu().numpy() + 1) % w["K"])
+    j = O.verify(X, Cg.cpu().numpy(), 0.0, labg.cpu().numpy(), (labg.cpu().numpy() + 1) % w["K"])
     assert j["primary_ok"].all()
 
 

@@ -431,13 +431,13 @@ def test_kmeanspp_distinct_and_degenerate():
     assert list(rows[1:]) == rest
 
 
-def test_judge_accepts_oracle_and_rejects_wrong(rnd_case):
+def test_verify_accepts_oracle_and_rejects_wrong(rnd_case):
     X, C = rnd_case
     p, dp, s, ls = O.assign(X, C, 1.0)
-    j = O.judge(X, C, 1.0, p, s, dp, ls)
+    j = O.verify(X, C, 1.0, p, s, dp, ls)
     assert j["all_ok"]
     bad = s.copy()
     bad[5] = p[5]                                      # the primary is never a valid spill
     bad[6] = (s[6] + 1) % C.shape[0] if (s[6] + 1) % C.shape[0] != p[6] else (s[6] + 2) % C.shape[0]
-    j = O.judge(X, C, 1.0, p, bad, dp, ls)
+    j = O.verify(X, C, 1.0, p, bad, dp, ls)
     assert not j["spill_ok"][5] and not j["spill_ok"][6] and j["spill_ok"].sum() == len(X) - 2
