@@ -474,12 +474,21 @@ void lowp_sweep_kernel(LowpParams P) {
   float espv[GPD ? SPW : 1][GU];                  // GPD: S of each stripe's centroid row
   // GR: do all stripes of the wave share their primary?  (Stripes are ordered by primary, so
   // most waves' stripes do.)  Wave-uniform.
-  bool samep = false;
+  // If not, do they hold only the primaries of the first and the last stripe (a wave across one
+  // partition boundary)?  Then two broadcasts serve them, and psel picks each stripe's.
+  bool samep = false, twop = false;
+  bool psel[GR ? SPW : 1];
   if constexpr (GR && SPW > 1) {
-    bool same = true;
+    bool same = true, two = true;
 #pragma unroll
-    for (int st = 1; st < SPW; ++st) same = same && sd[st].x == sd[0].x;
+    for (int st = 0; st < SPW; ++st) {
+      const bool first = sd[st].x == sd[0].x;
+      same = same && first;
+      two = two && (first || sd[st].x == sd[SPW - 1].x);
+      psel[st] = __builtin_amdgcn_readfirstlane((int)first) != 0;
+    }
     samep = __builtin_amdgcn_readfirstlane((int)same) != 0;
+    twop = __builtin_amdgcn_readfirstlane((int)two) != 0;
   }
   auto epi_prep = [&](auto set, int ts, int g) __attribute__((always_inline)) {
     constexpr int S = decltype(set)::value;
@@ -506,6 +515,13 @@ void lowp_sweep_kernel(LowpParams P) {
           const float e = bcast(0, b);
 #pragma unroll
           for (int st = 0; st < SPW; ++st) espv[st][b] = e;
+        }
+      } else if (GR && SPW > 2 && twop) {
+#pragma unroll
+        for (int b = 0; b < GU; ++b) {
+          const float e0 = bcast(0, b), e1 = bcast(SPW - 1, b);
+#pragma unroll
+          for (int st = 0; st < SPW; ++st) espv[st][b] = psel[st] ? e0 : e1;
         }
       } else {
 #pragma unroll
