@@ -94,6 +94,20 @@ def test_fp8_d768_lognormal():
 
 @pytest.mark.parametrize("form", ["grouped", "direct"])
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_wide_row_scales(prec, form):
+    """Row norms spread over 2^-20 .. 2^20: the FP8 rows' power-of-two scales reach the MFMA as
+    block-scale exponents far from 1, and the BF16 rows keep their own exponents."""
+    rng = np.random.default_rng(21)
+    X = gen_mixture(MixtureSpec(6000, 64, 64, 0.3, "unit", 21))
+    X = (X * np.exp2(rng.integers(-20, 21, size=(len(X), 1)))).astype(np.float32)
+    C = (X[rng.choice(len(X), 300, replace=False)] * 0.97).astype(np.float32)
+    r = _report(X, C, 1.0, _run(X, C, 1.0, prec, form=form), f"{prec} wide scales {form}")
+    bound = 1e-3 if prec == "bf16" else 1e-2
+    assert r["primary_regret_mean"] <= bound and r["spill_regret_mean"] <= bound
+
+
+@pytest.mark.parametrize("form", ["grouped", "direct"])
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
 @pytest.mark.parametrize("n,d,K,topk", [(1, 8, 2, 0), (37, 1, 3, 0), (300, 5, 9, 4), (513, 33, 17, 8),
                                         (200, 100, 70, 2), (129, 300, 40, 0), (4000, 64, 7, 8),
                                         (1000, 40, 16, 16), (700, 24, 13, 0)])
