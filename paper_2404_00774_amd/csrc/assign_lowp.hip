@@ -864,7 +864,7 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
   float x[RS_MAXD], r[RS_MAXD];
   rs_load<V4, RS_MAXD>(P.X + row * d, d, l16, x);
   int pi = -1;
-  float rr = 0.f;
+  float rr = 0.f, lr = 0.f;                       // ||r||^2 and lambda / ||r||^2
   if constexpr (SP) {
     pi = P.primary[row];
     if (pi < 0 || pi >= P.K) {   // no primary: nothing to spill
@@ -879,6 +879,7 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
       if (m & 1) a1 = fmaf(r[m], r[m], a1); else a0 = fmaf(r[m], r[m], a0);
     }
     rr = sum16(a0 + a1);
+    lr = rr > 0.f ? P.lam / rr : 0.f;             // one division per row, not per candidate
   }
   // FP32 pass
   float best = kInf;
@@ -903,7 +904,7 @@ __global__ __launch_bounds__(256) void lowp_rescore_kernel(LowpParams P) {
     float val = sq;
     if constexpr (SP) {
       const float pj = sum16(p0 + p1);
-      if (rr > 0.f) val = sq + P.lam * (pj * pj) / rr;
+      val = fmaf(lr, pj * pj, sq);
     }
     vals[c] = val;
     if (val < best || (val == best && j < bj)) { best = val; bj = j; }
