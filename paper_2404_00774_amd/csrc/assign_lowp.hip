@@ -1055,7 +1055,7 @@ struct SweepShape;
 #define SOAR_SHAPE_BF16_128 4, 2, 2, 1, 64, 3
 #endif
 #ifndef SOAR_SHAPE_BF16_768
-#define SOAR_SHAPE_BF16_768 2, 1, 2, 1, 32, 2
+#define SOAR_SHAPE_BF16_768 4, 1, 2, 1, 32, 2
 #endif
 #ifndef SOAR_SHAPE_FP8_768
 #define SOAR_SHAPE_FP8_768 2, 1, 2, 1, 32, 2
@@ -1119,13 +1119,18 @@ static void sweep_dp(const LowpParams& P, bool spill, hipStream_t st) {
 
 // The grouped spill runs one MFMA stream at the primary's waves per SIMD.  Over X rows it keeps
 // two more row constants than the primary sweep and takes the spill's stripes per wave; over
-// residual rows (GR) it keeps one, and takes the primary's up to 96 dimensions.  At 128 the
-// primary's four stripes would spill registers; three measured 5% faster than two
-// (BF16, n=1M, K=2000: 1.42 vs 1.50 ms).
+// residual rows (GR) it keeps one, and takes the primary's up to 96 dimensions and at 768.  At
+// 128 the primary's four stripes would spill registers; three measured 5% faster than two
+// (BF16, n=1M, K=2000: 1.42 vs 1.50 ms).  At 768 (one wave per SIMD) four BF16 stripes per wave
+// read each B operand from LDS for four MFMAs instead of two: 20.2 -> 16.1 ms at n=500K,
+// K=10,000 (three stripes measured far slower, and FP8 gained nothing from three or four).
 template <int FMT, int DP, bool GR>
 static void sweep_grouped_dp(const LowpParams& P, hipStream_t st) {
   using S = SweepShape<FMT, DP>;
-  constexpr int SPW = !GR ? S::SPW_S : DP <= 96 ? S::SPW_P : DP == 128 ? 3 : S::SPW_S;
+  constexpr int SPW = !GR                      ? S::SPW_S
+                      : DP <= 96 || DP == 768 ? S::SPW_P
+                      : DP == 128             ? 3
+                                              : S::SPW_S;
   const int64_t ms = group_max_stripes(P.n, P.K);
   constexpr int NW = lowp_wg_waves(S::WPE_P);
   const dim3 grid((unsigned)((ms + NW * SPW - 1) / (NW * SPW)));
