@@ -161,6 +161,20 @@ def test_full_size_sampled_parity():
         assert st["rows_full_scan"] < 0.02 * len(X)
 
 
+def test_full_size_d768_sampled():
+    """n = 2,000,000, d = 768, K = 10,000 with lognormal norms (the FP8 workload's shape) in FP32:
+    the direct two-stream form the benchmark times there; the oracle checks 2000 sampled rows."""
+    w = WORKLOADS["mix8192_n2m_d768_lognorm"]
+    spec = w["spec"]
+    X = gen_mixture(spec)
+    C = X[sample_rows(spec, w["K"])]
+    print("full size d768 fp32", flush=True)
+    p, s, dp, ls, st = _run(X, C, 1.0)
+    idx = np.sort(np.random.default_rng(11).choice(len(X), 2000, replace=False))
+    _check(X[idx], C, 1.0, (p[idx], s[idx], dp[idx], ls[idx], st))
+    assert st["rows_full_scan"] < 0.02 * len(X)
+
+
 @pytest.mark.parametrize("d,K", [(96, 3000), (200, 1000), (256, 1500)])
 def test_grouped_at_scale_matches_direct(d, K):
     """n = 100,000 (well past the size where the grouped spill is chosen) for the wider whole-row
