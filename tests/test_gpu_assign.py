@@ -161,14 +161,16 @@ def test_full_size_sampled_parity():
         assert st["rows_full_scan"] < 0.02 * len(X)
 
 
-def test_full_size_d768_sampled():
-    """n = 2,000,000, d = 768, K = 10,000 with lognormal norms (the FP8 workload's shape) in FP32:
-    the direct two-stream form the benchmark times there; the oracle checks 2000 sampled rows."""
-    w = WORKLOADS["mix8192_n2m_d768_lognorm"]
+@pytest.mark.parametrize("wl", ["mix8192_n2m_d768_lognorm", "mix16384_n10m_d96"])
+def test_full_size_large_sampled(wl):
+    """The large workloads in FP32 at full size: n = 2,000,000, d = 768, K = 10,000 with lognormal
+    norms (the direct two-stream form), and n = 10,000,000, d = 96, K = 40,000 (the grouped spill),
+    as the benchmark times them; the oracle checks 2000 sampled rows."""
+    w = WORKLOADS[wl]
     spec = w["spec"]
     X = gen_mixture(spec)
     C = X[sample_rows(spec, w["K"])]
-    print("full size d768 fp32", flush=True)
+    print(f"full size {wl} fp32", flush=True)
     p, s, dp, ls, st = _run(X, C, 1.0)
     idx = np.sort(np.random.default_rng(11).choice(len(X), 2000, replace=False))
     _check(X[idx], C, 1.0, (p[idx], s[idx], dp[idx], ls[idx], st))
