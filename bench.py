@@ -62,10 +62,12 @@ def measured_traffic(prec, workload):
     return (t["fetch_kib"] * COPY_SCALE["fetch"] + t["write_kib"] * COPY_SCALE["write"]) * 1024.0
 METRIC = "SOAR-assigned points/sec and % MFMA peak, BF16/FP8 vs FP32 at ≤1e-3 regret"
 DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8_e4m3"}
-KERNEL = {"fp32": "assign_f32_kernel (primary) + grouping by primary + assign_f32_spill_grouped "
-                  "(spill); the direct form runs primary and spill in assign_f32_kernel",
-          "bf16": "lowp_sweep_kernel x2 (primary sweep + spill sweep)",
-          "fp8": "lowp_sweep_kernel x2 (primary sweep + spill sweep)"}
+KERNEL = {"fp32": "codebook packing, assign_f32_kernel (primary), grouping by primary, "
+                  "assign_f32_spill_grouped (spill), exact full scan",
+          "bf16": "quantization, lowp_sweep_kernel (primary), lowp_rescore_kernel, grouping by "
+                  "primary, lowp_sweep_kernel (spill), lowp_rescore_kernel",
+          "fp8": "quantization, lowp_sweep_kernel (primary), lowp_rescore_kernel, grouping by "
+                 "primary, lowp_sweep_kernel (spill), lowp_rescore_kernel"}
 
 
 def parse():
@@ -73,18 +75,22 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mix4096_n1m_d128")
+    ap.add_argument("--workload", default="mix16384_n10m_d96")
     ap.add_argument("--lam", default=None,
                     help="comma list of lambdas (default: the workload's, 1.0 first); the first "
                          "is the headline, every one is timed and checked")
-    ap.add_argument("--recall-queries", type=int, default=1000,
-                    help="queries of the recall@10 check (workloads that define queries; 0: off)")
-    ap.add_argument("--precision", default="fp32,bf16,fp8")
-    ap.add_argument("--form-steps", type=int, default=5, help="timed steps of the extra forms")
+    ap.add_argument("--recall-queries", type=int, default=None,
+                    help="queries of the recall@10 check (workloads that define queries; 0: off; "
+                         "default: the workload's)")
+    ap.add_argument("--precision", default="bf16,fp32,fp8",
+                    help="comma list; the first is the headline form")
+    ap.add_argument("--form-steps", type=int, default=3, help="timed steps of the other forms")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (the oracle still checks a sample of every form)")
-    ap.add_argument("--cpu-sample", type=int, default=500_000)
-    ap.add_argument("--check-sample", type=int, default=5_000)
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="rows of the oracle timing (default: the workload's, ~10-30 s of CPU)")
+    ap.add_argument("--check-sample", type=int, default=None,
+                    help="rows the oracle checks every form on (default: the workload's)")
     ap.add_argument("--codebook", default="train", choices=["train", "sample"],
                     help="sample: K uniformly sampled rows, no training (for short profiling runs)")
     ap.add_argument("--rows", type=int, default=0, help="use only the first N rows (profiling)")
@@ -97,7 +103,10 @@ def parse():
     ap.add_argument("--serve-K", type=int, default=50_000)
     ap.add_argument("--serve-rates", default="5000,20000,50000,100000,200000",
                     help="offered insert rates, vectors/s")
-    ap.add_argument("--serve-seconds", type=float, default=8.0, help="arrival window per rate")
+    ap.add_argument("--serve-requests", type=int, default=10_000,
+                    help="requests per offered rate (the window is the time they take to arrive)")
+    ap.add_argument("--serve-max-seconds", type=float, default=60.0,
+                    help="cap on the arrival window per rate")
     ap.add_argument("--serve-step-rows", type=int, default=16384, help="rows per step slot")
     ap.add_argument("--serve-train-rows", type=int, default=2_000_000,
                     help="rows (a prefix of the base) the serving codebook is trained on")
@@ -108,67 +117,104 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline_leg(X, C, lams, spec, cpu_sample, check_idx, sweep, recall):
-    """The oracle leg: the FP64 oracle timed on a bounded sample of the workload (the CPU
-    baseline); the oracle's answers on a second sample compared with every GPU form at every
-    lambda; the lambda trend of the spilled residuals (Figure 9); and, with queries, recall@10 of
-    top-t partition probing with and without the spilled assignment (Eq. 1) against brute force."""
-    import oracle as O
-    from synth import sample_rows as sr
-    X64, C64 = X[check_idx].astype(np.float64), C.astype(np.float64)
-    trend = {}
-    for lam, forms in sweep.items():
-        for prec, r in forms.items():
-            outs = r.pop("out")
-            r["oracle_check"] = verify_form(O, X, C, lam, check_idx, outs)
-            if prec == next(iter(forms)):
-                p, s_ = outs[0].astype(np.int64), outs[1].astype(np.int64)
-                Rr, Rs = X64 - C64[p], X64 - C64[s_]
-                rr, ss = (Rr * Rr).sum(1), (Rs * Rs).sum(1)
-                ok = rr > 0
-                cos2 = (Rr * Rs).sum(1)[ok] ** 2 / (rr[ok] * ss[ok])
-                trend[lam] = {"form": prec, "mean_cos2_r_rspill": float(cos2.mean()),
-                              "mean_rspill_sq": float(ss.mean())}
-    lam_sorted = sorted(trend)
-    trend_out = {"per_lambda": {str(l): trend[l] for l in lam_sorted},
-                 "cos2_nonincreasing": all(trend[a]["mean_cos2_r_rspill"] >=
-                                           trend[b]["mean_cos2_r_rspill"] - 1e-12
-                                           for a, b in zip(lam_sorted, lam_sorted[1:])),
-                 "rspill_nondecreasing": all(trend[a]["mean_rspill_sq"] <=
-                                             trend[b]["mean_rspill_sq"] + 1e-12
-                                             for a, b in zip(lam_sorted, lam_sorted[1:]))}
-    rec = None
-    if recall:
-        Q, ts, full = recall["queries"], recall["ts"], recall["assign"]
-        gt = O.mips_topk(Q, X, 10)
-        rec = {"queries": int(len(Q)), "k": 10, "t": list(ts), "per_lambda": {}}
-        for lam, (p, s_) in full.items():
-            k0, n0 = O.kmr_curve(Q, X, C, [p], 10, ts, gt=gt)
-            k1, n1 = O.kmr_curve(Q, X, C, [p, s_], 10, ts, gt=gt)
-            rec["per_lambda"][str(lam)] = {
-                "recall_unspilled": [float(v) for v in k0], "recall_spilled": [float(v) for v in k1],
-                "points_searched_unspilled": [float(v) for v in n0],
-                "points_searched_spilled": [float(v) for v in n1]}
-    cpu = None
-    if cpu_sample:
-        try:
-            from threadpoolctl import threadpool_info
-            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-        except Exception:  # noqa: BLE001
-            threads = os.cpu_count() or 1
-        lam = lams[0]
-        Xs = X[sr(spec, cpu_sample)]
-        O.assign(Xs[:2000], C, lam)                     # warm-up (BLAS threads, page faults)
-        t0 = time.perf_counter()
-        O.assign(Xs, C, lam)
-        dt = time.perf_counter() - t0
-        cpu = {"value": len(Xs) / dt, "unit": "points/s", "cores": int(threads), "kind": "oracle",
-               "sample": f"{len(Xs)} uniformly sampled rows of the workload, FP64 screened oracle, "
-                         f"lambda {lam}, {dt:.2f} s wall"}
-    return cpu, trend_out, rec
+def _threads():
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except Exception:  # noqa: BLE001
+        return max(1, min(16, os.cpu_count() or 1))
 
 
-def time_form(soar, torch, Xg, Cg, lam, prec, steps, warmup, n, d, K):
+def oracle_reference(O, X, C, lam, idx, workers):
+    """The oracle's answers on rows idx, computed over row chunks in parallel threads (the oracle
+    is row-independent; BLAS runs single-threaded inside each worker)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
+    chunks = [idx[i:i + 2000] for i in range(0, len(idx), 2000)]
+    with threadpool_limits(1), ThreadPoolExecutor(workers) as ex:
+        parts = list(ex.map(lambda r: O.reference(X[r], C, lam), chunks))
+    return {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+
+
+def verify_form(O, X, C, lam, idx, outs, ref, workers, cands=None):
+    """The acceptance rule and regret statistics of one GPU form on rows idx (oracle reference
+    reused; rows whose GPU primary differs from the oracle's get the conditioned spill anew)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
+    p, s, dp, ls = outs
+    pos = np.arange(len(idx))
+    chunks = [pos[i:i + 2000] for i in range(0, len(idx), 2000)]
+
+    def one(r):
+        sub = {k: v[r] for k, v in ref.items()}
+        return O.verify(X[idx[r]], C, lam, p[r], s[r], dp[r], ls[r], ref=sub)
+    with threadpool_limits(1), ThreadPoolExecutor(workers) as ex:
+        parts = list(ex.map(one, chunks))
+    cat = lambda k: np.concatenate([q[k] for q in parts])  # noqa: E731
+    pr, sr = cat("primary_regret"), cat("spill_regret")
+    p_star, s_star = cat("p_star"), cat("s_star")
+    ok = cat("primary_ok") & cat("spill_ok")
+    out = {"rows": int(len(idx)), "exact_by_rule": bool(ok.all()),
+           "rows_outside_rule": int((~ok).sum()),
+           "primary_index_disagreement": float((p != p_star).mean()),
+           "spill_index_disagreement": float((s != s_star).mean()),
+           "primary_regret_mean": float(pr.mean()), "primary_regret_p99": float(np.quantile(pr, .99)),
+           "spill_regret_mean": float(sr.mean()), "spill_regret_p99": float(np.quantile(sr, .99)),
+           "values_exact_at_index": bool(cat("pdist_ok").all() and cat("sloss_ok").all())}
+    if cands is not None:
+        # rows whose oracle best was not among the candidates the GPU re-scored
+        pc, sc = cands
+        out["candidate_misses_primary"] = int((~(pc == p_star[:, None]).any(1)).sum())
+        out["candidate_misses_spill"] = int((~(sc == s_star[:, None]).any(1)).sum())
+    return out
+
+
+def cpu_baseline_leg(O, X, C, lam, rows):
+    """The oracle as it stands, timed on a bounded sample of the workload (the CPU baseline)."""
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        threads = os.cpu_count() or 1
+    Xs = X[rows]
+    O.assign(Xs[:200], C, lam)                      # warm-up (BLAS threads, page faults)
+    t0 = time.perf_counter()
+    O.assign(Xs, C, lam)
+    dt = time.perf_counter() - t0
+    return {"value": len(Xs) / dt, "unit": "points/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{len(Xs)} uniformly sampled rows of the workload (FP64 screened oracle, "
+                      f"lambda {lam}), {dt:.2f} s wall; BLAS on {threads} threads, the rest of "
+                      "the oracle single-threaded"}
+
+
+def lambda_trend(X64, C64, outs):
+    """Mean cos^2(r, r') and mean ||r'||^2 of a form's answers (Figure 9's lambda trend)."""
+    p, s_ = outs[0].astype(np.int64), outs[1].astype(np.int64)
+    Rr, Rs = X64 - C64[p], X64 - C64[s_]
+    rr, ss = (Rr * Rr).sum(1), (Rs * Rs).sum(1)
+    ok = rr > 0
+    cos2 = (Rr * Rs).sum(1)[ok] ** 2 / (rr[ok] * ss[ok])
+    return {"mean_cos2_r_rspill": float(cos2.mean()), "mean_rspill_sq": float(ss.mean())}
+
+
+def recall_leg(O, Q, X, C, ts, full):
+    """Recall@10 of top-t partition probing with and without the spilled assignment (Eq. 1)
+    against brute force."""
+    gt = O.mips_topk(Q, X, 10)
+    rec = {"queries": int(len(Q)), "k": 10, "t": list(ts), "per_lambda": {}}
+    for lam, (p, s_) in full.items():
+        k0, n0 = O.kmr_curve(Q, X, C, [p], 10, ts, gt=gt)
+        k1, n1 = O.kmr_curve(Q, X, C, [p, s_], 10, ts, gt=gt)
+        rec["per_lambda"][str(lam)] = {
+            "recall_unspilled": [float(v) for v in k0], "recall_spilled": [float(v) for v in k1],
+            "points_searched_unspilled": [float(v) for v in n0],
+            "points_searched_spilled": [float(v) for v in n1]}
+    return rec
+
+
+def time_form(soar, torch, Xg, Cg, lam, prec, steps, warmup, n, d, K, keep_candidates=False):
+    """Warm-up, then `steps` timed blocking soar_assign calls on resident inputs.  The wall clock
+    brackets the steps (torch.cuda.synchronize on both sides); the library's own HIP events on
+    its stream give each call's device time and its split into phases."""
     dev = Xg.device
     out = tuple(torch.empty(n, dtype=t, device=dev)
                 for t in (torch.int32, torch.int32, torch.float32, torch.float32))
@@ -176,37 +222,29 @@ def time_form(soar, torch, Xg, Cg, lam, prec, steps, warmup, n, d, K):
     for _ in range(warmup):
         soar.assign(Xg, Cg, lam, prec, out=out, workspace=ws)
     torch.cuda.synchronize()
-    kernel_ms, device_ms, full_scan, fp64 = [], [], [], []
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    stats = []
     t0 = time.perf_counter()
-    ev0.record()
     for _ in range(steps):
         *_, st = soar.assign(Xg, Cg, lam, prec, out=out, workspace=ws, stats=True)
-        kernel_ms.append(st["assign_kernel_ms"])
-        device_ms.append(st["device_ms"])
-        full_scan.append(st["rows_full_scan"])
-        fp64.append(st["rows_fp64"])
-    ev1.record()
+        stats.append(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    cands = None
+    if keep_candidates and prec != "fp32" and hasattr(soar, "assign_candidates"):
+        cands = soar.assign_candidates(ws, n, d, K, lam, prec)
+    phases = {k: float(np.mean([st["phase_ms"][k] for st in stats])) for k in stats[0]["phase_ms"]}
+    r = dict(ms_per_step=wall * 1e3 / steps,
+             device_ms=float(np.mean([st["device_ms"] for st in stats])),
+             sweep_ms=float(np.mean([st["assign_kernel_ms"] for st in stats])),
+             phase_ms=phases,
+             rows_full_scan=int(np.mean([st["rows_full_scan"] for st in stats])),
+             rows_fp64=int(np.mean([st["rows_fp64"] for st in stats])),
+             steps=steps, warmup=warmup,
+             out=tuple(t.cpu().numpy() for t in out))
+    if cands is not None:
+        r["cands"] = tuple(c.cpu().numpy() for c in cands)
     del ws
-    return dict(ms_per_step=wall * 1e3 / steps, event_ms_per_step=ev0.elapsed_time(ev1) / steps,
-                kernel_ms=float(np.mean(kernel_ms)), device_ms=float(np.mean(device_ms)),
-                rows_full_scan=int(np.mean(full_scan)), rows_fp64=int(np.mean(fp64)),
-                out=tuple(t.cpu().numpy() for t in out))
-
-
-def verify_form(O, X, C, lam, idx, outs):
-    p, s, dp, ls = outs
-    j = O.verify(X[idx], C, lam, p, s, dp, ls)
-    pr, sr = j["primary_regret"], j["spill_regret"]
-    return {"rows": int(len(idx)), "exact_by_rule": bool(j["all_ok"]),
-            "primary_index_disagreement": float((p != j["p_star"]).mean()),
-            "spill_index_disagreement": float((s != j["s_star"]).mean()),
-            "primary_regret_mean": float(pr.mean()), "primary_regret_p99": float(np.quantile(pr, .99)),
-            "spill_regret_mean": float(sr.mean()), "spill_regret_p99": float(np.quantile(sr, .99)),
-            "values_exact_at_index": bool(j["pdist_ok"].all() and j["sloss_ok"].all())}
+    return r
 
 
 def request_sizes(rng, count):
@@ -242,9 +280,10 @@ def serve_main(args):
     plans = []
     for rate in rates:
         req_rate = rate / mean_size
-        nreq = max(1, int(np.ceil(req_rate * args.serve_seconds * 1.2)) + 8)
+        window = min(args.serve_max_seconds, args.serve_requests / req_rate)
+        nreq = max(1, int(np.ceil(req_rate * window * 1.2)) + 8)
         arr = np.cumsum(rng.exponential(1.0 / req_rate, nreq))
-        arr = arr[arr < args.serve_seconds]
+        arr = arr[arr < window]
         plans.append((rate, arr, request_sizes(rng, len(arr))))
     # request rows: windows of a pool of new rows from the same mixture (a stream separate from
     # the base), reused cyclically; every inserted vector still gets its own id
@@ -350,7 +389,8 @@ def serve_main(args):
         "config": {"workload": f"serve_mix4096_base{spec.n}_d128_K{K}", "n_base": spec.n, "d": spec.d,
                    "K": K, "lambda": lam, "precision": prec, "step_rows": args.serve_step_rows,
                    "arrivals": "open-loop Poisson per rate, request rows floor(exp(U ln 4097)) "
-                               f"in [1, 4096], {args.serve_seconds} s window per rate",
+                               f"in [1, 4096], {args.serve_requests} requests or "
+                               f"{args.serve_max_seconds} s per rate, whichever is shorter",
                    "codebook": f"k-means++ on {min(args.serve_kpp_rows, ktr)} rows, "
                                f"{args.serve_lloyd} Lloyd iterations on {ktr} rows (same GPU)"},
         "base_build": {"rows": spec.n, "seconds": t_base, "vectors_per_s": base_rate},
@@ -397,14 +437,23 @@ def main():
         lams = [float(v) for v in args.lam.split(",") if v.strip()]
     else:
         lams = sorted(w["lambdas"], key=lambda v: (v != 1.0, v))
+    check_rows = args.check_sample if args.check_sample is not None else w.get("check_rows", 5000)
+    cpu_rows = args.cpu_sample if args.cpu_sample is not None else w.get("cpu_rows", 20_000)
+    nq = w.get("queries", 0) if args.recall_queries is None else min(args.recall_queries,
+                                                                       w.get("queries", 0))
+    workers = _threads()
     # inputs are drawn before the GPU is touched (threads: numpy releases the GIL)
     print(f"[bench] generating {args.workload}: n={n} d={d} K={K}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
     CH = 1 << 20
-    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
-        X = np.concatenate(list(ex.map(lambda k: gen_mixture(spec, k * CH, min(n, (k + 1) * CH)),
-                                       range((n + CH - 1) // CH))))
-    nq = min(args.recall_queries, w.get("queries", 0))
+    X = np.empty((n, d), dtype=np.float32)
+
+    def fill(k):
+        X[k * CH:min(n, (k + 1) * CH)] = gen_mixture(spec, k * CH, min(n, (k + 1) * CH))
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(fill, range((n + CH - 1) // CH)))
     Q = gen_queries(spec, nq) if nq else None
+    print(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
     import torch
     import paper_2404_00774_amd as soar
@@ -436,7 +485,7 @@ def main():
         t_lloyd = time.perf_counter() - t0
         del labels, C0
     C = Cg.cpu().numpy()
-    idx = sample_rows(spec, args.check_sample)
+    idx = sample_rows(spec, check_rows)
 
     sweep, full = {}, {}
     alg = 4.0 * n * K * d
@@ -447,37 +496,70 @@ def main():
             steps, warm = (args.steps, args.warmup) if first else (args.form_steps, 1)
             print(f"[bench] lambda {lam} {prec}: warmup {warm}, timing {steps} steps",
                   file=sys.stderr, flush=True)
-            r = time_form(soar, torch, Xg, Cg, lam, prec, steps, warm, n, d, K)
+            r = time_form(soar, torch, Xg, Cg, lam, prec, steps, warm, n, d, K,
+                          keep_candidates=True)
             outs = r.pop("out")
             if k == 0 and Q is not None:
                 full[lam] = (outs[0].copy(), outs[1].copy())
             r["out"] = tuple(a[idx] for a in outs)
-            print(f"[bench] lambda {lam} {prec}: {r['ms_per_step']:.3f} ms/step", file=sys.stderr,
-                  flush=True)
+            if "cands" in r:
+                r["cands"] = tuple(c[idx] for c in r["cands"])
             r["value"] = n / (r["ms_per_step"] / 1e3)
-            r["algorithmic_tflops"] = alg / (r["kernel_ms"] / 1e3) / 1e12
+            # whole call: algorithmic flops over the call's device time; sweeps alone beside it
+            r["algorithmic_tflops"] = alg / (r["device_ms"] / 1e3) / 1e12
             r["mfma_peak_frac"] = r["algorithmic_tflops"] / PEAKS_TFLOPS[prec]
-            r["steps"] = steps
+            r["sweeps_mfma_peak_frac"] = alg / (r["sweep_ms"] / 1e3) / 1e12 / PEAKS_TFLOPS[prec]
+            print(f"[bench] lambda {lam} {prec}: {r['ms_per_step']:.3f} ms/step, device "
+                  f"{r['device_ms']:.3f} ms, {r['mfma_peak_frac']:.3f} of peak; phases "
+                  f"{ {k_: round(v, 3) for k_, v in r['phase_ms'].items()} }",
+                  file=sys.stderr, flush=True)
             forms[prec] = r
         if "fp32" in forms:
             for prec, r in forms.items():
                 r["speedup_vs_fp32"] = forms["fp32"]["ms_per_step"] / r["ms_per_step"]
-        sweep[lams[li]] = forms
+        sweep[lam] = forms
 
     head = sweep[lams[0]][precs[0]]
+    phases = head["phase_ms"]
     roofline = {"bound": "mfma", "achieved": head["algorithmic_tflops"],
                 "peak": PEAKS_TFLOPS[precs[0]], "unit": "TFLOP/s", "frac": head["mfma_peak_frac"],
                 "traffic": measured_traffic(precs[0], args.workload) if not args.rows else None,
-                "kernel": KERNEL[precs[0]], "kernel_ms": head["kernel_ms"],
-                "algorithmic_flops_per_launch": alg}
+                "kernel": "soar_assign, the whole call: " + KERNEL[precs[0]],
+                "kernel_ms": head["device_ms"], "algorithmic_flops_per_launch": alg,
+                "phase_ms": phases,
+                "sweeps_frac": head["sweeps_mfma_peak_frac"]}
 
-    print(f"[bench] oracle leg: checking {len(idx)} rows per form and lambda"
-          + ("" if args.no_cpu_baseline else f", timing {args.cpu_sample} rows")
-          + (f", recall@10 over {nq} queries" if nq else ""), file=sys.stderr, flush=True)
-    recall = {"queries": Q, "ts": (1, 2, 4, 8, 16, 32, 64, 128), "assign": full} if nq else None
-    cpu, trend, rec = cpu_baseline_leg(X, C, lams, spec,
-                                       0 if args.no_cpu_baseline else args.cpu_sample, idx,
-                                       sweep, recall)
+    # ---- oracle leg: reference answers on the check rows, every form judged against them
+    import oracle as O
+    print(f"[bench] oracle leg: {len(idx)} rows, {workers} threads", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    X64, C64 = X[idx].astype(np.float64), C.astype(np.float64)
+    trend = {}
+    for lam, forms in sweep.items():
+        ref = oracle_reference(O, X, C, lam, idx, workers)
+        for prec, r in forms.items():
+            outs = r.pop("out")
+            r["oracle_check"] = verify_form(O, X, C, lam, idx, outs, ref, workers,
+                                            r.pop("cands", None))
+            if prec == next(iter(forms)):
+                trend[lam] = dict(form=prec, **lambda_trend(X64, C64, outs))
+    lam_sorted = sorted(trend)
+    trend_out = {"per_lambda": {str(l): trend[l] for l in lam_sorted},
+                 "cos2_nonincreasing": all(trend[a]["mean_cos2_r_rspill"] >=
+                                           trend[b]["mean_cos2_r_rspill"] - 1e-12
+                                           for a, b in zip(lam_sorted, lam_sorted[1:])),
+                 "rspill_nondecreasing": all(trend[a]["mean_rspill_sq"] <=
+                                             trend[b]["mean_rspill_sq"] + 1e-12
+                                             for a, b in zip(lam_sorted, lam_sorted[1:]))}
+    print(f"[bench] oracle checks done in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    rec = None
+    if Q is not None:
+        rec = recall_leg(O, Q, X, C, (1, 2, 4, 8, 16, 32, 64, 128), full)
+    cpu = None
+    if not args.no_cpu_baseline and cpu_rows:
+        print(f"[bench] CPU baseline: the oracle on {cpu_rows} rows", file=sys.stderr, flush=True)
+        cpu = cpu_baseline_leg(O, X, C, lams[0], sample_rows(spec, cpu_rows))
 
     rec_out = {
         "metric": METRIC, "value": head["value"], "unit": "points/s", "n_gpus": 1,
@@ -494,7 +576,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": sweep[lams[0]],
         "lambda_sweep": {str(l): sweep[l] for l in lams[1:]},
-        "lambda_trend": trend,
+        "lambda_trend": trend_out,
         "recall_at_10": rec,
         "train": {"kmeanspp_s": t_kpp, "kmeanspp_rows": int(sub if sub and sub < n else n),
                   "lloyd_s": t_lloyd, "inertia_first": inertia[0], "inertia_last": inertia[-1]},

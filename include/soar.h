@@ -55,7 +55,10 @@ typedef enum soar_precision {
   SOAR_FP8_E4M3 = 2         /* OCP e4m3 with per-row power-of-two scales, FP32 re-score of top-k */
 } soar_precision;
 
-#define SOAR_ASYNC 1u       /* flags bit: enqueue only; errors surface on the next blocking call */
+/* flags bit: enqueue only.  Nothing is read back; a non-finite input found by such a call is
+   kept in its workspace, and the next blocking soar_assign on the same workspace returns
+   SOAR_E_NONFINITE (and clears it).  Stats are not filled. */
+#define SOAR_ASYNC 1u
 /* Form of the spill sweep (results are the same up to the low-precision candidate ranking; only
    the work differs).  The grouped form sorts the rows by primary and takes <c_pi, c_j> from the
    same MFMA stream as the rows (x, or with lambda >= 1/64 the residual r); the direct
@@ -79,14 +82,17 @@ typedef struct soar_assign_opts {
 /* Optional statistics of one blocking call (host struct).  Set struct_size. */
 typedef struct soar_stats {
   uint32_t struct_size;
-  float device_ms;          /* device time from the first to the last kernel of the call         */
-  float assign_kernel_ms;   /* device time of the assignment kernels alone (HIP events): both
-                               sweeps and, in the grouped form, the grouping (not quantization,
-                               re-scores or the exact full scan)                                 */
+  float device_ms;          /* device time of the whole call (HIP events on the stream)          */
+  float assign_kernel_ms;   /* the sweeps and the grouping by primary: phase_ms[1] + [3] + [4]   */
   int64_t rows_full_scan;   /* rows whose candidate set could not be proven complete and were
                                re-done by an exact scan over all K                               */
   int64_t rows_fp64;        /* rows whose decision was taken in FP64 (near-ties)                 */
-  double mfma_flops;        /* MFMA flops executed                                               */
+  double mfma_flops;        /* algorithmic work 4 n K d: X C^T and R C^T, each once              */
+  float phase_ms[6];        /* [0] codebook and row preparation (norms, packing, quantization),
+                               [1] primary sweep, [2] primary re-score (BF16/FP8), [3] grouping
+                               of the rows by primary, [4] spill sweep, [5] spill re-score
+                               (BF16/FP8) or exact full scan (FP32).  An FP32 direct-form call
+                               runs both sweeps in one pass, reported under [1].                */
 } soar_stats;
 
 /* Bytes of device workspace soar_assign needs for these sizes and options. */

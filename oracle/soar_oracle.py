@@ -359,8 +359,18 @@ def kmr_curve(Q, X, C, assignments, k, ts, gt=None):
 # Acceptance rule for a GPU result
 # ----------------------------------------------------------------------------------------------
 
+def reference(X, C, lam, fast=True):
+    """The oracle's answer for every row: primary and its distance, and the spill and its loss
+    given that primary.  ``verify`` can reuse it for several GPU results on the same rows."""
+    prim = primary_fast if fast else primary_plain
+    spl = spill_fast if fast else spill_plain
+    p_star, d_star = prim(X, C)
+    s_star, l_star = spl(X, C, lam, primary=p_star)
+    return dict(p_star=p_star, d_star=d_star, s_given_p_star=s_star, l_given_p_star=l_star)
+
+
 def verify(X, C, lam, gpu_primary, gpu_spill, gpu_pdist=None, gpu_sloss=None, fast=True,
-          band=1e-6, loss_tol=1e-5):
+          band=1e-6, loss_tol=1e-5, ref=None):
     """Check a GPU assignment against the oracle.
 
     * primary: accepted if equal to the oracle's, or its exact distance is within ``band``
@@ -368,6 +378,8 @@ def verify(X, C, lam, gpu_primary, gpu_spill, gpu_pdist=None, gpu_sloss=None, fa
     * spill: checked with the oracle conditioned on the GPU primary; accepted if equal, or not the
       primary and its exact loss within ``band`` (relative) of the best;
     * reported distance / loss: within ``loss_tol`` (relative) of the exact value at the GPU's index.
+    ``ref`` (from ``reference`` on the same rows, C and lambda) saves recomputing the oracle: the
+    spill is then recomputed only for rows whose GPU primary differs from the oracle's.
     Returns a dict of per-row boolean arrays and regret statistics."""
     X, C = _f64(X), _f64(C)
     n = X.shape[0]
@@ -379,11 +391,21 @@ def verify(X, C, lam, gpu_primary, gpu_spill, gpu_pdist=None, gpu_sloss=None, fa
     gs_c = np.clip(gs, 0, K - 1)
     prim = primary_fast if fast else primary_plain
     spl = spill_fast if fast else spill_plain
-    p_star, d_star = prim(X, C)
+    if ref is None:
+        p_star, d_star = prim(X, C)
+    else:
+        p_star, d_star = ref["p_star"], ref["d_star"]
     d_gpu = _sqdist(X - C[gp_c])
     dscale = np.maximum(d_star, 1e-12)
     prim_ok = valid & ((gp == p_star) | (d_gpu - d_star <= band * dscale))
-    s_star, l_star = spl(X, C, lam, primary=gp_c)
+    if ref is None:
+        s_star, l_star = spl(X, C, lam, primary=gp_c)
+    else:
+        s_star = ref["s_given_p_star"].copy()
+        l_star = ref["l_given_p_star"].copy()
+        diff = np.flatnonzero(gp_c != p_star)
+        if diff.size:
+            s_star[diff], l_star[diff] = spl(X[diff], C, lam, primary=gp_c[diff])
     R = X - C[gp_c]
     rr = _sqdist(R)
     l_gpu = _soar_loss(X - C[gs_c], R, rr, float(lam))

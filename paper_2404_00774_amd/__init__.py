@@ -46,10 +46,15 @@ class AssignOpts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("device_ms", ctypes.c_float),
                 ("assign_kernel_ms", ctypes.c_float), ("rows_full_scan", ctypes.c_int64), ("rows_fp64", ctypes.c_int64),
-                ("mfma_flops", ctypes.c_double)]
+                ("mfma_flops", ctypes.c_double), ("phase_ms", ctypes.c_float * 6)]
+
+    PHASES = ("prep", "primary_sweep", "primary_rescore", "grouping", "spill_sweep",
+              "spill_rescore")
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("struct_size", "phase_ms")}
+        d["phase_ms"] = dict(zip(self.PHASES, [float(v) for v in self.phase_ms]))
+        return d
 
 
 _vp, _i64, _i32, _u64, _f32, _f64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,

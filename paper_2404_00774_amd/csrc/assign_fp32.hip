@@ -906,6 +906,21 @@ __global__ void reset_counters_kernel(unsigned* counters, int words) {
   if ((int)threadIdx.x < words) counters[threadIdx.x] = 0u;
 }
 
+// Status record of an enqueue-only call: its non-finite flag is kept in words the per-call reset
+// leaves alone, behind two magic words, so that garbage in a fresh workspace never reads as a
+// status.  The next blocking call reads the record and clears it.
+__global__ void async_note_kernel(unsigned* counters) {
+  if (threadIdx.x != 0 || counters[CNT_NONFINITE] == 0u) return;
+  if (counters[CNT_ASYNC_M0] != kAsyncMagic0 || counters[CNT_ASYNC_M1] != kAsyncMagic1)
+    counters[CNT_ASYNC_FLAGS] = 0u;
+  counters[CNT_ASYNC_M0] = kAsyncMagic0;
+  counters[CNT_ASYNC_M1] = kAsyncMagic1;
+  counters[CNT_ASYNC_FLAGS] |= 1u;
+}
+__global__ void async_clear_kernel(unsigned* counters) {
+  if (threadIdx.x < 3) counters[CNT_ASYNC_M0 + threadIdx.x] = 0u;
+}
+
 __global__ __launch_bounds__(256) void prep_codebook_kernel(const float* __restrict__ C, int K,
                                                             int d, float* __restrict__ cnorm,
                                                             unsigned* counters) {
@@ -1097,6 +1112,16 @@ hipError_t launch_prep_codebook(const float* C, int K, int d, float* cnorm, unsi
   return hipGetLastError();
 }
 
+hipError_t launch_async_note(unsigned* counters, hipStream_t st) {
+  hipLaunchKernelGGL(async_note_kernel, dim3(1), dim3(64), 0, st, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_async_clear(unsigned* counters, hipStream_t st) {
+  hipLaunchKernelGGL(async_clear_kernel, dim3(1), dim3(64), 0, st, counters);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset_step_counters(unsigned* counters, hipStream_t st) {
   hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, st, counters,
                      (int)CNT_STEP_WORDS);
@@ -1113,19 +1138,22 @@ static hipError_t launch_grouped_dp(const AssignParams& P, bool vec, hipStream_t
 }
 
 hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipStream_t st,
-                              hipEvent_t ev_begin, hipEvent_t ev_end, const GroupLayout* grouped) {
+                              hipEvent_t* ev, const GroupLayout* grouped) {
   hipError_t e;
   const int dp = fp32_padded_dim(P.d);
   if (dp < 0 || !P.Crec) return hipErrorInvalidValue;
-  if (ev_begin) (void)hipEventRecord(ev_begin, st);
+  auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], st); };
   if (spill && grouped && dp <= 256) {
     // primary pass, rows grouped by primary, grouped spill pass
 #define SOAR_X(DP, BN, CH) e = launch_dp<DP, BN, CH>(P, false, vec, st)
     switch (dp) { SOAR_F32_SHAPES(SOAR_X) }
 #undef SOAR_X
     if (e != hipSuccess) return e;
+    mark(0);
+    mark(1);
     e = launch_group_by_primary(P.primary, P.n, P.live_n, P.K, *grouped, st);
     if (e != hipSuccess) return e;
+    mark(2);
     AssignParams Q = P;
     Q.perm = grouped->perm;
     Q.stripes = grouped->stripes;
@@ -1141,9 +1169,13 @@ hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipSt
 #define SOAR_X(DP, BN, CH) e = launch_dp<DP, BN, CH>(P, spill, vec, st)
     switch (dp) { SOAR_F32_SHAPES(SOAR_X) }
 #undef SOAR_X
+    // one pass holds both sweeps: its time is the primary phase, the spill phases stay empty
+    mark(0);
+    mark(1);
+    mark(2);
   }
   if (e != hipSuccess) return e;
-  if (ev_end) (void)hipEventRecord(ev_end, st);
+  mark(3);
   const size_t smem = ((size_t)3 * P.d + (P.K <= FS_LDS_K ? (size_t)P.K : 0)) * sizeof(float);
   if (spill)
     hipLaunchKernelGGL(full_scan_kernel<true>, dim3(256), dim3(FS_THREADS), smem, st, P);

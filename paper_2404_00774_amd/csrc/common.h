@@ -16,8 +16,14 @@ enum Counter : int {
   CNT_NONFINITE = 1,  // set when a NaN/Inf was read from X or C
   CNT_FP64 = 2,       // rows whose decision was taken in FP64
   CNT_CMAX2 = 3,      // max_j ||c_j||^2 as float bits (non-negative floats order like uints)
-  CNT_WORDS = 8
+  CNT_WORDS = 8,      // words of one call's counters (cleared by every call)
+  // status record of enqueue-only calls, kept across calls (see async_note_kernel)
+  CNT_ASYNC_M0 = 8,
+  CNT_ASYNC_M1 = 9,
+  CNT_ASYNC_FLAGS = 10,
+  CNT_ALLOC_WORDS = 16
 };
+constexpr unsigned kAsyncMagic0 = 0x534f4152u, kAsyncMagic1 = 0x41535943u;
 // Counters cleared at the start of every assignment (the codebook's CNT_CMAX2 is kept).
 constexpr int CNT_STEP_WORDS = 3;
 

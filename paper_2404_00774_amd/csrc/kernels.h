@@ -61,12 +61,17 @@ hipError_t launch_prep_codebook(const float* C, int K, int d, float* cnorm, unsi
                                 hipStream_t st);
 // Clears the per-assignment counters only (the codebook's maximum norm is kept).
 hipError_t launch_reset_step_counters(unsigned* counters, hipStream_t st);
-// ev_begin / ev_end (nullable) are recorded around the assignment kernels (without the exact
-// full scan).  With `grouped` (rows of up to 256 dimensions only) the spill runs in its grouped
-// form: primary pass, grouping of the rows by primary into G, grouped spill pass.
+// Enqueue-only calls keep their non-finite flag in the counters' status record; a blocking call
+// reads and clears it.
+hipError_t launch_async_note(unsigned* counters, hipStream_t st);
+hipError_t launch_async_clear(unsigned* counters, hipStream_t st);
+// ev (nullable, 4 events) is recorded after the primary pass [0], after the primary phase's
+// tail [1] (same point here), after the grouping [2] and after the spill pass [3], before the
+// exact full scan; a single fused pass records all four after itself.  With `grouped` (rows of
+// up to 256 dimensions only) the spill runs in its grouped form: primary pass, grouping of the
+// rows by primary into G, grouped spill pass.
 hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipStream_t st,
-                              hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr,
-                              const GroupLayout* grouped = nullptr);
+                              hipEvent_t* ev = nullptr, const GroupLayout* grouped = nullptr);
 
 // ---- grouping rows by primary (grouped form of the spill sweep) ----
 constexpr int GROUP_ROWS = 15;   // data rows per 16-row MFMA stripe; the 16th row is the centroid

@@ -87,7 +87,7 @@ LowpLayout layout_lowp(void* ws, int64_t n, int32_t d, int32_t K, int fmt, int t
   const size_t eb = fmt == soar::LOWP_BF16 ? 2 : 1;
   Carver c(ws);
   LowpLayout L;
-  L.counters = c.take<unsigned>(soar::CNT_WORDS);
+  L.counters = c.take<unsigned>(soar::CNT_ALLOC_WORDS);
   L.cnorm = c.take<float>((size_t)K);
   L.Xq = c.take<char>((size_t)n * dp * eb);
   L.Cq = c.take<char>(soar::lowp_codebook_bytes(fmt, d, K));
@@ -123,7 +123,7 @@ struct AssignLayout {
 AssignLayout layout_assign(void* ws, int64_t n, int32_t d, int32_t K) {
   Carver c(ws);
   AssignLayout L;
-  L.counters = c.take<unsigned>(soar::CNT_WORDS);
+  L.counters = c.take<unsigned>(soar::CNT_ALLOC_WORDS);
   L.cnorm = c.take<float>((size_t)K);
   L.crec = c.take<char>(soar::fp32_codebook_bytes(d, K));
   L.gram = soar::fp32_uses_gram(d, K) ? c.take<float>((size_t)K * K) : nullptr;
@@ -168,8 +168,7 @@ float tie_threshold(int d, float lam, float near_tie_rel) {
 soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
                             float lam, float near_tie_rel, bool spill, int32_t* primary,
                             int32_t* spill_out, float* pdist, float* sloss, void* ws,
-                            hipStream_t st, unsigned* counters_out_host,
-                            hipEvent_t ev_kernel_begin, hipEvent_t ev_kernel_end,
+                            hipStream_t st, unsigned* counters_out_host, hipEvent_t* ev,
                             uint32_t spill_form) {
   AssignLayout L = layout_assign(ws, n, d, K);
   AssignParams P;
@@ -192,12 +191,14 @@ soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C
   }
   const GroupLayout GL = group_layout(L.group, n, K);
   const bool vec = (d % 4 == 0) && aligned(X, 16) && aligned(C, 16);
+  if (ev) (void)hipEventRecord(ev[0], st);
   hipError_t e = launch_prep_codebook(C, K, d, L.cnorm, L.counters, st);
   if (e == hipSuccess) e = launch_pack_fp32(C, K, d, L.cnorm, L.crec, st);
   if (e == hipSuccess && gram) e = launch_gram(C, K, d, L.gram, st);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
   if (e == hipSuccess)
-    e = launch_assign_fp32(P, spill, vec, st, ev_kernel_begin, ev_kernel_end,
-                           grouped ? &GL : nullptr);
+    e = launch_assign_fp32(P, spill, vec, st, ev ? ev + 2 : nullptr, grouped ? &GL : nullptr);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[6], st);
   if (e != hipSuccess) return SOAR_E_DEVICE;
   if (counters_out_host) {
     e = hipMemcpyAsync(counters_out_host, L.counters, CNT_WORDS * sizeof(unsigned),
@@ -212,7 +213,6 @@ size_t assign_workspace_bytes(int64_t n, int32_t d, int32_t K) {
 }
 
 // BF16 / FP8 pipeline: quantize, primary sweep + re-score, spill sweep + re-score.
-// ev (nullable, 4 events) brackets the primary sweep [0, 1] and the spill sweep [2, 3].
 soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
                             float lam, float near_tie_rel, int fmt, int topk, int32_t* primary,
                             int32_t* spill_out, float* pdist, float* sloss, void* ws,
@@ -244,32 +244,129 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
     P.perm = GL.perm; P.stripes = GL.stripes; P.nstripes = GL.meta;
     P.Cp = L.Cp; P.cps = L.cps;
   }
-  hipError_t e = launch_prep_codebook(C, K, d, L.cnorm, L.counters, st);
+  auto mark = [&](int k) { return ev ? hipEventRecord(ev[k], st) : hipSuccess; };
+  hipError_t e = mark(0);
+  if (e == hipSuccess) e = launch_prep_codebook(C, K, d, L.cnorm, L.counters, st);
   if (e == hipSuccess)
     e = launch_lowp_pack_codebook(fmt, C, K, d, L.cnorm, L.Cq, L.counters, st);
   if (e == hipSuccess && grouped)
     e = launch_lowp_quantize(fmt, C, K, d, P.dp, false, L.Cp, L.cps, L.counters, st);
   if (e == hipSuccess)
     e = launch_lowp_quantize(fmt, X, n, d, P.dp, false, L.Xq, L.xs, L.counters, st);
-  if (e == hipSuccess && ev) e = hipEventRecord(ev[0], st);
+  if (e == hipSuccess) e = mark(1);
   if (e == hipSuccess) e = launch_lowp_sweep(fmt, P, false, st);
-  if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
+  if (e == hipSuccess) e = mark(2);
   if (e == hipSuccess) e = launch_lowp_rescore(fmt, P, false, st);
-  if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
+  if (e == hipSuccess) e = mark(3);
   if (grouped) {
     if (e == hipSuccess) e = launch_group_by_primary(primary, n, nullptr, K, GL, st);
+    if (e == hipSuccess) e = mark(4);
     if (e == hipSuccess) e = launch_lowp_sweep_grouped(fmt, P, st);
   } else {
+    if (e == hipSuccess) e = mark(4);
     if (e == hipSuccess) e = launch_lowp_sweep(fmt, P, true, st);
   }
-  if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
+  if (e == hipSuccess) e = mark(5);
   if (e == hipSuccess) e = launch_lowp_rescore(fmt, P, true, st);
+  if (e == hipSuccess) e = mark(6);
   if (e != hipSuccess) return SOAR_E_DEVICE;
   if (counters_out_host &&
       hipMemcpyAsync(counters_out_host, L.counters, CNT_WORDS * sizeof(unsigned),
                      hipMemcpyDeviceToHost, st) != hipSuccess)
     return SOAR_E_DEVICE;
   return SOAR_OK;
+}
+
+}  // namespace soar
+
+namespace {
+
+// One assignment on a validated, large enough workspace.  A blocking call reads the counters
+// (and the status record an enqueue-only call left in the same workspace) and clears the record.
+soar_status assign_impl(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
+                        const OptsView& o, int32_t* primary, int32_t* spill, float* primary_dist,
+                        float* spill_loss, void* workspace, hipStream_t st, soar_stats* stats) {
+  const bool async = (o.flags & SOAR_ASYNC) != 0;
+  const bool lowp = o.precision != SOAR_FP32;
+  // the counters lead both workspace layouts
+  unsigned* counters = static_cast<unsigned*>(workspace);
+  hipEvent_t ev[soar::kPhaseEvents] = {};
+  auto destroy = [&]() {
+    for (hipEvent_t& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  };
+  if (!async && stats) {
+    for (hipEvent_t& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) { destroy(); return SOAR_E_DEVICE; }
+  }
+  unsigned cnt[soar::CNT_WORDS] = {0};
+  const uint32_t form = o.flags & (SOAR_SPILL_GROUPED | SOAR_SPILL_DIRECT);
+  soar_status s;
+  if (!lowp)
+    s = soar::run_assign_fp32(X, n, d, C, K, o.lambda, o.near_tie_rel, true, primary, spill,
+                              primary_dist, spill_loss, workspace, st, async ? nullptr : cnt,
+                              ev[0] ? ev : nullptr, form);
+  else
+    s = soar::run_assign_lowp(X, n, d, C, K, o.lambda, o.near_tie_rel, lowp_fmt(o),
+                              lowp_topk(o, d), primary, spill, primary_dist, spill_loss, workspace,
+                              st, async ? nullptr : cnt, ev[0] ? ev : nullptr, form);
+  if (s != SOAR_OK) { destroy(); return s; }
+  if (async) {
+    destroy();
+    return dev_err(soar::launch_async_note(counters, st));
+  }
+  unsigned rec[3] = {0u, 0u, 0u};
+  hipError_t e = hipMemcpyAsync(rec, counters + soar::CNT_ASYNC_M0, sizeof(rec),
+                                hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = soar::launch_async_clear(counters, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  s = dev_err(e);
+  if (s == SOAR_OK && stats) {
+    float ph[soar::kPhaseEvents - 1] = {};
+    for (int k = 0; k + 1 < soar::kPhaseEvents; ++k)
+      (void)hipEventElapsedTime(&ph[k], ev[k], ev[k + 1]);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[soar::kPhaseEvents - 1]);
+    stats->device_ms = ms;
+    // the sweeps and the grouping by primary
+    stats->assign_kernel_ms = ph[1] + ph[3] + ph[4];
+    stats->rows_full_scan = cnt[soar::CNT_FULLSCAN];
+    stats->rows_fp64 = cnt[soar::CNT_FP64];
+    stats->mfma_flops = 4.0 * (double)n * (double)K * (double)d;
+    for (int k = 0; k < 6; ++k) stats->phase_ms[k] = ph[k];
+  }
+  destroy();
+  const bool async_bad = rec[0] == soar::kAsyncMagic0 && rec[1] == soar::kAsyncMagic1 && rec[2];
+  if (s == SOAR_OK && (cnt[soar::CNT_NONFINITE] || async_bad)) s = SOAR_E_NONFINITE;
+  return s;
+}
+
+}  // namespace
+
+namespace soar {
+
+soar_status assign_validate(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
+                            const soar_assign_opts* opts, const int32_t* primary,
+                            const int32_t* spill, size_t* need) {
+  OptsView o;
+  if (!read_opts(opts, &o)) return SOAR_E_INVAL;
+  soar_status s = validate_assign(n, d, K, o);
+  if (s != SOAR_OK) return s;
+  if (!X || !C || !primary || !spill) return SOAR_E_INVAL;
+  if (!aligned(X, 4) || !aligned(C, 4)) return SOAR_E_INVAL;
+  *need = o.precision == SOAR_FP32 ? assign_workspace_bytes(n, d, K)
+                                   : layout_lowp(nullptr, n, d, K, lowp_fmt(o), lowp_topk(o, d)).bytes;
+  return SOAR_OK;
+}
+
+soar_status assign_run(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
+                       const soar_assign_opts* opts, int32_t* primary, int32_t* spill,
+                       float* primary_dist, float* spill_loss, void* workspace, hipStream_t st,
+                       soar_stats* stats) {
+  OptsView o;
+  if (!read_opts(opts, &o)) return SOAR_E_INVAL;
+  return assign_impl(X, n, d, C, K, o, primary, spill, primary_dist, spill_loss, workspace, st,
+                     stats);
 }
 
 }  // namespace soar
@@ -306,65 +403,13 @@ soar_status soar_assign(const float* X, int64_t n, int32_t d, const float* C, in
                         const soar_assign_opts* opts, int32_t* primary, int32_t* spill,
                         float* primary_dist, float* spill_loss, void* workspace, size_t ws_bytes,
                         void* stream, soar_stats* stats) {
-  OptsView o;
-  if (!read_opts(opts, &o)) return SOAR_E_INVAL;
-  soar_status s = validate_assign(n, d, K, o);
-  if (s != SOAR_OK) return s;
-  if (!X || !C || !primary || !spill || !workspace) return SOAR_E_INVAL;
-  if (!aligned(X, 4) || !aligned(C, 4) || !aligned(workspace, kAlign)) return SOAR_E_INVAL;
   size_t need = 0;
-  if (soar_assign_workspace_size(n, d, K, opts, &need) != SOAR_OK || ws_bytes < need)
-    return SOAR_E_INVAL;
+  const soar_status s = soar::assign_validate(X, n, d, C, K, opts, primary, spill, &need);
+  if (s != SOAR_OK) return s;
+  if (!workspace || !aligned(workspace, kAlign) || ws_bytes < need) return SOAR_E_INVAL;
   if (stats && stats->struct_size < sizeof(soar_stats)) return SOAR_E_INVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const bool async = (o.flags & SOAR_ASYNC) != 0;
-
-  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  auto destroy = [&]() {
-    for (hipEvent_t& e : ev)
-      if (e) (void)hipEventDestroy(e);
-  };
-  if (!async && stats) {
-    for (hipEvent_t& e : ev)
-      if (hipEventCreate(&e) != hipSuccess) { destroy(); return SOAR_E_DEVICE; }
-    (void)hipEventRecord(ev[0], st);
-  }
-  unsigned cnt[soar::CNT_WORDS] = {0};
-  const bool lowp = o.precision != SOAR_FP32;
-  if (!lowp)
-    s = soar::run_assign_fp32(X, n, d, C, K, o.lambda, o.near_tie_rel, true, primary, spill,
-                              primary_dist, spill_loss, workspace, st, async ? nullptr : cnt,
-                              ev[1], ev[2], o.flags & (SOAR_SPILL_GROUPED | SOAR_SPILL_DIRECT));
-  else
-    s = soar::run_assign_lowp(X, n, d, C, K, o.lambda, o.near_tie_rel, lowp_fmt(o), lowp_topk(o, d),
-                              primary, spill, primary_dist, spill_loss, workspace, st,
-                              async ? nullptr : cnt, ev[0] ? ev + 1 : nullptr,
-                              o.flags & (SOAR_SPILL_GROUPED | SOAR_SPILL_DIRECT));
-  if (s != SOAR_OK || async) {
-    destroy();
-    return s;
-  }
-  if (stats) (void)hipEventRecord(ev[5], st);
-  s = dev_err(hipStreamSynchronize(st));
-  if (s == SOAR_OK && stats) {
-    float ms = 0.f, kms = 0.f, k2 = 0.f;
-    (void)hipEventElapsedTime(&ms, ev[0], ev[5]);
-    (void)hipEventElapsedTime(&kms, ev[1], ev[2]);
-    if (lowp) {   // the two sweeps: [1, 2] primary, [3, 4] spill
-      (void)hipEventElapsedTime(&k2, ev[3], ev[4]);
-      kms += k2;
-    }
-    stats->device_ms = ms;
-    stats->assign_kernel_ms = kms;
-    stats->rows_full_scan = cnt[soar::CNT_FULLSCAN];
-    stats->rows_fp64 = cnt[soar::CNT_FP64];
-    stats->mfma_flops =
-        6.0 * (double)n * (double)K *
-        (double)(lowp ? soar::lowp_padded_dim(lowp_fmt(o), d) : soar::fp32_padded_dim(d));
-  }
-  destroy();
-  if (s == SOAR_OK && cnt[soar::CNT_NONFINITE]) s = SOAR_E_NONFINITE;
-  return s;
+  return soar::assign_run(X, n, d, C, K, opts, primary, spill, primary_dist, spill_loss,
+                          workspace, static_cast<hipStream_t>(stream), stats);
 }
 
 }  // extern "C"

@@ -111,11 +111,13 @@ WORKLOADS = {
     "mix64_n20k_d64": dict(spec=MixtureSpec(20_000, 64, 64, 0.3, "unit", 0), K=256, iters=10,
                            lambdas=(1.0,)),
     "mix4096_n1m_d128": dict(spec=MixtureSpec(1_000_000, 128, 4096, LOGU, "unit", 0), K=2000,
-                             iters=15, lambdas=(0.0, 0.5, 1.0, 1.5), queries=10_000),
+                             iters=15, lambdas=(0.0, 0.5, 1.0, 1.5), queries=10_000,
+                             check_rows=20_000, cpu_rows=100_000),
     "mix16384_n10m_d96": dict(spec=MixtureSpec(10_000_000, 96, 16384, LOGU, "unit", 0), K=40_000,
-                              iters=10, lambdas=(1.0,), seed_subsample=1_000_000),
+                              iters=10, lambdas=(1.0,), seed_subsample=1_000_000,
+                              check_rows=100_000, cpu_rows=10_000),
     "mix8192_n2m_d768_lognorm": dict(spec=MixtureSpec(2_000_000, 768, 8192, LOGU,
                                                       ("lognormal", 0.5), 0),
                                      K=10_000, iters=10, lambdas=(0.5, 1.0, 1.5),
-                                     seed_subsample=500_000),
+                                     seed_subsample=500_000, check_rows=20_000, cpu_rows=5_000),
 }

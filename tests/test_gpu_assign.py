@@ -234,3 +234,47 @@ def test_validation_and_errors():
     assert st == -1
     torch.cuda.synchronize()
     assert (p == -7).all() and (s == -7).all()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_async_status_reaches_next_blocking_call(prec):
+    """An enqueue-only call on non-finite input leaves its status in the workspace: the next
+    blocking call on that workspace (with finite input) returns SOAR_E_NONFINITE, and the one after
+    it returns ok.  A blocking call on another workspace is not affected."""
+    soar = _soar()
+    import torch
+    rng = np.random.default_rng(11)
+    Xf = rng.standard_normal((300, 24)).astype(np.float32)
+    C = _t(rng.standard_normal((20, 24)).astype(np.float32))
+    Xn = Xf.copy()
+    Xn[17, 5] = np.nan
+    n, d, K = 300, 24, 20
+    ws = torch.empty(soar.assign_workspace_size(n, d, K, 1.0, prec), dtype=torch.uint8,
+                     device="cuda")
+    other = torch.empty_like(ws)
+    soar.assign(_t(Xn), C, 1.0, prec, workspace=ws, flags=soar.ASYNC)
+    torch.cuda.synchronize()
+    soar.assign(_t(Xf), C, 1.0, prec, workspace=other)          # a different workspace: ok
+    with pytest.raises(soar.SoarError) as e:
+        soar.assign(_t(Xf), C, 1.0, prec, workspace=ws)
+    assert e.value.status == -5
+    soar.assign(_t(Xf), C, 1.0, prec, workspace=ws)             # the record was cleared
+    # an enqueue-only call on finite input leaves no record
+    soar.assign(_t(Xf), C, 1.0, prec, workspace=ws, flags=soar.ASYNC)
+    soar.assign(_t(Xf), C, 1.0, prec, workspace=ws)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_phase_times_cover_the_call(prec):
+    """The per-phase device times of a blocking call add up to the call's device time."""
+    X = gen_mixture(MixtureSpec(60_000, 64, 128, 0.3, "unit", 9))
+    C = X[::300].copy()
+    soar = _soar()
+    *_, st = soar.assign(_t(X), _t(C), 1.0, prec, stats=True)
+    ph = st["phase_ms"]
+    print(prec, st, flush=True)
+    assert all(v >= 0.0 for v in ph.values())
+    assert abs(sum(ph.values()) - st["device_ms"]) <= 0.02 * st["device_ms"] + 0.05
+    assert abs(st["assign_kernel_ms"] - (ph["primary_sweep"] + ph["grouping"] +
+                                         ph["spill_sweep"])) <= 1e-3 + 1e-3 * st["device_ms"]
+    assert st["mfma_flops"] == 4.0 * len(X) * len(C) * X.shape[1]

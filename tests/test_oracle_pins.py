@@ -441,3 +441,23 @@ def test_verify_accepts_oracle_and_rejects_wrong(rnd_case):
     bad[6] = (s[6] + 1) % C.shape[0] if (s[6] + 1) % C.shape[0] != p[6] else (s[6] + 2) % C.shape[0]
     j = O.verify(X, C, 1.0, p, bad, dp, ls)
     assert not j["spill_ok"][5] and not j["spill_ok"][6] and j["spill_ok"].sum() == len(X) - 2
+
+
+def test_verify_with_reference_equals_plain_verify():
+    """verify() with a precomputed reference gives the same judgement as without it, also for
+    rows whose (perturbed) primary differs from the oracle's."""
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((400, 12)).astype(np.float32)
+    C = rng.standard_normal((30, 12)).astype(np.float32)
+    lam = 1.0
+    ref = O.reference(X, C, lam)
+    p = ref["p_star"].copy()
+    s = ref["s_given_p_star"].copy()
+    p[::7] = (p[::7] + 1) % len(C)          # wrong primaries on some rows
+    s[::11] = (s[::11] + 3) % len(C)        # wrong spills on others
+    s[s == p] = (s[s == p] + 1) % len(C)
+    a = O.verify(X, C, lam, p, s)
+    b = O.verify(X, C, lam, p, s, ref=ref)
+    for k in ("primary_ok", "spill_ok", "primary_regret", "spill_regret", "s_star", "l_star"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["all_ok"] == b["all_ok"] and not a["all_ok"]
