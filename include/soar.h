@@ -117,6 +117,26 @@ soar_status soar_assign(const float* X, int64_t n, int32_t d, const float* C, in
                         float* primary_dist, float* spill_loss, void* workspace, size_t ws_bytes,
                         void* stream, soar_stats* stats);
 
+/*
+ * soar_assign without a workspace, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments, options,
+ * results and errors as soar_assign, minus workspace and stats; it allocates nothing.  Its
+ * workspace is a fixed device array of soar_assign_noalloc_limit() bytes (64 MiB) that each GPU
+ * holds from the library's load until the process ends.
+ *  - A call whose soar_assign_workspace_size exceeds that limit returns SOAR_E_NOMEM before any
+ *    launch (for BF16 at d=96 and K=40,000 that is about 100,000 rows).
+ *  - Every call on one GPU shares that GPU's array and leaves its contents behind (each call
+ *    initializes what it reads).  Calls that overlap on one GPU (two streams, two host threads,
+ *    an enqueue-only call still running) race on it: the caller must order them.
+ *  - SOAR_ASYNC works as for soar_assign; the status record then lives in the shared array.
+ */
+soar_status soar_assign_noalloc(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
+                                const soar_assign_opts* opts, int32_t* primary, int32_t* spill,
+                                float* primary_dist, float* spill_loss, void* stream);
+
+/* Bytes of the fixed device workspace of soar_assign_noalloc. */
+size_t soar_assign_noalloc_limit(void);
+
 /* Bytes of workspace for soar_kmeanspp / soar_lloyd_update / soar_train_codebook. */
 soar_status soar_train_workspace_size(int64_t n, int32_t d, int32_t K, size_t* bytes);
 

@@ -75,6 +75,9 @@ _sig("soar_assign_workspace_size", [_i64, _i32, _i32, ctypes.POINTER(AssignOpts)
                                     ctypes.POINTER(_sz)])
 _sig("soar_assign", [_vp, _i64, _i32, _vp, _i32, ctypes.POINTER(AssignOpts), _vp, _vp, _vp, _vp,
                      _vp, _sz, _vp, ctypes.POINTER(Stats)])
+_sig("soar_assign_noalloc", [_vp, _i64, _i32, _vp, _i32, ctypes.POINTER(AssignOpts), _vp, _vp, _vp,
+                             _vp, _vp])
+_sig("soar_assign_noalloc_limit", [], _sz)
 _sig("soar_train_workspace_size", [_i64, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("soar_kmeanspp", [_vp, _i64, _i32, _i32, _u64, _vp, _vp, _vp, _sz, _vp])
 _sig("soar_lloyd_update", [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp])
@@ -86,7 +89,8 @@ _sig("soar_wait", [_vp, _u64, _vp, _vp, _f64])
 _sig("soar_index_list", [_vp, _i32, _vp, _i64, ctypes.POINTER(_i64)])
 _sig("soar_index_destroy", [_vp], None)
 
-EXPORTED = [n for n in ("soar_assign_workspace_size", "soar_assign", "soar_train_workspace_size",
+EXPORTED = [n for n in ("soar_assign_workspace_size", "soar_assign", "soar_assign_noalloc",
+                        "soar_assign_noalloc_limit", "soar_train_workspace_size",
                         "soar_kmeanspp", "soar_lloyd_update", "soar_train_codebook",
                         "soar_index_arena_size", "soar_index_create", "soar_insert", "soar_wait",
                         "soar_index_list",
@@ -164,6 +168,33 @@ def assign(X, C, lam, precision="fp32", topk=0, near_tie_rel=0.0, stream=None, o
                               workspace.numel(), _stream(stream), ctypes.byref(st))
     _check(status, "soar_assign")
     return (*out, st.as_dict()) if stats else out
+
+
+def assign_noalloc(X, C, lam, precision="fp32", topk=0, near_tie_rel=0.0, stream=None, out=None,
+                   flags=0, spill_form="auto"):
+    """soar_assign_noalloc: the same assignment with the library's fixed device workspace
+    (nothing is allocated by the library; at most assign_noalloc_limit() bytes of workspace)."""
+    flags = int(flags) | _SPILL_FORM[spill_form]
+    X, C = _f32_matrix(X, "X"), _f32_matrix(C, "C")
+    n, d = X.shape
+    K = C.shape[0]
+    if C.shape[1] != d:
+        raise ValueError("X and C must have the same number of columns")
+    dev = X.device
+    if out is None:
+        out = (torch.empty(n, dtype=torch.int32, device=dev),
+               torch.empty(n, dtype=torch.int32, device=dev),
+               torch.empty(n, dtype=torch.float32, device=dev),
+               torch.empty(n, dtype=torch.float32, device=dev))
+    o = _opts(lam, precision, topk, near_tie_rel, flags)
+    _check(_lib.soar_assign_noalloc(_ptr(X), n, d, _ptr(C), K, ctypes.byref(o), _ptr(out[0]),
+                                    _ptr(out[1]), _ptr(out[2]), _ptr(out[3]), _stream(stream)),
+           "soar_assign_noalloc")
+    return out
+
+
+def assign_noalloc_limit():
+    return int(_lib.soar_assign_noalloc_limit())
 
 
 def train_workspace_size(n, d, K):

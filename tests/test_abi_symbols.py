@@ -11,7 +11,7 @@ LIB = os.path.join(ROOT, "paper_2404_00774_amd", "libsoar.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:soar_status|void|const char\*)\s+(soar_\w+)\s*\(",
+    return sorted(set(re.findall(r"^\s*(?:soar_status|void|size_t|const char\*)\s+(soar_\w+)\s*\(",
                                  text, flags=re.M)))
 
 
