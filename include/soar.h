@@ -137,6 +137,16 @@ soar_status soar_assign_noalloc(const float* X, int64_t n, int32_t d, const floa
 /* Bytes of the fixed device workspace of soar_assign_noalloc. */
 size_t soar_assign_noalloc_limit(void);
 
+/*
+ * Where a BF16/FP8 soar_assign leaves its re-scored candidates in its workspace (diagnostics):
+ * byte offsets from the workspace start of two row-major int32 [n x topk] arrays, the candidates
+ * of the primary and of the spill (-1: an empty place), for the same n, d, K and opts.  They hold
+ * the last such call's candidates until the workspace is reused.  FP32: SOAR_E_UNSUPPORTED (its
+ * candidate sets are proven complete instead, and rows that are not go to an exact full scan).
+ */
+soar_status soar_assign_candidates(int64_t n, int32_t d, int32_t K, const soar_assign_opts* opts,
+                                   size_t* primary_off, size_t* spill_off, int32_t* topk);
+
 /* Bytes of workspace for soar_kmeanspp / soar_lloyd_update / soar_train_codebook. */
 soar_status soar_train_workspace_size(int64_t n, int32_t d, int32_t K, size_t* bytes);
 
@@ -200,16 +210,20 @@ soar_status soar_index_create(const float* C, int32_t K, int32_t d, float lambda
 
 /*
  * Queue n vectors (HOST pointer X_host [n x d], copied before the call returns) with ids
- * first_id .. first_id + n - 1.  Non-blocking: returns a ticket for soar_wait.  Requests are
- * admitted as step slots and arena memory free up; a request that can never fit the arena gets
- * SOAR_E_NOMEM.
+ * first_id .. first_id + n - 1.  Non-blocking: returns a ticket for soar_wait.  Continuous
+ * batching: queued rows go into the next free step slot as soon as there is one, shared out
+ * max-min fairly between the queued requests (a small request behind a large one joins the next
+ * step), and steps in different slots overlap on the GPU.  A step is admitted when the list
+ * arena can take its worst-case growth; a request that can never fit gets SOAR_E_NOMEM.
  */
 soar_status soar_insert(soar_index* index, const float* X_host, int64_t n, int64_t first_id,
                         uint64_t* ticket);
 
 /* Wait for a ticket; writes its primary and spill indices to HOST arrays of n entries each.
-   timeout_s < 0 waits without limit; on SOAR_E_TIMEOUT the ticket stays valid.  A ticket is
-   consumed by the call that returns its result. */
+   It returns as soon as the last of the request's rows has been assigned; the ids then enter the
+   lists in step order (soar_index_list waits for every append in flight).  timeout_s < 0 waits
+   without limit; on SOAR_E_TIMEOUT the ticket stays valid.  A ticket is consumed by the call that
+   returns its result. */
 soar_status soar_wait(soar_index* index, uint64_t ticket, int32_t* primary_host,
                       int32_t* spill_host, double timeout_s);
 
@@ -217,6 +231,21 @@ soar_status soar_wait(soar_index* index, uint64_t ticket, int32_t* primary_host,
    The ids of a list are in no particular order.  Steps in flight finish first. */
 soar_status soar_index_list(soar_index* index, int32_t part, int64_t* ids_host, int64_t cap,
                             int64_t* len);
+
+/* Counters of an index (host struct; set struct_size). */
+typedef struct soar_index_stats {
+  uint32_t struct_size;
+  int64_t requests;             /* insert requests accepted                                     */
+  int64_t steps;                /* device steps launched                                        */
+  int64_t rows;                 /* rows assigned by those steps                                 */
+  int64_t max_steps_in_flight;  /* most steps on the device at once                             */
+  int64_t chunks_used;          /* list chunks in use (after the last finished append)          */
+  int64_t chunks_total;         /* list chunks the arena holds                                  */
+} soar_index_stats;
+soar_status soar_index_get_stats(soar_index* index, soar_index_stats* stats);
+
+/* Arena bytes one list chunk (64 ids and a link) takes. */
+size_t soar_index_chunk_bytes(void);
 
 /* Drain queued and in-flight work, then release the index's host objects (never the arena). */
 void soar_index_destroy(soar_index* index);

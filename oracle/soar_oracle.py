@@ -425,3 +425,60 @@ def verify(X, C, lam, gpu_primary, gpu_spill, gpu_pdist=None, gpu_sloss=None, fa
                          and out.get("pdist_ok", np.ones(n, bool)).all()
                          and out.get("sloss_ok", np.ones(n, bool)).all())
     return out
+
+
+# ----------------------------------------------------------------------------------------------
+# Query-side probing (Section 2.2 search with the spilled lists of Section 3.5)
+# ----------------------------------------------------------------------------------------------
+
+def probe_partitions(Q, C, t):
+    """Per query, the t partitions with the largest <q, c> (MIPS over the codebook), best first;
+    equal scores go to the lower partition index.  float64."""
+    Q, C = _f64(Q), _f64(C)
+    S = Q @ C.T
+    K = C.shape[0]
+    t = min(int(t), K)
+    out = np.empty((Q.shape[0], t), dtype=np.int64)
+    cols = np.arange(K)
+    for i in range(Q.shape[0]):
+        out[i] = np.lexsort((cols, -S[i]))[:t]
+    return out
+
+
+def partition_lists(assignments, K):
+    """The inverted lists: for every partition the ids assigned to it by any of the assignments,
+    ascending (a point spilled into a second partition is listed in both)."""
+    lists = []
+    for j in range(K):
+        ids = [np.flatnonzero(np.asarray(a) == j) for a in assignments]
+        lists.append(np.concatenate(ids) if ids else np.empty(0, np.int64))
+    return lists
+
+
+def search(Q, X, C, assignments, t, k):
+    """VQ search: probe the t best partitions of every query, take the union of their lists
+    (a point listed twice through its spilled copy counts once), score every candidate exactly
+    by <q, x> and return the k best, ties to the lowest id.
+
+    Returns (ids int64 [nq, k], -1 where fewer than k candidates; scores float64 [nq, k], -inf
+    there; searched int64 [nq]: the datapoints scored, i.e. the summed sizes of the probed
+    lists, spilled copies included)."""
+    Q, X, C = _f64(Q), _f64(X), _f64(C)
+    K = C.shape[0]
+    lists = partition_lists(assignments, K)
+    parts = probe_partitions(Q, C, t)
+    nq = Q.shape[0]
+    ids = np.full((nq, k), -1, dtype=np.int64)
+    scores = np.full((nq, k), -np.inf)
+    searched = np.zeros(nq, dtype=np.int64)
+    for i in range(nq):
+        members = [lists[p] for p in parts[i]]
+        searched[i] = sum(len(m) for m in members)
+        cand = np.unique(np.concatenate(members)) if members else np.empty(0, np.int64)
+        if cand.size == 0:
+            continue
+        s = X[cand] @ Q[i]
+        order = np.lexsort((cand, -s))[:k]
+        ids[i, :order.size] = cand[order]
+        scores[i, :order.size] = s[order]
+    return ids, scores, searched

@@ -78,6 +78,8 @@ _sig("soar_assign", [_vp, _i64, _i32, _vp, _i32, ctypes.POINTER(AssignOpts), _vp
 _sig("soar_assign_noalloc", [_vp, _i64, _i32, _vp, _i32, ctypes.POINTER(AssignOpts), _vp, _vp, _vp,
                              _vp, _vp])
 _sig("soar_assign_noalloc_limit", [], _sz)
+_sig("soar_assign_candidates", [_i64, _i32, _i32, ctypes.POINTER(AssignOpts), ctypes.POINTER(_sz),
+                                ctypes.POINTER(_sz), ctypes.POINTER(_i32)])
 _sig("soar_train_workspace_size", [_i64, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("soar_kmeanspp", [_vp, _i64, _i32, _i32, _u64, _vp, _vp, _vp, _sz, _vp])
 _sig("soar_lloyd_update", [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp])
@@ -89,11 +91,23 @@ _sig("soar_wait", [_vp, _u64, _vp, _vp, _f64])
 _sig("soar_index_list", [_vp, _i32, _vp, _i64, ctypes.POINTER(_i64)])
 _sig("soar_index_destroy", [_vp], None)
 
-EXPORTED = [n for n in ("soar_assign_workspace_size", "soar_assign", "soar_assign_noalloc",
+
+class IndexStats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("requests", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("rows", ctypes.c_int64),
+                ("max_steps_in_flight", ctypes.c_int64), ("chunks_used", ctypes.c_int64),
+                ("chunks_total", ctypes.c_int64)]
+
+
+_sig("soar_index_get_stats", [_vp, ctypes.POINTER(IndexStats)])
+_sig("soar_index_chunk_bytes", [], _sz)
+
+EXPORTED = [n for n in ("soar_assign_workspace_size", "soar_assign", "soar_assign_candidates",
+                        "soar_assign_noalloc",
                         "soar_assign_noalloc_limit", "soar_train_workspace_size",
                         "soar_kmeanspp", "soar_lloyd_update", "soar_train_codebook",
                         "soar_index_arena_size", "soar_index_create", "soar_insert", "soar_wait",
-                        "soar_index_list",
+                        "soar_index_list", "soar_index_get_stats", "soar_index_chunk_bytes",
                         "soar_index_destroy", "soar_status_string") if hasattr(_lib, n)]
 
 
@@ -168,6 +182,20 @@ def assign(X, C, lam, precision="fp32", topk=0, near_tie_rel=0.0, stream=None, o
                               workspace.numel(), _stream(stream), ctypes.byref(st))
     _check(status, "soar_assign")
     return (*out, st.as_dict()) if stats else out
+
+
+def assign_candidates(workspace, n, d, K, lam=1.0, precision="bf16", topk=0, near_tie_rel=0.0):
+    """The re-scored candidates the last BF16/FP8 assign() left in ``workspace`` (same sizes and
+    options): (primary int32[n, topk], spill int32[n, topk]) views of the workspace, -1 for an
+    empty place."""
+    o = _opts(lam, precision, topk, near_tie_rel, 0)
+    po, so, tk = _sz(), _sz(), _i32()
+    _check(_lib.soar_assign_candidates(n, d, K, ctypes.byref(o), ctypes.byref(po),
+                                       ctypes.byref(so), ctypes.byref(tk)),
+           "soar_assign_candidates")
+    nb = n * tk.value * 4
+    view = lambda off: workspace[off:off + nb].view(torch.int32).view(n, tk.value)  # noqa: E731
+    return view(po.value), view(so.value)
 
 
 def assign_noalloc(X, C, lam, precision="fp32", topk=0, near_tie_rel=0.0, stream=None, out=None,
@@ -301,6 +329,14 @@ class SoarIndex:
             self._n.pop(ticket, None)
         _check(st, "soar_wait")
         return p, s
+
+    CHUNK_BYTES = property(lambda self: int(_lib.soar_index_chunk_bytes()))
+
+    def stats(self):
+        st = IndexStats()
+        st.struct_size = ctypes.sizeof(IndexStats)
+        _check(_lib.soar_index_get_stats(self._h, ctypes.byref(st)), "soar_index_get_stats")
+        return {f: getattr(st, f) for f, _ in IndexStats._fields_ if f != "struct_size"}
 
     def list_len(self, part):
         ln = _i64()

@@ -16,12 +16,15 @@
 //   rescore   exact FP32 SOAR loss over the candidates, FP64 among near-ties -> pi', loss
 //
 // Candidates.  In the 16x16 MFMA result a lane sees one column of every 16-column block, so per
-// row the 16 lanes of a lane group see the 16 residue classes of j mod 16.  Each lane keeps the
-// minimum of its class: (tile mod TG, block) is packed into the six low mantissa bits of the
-// value (at most a 2^-17 relative perturbation; with the mask held in a register, packing is one
-// v_and_or) and the tile group (tile / TG) is recorded when the minimum has improved over a
-// group.
-// The topk (<= 16) smallest of the 16 class minima are re-scored.
+// row the 16 lanes of a lane group see the 16 residues j mod 16.  Each lane splits its columns
+// once more by the parity of the block within the tile, so a row's columns fall into 32 classes
+// (16 lanes x 2), and a lane keeps, per row and class, the smallest ranking value (BF16) or the
+// two smallest (FP8, whose coarser rounding moves the true best further down the approximate
+// order).  The global 16-column block index j / 16 is packed into the low mantissa bits of the
+// value (12 bits up to K = 65,536: a relative perturbation below 2^-11, against the 2^-8 of a
+// BF16 operand; with the mask held in a register, packing is one v_and_or), so a kept value
+// carries its column.  The topk (<= 16) smallest kept values of a row, ranked across its 16
+// lanes, are re-scored.
 #include <type_traits>
 
 #include "common.h"
@@ -34,7 +37,7 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr float kBig = 3.0e38f;       // finite sentinel: never a candidate, survives the packing
-constexpr int kMaxTopk = 16;          // candidates re-scored per row: at most the 16 class minima
+constexpr int kMaxTopk = 16;          // candidates re-scored per row
 
 template <int FMT>
 struct FmtTraits;
@@ -65,21 +68,28 @@ __device__ __forceinline__ double row_ror(double v) {
   const auto w = __builtin_bit_cast(int2, v);
   return __builtin_bit_cast(double, int2{row_ror<N>(w.x), row_ror<N>(w.y)});
 }
+#ifndef SOAR_CAND_BF16
+#define SOAR_CAND_BF16 1
+#endif
+#ifndef SOAR_CAND_FP8
+#define SOAR_CAND_FP8 2
+#endif
 
-// Six low mantissa bits carry a code < 64 (tile within its group, block within the tile).  The
-// mask ~63 is not an inline constant, so the sweep keeps it in a register (code_mask) and packing
-// stays one v_and_or.
-constexpr int kCodes = 64;
-__device__ __forceinline__ unsigned code_mask() {
-  unsigned m;
-  asm volatile("v_mov_b32 %0, -64" : "=v"(m));   // ~63, opaque to constant folding
-  return m;
+// The low cbits mantissa bits carry the global block index j / 16 (cbits: enough bits for every
+// block of the codebook).  The mask sits in a VGPR (the block code takes the one scalar operand
+// a VALU instruction may read), so packing stays one v_and_or.
+__device__ __forceinline__ int code_bits(int K) {
+  const unsigned nblk = (unsigned)(K + 15) >> 4;
+  return nblk <= 2u ? 1 : 32 - __builtin_clz(nblk - 1u);
+}
+__device__ __forceinline__ unsigned code_mask(int cbits) {
+  const unsigned m = ~((1u << cbits) - 1u);
+  unsigned v;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(m));
+  return v;
 }
 __device__ __forceinline__ float pack_code(float v, unsigned mask, unsigned c) {
   return __builtin_bit_cast(float, (__builtin_bit_cast(unsigned, v) & mask) | c);
-}
-__device__ __forceinline__ unsigned packed_code(float v) {
-  return __builtin_bit_cast(unsigned, v) & (unsigned)(kCodes - 1);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -91,7 +101,7 @@ __device__ __forceinline__ unsigned char fp8_of(float v) {
   return (unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0u, false) & 0xFFu);
 }
 
-template <int FMT>
+template <int FMT, bool V4 = false>
 __global__ __launch_bounds__(256) void quantize_rows_kernel(const float* __restrict__ A,
                                                             int64_t rows, int d, int dp,
                                                             float mult, void* __restrict__ out,
@@ -121,6 +131,19 @@ __global__ __launch_bounds__(256) void quantize_rows_kernel(const float* __restr
     unsigned char* o = static_cast<unsigned char*>(out) + row * dp;
     for (int k = l16; k < dp; k += 16) o[k] = k < d ? fp8_of(a[k] * scale) : (unsigned char)0;
     if (l16 == 0) inv_scale[row] = 1.f / scale;
+  } else if constexpr (V4) {
+    // rows of whole float4 chunks: 16-byte loads, 8-byte stores
+    __bf16* o = static_cast<__bf16*>(out) + row * dp;
+    for (int k = 4 * l16; k < dp; k += 64) {
+      v4f v = {0.f, 0.f, 0.f, 0.f};
+      if (k < d) v = *reinterpret_cast<const v4f*>(a + k);
+      fin = fin && all_finite4(v);
+      typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+      const bf16x4 b = {(__bf16)(v.x * mult), (__bf16)(v.y * mult), (__bf16)(v.z * mult),
+                        (__bf16)(v.w * mult)};
+      *reinterpret_cast<bf16x4*>(o + k) = b;
+    }
+    if (inv_scale && l16 == 0) inv_scale[row] = 1.f;
   } else {
     __bf16* o = static_cast<__bf16*>(out) + row * dp;
     for (int k = l16; k < dp; k += 16) {
@@ -397,14 +420,18 @@ void lowp_sweep_kernel(LowpParams P) {
 #pragma unroll
     for (int i = 0; i < NRS; ++i) kp[i] -= kbase;
   }
-  // (tile mod TG, block) codes fill the packed bits; the group t / TG is tracked per row
-  constexpr int TG = kCodes / NB;
-  static_assert(TG >= 1, "at most 64 blocks per tile");
-  const unsigned cmask = code_mask();
-  float b1[NR], old[NR];
-  int bt[NR];
+  // kept values per row: NCLS classes (block parity) x CAND smallest, packed with their block
+  constexpr int NCLS = NB >= 2 ? 2 : 1;
+  constexpr int CAND = BF ? SOAR_CAND_BF16 : SOAR_CAND_FP8;
+  static_assert(CAND == 1 || CAND == 2, "one or two kept values per class");
+  constexpr int NS = NCLS * CAND;
+  const int cbits = code_bits(P.K);
+  const unsigned cmask = code_mask(cbits);
+  float kept[NR][NS];
 #pragma unroll
-  for (int i = 0; i < NR; ++i) { b1[i] = kBig; old[i] = kBig; bt[i] = 0; }
+  for (int i = 0; i < NR; ++i)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) kept[i][k] = kBig;
   // lane's base addresses inside a ring stage: B operand rows and the norms
   const int lane_b = c16 * R::LDWB + (q * (DP / 4)) * T::BYTES;
   const int lane_cn = R::CN_OFF + c16 * 16;
@@ -423,6 +450,8 @@ void lowp_sweep_kernel(LowpParams P) {
   constexpr int GU = PIPE ? (NB >= 2 ? NB / 2 : 1) : NB;   // blocks per unit
   static_assert(PIPE || NB <= 4, "one unit per tile without the pipeline");
   constexpr int NU = NB / GU;                      // units per tile
+  static_assert(NU == 1 || NU == 2, "one or two units per tile");
+  // block b of unit g: g + NU b, so with two units each unit's blocks share one parity class
   v4f accS[2][SPW][GU], accT[2][ST2 ? SPW : 1][GU];
   // GR: ||c_j||^2 for row 15; FP8: E8M0 scale of the lane's column (2 / its quantization scale)
   float ucn[2][GR ? GU : 1];
@@ -433,7 +462,7 @@ void lowp_sweep_kernel(LowpParams P) {
     const char* tb = tile + lane_b;
 #pragma unroll
     for (int b = 0; b < GU; ++b) {
-      const int blk = g * GU + b;
+      const int blk = g + NU * b;
       v4f init = v4f{0.f, 0.f, 0.f, 0.f};
       if constexpr (GR) ucn[S][b] = *reinterpret_cast<const float*>(tile + lane_cn + blk * 256);
       else init = *reinterpret_cast<const v4f*>(tile + lane_cn + blk * 256);
@@ -451,7 +480,7 @@ void lowp_sweep_kernel(LowpParams P) {
       for (int b = 0; b < GU; ++b)
 #pragma unroll
         for (int ww = 0; ww < W4; ++ww)
-          bv[b][ww] = *reinterpret_cast<const u32x4*>(tb + (g * GU + b) * 16 * R::LDWB +
+          bv[b][ww] = *reinterpret_cast<const u32x4*>(tb + (g + NU * b) * 16 * R::LDWB +
                                                       s * T::LANE_B + ww * 16);
 #pragma unroll
       for (int b = 0; b < GU; ++b)
@@ -495,7 +524,7 @@ void lowp_sweep_kernel(LowpParams P) {
     // each packing is then one v_and_or with an SGPR
 #pragma unroll
     for (int b = 0; b < GU; ++b)
-      etc[b] = (unsigned)__builtin_amdgcn_readfirstlane((ts % TG) * NB + g * GU + b);
+      etc[b] = (unsigned)__builtin_amdgcn_readfirstlane((t0 + ts) * NB + g + NU * b);
     // GPD: stripe row 15 is lane group 3 (lanes 48..63), register 3.  It is broadcast to every
     // lane group with two lane swaps instead of an LDS permute: after the 32-lane swap of a
     // register with itself the second result holds lanes 32..63 in both halves, and after the
@@ -549,13 +578,28 @@ void lowp_sweep_kernel(LowpParams P) {
         val = fmaf(accT[S][st][b][v], accT[S][st][b][v], val);
       }
       if constexpr (SP && decltype(with_mask)::value)
-        val = (ts * BN + (g * GU + b) * 16 + c16 == kp[i]) ? kBig : val;
+        val = (ts * BN + (g + NU * b) * 16 + c16 == kp[i]) ? kBig : val;
       pv[b] = pack_code(val, cmask, etc[b]);
     }
-    float m = pv[0];
+    // block g + NU b has class (g + NU b) % NCLS: one class for the whole unit when NU == 2
 #pragma unroll
-    for (int b = 1; b < GU; ++b) m = fminf(m, pv[b]);
-    b1[i] = fminf(b1[i], m);
+    for (int c = 0; c < NCLS; ++c) {
+      if constexpr (CAND == 1) {
+        float m = kept[i][c];
+#pragma unroll
+        for (int b = 0; b < GU; ++b)
+          if ((NU == 2 ? g % NCLS : b % NCLS) == c) m = fminf(m, pv[b]);
+        kept[i][c] = m;
+      } else {
+#pragma unroll
+        for (int b = 0; b < GU; ++b)
+          if ((NU == 2 ? g % NCLS : b % NCLS) == c) {
+            // two smallest: the new second is the median of (first, second, new)
+            kept[i][2 * c + 1] = __builtin_amdgcn_fmed3f(kept[i][2 * c], kept[i][2 * c + 1], pv[b]);
+            kept[i][2 * c] = fminf(kept[i][2 * c], pv[b]);
+          }
+      }
+    }
   };
   auto epi_unit = [&](auto set, auto with_mask, int ts, int g) __attribute__((always_inline)) {
     epi_prep(set, ts, g);
@@ -577,7 +621,7 @@ void lowp_sweep_kernel(LowpParams P) {
     v4f init[GU];
 #pragma unroll
     for (int b = 0; b < GU; ++b) {
-      const int blk = g * GU + b;
+      const int blk = g + NU * b;
       if constexpr (GR) {
         init[b] = v4f{0.f, 0.f, 0.f, 0.f};
         ucn[S][b] = *reinterpret_cast<const float*>(tile + lane_cn + blk * 256);
@@ -592,7 +636,7 @@ void lowp_sweep_kernel(LowpParams P) {
       for (int b = 0; b < GU; ++b)
 #pragma unroll
         for (int ww = 0; ww < W4; ++ww)
-          bv[k][b][ww] = *reinterpret_cast<const u32x4*>(tb + (g * GU + b) * 16 * R::LDWB +
+          bv[k][b][ww] = *reinterpret_cast<const u32x4*>(tb + (g + NU * b) * 16 * R::LDWB +
                                                          s * T::LANE_B + ww * 16);
     };
     read_step(0, 0);
@@ -643,17 +687,6 @@ void lowp_sweep_kernel(LowpParams P) {
       return __builtin_amdgcn_readfirstlane((int)__any(hit)) != 0;
     }
   };
-  // after the last epilogue of tile ts: record the tile group of every improved minimum
-  auto close_tile = [&](int ts) __attribute__((always_inline)) {
-    // (a real branch: the updates run once per tile group, not as selects in every tile)
-    if (__builtin_expect((ts + 1) % TG == 0 || ts + 1 == ntiles, 0)) {
-#pragma unroll
-      for (int i = 0; i < NR; ++i) {
-        bt[i] = b1[i] < old[i] ? ts / TG : bt[i];
-        old[i] = b1[i];
-      }
-    }
-  };
 
   const char* tile = s_ring;
   int stage = 0;
@@ -686,7 +719,6 @@ void lowp_sweep_kernel(LowpParams P) {
       mfma_unit(s0, tile, G);
       if (__builtin_expect(m_cur, 0)) epi_unit(s0, std::true_type{}, t, G);
       else epi_unit(s0, std::false_type{}, t, G);
-      if (G == NU - 1) close_tile(t);
       return;
     }
     constexpr int GP = NU == 2 ? 1 - S : 0;        // the previous unit's g
@@ -702,7 +734,6 @@ void lowp_sweep_kernel(LowpParams P) {
     } else {
       fused_unit(set, tile, G, tp, GP);
     }
-    if (u > 0 && GP == NU - 1) close_tile(tp);
   };
   const int nunits = ntiles * NU;
   if constexpr (PIPE) {
@@ -724,42 +755,72 @@ void lowp_sweep_kernel(LowpParams P) {
       if (ml) epi_unit(std::integral_constant<int, 0>{}, std::true_type{}, ntiles - 1, NU - 1);
       else epi_unit(std::integral_constant<int, 0>{}, std::false_type{}, ntiles - 1, NU - 1);
     }
-    close_tile(ntiles - 1);
   }
 
-  // candidates: rank the 16 class minima of every row, keep the topk smallest
+  // candidates: the topk smallest kept values of every row across its 16 lanes (value, then
+  // column), by repeated extraction: each lane orders its NS keys, the row takes the least head
+  // of its lanes (DPP minima, so all 16 lanes agree), and the lane that held it moves on
   const int topk = P.topk;
+  const unsigned cfield = (1u << cbits) - 1u;
 #pragma unroll
   for (int st = 0; st < SPW; ++st)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = st * 4 + v;
       const int64_t r = row_of(st, 4 * q + v);
-      const float bv = b1[i];
-      const bool valid = bv < 1.0e38f;
-      const unsigned code = packed_code(bv);
-      // (lanes without a valid minimum get distinct keys past every column, so the ranks are a
-      // permutation and every one of the topk slots is written)
-      const int j = valid ? kbase + (bt[i] * TG + (int)(code / NB)) * BN + (int)(code % NB) * 16 +
-                                c16
-                          : 0x7fffff00 + c16;
-      int rank = 0;
+      float kv[NS];
+      int kj[NS];
 #pragma unroll
-      for (int o = 1; o < 16; ++o) {
-        const int src = (q << 4) | ((c16 + o) & 15);
-        const float ov = __shfl(bv, src);
-        const int oj = __shfl(j, src);
-        rank += (ov < bv || (ov == bv && oj < j)) ? 1 : 0;
+      for (int k = 0; k < NS; ++k) {
+        kv[k] = kept[i][k];
+        const bool valid = kv[k] < 1.0e38f;
+        // (slots without a value get distinct keys past every column, so every one of the topk
+        // places is written, with -1)
+        kj[k] = valid ? (int)((__builtin_bit_cast(unsigned, kv[k]) & cfield) * 16u) + c16
+                      : 0x7fffff00 + c16 * NS + k;
+        if (!valid) kv[k] = kInf;
       }
-      if (r >= 0 && rank < topk) {
-        const int jj = (valid && j < P.K) ? j : -1;
-        if constexpr (!KS) {
-          P.cand[r * topk + rank] = jj;
-        } else {                                   // per split, with values, for the merge
-          const int64_t o = (r * gridDim.y + blockIdx.y) * topk + rank;
-          P.cand_split[o] = jj;
-          P.cand_val[o] = jj >= 0 ? bv : kInf;
+      // order the lane's keys (a small exchange network)
+#pragma unroll
+      for (int a = 0; a < NS; ++a)
+#pragma unroll
+        for (int b = 0; b + 1 < NS - a; ++b) {
+          const bool sw = kv[b + 1] < kv[b] || (kv[b + 1] == kv[b] && kj[b + 1] < kj[b]);
+          const float tv = sw ? kv[b + 1] : kv[b];
+          const int tj = sw ? kj[b + 1] : kj[b];
+          kv[b + 1] = sw ? kv[b] : kv[b + 1];
+          kj[b + 1] = sw ? kj[b] : kj[b + 1];
+          kv[b] = tv;
+          kj[b] = tj;
         }
+      int head = 0;
+      for (int k = 0; k < topk; ++k) {
+        float h = kInf;
+        int hj = 0x7ffffff0 + c16;
+#pragma unroll
+        for (int a = 0; a < NS; ++a)
+          if (head == a) { h = kv[a]; hj = kj[a]; }
+        float m = fminf(h, row_ror<8>(h));
+        m = fminf(m, row_ror<4>(m));
+        m = fminf(m, row_ror<2>(m));
+        m = fminf(m, row_ror<1>(m));
+        int cj = h == m ? hj : 0x7fffffff;
+        cj = min(cj, row_ror<8>(cj));
+        cj = min(cj, row_ror<4>(cj));
+        cj = min(cj, row_ror<2>(cj));
+        cj = min(cj, row_ror<1>(cj));
+        const bool win = h == m && hj == cj;
+        if (win && r >= 0) {
+          const int jj = (m < kInf && cj < P.K) ? cj : -1;
+          if constexpr (!KS) {
+            P.cand[r * topk + k] = jj;
+          } else {                                 // per split, with values, for the merge
+            const int64_t o = (r * gridDim.y + blockIdx.y) * topk + k;
+            P.cand_split[o] = jj;
+            P.cand_val[o] = jj >= 0 ? m : kInf;
+          }
+        }
+        head += win ? 1 : 0;
       }
     }
 }
@@ -1032,7 +1093,11 @@ hipError_t launch_lowp_quantize(int fmt, const float* A, int64_t rows, int d, in
                                 bool codebook, void* out, float* inv_scale, unsigned* counters,
                                 hipStream_t st, const int64_t* live_n) {
   const dim3 grid((unsigned)((rows + 15) / 16)), block(256);
-  if (fmt == LOWP_BF16)
+  const bool v4 = d % 4 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0;
+  if (fmt == LOWP_BF16 && v4)
+    hipLaunchKernelGGL((quantize_rows_kernel<LOWP_BF16, true>), grid, block, 0, st, A, rows, d, dp,
+                       codebook ? -2.f : 1.f, out, inv_scale, counters, live_n);
+  else if (fmt == LOWP_BF16)
     hipLaunchKernelGGL(quantize_rows_kernel<LOWP_BF16>, grid, block, 0, st, A, rows, d, dp,
                        codebook ? -2.f : 1.f, out, inv_scale, counters, live_n);
   else

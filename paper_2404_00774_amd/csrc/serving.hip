@@ -2,19 +2,27 @@
 // the points assigned to it; with SOAR a point sits in the lists of pi(x) and pi'(x)), fed by
 // streaming insert requests.
 //
-// A scheduler thread batches queued rows FIFO into device steps of at most max_step_rows rows
-// (a request may span steps, a step may hold many requests).  Two step slots, each with its own
-// stream, buffers and pre-captured HIP graphs, let consecutive steps overlap on the GPU; a
-// request is admitted to a step when a slot is free and the list arena can take the step's
-// worst-case growth.  A step is
+// Continuous batching.  A scheduler thread builds device steps of at most max_step_rows rows from
+// the queued requests and launches each into a free step slot as soon as one is free (a request
+// may span steps, a step may hold many requests).  Rows are shared out max-min fairly: every
+// queued request gets up to an equal share of the step, and what a request does not need goes to
+// the others, so a small request that arrives behind a large one joins the very next step.  Each
+// slot has its own stream, buffers, pre-captured HIP graphs and a waiter thread, so steps overlap
+// on the GPU and each one's results are delivered the moment its own work is done.  A step is
 //   H2D (live row count, rows, ids) -> compute graph (the SOAR assignment kernels, which read the
-//   live row count from device memory) -> [waits for the previous step's list append] -> append
-//   graph (count, reserve chunks, scatter ids) -> D2H (indices, arena usage).
+//   live row count from device memory) -> D2H of the indices [results delivered here] ->
+//   [waits for the previous step's list append] -> append graph (count, reserve chunks, scatter
+//   ids) -> D2H of the step's list status [slot freed here].
+// Admission by memory: a step is admitted only if the list arena can take its worst-case growth
+// on top of what the steps in flight may take.
 //
-// Lists live in the caller's arena as chunks of CH ids; partition p owns up to MAXC chunks listed
-// in dir[p].  Appends of one step: count per partition, one thread per touched partition reserves
-// the chunks it needs (an atomic bump of the chunk pool), then every assignment takes a slot by an
-// atomic cursor.  The order of ids inside a list is therefore not fixed; its content is.
+// Lists live in the caller's arena as chains of chunks of CH ids: partition p has len[p] ids in
+// the chain head[p] -> next[] -> tail[p].  The appends of one step: count per partition; one
+// thread per touched partition takes the chunks it needs from the pool (a compare-and-swap bump
+// that never takes more than the pool holds) and links them behind its tail; then every
+// assignment takes a position by an atomic cursor and finds its chunk from the step's first new
+// chunk.  The order of ids inside a list is therefore not fixed; its content is.  Appends of
+// consecutive steps are ordered by events, so these per-step arrays are shared by all slots.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -34,15 +42,21 @@
 namespace soar {
 
 constexpr int LIST_CH = 64;        // ids per chunk
-constexpr int LIST_MAXC = 1024;    // chunks per partition (65536 ids)
+constexpr int kSlots = 2;          // step slots (steps in flight at once)
 
 struct ListDev {
   int32_t* len;      // [K] ids in the list
-  int32_t* cursor;   // [K] append cursor of the current step
-  int32_t* cnt;      // [K] appends of the current step (-1: could not reserve)
-  int32_t* dir;      // [K * LIST_MAXC] chunk numbers
+  int32_t* head;     // [K] first chunk (-1: empty list)
+  int32_t* tail;     // [K] last chunk
+  int32_t* next;     // [chunks] next chunk of the same list (-1: last)
   int64_t* pool;     // [chunks * LIST_CH] ids
-  int32_t* meta;     // [0] chunks in use, [1] overflow flag
+  // per-step state (appends of consecutive steps are serialized)
+  int32_t* cnt;      // [K] appends of the current step (-1: could not reserve)
+  int32_t* cursor;   // [K] append cursor (old length + appends taken so far)
+  int32_t* olen;     // [K] length before the step
+  int32_t* otail;    // [K] tail before the step
+  int32_t* first;    // [K] first new chunk of the step
+  int32_t* meta;     // [0] chunks in use
   int32_t chunks;    // pool capacity in chunks
   int32_t K;
 };
@@ -64,7 +78,10 @@ __global__ void list_count_kernel(const int32_t* __restrict__ prim, const int32_
   }
 }
 
-__global__ void list_reserve_kernel(ListDev L) {
+// One thread per partition with appends: reserve its new chunks and link them behind its tail.
+// A reservation that the pool cannot hold takes nothing, leaves the list as it was and sets
+// bit 0 of the step's status word.
+__global__ void list_reserve_kernel(ListDev L, unsigned* status) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= L.K) return;
   const int c = L.cnt[p];
@@ -72,16 +89,28 @@ __global__ void list_reserve_kernel(ListDev L) {
   const int old = L.len[p], nw = old + c;
   const int have = (old + LIST_CH - 1) / LIST_CH, need = (nw + LIST_CH - 1) / LIST_CH;
   const int k = need - have;
-  if (need > LIST_MAXC) { L.cnt[p] = -1; atomicOr(reinterpret_cast<unsigned*>(&L.meta[1]), 1u); return; }
+  int base = -1;
   if (k > 0) {
-    const int base = atomicAdd(&L.meta[0], k);
-    if (base + k > L.chunks) {
-      L.cnt[p] = -1;
-      atomicOr(reinterpret_cast<unsigned*>(&L.meta[1]), 2u);
-      return;
+    int cur = atomicAdd(&L.meta[0], 0);
+    for (;;) {
+      if (cur > L.chunks - k) {
+        L.cnt[p] = -1;
+        atomicOr(status, 1u);
+        return;
+      }
+      const int seen = atomicCAS(&L.meta[0], cur, cur + k);
+      if (seen == cur) break;
+      cur = seen;
     }
-    for (int i = 0; i < k; ++i) L.dir[(int64_t)p * LIST_MAXC + have + i] = base + i;
+    base = cur;
+    for (int i = 0; i < k; ++i) L.next[base + i] = i + 1 < k ? base + i + 1 : -1;
+    if (old == 0) L.head[p] = base;
+    else L.next[L.tail[p]] = base;
   }
+  L.olen[p] = old;
+  L.otail[p] = old == 0 ? -1 : L.tail[p];
+  L.first[p] = base;
+  if (k > 0) L.tail[p] = base + k - 1;
   L.cursor[p] = old;
   L.len[p] = nw;
 }
@@ -99,7 +128,9 @@ __global__ void list_scatter_kernel(const int32_t* __restrict__ prim,
       const int p = ab[k];
       if (p < 0 || p >= L.K || L.cnt[p] < 0) continue;
       const int pos = atomicAdd(&L.cursor[p], 1);
-      const int chunk = L.dir[(int64_t)p * LIST_MAXC + pos / LIST_CH];
+      // positions up to the old tail chunk's end stay in it; the rest go to the new chunks
+      const int ofull = (L.olen[p] + LIST_CH - 1) / LIST_CH * LIST_CH;
+      const int chunk = pos < ofull ? L.otail[p] : L.first[p] + (pos - ofull) / LIST_CH;
       L.pool[(int64_t)chunk * LIST_CH + pos % LIST_CH] = ids[i];
     }
   }
@@ -119,7 +150,7 @@ struct Request {
   std::vector<float> X;
   std::vector<int32_t> prim, spill;
   int64_t next_row = 0;    // rows handed to steps
-  int64_t done_rows = 0;   // rows whose step completed
+  int64_t done_rows = 0;   // rows whose results arrived
   soar_status status = SOAR_OK;
   bool complete = false;
 };
@@ -132,22 +163,24 @@ struct Part {
 struct Slot {
   hipStream_t st = nullptr;
   hipGraphExec_t g_compute = nullptr, g_append = nullptr;
-  hipEvent_t ev_done = nullptr, ev_append = nullptr;
+  hipEvent_t ev_results = nullptr, ev_append = nullptr, ev_done = nullptr;
   // device
   float* X = nullptr;
   int64_t* ids = nullptr;
   int64_t* live = nullptr;
   int32_t* prim = nullptr;
   int32_t* spill = nullptr;
+  unsigned* status = nullptr;    // list status of the step (bit 0: a reservation failed)
   void* ws = nullptr;            // assignment workspace of this slot
   unsigned* counters = nullptr;
   // pinned host staging
   char* h_in = nullptr;          // [live int64][ids cap int64][X cap*d float]
-  char* h_out = nullptr;         // [prim cap][spill cap][meta 4][counters 8]
+  char* h_out = nullptr;         // [prim cap][spill cap][counters 8][status, chunks used]
   bool busy = false;
   int64_t rows = 0, worst_chunks = 0;
-  uint64_t seq = 0;
   std::vector<Part> parts;
+  std::thread waiter;
+  std::condition_variable cv;    // a step was launched into this slot, or shutdown
 };
 
 }  // namespace
@@ -166,9 +199,8 @@ struct soar_index {
   float* cnorm = nullptr;
   void* crec = nullptr;          // packed codebook records of the sweeps
   ListDev L{};
-  Slot slots[2];
+  Slot slots[kSlots];
   hipEvent_t last_append = nullptr;   // append event of the latest launched step
-  uint64_t seq = 0;
   // scheduling state (guarded by mu)
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -179,8 +211,10 @@ struct soar_index {
   int64_t chunks_reserved = 0;   // worst case of the steps in flight
   bool shutdown = false;
   bool device_error = false;
-  bool paused = false;
+  bool list_error = false;       // an append could not be reserved (never with admission)
+  int paused = 0;
   int in_flight = 0;
+  soar_index_stats stats{};
   std::thread worker;
 };
 
@@ -193,19 +227,22 @@ namespace {
 // columns.  Fixed per index, so a row's result does not depend on the step it runs in.
 int serving_ksplit(int K) { return std::max(1, std::min(8, K / 4096)); }
 
-size_t step_ws_bytes(int fmt_or_fp32, int64_t cap, int d, int K, bool lowp, int fmt) {
-  if (!lowp) return al(CNT_WORDS * 4) + al((size_t)cap * 4);   // counters + full-scan rows
+size_t step_ws_bytes(int64_t cap, int d, int K, bool lowp, int fmt) {
+  if (!lowp) return al(CNT_ALLOC_WORDS * 4) + al((size_t)cap * 4);   // counters + full-scan rows
   const int dp = lowp_padded_dim(fmt, d);
   const size_t eb = fmt == LOWP_BF16 ? 2 : 1;
   const int S = serving_ksplit(K);
-  (void)fmt_or_fp32;
-  return al(CNT_WORDS * 4) + 2 * al((size_t)cap * dp * eb) + al((size_t)cap * 4) +
+  return al(CNT_ALLOC_WORDS * 4) + 2 * al((size_t)cap * dp * eb) + al((size_t)cap * 4) +
          al((size_t)cap * 16) + al((size_t)cap * 8 * 4) +
          (S > 1 ? 2 * al((size_t)cap * S * 8 * 4) : 0);
 }
 
+// Bytes of one list chunk: its ids and its link.
+constexpr size_t kChunkBytes = LIST_CH * 8 + 4;
+
 struct ArenaPlan {
-  size_t C, cnorm, crec, L_len, L_cursor, L_cnt, L_dir, L_meta, slot[2], pool;
+  size_t C, cnorm, crec, L_len, L_head, L_tail, L_cnt, L_cursor, L_olen, L_otail, L_first, L_meta;
+  size_t slot[kSlots], next, pool;
   size_t slot_bytes, fixed, total;
   int64_t chunks;
 };
@@ -220,22 +257,29 @@ ArenaPlan plan_arena(int K, int d, int precision, int cap, size_t arena_bytes) {
   P.cnorm = take((size_t)K * 4);
   P.crec = take(lowp ? lowp_codebook_bytes(fmt, d, K) : fp32_codebook_bytes(d, K));
   P.L_len = take((size_t)K * 4);
-  P.L_cursor = take((size_t)K * 4);
+  P.L_head = take((size_t)K * 4);
+  P.L_tail = take((size_t)K * 4);
   P.L_cnt = take((size_t)K * 4);
-  P.L_dir = take((size_t)K * LIST_MAXC * 4);
+  P.L_cursor = take((size_t)K * 4);
+  P.L_olen = take((size_t)K * 4);
+  P.L_otail = take((size_t)K * 4);
+  P.L_first = take((size_t)K * 4);
   P.L_meta = take(64);
   P.slot_bytes = al((size_t)cap * d * 4) + al((size_t)cap * 8) + al(8) + 2 * al((size_t)cap * 4) +
-                 step_ws_bytes(0, cap, d, K, lowp, fmt);
-  P.slot[0] = take(P.slot_bytes);
-  P.slot[1] = take(P.slot_bytes);
-  P.fixed = off;
-  P.pool = off;
-  P.chunks = arena_bytes > off ? (int64_t)((arena_bytes - off) / (LIST_CH * 8)) : 0;
-  if (P.chunks > INT32_MAX) P.chunks = INT32_MAX;
-  P.total = off + (size_t)P.chunks * LIST_CH * 8;
+                 al(64) + step_ws_bytes(cap, d, K, lowp, fmt);
+  for (int k = 0; k < kSlots; ++k) P.slot[k] = take(P.slot_bytes);
+  P.fixed = off + 2 * kAl;        // the link and id arrays start aligned
+  int64_t chunks = arena_bytes > P.fixed ? (int64_t)((arena_bytes - P.fixed) / kChunkBytes) : 0;
+  if (chunks > INT32_MAX) chunks = INT32_MAX;
+  P.chunks = chunks;
+  P.next = take((size_t)chunks * 4);
+  P.pool = take((size_t)chunks * LIST_CH * 8);
+  P.total = off;
   return P;
 }
 
+// Most chunks the appends of a step of `rows` rows can take: its ids fill whole chunks, plus at
+// most one partly filled new chunk per touched partition.
 int64_t worst_chunks(int64_t rows, int K) {
   const int64_t a = 2 * rows;
   return (a + LIST_CH - 1) / LIST_CH + std::min<int64_t>(a, K);
@@ -256,14 +300,14 @@ hipError_t enqueue_compute(soar_index* ix, Slot& s) {
     P.band_p = band_coef_primary(ix->d);
     P.band_s = band_coef_spill(ix->d, ix->lambda);
     P.primary = s.prim; P.spill = s.spill; P.pdist = nullptr; P.sloss = nullptr;
-    char* w = static_cast<char*>(s.ws) + al(CNT_WORDS * 4);
+    char* w = static_cast<char*>(s.ws) + al(CNT_ALLOC_WORDS * 4);
     P.full_rows = reinterpret_cast<int32_t*>(w);
     P.live_n = s.live;
     return launch_assign_fp32(P, true, ix->d % 4 == 0, s.st);
   }
   const int fmt = ix->fmt, dp = lowp_padded_dim(fmt, ix->d);
   const size_t eb = fmt == LOWP_BF16 ? 2 : 1;
-  char* w = static_cast<char*>(s.ws) + al(CNT_WORDS * 4);
+  char* w = static_cast<char*>(s.ws) + al(CNT_ALLOC_WORDS * 4);
   LowpParams P;
   P.n = ix->cap; P.d = ix->d; P.dp = dp; P.K = ix->K; P.topk = 8;
   P.lam = ix->lambda;
@@ -297,11 +341,15 @@ hipError_t enqueue_compute(soar_index* ix, Slot& s) {
 
 hipError_t enqueue_append(soar_index* ix, Slot& s) {
   const ListDev& L = ix->L;
+  // fill kernels, not memsets: these run inside a replayed graph
   hipLaunchKernelGGL(fill_i32, dim3((L.K + 255) / 256), dim3(256), 0, s.st, L.cnt, (int64_t)L.K, 0);
+  hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, s.st, reinterpret_cast<int32_t*>(s.status),
+                     (int64_t)1, 0);
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((ix->cap + 255) / 256, 1024));
   hipLaunchKernelGGL(list_count_kernel, dim3(g), dim3(256), 0, s.st, s.prim, s.spill, s.live,
                      (int64_t)ix->cap, L);
-  hipLaunchKernelGGL(list_reserve_kernel, dim3((L.K + 255) / 256), dim3(256), 0, s.st, L);
+  hipLaunchKernelGGL(list_reserve_kernel, dim3((L.K + 255) / 256), dim3(256), 0, s.st, L,
+                     s.status);
   hipLaunchKernelGGL(list_scatter_kernel, dim3(g), dim3(256), 0, s.st, s.prim, s.spill, s.ids,
                      s.live, (int64_t)ix->cap, L);
   return hipGetLastError();
@@ -321,42 +369,57 @@ hipError_t capture(hipStream_t st, hipGraphExec_t* out, F&& body) {
   return e;
 }
 
-// Completion of the oldest busy slot (called without the lock held while waiting).
-void complete_slot(soar_index* ix, Slot& s, std::unique_lock<std::mutex>& lk) {
-  lk.unlock();
-  const hipError_t e = hipEventSynchronize(s.ev_done);
-  lk.lock();
-  const int32_t* hp = reinterpret_cast<const int32_t*>(s.h_out);
-  const int32_t* hs = hp + ix->cap;
-  const int32_t* meta = hs + ix->cap;
-  const unsigned* cnt = reinterpret_cast<const unsigned*>(meta + 4);
-  soar_status st = SOAR_OK;
-  if (e != hipSuccess) { st = SOAR_E_DEVICE; ix->device_error = true; }
-  else if (meta[1] != 0) st = SOAR_E_NOMEM;
-  else if (cnt[CNT_NONFINITE]) st = SOAR_E_NONFINITE;
-  if (e == hipSuccess) ix->chunks_used = meta[0];
-  ix->chunks_reserved -= s.worst_chunks;
-  for (Part& p : s.parts) {
-    Request& r = *p.req;
-    std::memcpy(r.prim.data() + p.row0, hp + p.slot_off, p.rows * 4);
-    std::memcpy(r.spill.data() + p.row0, hs + p.slot_off, p.rows * 4);
-    if (st != SOAR_OK && r.status == SOAR_OK) r.status = st;
-    r.done_rows += p.rows;
-    if (r.done_rows == r.n) {
-      r.complete = true;
-      r.X.clear();
-      r.X.shrink_to_fit();
-    }
+// Host layout of a slot's results buffer.
+struct OutView {
+  int32_t* prim;
+  int32_t* spill;
+  unsigned* cnt;
+  unsigned* list;     // [0] step status, [1] chunks in use after the step
+};
+OutView out_view(const soar_index* ix, const Slot& s) {
+  OutView v;
+  v.prim = reinterpret_cast<int32_t*>(s.h_out);
+  v.spill = v.prim + ix->cap;
+  v.cnt = reinterpret_cast<unsigned*>(v.spill + ix->cap);
+  v.list = v.cnt + CNT_WORDS;
+  return v;
+}
+
+// The rows of `limit` a step takes from each queued request: max-min fair shares (a request
+// needing less than an equal share gets all it needs, the rest is split evenly), handed out in
+// queue order.
+std::vector<Part> plan_step(soar_index* ix, int64_t limit) {
+  std::vector<int64_t> need;
+  for (auto& r : ix->queue) need.push_back(r->n - r->next_row);
+  std::vector<int64_t> sorted = need;
+  std::sort(sorted.begin(), sorted.end());
+  // the largest share s with sum_i min(need_i, s) <= limit
+  const size_t m = sorted.size();
+  int64_t left = limit, share = m ? sorted[m - 1] : 0;
+  for (size_t i = 0; i < m; ++i) {
+    const int64_t eq = left / (int64_t)(m - i);
+    if (sorted[i] > eq) { share = eq; break; }
+    left -= sorted[i];
   }
-  s.parts.clear();
-  s.busy = false;
-  --ix->in_flight;
-  ix->cv_done.notify_all();
+  int64_t extra = limit;
+  for (int64_t v : need) extra -= std::min(v, share);
+  std::vector<Part> parts;
+  int64_t rows = 0;
+  size_t i = 0;
+  for (auto it = ix->queue.begin(); it != ix->queue.end(); ++it, ++i) {
+    int64_t take = std::min(need[i], share);
+    const int64_t more = std::max<int64_t>(0, std::min(need[i] - take, extra));
+    take += more;
+    extra -= more;
+    if (take <= 0) continue;
+    parts.push_back(Part{*it, (*it)->next_row, take, rows});
+    rows += take;
+  }
+  return parts;
 }
 
 // Fill slot s from the queue and launch it (lock held; released around the copies).
 bool try_launch(soar_index* ix, Slot& s, std::unique_lock<std::mutex>& lk) {
-  if (ix->queue.empty() || ix->device_error || ix->paused) return false;
   // admission by memory: the most rows whose worst-case list growth fits the free chunks
   const int64_t free_chunks = ix->L.chunks - ix->chunks_used - ix->chunks_reserved;
   int64_t limit = ix->cap;
@@ -372,33 +435,25 @@ bool try_launch(soar_index* ix, Slot& s, std::unique_lock<std::mutex>& lk) {
     }
     return false;
   }
-  // rows for this step, FIFO, splitting the last request if needed
+  std::vector<Part> parts = plan_step(ix, limit);
   int64_t rows = 0;
-  std::vector<Part> parts;
-  for (auto it = ix->queue.begin(); it != ix->queue.end() && rows < limit; ++it) {
-    Request& r = **it;
-    const int64_t take = std::min<int64_t>(r.n - r.next_row, limit - rows);
-    if (take <= 0) continue;
-    parts.push_back(Part{*it, r.next_row, take, rows});
-    rows += take;
-  }
+  for (Part& p : parts) rows += p.rows;
   if (rows == 0) return false;
-  const int64_t worst = worst_chunks(rows, ix->K);
-  // commit the rows to this step
-  for (Part& p : parts) {
-    p.req->next_row += p.rows;
-  }
-  while (!ix->queue.empty() && ix->queue.front()->next_row == ix->queue.front()->n)
-    ix->queue.pop_front();
-  s.parts = parts;
+  for (Part& p : parts) p.req->next_row += p.rows;
+  for (auto it = ix->queue.begin(); it != ix->queue.end();)
+    it = (*it)->next_row == (*it)->n ? ix->queue.erase(it) : it + 1;
+  s.parts = std::move(parts);
   s.rows = rows;
-  s.worst_chunks = worst;
+  s.worst_chunks = worst_chunks(rows, ix->K);
   s.busy = true;
-  s.seq = ++ix->seq;
-  ix->chunks_reserved += worst;
+  ix->chunks_reserved += s.worst_chunks;
   ++ix->in_flight;
+  ix->stats.steps += 1;
+  ix->stats.rows += rows;
+  ix->stats.max_steps_in_flight = std::max<int64_t>(ix->stats.max_steps_in_flight, ix->in_flight);
   hipEvent_t prev_append = ix->last_append;
   ix->last_append = s.ev_append;
+  ++ix->paused;                       // no soar_index_list while this slot is being launched
   lk.unlock();
   // stage the rows (pinned), then the step
   int64_t* hlive = reinterpret_cast<int64_t*>(s.h_in);
@@ -410,62 +465,107 @@ bool try_launch(soar_index* ix, Slot& s, std::unique_lock<std::mutex>& lk) {
     std::memcpy(hX + p.slot_off * ix->d, r.X.data() + p.row0 * ix->d, p.rows * ix->d * 4);
     for (int64_t i = 0; i < p.rows; ++i) hids[p.slot_off + i] = r.first_id + p.row0 + i;
   }
+  const OutView o = out_view(ix, s);
   hipError_t e = hipMemcpyAsync(s.live, hlive, 8, hipMemcpyHostToDevice, s.st);
   if (e == hipSuccess) e = hipMemcpyAsync(s.ids, hids, rows * 8, hipMemcpyHostToDevice, s.st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(s.X, hX, rows * ix->d * 4, hipMemcpyHostToDevice, s.st);
   if (e == hipSuccess) e = hipGraphLaunch(s.g_compute, s.st);
+  if (e == hipSuccess) e = hipMemcpyAsync(o.prim, s.prim, rows * 4, hipMemcpyDeviceToHost, s.st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(o.spill, s.spill, rows * 4, hipMemcpyDeviceToHost, s.st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(o.cnt, s.counters, CNT_WORDS * 4, hipMemcpyDeviceToHost, s.st);
+  if (e == hipSuccess) e = hipEventRecord(s.ev_results, s.st);
   if (e == hipSuccess && prev_append) e = hipStreamWaitEvent(s.st, prev_append, 0);
   if (e == hipSuccess) e = hipGraphLaunch(s.g_append, s.st);
   if (e == hipSuccess) e = hipEventRecord(s.ev_append, s.st);
-  int32_t* hp = reinterpret_cast<int32_t*>(s.h_out);
+  if (e == hipSuccess) e = hipMemcpyAsync(o.list, s.status, 4, hipMemcpyDeviceToHost, s.st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(hp, s.prim, rows * 4, hipMemcpyDeviceToHost, s.st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(hp + ix->cap, s.spill, rows * 4, hipMemcpyDeviceToHost, s.st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(hp + 2 * ix->cap, ix->L.meta, 16, hipMemcpyDeviceToHost, s.st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(hp + 2 * ix->cap + 4, s.counters, CNT_WORDS * 4, hipMemcpyDeviceToHost,
-                       s.st);
+    e = hipMemcpyAsync(o.list + 1, ix->L.meta, 4, hipMemcpyDeviceToHost, s.st);
   if (e == hipSuccess) e = hipEventRecord(s.ev_done, s.st);
   lk.lock();
+  --ix->paused;
   if (e != hipSuccess) ix->device_error = true;
+  s.cv.notify_one();                  // the slot's waiter takes it from here
+  ix->cv_done.notify_all();
   return true;
 }
 
+// Waiter thread of one slot: results to the requests as soon as the step's indices are in host
+// memory; the slot (and its worst-case list memory) free once its list append is done.
+void slot_loop(soar_index* ix, Slot& s) {
+  std::unique_lock<std::mutex> lk(ix->mu);
+  for (;;) {
+    s.cv.wait(lk, [&] { return s.busy || (ix->shutdown && ix->in_flight == 0 &&
+                                          ix->queue.empty()); });
+    if (!s.busy) break;
+    lk.unlock();
+    const hipError_t e1 = hipEventSynchronize(s.ev_results);
+    lk.lock();
+    const OutView o = out_view(ix, s);
+    soar_status st = SOAR_OK;
+    if (e1 != hipSuccess) { st = SOAR_E_DEVICE; ix->device_error = true; }
+    else if (o.cnt[CNT_NONFINITE]) st = SOAR_E_NONFINITE;
+    for (Part& p : s.parts) {
+      Request& r = *p.req;
+      std::memcpy(r.prim.data() + p.row0, o.prim + p.slot_off, p.rows * 4);
+      std::memcpy(r.spill.data() + p.row0, o.spill + p.slot_off, p.rows * 4);
+      if (st != SOAR_OK && r.status == SOAR_OK) r.status = st;
+      r.done_rows += p.rows;
+      if (r.done_rows == r.n) {
+        r.complete = true;
+        r.X.clear();
+        r.X.shrink_to_fit();
+      }
+    }
+    s.parts.clear();
+    ix->cv_done.notify_all();
+    lk.unlock();
+    const hipError_t e2 = hipEventSynchronize(s.ev_done);
+    lk.lock();
+    if (e2 != hipSuccess) ix->device_error = true;
+    else {
+      if (o.list[0] != 0) ix->list_error = true;
+      ix->chunks_used = o.list[1];
+    }
+    ix->chunks_reserved -= s.worst_chunks;
+    s.busy = false;
+    --ix->in_flight;
+    ix->cv_work.notify_all();
+    ix->cv_done.notify_all();
+  }
+}
+
+// Scheduler thread: launches queued rows into free slots as soon as both exist.
 void worker_loop(soar_index* ix) {
   std::unique_lock<std::mutex> lk(ix->mu);
   for (;;) {
-    bool progressed = false;
-    for (Slot& s : ix->slots)
-      if (!s.busy && try_launch(ix, s, lk)) progressed = true;
-    if (progressed) continue;
-    // wait for the oldest step in flight
-    Slot* oldest = nullptr;
-    for (Slot& s : ix->slots)
-      if (s.busy && (!oldest || s.seq < oldest->seq)) oldest = &s;
-    if (oldest) {
-      complete_slot(ix, *oldest, lk);
-      continue;
-    }
-    if (ix->shutdown && ix->queue.empty()) break;
     if (ix->device_error && !ix->queue.empty()) {
       for (auto& r : ix->queue) { r->status = SOAR_E_DEVICE; r->complete = true; }
       ix->queue.clear();
       ix->cv_done.notify_all();
-      continue;
     }
+    if (!ix->queue.empty() && ix->paused == 0 && !ix->device_error) {
+      Slot* free_slot = nullptr;
+      for (Slot& s : ix->slots)
+        if (!s.busy) { free_slot = &s; break; }
+      if (free_slot && try_launch(ix, *free_slot, lk)) continue;
+    }
+    if (ix->shutdown && ix->queue.empty()) break;
     ix->cv_work.wait(lk);
   }
+  // wake the slot waiters so they can leave once the last steps are done
+  for (Slot& s : ix->slots) s.cv.notify_all();
 }
 
 void free_index(soar_index* ix) {
   for (Slot& s : ix->slots) {
     if (s.g_compute) (void)hipGraphExecDestroy(s.g_compute);
     if (s.g_append) (void)hipGraphExecDestroy(s.g_append);
-    if (s.ev_done) (void)hipEventDestroy(s.ev_done);
+    if (s.ev_results) (void)hipEventDestroy(s.ev_results);
     if (s.ev_append) (void)hipEventDestroy(s.ev_append);
+    if (s.ev_done) (void)hipEventDestroy(s.ev_done);
     if (s.st) (void)hipStreamDestroy(s.st);
     if (s.h_in) (void)hipHostFree(s.h_in);
     if (s.h_out) (void)hipHostFree(s.h_out);
@@ -485,9 +585,11 @@ soar_status soar_index_arena_size(int32_t K, int32_t d, int32_t precision, int32
     return SOAR_E_UNSUPPORTED;
   const ArenaPlan P = plan_arena(K, d, precision, max_step_rows, 0);
   const int64_t chunks = (list_capacity_ids + LIST_CH - 1) / LIST_CH + 2 * (int64_t)K;
-  *bytes = P.fixed + (size_t)chunks * LIST_CH * 8;
+  *bytes = P.fixed + (size_t)chunks * kChunkBytes;
   return SOAR_OK;
 }
+
+size_t soar_index_chunk_bytes(void) { return kChunkBytes; }
 
 soar_status soar_index_create(const float* C, int32_t K, int32_t d, float lambda,
                               int32_t precision, void* arena, size_t arena_bytes,
@@ -501,7 +603,7 @@ soar_status soar_index_create(const float* C, int32_t K, int32_t d, float lambda
   if (precision == SOAR_FP32 ? fp32_padded_dim(d) < 0 : lowp_padded_dim(fmt, d) < 0)
     return SOAR_E_UNSUPPORTED;
   const ArenaPlan plan = plan_arena(K, d, precision, max_step_rows, arena_bytes);
-  if (plan.chunks < 1) return SOAR_E_NOMEM;
+  if (plan.chunks < 1 || plan.total > arena_bytes) return SOAR_E_NOMEM;
   soar_index* ix = new soar_index();
   ix->K = K; ix->d = d; ix->precision = precision; ix->cap = max_step_rows; ix->fmt = fmt;
   ix->lambda = lambda;
@@ -513,15 +615,20 @@ soar_status soar_index_create(const float* C, int32_t K, int32_t d, float lambda
   ix->crec = A + plan.crec;
   ListDev& L = ix->L;
   L.len = reinterpret_cast<int32_t*>(A + plan.L_len);
-  L.cursor = reinterpret_cast<int32_t*>(A + plan.L_cursor);
+  L.head = reinterpret_cast<int32_t*>(A + plan.L_head);
+  L.tail = reinterpret_cast<int32_t*>(A + plan.L_tail);
   L.cnt = reinterpret_cast<int32_t*>(A + plan.L_cnt);
-  L.dir = reinterpret_cast<int32_t*>(A + plan.L_dir);
+  L.cursor = reinterpret_cast<int32_t*>(A + plan.L_cursor);
+  L.olen = reinterpret_cast<int32_t*>(A + plan.L_olen);
+  L.otail = reinterpret_cast<int32_t*>(A + plan.L_otail);
+  L.first = reinterpret_cast<int32_t*>(A + plan.L_first);
   L.meta = reinterpret_cast<int32_t*>(A + plan.L_meta);
+  L.next = reinterpret_cast<int32_t*>(A + plan.next);
   L.pool = reinterpret_cast<int64_t*>(A + plan.pool);
   L.chunks = (int32_t)plan.chunks;
   L.K = K;
   hipError_t e = hipSuccess;
-  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+  for (int k = 0; k < kSlots && e == hipSuccess; ++k) {
     Slot& s = ix->slots[k];
     char* b = A + plan.slot[k];
     s.X = reinterpret_cast<float*>(b); b += al((size_t)max_step_rows * d * 4);
@@ -529,23 +636,25 @@ soar_status soar_index_create(const float* C, int32_t K, int32_t d, float lambda
     s.live = reinterpret_cast<int64_t*>(b); b += al(8);
     s.prim = reinterpret_cast<int32_t*>(b); b += al((size_t)max_step_rows * 4);
     s.spill = reinterpret_cast<int32_t*>(b); b += al((size_t)max_step_rows * 4);
+    s.status = reinterpret_cast<unsigned*>(b); b += al(64);
     s.ws = b;
     s.counters = reinterpret_cast<unsigned*>(b);
     e = hipStreamCreate(&s.st);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.ev_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.ev_results, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.ev_append, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.ev_done, hipEventDisableTiming);
     if (e == hipSuccess)
       e = hipHostMalloc(reinterpret_cast<void**>(&s.h_in),
                         8 + (size_t)max_step_rows * 8 + (size_t)max_step_rows * d * 4, 0);
     if (e == hipSuccess)
       e = hipHostMalloc(reinterpret_cast<void**>(&s.h_out),
-                        (size_t)max_step_rows * 8 + 16 + CNT_WORDS * 4, 0);
+                        (size_t)max_step_rows * 8 + CNT_WORDS * 4 + 16, 0);
   }
   hipStream_t st0 = ix->slots[0].st;
   // resident codebook, its norms (and maximum norm in every slot's counters), packed records
   if (e == hipSuccess)
     e = hipMemcpyAsync(ix->C, C, (size_t)K * d * 4, hipMemcpyDefault, st0);
-  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+  for (int k = 0; k < kSlots && e == hipSuccess; ++k)
     e = launch_prep_codebook(ix->C, K, d, ix->cnorm, ix->slots[k].counters, st0);
   if (e == hipSuccess && precision != SOAR_FP32)
     e = launch_lowp_pack_codebook(fmt, ix->C, K, d, ix->cnorm, ix->crec, ix->slots[0].counters, st0);
@@ -553,6 +662,8 @@ soar_status soar_index_create(const float* C, int32_t K, int32_t d, float lambda
     e = launch_pack_fp32(ix->C, K, d, ix->cnorm, ix->crec, st0);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(fill_i32, dim3((K + 255) / 256), dim3(256), 0, st0, L.len, (int64_t)K, 0);
+    hipLaunchKernelGGL(fill_i32, dim3((K + 255) / 256), dim3(256), 0, st0, L.head, (int64_t)K, -1);
+    hipLaunchKernelGGL(fill_i32, dim3((K + 255) / 256), dim3(256), 0, st0, L.tail, (int64_t)K, -1);
     hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st0, L.meta, (int64_t)16, 0);
     e = hipGetLastError();
   }
@@ -562,13 +673,14 @@ soar_status soar_index_create(const float* C, int32_t K, int32_t d, float lambda
   if (e == hipSuccess) e = hipStreamSynchronize(st0);
   if (e != hipSuccess) { free_index(ix); return SOAR_E_DEVICE; }
   if (cflags[CNT_NONFINITE]) { free_index(ix); return SOAR_E_NONFINITE; }
-  // graphs of the two slots
-  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+  // graphs of the slots
+  for (int k = 0; k < kSlots && e == hipSuccess; ++k) {
     Slot& s = ix->slots[k];
     e = capture(s.st, &s.g_compute, [&] { return enqueue_compute(ix, s); });
     if (e == hipSuccess) e = capture(s.st, &s.g_append, [&] { return enqueue_append(ix, s); });
   }
   if (e != hipSuccess) { free_index(ix); return SOAR_E_DEVICE; }
+  for (Slot& s : ix->slots) s.waiter = std::thread(slot_loop, ix, std::ref(s));
   ix->worker = std::thread(worker_loop, ix);
   *out = ix;
   return SOAR_OK;
@@ -577,7 +689,9 @@ soar_status soar_index_create(const float* C, int32_t K, int32_t d, float lambda
 soar_status soar_insert(soar_index* ix, const float* X_host, int64_t n, int64_t first_id,
                         uint64_t* ticket) {
   if (!ix || !X_host || !ticket || n < 1) return SOAR_E_INVAL;
-  if (2 * n > (int64_t)ix->L.chunks * LIST_CH) return SOAR_E_NOMEM;   // can never fit
+  if (worst_chunks(std::min<int64_t>(n, 1), ix->K) > ix->L.chunks ||
+      (2 * n + LIST_CH - 1) / LIST_CH > (int64_t)ix->L.chunks)
+    return SOAR_E_NOMEM;   // can never fit
   auto r = std::make_shared<Request>();
   r->n = n;
   r->first_id = first_id;
@@ -587,11 +701,13 @@ soar_status soar_insert(soar_index* ix, const float* X_host, int64_t n, int64_t 
   {
     std::lock_guard<std::mutex> g(ix->mu);
     if (ix->shutdown) return SOAR_E_SHUTDOWN;
+    if (ix->list_error) return SOAR_E_NOMEM;
     r->ticket = ix->next_ticket++;
     ix->tickets[r->ticket] = r;
     ix->queue.push_back(r);
+    ix->stats.requests += 1;
   }
-  ix->cv_work.notify_one();
+  ix->cv_work.notify_all();
   *ticket = r->ticket;
   return SOAR_OK;
 }
@@ -619,33 +735,50 @@ soar_status soar_index_list(soar_index* ix, int32_t part, int64_t* ids_host, int
   if (!ix || !len || part < 0 || part >= ix->K || cap < 0 || (cap > 0 && !ids_host))
     return SOAR_E_INVAL;
   std::unique_lock<std::mutex> lk(ix->mu);
-  // hold new steps and let the ones in flight finish
-  ix->paused = true;
+  // hold new steps and let the ones in flight (and their list appends) finish
+  ++ix->paused;
   ix->cv_done.wait(lk, [&] { return ix->in_flight == 0; });
   hipStream_t st = ix->slots[0].st;
-  int32_t n = 0;
-  std::vector<int32_t> dir;
-  hipError_t e = hipMemcpyAsync(&n, ix->L.len + part, 4, hipMemcpyDeviceToHost, st);
+  int32_t meta[3] = {0, -1, 0};
+  std::vector<int32_t> next;
+  hipError_t e = hipMemcpyAsync(&meta[0], ix->L.len + part, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&meta[1], ix->L.head + part, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&meta[2], ix->L.meta, 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e == hipSuccess && n > 0) {
-    const int nch = (n + LIST_CH - 1) / LIST_CH;
-    dir.resize(nch);
-    e = hipMemcpyAsync(dir.data(), ix->L.dir + (int64_t)part * LIST_MAXC, nch * 4,
-                       hipMemcpyDeviceToHost, st);
+  const int32_t n = meta[0];
+  const int64_t want = std::min<int64_t>(n, cap);
+  if (e == hipSuccess && want > 0) {
+    // the chunk links in use, then the chain from the head
+    next.resize(std::max(1, meta[2]));
+    e = hipMemcpyAsync(next.data(), ix->L.next, (size_t)meta[2] * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    const int64_t want = std::min<int64_t>(n, cap);
-    for (int c = 0; c < nch && e == hipSuccess && c * LIST_CH < want; ++c) {
-      const int64_t k = std::min<int64_t>(LIST_CH, want - (int64_t)c * LIST_CH);
-      e = hipMemcpyAsync(ids_host + (int64_t)c * LIST_CH, ix->L.pool + (int64_t)dir[c] * LIST_CH,
-                         k * 8, hipMemcpyDeviceToHost, st);
+    int32_t c = meta[1];
+    for (int64_t k = 0; e == hipSuccess && k * LIST_CH < want && c >= 0 && c < meta[2]; ++k) {
+      const int64_t m = std::min<int64_t>(LIST_CH, want - k * LIST_CH);
+      e = hipMemcpyAsync(ids_host + k * LIST_CH, ix->L.pool + (int64_t)c * LIST_CH, m * 8,
+                         hipMemcpyDeviceToHost, st);
+      c = next[c];
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
   }
-  ix->paused = false;
+  const bool bad = ix->list_error;
+  --ix->paused;
   lk.unlock();
-  ix->cv_work.notify_one();
+  ix->cv_work.notify_all();
   *len = n;
-  return e == hipSuccess ? SOAR_OK : SOAR_E_DEVICE;
+  if (e != hipSuccess) return SOAR_E_DEVICE;
+  return bad ? SOAR_E_NOMEM : SOAR_OK;
+}
+
+soar_status soar_index_get_stats(soar_index* ix, soar_index_stats* out) {
+  if (!ix || !out || out->struct_size < sizeof(soar_index_stats)) return SOAR_E_INVAL;
+  std::lock_guard<std::mutex> g(ix->mu);
+  const uint32_t sz = out->struct_size;
+  *out = ix->stats;
+  out->struct_size = sz;
+  out->chunks_used = ix->chunks_used;
+  out->chunks_total = ix->L.chunks;
+  return SOAR_OK;
 }
 
 void soar_index_destroy(soar_index* ix) {
@@ -656,6 +789,14 @@ void soar_index_destroy(soar_index* ix) {
   }
   ix->cv_work.notify_all();
   if (ix->worker.joinable()) ix->worker.join();
+  {
+    // the queue is empty now; wait for the steps in flight, then release the waiters
+    std::unique_lock<std::mutex> lk(ix->mu);
+    ix->cv_done.wait(lk, [&] { return ix->in_flight == 0; });
+    for (Slot& s : ix->slots) s.cv.notify_all();
+  }
+  for (Slot& s : ix->slots)
+    if (s.waiter.joinable()) s.waiter.join();
   free_index(ix);
 }
 

@@ -75,7 +75,8 @@ struct LowpLayout {
   float* xs;
   float* cs;
   float4* rowc;
-  int32_t* cand;
+  int32_t* cand_p;      // [n x topk] candidates of the primary sweep
+  int32_t* cand;        // [n x topk] candidates of the spill sweep
   void* Cp;             // codebook rows quantized like X (grouped spill form)
   float* cps;
   void* group;
@@ -95,6 +96,7 @@ LowpLayout layout_lowp(void* ws, int64_t n, int32_t d, int32_t K, int fmt, int t
   L.xs = c.take<float>((size_t)n);
   L.cs = c.take<float>((size_t)K);
   L.rowc = c.take<float4>((size_t)n);
+  L.cand_p = c.take<int32_t>((size_t)n * topk);
   L.cand = c.take<int32_t>((size_t)n * topk);
   L.Cp = c.take<char>((size_t)K * dp * eb);
   L.cps = c.take<float>((size_t)K);
@@ -106,8 +108,7 @@ LowpLayout layout_lowp(void* ws, int64_t n, int32_t d, int32_t K, int fmt, int t
 inline int lowp_fmt(const OptsView& o) {
   return o.precision == SOAR_BF16 ? soar::LOWP_BF16 : soar::LOWP_FP8;
 }
-// Default candidates per row: 8 of the 16 class minima.  (All 16 changed no FP8 answer at n=10M,
-// d=96, K=40,000: its misses are columns that lose to another column of their own class.)
+// Default candidates re-scored per row: the 8 smallest kept approximate values.
 inline int lowp_topk(const OptsView& o, int) { return o.topk > 0 ? o.topk : 8; }
 
 struct AssignLayout {
@@ -236,7 +237,7 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
   P.lam = lam;
   P.tie_rel = tie_threshold(d, lam, near_tie_rel);
   P.X = X; P.C = C; P.Xq = L.Xq; P.Cq = L.Cq; P.Rq = L.Rq;
-  P.xs = L.xs; P.cs = L.cs; P.cnorm = L.cnorm; P.rowc = L.rowc; P.cand = L.cand;
+  P.xs = L.xs; P.cs = L.cs; P.cnorm = L.cnorm; P.rowc = L.rowc; P.cand = L.cand_p;
   P.primary = primary; P.spill = spill_out; P.pdist = pdist; P.sloss = sloss;
   P.counters = L.counters; P.rowc_out = L.rowc;
   P.Rq_out = grouped && !grouped_residual_rows(fmt, lam) ? nullptr : L.Rq;
@@ -258,6 +259,7 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
   if (e == hipSuccess) e = mark(2);
   if (e == hipSuccess) e = launch_lowp_rescore(fmt, P, false, st);
   if (e == hipSuccess) e = mark(3);
+  P.cand = L.cand;
   if (grouped) {
     if (e == hipSuccess) e = launch_group_by_primary(primary, n, nullptr, K, GL, st);
     if (e == hipSuccess) e = mark(4);
@@ -396,6 +398,22 @@ soar_status soar_assign_workspace_size(int64_t n, int32_t d, int32_t K,
   *bytes = o.precision == SOAR_FP32
                ? soar::assign_workspace_bytes(n, d, K)
                : layout_lowp(nullptr, n, d, K, lowp_fmt(o), lowp_topk(o, d)).bytes;
+  return SOAR_OK;
+}
+
+soar_status soar_assign_candidates(int64_t n, int32_t d, int32_t K, const soar_assign_opts* opts,
+                                   size_t* primary_off, size_t* spill_off, int32_t* topk) {
+  OptsView o;
+  if (!primary_off || !spill_off || !topk || !read_opts(opts, &o)) return SOAR_E_INVAL;
+  const soar_status s = validate_assign(n, d, K, o);
+  if (s != SOAR_OK) return s;
+  if (o.precision == SOAR_FP32) return SOAR_E_UNSUPPORTED;
+  // the layout of a workspace placed at a stand-in address: only the offsets are used
+  char* base = reinterpret_cast<char*>(kAlign);
+  const LowpLayout L = layout_lowp(base, n, d, K, lowp_fmt(o), lowp_topk(o, d));
+  *primary_off = reinterpret_cast<char*>(L.cand_p) - base;
+  *spill_off = reinterpret_cast<char*>(L.cand) - base;
+  *topk = lowp_topk(o, d);
   return SOAR_OK;
 }
 

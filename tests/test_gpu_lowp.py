@@ -1,9 +1,10 @@
 """BF16 / FP8-e4m3 forms of the SOAR assignment against the FP64 oracle.
 
 These forms are approximations, so the parity bar is the one stated for them: the reported value
-at the chosen index is exact (FP32 re-score, 1e-5 relative), and the loss regret against the
-oracle's best has a mean of at most 1e-3 (BF16) on mixture data.  Index disagreement and regret
-are printed for every case.
+at the chosen index is exact (FP32 re-score, 1e-5 relative), the loss regret against the oracle's
+best has a mean of at most 1e-3, and the oracle's best is among the re-scored candidates for all
+but a few rows (candidate-set misses).  Index disagreement, regret and misses are printed for
+every case.
 """
 import numpy as np
 import pytest
@@ -25,9 +26,18 @@ def _t(a):
 
 
 def _run(X, C, lam, prec, topk=0, form="auto"):
+    """One assignment; the fifth element is the stats dict with the re-scored candidates of both
+    sweeps added ("cand_p", "cand_s": int32 [n, topk])."""
+    import torch
     soar = _soar()
-    p, s, dp, ls, st = soar.assign(_t(X), _t(C), lam, precision=prec, topk=topk, stats=True,
-                                   spill_form=form)
+    Xg, Cg = _t(X), _t(C)
+    n, d = X.shape
+    ws = torch.empty(soar.assign_workspace_size(n, d, len(C), lam, prec, topk), dtype=torch.uint8,
+                     device="cuda")
+    p, s, dp, ls, st = soar.assign(Xg, Cg, lam, precision=prec, topk=topk, stats=True,
+                                   spill_form=form, workspace=ws)
+    cp, cs = soar.assign_candidates(ws, n, d, len(C), lam, prec, topk)
+    st["cand_p"], st["cand_s"] = cp.cpu().numpy(), cs.cpu().numpy()
     return p.cpu().numpy(), s.cpu().numpy(), dp.cpu().numpy(), ls.cpu().numpy(), st
 
 
@@ -36,10 +46,16 @@ def _report(X, C, lam, res, tag):
     j = O.verify(X, C, lam, p, s, dp, ls)
     out = dict(primary_disagree=float((p != j["p_star"]).mean()),
                spill_disagree=float((s != j["s_star"]).mean()),
+               primary_outside_band=float((~j["primary_ok"]).mean()),
+               spill_outside_band=float((~j["spill_ok"]).mean()),
                primary_regret_mean=float(j["primary_regret"].mean()),
                primary_regret_p99=float(np.quantile(j["primary_regret"], 0.99)),
                spill_regret_mean=float(j["spill_regret"].mean()),
                spill_regret_p99=float(np.quantile(j["spill_regret"], 0.99)))
+    if "cand_p" in st:
+        # rows whose oracle best was not among the re-scored candidates
+        out["candidate_misses_primary"] = int((~(st["cand_p"] == j["p_star"][:, None]).any(1)).sum())
+        out["candidate_misses_spill"] = int((~(st["cand_s"] == j["s_star"][:, None]).any(1)).sum())
     print(tag, out, flush=True)
     worst = np.argsort(-j["spill_regret"])[:3]
     for i in worst:
@@ -67,8 +83,8 @@ def small():
 def test_small_workload(small, prec, lam, form):
     X, C = small
     r = _report(X, C, lam, _run(X, C, lam, prec, form=form), f"{prec} lam={lam} {form}")
-    bound = 1e-3 if prec == "bf16" else 1e-2
-    assert r["primary_regret_mean"] <= bound and r["spill_regret_mean"] <= bound
+    assert r["primary_regret_mean"] <= 1e-3 and r["spill_regret_mean"] <= 1e-3
+    assert r["candidate_misses_primary"] <= 60 and r["candidate_misses_spill"] <= 60   # of 20000
 
 
 @pytest.mark.parametrize("form", ["grouped", "direct"])
@@ -89,7 +105,7 @@ def test_fp8_d768_lognormal():
     for prec in ("fp8", "bf16"):
         for form in ("grouped", "direct"):
             r = _report(X, C, 1.0, _run(X, C, 1.0, prec, form=form), f"{prec} d768 {form}")
-            assert r["spill_regret_mean"] <= (1e-2 if prec == "fp8" else 1e-3)
+            assert r["primary_regret_mean"] <= 1e-3 and r["spill_regret_mean"] <= 1e-3
 
 
 @pytest.mark.parametrize("form", ["grouped", "direct"])
@@ -102,8 +118,7 @@ def test_wide_row_scales(prec, form):
     X = (X * np.exp2(rng.integers(-20, 21, size=(len(X), 1)))).astype(np.float32)
     C = (X[rng.choice(len(X), 300, replace=False)] * 0.97).astype(np.float32)
     r = _report(X, C, 1.0, _run(X, C, 1.0, prec, form=form), f"{prec} wide scales {form}")
-    bound = 1e-3 if prec == "bf16" else 1e-2
-    assert r["primary_regret_mean"] <= bound and r["spill_regret_mean"] <= bound
+    assert r["primary_regret_mean"] <= 1e-3 and r["spill_regret_mean"] <= 1e-3
 
 
 @pytest.mark.parametrize("form", ["grouped", "direct"])
@@ -125,22 +140,83 @@ def test_edge_shapes(prec, n, d, K, topk, form):
         assert j["primary_ok"].all() and j["spill_ok"].all()
 
 
+def _trained(wl):
+    """A full-size workload and the codebook bench.py trains for it on the GPU: k-means++ on the
+    workload's seeding subsample, then its Lloyd iterations over all rows."""
+    soar = _soar()
+    import torch
+    w = WORKLOADS[wl]
+    spec = w["spec"]
+    X = np.concatenate([gen_mixture(spec, k, min(spec.n, k + (1 << 20)))
+                        for k in range(0, spec.n, 1 << 20)])
+    Xg = _t(X)
+    C0, _ = soar.kmeanspp(_t(X[sample_rows(spec, w["seed_subsample"])]), w["K"], 0)
+    C, _, _ = soar.train_codebook(Xg, w["K"], w["iters"], C_init=C0)
+    torch.cuda.synchronize()
+    return X, Xg, C.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def config3():
+    return _trained("mix16384_n10m_d96")
+
+
+@pytest.fixture(scope="module")
+def config4():
+    return _trained("mix8192_n2m_d768_lognorm")
+
+
+def _full_size_check(X, Xg, C, lam, prec, rows):
+    import torch
+    soar = _soar()
+    n, d = X.shape
+    ws = torch.empty(soar.assign_workspace_size(n, d, len(C), lam, prec), dtype=torch.uint8,
+                     device="cuda")
+    p, s, dp, ls, st = soar.assign(Xg, _t(C), lam, precision=prec, stats=True, workspace=ws)
+    cp, cs = soar.assign_candidates(ws, n, d, len(C), lam, prec)
+    idx = np.sort(np.random.default_rng(7).choice(n, rows, replace=False))
+    it = torch.from_numpy(idx).cuda()
+    st = dict(st, cand_p=cp[it].cpu().numpy(), cand_s=cs[it].cpu().numpy())
+    r = _report(X[idx], C, lam, (p[it].cpu().numpy(), s[it].cpu().numpy(), dp[it].cpu().numpy(),
+                                 ls[it].cpu().numpy(), st), f"{prec} lam={lam} full size")
+    # the precision forms' bar: mean relative loss regret at most 1e-3, and the oracle's best is
+    # among the re-scored candidates for all but a few rows in ten thousand
+    assert r["primary_regret_mean"] <= 1e-3 and r["spill_regret_mean"] <= 1e-3
+    assert r["candidate_misses_primary"] <= max(2, rows // 500)
+    assert r["candidate_misses_spill"] <= max(2, rows // 500)
+    return r
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_full_size_config3_trained(config3, prec):
+    """n=10M, d=96, K=40,000 with the trained codebook, in the forms bench.py times (BF16 with the
+    grouped spill over residual rows, FP8 direct); the oracle checks 5000 sampled rows."""
+    X, Xg, C = config3
+    print(f"config3 trained {prec}", flush=True)
+    _full_size_check(X, Xg, C, 1.0, prec, 5000)
+
+
+@pytest.mark.parametrize("prec,lam", [("fp8", 0.5), ("fp8", 1.0), ("fp8", 1.5),
+                                      ("bf16", 0.5), ("bf16", 1.0), ("bf16", 1.5)])
+def test_full_size_config4_trained(config4, prec, lam):
+    """n=2M, d=768, K=10,000 (lognormal norms) with the trained codebook at every lambda of the
+    workload; the oracle checks 2000 sampled rows."""
+    X, Xg, C = config4
+    print(f"config4 trained {prec} lam={lam}", flush=True)
+    _full_size_check(X, Xg, C, lam, prec, 2000)
+
+
 @pytest.mark.parametrize("wl,prec", [("mix16384_n10m_d96", "bf16"),
                                      ("mix8192_n2m_d768_lognorm", "fp8")])
 def test_full_size_sampled(wl, prec):
-    """The large workloads at full size, in the launch forms the benchmark times (the grouped spill
-    over residual rows in both), with K sampled rows as the codebook as `bench.py --codebook
-    sample` takes it; the oracle checks 2000 sampled rows."""
+    """The large workloads at full size with K sampled rows as the codebook (as `bench.py
+    --codebook sample` takes it); the oracle checks 2000 sampled rows."""
     w = WORKLOADS[wl]
     spec = w["spec"]
     X = gen_mixture(spec)
     C = X[sample_rows(spec, w["K"])]
     print(f"full size {wl} {prec}", flush=True)
-    p, s, dp, ls, st = _run(X, C, 1.0, prec)
-    idx = np.sort(np.random.default_rng(7).choice(len(X), 2000, replace=False))
-    r = _report(X[idx], C, 1.0, (p[idx], s[idx], dp[idx], ls[idx], st), f"{prec} full {wl}")
-    bound = 1e-3 if prec == "bf16" else 1e-2
-    assert r["primary_regret_mean"] <= bound and r["spill_regret_mean"] <= bound
+    _full_size_check(X, _t(X), C, 1.0, prec, 2000)
 
 
 def test_deterministic(small):

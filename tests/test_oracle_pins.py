@@ -461,3 +461,55 @@ def test_verify_with_reference_equals_plain_verify():
     for k in ("primary_ok", "spill_ok", "primary_regret", "spill_regret", "s_star", "l_star"):
         assert np.array_equal(a[k], b[k]), k
     assert a["all_ok"] == b["all_ok"] and not a["all_ok"]
+
+
+# ---- query-side probing (Section 2.2 search over the spilled lists) ----
+
+def test_search_with_every_partition_is_brute_force_mips():
+    """Probing all K partitions scores every point: the result is the exact MIPS top-k."""
+    rng = np.random.default_rng(31)
+    X = rng.standard_normal((400, 6)).astype(np.float32)
+    C = rng.standard_normal((12, 6)).astype(np.float32)
+    Q = rng.standard_normal((25, 6)).astype(np.float32)
+    p, _, s, _ = O.assign(X, C, 1.0)
+    ids, scores, searched = O.search(Q, X, C, [p, s], len(C), 10)
+    assert np.array_equal(ids, O.mips_topk(Q, X, 10))
+    assert np.all(searched == 2 * len(X))          # every point through both of its lists
+    assert np.allclose(scores, np.take_along_axis(Q.astype(np.float64) @ X.T.astype(np.float64),
+                                                  ids, axis=1), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("t", [1, 2, 5])
+def test_search_recall_is_kmr(t):
+    """Every true neighbour in a probed list survives the exact re-rank, so the recall of the
+    search at depth t is the KMR curve of Eq. 1 at t (a neighbour counts if either of its
+    partitions ranks within t), and the points scored are the summed sizes of the probed lists:
+    two routes, one through the lists, one through the ranks."""
+    rng = np.random.default_rng(32 + t)
+    X = rng.standard_normal((600, 8)).astype(np.float32)
+    C = rng.standard_normal((30, 8)).astype(np.float32)
+    Q = rng.standard_normal((40, 8)).astype(np.float32)
+    p, _, s, _ = O.assign(X, C, 1.0)
+    gt = O.mips_topk(Q, X, 10)
+    for assign in ([p], [p, s]):
+        ids, _, searched = O.search(Q, X, C, assign, t, 10)
+        kmr, pts = O.kmr_curve(Q, X, C, assign, 10, [t], gt=gt)
+        recall = np.mean([len(set(a) & set(b)) / 10 for a, b in zip(ids, gt)])
+        assert abs(recall - kmr[0]) < 1e-12
+        assert abs(searched.mean() - pts[0]) < 1e-9
+
+
+def test_search_hand_example():
+    """Two partitions on a line; the query probes only the better one, and the spilled copy of
+    point 2 makes it reachable from there, listed once."""
+    C = np.array([[1.0, 0.0], [-1.0, 0.0]], np.float32)
+    X = np.array([[2.0, 0.0], [-2.0, 0.0], [0.1, 0.0], [-0.1, 0.0]], np.float32)
+    primary = np.array([0, 1, 0, 1])
+    spill = np.array([1, 0, 1, 0])
+    Q = np.array([[1.0, 0.0]], np.float32)
+    ids, scores, searched = O.search(Q, X, C, [primary], 1, 3)
+    assert ids.tolist() == [[0, 2, -1]] and searched.tolist() == [2]
+    ids, scores, searched = O.search(Q, X, C, [primary, spill], 1, 3)
+    # partition 0 now lists 0, 2 (primary) and 1, 3 (spilled): the best three by <q, x>
+    assert ids.tolist() == [[0, 2, 3]] and searched.tolist() == [4]
+    assert scores.tolist() == [[2.0, np.float32(0.1).item(), np.float32(-0.1).item()]]
