@@ -187,6 +187,42 @@ soar_status soar_train_codebook(const float* X, int64_t n, int32_t d, int32_t K,
                                 uint64_t seed, const float* C_init, float* C_out, int32_t* labels,
                                 double* inertia, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- Query-side probing over the inverted lists (Section 2.2 search; spilled copies, Section
+   3.5, count once) ---- */
+
+/* Bytes of workspace for soar_lists_build. */
+soar_status soar_lists_workspace_size(int64_t n, int32_t K, size_t* bytes);
+
+/*
+ * Inverted lists in CSR form from assignment arrays: partition j lists ids[offsets[j] ..
+ * offsets[j+1]) (device int64 offsets [K + 1], device int32 ids [n] or [2 n] with spill), every
+ * point under primary[i] and, if spill is non-null, also under spill[i].  The order of ids
+ * inside a list is not specified.  Indices outside [0, K): SOAR_E_INVAL (after the lists were
+ * written).  Blocking.
+ */
+soar_status soar_lists_build(const int32_t* primary, const int32_t* spill, int64_t n, int32_t K,
+                             int64_t* offsets, int32_t* ids, void* workspace, size_t ws_bytes,
+                             void* stream);
+
+/* Bytes of workspace for soar_search. */
+soar_status soar_search_workspace_size(int64_t nq, int32_t d, int32_t K, size_t* bytes);
+
+/*
+ * VQ search of nq queries Q [nq x d] (device FP32): per query the t partitions with the largest
+ * <q, c_j> (MIPS over the codebook C [K x d]; equal scores to the lower index) are probed, every
+ * point in their lists (offsets, ids from soar_lists_build over the dataset X [n x d]) is scored
+ * exactly by <q, x> and the k best distinct points (higher score, then lower id) are returned:
+ *   out_ids [nq x k] (device int32; -1 where fewer than k points were reached)
+ *   out_scores [nq x k] (device FP64: FP32 inputs, FP64 accumulation; -inf where empty)
+ *   searched [nq] (device int64, nullable): points scored, i.e. the summed sizes of the probed
+ *   lists, a spilled point counted once per list it was reached through.
+ * Requires 1 <= k <= 16, t >= 1 (t > K probes every partition), finite inputs.  Blocking.
+ */
+soar_status soar_search(const float* Q, int64_t nq, int32_t d, const float* C, int32_t K,
+                        const float* X, int64_t n, const int64_t* offsets, const int32_t* ids,
+                        int32_t t, int32_t k, int32_t* out_ids, double* out_scores,
+                        int64_t* searched, void* workspace, size_t ws_bytes, void* stream);
+
 /* ---- Serving: a resident codebook plus inverted lists (Section 2.2) fed by insert requests ---- */
 
 typedef struct soar_index soar_index;

@@ -80,6 +80,11 @@ _sig("soar_assign_noalloc", [_vp, _i64, _i32, _vp, _i32, ctypes.POINTER(AssignOp
 _sig("soar_assign_noalloc_limit", [], _sz)
 _sig("soar_assign_candidates", [_i64, _i32, _i32, ctypes.POINTER(AssignOpts), ctypes.POINTER(_sz),
                                 ctypes.POINTER(_sz), ctypes.POINTER(_i32)])
+_sig("soar_lists_workspace_size", [_i64, _i32, ctypes.POINTER(_sz)])
+_sig("soar_lists_build", [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp])
+_sig("soar_search_workspace_size", [_i64, _i32, _i32, ctypes.POINTER(_sz)])
+_sig("soar_search", [_vp, _i64, _i32, _vp, _i32, _vp, _i64, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp,
+                     _sz, _vp])
 _sig("soar_train_workspace_size", [_i64, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("soar_kmeanspp", [_vp, _i64, _i32, _i32, _u64, _vp, _vp, _vp, _sz, _vp])
 _sig("soar_lloyd_update", [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp])
@@ -108,6 +113,8 @@ EXPORTED = [n for n in ("soar_assign_workspace_size", "soar_assign", "soar_assig
                         "soar_kmeanspp", "soar_lloyd_update", "soar_train_codebook",
                         "soar_index_arena_size", "soar_index_create", "soar_insert", "soar_wait",
                         "soar_index_list", "soar_index_get_stats", "soar_index_chunk_bytes",
+                        "soar_lists_workspace_size", "soar_lists_build", "soar_search_workspace_size",
+                        "soar_search",
                         "soar_index_destroy", "soar_status_string") if hasattr(_lib, n)]
 
 
@@ -279,6 +286,44 @@ def train_codebook(X, K, iters, seed=0, C_init=None, stream=None):
                                     _ptr(labels), inertia, _ptr(ws), ws.numel(), _stream(stream)),
            "soar_train_codebook")
     return C, labels, list(inertia)
+
+
+def build_lists(primary, spill, K, stream=None):
+    """CSR inverted lists (offsets int64[K + 1], ids int32[n or 2 n]) of the assignments."""
+    if primary.dtype != torch.int32 or not primary.is_cuda:
+        raise TypeError("primary must be int32 on the GPU")
+    n = primary.numel()
+    dev = primary.device
+    offsets = torch.empty(K + 1, dtype=torch.int64, device=dev)
+    ids = torch.empty(n * (2 if spill is not None else 1), dtype=torch.int32, device=dev)
+    b = _sz()
+    _check(_lib.soar_lists_workspace_size(n, K, ctypes.byref(b)), "soar_lists_workspace_size")
+    ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=dev)
+    _check(_lib.soar_lists_build(_ptr(primary.contiguous()),
+                                 None if spill is None else _ptr(spill.contiguous()), n, K,
+                                 _ptr(offsets), _ptr(ids), _ptr(ws), ws.numel(), _stream(stream)),
+           "soar_lists_build")
+    return offsets, ids
+
+
+def search(Q, C, X, offsets, ids, t, k=10, stream=None, workspace=None):
+    """Probe the t best partitions per query and return the k best distinct points:
+    (ids int32[nq, k], scores float64[nq, k], searched int64[nq])."""
+    Q, C, X = _f32_matrix(Q, "Q"), _f32_matrix(C, "C"), _f32_matrix(X, "X")
+    nq, d = Q.shape
+    K, n = C.shape[0], X.shape[0]
+    dev = Q.device
+    out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    out_sc = torch.empty((nq, k), dtype=torch.float64, device=dev)
+    searched = torch.empty(nq, dtype=torch.int64, device=dev)
+    b = _sz()
+    _check(_lib.soar_search_workspace_size(nq, d, K, ctypes.byref(b)), "soar_search_workspace_size")
+    if workspace is None or workspace.numel() < b.value:
+        workspace = torch.empty(max(b.value, 256), dtype=torch.uint8, device=dev)
+    _check(_lib.soar_search(_ptr(Q), nq, d, _ptr(C), K, _ptr(X), n, _ptr(offsets), _ptr(ids),
+                            int(t), int(k), _ptr(out_ids), _ptr(out_sc), _ptr(searched),
+                            _ptr(workspace), workspace.numel(), _stream(stream)), "soar_search")
+    return out_ids, out_sc, searched
 
 
 class SoarIndex:

@@ -1,0 +1,92 @@
+"""GPU query-side probing (inverted lists, MIPS over the codebook, exact re-rank, one count per
+spilled point) against the oracle's search() on the same assignments."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import MixtureSpec, gen_mixture, gen_queries
+
+pytestmark = pytest.mark.gpu
+
+
+def _soar():
+    import paper_2404_00774_amd as soar
+    return soar
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _compare(got, want, Qn, Xn):
+    """ids equal wherever the oracle's scores are not tied within 1e-12 (relative); scores at the
+    GPU's ids equal their exact values; searched counts equal."""
+    gi, gs, gn = (a.cpu().numpy() for a in got)
+    wi, ws, wn = want
+    assert np.array_equal(gn, wn)
+    assert np.array_equal(gi < 0, wi < 0)
+    ok = gi >= 0
+    exact = np.einsum("ij,ikj->ik", Qn.astype(np.float64), Xn[np.where(ok, gi, 0)].astype(np.float64))
+    assert np.allclose(gs[ok], exact[ok], rtol=1e-12, atol=1e-12)
+    diff = (gi != wi) & ok
+    if diff.any():
+        # a different id only where the oracle's ranking has a near-tie at that place
+        assert np.allclose(gs[diff], ws[diff], rtol=1e-12, atol=1e-12), (gi[diff], wi[diff])
+
+
+@pytest.fixture(scope="module")
+def setup():
+    spec = MixtureSpec(20_000, 64, 64, 0.3, "unit", 17)
+    X = gen_mixture(spec)
+    Q = gen_queries(spec, 300)
+    C, _, _ = O.train_codebook(X, 200, 3, seed=2)
+    C = C.astype(np.float32)
+    soar = _soar()
+    p, s, _, _ = soar.assign(_t(X), _t(C), 1.0)
+    return X, Q, C, p, s
+
+
+def test_lists_are_the_assignments(setup):
+    X, Q, C, p, s = setup
+    soar = _soar()
+    off, ids = soar.build_lists(p, s, len(C))
+    off, ids = off.cpu().numpy(), ids.cpu().numpy()
+    want = O.partition_lists([p.cpu().numpy(), s.cpu().numpy()], len(C))
+    assert off[0] == 0 and off[-1] == 2 * len(X)
+    for j in range(len(C)):
+        assert np.array_equal(np.sort(ids[off[j]:off[j + 1]]), np.sort(want[j]))
+
+
+@pytest.mark.parametrize("t", [1, 3, 16, 200, 500])
+@pytest.mark.parametrize("spilled", [False, True])
+def test_search_matches_oracle(setup, t, spilled):
+    X, Q, C, p, s = setup
+    soar = _soar()
+    off, ids = soar.build_lists(p, s if spilled else None, len(C))
+    got = soar.search(_t(Q), _t(C), _t(X), off, ids, t, 10)
+    assign = [p.cpu().numpy()] + ([s.cpu().numpy()] if spilled else [])
+    want = O.search(Q, X, C, assign, t, 10)
+    print(f"t={t} spilled={spilled}: searched {float(want[2].mean()):.0f}", flush=True)
+    _compare(got, want, Q, X)
+
+
+def test_search_ties_and_short_lists():
+    """Duplicate centroids tie in the probe (the lower index goes first), a query that reaches
+    fewer than k points gets -1 places, and k = 16."""
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((90, 8)).astype(np.float32)
+    C = rng.standard_normal((12, 8)).astype(np.float32)
+    C[7] = C[3]                                   # exact tie in every query's probe
+    Q = rng.standard_normal((40, 8)).astype(np.float32)
+    p, _, s, _ = O.assign(X, C, 1.0)
+    soar = _soar()
+    import torch
+    pg = torch.from_numpy(p.astype(np.int32)).cuda()
+    sg = torch.from_numpy(s.astype(np.int32)).cuda()
+    off, ids = soar.build_lists(pg, sg, len(C))
+    for t in (1, 2, 5):
+        got = soar.search(_t(Q), _t(C), _t(X), off, ids, t, 16)
+        _compare(got, O.search(Q, X, C, [p, s], t, 16), Q, X)
+    with pytest.raises(soar.SoarError):
+        soar.search(_t(Q), _t(C), _t(X), off, ids, 2, 17)
