@@ -63,7 +63,7 @@ typedef enum soar_precision {
    the work differs).  The grouped form sorts the rows by primary and takes <c_pi, c_j> from the
    same MFMA stream as the rows (x, or with lambda >= 1/64 the residual r); the direct
    form runs a second stream over R = X - C[pi].  Without either bit the grouped form is taken when
-   n >= 8 K and, for FP32, d <= 256; for BF16, lambda >= 1/64; for FP8, d > 384.
+   n >= 8 K and, for BF16, lambda >= 1/64; for FP8, d > 384 (FP32: at every d).
    Both bits: SOAR_E_INVAL. */
 #define SOAR_SPILL_GROUPED 2u
 #define SOAR_SPILL_DIRECT 4u

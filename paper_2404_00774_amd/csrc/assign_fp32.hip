@@ -187,7 +187,7 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
   using R = F32Rec<DP, BN>;
   constexpr int KS = DP / 4, LDW = R::LDW, NB = BN / 16;
   static_assert(!GR || (SP && !CH), "Gram form: spill sweep of resident rows only");
-  static_assert(!GP || (SP && !CH && !GR), "grouped form: spill sweep of resident rows only");
+  static_assert(!GP || (SP && !GR), "grouped form: spill sweep only");
   const int lane = tid & 63, w = tid >> 6, q = lane >> 4, c16 = lane & 15;
   const int ntiles = (P.K + BN - 1) / BN;
   const int nsteps = ntiles * (CH ? nch : 1);
@@ -214,11 +214,16 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
       for (int v = 0; v < 4; ++v) gcur[b][v] = j < P.K ? grow[v][j] : 0.f;
     }
   }
-  // chunked rows: chunk 0 now, chunk u+1 during step u
-  float xn[CH ? KS : 1], cn[CH && SP ? KS : 1];
+  // chunked rows: chunk 0 now, chunk u+1 during step u.  In the grouped form stripe row 15 is
+  // the centroid c_pia, read from its record.
+  float xn[CH ? KS : 1], cn[CH && SP && !GP ? KS : 1];
+  auto load_x = [&](int ch, float(&v)[KS]) __attribute__((always_inline)) {
+    if (GP && c16 == 15) load_rec<KS>(rec_row<DP, BN>(recs, nch, pia, ch) + q * KS, v);
+    else load_seg<KS, VEC>(P.X, row, P.d, ch * DP + q * KS, ok, v);
+  };
   if constexpr (CH) {
-    load_seg<KS, VEC>(P.X, row, P.d, q * KS, ok, xa);
-    if constexpr (SP) {
+    load_x(0, xa);
+    if constexpr (SP && !GP) {
       if (pia >= 0) {
         load_rec<KS>(rec_row<DP, BN>(recs, nch, pia, 0) + q * KS, cn);
 #pragma unroll
@@ -237,8 +242,8 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
     if constexpr (CH) {
       if (u + 1 < nsteps) {
         const int cnx = (u + 1) % nch;
-        load_seg<KS, VEC>(P.X, row, P.d, cnx * DP + q * KS, ok, xn);
-        if constexpr (SP) {
+        load_x(cnx, xn);
+        if constexpr (SP && !GP) {
           if (pia >= 0) load_rec<KS>(rec_row<DP, BN>(recs, nch, pia, cnx) + q * KS, cn);
         }
       }
@@ -346,7 +351,7 @@ __device__ __forceinline__ void sweep(const AssignParams& P, char* ring, int nch
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
           xa[s] = xn[s];
-          if constexpr (SP) ra[s] = pia >= 0 ? xn[s] - cn[s] : 0.f;
+          if constexpr (SP && !GP) ra[s] = pia >= 0 ? xn[s] - cn[s] : 0.f;
         }
       }
     }
@@ -614,10 +619,14 @@ void assign_f32_kernel(AssignParams P) {
 // The error bound is the Gram form's.  Stripe rows past the stripe's size are zero and, like
 // row 15, produce no output.
 // ------------------------------------------------------------------------------------------------
-template <int DP, int BN, bool VEC>
+// Chunked rows (d > 256) run two waves per SIMD: two workgroups' rings fill the LDS.
+template <int DP, int BN, bool CH>
+constexpr int f32_grouped_waves() { return CH ? 2 : f32_kernel_waves<DP, BN, false, false>(); }
+
+template <int DP, int BN, bool CH, bool VEC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    f32_kernel_waves<DP, BN, false, false>(),
-    f32_kernel_waves<DP, BN, false, false>() > 2 ? f32_kernel_waves<DP, BN, false, false>() : 2)))
+    f32_grouped_waves<DP, BN, CH>(),
+    f32_grouped_waves<DP, BN, CH>() > 2 ? f32_grouped_waves<DP, BN, CH>() : 2)))
 void assign_f32_spill_grouped(AssignParams P) {
   using R = F32Rec<DP, BN>;
   constexpr int KS = DP / 4;
@@ -635,19 +644,22 @@ void assign_f32_spill_grouped(AssignParams P) {
   const int p = sd.x, nrows = sd.z;
   const bool data = c16 < nrows;
   const int64_t row = data ? (int64_t)P.perm[sd.y + c16] : 0;
+  const int nch = CH ? (P.d + DP - 1) / DP : 1;
 
+  // Row constants over all chunks; stripe row 15 is the centroid c_p.  c_p and R are not kept
+  // through the sweep (registers for a third wave per SIMD): the constants take r = x - c_p as
+  // they go, and R is formed again afterwards where the rows stay resident.
   float xa[KS], ra[KS];
-  if (c16 == 15) {
-    load_rec<KS>(rec_row<DP, BN>(P.Crec, 1, p, 0) + q * KS, xa);   // the centroid row c_p
-  } else {
-    load_seg<KS, VEC>(P.X, row, P.d, q * KS, data, xa);
-  }
-  // c_p and R are not kept through the sweep (registers for a third wave per SIMD): the row
-  // constants take r = x - c_p as it goes, and R is formed again afterwards
   float n0 = 0.f, n1 = 0.f, r0 = 0.f, r1 = 0.f, a0 = 0.f, a1 = 0.f;
-  {
+  for (int ch = 0; ch < nch; ++ch) {
     float cp[KS];
-    load_rec<KS>(rec_row<DP, BN>(P.Crec, 1, p, 0) + q * KS, cp);
+    load_rec<KS>(rec_row<DP, BN>(P.Crec, nch, p, ch) + q * KS, cp);
+    if (c16 == 15) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) xa[s] = cp[s];
+    } else {
+      load_seg<KS, VEC>(P.X, row, P.d, ch * DP + q * KS, data, xa);
+    }
 #pragma unroll
     for (int s = 0; s < KS; s += 2) {
       const float e0 = xa[s] - cp[s], e1 = xa[s + 1] - cp[s + 1];
@@ -682,19 +694,21 @@ void assign_f32_spill_grouped(AssignParams P) {
     b1[v] = b2[v] = b3[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
     lp[v] = S.lp[w][r]; av[v] = S.av[w][r]; pr[v] = p; xv[v] = S.xn[w][r]; Av[v] = S.A[w][r];
   }
-  sweep<DP, BN, false, VEC, true, false, true>(P, ring, 1, tid, row, data, p, xa, ra, lp, av, pr,
-                                               xv, Av, b1, i1, b2, i2, b3);
+  sweep<DP, BN, CH, VEC, true, false, true>(P, ring, nch, tid, row, data, p, xa, ra, lp, av, pr,
+                                            xv, Av, b1, i1, b2, i2, b3);
   publish_candidates(P, S, CS, w, lane, xv, Av, b1, i1, b2, i2, b3);
   __syncthreads();
   if (!data) return;
-  // R again: c_p from its record
-  load_rec<KS>(rec_row<DP, BN>(P.Crec, 1, p, 0) + q * KS, ra);
+  if constexpr (!CH) {
+    // R again: c_p from its record (chunked rows are read again chunk by chunk instead)
+    load_rec<KS>(rec_row<DP, BN>(P.Crec, 1, p, 0) + q * KS, ra);
 #pragma unroll
-  for (int s = 0; s < KS; ++s) ra[s] = xa[s] - ra[s];
+    for (int s = 0; s < KS; ++s) ra[s] = xa[s] - ra[s];
+  }
   bool ssat = S.sat[w][c16] != 0;
   int sj = -1;
   float sl = 0.f;
-  if (!ssat) decide<DP, BN, false, VEC, true>(P, S, CS, 1, w, c16, q, row, true, xa, ra, rr, p, sj, sl);
+  if (!ssat) decide<DP, BN, CH, VEC, true>(P, S, CS, nch, w, c16, q, row, true, xa, ra, rr, p, sj, sl);
   if (sj < 0 || sj >= P.K) ssat = true;
   if (q == 0) {
     if (ssat) {
@@ -1128,12 +1142,12 @@ hipError_t launch_reset_step_counters(unsigned* counters, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int DP, int BN>
+template <int DP, int BN, bool CH>
 static hipError_t launch_grouped_dp(const AssignParams& P, bool vec, hipStream_t st) {
   const int64_t ms = group_max_stripes(P.n, P.K);
   const dim3 grid((unsigned)((ms + 3) / 4)), block(256);
-  if (vec) hipLaunchKernelGGL((assign_f32_spill_grouped<DP, BN, true>), grid, block, 0, st, P);
-  else hipLaunchKernelGGL((assign_f32_spill_grouped<DP, BN, false>), grid, block, 0, st, P);
+  if (vec) hipLaunchKernelGGL((assign_f32_spill_grouped<DP, BN, CH, true>), grid, block, 0, st, P);
+  else hipLaunchKernelGGL((assign_f32_spill_grouped<DP, BN, CH, false>), grid, block, 0, st, P);
   return hipGetLastError();
 }
 
@@ -1143,7 +1157,7 @@ hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipSt
   const int dp = fp32_padded_dim(P.d);
   if (dp < 0 || !P.Crec) return hipErrorInvalidValue;
   auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], st); };
-  if (spill && grouped && dp <= 256) {
+  if (spill && grouped) {
     // primary pass, rows grouped by primary, grouped spill pass
 #define SOAR_X(DP, BN, CH) e = launch_dp<DP, BN, CH>(P, false, vec, st)
     switch (dp) { SOAR_F32_SHAPES(SOAR_X) }
@@ -1158,11 +1172,8 @@ hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipSt
     Q.perm = grouped->perm;
     Q.stripes = grouped->stripes;
     Q.nstripes = grouped->meta;
-    // the same shape table as the packing, so the kernel reads the records it was given (the
-    // chunked shapes do not occur here: dp <= 256)
-#define SOAR_X(DP, BN, CH)                                 \
-  if constexpr (!CH) e = launch_grouped_dp<DP, BN>(Q, vec, st); \
-  else e = hipErrorInvalidValue
+    // the same shape table as the packing, so the kernel reads the records it was given
+#define SOAR_X(DP, BN, CH) e = launch_grouped_dp<DP, BN, CH>(Q, vec, st)
     switch (dp) { SOAR_F32_SHAPES(SOAR_X) }
 #undef SOAR_X
   } else {

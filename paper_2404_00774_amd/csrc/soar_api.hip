@@ -181,7 +181,7 @@ soar_status run_assign_fp32(const float* X, int64_t n, int32_t d, const float* C
   P.band_s = band_coef_spill(d, lam);
   P.primary = primary; P.spill = spill_out; P.pdist = pdist; P.sloss = sloss;
   P.full_rows = L.full_rows;
-  const bool grouped = spill && d <= 256 &&
+  const bool grouped = spill &&
                        (spill_form == SOAR_SPILL_GROUPED ||
                         (spill_form == 0 && grouped_spill_pays(n, K)));
   const bool gram = spill && !grouped && L.gram != nullptr;

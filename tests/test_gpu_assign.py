@@ -91,15 +91,16 @@ def test_integer_ties_duplicates_and_zero_residual():
         assert res[4]["rows_full_scan"] > 0       # the duplicates force the exact full scan
 
 
+@pytest.mark.parametrize("form", ["grouped", "direct"])
 @pytest.mark.parametrize("lam", [0.5, 1.5])
-def test_heavy_tailed_norms_d768(lam):
-    """Unnormalised rows with lognormal norms at d = 768 (chunked rows, direct spill form): the
+def test_heavy_tailed_norms_d768(lam, form):
+    """Unnormalised rows with lognormal norms at d = 768 (chunked rows, both spill forms): the
     screening bounds are per centroid, so rows far from the largest centroids stay screened."""
     spec = MixtureSpec(6000, 768, 512, ("loguniform", 0.05, 0.5), ("lognormal", 0.5), 4)
     X = gen_mixture(spec)
     C = X[np.random.default_rng(2).choice(len(X), 5000, replace=False)] * 0.97
-    print(f"heavy tails d768 lam={lam}", flush=True)
-    res = _run(X, C, lam)
+    print(f"heavy tails d768 lam={lam} {form}", flush=True)
+    res = _run(X, C, lam, spill_form=form)
     _check(X, C, lam, res)
     assert res[4]["rows_full_scan"] <= len(X) // 100, res[4]
 
@@ -164,8 +165,8 @@ def test_full_size_sampled_parity():
 @pytest.mark.parametrize("wl", ["mix8192_n2m_d768_lognorm", "mix16384_n10m_d96"])
 def test_full_size_large_sampled(wl):
     """The large workloads in FP32 at full size: n = 2,000,000, d = 768, K = 10,000 with lognormal
-    norms (the direct two-stream form), and n = 10,000,000, d = 96, K = 40,000 (the grouped spill),
-    as the benchmark times them; the oracle checks 2000 sampled rows."""
+    norms (chunked rows), and n = 10,000,000, d = 96, K = 40,000, both with the grouped spill as
+    the benchmark times them; the oracle checks 2000 sampled rows."""
     w = WORKLOADS[wl]
     spec = w["spec"]
     X = gen_mixture(spec)
@@ -177,10 +178,11 @@ def test_full_size_large_sampled(wl):
     assert st["rows_full_scan"] < 0.02 * len(X)
 
 
-@pytest.mark.parametrize("d,K", [(96, 3000), (200, 1000), (256, 1500)])
+@pytest.mark.parametrize("d,K", [(96, 3000), (200, 1000), (256, 1500), (300, 1000), (768, 2000)])
 def test_grouped_at_scale_matches_direct(d, K):
     """n = 100,000 (well past the size where the grouped spill is chosen) for the wider whole-row
-    shapes: the grouped and direct forms agree row for row, and the oracle accepts a sample."""
+    shapes and for chunked rows (d = 300: a ragged last chunk; d = 768: six chunks): the grouped
+    and direct forms agree row for row, and the oracle accepts a sample."""
     n = 100_000
     X = gen_mixture(MixtureSpec(n, d, 512, 0.3, "unit", 5))
     rng = np.random.default_rng(d)
