@@ -310,6 +310,44 @@ def test_fast_equals_plain_bitwise(rnd_case):
             assert np.array_equal(u, v)
 
 
+def test_fast_equals_plain_small_config():
+    """The fast mode against the plain one at the small parity workload's size (n = 20,000,
+    d = 64, K = 256, a Lloyd-trained codebook), at every lambda the workload is run with."""
+    from synth.mixture import WORKLOADS, gen_mixture
+    w = WORKLOADS["mix64_n20k_d64"]
+    X = gen_mixture(w["spec"])
+    C, _, _ = O.train_codebook(X, w["K"], 3, seed=0)
+    for lam in (0.0, 0.5, 1.0, 1.5):
+        a = O.assign(X, C, lam, fast=False)
+        b = O.assign(X, C, lam, fast=True)
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+
+
+def test_fast_screen_under_cancellation():
+    """Rows and centroids near a common point far from the origin: the GEMM expansion loses about
+    1e-4 to cancellation while the distances differ by about 1e-6, so the expansion alone misranks
+    them.  The fast mode must still equal the plain one (its rounding margin keeps every row's
+    true arg-min among the directly evaluated candidates); a margin short of the expansion's error
+    would fail here."""
+    rng = np.random.default_rng(77)
+    n, d, K = 1500, 16, 50
+    base = np.zeros(d)
+    base[0] = 1.0e5
+    C = base + 1e-3 * rng.standard_normal((K, d))
+    X = base + 1e-3 * rng.standard_normal((n, d))
+    # the expansion alone does misrank here
+    Dh = (X * X).sum(1)[:, None] - 2.0 * X @ C.T + (C * C).sum(1)[None, :]
+    Dd = ((X[:, None, :] - C[None, :, :]) ** 2).sum(-1)
+    assert (Dh.argmin(1) != Dd.argmin(1)).mean() > 0.1
+    for lam in (0.0, 1.0):
+        a = O.assign(X, C, lam, fast=False)
+        b = O.assign(X, C, lam, fast=True)
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+    assert np.array_equal(O.assign(X, C, 0.0)[0], Dd.argmin(1))
+
+
 def test_input_validation():
     X = np.zeros((3, 2), np.float32)
     with pytest.raises(ValueError):
