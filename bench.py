@@ -196,10 +196,9 @@ def lambda_trend(X64, C64, outs):
     return {"mean_cos2_r_rspill": float(cos2.mean()), "mean_rspill_sq": float(ss.mean())}
 
 
-def recall_leg(O, Q, X, C, ts, full):
+def recall_leg(O, Q, X, C, ts, full, gt):
     """Recall@10 of top-t partition probing with and without the spilled assignment (Eq. 1)
-    against brute force."""
-    gt = O.mips_topk(Q, X, 10)
+    against brute force (gt: the oracle's exact MIPS top-10)."""
     rec = {"queries": int(len(Q)), "k": 10, "t": list(ts), "per_lambda": {}}
     for lam, (p, s_) in full.items():
         k0, n0 = O.kmr_curve(Q, X, C, [p], 10, ts, gt=gt)
@@ -209,6 +208,35 @@ def recall_leg(O, Q, X, C, ts, full):
             "points_searched_unspilled": [float(v) for v in n0],
             "points_searched_spilled": [float(v) for v in n1]}
     return rec
+
+
+def search_leg(soar, torch, Xg, Cg, Qg, assign, ts, gt, reps=3):
+    """Query-side probing on the GPU (soar_search over the lists built from the assignment):
+    per probe depth t, queries/s over the whole query set and recall@10 against brute force,
+    with the spilled lists and with the primary lists only."""
+    K = Cg.shape[0]
+    nq = Qg.shape[0]
+    out = {}
+    for name, lists in (("spilled", (assign[0], assign[1])), ("unspilled", (assign[0], None))):
+        p = torch.from_numpy(lists[0].astype(np.int32)).cuda()
+        s_ = None if lists[1] is None else torch.from_numpy(lists[1].astype(np.int32)).cuda()
+        off, ids = soar.build_lists(p, s_, K)
+        rows = []
+        for t in ts:
+            r = soar.search(Qg, Cg, Xg, off, ids, t, 10)     # warm-up (and the result)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                soar.search(Qg, Cg, Xg, off, ids, t, 10)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            got = r[0].cpu().numpy()
+            recall = float(np.mean([len(set(a) & set(b)) / 10.0 for a, b in zip(got, gt)]))
+            rows.append({"t": int(t), "queries_per_s": nq / dt, "ms": dt * 1e3, "recall_at_10": recall,
+                         "points_searched": float(r[2].double().mean().item())})
+        out[name] = rows
+        del off, ids
+    return out
 
 
 def time_form(soar, torch, Xg, Cg, lam, prec, steps, warmup, n, d, K, keep_candidates=False):
@@ -554,8 +582,17 @@ def main():
     print(f"[bench] oracle checks done in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
           flush=True)
     rec = None
+    search = None
     if Q is not None:
-        rec = recall_leg(O, Q, X, C, (1, 2, 4, 8, 16, 32, 64, 128), full)
+        ts = (1, 2, 4, 8, 16, 32, 64, 128)
+        print(f"[bench] recall@10 ground truth for {len(Q)} queries", file=sys.stderr, flush=True)
+        gt = O.mips_topk(Q, X, 10)
+        rec = recall_leg(O, Q, X, C, ts, full, gt)
+        Qg = torch.from_numpy(Q).to(dev)
+        search = {}
+        for lam, assign in full.items():
+            print(f"[bench] GPU search, lambda {lam}", file=sys.stderr, flush=True)
+            search[str(lam)] = search_leg(soar, torch, Xg, Cg, Qg, assign, ts, gt)
     cpu = None
     if not args.no_cpu_baseline and cpu_rows:
         print(f"[bench] CPU baseline: the oracle on {cpu_rows} rows", file=sys.stderr, flush=True)
@@ -578,6 +615,7 @@ def main():
         "lambda_sweep": {str(l): sweep[l] for l in lams[1:]},
         "lambda_trend": trend_out,
         "recall_at_10": rec,
+        "gpu_search": search,
         "train": {"kmeanspp_s": t_kpp, "kmeanspp_rows": int(sub if sub and sub < n else n),
                   "lloyd_s": t_lloyd, "inertia_first": inertia[0], "inertia_last": inertia[-1]},
     }
