@@ -13,6 +13,8 @@ differences, in the order the paper states the method:
   pi'(x) = argmin_{j != pi(x)} ||x - C_j||^2 + lambda * ||proj_r (x - C_j)||^2, and
   ||proj_r r'||^2 = <r, r'>^2 / ||r||^2;
 * indexing pipeline, Section 3.5: train VQ, primary, residual, spill;
+* further spilled assignments, Section 3.5.1: each adds one Theorem 3.1 penalty per earlier
+  residual (a reading: the paper gives no formula);
 * KMR curve, Eq. 1 (Section 2.2.1), with Rank as in Section 2.1.
 
 Readings where the paper is silent (each is listed with its reason in the design notes):
@@ -424,6 +426,162 @@ def verify(X, C, lam, gpu_primary, gpu_spill, gpu_pdist=None, gpu_sloss=None, fa
     out["all_ok"] = bool(prim_ok.all() and spill_ok.all()
                          and out.get("pdist_ok", np.ones(n, bool)).all()
                          and out.get("sloss_ok", np.ones(n, bool)).all())
+    return out
+
+
+# ----------------------------------------------------------------------------------------------
+# Further spilled assignments (Section 3.5.1).  The paper states only that each later assignment
+# weighs the score errors of all earlier ones.  Reading taken here: the m-th assignment adds one
+# Theorem 3.1 penalty per earlier residual,
+#     L_m(j) = ||x - c_j||^2 + lambda * sum_k <r_k, x - c_j>^2 / ||r_k||^2,  r_k = x - c_{pi_k},
+# minimised over the centroids not assigned yet.  With one earlier assignment (the primary) this
+# is the SOAR spill.
+# ----------------------------------------------------------------------------------------------
+
+def _prior_array(prior, n, K):
+    P = np.asarray(prior, dtype=np.int64)
+    if P.ndim == 1:
+        P = P[:, None]
+    if P.ndim != 2 or P.shape[0] != n or P.shape[1] < 1:
+        raise ValueError("prior must be [n x m] with m >= 1")
+    if P.shape[1] >= K:
+        raise ValueError("need more centroids than earlier assignments")
+    if ((P < 0) | (P >= K)).any():
+        raise ValueError("prior indices out of range")
+    srt = np.sort(P, axis=1)
+    if (srt[:, 1:] == srt[:, :-1]).any():
+        raise ValueError("a row's earlier assignments must be distinct")
+    return P
+
+
+def _further_loss(diff, R, rr, lam):
+    """||r'||^2 + lam * sum_k <r_k, r'>^2 / ||r_k||^2 with r' = diff [..., d] and the earlier
+    residuals R [..., m, d], rr [..., m] (terms with r_k = 0 dropped)."""
+    sq = _sqdist(diff)
+    pen = np.zeros_like(sq)
+    for k in range(R.shape[-2]):
+        proj = (diff * R[..., k, :]).sum(axis=-1)
+        rk = rr[..., k]
+        safe = np.where(rk > 0.0, rk, 1.0)
+        pen = pen + np.where(rk > 0.0, lam * (proj * proj) / safe, 0.0)
+    return sq + pen
+
+
+def further_losses(x, C, lam, prior):
+    """All K losses of one row given its earlier assignments (those included)."""
+    x, C = _f64(x), _f64(C)
+    P = np.asarray(prior, dtype=np.int64).reshape(-1)
+    R = x[None, :] - C[P]
+    rr = _sqdist(R)
+    return _further_loss(x[None, :] - C, R[None], rr[None], float(lam))
+
+
+def spill_further_plain(X, C, lam, prior):
+    """Next assignment of every row given its earlier ones prior [n x m]: the arg-min of the
+    further loss over the centroids not in the row's prior (lowest index on ties), and that loss,
+    all K losses by direct differences."""
+    lam = _check_lambda(lam)
+    X, C = _f64(X), _f64(C)
+    n, d = X.shape
+    K = C.shape[0]
+    P = _prior_array(prior, n, K)
+    m = P.shape[1]
+    out = np.empty(n, dtype=np.int64)
+    loss = np.empty(n, dtype=np.float64)
+    step = _chunk_rows(K, d, planes=2 + m)
+    for lo in range(0, n, step):
+        hi = min(n, lo + step)
+        rows = np.arange(hi - lo)
+        R = X[lo:hi, None, :] - C[P[lo:hi]]                      # [b, m, d]
+        rr = _sqdist(R)
+        L = _further_loss(X[lo:hi, None, :] - C[None, :, :], R[:, None, :, :], rr[:, None, :], lam)
+        for k in range(m):
+            L[rows, P[lo:hi, k]] = np.inf
+        out[lo:hi] = np.argmin(L, axis=1)
+        loss[lo:hi] = L[rows, out[lo:hi]]
+    return out, loss
+
+
+def spill_further_fast(X, C, lam, prior):
+    """Same result as ``spill_further_plain``; FP64 GEMMs screen with a rounding margin that grows
+    with the number of penalty terms, the direct-difference loss decides."""
+    lam = _check_lambda(lam)
+    X, C = _f64(X), _f64(C)
+    n, d = X.shape
+    K = C.shape[0]
+    P = _prior_array(prior, n, K)
+    m = P.shape[1]
+    cc = (C * C).sum(axis=1)
+    xx = (X * X).sum(axis=1)
+    bound = _screen_bound(X, C, 1.0 + 3.0 * m * lam)
+    out = np.empty(n, dtype=np.int64)
+    loss = np.empty(n, dtype=np.float64)
+    step = _chunk_rows(K, 1, planes=3 + m)
+    for lo in range(0, n, step):
+        hi = min(n, lo + step)
+        b = hi - lo
+        rows = np.arange(b)
+        Xb = X[lo:hi]
+        R = Xb[:, None, :] - C[P[lo:hi]]                          # [b, m, d]
+        rr = _sqdist(R)
+        Lh = xx[lo:hi, None] - 2.0 * (Xb @ C.T) + cc[None, :]
+        for k in range(m):
+            a = (R[:, k, :] * Xb).sum(axis=1)
+            E = a[:, None] - R[:, k, :] @ C.T
+            rk = rr[:, k]
+            Lh = Lh + np.where(rk[:, None] > 0, lam * E * E / np.where(rk > 0, rk, 1.0)[:, None],
+                               0.0)
+        for k in range(m):
+            Lh[rows, P[lo:hi, k]] = np.inf
+        thr = Lh.min(axis=1) + 2.0 * bound[lo:hi]
+        r_, c_ = np.nonzero(Lh <= thr[:, None])
+        vals = _further_loss(Xb[r_] - C[c_], R[r_], rr[r_], lam)
+        c, v = _pick_min(r_, c_, vals, b)
+        out[lo:hi], loss[lo:hi] = c, v
+    return out, loss
+
+
+def assign_multi(X, C, lam, M, fast=True):
+    """M assignments per row: the primary (Section 2.2), then M - 1 further assignments, each
+    given all earlier ones.  Returns ([n x M] indices, [n x M] distance / losses)."""
+    if M < 1:
+        raise ValueError("M >= 1")
+    prim = primary_fast if fast else primary_plain
+    nxt = spill_further_fast if fast else spill_further_plain
+    p, dp = prim(X, C)
+    A = [p]
+    V = [dp]
+    for _ in range(1, M):
+        j, v = nxt(X, C, lam, np.stack(A, axis=1))
+        A.append(j)
+        V.append(v)
+    return np.stack(A, axis=1), np.stack(V, axis=1)
+
+
+def verify_further(X, C, lam, prior, gpu_next, gpu_loss=None, band=1e-6, loss_tol=1e-5,
+                   fast=True):
+    """Check a GPU further assignment given the same earlier ones: accepted if equal to the
+    oracle's, or not among the earlier ones and its exact loss within ``band`` (relative) of the
+    best; a reported loss must lie within ``loss_tol`` (relative) of the exact loss at the GPU's
+    index."""
+    X, C = _f64(X), _f64(C)
+    n = X.shape[0]
+    K = C.shape[0]
+    P = _prior_array(prior, n, K)
+    g = np.asarray(gpu_next, dtype=np.int64)
+    valid = (g >= 0) & (g < K) & (g[:, None] != P).all(axis=1)
+    gc = np.clip(g, 0, K - 1)
+    nxt = spill_further_fast if fast else spill_further_plain
+    j_star, l_star = nxt(X, C, lam, P)
+    R = X[:, None, :] - C[P]
+    l_gpu = _further_loss(X - C[gc], R, _sqdist(R), float(lam))
+    tau = np.maximum(l_star, 1e-12)
+    ok = valid & ((g == j_star) | (l_gpu - l_star <= band * tau))
+    out = dict(ok=ok, regret=(l_gpu - l_star) / tau, mismatch=int((g != j_star).sum()),
+               j_star=j_star, l_star=l_star)
+    if gpu_loss is not None:
+        out["loss_ok"] = np.abs(np.asarray(gpu_loss, np.float64) - l_gpu) <= loss_tol * tau
+    out["all_ok"] = bool(ok.all() and out.get("loss_ok", np.ones(n, bool)).all())
     return out
 
 

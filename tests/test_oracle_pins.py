@@ -348,6 +348,109 @@ def test_fast_screen_under_cancellation():
     assert np.array_equal(O.assign(X, C, 0.0)[0], Dd.argmin(1))
 
 
+# ------------------------------------------------------------------------------------------------
+# Further spilled assignments (Section 3.5.1; the loss is the reading that adds one Theorem 3.1
+# penalty per earlier residual).
+# ------------------------------------------------------------------------------------------------
+def test_further_lambda_zero_is_mth_nearest():
+    """With lambda = 0 every penalty vanishes: the m-th assignment is the m-th nearest centroid
+    (stable order, so ties go to the lower index)."""
+    rng = np.random.default_rng(31)
+    X = rng.integers(-3, 4, size=(400, 5)).astype(np.float32)
+    C = rng.integers(-3, 4, size=(30, 5)).astype(np.float32)
+    D = ((X[:, None, :].astype(np.float64) - C[None].astype(np.float64)) ** 2).sum(-1)
+    order = np.argsort(D, axis=1, kind="stable")
+    for fast in (False, True):
+        A, V = O.assign_multi(X, C, 0.0, 4, fast=fast)
+        assert np.array_equal(A, order[:, :4])
+        assert np.array_equal(V, np.take_along_axis(D, order[:, :4], 1))
+
+
+def test_further_with_one_prior_is_the_soar_spill():
+    rng = np.random.default_rng(32)
+    X = rng.standard_normal((500, 12)).astype(np.float32)
+    C = rng.standard_normal((60, 12)).astype(np.float32)
+    p, _ = O.primary_plain(X, C)
+    for lam in (0.5, 1.0, 2.0):
+        s, ls = O.spill_plain(X, C, lam, p)
+        j, lj = O.spill_further_plain(X, C, lam, p[:, None])
+        assert np.array_equal(s, j) and np.array_equal(ls, lj)
+
+
+def test_further_orthogonal_priors_closed_form():
+    """x = 0 with earlier residuals r_0 = (1, 0, 0) and r_1 = (0, 2, 0), orthogonal.  A candidate
+    residual orthogonal to both is not penalised; one inside their span is penalised by all of
+    its length (the two projections add up to ||r'||^2), so its loss is (1 + lambda) ||r'||^2."""
+    x = np.zeros((1, 3), np.float32)
+    C = np.array([[-1, 0, 0], [0, -2, 0], [0, 0, -1.5], [-0.75, -0.5, 0], [-1.25, 0, 0],
+                  [-0.5, 0, -1.0]], np.float32)
+    for lam in (0.0, 0.25, 1.0, 3.0):
+        L = O.further_losses(x[0], C, lam, [0, 1])
+        assert L[2] == 2.25
+        assert L[3] == pytest.approx((1 + lam) * 13 / 16, rel=1e-15)
+        assert L[4] == pytest.approx((1 + lam) * 1.5625, rel=1e-15)
+        assert L[5] == pytest.approx(1.25 + lam * 0.25, rel=1e-15)     # only r_0 sees it
+        j, lj = O.spill_further_plain(x, C, lam, np.array([[0, 1]]))
+        want = min(range(2, 6), key=lambda k: (L[k], k))
+        assert j[0] == want and lj[0] == L[want]
+
+
+def _brute_further(x, C, lam, prior):
+    """Exact rationals; each projection formed as the vector (<r_k, r'>/<r_k, r_k>) r_k and then
+    squared."""
+    res = [[Fr(a) - Fr(b) for a, b in zip(x, C[k])] for k in prior]
+    rrs = [sum(v * v for v in r) for r in res]
+    losses = []
+    for c in C:
+        rp = [Fr(a) - Fr(b) for a, b in zip(x, c)]
+        total = sum(v * v for v in rp)
+        for r, rr in zip(res, rrs):
+            if rr != 0:
+                coef = sum(u * v for u, v in zip(r, rp)) / rr
+                total += lam * sum((coef * u) ** 2 for u in r)
+        losses.append(total)
+    j = min((k for k in range(len(C)) if k not in prior), key=lambda k: (losses[k], k))
+    return j, losses[j]
+
+
+@pytest.mark.parametrize("lam", [Fr(0), Fr(1, 2), Fr(1), Fr(5, 2)])
+def test_further_bruteforce_exact_rationals(lam):
+    rng = np.random.default_rng(33)
+    for trial in range(120):
+        m = int(rng.integers(1, 4))
+        K, d = int(rng.integers(m + 1, m + 5)), int(rng.integers(1, 4))
+        X = rng.integers(-2, 3, size=(3, d))
+        C = rng.integers(-2, 3, size=(K, d))
+        if trial % 4 == 0:
+            C[-1] = C[0]                              # duplicate centroid
+        P = np.stack([rng.permutation(K)[:m] for _ in range(3)])
+        if trial % 5 == 0:
+            X[0] = C[P[0, 0]]                         # an earlier residual of zero
+        j, l = O.spill_further_plain(X.astype(np.float32), C.astype(np.float32), float(lam), P)
+        for i in range(3):
+            bj, bl = _brute_further(X[i], C, lam, list(P[i]))
+            assert j[i] == bj, (trial, i)
+            assert l[i] == pytest.approx(float(bl), rel=1e-14, abs=1e-14)
+
+
+def test_further_symmetric_in_prior_order_and_fast_equals_plain():
+    rng = np.random.default_rng(34)
+    X = rng.standard_normal((800, 10)).astype(np.float32)
+    C = rng.standard_normal((90, 10)).astype(np.float32)
+    A, _ = O.assign_multi(X, C, 1.0, 3)
+    P = A[:, :3]
+    for lam in (0.5, 1.5):
+        j0, l0 = O.spill_further_plain(X, C, lam, P)
+        j1, l1 = O.spill_further_plain(X, C, lam, P[:, ::-1])
+        assert np.array_equal(j0, j1) and np.allclose(l0, l1, rtol=1e-14, atol=0)
+        jf, lf = O.spill_further_fast(X, C, lam, P)
+        assert np.array_equal(j0, jf) and np.array_equal(l0, lf)
+    with pytest.raises(ValueError):
+        O.spill_further_plain(X[:2], C, 1.0, np.array([[1, 1], [2, 3]]))
+    with pytest.raises(ValueError):
+        O.spill_further_plain(X[:1], C[:2], 1.0, np.array([[0, 1]]))
+
+
 def test_input_validation():
     X = np.zeros((3, 2), np.float32)
     with pytest.raises(ValueError):
