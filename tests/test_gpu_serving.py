@@ -118,6 +118,39 @@ def test_split_codebook_steps(prec):
     assert j["primary_regret"].mean() <= bound and j["spill_regret"].mean() <= bound
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_serving_codebook_50k_eight_splits(prec):
+    """The serving shape: K = 50,000 centroids at d = 128, so every sweep runs as 8 codebook
+    splits.  Requests of mixed sizes, the oracle's judgement of every row within the
+    low-precision bound, identical answers for a repeated request, and exact lists."""
+    soar = _soar()
+    X = gen_mixture(MixtureSpec(56_000, 128, 2048, 0.3, "unit", 13))
+    C = (X[:50_000] * 0.97).astype(np.float32)
+    Y = X[50_000:]
+    ix = soar.SoarIndex(_t(C), 1.0, precision=prec, max_step_rows=2048, list_capacity=50_000)
+    n, lo, tickets = len(Y), 0, []
+    for sz in (1, 15, 300, 2048, 1500, 2136):
+        tickets.append((ix.insert(Y[lo:lo + sz], lo), lo, sz))
+        lo += sz
+    assert lo == n
+    p, s = np.empty(n, np.int32), np.empty(n, np.int32)
+    for t, a, sz in tickets:
+        p[a:a + sz], s[a:a + sz] = ix.wait(t, timeout=120.0)
+    pa, sa = ix.wait(ix.insert(Y[:300], 100_000), timeout=60.0)
+    assert np.array_equal(pa, p[:300]) and np.array_equal(sa, s[:300])
+    got = sorted((int(i), k) for k in np.unique(np.concatenate([p, s])) for i in ix.list(int(k))
+                 if i < n)
+    want = sorted([(i, int(p[i])) for i in range(n)] + [(i, int(s[i])) for i in range(n)])
+    assert got == want
+    ix.close()
+    j = O.verify(Y, C, 1.0, p, s)
+    print(prec, "K=50000 serving: primary regret", float(j["primary_regret"].mean()),
+          "spill regret", float(j["spill_regret"].mean()), "index disagreement",
+          float((p != j["p_star"]).mean()), flush=True)
+    assert np.all(s != p) and np.all((p >= 0) & (p < len(C))) and np.all((s >= 0) & (s < len(C)))
+    assert j["primary_regret"].mean() <= 1e-3 and j["spill_regret"].mean() <= 1e-3
+
+
 def test_admission_waits_for_memory_and_rejects_too_large(data):
     soar = _soar()
     X, C = data
