@@ -147,6 +147,38 @@ size_t soar_assign_noalloc_limit(void);
 soar_status soar_assign_candidates(int64_t n, int32_t d, int32_t K, const soar_assign_opts* opts,
                                    size_t* primary_off, size_t* spill_off, int32_t* topk);
 
+/* ---- Further spilled assignments (Section 3.5.1) ---- */
+
+/* Bytes of device workspace soar_spill_further needs for these sizes. */
+soar_status soar_spill_further_workspace_size(int64_t n, int32_t d, int32_t K, int32_t m,
+                                              size_t* bytes);
+
+/*
+ * One more spilled assignment per row given its m earlier ones (Section 3.5.1 generalises the
+ * spill to further assignments without giving the loss; this library takes one Theorem 3.1
+ * penalty per earlier residual):
+ *   next_i = argmin over j not in prior_i of
+ *            ||x_i - c_j||^2 + lambda * sum_k <r_k, x_i - c_j>^2 / ||r_k||^2,
+ *   r_k = x_i - C[prior_i,k]  (a term with r_k = 0 is dropped; ties go to the lowest index).
+ * With m = 1 and the primary as prior this is soar_assign's FP32 spill; soar_assign followed by
+ * calls with m = 2, 3 gives up to four assignments per point.
+ *   X [n x d], C [K x d]    device float32 (4-byte aligned)
+ *   prior [n x m]           device int32, row-major; each row's entries distinct and in [0, K)
+ *                           (otherwise SOAR_E_INVAL, returned before any result is written)
+ *   m                       1..3; K > m
+ *   next [n]                device int32 output; next_loss [n] nullable device float32 output
+ *   workspace / ws_bytes    at least soar_spill_further_workspace_size bytes, 256-byte aligned
+ *   stats                   nullable; device_ms, rows_full_scan, rows_fp64 and mfma_flops
+ *                           (the algorithmic 2 n K d (1 + m)) are filled
+ * FP32 throughout, d <= 1024 (rows above 128 dimensions are processed in chunks of 64).  Accuracy
+ * as soar_assign's FP32 form: indices exact up to near-ties, reported losses within 1e-5
+ * relative.  Blocking: the call synchronises the stream (twice: after checking prior, at the end).
+ */
+soar_status soar_spill_further(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
+                               const int32_t* prior, int32_t m, float lambda, float near_tie_rel,
+                               int32_t* next, float* next_loss, void* workspace, size_t ws_bytes,
+                               void* stream, soar_stats* stats);
+
 /* Bytes of workspace for soar_kmeanspp / soar_lloyd_update / soar_train_codebook. */
 soar_status soar_train_workspace_size(int64_t n, int32_t d, int32_t K, size_t* bytes);
 

@@ -80,6 +80,9 @@ _sig("soar_assign_noalloc", [_vp, _i64, _i32, _vp, _i32, ctypes.POINTER(AssignOp
 _sig("soar_assign_noalloc_limit", [], _sz)
 _sig("soar_assign_candidates", [_i64, _i32, _i32, ctypes.POINTER(AssignOpts), ctypes.POINTER(_sz),
                                 ctypes.POINTER(_sz), ctypes.POINTER(_i32)])
+_sig("soar_spill_further_workspace_size", [_i64, _i32, _i32, _i32, ctypes.POINTER(_sz)])
+_sig("soar_spill_further", [_vp, _i64, _i32, _vp, _i32, _vp, _i32, _f32, _f32, _vp, _vp, _vp, _sz,
+                            _vp, ctypes.POINTER(Stats)])
 _sig("soar_lists_workspace_size", [_i64, _i32, ctypes.POINTER(_sz)])
 _sig("soar_lists_build", [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp])
 _sig("soar_search_workspace_size", [_i64, _i32, _i32, ctypes.POINTER(_sz)])
@@ -114,7 +117,8 @@ EXPORTED = [n for n in ("soar_assign_workspace_size", "soar_assign", "soar_assig
                         "soar_index_arena_size", "soar_index_create", "soar_insert", "soar_wait",
                         "soar_index_list", "soar_index_get_stats", "soar_index_chunk_bytes",
                         "soar_lists_workspace_size", "soar_lists_build", "soar_search_workspace_size",
-                        "soar_search",
+                        "soar_search", "soar_spill_further_workspace_size",
+                        "soar_spill_further",
                         "soar_index_destroy", "soar_status_string") if hasattr(_lib, n)]
 
 
@@ -230,6 +234,49 @@ def assign_noalloc(X, C, lam, precision="fp32", topk=0, near_tie_rel=0.0, stream
 
 def assign_noalloc_limit():
     return int(_lib.soar_assign_noalloc_limit())
+
+
+def spill_further(X, C, prior, lam, near_tie_rel=0.0, stream=None, stats=False):
+    """soar_spill_further: the next assignment of every row given its earlier ones
+    (prior int32[n, m] on the GPU, m = 1..3, distinct per row).  Returns (next int32[n],
+    loss float32[n]) and, with ``stats=True``, a dict of call statistics."""
+    X, C = _f32_matrix(X, "X"), _f32_matrix(C, "C")
+    n, d = X.shape
+    K = C.shape[0]
+    if C.shape[1] != d:
+        raise ValueError("X and C must have the same number of columns")
+    if not isinstance(prior, torch.Tensor) or prior.dtype != torch.int32 or not prior.is_cuda:
+        raise TypeError("prior must be an int32 tensor on the GPU")
+    P = prior.reshape(n, -1).contiguous()
+    m = P.shape[1]
+    b = _sz()
+    _check(_lib.soar_spill_further_workspace_size(n, d, K, m, ctypes.byref(b)),
+           "soar_spill_further_workspace_size")
+    ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=X.device)
+    nxt = torch.empty(n, dtype=torch.int32, device=X.device)
+    loss = torch.empty(n, dtype=torch.float32, device=X.device)
+    st = Stats()
+    st.struct_size = ctypes.sizeof(Stats)
+    _check(_lib.soar_spill_further(_ptr(X), n, d, _ptr(C), K, _ptr(P), m, float(lam),
+                                   float(near_tie_rel), _ptr(nxt), _ptr(loss), _ptr(ws),
+                                   ws.numel(), _stream(stream), ctypes.byref(st)),
+           "soar_spill_further")
+    return (nxt, loss, st.as_dict()) if stats else (nxt, loss)
+
+
+def assign_multi(X, C, lam, M, near_tie_rel=0.0, stream=None):
+    """M assignments per row (M = 1..4): the FP32 primary and spill of soar_assign, then M - 2
+    further assignments, each given all earlier ones.  Returns (int32[n, M], float32[n, M]):
+    indices, and the primary distance followed by each spill's loss."""
+    if not 1 <= M <= 4:
+        raise ValueError("M must be in 1..4")
+    p, s, dp, ls = assign(X, C, lam, near_tie_rel=near_tie_rel, stream=stream)
+    A, V = [p, s], [dp, ls]
+    for _ in range(2, M):
+        j, v = spill_further(X, C, torch.stack(A, dim=1), lam, near_tie_rel, stream)
+        A.append(j)
+        V.append(v)
+    return torch.stack(A[:M], dim=1), torch.stack(V[:M], dim=1)
 
 
 def train_workspace_size(n, d, K):

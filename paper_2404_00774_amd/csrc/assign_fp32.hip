@@ -914,6 +914,585 @@ __global__ __launch_bounds__(FS_THREADS) void full_scan_kernel(AssignParams P) {
 }
 
 // ------------------------------------------------------------------------------------------------
+// Further spilled assignments (Section 3.5.1).  Given NP earlier assignments of a row, the next
+// one minimises
+//     ||x - c_j||^2 + lambda * sum_k <r_k, x - c_j>^2 / ||r_k||^2,   r_k = x - c_{prior_k},
+// over the centroids not assigned yet (a term with r_k = 0 is dropped): one Theorem 3.1 penalty
+// per earlier residual; with NP = 1 and the primary it is the SOAR spill.  The work is the direct
+// spill form with NP residual streams: S = X C^T and T_k = R_k C^T on the matrix cores, the
+// screen of the spill with lambda NP (each penalty term's rounding error is bounded like the
+// spill's, so the bounds add up), the same candidate lists, FP32 re-scores by direct differences
+// and FP64 near-tie decisions, and an exact full scan for rows whose candidate set is not proven
+// complete.
+// ------------------------------------------------------------------------------------------------
+template <int NP>
+struct FurtherShared {
+  int pr[4][16][NP];    // earlier assignments of each row (-1: none)
+  float lp[4][16][NP];  // lambda / ||r_k||^2 (0 when r_k = 0)
+  float av[4][16][NP];  // <r_k, x>
+};
+
+template <int DP, int BN, bool CH, int NP>
+__device__ __forceinline__ void sweep_further(const AssignParams& P, char* ring, int nch, int tid,
+                                              int64_t row, bool ok, const int (&pk)[NP],
+                                              float (&xa)[DP / 4], float (&ra)[NP][DP / 4],
+                                              const float (&lp)[4][NP], const float (&av)[4][NP],
+                                              const int (&pr)[4][NP], const float (&xv)[4],
+                                              const float (&Av)[4], float (&b1)[4], int (&i1)[4],
+                                              float (&b2)[4], int (&i2)[4], float (&b3)[4]) {
+  using R = F32Rec<DP, BN>;
+  constexpr int KS = DP / 4, LDW = R::LDW, NB = BN / 16;
+  const int lane = tid & 63, w = tid >> 6, q = lane >> 4, c16 = lane & 15;
+  const int ntiles = (P.K + BN - 1) / BN;
+  const int nsteps = ntiles * (CH ? nch : 1);
+  const char* recs = P.Crec;
+  float kx[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) kx[v] = 2.f * xv[v];
+  // chunked rows: chunk 0 now, chunk u+1 during step u
+  float xn[CH ? KS : 1], cn[CH ? NP : 1][CH ? KS : 1];
+  if constexpr (CH) {
+    load_seg<KS, false>(P.X, row, P.d, q * KS, ok, xa);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      if (pk[k] >= 0) load_rec<KS>(rec_row<DP, BN>(recs, nch, pk[k], 0) + q * KS, cn[k]);
+#pragma unroll
+      for (int s = 0; s < KS; ++s) ra[k][s] = pk[k] >= 0 ? xa[s] - cn[k][s] : 0.f;
+    }
+  }
+  issue_record<R::BYTES, R::STAGE, R::NI, 2>(recs, ring, 0, w, lane);
+  v4f accS[NB], accT[NP][NB];
+  for (int u = 0; u < nsteps; ++u) {
+    const int ch = CH ? u % nch : 0, t = CH ? u / nch : u;
+    wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    if constexpr (CH) {
+      if (u + 1 < nsteps) {
+        const int cnx = (u + 1) % nch;
+        load_seg<KS, false>(P.X, row, P.d, cnx * DP + q * KS, ok, xn);
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+          if (pk[k] >= 0) load_rec<KS>(rec_row<DP, BN>(recs, nch, pk[k], cnx) + q * KS, cn[k]);
+      }
+    }
+    if (u + 1 < nsteps) issue_record<R::BYTES, R::STAGE, R::NI, 2>(recs, ring, u + 1, w, lane);
+    const float* sb = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE);
+    if (ch == 0) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        accS[b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < NP; ++k) accT[k][b] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < KS; s += 4) {
+      v4f bv[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        bv[b] = *reinterpret_cast<const v4f*>(sb + (b * 16 + c16) * LDW + q * KS + s);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          accS[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[s + e], bv[b][e], accS[b], 0, 0, 0);
+#pragma unroll
+          for (int k = 0; k < NP; ++k)
+            accT[k][b] =
+                __builtin_amdgcn_mfma_f32_16x16x4f32(ra[k][s + e], bv[b][e], accT[k][b], 0, 0, 0);
+        }
+      }
+    }
+    if (!CH || ch == nch - 1) {
+      const float* scn = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE + R::CN_OFF);
+      const float* ssn = reinterpret_cast<const float*>(ring + (u & 1) * R::STAGE + R::SN_OFF);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = t * BN + b * 16 + c16;
+        const float cnv = scn[b * 16 + c16];
+        const float snv = ssn[b * 16 + c16];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float val = fmaf(-2.f, accS[b][v], cnv);
+          bool masked = false;
+#pragma unroll
+          for (int k = 0; k < NP; ++k) {
+            // <r_k, c_j> - <r_k, x>
+            const float e = accT[k][b][v] - av[v][k];
+            val = fmaf(lp[v][k] * e, e, val);
+            masked = masked || j == pr[v][k];
+          }
+          if (masked) val = kInf;
+          // the lower end (shifted) and the (b1, i1) <= (b2, i2) <= b3 update of the spill sweep
+          const float lo = fmaf(-(Av[v] * (snv + kx[v])), snv, val);
+          const bool lt1 = lo < b1[v], lt2 = lo < b2[v];
+          b3[v] = __builtin_amdgcn_fmed3f(b2[v], lo, b3[v]);
+          const int t2 = __builtin_unpredictable(lt2) ? j : i2[v];
+          i2[v] = __builtin_unpredictable(lt1) ? i1[v] : t2;
+          b2[v] = __builtin_amdgcn_fmed3f(b1[v], lo, b2[v]);
+          i1[v] = __builtin_unpredictable(lt1) ? j : i1[v];
+          b1[v] = fminf(b1[v], lo);
+        }
+      }
+    }
+    if constexpr (CH) {
+      if (u + 1 < nsteps) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          xa[s] = xn[s];
+#pragma unroll
+          for (int k = 0; k < NP; ++k) ra[k][s] = pk[k] >= 0 ? xn[s] - cn[k][s] : 0.f;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// FP32 ||x - c_j||^2 and <r_k, x - c_j> over this lane's quarter of the dimensions; with CH the
+// rows' chunks are read again from X and the records of the earlier assignments.
+template <int DP, int BN, bool CH, int NP>
+__device__ __forceinline__ void direct32_further(const AssignParams& P, int nch, int64_t row,
+                                                 const int (&pk)[NP], int j, int q,
+                                                 const float (&xa)[DP / 4],
+                                                 const float (&ra)[NP][DP / 4], float& sq,
+                                                 float (&pj)[NP]) {
+  constexpr int KS = DP / 4;
+  float s0 = 0.f, s1 = 0.f, p0[NP], p1[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) p0[k] = p1[k] = 0.f;
+  for (int ch = 0; ch < (CH ? nch : 1); ++ch) {
+    float c[KS], xs[KS], e[KS];
+    load_rec<KS>(rec_row<DP, BN>(P.Crec, nch, j, ch) + q * KS, c);
+    if constexpr (CH) {
+      load_seg<KS, false>(P.X, row, P.d, ch * DP + q * KS, true, xs);
+    } else {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) xs[s] = xa[s];
+    }
+#pragma unroll
+    for (int s = 0; s < KS; s += 2) {
+      e[s] = xs[s] - c[s];
+      e[s + 1] = xs[s + 1] - c[s + 1];
+      s0 = fmaf(e[s], e[s], s0);
+      s1 = fmaf(e[s + 1], e[s + 1], s1);
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      float rs[KS];
+      if constexpr (CH) {
+        load_rec<KS>(rec_row<DP, BN>(P.Crec, nch, pk[k], ch) + q * KS, rs);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) rs[s] = xs[s] - rs[s];
+      } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) rs[s] = ra[k][s];
+      }
+#pragma unroll
+      for (int s = 0; s < KS; s += 2) {
+        p0[k] = fmaf(rs[s], e[s], p0[k]);
+        p1[k] = fmaf(rs[s + 1], e[s + 1], p1[k]);
+      }
+    }
+  }
+  sq = sum_quad_f(s0 + s1);
+#pragma unroll
+  for (int k = 0; k < NP; ++k) pj[k] = sum_quad_f(p0[k] + p1[k]);
+}
+
+// The same in FP64 with every residual formed exactly from its centroid (near-tie decisions
+// only); 4 values at a time in a rolled loop, which keeps this rare path's registers low.
+template <int DP, int BN, bool CH, int NP>
+__device__ __forceinline__ double direct64_further(const AssignParams& P, int nch, int64_t row,
+                                                   const int (&pk)[NP], int j, int q,
+                                                   const float (&xa)[DP / 4]) {
+  constexpr int KS = DP / 4;
+  double sq = 0.0, pj[NP], rr[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) pj[k] = rr[k] = 0.0;
+  for (int ch = 0; ch < (CH ? nch : 1); ++ch) {
+    const float* cj = rec_row<DP, BN>(P.Crec, nch, j, ch) + q * KS;
+    float xs[CH ? KS : 1];
+    if constexpr (CH) load_seg<KS, false>(P.X, row, P.d, ch * DP + q * KS, true, xs);
+#pragma unroll 1
+    for (int s0 = 0; s0 < KS; s0 += 4) {
+      float c[4], xg[4];
+      load_rec<4>(cj + s0, c);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        float xv = 0.f;
+#pragma unroll
+        for (int k = 0; k < KS; k += 4) xv = (k == s0) ? (CH ? xs[k + s] : xa[k + s]) : xv;
+        xg[s] = xv;
+      }
+      double e[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        e[s] = (double)xg[s] - (double)c[s];
+        sq = fma(e[s], e[s], sq);
+      }
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        float cp[4];
+        load_rec<4>(rec_row<DP, BN>(P.Crec, nch, pk[k], ch) + q * KS + s0, cp);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double r = (double)xg[s] - (double)cp[s];
+          pj[k] = fma(r, e[s], pj[k]);
+          rr[k] = fma(r, r, rr[k]);
+        }
+      }
+    }
+  }
+  // the penalty terms are summed first, then added to the distance: integer inputs then give
+  // the same FP64 value for every candidate whatever computes it, so exact ties break alike
+  double pen = 0.0;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const double p = sum_quad_d(pj[k]), r = sum_quad_d(rr[k]);
+    if (r > 0.0) pen += (double)P.lam * (p * p) / r;
+  }
+  return sum_quad_d(sq) + pen;
+}
+
+// Exact decision among a row's candidates (A layout), as for the spill.
+template <int DP, int BN, bool CH, int NP>
+__device__ __forceinline__ void decide_further(const AssignParams& P, RowShared& S, CandShared& CS,
+                                               int nch, int w, int c16, int q, int64_t row,
+                                               const int (&pk)[NP], const float (&xa)[DP / 4],
+                                               const float (&ra)[NP][DP / 4],
+                                               const float (&rr)[NP], int& best_j,
+                                               float& best_v) {
+  const int nc = S.nc[w][c16];
+  float best = kInf;
+  int bj = 0x7fffffff;
+  for (int k = 0; k < nc; ++k) {
+    const int j = CS.cand[w][c16][k];
+    float sq, pj[NP];
+    direct32_further<DP, BN, CH, NP>(P, nch, row, pk, j, q, xa, ra, sq, pj);
+    float val = sq;
+#pragma unroll
+    for (int m = 0; m < NP; ++m)
+      if (rr[m] > 0.f) val += P.lam * (pj[m] * pj[m]) / rr[m];
+    CS.cv[w][c16][k] = val;
+    if (val < best || (val == best && j < bj)) { best = val; bj = j; }
+  }
+  const float lim = best + best * P.tie_rel;
+  int ntie = 0;
+  for (int k = 0; k < nc; ++k) ntie += CS.cv[w][c16][k] <= lim;
+  if (ntie >= 2) {
+    double bd = __builtin_inf();
+    int bdj = 0x7fffffff;
+    for (int k = 0; k < nc; ++k) {
+      if (CS.cv[w][c16][k] <= lim) {
+        const int j = CS.cand[w][c16][k];
+        argmin_d(bd, bdj, direct64_further<DP, BN, CH, NP>(P, nch, row, pk, j, q, xa), j);
+      }
+    }
+    best = (float)bd;
+    bj = bdj;
+    if (q == 0) atomicAdd(&P.counters[CNT_FP64], 1u);
+  }
+  best_j = bj;
+  best_v = best;
+}
+
+// One pass over all K for 64 rows (one workgroup), as the FP32 spill pass.  Prior indices
+// outside [0, K) are not followed (the call has checked them and fails before any result is
+// used); such a row's result is left unspecified.
+template <int DP, int BN, bool CH, int NP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+void assign_f32_further(AssignParams P) {
+  using R = F32Rec<DP, BN>;
+  constexpr int KS = DP / 4;
+  static_assert(2 * R::STAGE >= (int)sizeof(CandShared), "candidate lists must fit in the ring");
+  __shared__ __attribute__((aligned(16)))
+  char lds[2 * R::STAGE + sizeof(RowShared) + sizeof(FurtherShared<NP>)];
+  char* ring = lds;
+  RowShared& S = *reinterpret_cast<RowShared*>(lds + 2 * R::STAGE);
+  FurtherShared<NP>& F =
+      *reinterpret_cast<FurtherShared<NP>*>(lds + 2 * R::STAGE + sizeof(RowShared));
+  CandShared& CS = *reinterpret_cast<CandShared*>(ring);
+
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, q = lane >> 4, c16 = lane & 15;
+  const int64_t n = P.n;
+  if ((int64_t)blockIdx.x * 64 >= n) return;   // whole block past the rows
+  const int64_t row = (int64_t)blockIdx.x * 64 + w * 16 + c16;  // A-layout row of this lane
+  const bool ok = row < n;
+  const int nch = CH ? (P.d + DP - 1) / DP : 1;
+  int pk[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int v = ok ? P.prior[row * NP + k] : -1;
+    pk[k] = (v >= 0 && v < P.K) ? v : -1;
+  }
+  // row constants over all chunks: ||x||, and per earlier assignment ||r_k||^2 and <r_k, x>
+  float xa[KS], ra[NP][KS];
+  float n0 = 0.f, n1 = 0.f, rq[NP], aq[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) rq[k] = aq[k] = 0.f;
+  bool fin = true;
+  for (int ch = 0; ch < nch; ++ch) {
+    load_seg<KS, false>(P.X, row, P.d, ch * DP + q * KS, ok, xa);
+#pragma unroll
+    for (int s = 0; s < KS; s += 4) {
+      fin = fin && all_finite4(v4f{xa[s], xa[s + 1], xa[s + 2], xa[s + 3]});
+      n0 = fmaf(xa[s], xa[s], n0); n1 = fmaf(xa[s + 1], xa[s + 1], n1);
+      n0 = fmaf(xa[s + 2], xa[s + 2], n0); n1 = fmaf(xa[s + 3], xa[s + 3], n1);
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      float cp[KS];
+      if (pk[k] >= 0) {
+        load_rec<KS>(rec_row<DP, BN>(P.Crec, nch, pk[k], ch) + q * KS, cp);
+      } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) cp[s] = xa[s];
+      }
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        ra[k][s] = xa[s] - cp[s];
+        rq[k] = fmaf(ra[k][s], ra[k][s], rq[k]);
+        aq[k] = fmaf(ra[k][s], xa[s], aq[k]);
+      }
+    }
+  }
+  if (!fin) atomicOr(&P.counters[CNT_NONFINITE], 1u);
+  const float xnorm = sqrtf(sum_quad_f(n0 + n1));
+  float rr[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    rr[k] = sum_quad_f(rq[k]);
+    aq[k] = sum_quad_f(aq[k]);
+  }
+  if (q == 0) {
+    S.xn[w][c16] = xnorm;
+    S.A[w][c16] = 0.5f * P.band_s;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      F.pr[w][c16][k] = pk[k];
+      F.lp[w][c16][k] = rr[k] > 0.f ? P.lam / rr[k] : 0.f;
+      F.av[w][c16][k] = aq[k];
+    }
+  }
+  __syncthreads();
+  float b1[4], b2[4], b3[4], xv[4], Av[4], lp[4][NP], av[4][NP];
+  int i1[4], i2[4], pr[4][NP];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = 4 * q + v;
+    b1[v] = b2[v] = b3[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
+    xv[v] = S.xn[w][r];
+    Av[v] = S.A[w][r];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      lp[v][k] = F.lp[w][r][k];
+      av[v][k] = F.av[w][r][k];
+      pr[v][k] = F.pr[w][r][k];
+    }
+  }
+  sweep_further<DP, BN, CH, NP>(P, ring, nch, tid, row, ok, pk, xa, ra, lp, av, pr, xv, Av, b1, i1,
+                                b2, i2, b3);
+  publish_candidates(P, S, CS, w, lane, xv, Av, b1, i1, b2, i2, b3);
+  __syncthreads();
+  if (!ok) return;
+  bool followed = true;                  // every earlier assignment in range
+#pragma unroll
+  for (int k = 0; k < NP; ++k) followed = followed && pk[k] >= 0;
+  bool sat = S.sat[w][c16] != 0;
+  int sj = -1;
+  float sl = 0.f;
+  if (!sat && followed)
+    decide_further<DP, BN, CH, NP>(P, S, CS, nch, w, c16, q, row, pk, xa, ra, rr, sj, sl);
+  if (sj < 0 || sj >= P.K) sat = true;
+  if (q == 0) {
+    if (sat) {
+      const unsigned slot = atomicAdd(&P.counters[CNT_FULLSCAN], 1u);
+      P.full_rows[slot] = (int32_t)row;
+    } else {
+      P.spill[row] = sj;
+      if (P.sloss) P.sloss[row] = sl;
+    }
+  }
+}
+
+// Exact full scan of the listed rows for the further assignment (one workgroup a row): x, the
+// residuals and the earlier centroids sit in LDS.
+template <int NP>
+__device__ __forceinline__ float fs_value32_further(const float* __restrict__ c, const float* sx,
+                                                    const float* sr, const float* rr, float lam,
+                                                    int d, int l) {
+  float sq0 = 0.f, sq1 = 0.f, p0[NP], p1[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) p0[m] = p1[m] = 0.f;
+  int k = l;
+  for (; k + 16 < d; k += 32) {
+    const float e0 = sx[k] - c[k], e1 = sx[k + 16] - c[k + 16];
+    sq0 = fmaf(e0, e0, sq0); sq1 = fmaf(e1, e1, sq1);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      p0[m] = fmaf(sr[m * d + k], e0, p0[m]);
+      p1[m] = fmaf(sr[m * d + k + 16], e1, p1[m]);
+    }
+  }
+  if (k < d) {
+    const float e0 = sx[k] - c[k];
+    sq0 = fmaf(e0, e0, sq0);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) p0[m] = fmaf(sr[m * d + k], e0, p0[m]);
+  }
+  float val = sum16_f(sq0 + sq1);
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    const float p = sum16_f(p0[m] + p1[m]);
+    if (rr[m] > 0.f) val += lam * (p * p) / rr[m];
+  }
+  return val;
+}
+
+template <int NP>
+__device__ __forceinline__ double fs_value64_further(const float* __restrict__ c, const float* sx,
+                                                     const float* scp, float lam, int d, int l) {
+  double sq = 0.0, pj[NP], rr[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) pj[m] = rr[m] = 0.0;
+  for (int k = l; k < d; k += 16) {
+    const double e = (double)sx[k] - (double)c[k];
+    sq = fma(e, e, sq);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      const double r = (double)sx[k] - (double)scp[m * d + k];
+      pj[m] = fma(r, e, pj[m]);
+      rr[m] = fma(r, r, rr[m]);
+    }
+  }
+  double pen = 0.0;                        // penalties first, as in direct64_further
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    const double p = sum16_d(pj[m]), r = sum16_d(rr[m]);
+    if (r > 0.0) pen += (double)lam * (p * p) / r;
+  }
+  return sum16_d(sq) + pen;
+}
+
+template <int NP>
+__global__ __launch_bounds__(FS_THREADS) void full_scan_further_kernel(AssignParams P) {
+  extern __shared__ float fs_smem[];
+  const int d = P.d, K = P.K, tid = threadIdx.x, lane = tid & 63;
+  float* sx = fs_smem;
+  float* sr = fs_smem + d;               // [NP x d] residuals
+  float* scp = fs_smem + (1 + NP) * d;   // [NP x d] earlier centroids
+  float* sv = K <= FS_LDS_K ? fs_smem + (1 + 2 * NP) * d : nullptr;
+  __shared__ float s_rr[NP];
+  __shared__ int s_pk[NP];
+  __shared__ float rv[FS_WAVES];
+  __shared__ int rj[FS_WAVES];
+  __shared__ double rd[FS_WAVES];
+  const unsigned count = P.counters[CNT_FULLSCAN];
+  const int l = tid & 15, g = tid >> 4;
+  for (unsigned e = blockIdx.x; e < count; e += gridDim.x) {
+    const int64_t row = P.full_rows[e];
+    if (tid < NP) {
+      const int v = P.prior[row * NP + tid];
+      s_pk[tid] = (v >= 0 && v < K) ? v : -1;
+    }
+    for (int k = tid; k < d; k += FS_THREADS) sx[k] = P.X[row * d + k];
+    __syncthreads();
+    bool valid = true;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) valid = valid && s_pk[m] >= 0;
+    if (!valid) {                         // not followed (the call reports SOAR_E_INVAL)
+      if (tid == 0) P.spill[row] = -1;
+      __syncthreads();
+      continue;
+    }
+#pragma unroll
+    for (int m = 0; m < NP; ++m)
+      for (int k = tid; k < d; k += FS_THREADS) {
+        const float c = P.C[(int64_t)s_pk[m] * d + k];
+        scp[m * d + k] = c;
+        sr[m * d + k] = sx[k] - c;
+      }
+    __syncthreads();
+    if (tid < 64) {
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        float a = 0.f;
+        for (int k = lane; k < d; k += 64) a = fmaf(sr[m * d + k], sr[m * d + k], a);
+        a = wave_sum_f(a);
+        if (tid == 0) s_rr[m] = a;
+      }
+    }
+    __syncthreads();
+    float rr[NP];
+    int pk[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) { rr[m] = s_rr[m]; pk[m] = s_pk[m]; }
+    auto skip = [&](int j) {
+      bool s = false;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) s = s || j == pk[m];
+      return s;
+    };
+    // FP32 direct values over all columns, then FP64 among the near-ties
+    float bv = kInf;
+    int bj = 0x7fffffff;
+    for (int j0 = g; j0 < K; j0 += FS_UNROLL * FS_GROUPS) {
+      float v[FS_UNROLL];
+#pragma unroll
+      for (int u = 0; u < FS_UNROLL; ++u) {
+        const int j = j0 + u * FS_GROUPS;
+        const int jj = j < K ? j : K - 1;
+        v[u] = fs_value32_further<NP>(P.C + (int64_t)jj * d, sx, sr, rr, P.lam, d, l);
+        if (j >= K || skip(j)) v[u] = kInf;
+      }
+#pragma unroll
+      for (int u = 0; u < FS_UNROLL; ++u) {
+        const int j = j0 + u * FS_GROUPS;
+        if (sv && j < K && l == 0) sv[j] = v[u];
+        if (v[u] < bv) { bv = v[u]; bj = j; }
+      }
+    }
+    wg_argmin<float>(bv, bj, rv, rj);
+    int out_j = -1;
+    float out_v = kInf;
+    if (bv < kInf) {
+      const float lim = bv + bv * P.tie_rel;
+      double dv = __builtin_inf();
+      int dj = 0x7fffffff;
+      for (int j = g; j < K; j += FS_GROUPS) {
+        if (skip(j)) continue;
+        const float* c = P.C + (int64_t)j * d;
+        const float v = sv ? sv[j] : fs_value32_further<NP>(c, sx, sr, rr, P.lam, d, l);
+        if (v <= lim) argmin_d(dv, dj, fs_value64_further<NP>(c, sx, scp, P.lam, d, l), j);
+      }
+      wg_argmin<double>(dv, dj, rd, rj);
+      out_j = dj < K ? dj : -1;
+      out_v = (float)dv;
+    }
+    if (tid == 0) {
+      P.spill[row] = out_j;
+      if (P.sloss) P.sloss[row] = out_v;
+      atomicAdd(&P.counters[CNT_FP64], 1u);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void check_priors_kernel(const int32_t* __restrict__ prior, int64_t n, int np, int K,
+                                    unsigned* counters) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool bad = false;
+  for (int a = 0; a < np; ++a) {
+    const int v = prior[i * np + a];
+    bad = bad || v < 0 || v >= K;
+    for (int b = 0; b < a; ++b) bad = bad || prior[i * np + b] == v;
+  }
+  if (bad) atomicOr(&counters[CNT_BADINPUT], 1u);
+}
+
+// ------------------------------------------------------------------------------------------------
 // Codebook preparation: ||c_j||^2, max ||c||^2 and the finiteness flag; counter reset.
 // ------------------------------------------------------------------------------------------------
 __global__ void reset_counters_kernel(unsigned* counters, int words) {
@@ -1192,6 +1771,82 @@ hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipSt
     hipLaunchKernelGGL(full_scan_kernel<true>, dim3(256), dim3(FS_THREADS), smem, st, P);
   else
     hipLaunchKernelGGL(full_scan_kernel<false>, dim3(256), dim3(FS_THREADS), smem, st, P);
+  return hipGetLastError();
+}
+
+// ---- further spilled assignments ----
+// Whole rows up to 128 dimensions; longer rows in chunks of 64, so that X and the NP residual
+// rows (and their next chunks) stay in registers.
+int fp32_further_padded_dim(int d) {
+  static const int dps[] = {16, 32, 48, 64, 96, 128};
+  for (int dp : dps)
+    if (d <= dp) return dp;
+  if (d <= kF32MaxD) return (d + 63) / 64 * 64;
+  return -1;
+}
+
+#define SOAR_F32F_SHAPES(X)            \
+  case 16: X(16, 64, false); break;   \
+  case 32: X(32, 64, false); break;   \
+  case 48: X(48, 64, false); break;   \
+  case 64: X(64, 64, false); break;   \
+  case 96: X(96, 32, false); break;   \
+  case 128: X(128, 32, false); break; \
+  default: X(64, 64, true); break;
+
+size_t fp32_further_codebook_bytes(int d, int K) {
+  const int dp = fp32_further_padded_dim(d);
+  if (dp < 0) return 0;
+#define SOAR_X(DP, BN, CH) return rec_bytes<DP, BN>(d, K)
+  switch (dp) { SOAR_F32F_SHAPES(SOAR_X) }
+#undef SOAR_X
+  return 0;
+}
+
+hipError_t launch_pack_fp32_further(const float* C, int K, int d, const float* cnorm, void* rec,
+                                    hipStream_t st) {
+  const int dp = fp32_further_padded_dim(d);
+  if (dp < 0) return hipErrorInvalidValue;
+#define SOAR_X(DP, BN, CH) return pack_dp<DP, BN>(C, K, d, cnorm, rec, st)
+  switch (dp) { SOAR_F32F_SHAPES(SOAR_X) }
+#undef SOAR_X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_check_priors(const int32_t* prior, int64_t n, int np, int K, unsigned* counters,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(check_priors_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     prior, n, np, K, counters);
+  return hipGetLastError();
+}
+
+template <int DP, int BN, bool CH>
+static hipError_t launch_further_dp(const AssignParams& P, int np, hipStream_t st) {
+  const dim3 grid((unsigned)((P.n + 63) / 64)), block(256);
+  switch (np) {
+    case 1: hipLaunchKernelGGL((assign_f32_further<DP, BN, CH, 1>), grid, block, 0, st, P); break;
+    case 2: hipLaunchKernelGGL((assign_f32_further<DP, BN, CH, 2>), grid, block, 0, st, P); break;
+    case 3: hipLaunchKernelGGL((assign_f32_further<DP, BN, CH, 3>), grid, block, 0, st, P); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_further_fp32(const AssignParams& P, int np, hipStream_t st) {
+  const int dp = fp32_further_padded_dim(P.d);
+  if (dp < 0 || !P.Crec || !P.prior || np < 1 || np > kFurtherMaxPrior) return hipErrorInvalidValue;
+  hipError_t e = hipSuccess;
+#define SOAR_X(DP, BN, CH) e = launch_further_dp<DP, BN, CH>(P, np, st)
+  switch (dp) { SOAR_F32F_SHAPES(SOAR_X) }
+#undef SOAR_X
+  if (e != hipSuccess) return e;
+  const size_t smem =
+      ((size_t)(1 + 2 * np) * P.d + (P.K <= FS_LDS_K ? (size_t)P.K : 0)) * sizeof(float);
+  switch (np) {
+    case 1: hipLaunchKernelGGL(full_scan_further_kernel<1>, dim3(256), dim3(FS_THREADS), smem, st, P); break;
+    case 2: hipLaunchKernelGGL(full_scan_further_kernel<2>, dim3(256), dim3(FS_THREADS), smem, st, P); break;
+    default: hipLaunchKernelGGL(full_scan_further_kernel<3>, dim3(256), dim3(FS_THREADS), smem, st, P); break;
+  }
   return hipGetLastError();
 }
 

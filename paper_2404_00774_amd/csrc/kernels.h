@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "common.h"
+
 namespace soar {
 
 struct GroupLayout;
@@ -36,6 +38,8 @@ struct AssignParams {
   float* sloss;
   int32_t* full_rows;   // [n] rows handed to the exact full scan
   const int64_t* live_n = nullptr;   // device row count <= n (serving steps), or null
+  // further spilled assignments: [n x np] earlier assignments per row (row-major)
+  const int32_t* prior = nullptr;
 };
 
 // Padded row length of the FP32 path (-1: unsupported); rows above 256 are processed in chunks.
@@ -72,6 +76,25 @@ hipError_t launch_async_clear(unsigned* counters, hipStream_t st);
 // rows by primary into G, grouped spill pass.
 hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipStream_t st,
                               hipEvent_t* ev = nullptr, const GroupLayout* grouped = nullptr);
+
+// ---- further spilled assignments (the next assignment given np = 1..3 earlier ones) ----
+constexpr int kFurtherMaxPrior = 3;
+// Counter word set when an earlier assignment is out of range or repeated within its row (one of
+// the words every call clears, unused by the other kernels).
+constexpr int CNT_BADINPUT = 4;
+static_assert(CNT_BADINPUT > CNT_CMAX2 && CNT_BADINPUT < CNT_WORDS, "a per-call counter word");
+// Padded row length of the further-assignment sweep (-1: unsupported); rows above 128 go in
+// chunks of 64 (the residual rows of every earlier assignment are held beside X).
+int fp32_further_padded_dim(int d);
+size_t fp32_further_codebook_bytes(int d, int K);
+hipError_t launch_pack_fp32_further(const float* C, int K, int d, const float* cnorm, void* rec,
+                                    hipStream_t st);
+// Sets CNT_BADINPUT when a row's earlier assignments leave [0, K) or repeat.
+hipError_t launch_check_priors(const int32_t* prior, int64_t n, int np, int K, unsigned* counters,
+                               hipStream_t st);
+// Sweep, candidate decision and exact full scan of the rows whose candidates were not proven
+// complete; writes P.spill (the next assignment) and P.sloss.
+hipError_t launch_further_fp32(const AssignParams& P, int np, hipStream_t st);
 
 // ---- grouping rows by primary (grouped form of the spill sweep) ----
 constexpr int GROUP_ROWS = 15;   // data rows per 16-row MFMA stripe; the 16th row is the centroid

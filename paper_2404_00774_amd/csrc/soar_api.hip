@@ -134,6 +134,34 @@ AssignLayout layout_assign(void* ws, int64_t n, int32_t d, int32_t K) {
   return L;
 }
 
+struct FurtherLayout {
+  unsigned* counters;
+  float* cnorm;
+  char* crec;
+  int32_t* full_rows;
+  size_t bytes;
+};
+
+FurtherLayout layout_further(void* ws, int64_t n, int32_t d, int32_t K) {
+  Carver c(ws);
+  FurtherLayout L;
+  L.counters = c.take<unsigned>(soar::CNT_ALLOC_WORDS);
+  L.cnorm = c.take<float>((size_t)K);
+  L.crec = c.take<char>(soar::fp32_further_codebook_bytes(d, K));
+  L.full_rows = c.take<int32_t>((size_t)n);
+  L.bytes = c.off;
+  return L;
+}
+
+soar_status validate_further(int64_t n, int32_t d, int32_t K, int32_t m, float lambda,
+                             float near_tie_rel) {
+  if (n < 1 || n > INT32_MAX || d < 1 || m < 1 || m > soar::kFurtherMaxPrior || K <= m)
+    return SOAR_E_INVAL;
+  if (!std::isfinite(lambda) || lambda < 0.f) return SOAR_E_INVAL;
+  if (!(near_tie_rel >= 0.f) || !std::isfinite(near_tie_rel)) return SOAR_E_INVAL;
+  return soar::fp32_further_padded_dim(d) < 0 ? SOAR_E_UNSUPPORTED : SOAR_OK;
+}
+
 }  // namespace
 
 namespace soar {
@@ -415,6 +443,80 @@ soar_status soar_assign_candidates(int64_t n, int32_t d, int32_t K, const soar_a
   *spill_off = reinterpret_cast<char*>(L.cand) - base;
   *topk = lowp_topk(o, d);
   return SOAR_OK;
+}
+
+soar_status soar_spill_further_workspace_size(int64_t n, int32_t d, int32_t K, int32_t m,
+                                             size_t* bytes) {
+  if (!bytes) return SOAR_E_INVAL;
+  const soar_status s = validate_further(n, d, K, m, 0.f, 0.f);
+  if (s != SOAR_OK) return s;
+  *bytes = layout_further(nullptr, n, d, K).bytes;
+  return SOAR_OK;
+}
+
+soar_status soar_spill_further(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
+                               const int32_t* prior, int32_t m, float lambda, float near_tie_rel,
+                               int32_t* next, float* next_loss, void* workspace, size_t ws_bytes,
+                               void* stream, soar_stats* stats) {
+  soar_status s = validate_further(n, d, K, m, lambda, near_tie_rel);
+  if (s != SOAR_OK) return s;
+  if (!X || !C || !prior || !next || !aligned(X, 4) || !aligned(C, 4) || !aligned(prior, 4))
+    return SOAR_E_INVAL;
+  const FurtherLayout L = layout_further(workspace, n, d, K);
+  if (!workspace || !aligned(workspace, kAlign) || ws_bytes < L.bytes) return SOAR_E_INVAL;
+  if (stats && stats->struct_size < sizeof(soar_stats)) return SOAR_E_INVAL;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t ev[2] = {};
+  auto destroy = [&]() {
+    for (hipEvent_t& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  };
+  if (stats)
+    for (hipEvent_t& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) { destroy(); return SOAR_E_DEVICE; }
+  // the penalty has m terms, each bounded like the spill's: the bands of lambda m
+  const float lam_m = lambda * (float)m;
+  AssignParams P;
+  P.X = X; P.n = n; P.d = d; P.C = C; P.K = K; P.Crec = L.crec;
+  P.cnorm = L.cnorm; P.counters = L.counters;
+  P.lam = lambda;
+  P.tie_rel = soar::tie_threshold(d, lam_m, near_tie_rel);
+  P.band_p = soar::band_coef_primary(d);
+  P.band_s = soar::band_coef_spill(d, lam_m);
+  P.primary = nullptr; P.spill = next; P.pdist = nullptr; P.sloss = next_loss;
+  P.full_rows = L.full_rows;
+  P.prior = prior;
+  unsigned cnt[soar::CNT_WORDS] = {0};
+  // the earlier assignments are checked before any kernel follows them
+  hipError_t e = ev[0] ? hipEventRecord(ev[0], st) : hipSuccess;
+  if (e == hipSuccess) e = soar::launch_prep_codebook(C, K, d, L.cnorm, L.counters, st);
+  if (e == hipSuccess) e = soar::launch_check_priors(prior, n, m, K, L.counters, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(cnt, L.counters, sizeof(cnt), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) { destroy(); return SOAR_E_DEVICE; }
+  if (cnt[soar::CNT_BADINPUT]) { destroy(); return SOAR_E_INVAL; }
+  e = soar::launch_pack_fp32_further(C, K, d, L.cnorm, L.crec, st);
+  if (e == hipSuccess) e = soar::launch_further_fp32(P, m, st);
+  if (e == hipSuccess && ev[1]) e = hipEventRecord(ev[1], st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(cnt, L.counters, sizeof(cnt), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  s = dev_err(e);
+  if (s == SOAR_OK && stats) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+    stats->device_ms = ms;
+    stats->assign_kernel_ms = ms;
+    stats->rows_full_scan = cnt[soar::CNT_FULLSCAN];
+    stats->rows_fp64 = cnt[soar::CNT_FP64];
+    stats->mfma_flops = 2.0 * (double)n * (double)K * (double)d * (double)(1 + m);
+    for (int k = 0; k < 6; ++k) stats->phase_ms[k] = 0.f;
+    stats->phase_ms[4] = ms;
+  }
+  destroy();
+  if (s == SOAR_OK && cnt[soar::CNT_NONFINITE]) s = SOAR_E_NONFINITE;
+  return s;
 }
 
 soar_status soar_assign(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
