@@ -9,8 +9,8 @@
 //   rerank  one workgroup per query walks the t probed lists; every candidate gets its exact
 //           <q, x> (FP64 accumulation, one fixed order, so a point reached through two lists gets
 //           the same value twice); each thread keeps its k best (score, then id) without
-//           repeats, and a bitonic sort of the workgroup's lists in LDS yields the k best
-//           distinct ids.
+//           repeats, and k rounds of a workgroup arg-max over the threads' lists yield the k
+//           best distinct ids.
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
@@ -90,23 +90,56 @@ __global__ void zero_i64_kernel(int64_t* p, int64_t count) {
 }
 
 // <q, c_j> in FP64 for the queries of a chunk: keys[(q - q0) * K + j], vals[...] = j, and the
-// segment bounds of the sort.
-__global__ void probe_scores_kernel(const float* __restrict__ Q, int64_t q0, int nqc, int d,
-                                    const float* __restrict__ C, int K, double* keys,
-                                    int32_t* vals, int* seg) {
-  const int qi = blockIdx.y;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j == 0) {
-    seg[qi] = qi * K;
-    if (qi == nqc - 1) seg[nqc] = nqc * K;
+// segment bounds of the sort.  A workgroup takes kPQ queries x kPC centroids; both go through LDS
+// kPD dimensions at a time in whole-row coalesced loads, and every (query, centroid) pair is
+// accumulated by one thread in dimension order: the sequential FP64 sum of the definition.
+constexpr int kPQ = 16, kPC = 64, kPD = 64;
+
+__global__ __launch_bounds__(256) void probe_scores_kernel(const float* __restrict__ Q, int64_t q0,
+                                                           int nqc, int d,
+                                                           const float* __restrict__ C, int K,
+                                                           double* keys, int32_t* vals, int* seg) {
+  __shared__ float sq[kPQ][kPD + 1];
+  __shared__ float sc[kPC][kPD + 1];
+  const int tid = threadIdx.x;
+  const int j0 = blockIdx.x * kPC, qb = blockIdx.y * kPQ;
+  if (blockIdx.x == 0 && tid < kPQ) {
+    const int qq = qb + tid;
+    if (qq < nqc) seg[qq] = qq * K;
+    if (qq == nqc - 1) seg[nqc] = nqc * K;
   }
-  if (j >= K) return;
-  const float* q = Q + (q0 + qi) * (int64_t)d;
-  const float* c = C + (int64_t)j * d;
-  double s = 0.0;
-  for (int k = 0; k < d; ++k) s = fma((double)q[k], (double)c[k], s);
-  keys[(int64_t)qi * K + j] = s + 0.0;   // -0 becomes +0, so equal scores sort as equal
-  vals[(int64_t)qi * K + j] = j;
+  const int ql = tid >> 4, cl = tid & 15;   // query ql, centroids cl + 16 m
+  double acc[kPC / 16];
+#pragma unroll
+  for (int m = 0; m < kPC / 16; ++m) acc[m] = 0.0;
+  for (int k0 = 0; k0 < d; k0 += kPD) {
+    const int kw = min(kPD, d - k0);
+    for (int i = tid; i < kPQ * kPD; i += 256) {
+      const int r = i / kPD, c = i % kPD, qq = qb + r;
+      sq[r][c] = (qq < nqc && c < kw) ? Q[(q0 + qq) * (int64_t)d + k0 + c] : 0.f;
+    }
+    for (int i = tid; i < kPC * kPD; i += 256) {
+      const int r = i / kPD, c = i % kPD, jj = j0 + r;
+      sc[r][c] = (jj < K && c < kw) ? C[(int64_t)jj * d + k0 + c] : 0.f;
+    }
+    __syncthreads();
+    for (int c = 0; c < kw; ++c) {
+      const double qv = (double)sq[ql][c];
+#pragma unroll
+      for (int m = 0; m < kPC / 16; ++m) acc[m] = fma(qv, (double)sc[cl + 16 * m][c], acc[m]);
+    }
+    __syncthreads();
+  }
+  const int qq = qb + ql;
+  if (qq >= nqc) return;
+#pragma unroll
+  for (int m = 0; m < kPC / 16; ++m) {
+    const int jj = j0 + cl + 16 * m;
+    if (jj < K) {
+      keys[(int64_t)qq * K + jj] = acc[m] + 0.0;   // -0 becomes +0, so equal scores sort as equal
+      vals[(int64_t)qq * K + jj] = jj;
+    }
+  }
 }
 
 // (score, id) order of the results: higher score first, then lower id.
@@ -115,43 +148,77 @@ __device__ __forceinline__ bool better(double s, int i, double t, int j) {
 }
 
 // One workgroup per query of the chunk: scan the t probed lists, keep the k best distinct ids.
+// The lists are taken kRerankThreads points at a time; their rows go through LDS kRD dimensions
+// at a time (coalesced), and each thread accumulates its point's <q, x> in dimension order (FP64),
+// so a point reached through two lists gets the same value twice.  Each thread keeps its
+// kSearchMaxK best without repeats; k rounds of a workgroup arg-max then take the k best distinct
+// ids (a point held by two threads is taken once: every holder moves past it).
+constexpr int kRD = 32;
+
+__device__ __forceinline__ void wave_best(double& s, int& i) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double os = __shfl_xor(s, off);
+    const int oi = __shfl_xor(i, off);
+    if (better(os, oi, s, i)) { s = os; i = oi; }
+  }
+}
+
 __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(
     const float* __restrict__ Q, int64_t q0, int d, const float* __restrict__ X,
     const int64_t* __restrict__ off, const int32_t* __restrict__ ids,
     const int32_t* __restrict__ order, int K, int t, int k, int32_t* out_ids, double* out_scores,
     int64_t* searched) {
-  __shared__ double s_sc[kRerankThreads * kSearchMaxK];
-  __shared__ int s_id[kRerankThreads * kSearchMaxK];
-  __shared__ int64_t s_count;
+  __shared__ float s_rows[kRerankThreads][kRD + 1];
+  __shared__ float s_q[kRD];
+  __shared__ double s_ws[kRerankThreads / 64];
+  __shared__ int s_wi[kRerankThreads / 64];
   const int qi = blockIdx.x;
   const int64_t qg = q0 + qi;
   const float* q = Q + qg * (int64_t)d;
-  const int tid = threadIdx.x;
-  if (tid == 0) s_count = 0;
-  // the thread's k best, best first (empty places: -inf and id INT_MAX)
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int64_t count = 0;
+  // the thread's kSearchMaxK best, best first (empty places: -inf and id INT_MAX)
   double sc[kSearchMaxK];
   int id_[kSearchMaxK];
 #pragma unroll
   for (int m = 0; m < kSearchMaxK; ++m) { sc[m] = -__builtin_inf(); id_[m] = 0x7fffffff; }
-  __syncthreads();
   for (int r = 0; r < t; ++r) {
     const int p = order[(int64_t)qi * K + r];
     const int64_t b = off[p], e = off[p + 1];
-    if (tid == 0) s_count += e - b;
-    for (int64_t i = b + tid; i < e; i += kRerankThreads) {
-      const int x = ids[i];
-      const float* xr = X + (int64_t)x * d;
+    count += e - b;
+    for (int64_t base = b; base < e; base += kRerankThreads) {
+      const int nb = (int)min<int64_t>(kRerankThreads, e - base);
+      const bool mine = tid < nb;
+      const int x = mine ? ids[base + tid] : 0;
       double s = 0.0;
-      for (int kk = 0; kk < d; ++kk) s = fma((double)q[kk], (double)xr[kk], s);
+      for (int k0 = 0; k0 < d; k0 += kRD) {
+        const int kw = min(kRD, d - k0);
+        // rows of the batch: 8 lanes per row, 4 floats each (zeros past d and past the batch)
+        for (int i = tid; i < kRerankThreads * (kRD / 4); i += kRerankThreads) {
+          const int rr = i / (kRD / 4), c4 = (i % (kRD / 4)) * 4;
+          float v[4] = {0.f, 0.f, 0.f, 0.f};
+          if (rr < nb) {
+            const float* xr = X + (int64_t)ids[base + rr] * d + k0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (c4 + u < kw) v[u] = xr[c4 + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) s_rows[rr][c4 + u] = v[u];
+        }
+        if (tid < kRD) s_q[tid] = tid < kw ? q[k0 + tid] : 0.f;
+        __syncthreads();
+        for (int c = 0; c < kw; ++c) s = fma((double)s_q[c], (double)s_rows[tid][c], s);
+        __syncthreads();
+      }
       s += 0.0;
-      // (every thread keeps its kSearchMaxK best; the first k of the merge are returned)
       // enters only if better than the current last and not already held
-      if (!better(s, x, sc[kSearchMaxK - 1], id_[kSearchMaxK - 1])) continue;
+      if (!mine || !better(s, x, sc[kSearchMaxK - 1], id_[kSearchMaxK - 1])) continue;
       bool held = false;
 #pragma unroll
       for (int m = 0; m < kSearchMaxK; ++m) held |= id_[m] == x;
       if (held) continue;
-      // insert: shift the worse entries down by one
       double cs = s;
       int ci = x;
 #pragma unroll
@@ -167,53 +234,35 @@ __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(
       }
     }
   }
-  // the workgroup's candidates: kRerankThreads * kSearchMaxK entries, bitonic sort, best first
+  // k rounds of a workgroup arg-max over the threads' heads
+  int h = 0;
+  for (int r = 0; r < k; ++r) {
+    double bs = -__builtin_inf();
+    int bi = 0x7fffffff;
 #pragma unroll
-  for (int m = 0; m < kSearchMaxK; ++m) {
-    s_sc[tid * kSearchMaxK + m] = sc[m];
-    s_id[tid * kSearchMaxK + m] = id_[m];
-  }
-  __syncthreads();
-  constexpr int N = kRerankThreads * kSearchMaxK;
-  for (int size = 2; size <= N; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < N; i += kRerankThreads) {
-        const int j = i ^ stride;
-        if (j > i) {
-          const bool up = (i & size) == 0;   // this pair's run is sorted best first
-          const bool swap = up ? better(s_sc[j], s_id[j], s_sc[i], s_id[i])
-                               : better(s_sc[i], s_id[i], s_sc[j], s_id[j]);
-          if (swap) {
-            const double ts = s_sc[i];
-            const int ti = s_id[i];
-            s_sc[i] = s_sc[j];
-            s_id[i] = s_id[j];
-            s_sc[j] = ts;
-            s_id[j] = ti;
-          }
-        }
-      }
-      __syncthreads();
+    for (int m = 0; m < kSearchMaxK; ++m)
+      if (h == m) { bs = sc[m]; bi = id_[m]; }
+    wave_best(bs, bi);
+    if (lane == 0) { s_ws[w] = bs; s_wi[w] = bi; }
+    __syncthreads();
+    double ws = s_ws[0];
+    int wi = s_wi[0];
+#pragma unroll
+    for (int v = 1; v < kRerankThreads / 64; ++v)
+      if (better(s_ws[v], s_wi[v], ws, wi)) { ws = s_ws[v]; wi = s_wi[v]; }
+    __syncthreads();
+    int hid = 0x7fffffff;
+#pragma unroll
+    for (int m = 0; m < kSearchMaxK; ++m)
+      if (h == m) hid = id_[m];
+    if (wi != 0x7fffffff && hid == wi) ++h;
+    if (tid == 0) {
+      const bool got = wi != 0x7fffffff && ws > -__builtin_inf();
+      out_ids[qg * k + r] = got ? wi : -1;
+      out_scores[qg * k + r] = got ? ws : -__builtin_inf();
     }
   }
-  if (tid == 0) {
-    int got = 0;
-    int last = -1;
-    for (int i = 0; i < N && got < k; ++i) {
-      const int x = s_id[i];
-      if (x == 0x7fffffff) break;
-      if (x == last) continue;         // a point met through both of its lists
-      out_ids[qg * k + got] = x;
-      out_scores[qg * k + got] = s_sc[i];
-      last = x;
-      ++got;
-    }
-    for (; got < k; ++got) {
-      out_ids[qg * k + got] = -1;
-      out_scores[qg * k + got] = -__builtin_inf();
-    }
-    if (searched) searched[qg] = s_count;
-  }
+  if (tid == 0 && searched) searched[qg] = count;
 }
 
 struct SearchLayout {
@@ -316,8 +365,8 @@ soar_status soar_search(const float* Q, int64_t nq, int32_t d, const float* C, i
   SearchLayout L = search_layout(workspace, nq, K);
   for (int64_t q0 = 0; q0 < nq; q0 += L.nqc) {
     const int nqc = (int)std::min<int64_t>(L.nqc, nq - q0);
-    hipLaunchKernelGGL(probe_scores_kernel, dim3((K + 255) / 256, nqc), dim3(256), 0, st, Q, q0,
-                       nqc, d, C, K, L.keys_in, L.vals_in, L.seg);
+    hipLaunchKernelGGL(probe_scores_kernel, dim3((K + kPC - 1) / kPC, (nqc + kPQ - 1) / kPQ),
+                       dim3(256), 0, st, Q, q0, nqc, d, C, K, L.keys_in, L.vals_in, L.seg);
     size_t tb = L.temp_bytes;
     if (hipcub::DeviceSegmentedRadixSort::SortPairsDescending(
             L.temp, tb, L.keys_in, L.keys_out, L.vals_in, L.vals_out, nqc * K, nqc, L.seg,
