@@ -34,8 +34,27 @@ PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2516.0, "fp8": 5032.0}   # MI355X dense M
 # are 2.0 and 1.0), summed over the kernels of one step.  A figure holds only for the kernel
 # sources it was taken on (sha256 below); after any change to them the traffic is reported as
 # null until it is measured again.
-COPY_SCALE = {"fetch": 1048576.0 / 524302.5, "write": 1.0}
+COPY_SCALE = {"fetch": 1048576.0 / 524302.5, "write": 1.0}   # 1 GiB device copy
+# L2-to-memory traffic of one whole call (rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB summed
+# over the call's dispatches), valid while the sources of its kernels are unchanged.
 TRAFFIC = {
+    # BF16, n=10M, d=96, K=40,000: quantization, primary sweep, re-score, grouping, grouped spill
+    # sweep over residual rows, re-score (plus the codebook norms and counter resets, 7.5 MB)
+    ("bf16", "mix16384_n10m_d96"): dict(
+        fetch_kib=118867289.375, write_kib=5711717.84375,
+        sources={"paper_2404_00774_amd/csrc/assign_lowp.hip":
+                 "814cbe3a918469dd870a87c8dbe13307344dc72e1e6478d26428a5dfb8931730",
+                 "paper_2404_00774_amd/csrc/group.hip":
+                 "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198",
+                 "paper_2404_00774_amd/csrc/common.h":
+                 "08810850b969fa684bc36a9d5144497379e1c98575c4717106f79b1a8f596bcf"}),
+    # FP8, same workload: direct spill form (two MFMA streams), no grouping
+    ("fp8", "mix16384_n10m_d96"): dict(
+        fetch_kib=51062149.3125, write_kib=3485803.59375,
+        sources={"paper_2404_00774_amd/csrc/assign_lowp.hip":
+                 "814cbe3a918469dd870a87c8dbe13307344dc72e1e6478d26428a5dfb8931730",
+                 "paper_2404_00774_amd/csrc/common.h":
+                 "08810850b969fa684bc36a9d5144497379e1c98575c4717106f79b1a8f596bcf"}),
     # grouped FP32 pipeline, per step: primary pass, grouping by primary, grouped spill pass
     ("fp32", "mix4096_n1m_d128"): dict(
         fetch_kib=256048.0 + 1966.1 + 6.8 + 2041.4 + 85.2 + 2 * 10.2 + 261088.9,
@@ -110,9 +129,9 @@ def parse():
     ap.add_argument("--serve-step-rows", type=int, default=16384, help="rows per step slot")
     ap.add_argument("--serve-train-rows", type=int, default=2_000_000,
                     help="rows (a prefix of the base) the serving codebook is trained on")
-    ap.add_argument("--serve-kpp-rows", type=int, default=500_000,
+    ap.add_argument("--serve-kpp-rows", type=int, default=2_000_000,
                     help="rows (a prefix of the base) k-means++ seeds the serving codebook on")
-    ap.add_argument("--serve-lloyd", type=int, default=3, help="Lloyd iterations of that codebook")
+    ap.add_argument("--serve-lloyd", type=int, default=10, help="Lloyd iterations of that codebook")
     ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     return ap.parse_args()
 
@@ -236,6 +255,42 @@ def search_leg(soar, torch, Xg, Cg, Qg, assign, ts, gt, reps=3):
                          "points_searched": float(r[2].double().mean().item())})
         out[name] = rows
         del off, ids
+    return out
+
+
+def further_leg(soar, torch, O, Xg, Cg, X, C, lam, assign, idx, steps, Q, ts, gt):
+    """A third assignment per point given the primary and spill (Section 3.5.1, soar_spill_further,
+    FP32): device time per call on resident inputs, algorithmic rate against the FP32 MFMA peak,
+    the oracle's judgement of the check rows, and recall@10 with three lists per point."""
+    n, d = Xg.shape
+    K = Cg.shape[0]
+    m = 2
+    P = torch.from_numpy(np.stack(assign, axis=1).astype(np.int32)).to(Xg.device)
+    soar.spill_further(Xg, Cg, P, lam)                      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev = []
+    for _ in range(steps):
+        nxt, loss, st = soar.spill_further(Xg, Cg, P, lam, stats=True)
+        dev.append(st["device_ms"])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps * 1e3
+    dms = float(np.mean(dev))
+    alg = 2.0 * n * K * d * (1 + m)
+    nx, ls = nxt.cpu().numpy(), loss.cpu().numpy()
+    Pn = P.cpu().numpy()
+    j = O.verify_further(X[idx], C, lam, Pn[idx], nx[idx], ls[idx])
+    out = {"earlier_assignments": m, "ms_per_call": wall, "device_ms": dms,
+           "algorithmic_flops_per_call": alg, "algorithmic_tflops": alg / (dms / 1e3) / 1e12,
+           "fp32_peak_frac": alg / (dms / 1e3) / 1e12 / PEAKS_TFLOPS["fp32"],
+           "rows_full_scan": int(st["rows_full_scan"]), "rows_fp64": int(st["rows_fp64"]),
+           "oracle_check": {"rows": int(len(idx)), "exact_by_rule": bool(j["all_ok"]),
+                            "index_disagreement": float(j["mismatch"] / len(idx)),
+                            "regret_mean": float(np.mean(j["regret"]))}}
+    if Q is not None:
+        k3, n3 = O.kmr_curve(Q, X, C, [assign[0], assign[1], nx], 10, ts, gt=gt)
+        out["recall_three_lists"] = [float(v) for v in k3]
+        out["points_searched_three_lists"] = [float(v) for v in n3]
     return out
 
 
@@ -593,6 +648,14 @@ def main():
         for lam, assign in full.items():
             print(f"[bench] GPU search, lambda {lam}", file=sys.stderr, flush=True)
             search[str(lam)] = search_leg(soar, torch, Xg, Cg, Qg, assign, ts, gt)
+    further = None
+    if Q is not None and lams[0] in full:
+        print(f"[bench] further spilled assignment (third list), lambda {lams[0]}",
+              file=sys.stderr, flush=True)
+        further = further_leg(soar, torch, O, Xg, Cg, X, C, lams[0], full[lams[0]], idx,
+                              args.form_steps, Q, ts, gt)
+        print(f"[bench] further: {further['device_ms']:.3f} ms, "
+              f"{further['fp32_peak_frac']:.3f} of FP32 peak", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline and cpu_rows:
         print(f"[bench] CPU baseline: the oracle on {cpu_rows} rows", file=sys.stderr, flush=True)
@@ -616,6 +679,7 @@ def main():
         "lambda_trend": trend_out,
         "recall_at_10": rec,
         "gpu_search": search,
+        "further_assignment": further,
         "train": {"kmeanspp_s": t_kpp, "kmeanspp_rows": int(sub if sub and sub < n else n),
                   "lloyd_s": t_lloyd, "inertia_first": inertia[0], "inertia_last": inertia[-1]},
     }
