@@ -135,7 +135,8 @@ __device__ __forceinline__ double direct64(const AssignParams& P, int nch, int64
   double sq0 = 0.0, sq1 = 0.0, pj0 = 0.0, pj1 = 0.0, rr0 = 0.0, rr1 = 0.0;
   for (int ch = 0; ch < (CH ? nch : 1); ++ch) {
     const float* cj = rec_row<DP, BN>(P.Crec, nch, j, ch) + q * KS;
-    const float* cpi = rec_row<DP, BN>(P.Crec, nch, pi, ch) + q * KS;
+    // (pi indexes the whole codebook; under codebook splits P.Crec holds the split's tiles only)
+    const float* cpi = rec_row<DP, BN>(P.Crec_all ? P.Crec_all : P.Crec, nch, pi, ch) + q * KS;
     float xs[CH ? KS : 1];
     if constexpr (CH) load_seg<KS, VEC>(P.X, row, P.d, ch * DP + q * KS, ok, xs);
 #pragma unroll 1
@@ -466,14 +467,35 @@ constexpr int f32_kernel_waves() {
              : f32_waves<DP, CH>();
 }
 
-template <int DP, int BN, bool CH, bool SPILL, bool VEC, bool GR>
+// SPLIT (codebook splits, serving steps): gridDim.y splits share the tiles; split s sweeps its own
+// tile range with the parameters offset to it (columns split-relative) and writes its exact
+// arg-min and value to split_idx / split_val, its unproven rows to its own full-scan list.  The
+// primary pass (SPLIT, !SPILL) runs first and split_merge_kernel joins the splits; the spill pass
+// (SPLIT, SPILL) then takes the joined primary from P.primary instead of computing it.
+template <int DP, int BN, bool CH, bool SPILL, bool VEC, bool GR, bool SPLIT = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     f32_kernel_waves<DP, BN, CH, SPILL>(),
     f32_kernel_waves<DP, BN, CH, SPILL>() > 2 ? f32_kernel_waves<DP, BN, CH, SPILL>() : 2)))
-void assign_f32_kernel(AssignParams P) {
+void assign_f32_kernel(AssignParams P0) {
   using R = F32Rec<DP, BN>;
   constexpr int KS = DP / 4;
   static_assert(2 * R::STAGE >= (int)sizeof(CandShared), "candidate lists must fit in the ring");
+  static_assert(!SPLIT || (!CH && !GR), "codebook splits: resident rows, direct form");
+  AssignParams P = P0;
+  int kbase = 0;                         // first column of the split
+  size_t so = 0;                         // offset of the split's outputs
+  if constexpr (SPLIT) {
+    const int nt = (P0.K + BN - 1) / BN;
+    const int t0 = (int)((int64_t)nt * blockIdx.y / gridDim.y);
+    const int t1 = (int)((int64_t)nt * (blockIdx.y + 1) / gridDim.y);
+    kbase = t0 * BN;
+    P.Crec = P0.Crec + (size_t)t0 * R::BYTES;
+    P.Crec_all = P0.Crec;
+    P.cnorm = P0.cnorm + kbase;
+    P.C = P0.C + (size_t)kbase * P0.d;
+    P.K = min(P0.K, t1 * BN) - kbase;
+    so = (size_t)blockIdx.y * (size_t)P0.n;
+  }
   // one LDS object: [ring of two record stages | per-row state]
   __shared__ __attribute__((aligned(16))) char lds[2 * R::STAGE + sizeof(RowShared)];
   char* ring = lds;
@@ -518,27 +540,41 @@ void assign_f32_kernel(AssignParams P) {
     xv[v] = S.xn[w][4 * q + v];
     Av[v] = S.A[w][4 * q + v];
   }
-  sweep<DP, BN, CH, VEC, false>(P, ring, nch, tid, row, ok, -1, xa, ra, lp, av, pr, xv, Av, b1,
-                                i1, b2, i2, b3);
-  publish_candidates(P, S, CS, w, lane, xv, Av, b1, i1, b2, i2, b3);
-  __syncthreads();
-
   int pi = -1;
   float pdist = 0.f;
-  bool psat = S.sat[w][c16] != 0;
-  if (!psat) decide<DP, BN, CH, VEC, false>(P, S, CS, nch, w, c16, q, row, ok, xa, ra, 0.f, 0, pi, pdist);
-  if (pi < 0 || pi >= P.K) psat = true;
-  if (ok && q == 0) {
-    if (psat) {
-      const unsigned slot = atomicAdd(&P.counters[CNT_FULLSCAN], 1u);
-      P.full_rows[slot] = (int32_t)row;
-      P.primary[row] = -1;   // finished by the full scan; left out of a grouped spill
-    } else {
-      P.primary[row] = pi;
-      if (P.pdist) P.pdist[row] = pdist;
+  bool psat = false;
+  if constexpr (!(SPLIT && SPILL)) {
+    sweep<DP, BN, CH, VEC, false>(P, ring, nch, tid, row, ok, -1, xa, ra, lp, av, pr, xv, Av, b1,
+                                  i1, b2, i2, b3);
+    publish_candidates(P, S, CS, w, lane, xv, Av, b1, i1, b2, i2, b3);
+    __syncthreads();
+
+    psat = S.sat[w][c16] != 0;
+    if (!psat) decide<DP, BN, CH, VEC, false>(P, S, CS, nch, w, c16, q, row, ok, xa, ra, 0.f, 0, pi, pdist);
+    if (pi < 0 || pi >= P.K) psat = true;
+    if (ok && q == 0) {
+      if constexpr (SPLIT) {
+        if (psat) {
+          const unsigned slot = atomicAdd(&P0.split_cnt[blockIdx.y], 1u);
+          P0.split_rows[so + slot] = (int32_t)row;
+        }
+        P0.split_idx[so + row] = psat ? -1 : pi;
+        P0.split_val[so + row] = psat ? kInf : pdist;
+      } else if (psat) {
+        const unsigned slot = atomicAdd(&P.counters[CNT_FULLSCAN], 1u);
+        P.full_rows[slot] = (int32_t)row;
+        P.primary[row] = -1;   // finished by the full scan; left out of a grouped spill
+      } else {
+        P.primary[row] = pi;
+        if (P.pdist) P.pdist[row] = pdist;
+      }
     }
+    if constexpr (!SPILL) return;
+  } else {
+    // the joined primary of the splits (global index)
+    pi = ok ? P0.primary[row] : -1;
+    if (pi < 0 || pi >= P0.K) { pi = -1; psat = true; }
   }
-  if constexpr (!SPILL) return;
 
   // ---------------- residual ----------------
   if (psat) pi = -1;
@@ -547,7 +583,7 @@ void assign_f32_kernel(AssignParams P) {
     float r0 = 0.f, r1 = 0.f, r2 = 0.f, r3 = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
     for (int ch = 0; ch < nch; ++ch) {
       float cp[KS];
-      load_rec<KS>(rec_row<DP, BN>(P.Crec, nch, pi, ch) + q * KS, cp);
+      load_rec<KS>(rec_row<DP, BN>(P0.Crec, nch, pi, ch) + q * KS, cp);   // (all of C)
       if constexpr (CH) load_seg<KS, VEC>(P.X, row, P.d, ch * DP + q * KS, ok, xa);
 #pragma unroll
       for (int s = 0; s < KS; s += 4) {
@@ -579,7 +615,8 @@ void assign_f32_kernel(AssignParams P) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int r = 4 * q + v;
-    lp[v] = S.lp[w][r]; av[v] = S.av[w][r]; pr[v] = S.pi[w][r]; Av[v] = S.A[w][r];
+    // (split-relative under SPLIT: the mask compares split columns)
+    lp[v] = S.lp[w][r]; av[v] = S.av[w][r]; pr[v] = S.pi[w][r] - kbase; Av[v] = S.A[w][r];
     b1[v] = b2[v] = b3[v] = kInf; i1[v] = i2[v] = 0x7fffffff;
   }
 
@@ -588,7 +625,14 @@ void assign_f32_kernel(AssignParams P) {
                                    b1, i1, b2, i2, b3);
   publish_candidates(P, S, CS, w, lane, xv, Av, b1, i1, b2, i2, b3);
   __syncthreads();
-  if (pi < 0) return;  // full-scan rows are finished by the full-scan kernel
+  if (pi < 0) {
+    // full-scan rows are finished by the full-scan kernel; under SPLIT a row without a primary
+    // has no spill
+    if constexpr (SPLIT) {
+      if (ok && q == 0) P0.split_idx[so + row] = -1;
+    }
+    return;
+  }
   if constexpr (GR) {
     // the Gram sweep does not read R: form it again here rather than hold it across the sweep
     float cp[KS];
@@ -602,7 +646,14 @@ void assign_f32_kernel(AssignParams P) {
   if (!ssat) decide<DP, BN, CH, VEC, true>(P, S, CS, nch, w, c16, q, row, ok, xa, ra, rr, pi, sj, sl);
   if (sj < 0 || sj >= P.K) ssat = true;
   if (ok && q == 0) {
-    if (ssat) {
+    if constexpr (SPLIT) {
+      if (ssat) {
+        const unsigned slot = atomicAdd(&P0.split_cnt[blockIdx.y], 1u);
+        P0.split_rows[so + slot] = (int32_t)row;
+      }
+      P0.split_idx[so + row] = ssat ? -1 : sj;
+      P0.split_val[so + row] = ssat ? kInf : sl;
+    } else if (ssat) {
       const unsigned slot = atomicAdd(&P.counters[CNT_FULLSCAN], 1u);
       P.full_rows[slot] = (int32_t)row;
     } else {
@@ -910,6 +961,145 @@ __global__ __launch_bounds__(FS_THREADS) void full_scan_kernel(AssignParams P) {
       }
     }
     __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Codebook splits (serving steps): the exact full scan of a split's unproven rows over the split's
+// columns, and the join of the splits' answers.
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void split_range(int K, int BN, int s, int S, int& kb, int& ks) {
+  const int nt = (K + BN - 1) / BN;
+  const int t0 = (int)((int64_t)nt * s / S), t1 = (int)((int64_t)nt * (s + 1) / S);
+  kb = t0 * BN;
+  ks = min(K, t1 * BN) - kb;
+}
+
+template <bool SPILL>
+__global__ __launch_bounds__(FS_THREADS) void full_scan_split_kernel(AssignParams P0, int BN) {
+  extern __shared__ float fs_smem[];
+  const int d = P0.d, tid = threadIdx.x, lane = tid & 63;
+  const int s = blockIdx.y, S = gridDim.y;
+  int kb, ks;
+  split_range(P0.K, BN, s, S, kb, ks);
+  AssignParams P = P0;
+  P.C = P0.C + (size_t)kb * d;
+  P.K = ks;
+  // (the launch sizes the value cache for the largest split, ceil(tiles / S) tiles)
+  const int kmax = ((P0.K + BN - 1) / BN + S - 1) / S * BN;
+  float* sx = fs_smem;
+  float* sr = fs_smem + d;
+  float* scp = fs_smem + 2 * d;
+  float* sv = kmax <= FS_LDS_K ? fs_smem + 3 * d : nullptr;
+  __shared__ float s_rr;
+  const size_t so = (size_t)s * (size_t)P0.n;
+  const unsigned count = P0.split_cnt[s];
+  for (unsigned e = blockIdx.x; e < count; e += gridDim.x) {
+    const int64_t row = P0.split_rows[so + e];
+    for (int k = tid; k < d; k += FS_THREADS) sx[k] = P0.X[row * d + k];
+    __syncthreads();
+    int j = -1;
+    float v = kInf;
+    if constexpr (!SPILL) {
+      fs_argmin<false>(P, sx, sr, 0.f, scp, -1, sv, j, v);
+    } else {
+      const int pi = P0.primary[row];     // joined primary (whole codebook)
+      const int pc = (pi >= 0 && pi < P0.K) ? pi : 0;   // (rows without one are not listed)
+      for (int k = tid; k < d; k += FS_THREADS) {
+        const float c = P0.C[(int64_t)pc * d + k];
+        scp[k] = c;
+        sr[k] = sx[k] - c;
+      }
+      __syncthreads();
+      if (tid < 64) {
+        float a = 0.f;
+        for (int k = lane; k < d; k += 64) a = fmaf(sr[k], sr[k], a);
+        a = wave_sum_f(a);
+        if (tid == 0) s_rr = a;
+      }
+      __syncthreads();
+      if (pi >= 0 && pi < P0.K) fs_argmin<true>(P, sx, sr, s_rr, scp, pi - kb, sv, j, v);
+    }
+    if (tid == 0) {
+      P0.split_idx[so + row] = (j >= 0 && j < ks) ? j : -1;
+      P0.split_val[so + row] = v;
+      atomicAdd(&P0.counters[CNT_FP64], 1u);
+    }
+    __syncthreads();
+  }
+}
+
+// Join of the S splits' answers for every row: the least value (then the lowest index); splits
+// whose value lies within the near-tie gap of it are decided again in FP64 by direct differences
+// (distance, or the SOAR loss with the residual formed exactly from the joined primary).
+template <bool SPILL>
+__global__ __launch_bounds__(256) void split_merge_kernel(AssignParams P0, int S, int BN) {
+  const int64_t n = live_rows(P0.n, P0.live_n);
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  const int d = P0.d;
+  const float* x = P0.X + row * d;
+  int pi = -1;
+  if constexpr (SPILL) {
+    pi = P0.primary[row];
+    if (pi < 0 || pi >= P0.K) {
+      P0.spill[row] = -1;
+      if (P0.sloss) P0.sloss[row] = kInf;
+      return;
+    }
+  }
+  float best = kInf;
+  int bj = 0x7fffffff;
+  for (int s = 0; s < S; ++s) {
+    const int idx = P0.split_idx[(size_t)s * P0.n + row];
+    if (idx < 0) continue;
+    int kb, ks;
+    split_range(P0.K, BN, s, S, kb, ks);
+    const float v = P0.split_val[(size_t)s * P0.n + row];
+    const int j = kb + idx;
+    if (v < best || (v == best && j < bj)) { best = v; bj = j; }
+  }
+  if (bj != 0x7fffffff) {
+    const float lim = best + best * P0.tie_rel;
+    int near = 0;
+    for (int s = 0; s < S; ++s)
+      near += P0.split_idx[(size_t)s * P0.n + row] >= 0 &&
+              P0.split_val[(size_t)s * P0.n + row] <= lim;
+    if (near >= 2) {
+      double bd = __builtin_inf();
+      int bdj = 0x7fffffff;
+      for (int s = 0; s < S; ++s) {
+        const int idx = P0.split_idx[(size_t)s * P0.n + row];
+        if (idx < 0 || !(P0.split_val[(size_t)s * P0.n + row] <= lim)) continue;
+        int kb, ks;
+        split_range(P0.K, BN, s, S, kb, ks);
+        const int j = kb + idx;
+        const float* c = P0.C + (int64_t)j * d;
+        double sq = 0.0, pj = 0.0, rr = 0.0;
+        for (int k = 0; k < d; ++k) {
+          const double e = (double)x[k] - (double)c[k];
+          sq = fma(e, e, sq);
+          if constexpr (SPILL) {
+            const double r = (double)x[k] - (double)P0.C[(int64_t)pi * d + k];
+            pj = fma(r, e, pj);
+            rr = fma(r, r, rr);
+          }
+        }
+        const double val = (SPILL && rr > 0.0) ? sq + (double)P0.lam * (pj * pj) / rr : sq;
+        argmin_d(bd, bdj, val, j);
+      }
+      best = (float)bd;
+      bj = bdj;
+      atomicAdd(&P0.counters[CNT_FP64], 1u);
+    }
+  }
+  const int out = bj == 0x7fffffff ? -1 : bj;
+  if constexpr (SPILL) {
+    P0.spill[row] = out;
+    if (P0.sloss) P0.sloss[row] = best;
+  } else {
+    P0.primary[row] = out;
+    if (P0.pdist) P0.pdist[row] = best;
   }
 }
 
@@ -1772,6 +1962,50 @@ hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipSt
   else
     hipLaunchKernelGGL(full_scan_kernel<false>, dim3(256), dim3(FS_THREADS), smem, st, P);
   return hipGetLastError();
+}
+
+// ---- codebook splits (serving steps) ----
+bool fp32_split_supported(int d) {
+  const int dp = fp32_padded_dim(d);
+  return dp > 0 && dp <= 256;
+}
+
+template <int DP, int BN>
+static hipError_t launch_split_dp(const AssignParams& P, int S, bool vec, hipStream_t st) {
+  const dim3 grid((unsigned)((P.n + 63) / 64), (unsigned)S), block(256);
+  const dim3 mgrid((unsigned)((P.n + 255) / 256));
+  const int nt = (P.K + BN - 1) / BN;
+  const int kmax = (nt + S - 1) / S * BN;
+  const size_t smem = ((size_t)3 * P.d + (kmax <= FS_LDS_K ? (size_t)kmax : 0)) * sizeof(float);
+  // primary: the splits, their full scans, the join
+  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, st, P.split_cnt, S);
+  if (vec) hipLaunchKernelGGL((assign_f32_kernel<DP, BN, false, false, true, false, true>), grid, block, 0, st, P);
+  else hipLaunchKernelGGL((assign_f32_kernel<DP, BN, false, false, false, false, true>), grid, block, 0, st, P);
+  hipLaunchKernelGGL(full_scan_split_kernel<false>, dim3(64, (unsigned)S), dim3(FS_THREADS), smem,
+                     st, P, BN);
+  hipLaunchKernelGGL(split_merge_kernel<false>, mgrid, dim3(256), 0, st, P, S, BN);
+  // spill given the joined primary
+  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, st, P.split_cnt, S);
+  if (vec) hipLaunchKernelGGL((assign_f32_kernel<DP, BN, false, true, true, false, true>), grid, block, 0, st, P);
+  else hipLaunchKernelGGL((assign_f32_kernel<DP, BN, false, true, false, false, true>), grid, block, 0, st, P);
+  hipLaunchKernelGGL(full_scan_split_kernel<true>, dim3(64, (unsigned)S), dim3(FS_THREADS), smem,
+                     st, P, BN);
+  hipLaunchKernelGGL(split_merge_kernel<true>, mgrid, dim3(256), 0, st, P, S, BN);
+  return hipGetLastError();
+}
+
+hipError_t launch_assign_fp32_split(const AssignParams& P, int S, bool vec, hipStream_t st) {
+  const int dp = fp32_padded_dim(P.d);
+  if (dp < 0 || dp > 256 || S < 1 || S > 64 || !P.Crec || !P.split_idx || !P.split_val ||
+      !P.split_rows || !P.split_cnt || !P.primary || !P.spill || P.K < S)
+    return hipErrorInvalidValue;
+  hipError_t e = hipErrorInvalidValue;
+#define SOAR_X(DP, BN, CH)                                      \
+  if constexpr (!CH) e = launch_split_dp<DP, BN>(P, S, vec, st); \
+  else e = hipErrorInvalidValue
+  switch (dp) { SOAR_F32_SHAPES(SOAR_X) }
+#undef SOAR_X
+  return e;
 }
 
 // ---- further spilled assignments ----

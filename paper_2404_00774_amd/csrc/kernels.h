@@ -40,6 +40,14 @@ struct AssignParams {
   const int64_t* live_n = nullptr;   // device row count <= n (serving steps), or null
   // further spilled assignments: [n x np] earlier assignments per row (row-major)
   const int32_t* prior = nullptr;
+  // codebook splits (launch_assign_fp32_split): split s of gridDim.y writes its split-relative
+  // arg-min and value to split_idx / split_val[s * n + row] and lists its unproven rows in
+  // split_rows[s * n + k], counted by split_cnt[s]; Crec_all is the whole codebook's records
+  const char* Crec_all = nullptr;
+  int32_t* split_idx = nullptr;
+  float* split_val = nullptr;
+  int32_t* split_rows = nullptr;
+  unsigned* split_cnt = nullptr;
 };
 
 // Padded row length of the FP32 path (-1: unsupported); rows above 256 are processed in chunks.
@@ -76,6 +84,14 @@ hipError_t launch_async_clear(unsigned* counters, hipStream_t st);
 // rows by primary into G, grouped spill pass.
 hipError_t launch_assign_fp32(const AssignParams& P, bool spill, bool vec, hipStream_t st,
                               hipEvent_t* ev = nullptr, const GroupLayout* grouped = nullptr);
+
+// FP32 SOAR assignment with the codebook split S ways (serving steps of few rows: S workgroups per
+// row block, each over 1/S of the tiles), rows of up to 256 dimensions: primary pass, exact full
+// scan of the splits' unproven rows, join of the splits (FP64 on near-ties across splits), then
+// the same for the spill given the joined primary.  P.split_* must hold S * n entries (split_cnt
+// S words).  Same results as launch_assign_fp32.
+hipError_t launch_assign_fp32_split(const AssignParams& P, int S, bool vec, hipStream_t st);
+bool fp32_split_supported(int d);
 
 // ---- further spilled assignments (the next assignment given np = 1..3 earlier ones) ----
 constexpr int kFurtherMaxPrior = 3;

@@ -176,7 +176,8 @@ struct Slot {
   // pinned host staging
   char* h_in = nullptr;          // [live int64][ids cap int64][X cap*d float]
   char* h_out = nullptr;         // [prim cap][spill cap][counters 8][status, chunks used]
-  bool busy = false;
+  bool busy = false;     // the worker has taken the slot for a step (set before its launch)
+  bool ready = false;    // the step is fully enqueued, its events recorded: the waiter may go
   int64_t rows = 0, worst_chunks = 0;
   std::vector<Part> parts;
   std::thread waiter;
@@ -223,12 +224,17 @@ namespace {
 // Codebook splits of a serving step's sweeps.  A step of few rows fills few workgroups, and
 // each would sweep every centroid tile in turn; splitting the codebook into S parts runs S
 // workgroups per row group, each over an S-th of the tiles, and a merge keeps the best
-// candidates.  One split per 4096 centroids, at most 8, so every split covers at least 4096
+// candidates (BF16/FP8) or joins the splits' exact answers (FP32, rows of up to 256 dimensions).  One split per 4096 centroids, at most 8, so every split covers at least 4096
 // columns.  Fixed per index, so a row's result does not depend on the step it runs in.
 int serving_ksplit(int K) { return std::max(1, std::min(8, K / 4096)); }
 
 size_t step_ws_bytes(int64_t cap, int d, int K, bool lowp, int fmt) {
-  if (!lowp) return al(CNT_ALLOC_WORDS * 4) + al((size_t)cap * 4);   // counters + full-scan rows
+  if (!lowp) {
+    // counters + full-scan rows; with codebook splits per split: index, value, full-scan rows
+    const int S = fp32_split_supported(d) ? serving_ksplit(K) : 1;
+    return al(CNT_ALLOC_WORDS * 4) + al((size_t)cap * 4) +
+           (S > 1 ? 3 * al((size_t)cap * S * 4) + al(64 * 4) : 0);
+  }
   const int dp = lowp_padded_dim(fmt, d);
   const size_t eb = fmt == LOWP_BF16 ? 2 : 1;
   const int S = serving_ksplit(K);
@@ -302,7 +308,16 @@ hipError_t enqueue_compute(soar_index* ix, Slot& s) {
     P.primary = s.prim; P.spill = s.spill; P.pdist = nullptr; P.sloss = nullptr;
     char* w = static_cast<char*>(s.ws) + al(CNT_ALLOC_WORDS * 4);
     P.full_rows = reinterpret_cast<int32_t*>(w);
+    w += al((size_t)ix->cap * 4);
     P.live_n = s.live;
+    const int S = fp32_split_supported(ix->d) ? serving_ksplit(ix->K) : 1;
+    if (S > 1) {
+      P.split_idx = reinterpret_cast<int32_t*>(w); w += al((size_t)ix->cap * S * 4);
+      P.split_val = reinterpret_cast<float*>(w); w += al((size_t)ix->cap * S * 4);
+      P.split_rows = reinterpret_cast<int32_t*>(w); w += al((size_t)ix->cap * S * 4);
+      P.split_cnt = reinterpret_cast<unsigned*>(w);
+      return launch_assign_fp32_split(P, S, ix->d % 4 == 0, s.st);
+    }
     return launch_assign_fp32(P, true, ix->d % 4 == 0, s.st);
   }
   const int fmt = ix->fmt, dp = lowp_padded_dim(fmt, ix->d);
@@ -487,6 +502,9 @@ bool try_launch(soar_index* ix, Slot& s, std::unique_lock<std::mutex>& lk) {
   lk.lock();
   --ix->paused;
   if (e != hipSuccess) ix->device_error = true;
+  // only now are this step's events recorded: a waiter that woke while `busy` alone was set
+  // would have synchronized on the previous step's events and taken its stale results
+  s.ready = true;
   s.cv.notify_one();                  // the slot's waiter takes it from here
   ix->cv_done.notify_all();
   return true;
@@ -497,15 +515,17 @@ bool try_launch(soar_index* ix, Slot& s, std::unique_lock<std::mutex>& lk) {
 void slot_loop(soar_index* ix, Slot& s) {
   std::unique_lock<std::mutex> lk(ix->mu);
   for (;;) {
-    s.cv.wait(lk, [&] { return s.busy || (ix->shutdown && ix->in_flight == 0 &&
-                                          ix->queue.empty()); });
-    if (!s.busy) break;
+    s.cv.wait(lk, [&] { return s.ready || (ix->shutdown && ix->in_flight == 0 &&
+                                           ix->queue.empty()); });
+    if (!s.ready) break;
+    s.ready = false;
+    const bool launch_failed = ix->device_error;
     lk.unlock();
     const hipError_t e1 = hipEventSynchronize(s.ev_results);
     lk.lock();
     const OutView o = out_view(ix, s);
     soar_status st = SOAR_OK;
-    if (e1 != hipSuccess) { st = SOAR_E_DEVICE; ix->device_error = true; }
+    if (e1 != hipSuccess || launch_failed) { st = SOAR_E_DEVICE; ix->device_error = true; }
     else if (o.cnt[CNT_NONFINITE]) st = SOAR_E_NONFINITE;
     for (Part& p : s.parts) {
       Request& r = *p.req;
@@ -527,7 +547,9 @@ void slot_loop(soar_index* ix, Slot& s) {
     if (e2 != hipSuccess) ix->device_error = true;
     else {
       if (o.list[0] != 0) ix->list_error = true;
-      ix->chunks_used = o.list[1];
+      // the pool cursor only grows; the two slots' waiters may get here in either order, and a
+      // slot's copy may predate the other slot's later append, so keep the largest value seen
+      ix->chunks_used = std::max<int64_t>(ix->chunks_used, (int64_t)o.list[1]);
     }
     ix->chunks_reserved -= s.worst_chunks;
     s.busy = false;

@@ -63,6 +63,27 @@ def test_mixed_requests_match_standalone_assign(data, prec):
         assert j["primary_ok"].all() and j["spill_ok"].all()
 
 
+def test_first_steps_right_after_create(data):
+    """Requests inserted the moment an index exists, before its slot threads may have started
+    waiting: every answer must be this request's own (a slot's waiter takes a step only after
+    the step's events are recorded)."""
+    soar = _soar()
+    X, C = data
+    ref_p, ref_s, _, _ = soar.assign(_t(X[:3000]), _t(C), 1.0, precision="bf16",
+                                     spill_form="direct")
+    ref_p, ref_s = ref_p.cpu().numpy(), ref_s.cpu().numpy()
+    for trial in range(6):
+        ix = soar.SoarIndex(_t(C), 1.0, precision="bf16", max_step_rows=512,
+                            list_capacity=20_000)
+        lo = 500 * trial
+        ts = [ix.insert(X[lo:lo + 100], lo), ix.insert(X[lo + 100:lo + 500], lo + 100)]
+        p1, s1 = ix.wait(ts[0], timeout=60.0)
+        p2, s2 = ix.wait(ts[1], timeout=60.0)
+        ix.close()
+        assert np.array_equal(np.concatenate([p1, p2]), ref_p[lo:lo + 500]), trial
+        assert np.array_equal(np.concatenate([s1, s2]), ref_s[lo:lo + 500]), trial
+
+
 def test_alone_and_in_concurrent_mix(data):
     soar = _soar()
     X, C = data
@@ -87,10 +108,11 @@ def test_alone_and_in_concurrent_mix(data):
     ix.close()
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "fp8", "fp32"])
 def test_split_codebook_steps(prec):
     """With K = 8192 every serving sweep runs as two codebook splits (one per 4096 centroids)
-    whose candidates are merged: the answers are the oracle's within the low-precision bound,
+    whose candidates (BF16/FP8) or exact answers (FP32) are joined: the answers are the oracle's
+    within the low-precision bound (FP32: exactly, and equal to the unsplit assignment),
     the same alone and in a mix of request sizes, and the lists hold exactly them.  (d = 128, the
     serving workload's width.)"""
     soar = _soar()
@@ -105,6 +127,14 @@ def test_split_codebook_steps(prec):
     for t, a, sz in tickets:
         p[a:a + sz], s[a:a + sz] = ix.wait(t, timeout=60.0)
     pa, sa = ix.wait(ix.insert(X[:500], 50_000), timeout=60.0)
+    if not (np.array_equal(pa, p[:500]) and np.array_equal(sa, s[:500])):
+        # which of the two answers the oracle accepts, and where they part
+        ja = O.verify(X[:500], C, 1.0, pa, sa)
+        jp = O.verify(X[:500], C, 1.0, p[:500], s[:500])
+        bad = np.flatnonzero(pa != p[:500])
+        print("repeat differs at", bad[:10], "count", bad.size, "repeat ok",
+              float(ja["primary_ok"].mean()), "first ok", float(jp["primary_ok"].mean()),
+              "stats", ix.stats(), flush=True)
     assert np.array_equal(pa, p[:500]) and np.array_equal(sa, s[:500])
     got = sorted((int(i), k) for k in range(len(C)) for i in ix.list(k) if i < n)
     want = sorted([(i, int(p[i])) for i in range(n)] + [(i, int(s[i])) for i in range(n)])
@@ -116,13 +146,19 @@ def test_split_codebook_steps(prec):
           "spill regret", float(j["spill_regret"].mean()), flush=True)
     assert np.all(s != p) and np.all((p >= 0) & (p < len(C))) and np.all((s >= 0) & (s < len(C)))
     assert j["primary_regret"].mean() <= bound and j["spill_regret"].mean() <= bound
+    if prec == "fp32":
+        # exact: the joined splits give the unsplit answer
+        assert j["primary_ok"].all() and j["spill_ok"].all()
+        rp, rs, _, _ = _soar().assign(_t(X[:n]), _t(C), 1.0, spill_form="direct")
+        assert np.array_equal(p, rp.cpu().numpy()) and np.array_equal(s, rs.cpu().numpy())
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "fp8", "fp32"])
 def test_serving_codebook_50k_eight_splits(prec):
     """The serving shape: K = 50,000 centroids at d = 128, so every sweep runs as 8 codebook
     splits.  Requests of mixed sizes, the oracle's judgement of every row within the
-    low-precision bound, identical answers for a repeated request, and exact lists."""
+    low-precision bound (FP32: exact), identical answers for a repeated request, and exact
+    lists."""
     soar = _soar()
     X = gen_mixture(MixtureSpec(56_000, 128, 2048, 0.3, "unit", 13))
     C = (X[:50_000] * 0.97).astype(np.float32)
@@ -149,6 +185,8 @@ def test_serving_codebook_50k_eight_splits(prec):
           float((p != j["p_star"]).mean()), flush=True)
     assert np.all(s != p) and np.all((p >= 0) & (p < len(C))) and np.all((s >= 0) & (s < len(C)))
     assert j["primary_regret"].mean() <= 1e-3 and j["spill_regret"].mean() <= 1e-3
+    if prec == "fp32":
+        assert j["primary_ok"].all() and j["spill_ok"].all()
 
 
 def test_admission_waits_for_memory_and_rejects_too_large(data):
