@@ -270,7 +270,11 @@ soar_status soar_index_arena_size(int32_t K, int32_t d, int32_t precision, int32
  * Create an index over codebook C [K x d] (device, copied into the arena) with spill weight
  * lambda.  The index places the codebook, its per-step buffers and the partition lists inside
  * the caller's device arena (arena_bytes) and never allocates device memory of its own.
- * max_step_rows bounds the rows assigned in one device step.
+ * max_step_rows bounds the rows assigned in one device step.  With K >= 8192 every step's sweeps
+ * run in S = min(8, K / 4096) codebook splits (workgroups over 1/S of the centroids each), whose
+ * candidates (BF16/FP8) or exact answers (FP32, d <= 256) are joined; S is fixed per index, so a
+ * point's assignment does not depend on the step it lands in, and FP32 answers equal
+ * soar_assign's.
  */
 soar_status soar_index_create(const float* C, int32_t K, int32_t d, float lambda,
                               int32_t precision, void* arena, size_t arena_bytes,

@@ -114,7 +114,31 @@ __global__ __launch_bounds__(256) void quantize_rows_kernel(const float* __restr
   const float* a = A + row * d;
   float scale = 1.f;
   bool fin = true;
-  if constexpr (FMT == LOWP_FP8) {
+  if constexpr (FMT == LOWP_FP8 && V4) {
+    // rows of whole float4 chunks: 16-byte loads, 4 codes per 4-byte store (the same scale and
+    // codes as the scalar form below; the second pass reads the row again from cache)
+    float m = 0.f;
+    for (int k = 4 * l16; k < d; k += 64) {
+      const v4f v = *reinterpret_cast<const v4f*>(a + k);
+      fin = fin && all_finite4(v);
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if (m > 0.f && is_finite_bits(m)) {
+      int e;
+      (void)frexpf(m, &e);
+      scale = ldexpf(1.f, 8 - e);
+    }
+    unsigned* o = reinterpret_cast<unsigned*>(static_cast<unsigned char*>(out) + row * dp);
+    for (int k = 4 * l16; k < dp; k += 64) {
+      v4f v = {0.f, 0.f, 0.f, 0.f};
+      if (k < d) v = *reinterpret_cast<const v4f*>(a + k);
+      o[k / 4] = (unsigned)fp8_of(v.x * scale) | ((unsigned)fp8_of(v.y * scale) << 8) |
+                 ((unsigned)fp8_of(v.z * scale) << 16) | ((unsigned)fp8_of(v.w * scale) << 24);
+    }
+    if (l16 == 0) inv_scale[row] = 1.f / scale;
+  } else if constexpr (FMT == LOWP_FP8) {
     float m = 0.f;
     for (int k = l16; k < d; k += 16) {
       const float v = a[k];
@@ -530,33 +554,70 @@ void lowp_sweep_kernel(LowpParams P) {
     // register with itself the second result holds lanes 32..63 in both halves, and after the
     // 16-lane swap of that with itself the second result holds lanes 48..63 in all four groups.
     if constexpr (GPD) {
-      auto bcast = [&](int st, int b) __attribute__((always_inline)) -> float {
+      auto row15 = [&](int st, int b) __attribute__((always_inline)) -> unsigned {
         const float v3 = GR ? accS[S][st][b][3] + ucn[S][b] : accS[S][st][b][3];
-        const unsigned u3 = __builtin_bit_cast(unsigned, v3);
+        return __builtin_bit_cast(unsigned, v3);
+      };
+      auto bcast = [&](int st, int b) __attribute__((always_inline)) -> float {
+        const unsigned u3 = row15(st, b);
         const auto h32 = __builtin_amdgcn_permlane32_swap(u3, u3, false, false);
         const auto h16 = __builtin_amdgcn_permlane16_swap(h32[1], h32[1], false, false);
         return __builtin_bit_cast(float, (unsigned)h16[1]);
       };
+      // both blocks of a two-block unit at once: with lane groups [x0 x1 x2 x3], the 32-lane
+      // swap of (a, b) leaves [a2 a3 b2 b3] second, the 16-lane swap of that with itself
+      // [a3 a3 b3 b3] second, and the 32-lane swap of that with itself [a3 a3 a3 a3] first and
+      // [b3 b3 b3 b3] second: three swaps for two broadcasts instead of four
+      auto bcast2 = [&](int st, float& e0, float& e1) __attribute__((always_inline)) {
+        const auto h32 = __builtin_amdgcn_permlane32_swap(row15(st, 0), row15(st, 1), false, false);
+        const auto h16 = __builtin_amdgcn_permlane16_swap(h32[1], h32[1], false, false);
+        const auto g32 = __builtin_amdgcn_permlane32_swap(h16[1], h16[1], false, false);
+        e0 = __builtin_bit_cast(float, (unsigned)g32[0]);
+        e1 = __builtin_bit_cast(float, (unsigned)g32[1]);
+      };
       if (GR && samep) {
         // every stripe of the wave has the same centroid row: one broadcast serves them all
+        if constexpr (GU == 2) {
+          float e0, e1;
+          bcast2(0, e0, e1);
 #pragma unroll
-        for (int b = 0; b < GU; ++b) {
-          const float e = bcast(0, b);
+          for (int st = 0; st < SPW; ++st) { espv[st][0] = e0; espv[st][1] = e1; }
+        } else {
 #pragma unroll
-          for (int st = 0; st < SPW; ++st) espv[st][b] = e;
+          for (int b = 0; b < GU; ++b) {
+            const float e = bcast(0, b);
+#pragma unroll
+            for (int st = 0; st < SPW; ++st) espv[st][b] = e;
+          }
         }
       } else if (GR && SPW > 2 && twop) {
+        if constexpr (GU == 2) {
+          float f0, f1, l0, l1;
+          bcast2(0, f0, f1);
+          bcast2(SPW - 1, l0, l1);
 #pragma unroll
-        for (int b = 0; b < GU; ++b) {
-          const float e0 = bcast(0, b), e1 = bcast(SPW - 1, b);
+          for (int st = 0; st < SPW; ++st) {
+            espv[st][0] = psel[st] ? f0 : l0;
+            espv[st][1] = psel[st] ? f1 : l1;
+          }
+        } else {
 #pragma unroll
-          for (int st = 0; st < SPW; ++st) espv[st][b] = psel[st] ? e0 : e1;
+          for (int b = 0; b < GU; ++b) {
+            const float e0 = bcast(0, b), e1 = bcast(SPW - 1, b);
+#pragma unroll
+            for (int st = 0; st < SPW; ++st) espv[st][b] = psel[st] ? e0 : e1;
+          }
         }
       } else {
 #pragma unroll
-        for (int st = 0; st < SPW; ++st)
+        for (int st = 0; st < SPW; ++st) {
+          if constexpr (GU == 2) {
+            bcast2(st, espv[st][0], espv[st][1]);
+          } else {
 #pragma unroll
-          for (int b = 0; b < GU; ++b) espv[st][b] = bcast(st, b);
+            for (int b = 0; b < GU; ++b) espv[st][b] = bcast(st, b);
+          }
+        }
       }
     }
   };
@@ -1100,6 +1161,9 @@ hipError_t launch_lowp_quantize(int fmt, const float* A, int64_t rows, int d, in
   else if (fmt == LOWP_BF16)
     hipLaunchKernelGGL(quantize_rows_kernel<LOWP_BF16>, grid, block, 0, st, A, rows, d, dp,
                        codebook ? -2.f : 1.f, out, inv_scale, counters, live_n);
+  else if (v4)
+    hipLaunchKernelGGL((quantize_rows_kernel<LOWP_FP8, true>), grid, block, 0, st, A, rows, d, dp,
+                       1.f, out, inv_scale, counters, live_n);
   else
     hipLaunchKernelGGL(quantize_rows_kernel<LOWP_FP8>, grid, block, 0, st, A, rows, d, dp, 1.f,
                        out, inv_scale, counters, live_n);
