@@ -15,6 +15,7 @@ differences, in the order the paper states the method:
 * indexing pipeline, Section 3.5: train VQ, primary, residual, spill;
 * further spilled assignments, Section 3.5.1: each adds one Theorem 3.1 penalty per earlier
   residual (a reading: the paper gives no formula);
+* PQ codes of each assignment's residual and the index memory model, Section 3.5;
 * KMR curve, Eq. 1 (Section 2.2.1), with Rank as in Section 2.1.
 
 Readings where the paper is silent (each is listed with its reason in the design notes):
@@ -583,6 +584,67 @@ def verify_further(X, C, lam, prior, gpu_next, gpu_loss=None, band=1e-6, loss_to
         out["loss_ok"] = np.abs(np.asarray(gpu_loss, np.float64) - l_gpu) <= loss_tol * tau
     out["all_ok"] = bool(ok.all() and out.get("loss_ok", np.ones(n, bool)).all())
     return out
+
+
+# ----------------------------------------------------------------------------------------------
+# Product-quantized residual codes and the index memory model (Section 3.5, implementation
+# considerations).  Each assignment of a point stores the PQ code of its own residual x - c_a:
+# with h = 16 centres per subspace of s dimensions a code takes d / (2 s) bytes, plus a 4-byte id
+# in the list; the highest-bitrate copy of the point is stored once.  Spilling therefore adds
+# 4 + d / (2 s) bytes per point.
+# ----------------------------------------------------------------------------------------------
+
+def pq_encode(R, P):
+    """codes[i, m] = argmin_k ||R[i, m s:(m + 1) s] - P[m, k]||^2 (lowest index on ties), all in
+    float64.  R [n x d], P [M x h x s] with d = M s."""
+    R, P = _f64(R), _f64(P)
+    n, d = R.shape
+    M, h, s = P.shape
+    if M * s != d:
+        raise ValueError("P must cover d = M s dimensions")
+    codes = np.empty((n, M), dtype=np.int64)
+    step = max(1, int(_CHUNK_BYTES // max(1, 8 * M * h * s)))
+    for lo in range(0, n, step):
+        hi = min(n, lo + step)
+        diff = R[lo:hi].reshape(hi - lo, M, 1, s) - P[None]
+        codes[lo:hi] = np.argmin((diff * diff).sum(axis=-1), axis=2)
+    return codes
+
+
+def pq_decode(codes, P):
+    """The reconstruction [n x d] of PQ codes [n x M] with codebook P [M x h x s]."""
+    P = _f64(P)
+    M, h, s = P.shape
+    codes = np.asarray(codes, dtype=np.int64)
+    return P[np.arange(M)[None, :], codes].reshape(codes.shape[0], M * s)
+
+
+def soar_pq_codes(X, C, P, assignments):
+    """PQ codes of every assignment's residual: [n x len(assignments) x M]."""
+    X, C = _f64(X), _f64(C)
+    return np.stack([pq_encode(X - C[np.asarray(a, dtype=np.int64)], P) for a in assignments],
+                    axis=1)
+
+
+def pq_pack(codes):
+    """4-bit codes [.., M] (M even, values < 16) as bytes [.., M / 2]: subspace 2 j in the low
+    nibble of byte j, 2 j + 1 in the high nibble."""
+    c = np.asarray(codes, dtype=np.int64)
+    if c.shape[-1] % 2 or (c < 0).any() or (c > 15).any():
+        raise ValueError("4-bit codes of an even number of subspaces")
+    return (c[..., 0::2] | (c[..., 1::2] << 4)).astype(np.uint8)
+
+
+def index_bytes(n, d, s, assignments, highres_bytes_per_dim):
+    """Bytes of a VQ-PQ index: per assignment a 4-byte id and a d / (2 s)-byte PQ code, per point
+    one highest-bitrate copy of highres_bytes_per_dim bytes per dimension."""
+    return n * (assignments * (4 + d / (2 * s)) + highres_bytes_per_dim * d)
+
+
+def spill_memory_overhead(d, s, highres_bytes_per_dim):
+    """Relative index growth from one assignment to two: (4 + d/(2s)) / (hd + 4 + d/(2s))."""
+    extra = 4 + d / (2 * s)
+    return extra / (highres_bytes_per_dim * d + extra)
 
 
 # ----------------------------------------------------------------------------------------------

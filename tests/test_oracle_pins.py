@@ -451,6 +451,83 @@ def test_further_symmetric_in_prior_order_and_fast_equals_plain():
         O.spill_further_plain(X[:1], C[:2], 1.0, np.array([[0, 1]]))
 
 
+# ------------------------------------------------------------------------------------------------
+# PQ residual codes and the memory model (Section 3.5, implementation considerations).
+# ------------------------------------------------------------------------------------------------
+def test_pq_encode_bruteforce_exact():
+    """Exact rational distances per subspace; ties go to the lowest codeword index."""
+    rng = np.random.default_rng(41)
+    for trial in range(60):
+        M, h, s = int(rng.integers(1, 4)), int(rng.integers(2, 6)), int(rng.integers(1, 4))
+        P = rng.integers(-2, 3, size=(M, h, s))
+        if trial % 3 == 0:
+            P[:, -1] = P[:, 0]                         # duplicate codewords: ties
+        R = rng.integers(-3, 4, size=(7, M * s))
+        codes = O.pq_encode(R.astype(np.float32), P.astype(np.float32))
+        for i in range(7):
+            for m in range(M):
+                d2 = [sum((Fr(int(R[i, m * s + t])) - Fr(int(P[m, k, t]))) ** 2 for t in range(s))
+                      for k in range(h)]
+                want = min(range(h), key=lambda k: (d2[k], k))
+                assert codes[i, m] == want, (trial, i, m)
+
+
+def test_soar_pq_codes_encode_each_assignments_residual():
+    """Each assignment's code is the code of x - c_a (integer data: exact), so a point's primary
+    and spilled copies carry different codes of different residuals."""
+    rng = np.random.default_rng(43)
+    X = rng.integers(-4, 5, size=(40, 6)).astype(np.float32)
+    C = rng.integers(-4, 5, size=(9, 6)).astype(np.float32)
+    P = rng.integers(-3, 4, size=(3, 16, 2)).astype(np.float32)
+    a0, a1 = rng.integers(0, 9, 40), rng.integers(0, 9, 40)
+    codes = O.soar_pq_codes(X, C, P, [a0, a1])
+    assert codes.shape == (40, 2, 3)
+    for i in range(40):
+        for j, a in enumerate((a0, a1)):
+            r = X[i].astype(np.int64) - C[a[i]].astype(np.int64)
+            for m in range(3):
+                d2 = [int(((r[2 * m:2 * m + 2] - P[m, k].astype(np.int64)) ** 2).sum())
+                      for k in range(16)]
+                assert codes[i, j, m] == min(range(16), key=lambda k: (d2[k], k))
+
+
+def test_pq_decode_encode_round_trip_and_optimality():
+    rng = np.random.default_rng(42)
+    M, h, s, n = 8, 16, 4, 300
+    P = rng.standard_normal((M, h, s))
+    codes = rng.integers(0, h, size=(n, M))
+    Y = O.pq_decode(codes, P)
+    assert Y.shape == (n, M * s)
+    assert np.array_equal(O.pq_encode(Y, P), codes)      # a codeword encodes to itself
+    R = rng.standard_normal((n, M * s))
+    c = O.pq_encode(R, P)
+    err = ((R - O.pq_decode(c, P)) ** 2).reshape(n, M, s).sum(-1)
+    for k in range(h):                                   # no other codeword is closer
+        other = ((R.reshape(n, M, s) - P[None, :, k, :]) ** 2).sum(-1)
+        assert (err <= other + 1e-12).all()
+    packed = O.pq_pack(c)
+    assert packed.shape == (n, M // 2)
+    assert np.array_equal(packed & 15, c[:, 0::2]) and np.array_equal(packed >> 4, c[:, 1::2])
+
+
+def test_spill_memory_model():
+    """The relative growth is (4 + d/(2s)) / (b d + 4 + d/(2s)); for large d it tends to
+    1/(2s + 1) with int8 and 1/(8s + 1) with float32 copies (Section 3.5), and the float32 case
+    with s = 2 gives the paper's 1/17 estimate for its Glove index."""
+    for s_ in (1, 2, 4):
+        assert O.spill_memory_overhead(10 ** 7, s_, 1) == pytest.approx(1 / (2 * s_ + 1), rel=1e-5)
+        assert O.spill_memory_overhead(10 ** 7, s_, 4) == pytest.approx(1 / (8 * s_ + 1), rel=1e-5)
+    assert O.spill_memory_overhead(10 ** 7, 2, 4) == pytest.approx(1 / 17, rel=1e-5)
+    d, s_ = 128, 2
+    extra = Fr(4) + Fr(d, 2 * s_)
+    assert O.spill_memory_overhead(d, s_, 4) == pytest.approx(float(extra / (4 * d + extra)),
+                                                              rel=1e-15)
+    one = O.index_bytes(1000, d, s_, 1, 4)
+    two = O.index_bytes(1000, d, s_, 2, 4)
+    assert two - one == 1000 * float(extra)
+    assert (two - one) / one == pytest.approx(O.spill_memory_overhead(d, s_, 4), rel=1e-15)
+
+
 def test_input_validation():
     X = np.zeros((3, 2), np.float32)
     with pytest.raises(ValueError):
