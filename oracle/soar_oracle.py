@@ -16,6 +16,9 @@ differences, in the order the paper states the method:
 * further spilled assignments, Section 3.5.1: each adds one Theorem 3.1 penalty per earlier
   residual (a reading: the paper gives no formula);
 * PQ codes of each assignment's residual and the index memory model, Section 3.5;
+* search over the lists with PQ-coded copies (Section 2.2 search, Section 3.5 layout): each
+  probed copy scored from its own residual code, a point keeping its best copy, the best points
+  re-scored exactly (a reading: the paper describes PQ as an intermediate scoring stage);
 * KMR curve, Eq. 1 (Section 2.2.1), with Rank as in Section 2.1.
 
 Readings where the paper is silent (each is listed with its reason in the design notes):
@@ -702,3 +705,100 @@ def search(Q, X, C, assignments, t, k):
         ids[i, :order.size] = cand[order]
         scores[i, :order.size] = s[order]
     return ids, scores, searched
+
+
+# ----------------------------------------------------------------------------------------------
+# Search over the lists with PQ-coded copies (Section 2.2 search, Section 3.5 index layout): the
+# probed partitions' copies are scored from their residual codes, the best points by that score
+# are re-scored exactly.  Every sum here runs in FP64 in one stated order (dimension order, then
+# subspace order), so each ranking decision is reproducible to the last bit.
+# ----------------------------------------------------------------------------------------------
+
+def seq_dot(A, B):
+    """<a_i, b_j> for all rows of A [na x d] and B [nb x d]: FP64, summed in dimension order."""
+    A, B = _f64(A), _f64(B)
+    S = np.zeros((A.shape[0], B.shape[0]))
+    for t in range(A.shape[1]):
+        S += A[:, t, None] * B[None, :, t]
+    return S
+
+
+def probe_partitions_seq(Q, C, t):
+    """probe_partitions with the scores summed in dimension order: (partitions [nq, t] best
+    first, equal scores to the lower index; their scores [nq, t])."""
+    S = seq_dot(Q, C)
+    K = C.shape[0]
+    t = min(int(t), K)
+    cols = np.arange(K)
+    parts = np.empty((S.shape[0], t), dtype=np.int64)
+    for i in range(S.shape[0]):
+        parts[i] = np.lexsort((cols, -S[i]))[:t]
+    return parts, np.take_along_axis(S, parts, axis=1)
+
+
+def pq_lut(q, P):
+    """LUT[m, k] = <q_m, P[m, k]> for one query q [d] and PQ codebook P [M x h x s]: FP64, summed
+    over the s dimensions of the subspace in order."""
+    q, P = _f64(q), _f64(P)
+    M, h, s = P.shape
+    qm = q.reshape(M, s)
+    L = np.zeros((M, h))
+    for t in range(s):
+        L += qm[:, t, None] * P[:, :, t]
+    return L
+
+
+def pq_scores(score_c, lut, codes):
+    """Approximate <q, x> of copies coded by `codes` [n x M] in a partition whose centre scores
+    score_c: score_c + LUT[0, code_0] + LUT[1, code_1] + ..., added in subspace order (FP64)."""
+    codes = np.asarray(codes, dtype=np.int64)
+    a = np.full(codes.shape[0], float(score_c))
+    for m in range(codes.shape[1]):
+        a = a + lut[m, codes[:, m]]
+    return a
+
+
+def search_pq(Q, X, C, assignments, codes, P, t, R, k):
+    """VQ-PQ search with spilled copies.  Per query: the t best partitions (probe_partitions_seq);
+    every copy listed there, i.e. a point i with assignments[j][i] = p, is scored approximately by
+    pq_scores with the code codes[i, j] of its own residual x_i - c_p; a point reached through
+    several probed copies keeps its largest approximate score; the R best points by that score
+    (ties to the lower id) are scored exactly by <q, x> (FP64, dimension order) and the k best
+    of them are returned (ties to the lower id).
+
+    codes: [n x len(assignments) x M] unpacked 4-bit codes.  Returns (ids int64 [nq, k], -1
+    where fewer than k points; scores float64 [nq, k], -inf there; scored int64 [nq]: copies
+    scored from their codes, i.e. the summed sizes of the probed lists)."""
+    Q, X, C = _f64(Q), _f64(X), _f64(C)
+    codes = np.asarray(codes, dtype=np.int64)
+    K = C.shape[0]
+    A = [np.asarray(a, dtype=np.int64) for a in assignments]
+    members = [[np.flatnonzero(a == p) for a in A] for p in range(K)]
+    parts, pscore = probe_partitions_seq(Q, C, t)
+    nq = Q.shape[0]
+    ids = np.full((nq, k), -1, dtype=np.int64)
+    scores = np.full((nq, k), -np.inf)
+    scored = np.zeros(nq, dtype=np.int64)
+    for i in range(nq):
+        lut = pq_lut(Q[i], P)
+        best = {}
+        for r in range(parts.shape[1]):
+            p = int(parts[i, r])
+            for j, mem in enumerate(members[p]):
+                if mem.size == 0:
+                    continue
+                scored[i] += mem.size
+                a = pq_scores(pscore[i, r], lut, codes[mem, j])
+                for v, s in zip(mem.tolist(), a.tolist()):
+                    if v not in best or s > best[v]:
+                        best[v] = s
+        if not best:
+            continue
+        cand = np.fromiter(best.keys(), dtype=np.int64, count=len(best))
+        approx = np.fromiter(best.values(), dtype=np.float64, count=len(best))
+        keep = cand[np.lexsort((cand, -approx))[:R]]
+        exact = seq_dot(X[keep], Q[i:i + 1])[:, 0]
+        order = np.lexsort((keep, -exact))[:k]
+        ids[i, :order.size] = keep[order]
+        scores[i, :order.size] = exact[order]
+    return ids, scores, scored

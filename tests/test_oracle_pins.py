@@ -731,3 +731,122 @@ def test_search_hand_example():
     # partition 0 now lists 0, 2 (primary) and 1, 3 (spilled): the best three by <q, x>
     assert ids.tolist() == [[0, 2, 3]] and searched.tolist() == [4]
     assert scores.tolist() == [[2.0, np.float32(0.1).item(), np.float32(-0.1).item()]]
+
+
+# ------------------------------------------------------------------------------------------------
+# Search over PQ-coded lists (Section 2.2 search with the Section 3.5 index layout)
+# ------------------------------------------------------------------------------------------------
+def test_ordered_sums_exact_on_integers():
+    """seq_dot, probe_partitions_seq and pq_lut against exact integer arithmetic; the ADC
+    identity: the centre's score plus the LUT entries of a code is <q, c + decode(code)>."""
+    rng = np.random.default_rng(61)
+    A = rng.integers(-5, 6, size=(7, 10))
+    B = rng.integers(-5, 6, size=(9, 10))
+    S = O.seq_dot(A.astype(np.float32), B.astype(np.float32))
+    for i in range(7):
+        for j in range(9):
+            assert S[i, j] == sum(int(A[i, u]) * int(B[j, u]) for u in range(10))
+    parts, ps = O.probe_partitions_seq(A.astype(np.float32), B.astype(np.float32), 4)
+    for i in range(7):
+        want = sorted(range(9), key=lambda j: (-int(A[i] @ B[j]), j))[:4]
+        assert parts[i].tolist() == want
+        assert ps[i].tolist() == [float(A[i] @ B[j]) for j in want]
+    P = rng.integers(-3, 4, size=(5, 16, 2))
+    q = A[0]
+    L = O.pq_lut(q.astype(np.float32), P.astype(np.float32))
+    for m in range(5):
+        for k in range(16):
+            assert L[m, k] == int(q[2 * m:2 * m + 2] @ P[m, k])
+    codes = rng.integers(0, 16, size=(30, 5))
+    c = B[3]
+    a = O.pq_scores(float(q @ c), L, codes)
+    dec = O.pq_decode(codes, P.astype(np.float64))
+    assert np.array_equal(a, (dec + c) @ q)
+
+
+def _search_pq_brute(Q, X, C, A, codes, P, t, R, k):
+    """Exact rationals on integer data, straight from the description."""
+    out_i, out_s = [], []
+    K, M = len(C), P.shape[0]
+    s = P.shape[2]
+    for q in Q:
+        qf = [Fr(int(v)) for v in q]
+        dot = lambda v: sum(a * Fr(int(b)) for a, b in zip(qf, v))
+        probe = sorted(range(K), key=lambda j: (-dot(C[j]), j))[:t]
+        best = {}
+        for p in probe:
+            for j, a in enumerate(A):
+                for i in np.flatnonzero(np.asarray(a) == p).tolist():
+                    r_hat = [int(P[m, codes[i, j, m], u]) for m in range(M) for u in range(s)]
+                    v = dot(C[p]) + dot(r_hat)
+                    best[i] = max(best.get(i, v), v)
+        keep = sorted(best, key=lambda i: (-best[i], i))[:R]
+        top = sorted(keep, key=lambda i: (-dot(X[i]), i))[:k]
+        out_i.append(top + [-1] * (k - len(top)))
+        out_s.append([float(dot(X[i])) for i in top] + [-np.inf] * (k - len(top)))
+    return np.array(out_i), np.array(out_s)
+
+
+def test_search_pq_brute_force():
+    """Integer data (every FP64 sum exact, many ties): ids and scores equal an exact-rational
+    evaluation of the description, for depths, re-rank sizes and one or two assignments; the
+    copies scored are the summed sizes of the probed lists."""
+    rng = np.random.default_rng(62)
+    for trial in range(12):
+        n, d, K, s = 60, 4, 6, 2
+        X = rng.integers(-3, 4, size=(n, d)).astype(np.float32)
+        C = rng.integers(-2, 3, size=(K, d)).astype(np.float32)
+        P = rng.integers(-2, 3, size=(d // s, 16, s)).astype(np.float32)
+        Q = rng.integers(-2, 3, size=(5, d)).astype(np.float32)
+        a0 = rng.integers(0, K, n)
+        a1 = (a0 + rng.integers(1, K, n)) % K
+        A = [a0, a1] if trial % 3 else [a0]
+        codes = O.soar_pq_codes(X, C, P, A)
+        t, R, k = int(rng.integers(1, 4)), int(rng.integers(1, 12)), int(rng.integers(1, 6))
+        ids, sc, scored = O.search_pq(Q, X, C, A, codes, P, t, R, k)
+        wi, ws = _search_pq_brute(Q, X, C, A, codes, P, t, R, k)
+        assert np.array_equal(ids, wi), trial
+        assert np.array_equal(sc, ws), trial
+        parts, _ = O.probe_partitions_seq(Q, C, t)
+        assert scored.tolist() == [sum(int((a == p).sum()) for p in pr for a in A) for pr in parts]
+
+
+def test_search_pq_large_rerank_is_exact_search():
+    """With every reached point re-scored (R >= n) the codes only order the candidates, so the
+    result is the exact search over the probed lists (integer data: exact)."""
+    rng = np.random.default_rng(63)
+    n, d, K = 300, 8, 20
+    X = rng.integers(-4, 5, size=(n, d)).astype(np.float32)
+    C = rng.integers(-3, 4, size=(K, d)).astype(np.float32)
+    Q = rng.integers(-3, 4, size=(12, d)).astype(np.float32)
+    P = rng.integers(-2, 3, size=(d // 2, 16, 2)).astype(np.float32)
+    p, _, s_, _ = O.assign(X, C, 1.0)
+    codes = O.soar_pq_codes(X, C, P, [p, s_])
+    for t in (1, 3, K):
+        ids, sc, scored = O.search_pq(Q, X, C, [p, s_], codes, P, t, n, 10)
+        wi, ws, wn = O.search(Q, X, C, [p, s_], t, 10)
+        assert np.array_equal(ids, wi) and np.array_equal(sc, ws) and np.array_equal(scored, wn)
+
+
+def test_search_pq_spilled_copy_uses_its_own_code():
+    """A point whose primary copy's code is poor and whose spilled copy's code is exact is taken
+    into a re-rank of one point through its spilled copy: each copy keeps its own residual's
+    code, and a point its best copy's estimate."""
+    C = np.array([[1.0, 0.0], [0.0, 1.0]], np.float32)
+    P = np.zeros((1, 16, 2), np.float32)
+    P[0, 1] = [1.0, 0.0]                         # exact residual of point 0 from partition 1
+    P[0, 2] = [-4.0, 0.0]
+    X = np.array([[1.0, 1.0], [1.0, 0.5]], np.float32)
+    A = [np.array([0, 0]), np.array([1, 1])]
+    codes = np.zeros((2, 2, 1), np.int64)
+    codes[0, 0, 0] = 2                           # point 0, primary copy: estimate 1 - 4 = -3
+    codes[0, 1, 0] = 1                           # point 0, spilled copy: estimate 1 + 1 = 2
+    codes[1, 0, 0] = 0                           # point 1, primary copy: estimate 1 + 0 = 1
+    codes[1, 1, 0] = 2                           # point 1, spilled copy: estimate -3
+    Q = np.array([[1.0, 1.0]], np.float32)
+    ids, sc, scored = O.search_pq(Q, X, C, A, codes, P, 2, 2, 2)
+    assert ids.tolist() == [[0, 1]] and sc.tolist() == [[2.0, 1.5]] and scored.tolist() == [4]
+    ids, _, _ = O.search_pq(Q, X, C, A, codes, P, 2, 1, 2)
+    assert ids.tolist() == [[0, -1]]
+    ids, _, _ = O.search_pq(Q, X, C, A[:1], codes[:, :1], P, 2, 1, 2)
+    assert ids.tolist() == [[1, -1]]             # without the spilled copies point 1 leads
