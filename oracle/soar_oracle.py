@@ -773,7 +773,13 @@ def search_pq(Q, X, C, assignments, codes, P, t, R, k):
     codes = np.asarray(codes, dtype=np.int64)
     K = C.shape[0]
     A = [np.asarray(a, dtype=np.int64) for a in assignments]
-    members = [[np.flatnonzero(a == p) for a in A] for p in range(K)]
+    # members[p][j]: the points with assignments[j] == p, ascending (a stable sort per assignment)
+    members = [[] for _ in range(K)]
+    for a in A:
+        order = np.argsort(a, kind="stable")
+        bounds = np.searchsorted(a[order], np.arange(K + 1))
+        for p in range(K):
+            members[p].append(order[bounds[p]:bounds[p + 1]])
     parts, pscore = probe_partitions_seq(Q, C, t)
     nq = Q.shape[0]
     ids = np.full((nq, k), -1, dtype=np.int64)
