@@ -41,18 +41,11 @@ TRAFFIC = {
     # BF16, n=10M, d=96, K=40,000: quantization, primary sweep, re-score, grouping, grouped spill
     # sweep over residual rows, re-score (plus the codebook norms and counter resets, 7.5 MB)
     ("bf16", "mix16384_n10m_d96"): dict(
-        fetch_kib=118867289.375, write_kib=5711717.84375,
+        fetch_kib=96044997.8125, write_kib=5712093.4375,
         sources={"paper_2404_00774_amd/csrc/assign_lowp.hip":
-                 "814cbe3a918469dd870a87c8dbe13307344dc72e1e6478d26428a5dfb8931730",
+                 "ddbc17d502a0315a6da72c3f215db9fdac88e927251e490e3ea87ceee35630ed",
                  "paper_2404_00774_amd/csrc/group.hip":
                  "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198",
-                 "paper_2404_00774_amd/csrc/common.h":
-                 "08810850b969fa684bc36a9d5144497379e1c98575c4717106f79b1a8f596bcf"}),
-    # FP8, same workload: direct spill form (two MFMA streams), no grouping
-    ("fp8", "mix16384_n10m_d96"): dict(
-        fetch_kib=51062149.3125, write_kib=3485803.59375,
-        sources={"paper_2404_00774_amd/csrc/assign_lowp.hip":
-                 "814cbe3a918469dd870a87c8dbe13307344dc72e1e6478d26428a5dfb8931730",
                  "paper_2404_00774_amd/csrc/common.h":
                  "08810850b969fa684bc36a9d5144497379e1c98575c4717106f79b1a8f596bcf"}),
     # grouped FP32 pipeline, per step: primary pass, grouping by primary, grouped spill pass
@@ -258,6 +251,44 @@ def search_leg(soar, torch, Xg, Cg, Qg, assign, ts, gt, reps=3):
     return out
 
 
+def search_pq_leg(soar, torch, Xg, Cg, Qg, assign, P, codes, ts, gt, Rs=(100, 1000), reps=3):
+    """Search over the lists with PQ-coded copies (soar_search_pq): every probed copy estimated
+    from its own residual's code, the R best points re-scored exactly; per re-rank size R and
+    probe depth t, queries/s and recall@10, with the spilled lists and with the primary lists
+    only."""
+    return {str(R): _search_pq_rows(soar, torch, Xg, Cg, Qg, assign, P, codes, ts, gt, R, reps)
+            for R in Rs}
+
+
+def _search_pq_rows(soar, torch, Xg, Cg, Qg, assign, P, codes, ts, gt, R, reps):
+    K = Cg.shape[0]
+    nq = Qg.shape[0]
+    out = {}
+    for name, m in (("spilled", 2), ("unspilled", 1)):
+        p = torch.from_numpy(assign[0].astype(np.int32)).cuda()
+        s_ = torch.from_numpy(assign[1].astype(np.int32)).cuda() if m == 2 else None
+        off, ids = soar.build_lists(p, s_, K)
+        A = torch.from_numpy(np.stack(assign[:m], axis=1).astype(np.int32)).cuda()
+        lc, mx = soar.list_codes(off, ids, A, codes[:, :m].contiguous())
+        rows = []
+        for t in ts:
+            r = soar.search_pq(Qg, Cg, Xg, off, ids, lc, P, mx, t, R, 10)   # warm-up and result
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                soar.search_pq(Qg, Cg, Xg, off, ids, lc, P, mx, t, R, 10)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            got = r[0].cpu().numpy()
+            recall = float(np.mean([len(set(a) & set(b)) / 10.0 for a, b in zip(got, gt)]))
+            rows.append({"t": int(t), "queries_per_s": nq / dt, "ms": dt * 1e3,
+                         "recall_at_10": recall,
+                         "copies_estimated": float(r[2].double().mean().item())})
+        out[name] = rows
+        del off, ids, lc
+    return out
+
+
 def further_leg(soar, torch, O, Xg, Cg, X, C, lam, assign, idx, steps, Q, ts, gt):
     """A third assignment per point given the primary and spill (Section 3.5.1, soar_spill_further,
     FP32): device time per call on resident inputs, algorithmic rate against the FP32 MFMA peak,
@@ -292,6 +323,68 @@ def further_leg(soar, torch, O, Xg, Cg, X, C, lam, assign, idx, steps, Q, ts, gt
         out["recall_three_lists"] = [float(v) for v in k3]
         out["points_searched_three_lists"] = [float(v) for v in n3]
     return out
+
+
+def pq_leg(soar, torch, O, Xg, Cg, X, C, assign, idx, steps, s=2, train_rows=100_000):
+    """PQ codes of both assignments' residuals (Section 3.5, soar_pq_encode): a PQ codebook of 16
+    centres per subspace of s dimensions trained on the GPU from primary residuals of a row
+    sample, the encode kernel's time against the HBM roofline, the oracle's codes on the check
+    rows, each residual's relative reconstruction error, and the index bytes with and without the
+    spilled copy (ids, codes and a float32 or int8 copy of every point)."""
+    n, d = Xg.shape
+    K = Cg.shape[0]
+    A = torch.from_numpy(np.stack(assign, axis=1).astype(np.int32)).to(Xg.device)
+    m = A.shape[1]
+    rows = torch.from_numpy(np.sort(np.random.default_rng(11).choice(n, min(n, train_rows),
+                                                                     replace=False))).to(Xg.device)
+    R = (Xg[rows] - Cg[A[rows, 0].long()]).contiguous()
+    t0 = time.perf_counter()
+    P = soar.pq_train(R, s, iters=10)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del R
+    codes = soar.pq_encode(Xg, Cg, A, P)                    # warm-up
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for _ in range(steps):
+        codes = soar.pq_encode(Xg, Cg, A, P)
+    ev[1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps * 1e3
+    dms = ev[0].elapsed_time(ev[1]) / steps
+    nb = d // s // 2
+    # algorithmic bytes: every point row and assignment once, the codebook once, the codes written
+    alg = n * (4 * d + 4 * m + m * nb) + K * 4 * d
+    cn, Pn = codes.cpu().numpy(), P.cpu().numpy()
+    An = A.cpu().numpy()
+    want = O.pq_pack(O.soar_pq_codes(X[idx], C, Pn, [An[idx, j] for j in range(m)]))
+    agree = float(np.mean(cn[idx] == want))
+    err = []
+    for j in range(m):
+        u = cn[idx, j].astype(np.int64)
+        full = np.empty((len(idx), 2 * nb), np.int64)
+        full[:, 0::2], full[:, 1::2] = u & 15, u >> 4
+        r = X[idx].astype(np.float64) - C[An[idx, j]]
+        q = O.pq_decode(full, Pn)
+        err.append(float(((r - q) ** 2).sum() / (r ** 2).sum()))
+    ids = 4
+    mem = {}
+    for name, hb in (("float32", 4), ("int8", 1)):
+        one = n * (ids + nb) + n * hb * d
+        two = n * m * (ids + nb) + n * hb * d
+        mem[name] = {"bytes_one_assignment": int(one), "bytes_with_spill": int(two),
+                     "growth": (two - one) / one,
+                     "model_growth": O.spill_memory_overhead(d, s, hb),
+                     "model_approx_1_over": 8 * s + 1 if hb == 4 else 2 * s + 1}
+    return P, codes, {"s": s, "centres_per_subspace": 16, "subspaces": d // s, "code_bytes": nb,
+            "train_rows": int(len(rows)), "train_s": t_train,
+            "ms_per_call": wall, "device_ms": dms, "algorithmic_bytes_per_call": alg,
+            "achieved_gbs": alg / (dms / 1e3) / 1e9, "hbm_peak_frac": alg / (dms / 1e3) / 8e12,
+            "oracle_check": {"rows": int(len(idx)), "byte_agreement": agree},
+            "relative_error_sum_sq": {"primary": err[0], "spill": err[1] if m > 1 else None},
+            "index_memory": mem}
 
 
 def time_form(soar, torch, Xg, Cg, lam, prec, steps, warmup, n, d, K, keep_candidates=False):
@@ -582,7 +675,7 @@ def main():
             r = time_form(soar, torch, Xg, Cg, lam, prec, steps, warm, n, d, K,
                           keep_candidates=True)
             outs = r.pop("out")
-            if k == 0 and Q is not None:
+            if k == 0 and (Q is not None or li == 0):
                 full[lam] = (outs[0].copy(), outs[1].copy())
             r["out"] = tuple(a[idx] for a in outs)
             if "cands" in r:
@@ -656,6 +749,21 @@ def main():
                               args.form_steps, Q, ts, gt)
         print(f"[bench] further: {further['device_ms']:.3f} ms, "
               f"{further['fp32_peak_frac']:.3f} of FP32 peak", file=sys.stderr, flush=True)
+    pq = None
+    if lams[0] in full and d % 4 == 0:
+        print(f"[bench] PQ codes of both residuals, lambda {lams[0]}", file=sys.stderr,
+              flush=True)
+        P_pq, codes_pq, pq = pq_leg(soar, torch, O, Xg, Cg, X, C, full[lams[0]], idx,
+                                    args.form_steps)
+        print(f"[bench] PQ encode: {pq['device_ms']:.3f} ms, {pq['hbm_peak_frac']:.3f} of HBM "
+              f"peak, byte agreement {pq['oracle_check']['byte_agreement']:.6f}",
+              file=sys.stderr, flush=True)
+        if Q is not None:
+            print(f"[bench] GPU search over PQ-coded lists, lambda {lams[0]}", file=sys.stderr,
+                  flush=True)
+            pq["gpu_search_pq"] = search_pq_leg(soar, torch, Xg, Cg, Qg, full[lams[0]], P_pq,
+                                                codes_pq, ts, gt)
+        del P_pq, codes_pq
     cpu = None
     if not args.no_cpu_baseline and cpu_rows:
         print(f"[bench] CPU baseline: the oracle on {cpu_rows} rows", file=sys.stderr, flush=True)
@@ -680,6 +788,7 @@ def main():
         "recall_at_10": rec,
         "gpu_search": search,
         "further_assignment": further,
+        "pq_codes": pq,
         "train": {"kmeanspp_s": t_kpp, "kmeanspp_rows": int(sub if sub and sub < n else n),
                   "lloyd_s": t_lloyd, "inertia_first": inertia[0], "inertia_last": inertia[-1]},
     }

@@ -179,6 +179,28 @@ soar_status soar_spill_further(const float* X, int64_t n, int32_t d, const float
                                int32_t* next, float* next_loss, void* workspace, size_t ws_bytes,
                                void* stream, soar_stats* stats);
 
+/* ---- PQ codes of the residuals (Section 3.5, implementation considerations) ---- */
+
+/*
+ * For every point i and each of its m assignments a = assign[i m + j], the residual x_i - C[a]
+ * is cut into M = d / s subspaces of s dimensions and each piece is coded by the index of the
+ * nearest of the 16 codewords P[sub][0..15] of its subspace (squared Euclidean distance formed in
+ * FP64 from the FP32 inputs; ties to the lowest index).  A spilled copy of a point thus carries
+ * the code of its own residual; these codes (d / (2 s) bytes) plus a 4-byte id per copy are what
+ * spilling adds to a VQ-PQ index.
+ *   X [n x d], C [K x d]      device float32
+ *   assign [n x m]            device int32, row-major, values in [0, K)
+ *   P [M x 16 x s]            device float32 PQ codebook
+ *   codes [n x m x M/2]       device uint8 output: subspace 2 j in the low nibble of byte j,
+ *                             2 j + 1 in the high nibble
+ *   workspace                 >= 256 bytes of device memory
+ * Requires 1 <= s <= 16, d % (2 s) == 0, d <= 1024 (larger: SOAR_E_UNSUPPORTED).  An assignment
+ * outside [0, K): SOAR_E_INVAL after the call (its code is written as zeros).  Blocking.
+ */
+soar_status soar_pq_encode(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
+                           const int32_t* assign, int32_t m, const float* P, int32_t s,
+                           uint8_t* codes, void* workspace, size_t ws_bytes, void* stream);
+
 /* Bytes of workspace for soar_kmeanspp / soar_lloyd_update / soar_train_codebook. */
 soar_status soar_train_workspace_size(int64_t n, int32_t d, int32_t K, size_t* bytes);
 
@@ -254,6 +276,59 @@ soar_status soar_search(const float* Q, int64_t nq, int32_t d, const float* C, i
                         const float* X, int64_t n, const int64_t* offsets, const int32_t* ids,
                         int32_t t, int32_t k, int32_t* out_ids, double* out_scores,
                         int64_t* searched, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- Lists with PQ-coded copies and their search (Section 2.2 search, Section 3.5 layout) ---- */
+
+/*
+ * The PQ codes of the list entries, in list order: entry pos of list p (offsets, ids from
+ * soar_lists_build) is a copy of point i = ids[pos] in partition p, made by the first
+ * assignment j with assign[i m + j] == p, and takes that copy's code codes[(i m + j) code_bytes
+ * ..] (from soar_pq_encode with the same assign [n x m]).  list_codes [offsets[K] x code_bytes]
+ * device uint8 output.  *max_list (host, nullable) receives the longest list's length, the bound
+ * soar_search_pq's workspace is sized for.  An entry whose point has no assignment to its list,
+ * or an id outside [0, n): SOAR_E_INVAL after the call (its code is written as zeros).
+ * workspace >= 256 bytes of device memory.  Blocking.
+ */
+soar_status soar_lists_codes(const int64_t* offsets, const int32_t* ids, int32_t K, int64_t n,
+                             const int32_t* assign, int32_t m, const uint8_t* codes,
+                             int32_t code_bytes, uint8_t* list_codes, int64_t* max_list,
+                             void* workspace, size_t ws_bytes, void* stream);
+
+/* Bytes of workspace for soar_search_pq with lists no longer than max_list entries
+ * (SOAR_E_UNSUPPORTED when min(t, K) * max_list reaches 2^31). */
+soar_status soar_search_pq_workspace_size(int64_t nq, int32_t d, int32_t K, int32_t t,
+                                          int64_t max_list, size_t* bytes);
+
+/*
+ * VQ-PQ search of nq queries Q [nq x d] over lists whose copies carry PQ codes of their own
+ * residuals.  Per query:
+ *   1. the t partitions with the largest <q, c_p> (FP64 products of the FP32 inputs summed in
+ *      dimension order; equal scores to the lower index) are probed;
+ *   2. every copy listed there is estimated from its code: <q, c_p> + sum over subspaces m, in
+ *      order, of LUT[m][code_m] with LUT[m][c] = <q_m, P[m][c]> (FP64, the s dimensions in
+ *      order), P [M x 16 x s] the PQ codebook, M = d / s;
+ *   3. a point reached through several copies keeps its largest estimate, and the R points with
+ *      the largest estimates (equal estimates: lower id first) are scored exactly by <q, x>
+ *      (FP64, dimension order) over X [n x d];
+ *   4. the k best of them (higher score, then lower id) are returned.
+ *   offsets, ids           lists from soar_lists_build; list_codes [offsets[K] x M/2] from
+ *                          soar_lists_codes (4-byte aligned)
+ *   out_ids [nq x k]       device int32 (-1 where fewer than k points were reached)
+ *   out_scores [nq x k]    device FP64 exact scores (-inf there)
+ *   scored [nq]            device int64, nullable: copies estimated (the probed lists' sizes)
+ * Every step is the same arithmetic in the same order as its definition above, so the result is
+ * reproducible bit for bit.  The lists hold each point at most twice (as soar_lists_build makes
+ * them): only the 2 R best copies of a query can then matter, and the call keeps a superset of
+ * them before selecting.  Requires 1 <= k <= 16, k <= R <= 4096, t >= 1, d % (2 s) == 0,
+ * M <= 512 (larger: SOAR_E_UNSUPPORTED), finite inputs, and no list longer than max_list (else
+ * SOAR_E_INVAL; the workspace is sized for max_list).  Blocking.
+ */
+soar_status soar_search_pq(const float* Q, int64_t nq, int32_t d, const float* C, int32_t K,
+                           const float* X, int64_t n, const int64_t* offsets, const int32_t* ids,
+                           const uint8_t* list_codes, const float* P, int32_t s, int32_t t,
+                           int32_t R, int32_t k, int64_t max_list, int32_t* out_ids,
+                           double* out_scores, int64_t* scored, void* workspace, size_t ws_bytes,
+                           void* stream);
 
 /* ---- Serving: a resident codebook plus inverted lists (Section 2.2) fed by insert requests ---- */
 

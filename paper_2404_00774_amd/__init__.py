@@ -83,11 +83,17 @@ _sig("soar_assign_candidates", [_i64, _i32, _i32, ctypes.POINTER(AssignOpts), ct
 _sig("soar_spill_further_workspace_size", [_i64, _i32, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("soar_spill_further", [_vp, _i64, _i32, _vp, _i32, _vp, _i32, _f32, _f32, _vp, _vp, _vp, _sz,
                             _vp, ctypes.POINTER(Stats)])
+_sig("soar_pq_encode", [_vp, _i64, _i32, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _sz, _vp])
 _sig("soar_lists_workspace_size", [_i64, _i32, ctypes.POINTER(_sz)])
 _sig("soar_lists_build", [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp])
 _sig("soar_search_workspace_size", [_i64, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("soar_search", [_vp, _i64, _i32, _vp, _i32, _vp, _i64, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp,
                      _sz, _vp])
+_sig("soar_lists_codes", [_vp, _vp, _i32, _i64, _vp, _i32, _vp, _i32, _vp, ctypes.POINTER(_i64),
+                          _vp, _sz, _vp])
+_sig("soar_search_pq_workspace_size", [_i64, _i32, _i32, _i32, _i64, ctypes.POINTER(_sz)])
+_sig("soar_search_pq", [_vp, _i64, _i32, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _i32, _i32,
+                        _i32, _i32, _i64, _vp, _vp, _vp, _vp, _sz, _vp])
 _sig("soar_train_workspace_size", [_i64, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("soar_kmeanspp", [_vp, _i64, _i32, _i32, _u64, _vp, _vp, _vp, _sz, _vp])
 _sig("soar_lloyd_update", [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp])
@@ -118,7 +124,8 @@ EXPORTED = [n for n in ("soar_assign_workspace_size", "soar_assign", "soar_assig
                         "soar_index_list", "soar_index_get_stats", "soar_index_chunk_bytes",
                         "soar_lists_workspace_size", "soar_lists_build", "soar_search_workspace_size",
                         "soar_search", "soar_spill_further_workspace_size",
-                        "soar_spill_further",
+                        "soar_spill_further", "soar_pq_encode", "soar_lists_codes",
+                        "soar_search_pq_workspace_size", "soar_search_pq",
                         "soar_index_destroy", "soar_status_string") if hasattr(_lib, n)]
 
 
@@ -279,6 +286,44 @@ def assign_multi(X, C, lam, M, near_tie_rel=0.0, stream=None):
     return torch.stack(A[:M], dim=1), torch.stack(V[:M], dim=1)
 
 
+def pq_encode(X, C, assign, P, stream=None):
+    """soar_pq_encode: 4-bit PQ codes of every assignment's residual.  assign int32 [n, m] (or [n])
+    and P float32 [M, 16, s] on the GPU; returns uint8 [n, m, M / 2] (two codes per byte, the
+    even subspace in the low nibble)."""
+    X, C = _f32_matrix(X, "X"), _f32_matrix(C, "C")
+    n, d = X.shape
+    if not isinstance(assign, torch.Tensor) or assign.dtype != torch.int32 or not assign.is_cuda:
+        raise TypeError("assign must be an int32 tensor on the GPU")
+    if not isinstance(P, torch.Tensor) or P.dtype != torch.float32 or P.dim() != 3 or not P.is_cuda:
+        raise TypeError("P must be a float32 [M, 16, s] tensor on the GPU")
+    A = assign.reshape(n, -1).contiguous()
+    m = A.shape[1]
+    M, h, s = P.shape
+    if h != 16 or M * s != d:
+        raise ValueError("P must be [d / s, 16, s]")
+    codes = torch.empty((n, m, M // 2), dtype=torch.uint8, device=X.device)
+    ws = torch.empty(256, dtype=torch.uint8, device=X.device)
+    _check(_lib.soar_pq_encode(_ptr(X), n, d, _ptr(C), C.shape[0], _ptr(A), m,
+                               _ptr(P.contiguous()), s, _ptr(codes), _ptr(ws), ws.numel(),
+                               _stream(stream)), "soar_pq_encode")
+    return codes
+
+
+def pq_train(R, s, iters=10, seed=0, stream=None):
+    """A PQ codebook [d / s, 16, s] for residual rows R (float32 [n, d] on the GPU): per subspace,
+    k-means++ then `iters` Lloyd iterations (soar_train_codebook) on that subspace's columns."""
+    R = _f32_matrix(R, "R")
+    n, d = R.shape
+    if d % s:
+        raise ValueError("s must divide d")
+    out = []
+    for m in range(d // s):
+        Rm = R[:, m * s:(m + 1) * s].contiguous()
+        Cm, _, _ = train_codebook(Rm, 16, iters, seed=seed + m, stream=stream)
+        out.append(Cm)
+    return torch.stack(out)
+
+
 def train_workspace_size(n, d, K):
     b = _sz()
     _check(_lib.soar_train_workspace_size(n, d, K, ctypes.byref(b)), "soar_train_workspace_size")
@@ -371,6 +416,54 @@ def search(Q, C, X, offsets, ids, t, k=10, stream=None, workspace=None):
                             int(t), int(k), _ptr(out_ids), _ptr(out_sc), _ptr(searched),
                             _ptr(workspace), workspace.numel(), _stream(stream)), "soar_search")
     return out_ids, out_sc, searched
+
+
+def list_codes(offsets, ids, assign, codes, stream=None):
+    """soar_lists_codes: the PQ codes of the list entries in list order.  assign int32 [n, m] and
+    codes uint8 [n, m, M / 2] (soar_pq_encode) on the GPU.  Returns (list_codes uint8
+    [offsets[K], M / 2], max_list: the longest list's length)."""
+    if not isinstance(codes, torch.Tensor) or codes.dtype != torch.uint8 or codes.dim() != 3:
+        raise TypeError("codes must be a uint8 [n, m, M / 2] tensor")
+    n, m, nb = codes.shape
+    A = assign.reshape(n, m).contiguous()
+    if A.dtype != torch.int32:
+        raise TypeError("assign must be int32")
+    K = offsets.numel() - 1
+    out = torch.empty((ids.numel(), nb), dtype=torch.uint8, device=codes.device)
+    ws = torch.empty(256, dtype=torch.uint8, device=codes.device)
+    mx = ctypes.c_int64(0)
+    _check(_lib.soar_lists_codes(_ptr(offsets), _ptr(ids), K, n, _ptr(A), m,
+                                 _ptr(codes.contiguous()), nb, _ptr(out), ctypes.byref(mx),
+                                 _ptr(ws), ws.numel(), _stream(stream)), "soar_lists_codes")
+    return out, mx.value
+
+
+def search_pq(Q, C, X, offsets, ids, list_codes_, P, max_list, t, R, k=10, stream=None,
+              workspace=None):
+    """soar_search_pq: probe t partitions, estimate every listed copy from its PQ code, re-score
+    the R best points exactly and return the k best: (ids int32[nq, k], scores float64[nq, k],
+    scored int64[nq]: copies estimated).  P float32 [d / s, 16, s] on the GPU."""
+    Q, C, X = _f32_matrix(Q, "Q"), _f32_matrix(C, "C"), _f32_matrix(X, "X")
+    nq, d = Q.shape
+    K, n = C.shape[0], X.shape[0]
+    if not isinstance(P, torch.Tensor) or P.dtype != torch.float32 or P.dim() != 3:
+        raise TypeError("P must be a float32 [M, 16, s] tensor")
+    s = P.shape[2]
+    dev = Q.device
+    out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    out_sc = torch.empty((nq, k), dtype=torch.float64, device=dev)
+    scored = torch.empty(nq, dtype=torch.int64, device=dev)
+    b = _sz()
+    _check(_lib.soar_search_pq_workspace_size(nq, d, K, int(t), int(max_list), ctypes.byref(b)),
+           "soar_search_pq_workspace_size")
+    if workspace is None or workspace.numel() < b.value:
+        workspace = torch.empty(max(b.value, 256), dtype=torch.uint8, device=dev)
+    _check(_lib.soar_search_pq(_ptr(Q), nq, d, _ptr(C), K, _ptr(X), n, _ptr(offsets), _ptr(ids),
+                               _ptr(list_codes_), _ptr(P.contiguous()), s, int(t), int(R), int(k),
+                               int(max_list), _ptr(out_ids), _ptr(out_sc), _ptr(scored),
+                               _ptr(workspace), workspace.numel(), _stream(stream)),
+           "soar_search_pq")
+    return out_ids, out_sc, scored
 
 
 class SoarIndex:

@@ -249,16 +249,15 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
                             uint32_t spill_form) {
   LowpLayout L = layout_lowp(ws, n, d, K, fmt, topk);
   // The grouped form trades the second MFMA stream for epilogue work.  Over residual rows
-  // (lambda >= kGroupedResidualMinLam) that work is the direct form's one fma per element, so for
-  // BF16 it pays wherever grouping does (n=10M, d=96, K=40,000: 142.7 vs 173.6 ms).  An FP8
-  // MFMA does four times the work of a BF16 one, so below 512 dimensions the second stream
-  // costs less than the stripes' padding (d=96: 144.3 vs 141.5 ms); at d=768 grouping pays
-  // (7.5 vs 10.3 ms at n=500K).  Over X rows (small lambda) the form costs about two more VALU
-  // operations per element.
+  // (lambda >= kGroupedResidualMinLam) that work is the direct form's one fma per element, so it
+  // pays wherever grouping does: n=10M, d=96, K=40,000, BF16 149.5 vs 186.0 ms per call, FP8
+  // 169.1 vs 178.5 ms; FP8 at d=768, n=500K, 7.5 vs 10.3 ms.  Over X rows (small lambda) the
+  // form costs about two more VALU operations per element, which pays only where the direct
+  // form's two B operands per LDS fetch bound it (FP8 rows of 512 dimensions and more).
   const bool grouped = spill_form == SOAR_SPILL_GROUPED ||
                        (spill_form == 0 && grouped_spill_pays(n, K) &&
-                        (fmt == LOWP_BF16 ? grouped_residual_rows(fmt, lam)
-                                          : lowp_padded_dim(fmt, d) >= 512));
+                        (grouped_residual_rows(fmt, lam) ||
+                         (fmt != LOWP_BF16 && lowp_padded_dim(fmt, d) >= 512)));
   const GroupLayout GL = group_layout(L.group, n, K);
   LowpParams P;
   P.n = n; P.d = d; P.dp = lowp_padded_dim(fmt, d); P.K = K; P.topk = topk;
