@@ -47,17 +47,44 @@ TRAFFIC = {
                  "paper_2404_00774_amd/csrc/group.hip":
                  "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198",
                  "paper_2404_00774_amd/csrc/common.h":
-                 "08810850b969fa684bc36a9d5144497379e1c98575c4717106f79b1a8f596bcf"}),
-    # grouped FP32 pipeline, per step: primary pass, grouping by primary, grouped spill pass
-    ("fp32", "mix4096_n1m_d128"): dict(
-        fetch_kib=256048.0 + 1966.1 + 6.8 + 2041.4 + 85.2 + 2 * 10.2 + 261088.9,
-        write_kib=7820.1 + 960.1 + 15.7 + 10327.4 + 1056.3 + 2 * 7.8 + 65646.3,
-        sources={"paper_2404_00774_amd/csrc/assign_fp32.hip":
-                 "4a87372bd2ae3d68bfc31fc169bbd0b947cc0725726c1eb1b6477972277de292",
+                 "08810850b969fa684bc36a9d5144497379e1c98575c4717106f79b1a8f596bcf",
+                 "paper_2404_00774_amd/csrc/soar_api.hip":
+                 "0f0bd156f3ebf639e438f7d74359f1e1a6c75b952566785d097956e6a548202d"}),
+    # FP8, same workload and the same stages (grouped spill over residual rows)
+    ("fp8", "mix16384_n10m_d96"): dict(
+        fetch_kib=80853062.9375, write_kib=4447144.65625,
+        sources={"paper_2404_00774_amd/csrc/assign_lowp.hip":
+                 "ddbc17d502a0315a6da72c3f215db9fdac88e927251e490e3ea87ceee35630ed",
                  "paper_2404_00774_amd/csrc/group.hip":
                  "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198",
                  "paper_2404_00774_amd/csrc/common.h":
-                 "30af1c3591c8e4aee3673658e5a9f1863ae422a598a1e02c2ad3f5bd7c1f02f5"}),
+                 "08810850b969fa684bc36a9d5144497379e1c98575c4717106f79b1a8f596bcf",
+                 "paper_2404_00774_amd/csrc/soar_api.hip":
+                 "0f0bd156f3ebf639e438f7d74359f1e1a6c75b952566785d097956e6a548202d"}),
+    # grouped FP32 pipeline, per step: codebook packing, primary pass, grouping by primary,
+    # grouped spill pass, exact full scan
+    ("fp32", "mix4096_n1m_d128"): dict(
+        fetch_kib=519893.5, write_kib=87973.0625,
+        sources={"paper_2404_00774_amd/csrc/assign_fp32.hip":
+                 "d1ec9a821044596c233f27954c3f9d87d307d629d95deef8c1f5b8ce9c3e953a",
+                 "paper_2404_00774_amd/csrc/group.hip":
+                 "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198",
+                 "paper_2404_00774_amd/csrc/common.h":
+                 "08810850b969fa684bc36a9d5144497379e1c98575c4717106f79b1a8f596bcf",
+                 "paper_2404_00774_amd/csrc/soar_api.hip":
+                 "0f0bd156f3ebf639e438f7d74359f1e1a6c75b952566785d097956e6a548202d"}),
+    # FP32, n=2M, d=768, K=10,000 (rows in chunks of 128 dimensions): the same stages; the
+    # 30.7 MB codebook does not fit an XCD's L2, so the sweeps refetch it past L2 (5 TB/s)
+    ("fp32", "mix8192_n2m_d768_lognorm"): dict(
+        fetch_kib=1858119085.1875, write_kib=227337.96875,
+        sources={"paper_2404_00774_amd/csrc/assign_fp32.hip":
+                 "d1ec9a821044596c233f27954c3f9d87d307d629d95deef8c1f5b8ce9c3e953a",
+                 "paper_2404_00774_amd/csrc/group.hip":
+                 "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198",
+                 "paper_2404_00774_amd/csrc/common.h":
+                 "08810850b969fa684bc36a9d5144497379e1c98575c4717106f79b1a8f596bcf",
+                 "paper_2404_00774_amd/csrc/soar_api.hip":
+                 "0f0bd156f3ebf639e438f7d74359f1e1a6c75b952566785d097956e6a548202d"}),
 }
 
 

@@ -889,34 +889,55 @@ void lowp_sweep_kernel(LowpParams P) {
 // Candidates of a codebook swept in S splits: per row, the topk smallest (value, column) pairs
 // of the S * topk the splits kept, in order.  The splits partition the columns, so every column
 // appears at most once.
+// Eight lanes per row: lane g holds the row's split candidates g, g + 8, ... (S topk <= 128 of
+// them, so at most 16 per lane, loaded once); each of the topk rounds takes every lane's best
+// candidate after the previous pick, and the row's best of those by three lane swaps.
+constexpr int kMergeLanes = 8;
+constexpr int kMergeMax = 128 / kMergeLanes;
+
 __global__ __launch_bounds__(256) void lowp_merge_kernel(LowpParams P, int S) {
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (r >= live_rows(P.n, P.live_n)) return;
+  const int64_t r = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kMergeLanes;
+  const int g = threadIdx.x % kMergeLanes;
+  const bool live = r < live_rows(P.n, P.live_n);
   const int topk = P.topk, m = S * topk;
-  const int32_t* cj = P.cand_split + r * m;
-  const float* cv = P.cand_val + r * m;
+  int j[kMergeMax];
+  float v[kMergeMax];
+#pragma unroll
+  for (int e = 0; e < kMergeMax; ++e) {
+    const int idx = g + kMergeLanes * e;
+    const bool ok = live && idx < m;
+    j[e] = ok ? P.cand_split[r * m + idx] : -1;
+    v[e] = ok ? P.cand_val[r * m + idx] : kInf;
+  }
   float pv = -kInf;                                // the previous pick: (pv, pj)
   int pj = -1;
   for (int k = 0; k < topk; ++k) {
     float bv = kInf;
     int bj = -1;
-    for (int e = 0; e < m; ++e) {
-      const int j = cj[e];
-      const float v = cv[e];
-      const bool after = v > pv || (v == pv && j > pj);
-      const bool better = bj < 0 || v < bv || (v == bv && j < bj);
-      if (j >= 0 && after && better) { bv = v; bj = j; }
+#pragma unroll
+    for (int e = 0; e < kMergeMax; ++e) {
+      const bool after = v[e] > pv || (v[e] == pv && j[e] > pj);
+      const bool better = bj < 0 || v[e] < bv || (v[e] == bv && j[e] < bj);
+      if (j[e] >= 0 && after && better) { bv = v[e]; bj = j[e]; }
     }
-    P.cand[r * topk + k] = bj;
+#pragma unroll
+    for (int off = kMergeLanes / 2; off >= 1; off >>= 1) {
+      const float ov = __shfl_xor(bv, off);
+      const int oj = __shfl_xor(bj, off);
+      if (oj >= 0 && (bj < 0 || ov < bv || (ov == bv && oj < bj))) { bv = ov; bj = oj; }
+    }
+    if (live && g == 0) P.cand[r * topk + k] = bj;
     if (bj >= 0) { pv = bv; pj = bj; }
   }
 }
 
 hipError_t launch_lowp_merge(const LowpParams& P, hipStream_t st) {
   if (P.ksplit <= 1) return hipSuccess;
-  if (!P.cand_split || !P.cand_val) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(lowp_merge_kernel, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P,
-                     P.ksplit);
+  if (!P.cand_split || !P.cand_val || P.ksplit * P.topk > kMergeLanes * kMergeMax)
+    return hipErrorInvalidValue;
+  const int64_t threads = P.n * kMergeLanes;
+  hipLaunchKernelGGL(lowp_merge_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st,
+                     P, P.ksplit);
   return hipGetLastError();
 }
 

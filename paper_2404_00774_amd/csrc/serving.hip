@@ -79,30 +79,61 @@ __global__ void list_count_kernel(const int32_t* __restrict__ prim, const int32_
 }
 
 // One thread per partition with appends: reserve its new chunks and link them behind its tail.
-// A reservation that the pool cannot hold takes nothing, leaves the list as it was and sets
-// bit 0 of the step's status word.
-__global__ void list_reserve_kernel(ListDev L, unsigned* status) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= L.K) return;
-  const int c = L.cnt[p];
-  if (c <= 0) return;
-  const int old = L.len[p], nw = old + c;
+// A workgroup's partitions reserve their chunks together (a prefix sum of their needs and one
+// compare-and-swap on the pool cursor for the total), so the cursor sees one update per 256
+// partitions instead of one per partition.  If the pool cannot hold the workgroup's total, each
+// partition tries alone; a reservation that the pool cannot hold takes nothing, leaves the list
+// as it was and sets bit 0 of the step's status word.
+constexpr int kReserveThreads = 256;
+
+__device__ __forceinline__ bool reserve_chunks(int32_t* cursor, int chunks, int k, int* base) {
+  int cur = atomicAdd(cursor, 0);
+  for (;;) {
+    if (cur > chunks - k) return false;
+    const int seen = atomicCAS(cursor, cur, cur + k);
+    if (seen == cur) break;
+    cur = seen;
+  }
+  *base = cur;
+  return true;
+}
+
+__global__ __launch_bounds__(kReserveThreads) void list_reserve_kernel(ListDev L,
+                                                                       unsigned* status) {
+  __shared__ int s_k[kReserveThreads];
+  __shared__ int s_base;
+  const int tid = threadIdx.x;
+  const int p = blockIdx.x * kReserveThreads + tid;
+  const int c = p < L.K ? L.cnt[p] : 0;
+  const int old = c > 0 ? L.len[p] : 0, nw = old + (c > 0 ? c : 0);
   const int have = (old + LIST_CH - 1) / LIST_CH, need = (nw + LIST_CH - 1) / LIST_CH;
-  const int k = need - have;
+  const int k = c > 0 ? need - have : 0;
+  // inclusive prefix sum of the chunk needs over the workgroup
+  s_k[tid] = k;
+  __syncthreads();
+  for (int o = 1; o < kReserveThreads; o <<= 1) {
+    const int add = tid >= o ? s_k[tid - o] : 0;
+    __syncthreads();
+    s_k[tid] += add;
+    __syncthreads();
+  }
+  const int total = s_k[kReserveThreads - 1];
+  if (tid == 0) {
+    int b = -1;
+    if (total > 0 && !reserve_chunks(&L.meta[0], L.chunks, total, &b)) b = -1;
+    s_base = b;
+  }
+  __syncthreads();
+  if (c <= 0) return;
   int base = -1;
   if (k > 0) {
-    int cur = atomicAdd(&L.meta[0], 0);
-    for (;;) {
-      if (cur > L.chunks - k) {
-        L.cnt[p] = -1;
-        atomicOr(status, 1u);
-        return;
-      }
-      const int seen = atomicCAS(&L.meta[0], cur, cur + k);
-      if (seen == cur) break;
-      cur = seen;
+    if (s_base >= 0) {
+      base = s_base + s_k[tid] - k;
+    } else if (!reserve_chunks(&L.meta[0], L.chunks, k, &base)) {
+      L.cnt[p] = -1;
+      atomicOr(status, 1u);
+      return;
     }
-    base = cur;
     for (int i = 0; i < k; ++i) L.next[base + i] = i + 1 < k ? base + i + 1 : -1;
     if (old == 0) L.head[p] = base;
     else L.next[L.tail[p]] = base;
@@ -363,7 +394,8 @@ hipError_t enqueue_append(soar_index* ix, Slot& s) {
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((ix->cap + 255) / 256, 1024));
   hipLaunchKernelGGL(list_count_kernel, dim3(g), dim3(256), 0, s.st, s.prim, s.spill, s.live,
                      (int64_t)ix->cap, L);
-  hipLaunchKernelGGL(list_reserve_kernel, dim3((L.K + 255) / 256), dim3(256), 0, s.st, L,
+  hipLaunchKernelGGL(list_reserve_kernel, dim3((L.K + kReserveThreads - 1) / kReserveThreads),
+                     dim3(kReserveThreads), 0, s.st, L,
                      s.status);
   hipLaunchKernelGGL(list_scatter_kernel, dim3(g), dim3(256), 0, s.st, s.prim, s.spill, s.ids,
                      s.live, (int64_t)ix->cap, L);
