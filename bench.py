@@ -43,7 +43,7 @@ TRAFFIC = {
     ("bf16", "mix16384_n10m_d96"): dict(
         fetch_kib=96044997.8125, write_kib=5712093.4375,
         sources={"paper_2404_00774_amd/csrc/assign_lowp.hip":
-                 "ddbc17d502a0315a6da72c3f215db9fdac88e927251e490e3ea87ceee35630ed",
+                 "0a9b42cb0db6a6ab65ef03bbe158e7e7a68c1ba2084aae79fe7189b4c4ca486f",
                  "paper_2404_00774_amd/csrc/group.hip":
                  "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198",
                  "paper_2404_00774_amd/csrc/common.h":
@@ -54,7 +54,7 @@ TRAFFIC = {
     ("fp8", "mix16384_n10m_d96"): dict(
         fetch_kib=80853062.9375, write_kib=4447144.65625,
         sources={"paper_2404_00774_amd/csrc/assign_lowp.hip":
-                 "ddbc17d502a0315a6da72c3f215db9fdac88e927251e490e3ea87ceee35630ed",
+                 "0a9b42cb0db6a6ab65ef03bbe158e7e7a68c1ba2084aae79fe7189b4c4ca486f",
                  "paper_2404_00774_amd/csrc/group.hip":
                  "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198",
                  "paper_2404_00774_amd/csrc/common.h":
