@@ -29,17 +29,20 @@ constexpr int kPQMaxS = 16;
 constexpr int kPQMaxD = 1024;         // 16 d floats of codebook in 64 KB of LDS
 
 // S: the subspace width at compile time (1, 2, 4, 8, 16), or 0 for any width up to 16.
-template <int S>
+// T: the codebook's type in LDS: double where 16 d of them fit 64 KB (d <= 512; no conversion
+// per use), else float.
+template <int S, typename T>
 __global__ __launch_bounds__(256) void pq_encode_kernel(
     const float* __restrict__ X, int64_t n, int d, const float* __restrict__ C, int K,
     const int32_t* __restrict__ assign, int m, const float* __restrict__ P, int s_rt,
     uint8_t* __restrict__ codes, unsigned* bad) {
-  extern __shared__ float sP[];          // [16][s][M]
+  extern __shared__ __attribute__((aligned(16))) char sP_raw[];
+  T* sP = reinterpret_cast<T*>(sP_raw);  // [16][s][M]
   const int s = S ? S : s_rt;
   const int M = d / s;
   for (int i = threadIdx.x; i < kPQCentres * d; i += blockDim.x) {
     const int sub = i / (kPQCentres * s), rem = i % (kPQCentres * s);   // P is [M][16][s]
-    sP[rem * M + sub] = P[i];
+    sP[rem * M + sub] = (T)P[i];
   }
   __syncthreads();
   const int64_t items = n * m * M;       // M is even, so each byte's two subspaces are lanes
@@ -98,9 +101,14 @@ void launch_pq(const float* X, int64_t n, int d, const float* C, int K, const in
                int m, const float* P, int s, uint8_t* codes, unsigned* bad, hipStream_t st) {
   const int64_t items = n * m * (d / s);
   const int64_t blocks = std::min<int64_t>((items + 255) / 256, 8 * 256);
-  hipLaunchKernelGGL(pq_encode_kernel<S>, dim3((unsigned)blocks), dim3(256),
-                     (size_t)kPQCentres * d * sizeof(float), st, X, n, d, C, K, assign, m, P, s,
-                     codes, bad);
+  if ((size_t)kPQCentres * d * sizeof(double) <= 65536)
+    hipLaunchKernelGGL((pq_encode_kernel<S, double>), dim3((unsigned)blocks), dim3(256),
+                       (size_t)kPQCentres * d * sizeof(double), st, X, n, d, C, K, assign, m, P,
+                       s, codes, bad);
+  else
+    hipLaunchKernelGGL((pq_encode_kernel<S, float>), dim3((unsigned)blocks), dim3(256),
+                       (size_t)kPQCentres * d * sizeof(float), st, X, n, d, C, K, assign, m, P,
+                       s, codes, bad);
 }
 
 }  // namespace

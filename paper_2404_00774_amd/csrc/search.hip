@@ -142,6 +142,147 @@ __global__ __launch_bounds__(256) void probe_scores_kernel(const float* __restri
   }
 }
 
+// The t best partitions of each query of a chunk (t <= kSelMax) in the order a stable
+// descending sort gives them (higher score, then lower index), without sorting all K: per query
+// one workgroup finds the t-th largest score T by a radix select over an order-preserving 64-bit
+// image of the scores (six passes of at most 11 bits, counts in LDS), takes every score above T
+// and the lowest-indexed scores equal to T, and sorts those t entries in LDS (bitonic).  The
+// first t places of keys_out / vals_out are written as the sort would write them.
+constexpr int kSelMax = 256;
+constexpr int kSelBins = 2048;
+constexpr int kSelStage = 4096;        // up to this many scores per query are read once, into LDS
+
+__device__ __forceinline__ uint64_t order_key(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+template <bool STAGE>
+__global__ __launch_bounds__(256) void probe_select_kernel(const double* __restrict__ keys,
+                                                           int K, int t, double* keys_out,
+                                                           int32_t* vals_out) {
+  __shared__ double s_keys[STAGE ? kSelStage : 1];
+  __shared__ unsigned hist[kSelBins];
+  __shared__ unsigned part[256];
+  __shared__ uint64_t s_prefix;
+  __shared__ int s_need, s_cnt, s_taken;
+  __shared__ double sel_s[kSelMax];
+  __shared__ int sel_j[kSelMax];
+  const int tid = threadIdx.x, qi = blockIdx.x;
+  const double* kg = keys + (int64_t)qi * K;
+  if constexpr (STAGE)
+    for (int j = tid; j < K; j += 256) s_keys[j] = kg[j];
+  const double* kq = STAGE ? s_keys : kg;
+  if (tid == 0) { s_prefix = 0; s_need = t; }
+  __syncthreads();
+  // radix select: digits of 11 bits from the top (bits 53..63, 42..52, 31..41, 20..30, 9..19),
+  // then the last 9 bits
+  for (int pass = 0; pass < 6; ++pass) {
+    const int base_shift = pass < 5 ? 53 - 11 * pass : 0;
+    const int bits = pass < 5 ? 11 : 9;
+    const uint64_t high_mask = base_shift + bits >= 64 ? 0ull : ~0ull << (base_shift + bits);
+    const uint64_t prefix = s_prefix;
+    const int need = s_need;
+    for (int i = tid; i < kSelBins; i += 256) hist[i] = 0u;
+    __syncthreads();
+    for (int j = tid; j < K; j += 256) {
+      const uint64_t key = order_key(kq[j]);
+      if ((key & high_mask) == prefix)
+        atomicAdd(&hist[(key >> base_shift) & ((1u << bits) - 1u)], 1u);
+    }
+    __syncthreads();
+    // counts from the top digit down: thread i sums the 8 digits nb - 8 i - 1 .. nb - 8 i - 8
+    const int nb = 1 << bits;
+    unsigned mine = 0;
+    for (int u = 0; u < 8; ++u) {
+      const int dgt = nb - 1 - (8 * tid + u);
+      if (dgt >= 0) mine += hist[dgt];
+    }
+    part[tid] = mine;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      const unsigned add = tid >= o ? part[tid - o] : 0u;
+      __syncthreads();
+      part[tid] += add;
+      __syncthreads();
+    }
+    const unsigned before = tid > 0 ? part[tid - 1] : 0u;
+    if (before < (unsigned)need && part[tid] >= (unsigned)need) {
+      unsigned c = before;
+      for (int u = 0; u < 8; ++u) {
+        const int dgt = nb - 1 - (8 * tid + u);
+        if (dgt < 0) break;
+        if (c + hist[dgt] >= (unsigned)need) {
+          s_prefix = prefix | ((uint64_t)dgt << base_shift);
+          s_need = need - (int)c;
+          break;
+        }
+        c += hist[dgt];
+      }
+    }
+    __syncthreads();
+  }
+  const uint64_t T = s_prefix;
+  const int need_eq = s_need;                   // entries equal to T to take, lowest index first
+  if (tid == 0) { s_cnt = 0; s_taken = 0; }
+  __syncthreads();
+  // every key above T
+  for (int j = tid; j < K; j += 256) {
+    const double v = kq[j];
+    if (order_key(v) > T) {
+      const int pos = atomicAdd(&s_cnt, 1);
+      sel_s[pos] = v;
+      sel_j[pos] = j;
+    }
+  }
+  __syncthreads();
+  const int above = s_cnt;
+  // the need_eq lowest-indexed keys equal to T, in index order
+  for (int j0 = 0; j0 < K && s_taken < need_eq; j0 += 256) {
+    const int j = j0 + tid;
+    const bool eq = j < K && order_key(kq[j]) == T;
+    part[tid] = eq ? 1u : 0u;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      const unsigned add = tid >= o ? part[tid - o] : 0u;
+      __syncthreads();
+      part[tid] += add;
+      __syncthreads();
+    }
+    const int rank = s_taken + (int)part[tid] - 1;
+    if (eq && rank < need_eq) {
+      sel_s[above + rank] = kq[j];
+      sel_j[above + rank] = j;
+    }
+    __syncthreads();
+    if (tid == 0) s_taken += (int)part[255];
+    __syncthreads();
+  }
+  // bitonic sort of the t selected entries (padded to kSelMax): higher score, then lower index
+  if (tid >= t) { sel_s[tid] = -__builtin_inf(); sel_j[tid] = 0x7fffffff; }
+  __syncthreads();
+  for (int k = 2; k <= kSelMax; k <<= 1) {
+    for (int h = k >> 1; h > 0; h >>= 1) {
+      const int o = tid ^ h;
+      if (o > tid) {
+        const bool up = (tid & k) == 0;        // this half ascends in the sort order
+        const double a = sel_s[tid], b = sel_s[o];
+        const int ia = sel_j[tid], ib = sel_j[o];
+        const bool a_first = a > b || (a == b && ia < ib);
+        if (up ? !a_first : a_first) {
+          sel_s[tid] = b; sel_s[o] = a;
+          sel_j[tid] = ib; sel_j[o] = ia;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid < t) {
+    keys_out[(int64_t)qi * K + tid] = sel_s[tid];
+    vals_out[(int64_t)qi * K + tid] = sel_j[tid];
+  }
+}
+
 // (score, id) order of the results: higher score first, then lower id.
 __device__ __forceinline__ bool better(double s, int i, double t, int j) {
   return s > t || (s == t && i < j);
@@ -626,6 +767,24 @@ SearchLayout search_layout(void* ws, int64_t nq, int K) {
 }
 
 
+// The first t places of keys_out / vals_out per query: the selection kernel for t <= kSelMax,
+// else a stable descending segmented sort of all K scores.
+bool probe_top(const SearchLayout& L, int nqc, int K, int t, hipStream_t st) {
+  if (t <= kSelMax) {
+    if (K <= kSelStage)
+      hipLaunchKernelGGL(probe_select_kernel<true>, dim3(nqc), dim3(256), 0, st, L.keys_in, K, t,
+                         L.keys_out, L.vals_out);
+    else
+      hipLaunchKernelGGL(probe_select_kernel<false>, dim3(nqc), dim3(256), 0, st, L.keys_in, K,
+                         t, L.keys_out, L.vals_out);
+    return hipGetLastError() == hipSuccess;
+  }
+  size_t tb = L.temp_bytes;
+  return hipcub::DeviceSegmentedRadixSort::SortPairsDescending(
+             L.temp, tb, L.keys_in, L.keys_out, L.vals_in, L.vals_out, nqc * K, nqc, L.seg,
+             L.seg + 1, 0, 64, st) == hipSuccess;
+}
+
 // Workspace of soar_search_pq: the probe's sort arrays for nqc queries and the candidate arrays
 // (ids and estimates, twice each, and the sorts' temporary storage) for nqc queries of at most
 // t * max_list copies each.
@@ -768,11 +927,7 @@ soar_status soar_search(const float* Q, int64_t nq, int32_t d, const float* C, i
     const int nqc = (int)std::min<int64_t>(L.nqc, nq - q0);
     hipLaunchKernelGGL(probe_scores_kernel, dim3((K + kPC - 1) / kPC, (nqc + kPQ - 1) / kPQ),
                        dim3(256), 0, st, Q, q0, nqc, d, C, K, L.keys_in, L.vals_in, L.seg);
-    size_t tb = L.temp_bytes;
-    if (hipcub::DeviceSegmentedRadixSort::SortPairsDescending(
-            L.temp, tb, L.keys_in, L.keys_out, L.vals_in, L.vals_out, nqc * K, nqc, L.seg,
-            L.seg + 1, 0, 64, st) != hipSuccess)
-      return SOAR_E_DEVICE;
+    if (!probe_top(L, nqc, K, t, st)) return SOAR_E_DEVICE;
     if ((d & 3) == 0)
       hipLaunchKernelGGL(rerank_kernel<true>, dim3(nqc), dim3(kRerankThreads), 0, st, Q, q0, d,
                          X, offsets, ids, L.vals_out, K, t, k, out_ids, out_scores, searched);
@@ -852,11 +1007,8 @@ soar_status soar_search_pq(const float* Q, int64_t nq, int32_t d, const float* C
     SearchLayout& PL = L.probe;
     hipLaunchKernelGGL(probe_scores_kernel, dim3((K + kPC - 1) / kPC, (nqc + kPQ - 1) / kPQ),
                        dim3(256), 0, st, Q, q0, nqc, d, C, K, PL.keys_in, PL.vals_in, PL.seg);
+    if (!probe_top(PL, nqc, K, t, st)) return SOAR_E_DEVICE;
     size_t tb = L.temp_bytes;
-    if (hipcub::DeviceSegmentedRadixSort::SortPairsDescending(
-            L.temp, tb, PL.keys_in, PL.keys_out, PL.vals_in, PL.vals_out, nqc * K, nqc, PL.seg,
-            PL.seg + 1, 0, 64, st) != hipSuccess)
-      return SOAR_E_DEVICE;
     hipLaunchKernelGGL(pq_slots_kernel, dim3((nqc + 255) / 256), dim3(256), 0, st, offsets,
                        PL.vals_out, K, nqc, t, L.slot, L.cnt, scored, q0);
     hipLaunchKernelGGL(pq_seg_kernel, dim3(1), dim3(1024), 0, st, L.cnt, nqc, L.seg);

@@ -90,3 +90,26 @@ def test_search_ties_and_short_lists():
         _compare(got, O.search(Q, X, C, [p, s], t, 16), Q, X)
     with pytest.raises(soar.SoarError):
         soar.search(_t(Q), _t(C), _t(X), off, ids, 2, 17)
+
+
+@pytest.mark.parametrize("K", [300, 5000])
+def test_probe_selection_ties_and_depths(K):
+    """The probe keeps a query's t best partitions in the order of a stable descending sort:
+    integer centroids and queries make many exact score ties across the t-th place, on both
+    sides of the depth where the selection hands over to the full sort (t = 256), and with more
+    centroids than the selection stages in LDS (K = 5000)."""
+    rng = np.random.default_rng(K)
+    n, d = 6000, 8
+    C = rng.integers(-2, 3, size=(K, d)).astype(np.float32)
+    X = (C[rng.integers(0, K, n)] + rng.standard_normal((n, d)) * 0.3).astype(np.float32)
+    Q = rng.integers(-2, 3, size=(30, d)).astype(np.float32)
+    a0 = rng.integers(0, K, n)
+    a1 = (a0 + rng.integers(1, K, n)) % K
+    soar = _soar()
+    import torch
+    off, ids = soar.build_lists(torch.from_numpy(a0.astype(np.int32)).cuda(),
+                                torch.from_numpy(a1.astype(np.int32)).cuda(), K)
+    for t in (1, 3, 64, 255, 256, 257, 400):
+        print(f"probe selection K={K} t={t}", flush=True)
+        got = soar.search(_t(Q), _t(C), _t(X), off, ids, t, 10)
+        _compare(got, O.search(Q, X, C, [a0, a1], t, 10), Q, X)
