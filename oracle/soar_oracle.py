@@ -16,6 +16,8 @@ differences, in the order the paper states the method:
 * further spilled assignments, Section 3.5.1: each adds one Theorem 3.1 penalty per earlier
   residual (a reading: the paper gives no formula);
 * PQ codes of each assignment's residual and the index memory model, Section 3.5;
+* two-level VQ probing (App. A.4.1): the partition centres quantized again, a query's partitions
+  taken from the lists of its best upper centroids;
 * search over the lists with PQ-coded copies (Section 2.2 search, Section 3.5 layout): each
   probed copy scored from its own residual code, a point keeping its best copy, the best points
   re-scored exactly (a reading: the paper describes PQ as an intermediate scoring stage);
@@ -808,3 +810,57 @@ def search_pq(Q, X, C, assignments, codes, P, t, R, k):
         ids[i, :order.size] = keep[order]
         scores[i, :order.size] = exact[order]
     return ids, scores, scored
+
+
+# ----------------------------------------------------------------------------------------------
+# Two-level VQ (App. A.4.1: the partition centres are vector-quantized again): a query probes the
+# upper centroids first and scores only the partitions listed under the best of them.
+# ----------------------------------------------------------------------------------------------
+
+def probe_two_level(Q, U, upper_assign, C, t2, t):
+    """Per query: the t2 upper centroids with the largest <q, u> (seq_dot; equal scores to the
+    lower index), the partitions p with upper_assign[p] among them, and of those the t with the
+    largest <q, c_p> (seq_dot; equal scores to the lower partition index), best first.
+
+    Returns (parts int64 [nq, t], -1 where fewer than t partitions were listed; their scores
+    float64 [nq, t], -inf there)."""
+    ua = np.asarray(upper_assign, dtype=np.int64)
+    uparts, _ = probe_partitions_seq(Q, U, t2)
+    S = seq_dot(Q, C)
+    nq = S.shape[0]
+    parts = np.full((nq, t), -1, dtype=np.int64)
+    scores = np.full((nq, t), -np.inf)
+    for i in range(nq):
+        cand = np.flatnonzero(np.isin(ua, uparts[i]))
+        if cand.size == 0:
+            continue
+        order = np.lexsort((cand, -S[i, cand]))[:t]
+        parts[i, :order.size] = cand[order]
+        scores[i, :order.size] = S[i, cand[order]]
+    return parts, scores
+
+
+def search_two_level(Q, X, C, U, upper_assign, assignments, t2, t, k):
+    """search() with the partitions of probe_two_level: the union of the probed lists (a point
+    listed twice counts once) scored exactly by <q, x> (FP64, dimension order), the k best returned
+    (ties to the lower id).  Returns (ids [nq, k] with -1 padding, scores [nq, k] with -inf
+    padding, searched [nq]: the summed sizes of the probed lists)."""
+    Q, X = _f64(Q), _f64(X)
+    K = np.asarray(C).shape[0]
+    lists = partition_lists(assignments, K)
+    parts, _ = probe_two_level(Q, U, upper_assign, C, t2, t)
+    nq = Q.shape[0]
+    ids = np.full((nq, k), -1, dtype=np.int64)
+    scores = np.full((nq, k), -np.inf)
+    searched = np.zeros(nq, dtype=np.int64)
+    for i in range(nq):
+        members = [lists[p] for p in parts[i] if p >= 0]
+        searched[i] = sum(len(m) for m in members)
+        cand = np.unique(np.concatenate(members)) if members else np.empty(0, np.int64)
+        if cand.size == 0:
+            continue
+        s = seq_dot(X[cand], Q[i:i + 1])[:, 0]
+        order = np.lexsort((cand, -s))[:k]
+        ids[i, :order.size] = cand[order]
+        scores[i, :order.size] = s[order]
+    return ids, scores, searched

@@ -850,3 +850,55 @@ def test_search_pq_spilled_copy_uses_its_own_code():
     assert ids.tolist() == [[0, -1]]
     ids, _, _ = O.search_pq(Q, X, C, A[:1], codes[:, :1], P, 2, 1, 2)
     assert ids.tolist() == [[1, -1]]             # without the spilled copies point 1 leads
+
+
+# ------------------------------------------------------------------------------------------------
+# Two-level VQ probing (App. A.4.1)
+# ------------------------------------------------------------------------------------------------
+def test_two_level_probe_brute_force_and_full_upper_probe():
+    """Integer data, exact: the upper probe, the listed partitions and the top t by score then
+    index follow the description; probing every upper centroid gives the flat probe; fewer listed
+    partitions than t leave -1 places."""
+    rng = np.random.default_rng(71)
+    for trial in range(20):
+        K, K2, d = int(rng.integers(3, 25)), int(rng.integers(1, 6)), int(rng.integers(1, 5))
+        C = rng.integers(-2, 3, size=(K, d)).astype(np.float32)
+        U = rng.integers(-2, 3, size=(K2, d)).astype(np.float32)
+        ua = rng.integers(0, K2, K)
+        Q = rng.integers(-2, 3, size=(6, d)).astype(np.float32)
+        t2, t = int(rng.integers(1, K2 + 1)), int(rng.integers(1, K + 3))
+        parts, sc = O.probe_two_level(Q, U, ua, C, t2, t)
+        for i, q in enumerate(Q.astype(np.int64)):
+            ups = sorted(range(K2), key=lambda u: (-int(q @ U[u]), u))[:t2]
+            cand = [p for p in range(K) if ua[p] in ups]
+            want = sorted(cand, key=lambda p: (-int(q @ C[p]), p))[:t]
+            assert parts[i].tolist() == want + [-1] * (t - len(want)), trial
+            assert sc[i, :len(want)].tolist() == [float(q @ C[p]) for p in want]
+        flat, fsc = O.probe_partitions_seq(Q, C, min(t, K))
+        parts, sc = O.probe_two_level(Q, U, ua, C, K2, min(t, K))
+        assert np.array_equal(parts, flat) and np.array_equal(sc, fsc)
+
+
+def test_two_level_search_full_upper_probe_is_flat_search_and_a_missed_partition():
+    rng = np.random.default_rng(72)
+    n, d, K, K2 = 400, 6, 30, 5
+    X = rng.integers(-3, 4, size=(n, d)).astype(np.float32)
+    C = rng.integers(-2, 3, size=(K, d)).astype(np.float32)
+    U = rng.integers(-2, 3, size=(K2, d)).astype(np.float32)
+    ua = rng.integers(0, K2, K)
+    Q = rng.integers(-2, 3, size=(10, d)).astype(np.float32)
+    p, _, s_, _ = O.assign(X, C, 1.0)
+    for t in (1, 4, K):
+        got = O.search_two_level(Q, X, C, U, ua, [p, s_], K2, t, 8)
+        want = O.search(Q, X, C, [p, s_], t, 8)
+        for g, w in zip(got, want):
+            assert np.array_equal(g, w)
+    # the query's best partition sits under the second upper centroid, which is not probed
+    C2 = np.array([[3.0, 0.0], [1.0, 0.0], [0.0, 1.0]], np.float32)
+    U2 = np.array([[1.0, 0.0], [0.0, 1.0]], np.float32)
+    ua2 = np.array([1, 0, 1])
+    q = np.array([[1.0, 0.2]], np.float32)
+    parts, _ = O.probe_two_level(q, U2, ua2, C2, 1, 2)
+    assert parts.tolist() == [[1, -1]]
+    parts, _ = O.probe_two_level(q, U2, ua2, C2, 2, 2)
+    assert parts.tolist() == [[0, 1]]
