@@ -278,6 +278,39 @@ def search_leg(soar, torch, Xg, Cg, Qg, assign, ts, gt, reps=3):
     return out
 
 
+def two_level_leg(soar, torch, Xg, Cg, Qg, assign, ts, gt, K2=64, t2s=(2, 8, 32), reps=3):
+    """Two-level VQ probing (App. A.4.1, soar_search_two_level): an upper codebook of K2
+    centroids trained on the partition centres (k-means++ and 10 Lloyd iterations on the GPU),
+    each partition listed under its nearest upper centroid; per t2 and probe depth t, queries/s,
+    recall@10 and the partitions probed, over the spilled lists."""
+    K = Cg.shape[0]
+    nq = Qg.shape[0]
+    Ug, _, _ = soar.train_codebook(Cg, K2, 10)
+    ua, _, _, _ = soar.assign(Cg, Ug, 0.0)
+    uoff, uids = soar.build_lists(ua, None, K2)
+    p = torch.from_numpy(assign[0].astype(np.int32)).cuda()
+    s_ = torch.from_numpy(assign[1].astype(np.int32)).cuda()
+    off, ids = soar.build_lists(p, s_, K)
+    out = {"K2": K2, "upper_list_max": int((uoff[1:] - uoff[:-1]).max().item())}
+    for t2 in t2s:
+        rows = []
+        for t in ts:
+            r = soar.search_two_level(Qg, Ug, uoff, uids, t2, Cg, Xg, off, ids, t, 10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                soar.search_two_level(Qg, Ug, uoff, uids, t2, Cg, Xg, off, ids, t, 10)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            got = r[0].cpu().numpy()
+            recall = float(np.mean([len(set(a) & set(b)) / 10.0 for a, b in zip(got, gt)]))
+            rows.append({"t": int(t), "queries_per_s": nq / dt, "ms": dt * 1e3,
+                         "recall_at_10": recall,
+                         "points_searched": float(r[2].double().mean().item())})
+        out[str(t2)] = rows
+    return out
+
+
 def search_pq_leg(soar, torch, Xg, Cg, Qg, assign, P, codes, ts, gt, Rs=(100, 1000), reps=3):
     """Search over the lists with PQ-coded copies (soar_search_pq): every probed copy estimated
     from its own residual's code, the R best points re-scored exactly; per re-rank size R and
@@ -768,6 +801,8 @@ def main():
         for lam, assign in full.items():
             print(f"[bench] GPU search, lambda {lam}", file=sys.stderr, flush=True)
             search[str(lam)] = search_leg(soar, torch, Xg, Cg, Qg, assign, ts, gt)
+        print(f"[bench] two-level probing, lambda {lams[0]}", file=sys.stderr, flush=True)
+        search["two_level"] = two_level_leg(soar, torch, Xg, Cg, Qg, full[lams[0]], ts, gt)
     further = None
     if Q is not None and lams[0] in full:
         print(f"[bench] further spilled assignment (third list), lambda {lams[0]}",

@@ -277,6 +277,33 @@ soar_status soar_search(const float* Q, int64_t nq, int32_t d, const float* C, i
                         int32_t t, int32_t k, int32_t* out_ids, double* out_scores,
                         int64_t* searched, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- Two-level VQ probing (App. A.4.1: the partition centres vector-quantized again) ---- */
+
+/* Bytes of workspace for soar_search_two_level. */
+soar_status soar_search_two_level_workspace_size(int64_t nq, int32_t d, int32_t K, int32_t K2,
+                                                 size_t* bytes);
+
+/*
+ * soar_search with a two-level probe.  The K partition centres C are themselves quantized by an
+ * upper codebook U [K2 x d] (device FP32); upper_offsets [K2 + 1] / upper_ids list the partitions
+ * under each upper centroid (soar_lists_build over the partitions' upper assignment, n = K).
+ * Per query the t2 upper centroids with the largest <q, u> are probed, every partition listed
+ * under them is scored by <q, c_p>, and the t best of those (equal scores to the lower index)
+ * are searched as soar_search does: their lists' points scored exactly, the k best distinct
+ * points returned.  All inner products are FP64 sums of the FP32 products in dimension order, so
+ * with t2 = K2 the probed partitions, and the result, are soar_search's.  A query whose probed
+ * upper lists hold fewer than t partitions searches those.  out_ids / out_scores / searched as
+ * for soar_search.  Requires 1 <= k <= 16, t >= 1, t2 >= 1, d <= 1024 (larger:
+ * SOAR_E_UNSUPPORTED), finite inputs.  Blocking.
+ */
+soar_status soar_search_two_level(const float* Q, int64_t nq, int32_t d, const float* U,
+                                  int32_t K2, const int64_t* upper_offsets,
+                                  const int32_t* upper_ids, int32_t t2, const float* C, int32_t K,
+                                  const float* X, int64_t n, const int64_t* offsets,
+                                  const int32_t* ids, int32_t t, int32_t k, int32_t* out_ids,
+                                  double* out_scores, int64_t* searched, void* workspace,
+                                  size_t ws_bytes, void* stream);
+
 /* ---- Lists with PQ-coded copies and their search (Section 2.2 search, Section 3.5 layout) ---- */
 
 /*

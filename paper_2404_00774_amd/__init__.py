@@ -94,6 +94,9 @@ _sig("soar_lists_codes", [_vp, _vp, _i32, _i64, _vp, _i32, _vp, _i32, _vp, ctype
 _sig("soar_search_pq_workspace_size", [_i64, _i32, _i32, _i32, _i64, ctypes.POINTER(_sz)])
 _sig("soar_search_pq", [_vp, _i64, _i32, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _i32, _i32,
                         _i32, _i32, _i64, _vp, _vp, _vp, _vp, _sz, _vp])
+_sig("soar_search_two_level_workspace_size", [_i64, _i32, _i32, _i32, ctypes.POINTER(_sz)])
+_sig("soar_search_two_level", [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _i64,
+                               _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp])
 _sig("soar_train_workspace_size", [_i64, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("soar_kmeanspp", [_vp, _i64, _i32, _i32, _u64, _vp, _vp, _vp, _sz, _vp])
 _sig("soar_lloyd_update", [_vp, _i64, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp])
@@ -126,6 +129,7 @@ EXPORTED = [n for n in ("soar_assign_workspace_size", "soar_assign", "soar_assig
                         "soar_search", "soar_spill_further_workspace_size",
                         "soar_spill_further", "soar_pq_encode", "soar_lists_codes",
                         "soar_search_pq_workspace_size", "soar_search_pq",
+                        "soar_search_two_level_workspace_size", "soar_search_two_level",
                         "soar_index_destroy", "soar_status_string") if hasattr(_lib, n)]
 
 
@@ -415,6 +419,33 @@ def search(Q, C, X, offsets, ids, t, k=10, stream=None, workspace=None):
     _check(_lib.soar_search(_ptr(Q), nq, d, _ptr(C), K, _ptr(X), n, _ptr(offsets), _ptr(ids),
                             int(t), int(k), _ptr(out_ids), _ptr(out_sc), _ptr(searched),
                             _ptr(workspace), workspace.numel(), _stream(stream)), "soar_search")
+    return out_ids, out_sc, searched
+
+
+def search_two_level(Q, U, upper_offsets, upper_ids, t2, C, X, offsets, ids, t, k=10,
+                     stream=None, workspace=None):
+    """soar_search_two_level: probe the t2 best upper centroids of U, then the t best of the
+    partitions listed under them (upper_offsets / upper_ids: lists of partitions, e.g. from
+    build_lists over the partitions' upper assignment), then search their lists as search():
+    (ids int32[nq, k], scores float64[nq, k], searched int64[nq])."""
+    Q, U, C, X = (_f32_matrix(a, nm) for a, nm in ((Q, "Q"), (U, "U"), (C, "C"), (X, "X")))
+    nq, d = Q.shape
+    K, K2, n = C.shape[0], U.shape[0], X.shape[0]
+    dev = Q.device
+    out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    out_sc = torch.empty((nq, k), dtype=torch.float64, device=dev)
+    searched = torch.empty(nq, dtype=torch.int64, device=dev)
+    b = _sz()
+    _check(_lib.soar_search_two_level_workspace_size(nq, d, K, K2, ctypes.byref(b)),
+           "soar_search_two_level_workspace_size")
+    if workspace is None or workspace.numel() < b.value:
+        workspace = torch.empty(max(b.value, 256), dtype=torch.uint8, device=dev)
+    _check(_lib.soar_search_two_level(_ptr(Q), nq, d, _ptr(U), K2, _ptr(upper_offsets),
+                                      _ptr(upper_ids), int(t2), _ptr(C), K, _ptr(X), n,
+                                      _ptr(offsets), _ptr(ids), int(t), int(k), _ptr(out_ids),
+                                      _ptr(out_sc), _ptr(searched), _ptr(workspace),
+                                      workspace.numel(), _stream(stream)),
+           "soar_search_two_level")
     return out_ids, out_sc, searched
 
 

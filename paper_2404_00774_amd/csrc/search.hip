@@ -434,8 +434,8 @@ template <bool VEC>
 __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(
     const float* __restrict__ Q, int64_t q0, int d, const float* __restrict__ X,
     const int64_t* __restrict__ off, const int32_t* __restrict__ ids,
-    const int32_t* __restrict__ order, int K, int t, int k, int32_t* out_ids, double* out_scores,
-    int64_t* searched) {
+    const int32_t* __restrict__ order, const double* __restrict__ oscore, int K, int t, int k,
+    int32_t* out_ids, double* out_scores, int64_t* searched) {
   __shared__ float s_rows[kRerankThreads][kRD + 1];
   __shared__ float s_q[kRD];
   __shared__ double s_ws[kRerankThreads / 64];
@@ -451,6 +451,7 @@ __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(
 #pragma unroll
   for (int m = 0; m < kSearchMaxK; ++m) { sc[m] = -__builtin_inf(); id_[m] = 0x7fffffff; }
   for (int r = 0; r < t; ++r) {
+    if (oscore && oscore[(int64_t)qi * K + r] == -__builtin_inf()) break;   // nothing listed
     const int p = order[(int64_t)qi * K + r];
     const int64_t b = off[p], e = off[p + 1];
     count += e - b;
@@ -729,6 +730,63 @@ __global__ __launch_bounds__(kRerankThreads) void pq_rerank_kernel(
   emit_best(sc, id_, k, out_ids + qg * k, out_scores + qg * k, s_ws, s_wi);
 }
 
+// Second level of a two-level probe: for each of a query's t2 best upper centroids (one
+// workgroup each), every partition listed under it gets its score <q, c_p> at place p of the
+// query's K scores (FP64 in dimension order from zero, as probe_scores_kernel forms it); the
+// places of partitions not listed stay -inf.
+__global__ __launch_bounds__(256) void probe_second_kernel(
+    const float* __restrict__ Q, int64_t q0, int d, const float* __restrict__ C, int K,
+    const int64_t* __restrict__ uoff, const int32_t* __restrict__ uids,
+    const int32_t* __restrict__ uorder, int K2, double* keys) {
+  __shared__ float sq[1024];
+  const int r = blockIdx.x, qi = blockIdx.y;
+  const float* q = Q + (q0 + qi) * (int64_t)d;
+  for (int j = threadIdx.x; j < d; j += blockDim.x) sq[j] = q[j];
+  __syncthreads();
+  const int u = uorder[(int64_t)qi * K2 + r];
+  for (int64_t pos = uoff[u] + threadIdx.x; pos < uoff[u + 1]; pos += blockDim.x) {
+    const int p = uids[pos];
+    if (p < 0 || p >= K) continue;
+    const float* c = C + (int64_t)p * d;
+    double acc = 0.0;
+    for (int j = 0; j < d; ++j) acc = fma((double)sq[j], (double)c[j], acc);
+    keys[(int64_t)qi * K + p] = acc + 0.0;
+  }
+}
+
+// Segment bounds q K of nqc queries of K scores, and the index of every place (the inputs a
+// segmented sort of the scores needs when the probe depth is beyond the selection's).
+__global__ void seg_bounds_kernel(int nqc, int K, int* seg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= nqc) seg[i] = i * K;
+}
+
+__global__ void iota_rows_kernel(int32_t* vals, int nqc, int K) {
+  const int64_t cells = (int64_t)nqc * K;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cells;
+       i += (int64_t)gridDim.x * blockDim.x)
+    vals[i] = (int32_t)(i % K);
+}
+
+__global__ void fill_f64_kernel(double* p, int64_t count, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+bool launch_rerank(const float* Q, int64_t q0, int d, const float* X, const int64_t* offsets,
+                   const int32_t* ids, const int32_t* order, const double* oscore, int K, int t,
+                   int k, int32_t* out_ids, double* out_scores, int64_t* searched, int nqc,
+                   hipStream_t st) {
+  if ((d & 3) == 0)
+    hipLaunchKernelGGL(rerank_kernel<true>, dim3(nqc), dim3(kRerankThreads), 0, st, Q, q0, d, X,
+                       offsets, ids, order, oscore, K, t, k, out_ids, out_scores, searched);
+  else
+    hipLaunchKernelGGL(rerank_kernel<false>, dim3(nqc), dim3(kRerankThreads), 0, st, Q, q0, d, X,
+                       offsets, ids, order, oscore, K, t, k, out_ids, out_scores, searched);
+  return hipGetLastError() == hipSuccess;
+}
+
 struct SearchLayout {
   double* keys_in;
   double* keys_out;
@@ -741,31 +799,38 @@ struct SearchLayout {
   int nqc;
 };
 
-SearchLayout search_layout(void* ws, int64_t nq, int K) {
-  SearchLayout L{};
-  // queries per chunk: about 256 MB of sort keys and values
+// Queries per chunk for K scores each: about 256 MB of sort keys and values.
+int search_chunk(int64_t nq, int K) {
   const int64_t per_q = (int64_t)K * 24;
-  L.nqc = (int)std::max<int64_t>(
+  return (int)std::max<int64_t>(
       1, std::min<int64_t>(std::min<int64_t>(nq, 65535), ((int64_t)256 << 20) / per_q));
-  const int64_t items = (int64_t)L.nqc * K;
-  char* base = static_cast<char*>(ws);
-  size_t off = 0;
-  auto take = [&](size_t b) { char* p = base ? base + off : nullptr; off = al(off + b); return p; };
+}
+
+// The probe arrays of nqc queries of K scores, placed at *off in ws (nullptr: sizes only).
+SearchLayout search_layout_at(char* base, size_t* off, int nqc, int K) {
+  SearchLayout L{};
+  L.nqc = nqc;
+  const int64_t items = (int64_t)nqc * K;
+  auto take = [&](size_t b) { char* p = base ? base + *off : nullptr; *off = al(*off + b); return p; };
   L.keys_in = reinterpret_cast<double*>(take(items * 8));
   L.keys_out = reinterpret_cast<double*>(take(items * 8));
   L.vals_in = reinterpret_cast<int32_t*>(take(items * 4));
   L.vals_out = reinterpret_cast<int32_t*>(take(items * 4));
-  L.seg = reinterpret_cast<int*>(take((size_t)(L.nqc + 1) * 4));
+  L.seg = reinterpret_cast<int*>(take((size_t)(nqc + 1) * 4));
   size_t tb = 0;
   (void)hipcub::DeviceSegmentedRadixSort::SortPairsDescending(
-      nullptr, tb, L.keys_in, L.keys_out, L.vals_in, L.vals_out, (int)items, L.nqc, L.seg,
+      nullptr, tb, L.keys_in, L.keys_out, L.vals_in, L.vals_out, (int)items, nqc, L.seg,
       L.seg + 1);
   L.temp_bytes = tb;
   L.temp = take(tb);
-  L.bytes = off;
+  L.bytes = *off;
   return L;
 }
 
+SearchLayout search_layout(void* ws, int64_t nq, int K) {
+  size_t off = 0;
+  return search_layout_at(static_cast<char*>(ws), &off, search_chunk(nq, K), K);
+}
 
 // The first t places of keys_out / vals_out per query: the selection kernel for t <= kSelMax,
 // else a stable descending segmented sort of all K scores.
@@ -783,6 +848,24 @@ bool probe_top(const SearchLayout& L, int nqc, int K, int t, hipStream_t st) {
   return hipcub::DeviceSegmentedRadixSort::SortPairsDescending(
              L.temp, tb, L.keys_in, L.keys_out, L.vals_in, L.vals_out, nqc * K, nqc, L.seg,
              L.seg + 1, 0, 64, st) == hipSuccess;
+}
+
+// Workspace of soar_search_two_level: the probe arrays of both levels for one chunk of queries.
+struct TwoLevelLayout {
+  SearchLayout upper, lower;
+  size_t bytes;
+  int nqc;
+};
+
+TwoLevelLayout two_level_layout(void* ws, int64_t nq, int K, int K2) {
+  TwoLevelLayout L{};
+  L.nqc = std::min(search_chunk(nq, K), search_chunk(nq, K2));
+  size_t off = 0;
+  char* base = static_cast<char*>(ws);
+  L.upper = search_layout_at(base, &off, L.nqc, K2);
+  L.lower = search_layout_at(base, &off, L.nqc, K);
+  L.bytes = off;
+  return L;
 }
 
 // Workspace of soar_search_pq: the probe's sort arrays for nqc queries and the candidate arrays
@@ -928,12 +1011,9 @@ soar_status soar_search(const float* Q, int64_t nq, int32_t d, const float* C, i
     hipLaunchKernelGGL(probe_scores_kernel, dim3((K + kPC - 1) / kPC, (nqc + kPQ - 1) / kPQ),
                        dim3(256), 0, st, Q, q0, nqc, d, C, K, L.keys_in, L.vals_in, L.seg);
     if (!probe_top(L, nqc, K, t, st)) return SOAR_E_DEVICE;
-    if ((d & 3) == 0)
-      hipLaunchKernelGGL(rerank_kernel<true>, dim3(nqc), dim3(kRerankThreads), 0, st, Q, q0, d,
-                         X, offsets, ids, L.vals_out, K, t, k, out_ids, out_scores, searched);
-    else
-      hipLaunchKernelGGL(rerank_kernel<false>, dim3(nqc), dim3(kRerankThreads), 0, st, Q, q0, d,
-                         X, offsets, ids, L.vals_out, K, t, k, out_ids, out_scores, searched);
+    if (!launch_rerank(Q, q0, d, X, offsets, ids, L.vals_out, nullptr, K, t, k, out_ids,
+                       out_scores, searched, nqc, st))
+      return SOAR_E_DEVICE;
     if (hipGetLastError() != hipSuccess) return SOAR_E_DEVICE;
   }
   return hipStreamSynchronize(st) == hipSuccess ? SOAR_OK : SOAR_E_DEVICE;
@@ -1043,6 +1123,60 @@ soar_status soar_search_pq(const float* Q, int64_t nq, int32_t d, const float* C
       hipLaunchKernelGGL(pq_rerank_kernel<false>, dim3(nqc), dim3(kRerankThreads), 0, st, Q, q0,
                          d, X, L.seg2, L.cv_a, L.cid_b, R, k, out_ids, out_scores);
     if (hipGetLastError() != hipSuccess) return SOAR_E_DEVICE;
+  }
+  return hipStreamSynchronize(st) == hipSuccess ? SOAR_OK : SOAR_E_DEVICE;
+}
+
+
+soar_status soar_search_two_level_workspace_size(int64_t nq, int32_t d, int32_t K, int32_t K2,
+                                                 size_t* bytes) {
+  if (!bytes || nq < 1 || d < 1 || K < 1 || K2 < 1) return SOAR_E_INVAL;
+  *bytes = two_level_layout(nullptr, nq, K, K2).bytes;
+  return SOAR_OK;
+}
+
+soar_status soar_search_two_level(const float* Q, int64_t nq, int32_t d, const float* U,
+                                  int32_t K2, const int64_t* upper_offsets,
+                                  const int32_t* upper_ids, int32_t t2, const float* C, int32_t K,
+                                  const float* X, int64_t n, const int64_t* offsets,
+                                  const int32_t* ids, int32_t t, int32_t k, int32_t* out_ids,
+                                  double* out_scores, int64_t* searched, void* workspace,
+                                  size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  if (!Q || !U || !upper_offsets || !upper_ids || !C || !X || !offsets || !ids || !out_ids ||
+      !out_scores || !workspace || n < 1 || t < 1 || t2 < 1 || k < 1 || k > kSearchMaxK ||
+      soar_search_two_level_workspace_size(nq, d, K, K2, &need) != SOAR_OK || ws_bytes < need)
+    return SOAR_E_INVAL;
+  if (d > 1024) return SOAR_E_UNSUPPORTED;
+  t = std::min(t, K);
+  t2 = std::min(t2, K2);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TwoLevelLayout L = two_level_layout(workspace, nq, K, K2);
+  for (int64_t q0 = 0; q0 < nq; q0 += L.nqc) {
+    const int nqc = (int)std::min<int64_t>(L.nqc, nq - q0);
+    // upper level: <q, u> for every upper centroid, the t2 best
+    hipLaunchKernelGGL(probe_scores_kernel, dim3((K2 + kPC - 1) / kPC, (nqc + kPQ - 1) / kPQ),
+                       dim3(256), 0, st, Q, q0, nqc, d, U, K2, L.upper.keys_in, L.upper.vals_in,
+                       L.upper.seg);
+    if (!probe_top(L.upper, nqc, K2, t2, st)) return SOAR_E_DEVICE;
+    // lower level: the partitions listed under those, scored; the rest stay -inf
+    const int64_t cells = (int64_t)nqc * K;
+    hipLaunchKernelGGL(fill_f64_kernel,
+                       dim3((unsigned)std::min<int64_t>((cells + 255) / 256, 4096)), dim3(256), 0,
+                       st, L.lower.keys_in, cells, -__builtin_inf());
+    hipLaunchKernelGGL(probe_second_kernel, dim3(t2, nqc), dim3(256), 0, st, Q, q0, d, C, K,
+                       upper_offsets, upper_ids, L.upper.vals_out, K2, L.lower.keys_in);
+    if (t > kSelMax) {   // the segmented sort's inputs: segment bounds and place indices
+      hipLaunchKernelGGL(seg_bounds_kernel, dim3((nqc + 256) / 256), dim3(256), 0, st, nqc, K,
+                         L.lower.seg);
+      hipLaunchKernelGGL(iota_rows_kernel,
+                         dim3((unsigned)std::min<int64_t>((cells + 255) / 256, 4096)), dim3(256),
+                         0, st, L.lower.vals_in, nqc, K);
+    }
+    if (!probe_top(L.lower, nqc, K, t, st)) return SOAR_E_DEVICE;
+    if (!launch_rerank(Q, q0, d, X, offsets, ids, L.lower.vals_out, L.lower.keys_out, K, t, k,
+                       out_ids, out_scores, searched, nqc, st))
+      return SOAR_E_DEVICE;
   }
   return hipStreamSynchronize(st) == hipSuccess ? SOAR_OK : SOAR_E_DEVICE;
 }
