@@ -16,6 +16,9 @@ Recipe (the same for every workload):
   per-dimension draw from log-uniform[lo, hi];
 * ``norm`` is ``"unit"`` (rows L2-normalised), ``"none"``, or ``"lognormal"``
   (direction normalised, then scaled by a norm drawn from lognormal(0, s)).
+* with ``groups = G > 0`` the component means cluster: ``mu_m = nu_(m mod G) + spread * mu'_m``
+  with group means ``nu_g ~ N(0, I_d)`` from a stream spawned off [0] and ``mu'_m`` the draw
+  above (``groups = 0`` leaves the means exactly as before).
 
 Rows are produced in chunks of ``CHUNK`` rows, each chunk from its own spawned child
 stream, so any row range can be regenerated without generating the rows before it.
@@ -36,6 +39,8 @@ class MixtureSpec:
     sigma: object = 0.3            # float (isotropic) or ("loguniform", lo, hi)
     norm: object = "unit"          # "unit" | "none" | ("lognormal", s)
     seed: int = 0
+    groups: int = 0                # > 0: component means cluster around this many group means
+    group_spread: float = 1.0
 
 
 def _streams(seed: int):
@@ -46,6 +51,10 @@ def _component_params(spec: MixtureSpec):
     ss = _streams(spec.seed)
     rng_mu = np.random.Generator(np.random.PCG64(ss[0]))
     mu = rng_mu.standard_normal((spec.components, spec.d))
+    if spec.groups > 0:
+        rng_nu = np.random.Generator(np.random.PCG64(ss[0].spawn(1)[0]))
+        nu = rng_nu.standard_normal((spec.groups, spec.d))
+        mu = nu[np.arange(spec.components) % spec.groups] + spec.group_spread * mu
     rng_sig = np.random.Generator(np.random.PCG64(ss[2].spawn(1)[0]))
     if isinstance(spec.sigma, tuple) and spec.sigma[0] == "loguniform":
         lo, hi = float(spec.sigma[1]), float(spec.sigma[2])
@@ -105,7 +114,7 @@ def sample_rows(spec: MixtureSpec, count: int, population: int | None = None) ->
     return np.sort(rng.choice(population, size=min(count, population), replace=False))
 
 
-# The five workloads, by what they are.
+# The workloads, by what they are.
 LOGU = ("loguniform", 0.05, 0.5)
 WORKLOADS = {
     "mix64_n20k_d64": dict(spec=MixtureSpec(20_000, 64, 64, 0.3, "unit", 0), K=256, iters=10,
@@ -113,6 +122,9 @@ WORKLOADS = {
     "mix4096_n1m_d128": dict(spec=MixtureSpec(1_000_000, 128, 4096, LOGU, "unit", 0), K=2000,
                              iters=15, lambdas=(0.0, 0.5, 1.0, 1.5), queries=10_000,
                              check_rows=20_000, cpu_rows=100_000),
+    "mix4096g64_n1m_d128": dict(spec=MixtureSpec(1_000_000, 128, 4096, LOGU, "unit", 0, groups=64),
+                                K=2000, iters=15, lambdas=(1.0,), queries=10_000,
+                                check_rows=20_000, cpu_rows=100_000),
     "mix16384_n10m_d96": dict(spec=MixtureSpec(10_000_000, 96, 16384, LOGU, "unit", 0), K=40_000,
                               iters=10, lambdas=(1.0,), seed_subsample=1_000_000,
                               check_rows=100_000, cpu_rows=10_000),
