@@ -329,14 +329,15 @@ def _search_pq_rows(soar, torch, Xg, Cg, Qg, assign, P, codes, ts, gt, R, reps):
         s_ = torch.from_numpy(assign[1].astype(np.int32)).cuda() if m == 2 else None
         off, ids = soar.build_lists(p, s_, K)
         A = torch.from_numpy(np.stack(assign[:m], axis=1).astype(np.int32)).cuda()
-        lc, mx = soar.list_codes(off, ids, A, codes[:, :m].contiguous())
+        lc, _ = soar.list_codes(off, ids, A, codes[:, :m].contiguous())
         rows = []
         for t in ts:
-            r = soar.search_pq(Qg, Cg, Xg, off, ids, lc, P, mx, t, R, 10)   # warm-up and result
+            bound = soar.lists_probe_bound(off, t)
+            r = soar.search_pq(Qg, Cg, Xg, off, ids, lc, P, bound, t, R, 10)   # warm-up, result
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(reps):
-                soar.search_pq(Qg, Cg, Xg, off, ids, lc, P, mx, t, R, 10)
+                soar.search_pq(Qg, Cg, Xg, off, ids, lc, P, bound, t, R, 10)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / reps
             got = r[0].cpu().numpy()

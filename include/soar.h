@@ -311,20 +311,24 @@ soar_status soar_search_two_level(const float* Q, int64_t nq, int32_t d, const f
  * soar_lists_build) is a copy of point i = ids[pos] in partition p, made by the first
  * assignment j with assign[i m + j] == p, and takes that copy's code codes[(i m + j) code_bytes
  * ..] (from soar_pq_encode with the same assign [n x m]).  list_codes [offsets[K] x code_bytes]
- * device uint8 output.  *max_list (host, nullable) receives the longest list's length, the bound
- * soar_search_pq's workspace is sized for.  An entry whose point has no assignment to its list,
- * or an id outside [0, n): SOAR_E_INVAL after the call (its code is written as zeros).
- * workspace >= 256 bytes of device memory.  Blocking.
+ * device uint8 output.  *max_list (host, nullable) receives the longest list's length.  An
+ * entry whose point has no assignment to its list, or an id outside [0, n): SOAR_E_INVAL after
+ * the call (its code is written as zeros).  workspace >= 256 bytes of device memory.  Blocking.
  */
 soar_status soar_lists_codes(const int64_t* offsets, const int32_t* ids, int32_t K, int64_t n,
                              const int32_t* assign, int32_t m, const uint8_t* codes,
                              int32_t code_bytes, uint8_t* list_codes, int64_t* max_list,
                              void* workspace, size_t ws_bytes, void* stream);
 
-/* Bytes of workspace for soar_search_pq with lists no longer than max_list entries
- * (SOAR_E_UNSUPPORTED when min(t, K) * max_list reaches 2^31). */
+/* The most list entries any t of the lists hold: the sum of the t longest lists' lengths
+ * (offsets [K + 1] on the device, read back).  *bound on the host.  Blocking. */
+soar_status soar_lists_probe_bound(const int64_t* offsets, int32_t K, int32_t t, int64_t* bound,
+                                   void* stream);
+
+/* Bytes of workspace for soar_search_pq when a query's t probed lists hold at most max_probed
+ * entries (soar_lists_probe_bound; SOAR_E_UNSUPPORTED from 2^31). */
 soar_status soar_search_pq_workspace_size(int64_t nq, int32_t d, int32_t K, int32_t t,
-                                          int64_t max_list, size_t* bytes);
+                                          int64_t max_probed, size_t* bytes);
 
 /*
  * VQ-PQ search of nq queries Q [nq x d] over lists whose copies carry PQ codes of their own
@@ -347,13 +351,14 @@ soar_status soar_search_pq_workspace_size(int64_t nq, int32_t d, int32_t K, int3
  * reproducible bit for bit.  The lists hold each point at most twice (as soar_lists_build makes
  * them): only the 2 R best copies of a query can then matter, and the call keeps a superset of
  * them before selecting.  Requires 1 <= k <= 16, k <= R <= 4096, t >= 1, d % (2 s) == 0,
- * M <= 512 (larger: SOAR_E_UNSUPPORTED), finite inputs, and no list longer than max_list (else
- * SOAR_E_INVAL; the workspace is sized for max_list).  Blocking.
+ * M <= 512 (larger: SOAR_E_UNSUPPORTED), finite inputs, and t lists holding at most max_probed
+ * entries, which the call checks (else SOAR_E_INVAL; the workspace is sized for max_probed).
+ * Blocking.
  */
 soar_status soar_search_pq(const float* Q, int64_t nq, int32_t d, const float* C, int32_t K,
                            const float* X, int64_t n, const int64_t* offsets, const int32_t* ids,
                            const uint8_t* list_codes, const float* P, int32_t s, int32_t t,
-                           int32_t R, int32_t k, int64_t max_list, int32_t* out_ids,
+                           int32_t R, int32_t k, int64_t max_probed, int32_t* out_ids,
                            double* out_scores, int64_t* scored, void* workspace, size_t ws_bytes,
                            void* stream);
 

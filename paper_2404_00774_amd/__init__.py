@@ -91,6 +91,7 @@ _sig("soar_search", [_vp, _i64, _i32, _vp, _i32, _vp, _i64, _vp, _vp, _i32, _i32
                      _sz, _vp])
 _sig("soar_lists_codes", [_vp, _vp, _i32, _i64, _vp, _i32, _vp, _i32, _vp, ctypes.POINTER(_i64),
                           _vp, _sz, _vp])
+_sig("soar_lists_probe_bound", [_vp, _i32, _i32, ctypes.POINTER(_i64), _vp])
 _sig("soar_search_pq_workspace_size", [_i64, _i32, _i32, _i32, _i64, ctypes.POINTER(_sz)])
 _sig("soar_search_pq", [_vp, _i64, _i32, _vp, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _i32, _i32,
                         _i32, _i32, _i64, _vp, _vp, _vp, _vp, _sz, _vp])
@@ -128,7 +129,8 @@ EXPORTED = [n for n in ("soar_assign_workspace_size", "soar_assign", "soar_assig
                         "soar_lists_workspace_size", "soar_lists_build", "soar_search_workspace_size",
                         "soar_search", "soar_spill_further_workspace_size",
                         "soar_spill_further", "soar_pq_encode", "soar_lists_codes",
-                        "soar_search_pq_workspace_size", "soar_search_pq",
+                        "soar_lists_probe_bound", "soar_search_pq_workspace_size",
+                        "soar_search_pq",
                         "soar_search_two_level_workspace_size", "soar_search_two_level",
                         "soar_index_destroy", "soar_status_string") if hasattr(_lib, n)]
 
@@ -469,11 +471,22 @@ def list_codes(offsets, ids, assign, codes, stream=None):
     return out, mx.value
 
 
-def search_pq(Q, C, X, offsets, ids, list_codes_, P, max_list, t, R, k=10, stream=None,
+def lists_probe_bound(offsets, t, stream=None):
+    """soar_lists_probe_bound: the most entries any t of the lists hold."""
+    b = ctypes.c_int64(0)
+    _check(_lib.soar_lists_probe_bound(_ptr(offsets), offsets.numel() - 1, int(t), ctypes.byref(b),
+                                       _stream(stream)), "soar_lists_probe_bound")
+    return b.value
+
+
+def search_pq(Q, C, X, offsets, ids, list_codes_, P, max_probed, t, R, k=10, stream=None,
               workspace=None):
     """soar_search_pq: probe t partitions, estimate every listed copy from its PQ code, re-score
     the R best points exactly and return the k best: (ids int32[nq, k], scores float64[nq, k],
-    scored int64[nq]: copies estimated).  P float32 [d / s, 16, s] on the GPU."""
+    scored int64[nq]: copies estimated).  P float32 [d / s, 16, s] on the GPU; max_probed bounds
+    the entries of any t lists (None: lists_probe_bound)."""
+    if max_probed is None:
+        max_probed = lists_probe_bound(offsets, min(int(t), offsets.numel() - 1), stream)
     Q, C, X = _f32_matrix(Q, "Q"), _f32_matrix(C, "C"), _f32_matrix(X, "X")
     nq, d = Q.shape
     K, n = C.shape[0], X.shape[0]
@@ -485,13 +498,13 @@ def search_pq(Q, C, X, offsets, ids, list_codes_, P, max_list, t, R, k=10, strea
     out_sc = torch.empty((nq, k), dtype=torch.float64, device=dev)
     scored = torch.empty(nq, dtype=torch.int64, device=dev)
     b = _sz()
-    _check(_lib.soar_search_pq_workspace_size(nq, d, K, int(t), int(max_list), ctypes.byref(b)),
+    _check(_lib.soar_search_pq_workspace_size(nq, d, K, int(t), int(max_probed), ctypes.byref(b)),
            "soar_search_pq_workspace_size")
     if workspace is None or workspace.numel() < b.value:
         workspace = torch.empty(max(b.value, 256), dtype=torch.uint8, device=dev)
     _check(_lib.soar_search_pq(_ptr(Q), nq, d, _ptr(C), K, _ptr(X), n, _ptr(offsets), _ptr(ids),
                                _ptr(list_codes_), _ptr(P.contiguous()), s, int(t), int(R), int(k),
-                               int(max_list), _ptr(out_ids), _ptr(out_sc), _ptr(scored),
+                               int(max_probed), _ptr(out_ids), _ptr(out_sc), _ptr(scored),
                                _ptr(workspace), workspace.numel(), _stream(stream)),
            "soar_search_pq")
     return out_ids, out_sc, scored

@@ -14,6 +14,8 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <functional>
+#include <vector>
 
 #include "../../include/soar.h"
 #include "common.h"
@@ -499,11 +501,6 @@ __global__ __launch_bounds__(256) void list_codes_kernel(
   }
 }
 
-__global__ void list_max_kernel(const int64_t* __restrict__ off, int K, unsigned long long* mx) {
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < K; p += gridDim.x * blockDim.x)
-    atomicMax(mx, (unsigned long long)(off[p + 1] - off[p]));
-}
-
 // Per query of the chunk: where each probed list's copies start inside the query's candidate
 // segment, the query's copy count, and (scored) that count for the caller.
 __global__ void pq_slots_kernel(const int64_t* __restrict__ off, const int32_t* __restrict__ order,
@@ -870,7 +867,7 @@ TwoLevelLayout two_level_layout(void* ws, int64_t nq, int K, int K2) {
 
 // Workspace of soar_search_pq: the probe's sort arrays for nqc queries and the candidate arrays
 // (ids and estimates, twice each, and the sorts' temporary storage) for nqc queries of at most
-// t * max_list copies each.
+// max_probed copies each (the most that t probed lists can hold).
 struct SearchPQLayout {
   SearchLayout probe;
   int64_t* slot;
@@ -892,11 +889,11 @@ struct SearchPQLayout {
   int nqc;
 };
 
-constexpr int64_t kPQCandidates = (int64_t)1 << 27;   // copies per chunk of queries (about 3.2 GB)
+constexpr int64_t kPQCandidates = (int64_t)1 << 28;   // copies per chunk of queries (about 6.4 GB)
 
-SearchPQLayout search_pq_layout(void* ws, int64_t nq, int K, int t, int64_t max_list) {
+SearchPQLayout search_pq_layout(void* ws, int64_t nq, int K, int t, int64_t max_probed) {
   SearchPQLayout L{};
-  const int64_t per_q = std::max<int64_t>(1, (int64_t)t * max_list);
+  const int64_t per_q = std::max<int64_t>(1, max_probed);
   const int64_t probe_q = search_layout(nullptr, nq, K).nqc;
   L.nqc = (int)std::max<int64_t>(1, std::min<int64_t>(probe_q, kPQCandidates / per_q));
   L.cap = (int64_t)L.nqc * per_q;
@@ -937,6 +934,26 @@ SearchPQLayout search_pq_layout(void* ws, int64_t nq, int K, int t, int64_t max_
   L.probe.temp_bytes = L.temp_bytes;
   L.bytes = off;
   return L;
+}
+
+// The most copies any t lists hold: the sum of the t longest list lengths (offsets read back).
+soar_status probe_bound(const int64_t* offsets, int K, int t, hipStream_t st, int64_t* bound) {
+  std::vector<int64_t> off((size_t)K + 1);
+  if (hipMemcpyAsync(off.data(), offsets, off.size() * sizeof(int64_t), hipMemcpyDeviceToHost,
+                     st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return SOAR_E_DEVICE;
+  std::vector<int64_t> len((size_t)K);
+  for (int p = 0; p < K; ++p) {
+    len[p] = off[p + 1] - off[p];
+    if (len[p] < 0) return SOAR_E_INVAL;
+  }
+  const int tt = std::min(t, K);
+  std::nth_element(len.begin(), len.begin() + (tt - 1), len.end(), std::greater<int64_t>());
+  int64_t b = 0;
+  for (int i = 0; i < tt; ++i) b += len[i];
+  *bound = b;
+  return SOAR_OK;
 }
 
 int id_bits(int64_t n) {
@@ -1042,19 +1059,25 @@ soar_status soar_lists_codes(const int64_t* offsets, const int32_t* ids, int32_t
   return h[1] ? SOAR_E_INVAL : SOAR_OK;
 }
 
+soar_status soar_lists_probe_bound(const int64_t* offsets, int32_t K, int32_t t, int64_t* bound,
+                                   void* stream) {
+  if (!offsets || !bound || K < 1 || t < 1) return SOAR_E_INVAL;
+  return probe_bound(offsets, K, t, static_cast<hipStream_t>(stream), bound);
+}
+
 soar_status soar_search_pq_workspace_size(int64_t nq, int32_t d, int32_t K, int32_t t,
-                                          int64_t max_list, size_t* bytes) {
-  if (!bytes || nq < 1 || d < 1 || K < 1 || t < 1 || max_list < 0) return SOAR_E_INVAL;
+                                          int64_t max_probed, size_t* bytes) {
+  if (!bytes || nq < 1 || d < 1 || K < 1 || t < 1 || max_probed < 0) return SOAR_E_INVAL;
   t = std::min(t, K);
-  if ((int64_t)t * max_list >= ((int64_t)1 << 31)) return SOAR_E_UNSUPPORTED;
-  *bytes = search_pq_layout(nullptr, nq, K, t, max_list).bytes;
+  if (max_probed >= ((int64_t)1 << 31)) return SOAR_E_UNSUPPORTED;
+  *bytes = search_pq_layout(nullptr, nq, K, t, max_probed).bytes;
   return SOAR_OK;
 }
 
 soar_status soar_search_pq(const float* Q, int64_t nq, int32_t d, const float* C, int32_t K,
                            const float* X, int64_t n, const int64_t* offsets, const int32_t* ids,
                            const uint8_t* list_codes, const float* P, int32_t s, int32_t t,
-                           int32_t R, int32_t k, int64_t max_list, int32_t* out_ids,
+                           int32_t R, int32_t k, int64_t max_probed, int32_t* out_ids,
                            double* out_scores, int64_t* scored, void* workspace, size_t ws_bytes,
                            void* stream) {
   size_t need = 0;
@@ -1064,22 +1087,17 @@ soar_status soar_search_pq(const float* Q, int64_t nq, int32_t d, const float* C
     return SOAR_E_INVAL;
   const int M = d / s;
   if (M > kPQMaxSub) return SOAR_E_UNSUPPORTED;
-  const soar_status sz = soar_search_pq_workspace_size(nq, d, K, t, max_list, &need);
+  const soar_status sz = soar_search_pq_workspace_size(nq, d, K, t, max_probed, &need);
   if (sz != SOAR_OK) return sz;
   if (ws_bytes < need) return SOAR_E_INVAL;
   t = std::min(t, K);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  SearchPQLayout L = search_pq_layout(workspace, nq, K, t, max_list);
-  // the lists must fit the bound the workspace was sized for
-  unsigned long long* mx = reinterpret_cast<unsigned long long*>(L.cnt);
-  hipLaunchKernelGGL(zero_i64_kernel, dim3(1), dim3(64), 0, st, L.cnt, (int64_t)1);
-  hipLaunchKernelGGL(list_max_kernel, dim3((K + 255) / 256), dim3(256), 0, st, offsets, K, mx);
-  unsigned long long hmx = 0;
-  if (hipGetLastError() != hipSuccess ||
-      hipMemcpyAsync(&hmx, mx, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return SOAR_E_DEVICE;
-  if ((int64_t)hmx > max_list) return SOAR_E_INVAL;
+  SearchPQLayout L = search_pq_layout(workspace, nq, K, t, max_probed);
+  // any t lists must fit the bound the workspace was sized for
+  int64_t actual = 0;
+  const soar_status bs = probe_bound(offsets, K, t, st, &actual);
+  if (bs != SOAR_OK) return bs;
+  if (actual > max_probed) return SOAR_E_INVAL;
   const size_t lut_bytes = (size_t)M * 16 * sizeof(double);
   const int bits = id_bits(n);
   for (int64_t q0 = 0; q0 < nq; q0 += L.nqc) {

@@ -42,7 +42,7 @@ def _index(X, C, A, codes):
 def _run(X, C, A, codes, P, Q, t, R, k):
     soar = _soar()
     off, ids, lc, mx = _index(X, C, A, codes)
-    gi, gs, gn = soar.search_pq(_t(Q), _t(C), _t(X), off, ids, lc, _t(P), mx, t, R, k)
+    gi, gs, gn = soar.search_pq(_t(Q), _t(C), _t(X), off, ids, lc, _t(P), None, t, R, k)
     return gi.cpu().numpy(), gs.cpu().numpy(), gn.cpu().numpy()
 
 
@@ -99,7 +99,7 @@ def test_large_rerank_equals_exact_search(small):
     soar = _soar()
     off, ids, lc, mx = _index(X, C, A, codes)
     for t in (1, 4):
-        gi, gs, gn = soar.search_pq(_t(Q), _t(C), _t(X), off, ids, lc, _t(P), mx, t, 4096, 10)
+        gi, gs, gn = soar.search_pq(_t(Q), _t(C), _t(X), off, ids, lc, _t(P), None, t, 4096, 10)
         ei, es, en = soar.search(_t(Q), _t(C), _t(X), off, ids, t, 10)
         assert int(en.max()) <= 4096
         assert np.array_equal(gi.cpu().numpy(), ei.cpu().numpy())
@@ -131,18 +131,21 @@ def test_validation(small):
     soar = _soar()
     off, ids, lc, mx = _index(X, C, A, codes)
     Qg, Cg, Xg, Pg = _t(Q), _t(C), _t(X), _t(P)
+    bound = soar.lists_probe_bound(off, 2)
+    lens = np.sort(np.diff(off.cpu().numpy()))[::-1]
+    assert bound == int(lens[:2].sum()) and soar.lists_probe_bound(off, 1) == mx
     with pytest.raises(soar.SoarError) as e:
-        soar.search_pq(Qg, Cg, Xg, off, ids, lc, Pg, mx, 2, 5, 10)        # R < k
+        soar.search_pq(Qg, Cg, Xg, off, ids, lc, Pg, bound, 2, 5, 10)        # R < k
     assert e.value.status == -1
     with pytest.raises(soar.SoarError) as e:
-        soar.search_pq(Qg, Cg, Xg, off, ids, lc, Pg, mx - 1, 2, 20, 10)   # a longer list
+        soar.search_pq(Qg, Cg, Xg, off, ids, lc, Pg, bound - 1, 2, 20, 10)   # two longer lists
     assert e.value.status == -1
     import torch
     raw = torch.empty(lc.numel() + 4, dtype=torch.uint8, device=lc.device)
     mis = raw[1:1 + lc.numel()].view(lc.shape)
     mis.copy_(lc)
     with pytest.raises(soar.SoarError) as e:
-        soar.search_pq(Qg, Cg, Xg, off, ids, mis, Pg, mx, 2, 20, 10)       # not 4-byte aligned
+        soar.search_pq(Qg, Cg, Xg, off, ids, mis, Pg, bound, 2, 20, 10)    # not 4-byte aligned
     assert e.value.status == -1
     bad_assign = _ti(np.stack([(A[0] + 1) % len(C), A[1]], axis=1))
     with pytest.raises(soar.SoarError) as e:
@@ -176,7 +179,7 @@ def test_full_size_sampled():
     P = (rng.standard_normal((d // 2, 16, 2)) * 0.1).astype(np.float32)
     codes = rng.integers(0, 16, size=(n, 2, d // 2))
     off, ids, lc, mx = _index(X, C, [a0, a1], codes)
-    gi, gs, gn = soar.search_pq(_t(Q), _t(C), _t(X), off, ids, lc, _t(P), mx, 8, 100, 10)
+    gi, gs, gn = soar.search_pq(_t(Q), _t(C), _t(X), off, ids, lc, _t(P), None, 8, 100, 10)
     gi, gs, gn = gi.cpu().numpy(), gs.cpu().numpy(), gn.cpu().numpy()
     sample = np.sort(np.random.default_rng(5).choice(len(Q), 40, replace=False))
     want = O.search_pq(Q[sample], X, C, [a0, a1], codes, P, 8, 100, 10)
