@@ -140,7 +140,8 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--serve-base", type=int, default=20_000_000, help="rows of the base index")
     ap.add_argument("--serve-K", type=int, default=50_000)
-    ap.add_argument("--serve-rates", default="5000,20000,50000,100000,200000",
+    ap.add_argument("--serve-rates",
+                    default="5000,20000,50000,100000,200000,500000,1000000,2000000",
                     help="offered insert rates, vectors/s")
     ap.add_argument("--serve-requests", type=int, default=10_000,
                     help="requests per offered rate (the window is the time they take to arrive)")
