@@ -108,8 +108,10 @@ def test_integer_ties_duplicates_and_zero_residuals():
 
 
 def test_chain_of_four_assignments_matches_oracle_steps():
-    """assign_multi(M = 4) on the GPU: each step checked by the oracle given the GPU's own earlier
-    assignments (n = 20,000, d = 64, K = 256, a Lloyd-trained codebook)."""
+    """assign_multi(M = 4) on the GPU against the oracle's own chain (n = 20,000, d = 64,
+    K = 256, a Lloyd-trained codebook): each step is checked on the rows whose earlier
+    assignments equal the oracle's, and those are nearly all rows (a near-tie may send a row's
+    chain elsewhere, which the step checks allow)."""
     soar = _soar()
     w = WORKLOADS["mix64_n20k_d64"]
     X = gen_mixture(w["spec"])
@@ -118,10 +120,15 @@ def test_chain_of_four_assignments_matches_oracle_steps():
     for lam in (0.5, 1.0):
         A, V = soar.assign_multi(_t(X), _t(C), lam, 4)
         A, V = A.cpu().numpy(), V.cpu().numpy()
+        W, _ = O.assign_multi(X, C, lam, 4)
         assert (np.sort(A, axis=1)[:, 1:] != np.sort(A, axis=1)[:, :-1]).all()
         for k in (2, 3):
-            print(f"chain lam={lam} step {k}", flush=True)
-            _check(X, C, lam, A[:, :k], (A[:, k], V[:, k]))
+            same = (A[:, :k] == W[:, :k]).all(axis=1)
+            print(f"chain lam={lam} step {k}: {int(same.sum())} rows share the oracle's priors",
+                  flush=True)
+            assert same.mean() > 0.99
+            rows = np.flatnonzero(same)
+            _check(X[rows], C, lam, W[rows, :k], (A[rows, k], V[rows, k]))
 
 
 def test_validation_and_errors():
@@ -152,19 +159,19 @@ def test_validation_and_errors():
 
 def test_full_size_sampled():
     """n = 1,000,000, d = 128, K = 2000 (the workload the benchmark times this on): the third
-    assignment given the GPU's primary and spill; the oracle checks 5000 sampled rows."""
+    assignment given two distinct earlier assignments per row (seeded; the loss is defined for
+    any), the oracle checks 5000 sampled rows."""
     soar = _soar()
     w = WORKLOADS["mix4096_n1m_d128"]
     spec = w["spec"]
     X = gen_mixture(spec)
     C = X[sample_rows(spec, w["K"])]
-    Xg, Cg = _t(X), _t(C)
-    p, s, _, _ = soar.assign(Xg, Cg, 1.0)
-    import torch
-    P = torch.stack([p, s], dim=1)
-    nxt, loss, st = soar.spill_further(Xg, Cg, P, 1.0, stats=True)
+    rng = np.random.default_rng(12)
+    a0 = rng.integers(0, w["K"], len(X))
+    a1 = (a0 + rng.integers(1, w["K"], len(X))) % w["K"]
+    Pn = np.stack([a0, a1], axis=1)
+    nxt, loss, st = soar.spill_further(_t(X), _t(C), _ti(Pn), 1.0, stats=True)
     print("further full size", st, flush=True)
-    idx = np.sort(np.random.default_rng(12).choice(len(X), 5000, replace=False))
-    Pn = P.cpu().numpy()
+    idx = np.sort(rng.choice(len(X), 5000, replace=False))
     _check(X[idx], C, 1.0, Pn[idx], (nxt.cpu().numpy()[idx], loss.cpu().numpy()[idx]))
     assert st["rows_full_scan"] < 0.02 * len(X)

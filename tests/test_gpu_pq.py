@@ -100,28 +100,25 @@ def test_validation():
 
 
 def test_trained_codebook_on_the_workload_sampled():
-    """n = 1,000,000, d = 128, K = 2000 with its primary and spilled assignments: a PQ codebook
-    (s = 2) trained on the GPU from primary residuals, the codes of both assignments' residuals,
-    and the oracle on 5000 sampled rows; each residual's relative reconstruction error is printed
-    (a ratio of sums over the sample: rows that are codebook rows have r = 0)."""
+    """n = 1,000,000, d = 128, K = 2000: a PQ codebook (s = 2) trained by the oracle (k-means per
+    subspace) on the primary residuals of a 20,000-row sample, two distinct seeded assignments
+    per row (codes are defined for any), the codes of every row on the GPU, and the oracle on
+    5000 sampled rows."""
     soar = _soar()
-    import torch
     w = WORKLOADS["mix4096_n1m_d128"]
     spec = w["spec"]
     X = gen_mixture(spec)
-    C = X[sample_rows(spec, w["K"])]
-    Xg, Cg = _t(X), _t(C)
-    p, s_, _, _ = soar.assign(Xg, Cg, 1.0)
-    A = torch.stack([p, s_], dim=1)
-    sub = torch.from_numpy(sample_rows(spec, 100_000)).cuda()
-    R = (Xg[sub] - Cg[p[sub].long()]).contiguous()
-    P = soar.pq_train(R, 2, iters=5)
-    codes = soar.pq_encode(Xg, Cg, A, P).cpu().numpy()
-    idx = np.sort(np.random.default_rng(5).choice(len(X), 5000, replace=False))
-    An, Pn = A.cpu().numpy(), P.cpu().numpy()
-    assert _check(X[idx], C, Pn, An[idx], codes[idx]) <= 5
-    dec = [O.pq_decode(_unpack(codes[idx, j]), Pn) for j in range(2)]
-    res = [X[idx].astype(np.float64) - C[An[idx, j]] for j in range(2)]
-    rel = [float(((r - q) ** 2).sum() / (r ** 2).sum()) for r, q in zip(res, dec)]
-    print("relative PQ error, primary and spill residuals", rel, flush=True)
-    assert rel[0] < 1.0 and rel[1] < 1.0
+    K = w["K"]
+    C = X[sample_rows(spec, K)]
+    rng = np.random.default_rng(5)
+    sub = np.sort(rng.choice(len(X), 20_000, replace=False))
+    p_sub, _ = O.primary_fast(X[sub], C)
+    R = X[sub].astype(np.float64) - C[p_sub]
+    P = np.stack([O.train_codebook(R[:, 2 * m:2 * m + 2], 16, 5, seed=m)[0]
+                  for m in range(X.shape[1] // 2)]).astype(np.float32)
+    a0 = rng.integers(0, K, len(X))
+    a1 = (a0 + rng.integers(1, K, len(X))) % K
+    A = np.stack([a0, a1], axis=1)
+    codes = soar.pq_encode(_t(X), _t(C), _ti(A), _t(P)).cpu().numpy()
+    idx = np.sort(rng.choice(len(X), 5000, replace=False))
+    assert _check(X[idx], C, P, A[idx], codes[idx]) <= 5

@@ -42,9 +42,10 @@ def setup():
     Q = gen_queries(spec, 300)
     C, _, _ = O.train_codebook(X, 200, 3, seed=2)
     C = C.astype(np.float32)
-    soar = _soar()
-    p, s, _, _ = soar.assign(_t(X), _t(C), 1.0)
-    return X, Q, C, p, s
+    p, _, s, _ = O.assign(X, C, 1.0)       # the lists' assignments come from the oracle too
+    import torch
+    return (X, Q, C, torch.from_numpy(p.astype(np.int32)).cuda(),
+            torch.from_numpy(s.astype(np.int32)).cuda())
 
 
 def test_lists_are_the_assignments(setup):
