@@ -36,7 +36,9 @@ PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2516.0, "fp8": 5032.0}   # MI355X dense M
 # null until it is measured again.
 COPY_SCALE = {"fetch": 1048576.0 / 524302.5, "write": 1.0}   # 1 GiB device copy
 # L2-to-memory traffic of one whole call (rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB summed
-# over the call's dispatches), valid while the sources of its kernels are unchanged.
+# over the call's dispatches), valid while the sources of its kernels are unchanged.  The runs
+# took K uniformly sampled rows as the codebook (--codebook sample); a trained codebook of the
+# same shape changes the partition sizes, not the streams.
 TRAFFIC = {
     # BF16, n=10M, d=96, K=40,000: quantization, primary sweep, re-score, grouping, grouped spill
     # sweep over residual rows, re-score (plus the codebook norms and counter resets, 7.5 MB)
