@@ -22,7 +22,9 @@
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are stream-ordered and, unless
  *    SOAR_ASYNC is set in a flags field, block until the device work has finished so that the
  *    returned status covers device-side errors.
- *  - Validation runs before any launch; on SOAR_E_INVAL / SOAR_E_UNSUPPORTED nothing is written.
+ *  - Validation runs before any launch; on SOAR_E_INVAL / SOAR_E_UNSUPPORTED nothing is written,
+ *    except for checks of array contents made on the device (indices in range), whose
+ *    SOAR_E_INVAL comes after the call: each such call's comment says what it wrote.
  *    On SOAR_E_NONFINITE (a NaN or Inf in X or C) the outputs have been written but hold no
  *    meaning.  Nothing aborts and nothing throws across this interface.
  *  - Ties: an arg-min tie goes to the lowest index.  ||r|| = 0 makes the projection term 0.
