@@ -894,7 +894,7 @@ constexpr int64_t kPQCandidates = (int64_t)1 << 28;   // copies per chunk of que
 SearchPQLayout search_pq_layout(void* ws, int64_t nq, int K, int t, int64_t max_probed) {
   SearchPQLayout L{};
   const int64_t per_q = std::max<int64_t>(1, max_probed);
-  const int64_t probe_q = search_layout(nullptr, nq, K).nqc;
+  const int64_t probe_q = search_chunk(nq, K);
   L.nqc = (int)std::max<int64_t>(1, std::min<int64_t>(probe_q, kPQCandidates / per_q));
   L.cap = (int64_t)L.nqc * per_q;
   char* base = static_cast<char*>(ws);
