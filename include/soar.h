@@ -69,6 +69,14 @@ typedef enum soar_precision {
    Both bits: SOAR_E_INVAL. */
 #define SOAR_SPILL_GROUPED 2u
 #define SOAR_SPILL_DIRECT 4u
+/* BF16/FP8, grouped form, topk <= 8: the spill bound is on by default.  A row with primary p
+   whose nearest other re-scored candidate j2 gives U = (1 + lambda) ||x - C_j2||^2 has its spill
+   within ||r|| + sqrt(U) of C_p (the penalty lies between 0 and lambda ||x - C_j||^2, then the
+   triangle inequality; Section 3.4's loss).  When the topk centroids nearest to C_p include all
+   centroids that close (FP32 distances lowered by their rounding bound), those topk are the row's
+   spill candidates, re-scored exactly, and the row skips the spill sweep.  This bit turns the
+   bound off (every row goes through the sweep). */
+#define SOAR_NO_BOUND 8u
 
 /* Options of soar_assign.  Set struct_size = sizeof(soar_assign_opts). */
 typedef struct soar_assign_opts {
@@ -90,11 +98,16 @@ typedef struct soar_stats {
                                re-done by an exact scan over all K                               */
   int64_t rows_fp64;        /* rows whose decision was taken in FP64 (near-ties)                 */
   double mfma_flops;        /* algorithmic work 4 n K d: X C^T and R C^T, each once              */
-  float phase_ms[6];        /* [0] codebook and row preparation (norms, packing, quantization),
+  float phase_ms[6];        /* [0] codebook and row preparation (norms, packing, quantization;
+                               BF16/FP8 with the spill bound: its table of nearest centroids),
                                [1] primary sweep, [2] primary re-score (BF16/FP8), [3] grouping
                                of the rows by primary, [4] spill sweep, [5] spill re-score
                                (BF16/FP8) or exact full scan (FP32).  An FP32 direct-form call
                                runs both sweeps in one pass, reported under [1].                */
+  int64_t rows_bounded;     /* BF16/FP8: rows whose spill the spill bound confined to the topk
+                               centroids nearest their primary (no spill sweep; see
+                               SOAR_NO_BOUND); filled when struct_size covers it (a struct that
+                               ends at phase_ms is accepted)                                     */
 } soar_stats;
 
 /* Bytes of device workspace soar_assign needs for these sizes and options. */
@@ -143,11 +156,15 @@ size_t soar_assign_noalloc_limit(void);
  * Where a BF16/FP8 soar_assign leaves its re-scored candidates in its workspace (diagnostics):
  * byte offsets from the workspace start of two row-major int32 [n x topk] arrays, the candidates
  * of the primary and of the spill (-1: an empty place), for the same n, d, K and opts.  They hold
- * the last such call's candidates until the workspace is reused.  FP32: SOAR_E_UNSUPPORTED (its
- * candidate sets are proven complete instead, and rows that are not go to an exact full scan).
+ * the last such call's candidates until the workspace is reused.  bound_key_off (nullable): an
+ * int32 [n] array that a call which used the spill bound (SOAR_NO_BOUND) leaves there: -1 for
+ * the rows the bound decided (and rows without a primary), else the row's primary.  FP32:
+ * SOAR_E_UNSUPPORTED (its candidate sets are proven complete instead, and rows that are not go
+ * to an exact full scan).
  */
 soar_status soar_assign_candidates(int64_t n, int32_t d, int32_t K, const soar_assign_opts* opts,
-                                   size_t* primary_off, size_t* spill_off, int32_t* topk);
+                                   size_t* primary_off, size_t* spill_off, int32_t* topk,
+                                   size_t* bound_key_off);
 
 /* ---- Further spilled assignments (Section 3.5.1) ---- */
 

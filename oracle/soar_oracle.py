@@ -864,3 +864,52 @@ def search_two_level(Q, X, C, U, upper_assign, assignments, t2, t, k):
         ids[i, :order.size] = cand[order]
         scores[i, :order.size] = s[order]
     return ids, scores, searched
+
+
+# ---- Spill bound (a consequence of Section 3.4's loss) ----
+#
+# For a row with primary p, residual r and any centroid j2 != p, the spill j* has
+# ||x - c_j*||^2 <= L(j*) <= L(j2) <= (1 + lambda) ||x - c_j2||^2 (the penalty term of Theorem
+# 3.1 lies between 0 and lambda ||x - c||^2 by Cauchy-Schwarz), hence, by the triangle
+# inequality, ||c_p - c_j*|| <= ||r|| + sqrt((1 + lambda) ||x - c_j2||^2).  The library uses this
+# to decide some rows' spill from a few centroids; these two functions state it plainly so that
+# the tests can pin it and check the library's decisions.
+
+def centroid_neighbours(C, M):
+    """For every centroid p: the M other centroids nearest to c_p (float64 direct differences,
+    ties to the lowest index; -1 where K - 1 < M) and the distance from c_p to the (M+1)-th
+    nearest other centroid (inf when no other centroid is left out)."""
+    C = _f64(C)
+    K = C.shape[0]
+    m = min(M, K - 1)
+    nb = np.full((K, M), -1, dtype=np.int64)
+    beyond = np.full(K, np.inf)
+    idx = np.arange(K)
+    for p in range(K):
+        dist = np.sqrt(_sqdist(C - C[p]))
+        dist[p] = np.inf
+        order = np.lexsort((idx, dist))
+        nb[p, :m] = order[:m]
+        if K - 1 > M:
+            beyond[p] = dist[order[M]]
+    return nb, beyond
+
+
+def spill_bound_rows(X, C, lam, primary, M):
+    """Rows whose spill the bound confines to the M centroids nearest their primary centroid.
+
+    j2 is taken as the nearest centroid other than the primary.  Returns (mask [n] bool,
+    radius [n] = ||r|| + sqrt((1 + lam) ||x - c_j2||^2), neighbours [K, M] and the distance to
+    the (M+1)-th nearest centroid [K] from ``centroid_neighbours``)."""
+    lam = _check_lambda(lam)
+    X, C = _f64(X), _f64(C)
+    p = np.asarray(primary, dtype=np.int64)
+    n = X.shape[0]
+    nb, beyond = centroid_neighbours(C, M)
+    radius = np.empty(n)
+    for i in range(n):
+        dist2 = _sqdist(X[i][None, :] - C)
+        rn = np.sqrt(dist2[p[i]])
+        dist2[p[i]] = np.inf
+        radius[i] = rn + np.sqrt((1.0 + lam) * dist2.min())
+    return radius < beyond[p], radius, nb, beyond

@@ -24,6 +24,7 @@ FP32, BF16, FP8_E4M3 = 0, 1, 2
 _PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
 ASYNC = 1
 SPILL_GROUPED, SPILL_DIRECT = 2, 4
+NO_BOUND = 8
 _SPILL_FORM = {"auto": 0, "grouped": SPILL_GROUPED, "direct": SPILL_DIRECT}
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error",
@@ -46,7 +47,8 @@ class AssignOpts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("device_ms", ctypes.c_float),
                 ("assign_kernel_ms", ctypes.c_float), ("rows_full_scan", ctypes.c_int64), ("rows_fp64", ctypes.c_int64),
-                ("mfma_flops", ctypes.c_double), ("phase_ms", ctypes.c_float * 6)]
+                ("mfma_flops", ctypes.c_double), ("phase_ms", ctypes.c_float * 6),
+                ("rows_bounded", ctypes.c_int64)]
 
     PHASES = ("prep", "primary_sweep", "primary_rescore", "grouping", "spill_sweep",
               "spill_rescore")
@@ -79,7 +81,7 @@ _sig("soar_assign_noalloc", [_vp, _i64, _i32, _vp, _i32, ctypes.POINTER(AssignOp
                              _vp, _vp])
 _sig("soar_assign_noalloc_limit", [], _sz)
 _sig("soar_assign_candidates", [_i64, _i32, _i32, ctypes.POINTER(AssignOpts), ctypes.POINTER(_sz),
-                                ctypes.POINTER(_sz), ctypes.POINTER(_i32)])
+                                ctypes.POINTER(_sz), ctypes.POINTER(_i32), ctypes.POINTER(_sz)])
 _sig("soar_spill_further_workspace_size", [_i64, _i32, _i32, _i32, ctypes.POINTER(_sz)])
 _sig("soar_spill_further", [_vp, _i64, _i32, _vp, _i32, _vp, _i32, _f32, _f32, _vp, _vp, _vp, _sz,
                             _vp, ctypes.POINTER(Stats)])
@@ -177,13 +179,14 @@ def assign_workspace_size(n, d, K, lam=1.0, precision="fp32", topk=0, near_tie_r
 
 
 def assign(X, C, lam, precision="fp32", topk=0, near_tie_rel=0.0, stream=None, out=None,
-           workspace=None, flags=0, stats=False, spill_form="auto"):
+           workspace=None, flags=0, stats=False, spill_form="auto", bound=True):
     """SOAR assignment of every row of X against codebook C (both float32 on the GPU).
 
     ``spill_form``: "auto", "grouped" or "direct" (the form of the spill sweep; same results).
+    ``bound=False`` sets SOAR_NO_BOUND (every row's spill goes through the sweep).
     Returns (primary int32[n], spill int32[n], primary_dist float32[n], spill_loss float32[n])
     and, with ``stats=True``, a dict of call statistics as a fifth element."""
-    flags = int(flags) | _SPILL_FORM[spill_form]
+    flags = int(flags) | _SPILL_FORM[spill_form] | (0 if bound else NO_BOUND)
     X, C = _f32_matrix(X, "X"), _f32_matrix(C, "C")
     n, d = X.shape
     K = C.shape[0]
@@ -208,17 +211,22 @@ def assign(X, C, lam, precision="fp32", topk=0, near_tie_rel=0.0, stream=None, o
     return (*out, st.as_dict()) if stats else out
 
 
-def assign_candidates(workspace, n, d, K, lam=1.0, precision="bf16", topk=0, near_tie_rel=0.0):
+def assign_candidates(workspace, n, d, K, lam=1.0, precision="bf16", topk=0, near_tie_rel=0.0,
+                      bound_key=False):
     """The re-scored candidates the last BF16/FP8 assign() left in ``workspace`` (same sizes and
     options): (primary int32[n, topk], spill int32[n, topk]) views of the workspace, -1 for an
-    empty place."""
+    empty place.  With ``bound_key=True`` a third view, int32[n]: after a call that used the
+    spill bound, -1 for the rows it decided (and rows without a primary), else the primary."""
     o = _opts(lam, precision, topk, near_tie_rel, 0)
-    po, so, tk = _sz(), _sz(), _i32()
+    po, so, tk, bo = _sz(), _sz(), _i32(), _sz()
     _check(_lib.soar_assign_candidates(n, d, K, ctypes.byref(o), ctypes.byref(po),
-                                       ctypes.byref(so), ctypes.byref(tk)),
+                                       ctypes.byref(so), ctypes.byref(tk), ctypes.byref(bo)),
            "soar_assign_candidates")
     nb = n * tk.value * 4
     view = lambda off: workspace[off:off + nb].view(torch.int32).view(n, tk.value)  # noqa: E731
+    if bound_key:
+        return (view(po.value), view(so.value),
+                workspace[bo.value:bo.value + n * 4].view(torch.int32))
     return view(po.value), view(so.value)
 
 

@@ -530,6 +530,7 @@ void lowp_sweep_kernel(LowpParams P) {
   // If not, do they hold only the primaries of the first and the last stripe (a wave across one
   // partition boundary)?  Then two broadcasts serve them, and psel picks each stripe's.
   bool samep = false, twop = false;
+  const int plane = GR ? sd[0].x - c16 : 0;       // GR: first column of a block whose lane c16 is p
   bool psel[GR ? SPW : 1];
   if constexpr (GR && SPW > 1) {
     bool same = true, two = true;
@@ -543,7 +544,10 @@ void lowp_sweep_kernel(LowpParams P) {
     samep = __builtin_amdgcn_readfirstlane((int)same) != 0;
     twop = __builtin_amdgcn_readfirstlane((int)two) != 0;
   }
-  auto epi_prep = [&](auto set, int ts, int g) __attribute__((always_inline)) {
+  // em (wave-uniform, fixed for the wave's lifetime): 1 when every stripe shares its primary
+  // (GR); the sweep loop is instantiated once per value, so that a shared broadcast is one
+  // register per block in the epilogue rather than a copy per stripe.
+  auto epi_prep = [&](auto set, auto em, int ts, int g) __attribute__((always_inline)) {
     constexpr int S = decltype(set)::value;
     // each packing is then one v_and_or with an SGPR
 #pragma unroll
@@ -575,20 +579,22 @@ void lowp_sweep_kernel(LowpParams P) {
         e0 = __builtin_bit_cast(float, (unsigned)g32[0]);
         e1 = __builtin_bit_cast(float, (unsigned)g32[1]);
       };
-      if (GR && samep) {
-        // every stripe of the wave has the same centroid row: one broadcast serves them all
+      if (GR && decltype(em)::value == 1) {
+        // every stripe of the wave has the same centroid row: one broadcast serves them all.
+        // The shared primary's column is masked here, once per block: its D_j becomes kBig, so
+        // its value z^2 + kBig never leads a class (the sweep takes no masked epilogue).
+        float e[GU];
         if constexpr (GU == 2) {
-          float e0, e1;
-          bcast2(0, e0, e1);
-#pragma unroll
-          for (int st = 0; st < SPW; ++st) { espv[st][0] = e0; espv[st][1] = e1; }
+          bcast2(0, e[0], e[1]);
         } else {
 #pragma unroll
-          for (int b = 0; b < GU; ++b) {
-            const float e = bcast(0, b);
+          for (int b = 0; b < GU; ++b) e[b] = bcast(0, b);
+        }
 #pragma unroll
-            for (int st = 0; st < SPW; ++st) espv[st][b] = e;
-          }
+        for (int b = 0; b < GU; ++b) {
+          e[b] = ts * BN + (g + NU * b) * 16 == plane ? kBig : e[b];
+#pragma unroll
+          for (int st = 0; st < SPW; ++st) espv[st][b] = e[b];
         }
       } else if (GR && SPW > 2 && twop) {
         if constexpr (GU == 2) {
@@ -662,8 +668,9 @@ void lowp_sweep_kernel(LowpParams P) {
       }
     }
   };
-  auto epi_unit = [&](auto set, auto with_mask, int ts, int g) __attribute__((always_inline)) {
-    epi_prep(set, ts, g);
+  auto epi_unit = [&](auto set, auto em, auto with_mask, int ts, int g)
+                      __attribute__((always_inline)) {
+    epi_prep(set, em, ts, g);
 #pragma unroll
     for (int i = 0; i < NR; ++i) epi_slot(set, with_mask, i, ts, g);
   };
@@ -672,7 +679,7 @@ void lowp_sweep_kernel(LowpParams P) {
   // by hand between them: a few row slots while the first operands arrive from LDS, the rest
   // spread evenly after the MFMAs; scheduling barriers keep that order, so the wave always has
   // independent VALU work to issue while the matrix core runs.
-  auto fused_unit = [&](auto set, const char* tile, int g, int tsp, int gp)
+  auto fused_unit = [&](auto set, auto em, const char* tile, int g, int tsp, int gp)
                         __attribute__((always_inline)) {
     constexpr int S = decltype(set)::value;
     const auto pset = std::integral_constant<int, 1 - S>{};
@@ -702,7 +709,7 @@ void lowp_sweep_kernel(LowpParams P) {
     };
     read_step(0, 0);
     if constexpr (NSTEP > 1) read_step(1, 1);
-    epi_prep(pset, tsp, gp);
+    epi_prep(pset, em, tsp, gp);
 #pragma unroll
     for (int i = 0; i < PRE; ++i) epi_slot(pset, std::false_type{}, i, tsp, gp);
     __builtin_amdgcn_sched_barrier(0);
@@ -752,70 +759,88 @@ void lowp_sweep_kernel(LowpParams P) {
   const char* tile = s_ring;
   int stage = 0;
   bool m_cur = false, m_last = false;             // masks of the current and the previous tile
-  // One pipeline step: unit u = (t, g) into set S, the epilogue of unit u - 1 from set 1 - S.
-  auto step = [&](auto set, int u) __attribute__((always_inline)) {
-    constexpr int S = decltype(set)::value;
-    constexpr int G = NU == 2 ? S : 0;             // unit u has g = u % NU = S when NU == 2
-    const int t = NU == 2 ? (u >> 1) : u;
-    if (G == 0) {
-      // record t has landed in LDS for this wave (later records may still be in flight) ...
-      // (vmcnt counts VMEM operations of this wave in order: with later records in flight,
-      // leaving at most the last record's NI copies outstanding means record t is complete)
-      if (STG > 2 && t + 1 < ntiles)
-        wait_vmcnt<NI>();
-      else
-        wait_vmcnt<0>();
-      // ... and for every wave; every wave is also done reading the stage refilled next (its
-      // last reads were the B operands of tile t - 1, issued before this barrier)
-      __builtin_amdgcn_s_barrier();
-      if (t + STG - 1 < ntiles)
-        issue(t + STG - 1);
-      tile = s_ring + stage * STAGE;
-      stage = stage + 1 == STG ? 0 : stage + 1;
-      m_last = m_cur;
-      m_cur = tile_masked(t);
-    }
-    if constexpr (!PIPE) {
-      const auto s0 = std::integral_constant<int, 0>{};
-      mfma_unit(s0, tile, G);
-      if (__builtin_expect(m_cur, 0)) epi_unit(s0, std::true_type{}, t, G);
-      else epi_unit(s0, std::false_type{}, t, G);
-      return;
-    }
-    constexpr int GP = NU == 2 ? 1 - S : 0;        // the previous unit's g
-    constexpr bool SAME_TILE = NU == 2 && S == 1;  // the previous unit is in tile t
-    const int tp = SAME_TILE ? t : t - 1;
-    const bool mp = SAME_TILE ? m_cur : m_last;
-    const auto prev = std::integral_constant<int, 1 - S>{};
-    if (u == 0) {
-      mfma_unit(set, tile, G);
-    } else if (__builtin_expect(mp, 0)) {
-      epi_unit(prev, std::true_type{}, tp, GP);
-      mfma_unit(set, tile, G);
+  // Start of tile t: its record is in LDS for every wave, and a later record is issued.
+  auto begin_tile = [&](int t) __attribute__((always_inline)) {
+    // record t has landed in LDS for this wave (later records may still be in flight) ...
+    // (vmcnt counts VMEM operations of this wave in order: with later records in flight,
+    // leaving at most the last record's NI copies outstanding means record t is complete)
+    if (STG > 2 && t + 1 < ntiles)
+      wait_vmcnt<NI>();
+    else
+      wait_vmcnt<0>();
+    // ... and for every wave; every wave is also done reading the stage refilled next (its
+    // last reads were the B operands of tile t - 1, issued before this barrier)
+    __builtin_amdgcn_s_barrier();
+    if (t + STG - 1 < ntiles)
+      issue(t + STG - 1);
+    tile = s_ring + stage * STAGE;
+    stage = stage + 1 == STG ? 0 : stage + 1;
+    m_last = m_cur;
+    m_cur = tile_masked(t);
+  };
+  const auto s0 = std::integral_constant<int, 0>{};
+  const auto s1 = std::integral_constant<int, 1>{};
+  // One pipeline step: unit (current tile, g) into set S, and the epilogue of the previous unit
+  // (tp, gp) from set 1 - S, masked when that unit's tile holds a primary (mp).
+  auto step = [&](auto set, auto em, int g, int tp, int gp, bool mp)
+                  __attribute__((always_inline)) {
+    const auto prev = std::integral_constant<int, 1 - decltype(set)::value>{};
+    if (decltype(em)::value != 1 && __builtin_expect(mp, 0)) {
+      epi_unit(prev, em, std::true_type{}, tp, gp);
+      mfma_unit(set, tile, g);
     } else {
-      fused_unit(set, tile, G, tp, GP);
+      fused_unit(set, em, tile, g, tp, gp);
     }
   };
-  const int nunits = ntiles * NU;
-  if constexpr (PIPE) {
-    for (int u = 0; u < nunits; u += 2) {
-      step(std::integral_constant<int, 0>{}, u);
-      if (u + 1 < nunits) step(std::integral_constant<int, 1>{}, u + 1);
-    }
-  } else {
-    for (int u = 0; u < nunits; ++u) step(std::integral_constant<int, 0>{}, u);
-  }
-  // drain: the epilogue of the last unit
-  if constexpr (PIPE) {
-    const int ul = nunits - 1;
-    const bool ml = m_cur;                       // the last unit is in the last tile
-    if (ul & 1) {
-      if (ml) epi_unit(std::integral_constant<int, 1>{}, std::true_type{}, ntiles - 1, NU - 1);
-      else epi_unit(std::integral_constant<int, 1>{}, std::false_type{}, ntiles - 1, NU - 1);
+  auto drain = [&](auto set, auto em, int tp, int gp) __attribute__((always_inline)) {
+    if (decltype(em)::value != 1 && m_cur) epi_unit(set, em, std::true_type{}, tp, gp);
+    else epi_unit(set, em, std::false_type{}, tp, gp);
+  };
+  // The tile loop, with the first unit peeled and the sets fixed per position, so that no
+  // accumulator changes registers between iterations.
+  auto run = [&](auto em) __attribute__((always_inline)) {
+    if constexpr (!PIPE) {
+      for (int t = 0; t < ntiles; ++t) {
+        begin_tile(t);
+        mfma_unit(s0, tile, 0);
+        drain(s0, em, t, 0);
+      }
+    } else if constexpr (NU == 2) {
+      // units (t, 0) in set 0 and (t, 1) in set 1
+      begin_tile(0);
+      mfma_unit(s0, tile, 0);
+      step(s1, em, 1, 0, 0, m_cur);
+      for (int t = 1; t < ntiles; ++t) {
+        begin_tile(t);
+        step(s0, em, 0, t - 1, 1, m_last);
+        step(s1, em, 1, t, 0, m_cur);
+      }
+      drain(s1, em, ntiles - 1, 1);
     } else {
-      if (ml) epi_unit(std::integral_constant<int, 0>{}, std::true_type{}, ntiles - 1, NU - 1);
-      else epi_unit(std::integral_constant<int, 0>{}, std::false_type{}, ntiles - 1, NU - 1);
+      // one unit per tile: even tiles in set 0, odd tiles in set 1
+      begin_tile(0);
+      mfma_unit(s0, tile, 0);
+      int t = 1;
+      for (; t + 1 < ntiles; t += 2) {
+        begin_tile(t);
+        step(s1, em, 0, t - 1, 0, m_last);
+        begin_tile(t + 1);
+        step(s0, em, 0, t, 0, m_last);
+      }
+      if (t < ntiles) {
+        begin_tile(t);
+        step(s1, em, 0, t - 1, 0, m_last);
+        drain(s1, em, t, 0);
+      } else {
+        drain(s0, em, t - 1, 0);
+      }
     }
+  };
+  if constexpr (GR && SPW > 1) {
+    if (samep) run(std::integral_constant<int, 1>{});
+    else run(std::integral_constant<int, 0>{});
+  } else {
+    run(std::integral_constant<int, 0>{});
   }
 
   // candidates: the topk smallest kept values of every row across its 16 lanes (value, then
@@ -1060,7 +1085,11 @@ void lowp_rescore_kernel(LowpParams P) {
   if (bj == 0x7fffffff) {
     if (l16 == 0) {
       if (SP) { P.spill[row] = -1; if (P.sloss) P.sloss[row] = kInf; }
-      else { P.primary[row] = -1; if (P.pdist) P.pdist[row] = kInf; }
+      else {
+        P.primary[row] = -1;
+        if (P.pdist) P.pdist[row] = kInf;
+        if (P.gkey) P.gkey[row] = -1;            // no primary: no spill, no group
+      }
     }
     return;
   }
@@ -1123,6 +1152,22 @@ void lowp_rescore_kernel(LowpParams P) {
   // sigma = sqrt(lambda) / (2 ||r||): the residual rows are stored pre-scaled by it, FP8 ones
   // with a power-of-two scale of their own
   const float rn = sqrtf(r2);
+  if (P.nbr) {
+    // Spill bound: U = (1 + lambda) ||x - c_j2||^2 for the nearest other candidate j2 bounds the
+    // spill's loss, so the spill lies within ||r|| + sqrt(U) of c_pi; when the table's bound on
+    // the centroids beyond c_pi's topk nearest exceeds that radius (with a margin for the FP32
+    // rounding of both sides), those topk are the row's spill candidates.
+    float second = kInf;
+#pragma unroll
+    for (int c = 0; c < kMaxTopk; ++c) {
+      if (c >= topk) continue;
+      if (P.cand[row * topk + c] != bj) second = fminf(second, vals[c]);
+    }
+    const float rad = (rn + sqrtf((1.f + P.lam) * second)) * (1.f + 4.f * (float)(d + 8) * kU32);
+    const bool in = rad < P.nbr_lb[bj];
+    if (in && l16 < topk) P.cand_spill[row * topk + l16] = P.nbr[(int64_t)bj * topk + l16];
+    if (l16 == 0) P.gkey[row] = in ? -1 : bj;
+  }
   const float sigma = rn > 0.f ? 0.5f * sqrtf(P.lam) / rn : 0.f;
   float inv = 1.f, scale = 1.f;
   if constexpr (FMT == LOWP_FP8) {

@@ -16,6 +16,7 @@ enum Counter : int {
   CNT_NONFINITE = 1,  // set when a NaN/Inf was read from X or C
   CNT_FP64 = 2,       // rows whose decision was taken in FP64
   CNT_CMAX2 = 3,      // max_j ||c_j||^2 as float bits (non-negative floats order like uints)
+  CNT_BOUNDED = 5,    // rows whose spill candidates came from the spill bound (no sweep)
   CNT_WORDS = 8,      // words of one call's counters (cleared by every call)
   // status record of enqueue-only calls, kept across calls (see async_note_kernel)
   CNT_ASYNC_M0 = 8,

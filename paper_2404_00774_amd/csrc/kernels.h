@@ -173,6 +173,14 @@ struct LowpParams {
   int ksplit = 1;
   int32_t* cand_split = nullptr;
   float* cand_val = nullptr;
+  // spill bound (launch_centroid_knn): with nbr set, the primary re-score writes, for each row
+  // whose spill provably lies among its primary centroid's topk nearest centroids, those as the
+  // row's spill candidates (cand_spill) and -1 as its group key; every other row gets its
+  // primary as group key (gkey), and only those rows are grouped for the spill sweep
+  const int32_t* nbr = nullptr;     // [K x topk]
+  const float* nbr_lb = nullptr;    // [K]
+  int32_t* cand_spill = nullptr;    // [n x topk]
+  int32_t* gkey = nullptr;          // [n]
 };
 
 int lowp_padded_dim(int fmt, int d);
@@ -197,5 +205,14 @@ hipError_t launch_lowp_pack_codebook(int fmt, const float* C, int K, int d, cons
 hipError_t launch_lowp_rescore(int fmt, const LowpParams& P, bool spill, hipStream_t st);
 // Merges the split candidates of a sweep (no-op for P.ksplit <= 1).
 hipError_t launch_lowp_merge(const LowpParams& P, hipStream_t st);
+// The spill bound's table: for every centroid p, its M (<= kBoundMaxM) nearest other centroids
+// (ascending; -1 where K - 1 < M) and a lower bound on ||c_p - c_j|| over every other j
+// (+inf when none is left out).  cnorm holds ||c_j||^2.
+constexpr int kBoundMaxM = 8;
+hipError_t launch_centroid_knn(const float* C, int K, int d, const float* cnorm, int M,
+                               int32_t* nbr, float* nbr_lb, hipStream_t st);
+// counters[CNT_BOUNDED] = n - group_off[K]: the rows the grouping left out.
+hipError_t launch_bound_count(const int32_t* group_off, int K, int64_t n, unsigned* counters,
+                              hipStream_t st);
 
 }  // namespace soar

@@ -80,6 +80,9 @@ struct LowpLayout {
   void* Cp;             // codebook rows quantized like X (grouped spill form)
   float* cps;
   void* group;
+  int32_t* nbr;         // [K x topk] spill bound: nearest centroids of every centroid
+  float* nbr_lb;        // [K] and the bound on the distance to the others
+  int32_t* gkey;        // [n] group key of the spill sweep (-1: bounded row)
   size_t bytes;
 };
 
@@ -101,6 +104,9 @@ LowpLayout layout_lowp(void* ws, int64_t n, int32_t d, int32_t K, int fmt, int t
   L.Cp = c.take<char>((size_t)K * dp * eb);
   L.cps = c.take<float>((size_t)K);
   L.group = c.take<char>(soar::group_layout(nullptr, n, K).bytes);
+  L.nbr = c.take<int32_t>((size_t)K * topk);
+  L.nbr_lb = c.take<float>((size_t)K);
+  L.gkey = c.take<int32_t>((size_t)n);
   L.bytes = c.off;
   return L;
 }
@@ -246,8 +252,9 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
                             float lam, float near_tie_rel, int fmt, int topk, int32_t* primary,
                             int32_t* spill_out, float* pdist, float* sloss, void* ws,
                             hipStream_t st, unsigned* counters_out_host, hipEvent_t* ev,
-                            uint32_t spill_form) {
+                            uint32_t flags) {
   LowpLayout L = layout_lowp(ws, n, d, K, fmt, topk);
+  const uint32_t spill_form = flags & (SOAR_SPILL_GROUPED | SOAR_SPILL_DIRECT);
   // The grouped form trades the second MFMA stream for epilogue work.  Over residual rows
   // (lambda >= kGroupedResidualMinLam) that work is the direct form's one fma per element, so it
   // pays wherever grouping does: n=10M, d=96, K=40,000, BF16 149.5 vs 186.0 ms per call, FP8
@@ -259,6 +266,9 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
                         (grouped_residual_rows(fmt, lam) ||
                          (fmt != LOWP_BF16 && lowp_padded_dim(fmt, d) >= 512)));
   const GroupLayout GL = group_layout(L.group, n, K);
+  // The spill bound (bound.hip) serves the grouped form: rows it decides leave the grouping, and
+  // the spill sweep runs over the rest.
+  const bool bound = grouped && topk <= kBoundMaxM && !(flags & SOAR_NO_BOUND);
   LowpParams P;
   P.n = n; P.d = d; P.dp = lowp_padded_dim(fmt, d); P.K = K; P.topk = topk;
   P.lam = lam;
@@ -279,16 +289,22 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
     e = launch_lowp_pack_codebook(fmt, C, K, d, L.cnorm, L.Cq, L.counters, st);
   if (e == hipSuccess && grouped)
     e = launch_lowp_quantize(fmt, C, K, d, P.dp, false, L.Cp, L.cps, L.counters, st);
+  if (e == hipSuccess && bound)
+    e = launch_centroid_knn(C, K, d, L.cnorm, topk, L.nbr, L.nbr_lb, st);
   if (e == hipSuccess)
     e = launch_lowp_quantize(fmt, X, n, d, P.dp, false, L.Xq, L.xs, L.counters, st);
   if (e == hipSuccess) e = mark(1);
   if (e == hipSuccess) e = launch_lowp_sweep(fmt, P, false, st);
   if (e == hipSuccess) e = mark(2);
+  if (bound) { P.nbr = L.nbr; P.nbr_lb = L.nbr_lb; P.cand_spill = L.cand; P.gkey = L.gkey; }
   if (e == hipSuccess) e = launch_lowp_rescore(fmt, P, false, st);
+  P.nbr = nullptr; P.nbr_lb = nullptr; P.cand_spill = nullptr; P.gkey = nullptr;
   if (e == hipSuccess) e = mark(3);
   P.cand = L.cand;
   if (grouped) {
-    if (e == hipSuccess) e = launch_group_by_primary(primary, n, nullptr, K, GL, st);
+    if (e == hipSuccess)
+      e = launch_group_by_primary(bound ? L.gkey : primary, n, nullptr, K, GL, st);
+    if (e == hipSuccess && bound) e = launch_bound_count(GL.off, K, n, L.counters, st);
     if (e == hipSuccess) e = mark(4);
     if (e == hipSuccess) e = launch_lowp_sweep_grouped(fmt, P, st);
   } else {
@@ -330,6 +346,7 @@ soar_status assign_impl(const float* X, int64_t n, int32_t d, const float* C, in
   }
   unsigned cnt[soar::CNT_WORDS] = {0};
   const uint32_t form = o.flags & (SOAR_SPILL_GROUPED | SOAR_SPILL_DIRECT);
+  const uint32_t lowp_flags = form | (o.flags & SOAR_NO_BOUND);
   soar_status s;
   if (!lowp)
     s = soar::run_assign_fp32(X, n, d, C, K, o.lambda, o.near_tie_rel, true, primary, spill,
@@ -338,7 +355,7 @@ soar_status assign_impl(const float* X, int64_t n, int32_t d, const float* C, in
   else
     s = soar::run_assign_lowp(X, n, d, C, K, o.lambda, o.near_tie_rel, lowp_fmt(o),
                               lowp_topk(o, d), primary, spill, primary_dist, spill_loss, workspace,
-                              st, async ? nullptr : cnt, ev[0] ? ev : nullptr, form);
+                              st, async ? nullptr : cnt, ev[0] ? ev : nullptr, lowp_flags);
   if (s != SOAR_OK) { destroy(); return s; }
   if (async) {
     destroy();
@@ -363,6 +380,8 @@ soar_status assign_impl(const float* X, int64_t n, int32_t d, const float* C, in
     stats->rows_fp64 = cnt[soar::CNT_FP64];
     stats->mfma_flops = 4.0 * (double)n * (double)K * (double)d;
     for (int k = 0; k < 6; ++k) stats->phase_ms[k] = ph[k];
+    if (stats->struct_size >= offsetof(soar_stats, rows_bounded) + sizeof(int64_t))
+      stats->rows_bounded = cnt[soar::CNT_BOUNDED];
   }
   destroy();
   const bool async_bad = rec[0] == soar::kAsyncMagic0 && rec[1] == soar::kAsyncMagic1 && rec[2];
@@ -429,7 +448,8 @@ soar_status soar_assign_workspace_size(int64_t n, int32_t d, int32_t K,
 }
 
 soar_status soar_assign_candidates(int64_t n, int32_t d, int32_t K, const soar_assign_opts* opts,
-                                   size_t* primary_off, size_t* spill_off, int32_t* topk) {
+                                   size_t* primary_off, size_t* spill_off, int32_t* topk,
+                                   size_t* bound_key_off) {
   OptsView o;
   if (!primary_off || !spill_off || !topk || !read_opts(opts, &o)) return SOAR_E_INVAL;
   const soar_status s = validate_assign(n, d, K, o);
@@ -440,6 +460,7 @@ soar_status soar_assign_candidates(int64_t n, int32_t d, int32_t K, const soar_a
   const LowpLayout L = layout_lowp(base, n, d, K, lowp_fmt(o), lowp_topk(o, d));
   *primary_off = reinterpret_cast<char*>(L.cand_p) - base;
   *spill_off = reinterpret_cast<char*>(L.cand) - base;
+  if (bound_key_off) *bound_key_off = reinterpret_cast<char*>(L.gkey) - base;
   *topk = lowp_topk(o, d);
   return SOAR_OK;
 }
@@ -463,7 +484,7 @@ soar_status soar_spill_further(const float* X, int64_t n, int32_t d, const float
     return SOAR_E_INVAL;
   const FurtherLayout L = layout_further(workspace, n, d, K);
   if (!workspace || !aligned(workspace, kAlign) || ws_bytes < L.bytes) return SOAR_E_INVAL;
-  if (stats && stats->struct_size < sizeof(soar_stats)) return SOAR_E_INVAL;
+  if (stats && stats->struct_size < offsetof(soar_stats, rows_bounded)) return SOAR_E_INVAL;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   hipEvent_t ev[2] = {};
   auto destroy = [&]() {
@@ -526,7 +547,7 @@ soar_status soar_assign(const float* X, int64_t n, int32_t d, const float* C, in
   const soar_status s = soar::assign_validate(X, n, d, C, K, opts, primary, spill, &need);
   if (s != SOAR_OK) return s;
   if (!workspace || !aligned(workspace, kAlign) || ws_bytes < need) return SOAR_E_INVAL;
-  if (stats && stats->struct_size < sizeof(soar_stats)) return SOAR_E_INVAL;
+  if (stats && stats->struct_size < offsetof(soar_stats, rows_bounded)) return SOAR_E_INVAL;
   return soar::assign_run(X, n, d, C, K, opts, primary, spill, primary_dist, spill_loss,
                           workspace, static_cast<hipStream_t>(stream), stats);
 }

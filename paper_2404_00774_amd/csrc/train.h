@@ -17,7 +17,7 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
                             float lam, float near_tie_rel, int fmt, int topk, int32_t* primary,
                             int32_t* spill_out, float* pdist, float* sloss, void* ws,
                             hipStream_t st, unsigned* counters_out_host,
-                            hipEvent_t* ev = nullptr, uint32_t spill_form = 0);
+                            hipEvent_t* ev = nullptr, uint32_t flags = 0);
 // Phase boundaries recorded by run_assign_fp32 / run_assign_lowp when given 7 events:
 // [0] start, [1] after the codebook and row preparation, [2] after the primary sweep, [3] after
 // the primary re-score, [4] after the grouping by primary, [5] after the spill sweep, [6] end

@@ -902,3 +902,58 @@ def test_two_level_search_full_upper_probe_is_flat_search_and_a_missed_partition
     assert parts.tolist() == [[1, -1]]
     parts, _ = O.probe_two_level(q, U2, ua2, C2, 2, 2)
     assert parts.tolist() == [[0, 1]]
+
+
+# ------------------------------------------------------------------------------------------------
+# Spill bound (Section 3.4's loss, Cauchy-Schwarz and the triangle inequality): the spill lies
+# within ||r|| + sqrt((1 + lambda) ||x - c_j2||^2) of the primary centroid, so rows whose
+# radius stays below the (M+1)-th nearest centroid have their spill among the M nearest.
+# ------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("lam", [0.0, 0.5, 1.0, 4.0])
+def test_spill_bound_confines_the_spill(lam):
+    from synth import MixtureSpec, gen_mixture
+    X = gen_mixture(MixtureSpec(3000, 16, 40, ("loguniform", 0.05, 0.5), "unit", 5))
+    C, _, _ = O.train_codebook(X, 100, 3, seed=0)
+    p, _ = O.primary_plain(X, C)
+    s, _ = O.spill_plain(X, C, lam, p)
+    C64 = C.astype(np.float64)
+    for M in (1, 4, 8):
+        mask, radius, nb, beyond = O.spill_bound_rows(X, C, lam, p, M)
+        # the radius bounds the spill's distance from c_p on every row, decided or not
+        reach = np.sqrt(((C64[p] - C64[s]) ** 2).sum(1))
+        assert np.all(reach <= radius * (1 + 1e-12))
+        # decided rows have their spill among the M nearest centroids of c_p
+        assert all(s[i] in nb[p[i]] for i in np.flatnonzero(mask))
+        if M == 8:
+            assert mask.mean() > 0.3, mask.mean()   # the bound decides a good share of rows
+
+
+def test_spill_bound_radius_is_tight_where_it_should_be():
+    # x on the segment between c_0 and c_1 with c_1 the spill: the radius is reached exactly
+    # when lambda = 0 (||c_0 - c_1|| = ||r|| + ||x - c_1||)
+    X = np.array([[1.0, 0.0]], dtype=np.float32)
+    C = np.array([[0.0, 0.0], [3.0, 0.0], [0.0, 9.0]], dtype=np.float32)
+    mask, radius, nb, beyond = O.spill_bound_rows(X, C, 0.0, [0], 1)
+    assert radius[0] == 3.0 and nb[0, 0] == 1 and beyond[0] == 9.0 and mask[0]
+    mask, radius, _, _ = O.spill_bound_rows(X, C, 8.0, [0], 1)
+    assert radius[0] == 1.0 + 6.0 and mask[0]
+    mask, radius, _, _ = O.spill_bound_rows(X, C, 24.0, [0], 1)
+    assert radius[0] == 11.0 and not mask[0]
+
+
+def test_centroid_neighbours_order_ties_and_short_codebooks():
+    C = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [3, 0]], dtype=np.float32)
+    nb, beyond = O.centroid_neighbours(C, 2)
+    # from c_0 three centroids are at distance 1: the two lowest indices are kept
+    assert list(nb[0]) == [1, 2] and beyond[0] == 1.0
+    assert list(nb[4]) == [1, 0] and beyond[4] == np.sqrt(10.0)
+    nb, beyond = O.centroid_neighbours(C[:3], 4)
+    assert list(nb[1]) == [0, 2, -1, -1] and np.isinf(beyond).all()
+    # brute force on random centroids
+    R = np.random.default_rng(3).standard_normal((30, 5)).astype(np.float32)
+    nb, beyond = O.centroid_neighbours(R, 6)
+    for q in range(30):
+        dd = [(float(np.sqrt(((R[q].astype(float) - R[j]) ** 2).sum())), j) for j in range(30)
+              if j != q]
+        dd.sort()
+        assert [j for _, j in dd[:6]] == list(nb[q]) and dd[6][0] == beyond[q]
