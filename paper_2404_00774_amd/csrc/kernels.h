@@ -209,8 +209,11 @@ hipError_t launch_lowp_merge(const LowpParams& P, hipStream_t st);
 // (ascending; -1 where K - 1 < M) and a lower bound on ||c_p - c_j|| over every other j
 // (+inf when none is left out).  cnorm holds ||c_j||^2.
 constexpr int kBoundMaxM = 8;
+// scratch_v / scratch_j: knn_scratch_entries(K) entries each (per-part lists before the merge).
+size_t knn_scratch_entries(int K);
 hipError_t launch_centroid_knn(const float* C, int K, int d, const float* cnorm, int M,
-                               int32_t* nbr, float* nbr_lb, hipStream_t st);
+                               float* scratch_v, int32_t* scratch_j, int32_t* nbr, float* nbr_lb,
+                               hipStream_t st);
 // counters[CNT_BOUNDED] = n - group_off[K]: the rows the grouping left out.
 hipError_t launch_bound_count(const int32_t* group_off, int K, int64_t n, unsigned* counters,
                               hipStream_t st);

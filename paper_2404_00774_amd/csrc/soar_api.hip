@@ -83,6 +83,8 @@ struct LowpLayout {
   int32_t* nbr;         // [K x topk] spill bound: nearest centroids of every centroid
   float* nbr_lb;        // [K] and the bound on the distance to the others
   int32_t* gkey;        // [n] group key of the spill sweep (-1: bounded row)
+  float* knn_v;         // the table's per-part lists before their merge
+  int32_t* knn_j;
   size_t bytes;
 };
 
@@ -107,6 +109,8 @@ LowpLayout layout_lowp(void* ws, int64_t n, int32_t d, int32_t K, int fmt, int t
   L.nbr = c.take<int32_t>((size_t)K * topk);
   L.nbr_lb = c.take<float>((size_t)K);
   L.gkey = c.take<int32_t>((size_t)n);
+  L.knn_v = c.take<float>(soar::knn_scratch_entries(K));
+  L.knn_j = c.take<int32_t>(soar::knn_scratch_entries(K));
   L.bytes = c.off;
   return L;
 }
@@ -290,7 +294,7 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
   if (e == hipSuccess && grouped)
     e = launch_lowp_quantize(fmt, C, K, d, P.dp, false, L.Cp, L.cps, L.counters, st);
   if (e == hipSuccess && bound)
-    e = launch_centroid_knn(C, K, d, L.cnorm, topk, L.nbr, L.nbr_lb, st);
+    e = launch_centroid_knn(C, K, d, L.cnorm, topk, L.knn_v, L.knn_j, L.nbr, L.nbr_lb, st);
   if (e == hipSuccess)
     e = launch_lowp_quantize(fmt, X, n, d, P.dp, false, L.Xq, L.xs, L.counters, st);
   if (e == hipSuccess) e = mark(1);
