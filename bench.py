@@ -105,10 +105,12 @@ METRIC = "SOAR-assigned points/sec and % MFMA peak, BF16/FP8 vs FP32 at ≤1e-3 
 DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8_e4m3"}
 KERNEL = {"fp32": "codebook packing, assign_f32_kernel (primary), grouping by primary, "
                   "assign_f32_spill_grouped (spill), exact full scan",
-          "bf16": "quantization, lowp_sweep_kernel (primary), lowp_rescore_kernel, grouping by "
-                  "primary, lowp_sweep_kernel (spill), lowp_rescore_kernel",
-          "fp8": "quantization, lowp_sweep_kernel (primary), lowp_rescore_kernel, grouping by "
-                 "primary, lowp_sweep_kernel (spill), lowp_rescore_kernel"}
+          "bf16": "quantization, centroid_knn_kernel (spill bound table), lowp_sweep_kernel "
+                  "(primary), lowp_rescore_kernel (with the bound), grouping of the unbounded rows "
+                  "by primary, lowp_sweep_kernel (spill), lowp_rescore_kernel",
+          "fp8": "quantization, centroid_knn_kernel (spill bound table), lowp_sweep_kernel "
+                 "(primary), lowp_rescore_kernel (with the bound), grouping of the unbounded rows "
+                 "by primary, lowp_sweep_kernel (spill), lowp_rescore_kernel"}
 
 
 def parse():
@@ -479,6 +481,7 @@ def time_form(soar, torch, Xg, Cg, lam, prec, steps, warmup, n, d, K, keep_candi
              phase_ms=phases,
              rows_full_scan=int(np.mean([st["rows_full_scan"] for st in stats])),
              rows_fp64=int(np.mean([st["rows_fp64"] for st in stats])),
+             rows_bounded=int(np.mean([st["rows_bounded"] for st in stats])),
              steps=steps, warmup=warmup,
              out=tuple(t.cpu().numpy() for t in out))
     if cands is not None:
@@ -749,6 +752,15 @@ def main():
             r["algorithmic_tflops"] = alg / (r["device_ms"] / 1e3) / 1e12
             r["mfma_peak_frac"] = r["algorithmic_tflops"] / PEAKS_TFLOPS[prec]
             r["sweeps_mfma_peak_frac"] = alg / (r["sweep_ms"] / 1e3) / 1e12 / PEAKS_TFLOPS[prec]
+            if prec != "fp32":
+                # MFMA work the call executes: the primary sweep over every row, the spill sweep
+                # over the rows the spill bound left (stripes of 15 rows and the centroid: at
+                # least 16/15 of them), the bound's table (FP32, 2 K^2 d)
+                ex = 2.0 * n * K * d + 2.0 * (n - r["rows_bounded"]) * K * d * 16 / 15
+                r["executed_mfma_flops"] = ex
+                r["executed_tflops"] = ex / (r["device_ms"] / 1e3) / 1e12
+                r["executed_frac"] = r["executed_tflops"] / PEAKS_TFLOPS[prec]
+                r["table_flops_fp32"] = 2.0 * K * K * d
             print(f"[bench] lambda {lam} {prec}: {r['ms_per_step']:.3f} ms/step, device "
                   f"{r['device_ms']:.3f} ms, {r['mfma_peak_frac']:.3f} of peak; phases "
                   f"{ {k_: round(v, 3) for k_, v in r['phase_ms'].items()} }",
@@ -768,6 +780,12 @@ def main():
                 "kernel_ms": head["device_ms"], "algorithmic_flops_per_launch": alg,
                 "phase_ms": phases,
                 "sweeps_frac": head["sweeps_mfma_peak_frac"]}
+    if "executed_frac" in head:
+        # the algorithmic 4 n K d counts both contractions over every row; the spill bound skips
+        # the second for the rows it decides, so the MFMA work executed is smaller
+        roofline.update(rows_bounded=head["rows_bounded"],
+                        executed_mfma_flops=head["executed_mfma_flops"],
+                        executed_frac=head["executed_frac"])
 
     # ---- oracle leg: reference answers on the check rows, every form judged against them
     import oracle as O
