@@ -36,22 +36,26 @@ PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2516.0, "fp8": 5032.0}   # MI355X dense M
 # null until it is measured again.
 COPY_SCALE = {"fetch": 1048576.0 / 524302.5, "write": 1.0}   # 1 GiB device copy
 # L2-to-memory traffic of one whole call (rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, KiB summed
-# over the call's dispatches), valid while the sources of its kernels are unchanged.  The runs
-# took K uniformly sampled rows as the codebook (--codebook sample); a trained codebook of the
-# same shape changes the partition sizes, not the streams.
+# over the call's dispatches), valid while the sources of its kernels are unchanged.  Runs before
+# the spill bound took K uniformly sampled rows as the codebook (--codebook sample); the BF16
+# entry below was taken with the Lloyd-trained codebook of the default run (--codebook-file),
+# since the rows the bound decides, and so the spill sweep's stream, depend on the codebook.
 TRAFFIC = {
-    # BF16, n=10M, d=96, K=40,000: quantization, primary sweep, re-score, grouping, grouped spill
-    # sweep over residual rows, re-score (plus the codebook norms and counter resets, 7.5 MB)
+    # BF16, n=10M, d=96, K=40,000: codebook norms and packing, the spill bound's table,
+    # quantization, primary sweep, re-score with the bound, grouping of the unbounded rows,
+    # grouped spill sweep over their residual rows, re-score
     ("bf16", "mix16384_n10m_d96"): dict(
-        fetch_kib=96044997.8125, write_kib=5712093.4375,
+        fetch_kib=62002694.5625, write_kib=5008075.6875,
         sources={"paper_2404_00774_amd/csrc/assign_lowp.hip":
-                 "0a9b42cb0db6a6ab65ef03bbe158e7e7a68c1ba2084aae79fe7189b4c4ca486f",
+                 "de272ea975ff788a4cc331f73a55bab843ecc7b3e89d22e5ae2178be1c8b6d52",
                  "paper_2404_00774_amd/csrc/group.hip":
                  "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198",
                  "paper_2404_00774_amd/csrc/common.h":
-                 "08810850b969fa684bc36a9d5144497379e1c98575c4717106f79b1a8f596bcf",
+                 "9a129011de60ae36ab0840a680f6b957f22209852444aed35c9d039e2291cc27",
                  "paper_2404_00774_amd/csrc/soar_api.hip":
-                 "0f0bd156f3ebf639e438f7d74359f1e1a6c75b952566785d097956e6a548202d"}),
+                 "02248c27b37137376617415f87a4900ac8b5b2c670223b293a5ba7a328447b1d",
+                 "paper_2404_00774_amd/csrc/bound.hip":
+                 "b185e71dbdfe6be47355134fccf2de03f9c25eb03d18f89f6ad6c4783aabd0eb"}),
     # FP8, same workload and the same stages (grouped spill over residual rows)
     ("fp8", "mix16384_n10m_d96"): dict(
         fetch_kib=80853062.9375, write_kib=4447144.65625,
@@ -136,6 +140,9 @@ def parse():
                     help="rows the oracle checks every form on (default: the workload's)")
     ap.add_argument("--codebook", default="train", choices=["train", "sample"],
                     help="sample: K uniformly sampled rows, no training (for short profiling runs)")
+    ap.add_argument("--codebook-file", default=None,
+                    help="train: load the trained codebook from this .npy when it exists, else "
+                         "train and save it there (profiler runs that cannot trace the training)")
     ap.add_argument("--rows", type=int, default=0, help="use only the first N rows (profiling)")
     ap.add_argument("--mode", default="assign", choices=["assign", "serve", "copy"],
                     help="serve: the serving form (resident index, open-loop Poisson inserts); "
@@ -710,6 +717,11 @@ def main():
     inertia = [float("nan")]
     if args.codebook == "sample":
         Cg = torch.from_numpy(X[sample_rows(spec, K)]).to(dev)
+    elif args.codebook_file and os.path.exists(args.codebook_file):
+        Cg = torch.from_numpy(np.load(args.codebook_file)).to(dev)
+        if tuple(Cg.shape) != (K, d):
+            raise SystemExit(f"{args.codebook_file}: shape {tuple(Cg.shape)}, not {(K, d)}")
+        print(f"[bench] codebook loaded from {args.codebook_file}", file=sys.stderr, flush=True)
     else:
         print("[bench] training codebook", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
@@ -727,6 +739,8 @@ def main():
         torch.cuda.synchronize()
         t_lloyd = time.perf_counter() - t0
         del labels, C0
+        if args.codebook_file:
+            np.save(args.codebook_file, Cg.cpu().numpy())
     C = Cg.cpu().numpy()
     idx = sample_rows(spec, check_rows)
 

@@ -1088,7 +1088,7 @@ void lowp_rescore_kernel(LowpParams P) {
       else {
         P.primary[row] = -1;
         if (P.pdist) P.pdist[row] = kInf;
-        if (P.gkey) P.gkey[row] = -1;            // no primary: no spill, no group
+        if (P.radius) P.radius[row] = kInf;      // no primary: no spill, no bound
       }
     }
     return;
@@ -1152,11 +1152,10 @@ void lowp_rescore_kernel(LowpParams P) {
   // sigma = sqrt(lambda) / (2 ||r||): the residual rows are stored pre-scaled by it, FP8 ones
   // with a power-of-two scale of their own
   const float rn = sqrtf(r2);
-  if (P.nbr) {
+  if (P.radius) {
     // Spill bound: U = (1 + lambda) ||x - c_j2||^2 for the nearest other candidate j2 bounds the
-    // spill's loss, so the spill lies within ||r|| + sqrt(U) of c_pi; when the table's bound on
-    // the centroids beyond c_pi's topk nearest exceeds that radius (with a margin for the FP32
-    // rounding of both sides), those topk are the row's spill candidates.
+    // spill's loss, so the spill lies within ||r|| + sqrt(U) of c_pi (raised by a margin for the
+    // FP32 rounding of both terms); launch_bound_decide compares it with c_pi's table entry.
     float second = kInf;
 #pragma unroll
     for (int c = 0; c < kMaxTopk; ++c) {
@@ -1164,9 +1163,7 @@ void lowp_rescore_kernel(LowpParams P) {
       if (P.cand[row * topk + c] != bj) second = fminf(second, vals[c]);
     }
     const float rad = (rn + sqrtf((1.f + P.lam) * second)) * (1.f + 4.f * (float)(d + 8) * kU32);
-    const bool in = rad < P.nbr_lb[bj];
-    if (in && l16 < topk) P.cand_spill[row * topk + l16] = P.nbr[(int64_t)bj * topk + l16];
-    if (l16 == 0) P.gkey[row] = in ? -1 : bj;
+    if (l16 == 0) P.radius[row] = rad;
   }
   const float sigma = rn > 0.f ? 0.5f * sqrtf(P.lam) / rn : 0.f;
   float inv = 1.f, scale = 1.f;

@@ -173,14 +173,10 @@ struct LowpParams {
   int ksplit = 1;
   int32_t* cand_split = nullptr;
   float* cand_val = nullptr;
-  // spill bound (launch_centroid_knn): with nbr set, the primary re-score writes, for each row
-  // whose spill provably lies among its primary centroid's topk nearest centroids, those as the
-  // row's spill candidates (cand_spill) and -1 as its group key; every other row gets its
-  // primary as group key (gkey), and only those rows are grouped for the spill sweep
-  const int32_t* nbr = nullptr;     // [K x topk]
-  const float* nbr_lb = nullptr;    // [K]
-  int32_t* cand_spill = nullptr;    // [n x topk]
-  int32_t* gkey = nullptr;          // [n]
+  // spill bound: with radius set, the primary re-score writes every row's bound radius
+  // ||r|| + sqrt((1 + lambda) ||x - c_j2||^2) (j2: the nearest other candidate; +inf without a
+  // primary) for launch_bound_decide
+  float* radius = nullptr;          // [n]
 };
 
 int lowp_padded_dim(int fmt, int d);
@@ -205,15 +201,39 @@ hipError_t launch_lowp_pack_codebook(int fmt, const float* C, int K, int d, cons
 hipError_t launch_lowp_rescore(int fmt, const LowpParams& P, bool spill, hipStream_t st);
 // Merges the split candidates of a sweep (no-op for P.ksplit <= 1).
 hipError_t launch_lowp_merge(const LowpParams& P, hipStream_t st);
-// The spill bound's table: for every centroid p, its M (<= kBoundMaxM) nearest other centroids
-// (ascending; -1 where K - 1 < M) and a lower bound on ||c_p - c_j|| over every other j
-// (+inf when none is left out).  cnorm holds ||c_j||^2.
+// Spill bound (bound.hip).  launch_bound_table, before the sweeps: from the two nearest
+// centroids of a sample of rows it estimates on the device how many rows the bound would decide;
+// when that pays for the table (2 K^2 d FP32 flop), it builds for every centroid p its M
+// (<= kBoundMaxM) nearest other centroids and a lower bound on the distance to the others.
+// launch_bound_decide, after the primary re-score (radius): a row whose radius lies below its
+// primary's bound takes those M as spill candidates (cand) and -1 as group key (gkey); every
+// other row takes its primary (-1 without one).  counters[CNT_BOUNDED] then counts the decided
+// rows once the grouping has run (launch_bound_count).  cnorm holds ||c_j||^2.
 constexpr int kBoundMaxM = 8;
-// scratch_v / scratch_j: knn_scratch_entries(K) entries each (per-part lists before the merge).
-size_t knn_scratch_entries(int K);
-hipError_t launch_centroid_knn(const float* C, int K, int d, const float* cnorm, int M,
-                               float* scratch_v, int32_t* scratch_j, int32_t* nbr, float* nbr_lb,
-                               hipStream_t st);
+constexpr int kBoundSample = 1024;
+struct BoundLayout {
+  int32_t* nbr;        // [K x M]
+  float* nbr_lb;       // [K]
+  int32_t* xrows;      // [kBoundSample] the sample rows
+  float* xnorm;        // [kBoundSample] their squared norms
+  int32_t* xnear;      // [kBoundSample] their nearest centroids
+  float* xd1;          // [kBoundSample] distances to them
+  float* xd2;          // [kBoundSample] distances to the second nearest
+  int32_t* snbr;       // [kBoundSample x M] table entries of xnear
+  float* slb;          // [kBoundSample]
+  float* scratch_v;    // per-part lists before their merge
+  int32_t* scratch_j;
+  int32_t* enable;     // [1] the device's decision to build the table
+  size_t bytes;
+};
+BoundLayout bound_layout(void* ws, int K, int M);
+// payoff: rows per centroid the bound must decide to pay for the table.
+hipError_t launch_bound_table(const float* X, int64_t n, const float* C, int K, int d,
+                              const float* cnorm, int M, float lam, const BoundLayout& B,
+                              int payoff, hipStream_t st);
+hipError_t launch_bound_decide(int M, int64_t n, int K, const int32_t* primary,
+                               const float* radius, const BoundLayout& B, int32_t* cand,
+                               int32_t* gkey, hipStream_t st);
 // counters[CNT_BOUNDED] = n - group_off[K]: the rows the grouping left out.
 hipError_t launch_bound_count(const int32_t* group_off, int K, int64_t n, unsigned* counters,
                               hipStream_t st);

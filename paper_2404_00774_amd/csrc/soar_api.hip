@@ -80,11 +80,9 @@ struct LowpLayout {
   void* Cp;             // codebook rows quantized like X (grouped spill form)
   float* cps;
   void* group;
-  int32_t* nbr;         // [K x topk] spill bound: nearest centroids of every centroid
-  float* nbr_lb;        // [K] and the bound on the distance to the others
+  float* radius;        // [n] spill bound: each row's radius around its primary centroid
   int32_t* gkey;        // [n] group key of the spill sweep (-1: bounded row)
-  float* knn_v;         // the table's per-part lists before their merge
-  int32_t* knn_j;
+  void* bound;          // the bound's table, sample and flag (bound_layout)
   size_t bytes;
 };
 
@@ -106,11 +104,10 @@ LowpLayout layout_lowp(void* ws, int64_t n, int32_t d, int32_t K, int fmt, int t
   L.Cp = c.take<char>((size_t)K * dp * eb);
   L.cps = c.take<float>((size_t)K);
   L.group = c.take<char>(soar::group_layout(nullptr, n, K).bytes);
-  L.nbr = c.take<int32_t>((size_t)K * topk);
-  L.nbr_lb = c.take<float>((size_t)K);
+  L.radius = c.take<float>((size_t)n);
   L.gkey = c.take<int32_t>((size_t)n);
-  L.knn_v = c.take<float>(soar::knn_scratch_entries(K));
-  L.knn_j = c.take<int32_t>(soar::knn_scratch_entries(K));
+  L.bound = c.take<char>(soar::bound_layout(nullptr, K, topk < soar::kBoundMaxM ? topk
+                                                                         : soar::kBoundMaxM).bytes);
   L.bytes = c.off;
   return L;
 }
@@ -293,19 +290,25 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
     e = launch_lowp_pack_codebook(fmt, C, K, d, L.cnorm, L.Cq, L.counters, st);
   if (e == hipSuccess && grouped)
     e = launch_lowp_quantize(fmt, C, K, d, P.dp, false, L.Cp, L.cps, L.counters, st);
+  // the spill bound's table (only where a sample says it pays: FP8's sweep costs about half
+  // BF16's per row, so there it must decide more rows)
+  const BoundLayout BL = bound_layout(L.bound, K, bound ? topk : 1);
   if (e == hipSuccess && bound)
-    e = launch_centroid_knn(C, K, d, L.cnorm, topk, L.knn_v, L.knn_j, L.nbr, L.nbr_lb, st);
+    e = launch_bound_table(X, n, C, K, d, L.cnorm, topk, lam, BL, fmt == LOWP_BF16 ? 32 : 48, st);
   if (e == hipSuccess)
     e = launch_lowp_quantize(fmt, X, n, d, P.dp, false, L.Xq, L.xs, L.counters, st);
   if (e == hipSuccess) e = mark(1);
   if (e == hipSuccess) e = launch_lowp_sweep(fmt, P, false, st);
   if (e == hipSuccess) e = mark(2);
-  if (bound) { P.nbr = L.nbr; P.nbr_lb = L.nbr_lb; P.cand_spill = L.cand; P.gkey = L.gkey; }
+  if (bound) P.radius = L.radius;
   if (e == hipSuccess) e = launch_lowp_rescore(fmt, P, false, st);
-  P.nbr = nullptr; P.nbr_lb = nullptr; P.cand_spill = nullptr; P.gkey = nullptr;
+  P.radius = nullptr;
   if (e == hipSuccess) e = mark(3);
   P.cand = L.cand;
   if (grouped) {
+    // rows the spill bound decides
+    if (e == hipSuccess && bound)
+      e = launch_bound_decide(topk, n, K, primary, L.radius, BL, L.cand, L.gkey, st);
     if (e == hipSuccess)
       e = launch_group_by_primary(bound ? L.gkey : primary, n, nullptr, K, GL, st);
     if (e == hipSuccess && bound) e = launch_bound_count(GL.off, K, n, L.counters, st);
