@@ -41,21 +41,21 @@ COPY_SCALE = {"fetch": 1048576.0 / 524302.5, "write": 1.0}   # 1 GiB device copy
 # entry below was taken with the Lloyd-trained codebook of the default run (--codebook-file),
 # since the rows the bound decides, and so the spill sweep's stream, depend on the codebook.
 TRAFFIC = {
-    # BF16, n=10M, d=96, K=40,000: codebook norms and packing, the spill bound's table,
-    # quantization, primary sweep, re-score with the bound, grouping of the unbounded rows,
-    # grouped spill sweep over their residual rows, re-score
+    # BF16, n=10M, d=96, K=40,000: codebook norms and packing, the spill bound's sample and
+    # table, quantization, primary sweep, re-score, the bound's decisions, grouping of the rows
+    # it left, grouped spill sweep over their residual rows, re-score
     ("bf16", "mix16384_n10m_d96"): dict(
-        fetch_kib=62002694.5625, write_kib=5008075.6875,
+        fetch_kib=60396378.125, write_kib=5047980.28125,
         sources={"paper_2404_00774_amd/csrc/assign_lowp.hip":
-                 "de272ea975ff788a4cc331f73a55bab843ecc7b3e89d22e5ae2178be1c8b6d52",
+                 "f739b8c4c985ac40e434c23912d749241bc8439dd518f154db3ae775d98f5dcb",
                  "paper_2404_00774_amd/csrc/group.hip":
                  "4413a44cf489a8b77a65e6439b438c875b44e66230830bd7d03cce73d83c5198",
                  "paper_2404_00774_amd/csrc/common.h":
                  "9a129011de60ae36ab0840a680f6b957f22209852444aed35c9d039e2291cc27",
                  "paper_2404_00774_amd/csrc/soar_api.hip":
-                 "02248c27b37137376617415f87a4900ac8b5b2c670223b293a5ba7a328447b1d",
+                 "a92ad3b07afea5d9aeb4c89ccfb4517eb110ad874d65df2816ae2b484481a1d7",
                  "paper_2404_00774_amd/csrc/bound.hip":
-                 "b185e71dbdfe6be47355134fccf2de03f9c25eb03d18f89f6ad6c4783aabd0eb"}),
+                 "ae2c48b34480bf00bffb41139c0394da49f4c20a6964a8085bb9e516197e193f"}),
     # FP8, same workload and the same stages (grouped spill over residual rows)
     ("fp8", "mix16384_n10m_d96"): dict(
         fetch_kib=80853062.9375, write_kib=4447144.65625,
