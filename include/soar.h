@@ -74,9 +74,14 @@ typedef enum soar_precision {
    within ||r|| + sqrt(U) of C_p (the penalty lies between 0 and lambda ||x - C_j||^2, then the
    triangle inequality; Section 3.4's loss).  When the topk centroids nearest to C_p include all
    centroids that close (FP32 distances lowered by their rounding bound), those topk are the row's
-   spill candidates, re-scored exactly, and the row skips the spill sweep.  This bit turns the
-   bound off (every row goes through the sweep). */
+   spill candidates, re-scored exactly, and the row skips the spill sweep.  The bound needs a
+   table of every centroid's topk nearest centroids (2 K^2 d FP32 flop); for calls of at least
+   2^40 n K d a sample of 256 rows decides on the device whether it pays (it must decide 32 rows
+   per centroid for BF16, 48 for FP8), smaller calls go without it.  SOAR_NO_BOUND turns the bound
+   off (every row goes through the sweep); SOAR_BOUND_ALWAYS builds the table at any size.  Both
+   bits: SOAR_E_INVAL. */
 #define SOAR_NO_BOUND 8u
+#define SOAR_BOUND_ALWAYS 16u
 
 /* Options of soar_assign.  Set struct_size = sizeof(soar_assign_opts). */
 typedef struct soar_assign_opts {

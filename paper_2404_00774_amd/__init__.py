@@ -24,7 +24,8 @@ FP32, BF16, FP8_E4M3 = 0, 1, 2
 _PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3}
 ASYNC = 1
 SPILL_GROUPED, SPILL_DIRECT = 2, 4
-NO_BOUND = 8
+NO_BOUND, BOUND_ALWAYS = 8, 16
+_BOUND = {True: 0, "auto": 0, False: NO_BOUND, "off": NO_BOUND, "always": BOUND_ALWAYS}
 _SPILL_FORM = {"auto": 0, "grouped": SPILL_GROUPED, "direct": SPILL_DIRECT}
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error",
@@ -183,10 +184,11 @@ def assign(X, C, lam, precision="fp32", topk=0, near_tie_rel=0.0, stream=None, o
     """SOAR assignment of every row of X against codebook C (both float32 on the GPU).
 
     ``spill_form``: "auto", "grouped" or "direct" (the form of the spill sweep; same results).
-    ``bound=False`` sets SOAR_NO_BOUND (every row's spill goes through the sweep).
+    ``bound``: "auto" (or True; the library decides), False ("off": SOAR_NO_BOUND, every row's
+    spill goes through the sweep) or "always" (SOAR_BOUND_ALWAYS).
     Returns (primary int32[n], spill int32[n], primary_dist float32[n], spill_loss float32[n])
     and, with ``stats=True``, a dict of call statistics as a fifth element."""
-    flags = int(flags) | _SPILL_FORM[spill_form] | (0 if bound else NO_BOUND)
+    flags = int(flags) | _SPILL_FORM[spill_form] | _BOUND[bound]
     X, C = _f32_matrix(X, "X"), _f32_matrix(C, "C")
     n, d = X.shape
     K = C.shape[0]

@@ -11,9 +11,10 @@
 // re-score of them decides the spill.  This file computes, for every centroid p, its M nearest
 // other centroids and a lower bound on the distance from c_p to every other centroid, and
 // decides the rows.  The table costs 2 K^2 d FP32 flop, so it is built only where it pays: the
-// same kernels first run over the primaries of 1,024 sample rows, and a one-workgroup kernel
-// scales the sample's decided share to n and sets a device flag that the full table's kernels
-// and the decision kernel read (no host round trip; an enqueue-only call stays one).
+// same kernels first run over 256 sample rows (their two nearest centroids, then the table
+// entries of their nearest centroids), and a one-workgroup kernel scales the sample's decided
+// share to n and sets a device flag that the full table's kernels and the decision kernel read
+// (no host round trip; an enqueue-only call stays one).
 //
 // Distances come from the expansion ||a||^2 + ||b||^2 - 2 <a, b> in FP32.  Its error is at most
 // (d + 2) u (||a|| + ||b||)^2 (u = 2^-24: the dot product's and the norms' accumulations and
@@ -348,6 +349,10 @@ __global__ __launch_bounds__(1024) void bound_estimate_kernel(const float* __res
   if (threadIdx.x == 0) enable[0] = (double)cnt * (double)n / ns > (double)payoff * K ? 1 : 0;
 }
 
+__global__ void bound_enable_kernel(int32_t* enable) {
+  if (threadIdx.x == 0) enable[0] = 1;
+}
+
 // Every row: bounded (the primary's neighbours as spill candidates, group key -1) when the table
 // was built and the row's radius lies below its primary's bound; else the primary as group key.
 template <int M>
@@ -373,12 +378,15 @@ __global__ __launch_bounds__(256) void bound_decide_kernel(const int32_t* __rest
 }
 
 // Parts of the codebook per block of 64 list positions: about 2,048 workgroups in all, at most
-// one part per tile and 16 parts (the merge reads 16 (M + 1) entries per list position).
+// one part per tile, and at most 16 parts for the whole codebook's table (its merge reads
+// 16 (M + 1) entries per centroid) or 64 for a sample's (a few hundred positions, so the merge
+// stays short, while each workgroup walks few tiles one after another).
 int knn_parts(int np, int K) {
   const int ntiles = (K + KT - 1) / KT, nblk = (np + KT - 1) / KT;
   int parts = (2048 + nblk - 1) / nblk;
   if (parts > ntiles) parts = ntiles;
-  if (parts > 16) parts = 16;
+  const int cap = np <= kBoundSample ? 64 : 16;
+  if (parts > cap) parts = cap;
   return parts < 1 ? 1 : parts;
 }
 
@@ -430,6 +438,13 @@ template <int M>
 void launch_bound_table_m(const float* X, int64_t n, const float* C, int K, int d,
                           const float* cnorm, float lam, const BoundLayout& B, int payoff,
                           hipStream_t st) {
+  if (payoff <= 0) {
+    // no estimate: the table is built
+    hipLaunchKernelGGL(bound_enable_kernel, dim3(1), dim3(64), 0, st, B.enable);
+    launch_table<M>(C, K, nullptr, 1, C, K, d, cnorm, nullptr, K, nullptr, B.scratch_v,
+                    B.scratch_j, B.nbr, B.nbr_lb, nullptr, st);
+    return;
+  }
   const int ns = n < kBoundSample ? (int)n : kBoundSample;
   // the sample rows' two nearest centroids, then the bound of the nearest, then the decision
   hipLaunchKernelGGL(bound_sample_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, X,

@@ -210,7 +210,7 @@ hipError_t launch_lowp_merge(const LowpParams& P, hipStream_t st);
 // other row takes its primary (-1 without one).  counters[CNT_BOUNDED] then counts the decided
 // rows once the grouping has run (launch_bound_count).  cnorm holds ||c_j||^2.
 constexpr int kBoundMaxM = 8;
-constexpr int kBoundSample = 1024;
+constexpr int kBoundSample = 256;
 struct BoundLayout {
   int32_t* nbr;        // [K x M]
   float* nbr_lb;       // [K]
@@ -227,7 +227,7 @@ struct BoundLayout {
   size_t bytes;
 };
 BoundLayout bound_layout(void* ws, int K, int M);
-// payoff: rows per centroid the bound must decide to pay for the table.
+// payoff: rows per centroid the bound must decide to pay for the table; 0 builds it regardless.
 hipError_t launch_bound_table(const float* X, int64_t n, const float* C, int K, int d,
                               const float* cnorm, int M, float lam, const BoundLayout& B,
                               int payoff, hipStream_t st);

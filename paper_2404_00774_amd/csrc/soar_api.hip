@@ -57,6 +57,7 @@ soar_status validate_assign(int64_t n, int32_t d, int32_t K, const OptsView& o) 
   if (n < 1 || n > INT32_MAX || d < 1 || K < 2) return SOAR_E_INVAL;
   if (!std::isfinite(o.lambda) || o.lambda < 0.f) return SOAR_E_INVAL;
   if ((o.flags & SOAR_SPILL_GROUPED) && (o.flags & SOAR_SPILL_DIRECT)) return SOAR_E_INVAL;
+  if ((o.flags & SOAR_NO_BOUND) && (o.flags & SOAR_BOUND_ALWAYS)) return SOAR_E_INVAL;
   if (!(o.near_tie_rel >= 0.f) || !std::isfinite(o.near_tie_rel)) return SOAR_E_INVAL;
   if (o.precision == SOAR_FP32) return soar::fp32_padded_dim(d) < 0 ? SOAR_E_UNSUPPORTED : SOAR_OK;
   if (o.precision != SOAR_BF16 && o.precision != SOAR_FP8_E4M3) return SOAR_E_INVAL;
@@ -269,7 +270,12 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
   const GroupLayout GL = group_layout(L.group, n, K);
   // The spill bound (bound.hip) serves the grouped form: rows it decides leave the grouping, and
   // the spill sweep runs over the rest.
-  const bool bound = grouped && topk <= kBoundMaxM && !(flags & SOAR_NO_BOUND);
+  // The spill bound: a sample decides on the device whether its table pays, for calls of at
+  // least 2^40 n K d (below that the sample's fixed cost, a few dependent launches, weighs more
+  // than the sweep it could save); SOAR_BOUND_ALWAYS builds the table regardless.
+  const bool always = (flags & SOAR_BOUND_ALWAYS) != 0;
+  const bool bound = grouped && topk <= kBoundMaxM && !(flags & SOAR_NO_BOUND) &&
+                     (always || (double)n * K * d >= 1099511627776.0);
   LowpParams P;
   P.n = n; P.d = d; P.dp = lowp_padded_dim(fmt, d); P.K = K; P.topk = topk;
   P.lam = lam;
@@ -294,7 +300,8 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
   // BF16's per row, so there it must decide more rows)
   const BoundLayout BL = bound_layout(L.bound, K, bound ? topk : 1);
   if (e == hipSuccess && bound)
-    e = launch_bound_table(X, n, C, K, d, L.cnorm, topk, lam, BL, fmt == LOWP_BF16 ? 32 : 48, st);
+    e = launch_bound_table(X, n, C, K, d, L.cnorm, topk, lam, BL,
+                           always ? 0 : fmt == LOWP_BF16 ? 32 : 48, st);
   if (e == hipSuccess)
     e = launch_lowp_quantize(fmt, X, n, d, P.dp, false, L.Xq, L.xs, L.counters, st);
   if (e == hipSuccess) e = mark(1);
@@ -353,7 +360,7 @@ soar_status assign_impl(const float* X, int64_t n, int32_t d, const float* C, in
   }
   unsigned cnt[soar::CNT_WORDS] = {0};
   const uint32_t form = o.flags & (SOAR_SPILL_GROUPED | SOAR_SPILL_DIRECT);
-  const uint32_t lowp_flags = form | (o.flags & SOAR_NO_BOUND);
+  const uint32_t lowp_flags = form | (o.flags & (SOAR_NO_BOUND | SOAR_BOUND_ALWAYS));
   soar_status s;
   if (!lowp)
     s = soar::run_assign_fp32(X, n, d, C, K, o.lambda, o.near_tie_rel, true, primary, spill,

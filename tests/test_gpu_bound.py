@@ -3,7 +3,9 @@
 A row whose spill the bound confines to the topk centroids nearest its primary centroid skips the
 spill sweep and has those centroids re-scored exactly, so its spill must be exact by the
 acceptance rule (conditional on the GPU's primary); its candidates must be the oracle's nearest
-centroids of that primary.  The other rows go through the sweep as before.
+centroids of that primary.  The other rows go through the sweep as before.  The inputs here are
+small, so the tests ask for the table (SOAR_BOUND_ALWAYS) unless they test the library's own
+decision; the benchmark-size tests in test_gpu_lowp.py run that decision.
 """
 import numpy as np
 import pytest
@@ -24,7 +26,7 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-def _run(X, C, lam, prec, topk=0, bound=True):
+def _run(X, C, lam, prec, topk=0, bound="always"):
     import torch
     soar = _soar()
     n, d = X.shape
@@ -114,3 +116,20 @@ def test_bound_follows_topk(clustered, topk):
         assert 0 < st["rows_bounded"] < len(X)
         j = O.verify(X, C, 1.0, p, s, dp, ls)
         assert np.all(j["spill_ok"][key < 0])
+
+
+def test_auto_mode_skips_small_calls(clustered):
+    # below 2^40 n K d the library does not build the table on its own
+    X, C = clustered
+    p, s, dp, ls, st, cs, key = _run(X, C, 1.0, "bf16", bound="auto")
+    assert st["rows_bounded"] == 0
+    j = O.verify(X, C, 1.0, p, s, dp, ls)
+    assert j["pdist_ok"].all() and j["sloss_ok"].all()
+
+
+def test_conflicting_bound_flags_rejected(clustered):
+    import paper_2404_00774_amd as soar
+    X, C = clustered
+    with pytest.raises(soar.SoarError):
+        soar.assign(_t(X[:1000]), _t(C), 1.0, precision="bf16", bound="always",
+                    flags=soar.NO_BOUND)

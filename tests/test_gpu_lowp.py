@@ -66,6 +66,7 @@ def _report(X, C, lam, res, tag):
     assert j["pdist_ok"].all() and j["sloss_ok"].all()
     assert np.all(s != p) and np.all((p >= 0) & (p < len(C))) and np.all((s >= 0) & (s < len(C)))
     assert np.all(j["primary_regret"] >= -1e-6) and np.all(j["spill_regret"] >= -1e-6)
+    out["spill_ok_rows"] = j["spill_ok"]
     return out
 
 
@@ -184,6 +185,8 @@ def _full_size_check(X, Xg, C, lam, prec, rows):
     assert r["primary_regret_mean"] <= 1e-3 and r["spill_regret_mean"] <= 1e-3
     assert r["candidate_misses_primary"] <= max(2, rows // 500)
     assert r["candidate_misses_spill"] <= max(2, rows // 500)
+    r["rows_bounded"] = st["rows_bounded"]
+    r["bound_key"] = soar.assign_candidates(ws, n, d, len(C), lam, prec, bound_key=True)[2][it]
     return r
 
 
@@ -193,7 +196,12 @@ def test_full_size_config3_trained(config3, prec):
     grouped spill over residual rows, FP8 direct); the oracle checks 5000 sampled rows."""
     X, Xg, C = config3
     print(f"config3 trained {prec}", flush=True)
-    _full_size_check(X, Xg, C, 1.0, prec, 5000)
+    r = _full_size_check(X, Xg, C, 1.0, prec, 5000)
+    # the library builds the spill bound's table on its own here (most rows decided), and every
+    # sampled row the bound decided has the exact spill
+    assert r["rows_bounded"] > len(X) // 2
+    bounded = r["bound_key"].cpu().numpy() < 0
+    assert bounded.sum() > 2000 and r["spill_ok_rows"][bounded].all()
 
 
 @pytest.mark.parametrize("prec,lam", [("fp8", 0.5), ("fp8", 1.0), ("fp8", 1.5),
