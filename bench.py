@@ -45,7 +45,7 @@ TRAFFIC = {
     # table, quantization, primary sweep, re-score, the bound's decisions, grouping of the rows
     # it left, grouped spill sweep over their residual rows, re-score
     ("bf16", "mix16384_n10m_d96"): dict(
-        fetch_kib=60396378.125, write_kib=5047980.28125,
+        fetch_kib=60497952.3125, write_kib=5049305.625,
         sources={"paper_2404_00774_amd/csrc/assign_lowp.hip":
                  "f739b8c4c985ac40e434c23912d749241bc8439dd518f154db3ae775d98f5dcb",
                  "paper_2404_00774_amd/csrc/group.hip":
@@ -53,9 +53,9 @@ TRAFFIC = {
                  "paper_2404_00774_amd/csrc/common.h":
                  "9a129011de60ae36ab0840a680f6b957f22209852444aed35c9d039e2291cc27",
                  "paper_2404_00774_amd/csrc/soar_api.hip":
-                 "a92ad3b07afea5d9aeb4c89ccfb4517eb110ad874d65df2816ae2b484481a1d7",
+                 "b40bd7a878a31fd7f3471d8737dc906b93ce704649bed79f91c5bbbf32475c46",
                  "paper_2404_00774_amd/csrc/bound.hip":
-                 "ae2c48b34480bf00bffb41139c0394da49f4c20a6964a8085bb9e516197e193f"}),
+                 "f5de11f98d60a418a4d9fbdcde03b757376ea6018e732f37f8dfdfdc7799501c"}),
     # FP8, same workload and the same stages (grouped spill over residual rows)
     ("fp8", "mix16384_n10m_d96"): dict(
         fetch_kib=80853062.9375, write_kib=4447144.65625,
