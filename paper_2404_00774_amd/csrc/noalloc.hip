@@ -46,7 +46,7 @@ soar_status soar_assign_noalloc(const float* X, int64_t n, int32_t d, const floa
   void* ws = scratch_ptr();
   if (!ws) return SOAR_E_DEVICE;
   return soar::assign_run(X, n, d, C, K, opts, primary, spill, primary_dist, spill_loss, ws,
-                          static_cast<hipStream_t>(stream), nullptr);
+                          static_cast<hipStream_t>(stream), nullptr, false);
 }
 
 size_t soar_assign_noalloc_limit(void) { return kScratchBytes; }

@@ -3,6 +3,7 @@
 // them on the caller's stream.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/soar.h"
@@ -249,6 +250,20 @@ size_t assign_workspace_bytes(int64_t n, int32_t d, int32_t K) {
   return layout_assign(nullptr, n, d, K).bytes;
 }
 
+// A second stream per device (created on first use, kept for the process) on which the spill
+// bound's table runs beside the quantization and the primary sweep: the table waits mostly on
+// latency and fits beside the sweep's workgroups on a CU.  Default priority, non-blocking.
+hipStream_t side_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    streams[dev] = nullptr;
+  return streams[dev];
+}
+
 // BF16 / FP8 pipeline: quantize, primary sweep + re-score, spill sweep + re-score.
 soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
                             float lam, float near_tie_rel, int fmt, int topk, int32_t* primary,
@@ -299,9 +314,38 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
   // the spill bound's table (only where a sample says it pays: FP8's sweep costs about half
   // BF16's per row, so there it must decide more rows)
   const BoundLayout BL = bound_layout(L.bound, K, bound ? topk : 1);
-  if (e == hipSuccess && bound)
-    e = launch_bound_table(X, n, C, K, d, L.cnorm, topk, lam, BL,
-                           always ? 0 : fmt == LOWP_BF16 ? 32 : 48, st);
+  // the table forks off to the side stream once the codebook norms are ready and joins back
+  // before the decisions (it reads X, C and the norms, and writes only its own workspace part);
+  // without a side stream it runs in place
+  hipStream_t side = bound && !(flags & kLowpNoSideStream) ? side_stream() : nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  // on every return: the caller's stream waits for the side stream's part (a no-op when the
+  // join was never recorded), then the events go (their release waits for their completion)
+  struct Joined {
+    hipStream_t st;
+    hipStream_t& side;
+    hipEvent_t& fork;
+    hipEvent_t& join;
+    ~Joined() {
+      if (side && join) (void)hipStreamWaitEvent(st, join, 0);
+      if (fork) (void)hipEventDestroy(fork);
+      if (join) (void)hipEventDestroy(join);
+    }
+  } joined{st, side, fork, join};
+  if (side && (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+               hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess))
+    side = nullptr;
+  if (e == hipSuccess && bound) {
+    const int payoff = always ? 0 : fmt == LOWP_BF16 ? 32 : 48;
+    if (side) {
+      e = hipEventRecord(fork, st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+      if (e == hipSuccess) e = launch_bound_table(X, n, C, K, d, L.cnorm, topk, lam, BL, payoff, side);
+      if (e == hipSuccess) e = hipEventRecord(join, side);
+    } else {
+      e = launch_bound_table(X, n, C, K, d, L.cnorm, topk, lam, BL, payoff, st);
+    }
+  }
   if (e == hipSuccess)
     e = launch_lowp_quantize(fmt, X, n, d, P.dp, false, L.Xq, L.xs, L.counters, st);
   if (e == hipSuccess) e = mark(1);
@@ -314,6 +358,7 @@ soar_status run_assign_lowp(const float* X, int64_t n, int32_t d, const float* C
   P.cand = L.cand;
   if (grouped) {
     // rows the spill bound decides
+    if (e == hipSuccess && side) e = hipStreamWaitEvent(st, join, 0);
     if (e == hipSuccess && bound)
       e = launch_bound_decide(topk, n, K, primary, L.radius, BL, L.cand, L.gkey, st);
     if (e == hipSuccess)
@@ -344,7 +389,8 @@ namespace {
 // (and the status record an enqueue-only call left in the same workspace) and clears the record.
 soar_status assign_impl(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
                         const OptsView& o, int32_t* primary, int32_t* spill, float* primary_dist,
-                        float* spill_loss, void* workspace, hipStream_t st, soar_stats* stats) {
+                        float* spill_loss, void* workspace, hipStream_t st, soar_stats* stats,
+                        bool side_ok) {
   const bool async = (o.flags & SOAR_ASYNC) != 0;
   const bool lowp = o.precision != SOAR_FP32;
   // the counters lead both workspace layouts
@@ -360,7 +406,8 @@ soar_status assign_impl(const float* X, int64_t n, int32_t d, const float* C, in
   }
   unsigned cnt[soar::CNT_WORDS] = {0};
   const uint32_t form = o.flags & (SOAR_SPILL_GROUPED | SOAR_SPILL_DIRECT);
-  const uint32_t lowp_flags = form | (o.flags & (SOAR_NO_BOUND | SOAR_BOUND_ALWAYS));
+  const uint32_t lowp_flags = form | (o.flags & (SOAR_NO_BOUND | SOAR_BOUND_ALWAYS)) |
+                              (side_ok ? 0u : soar::kLowpNoSideStream);
   soar_status s;
   if (!lowp)
     s = soar::run_assign_fp32(X, n, d, C, K, o.lambda, o.near_tie_rel, true, primary, spill,
@@ -424,11 +471,11 @@ soar_status assign_validate(const float* X, int64_t n, int32_t d, const float* C
 soar_status assign_run(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
                        const soar_assign_opts* opts, int32_t* primary, int32_t* spill,
                        float* primary_dist, float* spill_loss, void* workspace, hipStream_t st,
-                       soar_stats* stats) {
+                       soar_stats* stats, bool side_stream) {
   OptsView o;
   if (!read_opts(opts, &o)) return SOAR_E_INVAL;
   return assign_impl(X, n, d, C, K, o, primary, spill, primary_dist, spill_loss, workspace, st,
-                     stats);
+                     stats, side_stream);
 }
 
 }  // namespace soar

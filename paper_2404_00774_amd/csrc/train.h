@@ -29,9 +29,13 @@ constexpr int kPhaseEvents = 7;
 soar_status assign_validate(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
                             const soar_assign_opts* opts, const int32_t* primary,
                             const int32_t* spill, size_t* need);
+// side_stream: the spill bound may run its table on a second stream of the library's (the
+// allocation-free entry point asks for none: creating one allocates).
 soar_status assign_run(const float* X, int64_t n, int32_t d, const float* C, int32_t K,
                        const soar_assign_opts* opts, int32_t* primary, int32_t* spill,
                        float* primary_dist, float* spill_loss, void* workspace, hipStream_t st,
-                       soar_stats* stats);
+                       soar_stats* stats, bool side_stream = true);
+// run_assign_lowp flags bit (beside the public ones): no second stream.
+constexpr uint32_t kLowpNoSideStream = 1u << 30;
 
 }  // namespace soar
