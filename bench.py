@@ -45,7 +45,7 @@ TRAFFIC = {
     # table, quantization, primary sweep, re-score, the bound's decisions, grouping of the rows
     # it left, grouped spill sweep over their residual rows, re-score
     ("bf16", "mix16384_n10m_d96"): dict(
-        fetch_kib=60497952.3125, write_kib=5049305.625,
+        fetch_kib=61515098.125, write_kib=5048747.21875,
         sources={"paper_2404_00774_amd/csrc/assign_lowp.hip":
                  "f739b8c4c985ac40e434c23912d749241bc8439dd518f154db3ae775d98f5dcb",
                  "paper_2404_00774_amd/csrc/group.hip":
@@ -53,7 +53,7 @@ TRAFFIC = {
                  "paper_2404_00774_amd/csrc/common.h":
                  "9a129011de60ae36ab0840a680f6b957f22209852444aed35c9d039e2291cc27",
                  "paper_2404_00774_amd/csrc/soar_api.hip":
-                 "b40bd7a878a31fd7f3471d8737dc906b93ce704649bed79f91c5bbbf32475c46",
+                 "d726c161aaec18f71ab2c0b2e681d42e2009e8cac74f51acf210522158b0da24",
                  "paper_2404_00774_amd/csrc/bound.hip":
                  "f5de11f98d60a418a4d9fbdcde03b757376ea6018e732f37f8dfdfdc7799501c"}),
     # FP8, same workload and the same stages (grouped spill over residual rows)
