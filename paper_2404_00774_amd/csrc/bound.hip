@@ -317,7 +317,9 @@ __global__ __launch_bounds__(256) void bound_sample_kernel(const float* __restri
                                                            float* __restrict__ xnorm) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (k >= ns) return;
-  const int64_t i = (int64_t)k * n / ns;
+  // (the rows are listed as int32: beyond 2^31 - 1 rows the sample spans the first 2^31 - 1)
+  const int64_t span = n < 2147483647 ? n : 2147483647;
+  const int64_t i = (int64_t)k * span / ns;
   const float* x = X + i * d;
   float s0 = 0.f;
   for (int m = 0; m < d; ++m) s0 = fmaf(x[m], x[m], s0);
