@@ -45,7 +45,7 @@ TRAFFIC = {
     # table, quantization, primary sweep, re-score, the bound's decisions, grouping of the rows
     # it left, grouped spill sweep over their residual rows, re-score
     ("bf16", "mix16384_n10m_d96"): dict(
-        fetch_kib=61515098.125, write_kib=5048747.21875,
+        fetch_kib=62024592.5, write_kib=5048881.46875,
         sources={"paper_2404_00774_amd/csrc/assign_lowp.hip":
                  "f739b8c4c985ac40e434c23912d749241bc8439dd518f154db3ae775d98f5dcb",
                  "paper_2404_00774_amd/csrc/group.hip":
@@ -55,7 +55,7 @@ TRAFFIC = {
                  "paper_2404_00774_amd/csrc/soar_api.hip":
                  "d726c161aaec18f71ab2c0b2e681d42e2009e8cac74f51acf210522158b0da24",
                  "paper_2404_00774_amd/csrc/bound.hip":
-                 "f5de11f98d60a418a4d9fbdcde03b757376ea6018e732f37f8dfdfdc7799501c"}),
+                 "0d20dae175898ad1294ad2a29e74a5a5f2d540fe4041755794db3f749a133882"}),
     # FP8, same workload and the same stages (grouped spill over residual rows)
     ("fp8", "mix16384_n10m_d96"): dict(
         fetch_kib=80853062.9375, write_kib=4447144.65625,
